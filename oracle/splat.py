@@ -1,0 +1,293 @@
+"""FP64 Gaussian-splatting renderer (oracle).
+
+CrowdSplat §2 renders all characters with the 3D Gaussian Splatting
+rasteriser (Kerbl et al. 2023): project each 3D Gaussian to a 2D screen-space
+Gaussian (EWA splatting, the local affine approximation of the perspective
+map), bin it into the screen tiles its footprint touches, sort every tile's
+list front to back, and alpha-composite per pixel. The constants are that
+renderer's: alpha clamped to 0.99, contributions below 1/255 skipped, and a
+pixel stops before its transmittance would fall below 1e-4.
+
+Readings where the paper is silent (listed in the design doc):
+* pinhole camera, vertical field of view, pixel centres at +1/2, near plane
+  0.2 m, a 1.5x guard band on the normalised image coordinates;
+* the screen-space covariance gets +0.3 px^2 on its diagonal (low-pass
+  filter) with no opacity compensation;
+* the footprint is the exact bounding box of the alpha >= 1/255 ellipse,
+  widened by 1e-4 relative and 0.01 px, so that the image does not depend on
+  the tile shape;
+* colour = max(0, 0.5 + sum_k sh_k Y_k(d)), with d the viewing direction in
+  the Gaussian's canonical frame (L^T (mu' - eye), normalised) and Y_k the
+  real orthonormal spherical harmonics without the Condon-Shortley phase;
+* sort key = (tile << 31) | bits(float32(depth)); ties keep emission order
+  (instance-major, then Gaussian, then tiles row-major);
+* the exponent is clamped to <= 0; the splat that would take T below 1e-4 is
+  not added.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+ALPHA_MAX = 0.99
+ALPHA_MIN = 1.0 / 255.0
+T_MIN = 1e-4
+LOWPASS = 0.3
+GUARD = 1.5
+RECT_REL = 1e-4
+RECT_ABS = 0.01
+
+
+# ----------------------------------------------------------------------------
+# spherical harmonics
+# ----------------------------------------------------------------------------
+
+def sh_basis(d: np.ndarray, degree: int) -> np.ndarray:
+    """Real orthonormal SH (no Condon-Shortley phase, polar axis +z) at unit
+    directions d [N,3]; column k = l^2 + l + m. Returns [N,(degree+1)^2]."""
+    d = np.asarray(d, np.float64)
+    x, y, z = d[:, 0], d[:, 1], d[:, 2]
+    pi = math.pi
+    cols = [np.full_like(x, 0.5 * math.sqrt(1.0 / pi))]
+    if degree >= 1:
+        c = math.sqrt(3.0 / (4.0 * pi))
+        cols += [c * y, c * z, c * x]
+    if degree >= 2:
+        cols += [0.5 * math.sqrt(15.0 / pi) * x * y,
+                 0.5 * math.sqrt(15.0 / pi) * y * z,
+                 0.25 * math.sqrt(5.0 / pi) * (3.0 * z * z - 1.0),
+                 0.5 * math.sqrt(15.0 / pi) * x * z,
+                 0.25 * math.sqrt(15.0 / pi) * (x * x - y * y)]
+    if degree >= 3:
+        cols += [0.25 * math.sqrt(35.0 / (2.0 * pi)) * y * (3.0 * x * x - y * y),
+                 0.5 * math.sqrt(105.0 / pi) * x * y * z,
+                 0.25 * math.sqrt(21.0 / (2.0 * pi)) * y * (5.0 * z * z - 1.0),
+                 0.25 * math.sqrt(7.0 / pi) * (5.0 * z ** 3 - 3.0 * z),
+                 0.25 * math.sqrt(21.0 / (2.0 * pi)) * x * (5.0 * z * z - 1.0),
+                 0.25 * math.sqrt(105.0 / pi) * z * (x * x - y * y),
+                 0.25 * math.sqrt(35.0 / (2.0 * pi)) * x * (x * x - 3.0 * y * y)]
+    return np.stack(cols, axis=1)
+
+
+def colour(sh, mu, L, eye, degree: int) -> np.ndarray:
+    """rgb [N,3] = max(0, 0.5 + sum_k sh_k Y_k(normalise(L^T (mu - eye))))."""
+    v = np.asarray(mu, np.float64) - np.asarray(eye, np.float64)
+    d = np.einsum("nji,nj->ni", np.asarray(L, np.float64), v)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    Y = sh_basis(d, degree)
+    sh = np.asarray(sh, np.float64)[:, : (degree + 1) ** 2, :]
+    return np.maximum(0.0, 0.5 + np.einsum("nk,nkc->nc", Y, sh))
+
+
+# ----------------------------------------------------------------------------
+# projection and footprint
+# ----------------------------------------------------------------------------
+
+def project(mu, cov, cam):
+    """EWA projection of posed Gaussians. Returns a dict of FP64 arrays:
+    t (camera-space mean), u, v, cov2d (a, b, c), conic (A, B, C) and the
+    visibility mask after the near-plane, guard-band and determinant culls."""
+    mu = np.asarray(mu, np.float64)
+    cov = np.asarray(cov, np.float64)
+    R = np.asarray(cam.R, np.float64)
+    t = (mu - np.asarray(cam.eye, np.float64)) @ R.T
+    tx, ty, tz = t[:, 0], t[:, 1], t[:, 2]
+    ok = tz > cam.near
+    tzs = np.where(ok, tz, 1.0)
+    xn, yn = tx / tzs, ty / tzs
+    ok &= np.abs(xn) <= GUARD * cam.width / (2.0 * cam.fx)
+    ok &= np.abs(yn) <= GUARD * cam.height / (2.0 * cam.fy)
+    u = cam.fx * xn + cam.cx
+    v = cam.fy * yn + cam.cy
+    J = np.zeros((mu.shape[0], 2, 3))
+    J[:, 0, 0] = cam.fx / tzs
+    J[:, 0, 2] = -cam.fx * tx / (tzs * tzs)
+    J[:, 1, 1] = cam.fy / tzs
+    J[:, 1, 2] = -cam.fy * ty / (tzs * tzs)
+    T = J @ R
+    S = np.einsum("nij,njk,nlk->nil", T, cov, T)
+    a = S[:, 0, 0] + LOWPASS
+    b = S[:, 0, 1]
+    c = S[:, 1, 1] + LOWPASS
+    det = a * c - b * b
+    ok &= det > 0
+    dets = np.where(det > 0, det, 1.0)
+    return dict(t=t, u=u, v=v, depth=tz, a=a, b=b, c=c,
+                A=c / dets, B=-b / dets, C=a / dets, visible=ok)
+
+
+def footprint(u, v, a, c, opacity, visible, width, height, tw, th):
+    """Opacity-aware pixel AABB half-extents, tile rect [x0, y0, x1, y1]
+    (inclusive, in tiles) and tile count; culls alpha-invisible and off-screen
+    splats. Also returns the four pre-floor pixel bounds."""
+    o = np.asarray(opacity, np.float64)
+    vis = np.asarray(visible, bool) & (o >= ALPHA_MIN)
+    k = 2.0 * np.log(np.maximum(255.0 * o, 1.0)) * (1.0 + RECT_REL)
+    rx = np.sqrt(k * a) + RECT_ABS
+    ry = np.sqrt(k * c) + RECT_ABS
+    bounds = np.stack([u - rx, v - ry, u + rx, v + ry], axis=1)
+    px0, py0 = np.floor(u - rx), np.floor(v - ry)
+    px1, py1 = np.floor(u + rx), np.floor(v + ry)
+    vis &= (px1 >= 0) & (px0 <= width - 1) & (py1 >= 0) & (py0 <= height - 1)
+    px0 = np.clip(px0, 0, width - 1).astype(np.int64)
+    px1 = np.clip(px1, 0, width - 1).astype(np.int64)
+    py0 = np.clip(py0, 0, height - 1).astype(np.int64)
+    py1 = np.clip(py1, 0, height - 1).astype(np.int64)
+    rect = np.stack([px0 // tw, py0 // th, px1 // tw, py1 // th], axis=1)
+    count = np.where(vis, (rect[:, 2] - rect[:, 0] + 1) * (rect[:, 3] - rect[:, 1] + 1), 0)
+    return dict(rx=rx, ry=ry, rect=rect, count=count.astype(np.int64),
+                visible=vis, bounds=bounds)
+
+
+# ----------------------------------------------------------------------------
+# binning and the stable (tile | depth) sort
+# ----------------------------------------------------------------------------
+
+def depth_bits(depth) -> np.ndarray:
+    """The IEEE-754 bit pattern of float32(depth) as uint64 (depth > 0)."""
+    return np.asarray(depth, np.float64).astype(np.float32).view(np.uint32).astype(np.uint64)
+
+
+def emit_pairs(rect, count, visible, depth, n_tiles_x):
+    """(key, value) pairs in emission order: splat-major, tiles row-major.
+    key = (tile << 31) | depth bits; value = splat index."""
+    rect = np.asarray(rect, np.int64)
+    splats = np.nonzero(visible)[0]
+    cnt = np.asarray(count, np.int64)[splats]
+    s_rep = np.repeat(splats, cnt)
+    first = np.repeat(np.cumsum(cnt) - cnt, cnt)
+    local = np.arange(s_rep.shape[0], dtype=np.int64) - first
+    width = rect[s_rep, 2] - rect[s_rep, 0] + 1
+    ty = rect[s_rep, 1] + local // width
+    tx = rect[s_rep, 0] + local % width
+    tile = (ty * n_tiles_x + tx).astype(np.uint64)
+    keys = (tile << np.uint64(31)) | depth_bits(depth)[s_rep]
+    return keys, s_rep.astype(np.uint32)
+
+
+def sort_pairs(keys, vals):
+    """Stable ascending sort by key (ties keep emission order)."""
+    order = np.argsort(keys, kind="stable")
+    return keys[order], vals[order]
+
+
+def tile_ranges(sorted_keys, n_tiles: int) -> np.ndarray:
+    """[start, end) into the sorted pairs for every tile, [n_tiles, 2]."""
+    tiles = (np.asarray(sorted_keys, np.uint64) >> np.uint64(31)).astype(np.int64)
+    idx = np.arange(n_tiles)
+    start = np.searchsorted(tiles, idx, side="left")
+    end = np.searchsorted(tiles, idx, side="right")
+    return np.stack([start, end], axis=1)
+
+
+# ----------------------------------------------------------------------------
+# compositing
+# ----------------------------------------------------------------------------
+
+def _blend_list(px, py, order, sp, bg, fragile_alpha, fragile_t):
+    """Front-to-back compositing of the splats ``order`` at pixel centres
+    (px + 1/2, py + 1/2). Returns colour [3,P], final T [P], fragile [P] and
+    the number of splats added per pixel."""
+    P = px.shape[0]
+    T = np.ones(P)
+    C = np.zeros((3, P))
+    done = np.zeros(P, bool)
+    fragile = np.zeros(P, bool)
+    n_added = np.zeros(P, np.int64)
+    cx, cy = px + 0.5, py + 0.5
+    for s in order:
+        if done.all():
+            break
+        dx = cx - sp["u"][s]
+        dy = cy - sp["v"][s]
+        power = -0.5 * (sp["A"][s] * dx * dx + 2.0 * sp["B"][s] * dx * dy
+                        + sp["C"][s] * dy * dy)
+        power = np.minimum(0.0, power)
+        raw = sp["opacity"][s] * np.exp(power)
+        alpha = np.minimum(ALPHA_MAX, raw)
+        live = ~done
+        fragile |= live & (np.abs(raw - ALPHA_MIN) <= fragile_alpha * ALPHA_MIN)
+        use = live & (alpha >= ALPHA_MIN)
+        Tn = T * (1.0 - alpha)
+        fragile |= use & (np.abs(Tn - T_MIN) <= fragile_t * T_MIN)
+        stop = use & (Tn < T_MIN)
+        done |= stop
+        add = use & ~stop
+        C += np.where(add, sp["rgb"][s][:, None] * (alpha * T), 0.0)
+        T = np.where(add, Tn, T)
+        n_added += add
+    C += T[None, :] * np.asarray(bg, np.float64)[:, None]
+    return C, T, fragile, n_added
+
+
+def composite_tiled(sp, sorted_vals, ranges, width, height, tw, th, bg,
+                    fragile_alpha=1e-4, fragile_t=1e-4, tiles=None):
+    """Per-tile front-to-back compositing over each tile's sorted list.
+    Returns image [3,H,W], final transmittance [H,W] and the fragile mask."""
+    ntx = (width + tw - 1) // tw
+    nty = (height + th - 1) // th
+    img = np.zeros((3, height, width))
+    Tfin = np.ones((height, width))
+    frag = np.zeros((height, width), bool)
+    tile_ids = range(ntx * nty) if tiles is None else tiles
+    for t in tile_ids:
+        ty, tx = divmod(int(t), ntx)
+        x0, y0 = tx * tw, ty * th
+        x1, y1 = min(x0 + tw, width), min(y0 + th, height)
+        gy, gx = np.mgrid[y0:y1, x0:x1]
+        s0, s1 = ranges[t]
+        C, T, f, _ = _blend_list(gx.ravel().astype(np.float64), gy.ravel().astype(np.float64),
+                                 sorted_vals[s0:s1], sp, bg, fragile_alpha, fragile_t)
+        img[:, y0:y1, x0:x1] = C.reshape(3, y1 - y0, x1 - x0)
+        Tfin[y0:y1, x0:x1] = T.reshape(y1 - y0, x1 - x0)
+        frag[y0:y1, x0:x1] = f.reshape(y1 - y0, x1 - x0)
+    return img, Tfin, frag
+
+
+def composite_bruteforce(sp, visible, depth, width, height, bg):
+    """Untiled compositing: every pixel walks all visible splats in
+    (float32 depth, splat index) order. Must equal the tiled result exactly."""
+    vis = np.nonzero(visible)[0]
+    order = vis[np.lexsort((vis, depth_bits(depth)[vis]))]
+    gy, gx = np.mgrid[0:height, 0:width]
+    C, T, _, _ = _blend_list(gx.ravel().astype(np.float64), gy.ravel().astype(np.float64),
+                             order, sp, bg, 0.0, 0.0)
+    return C.reshape(3, height, width), T.reshape(height, width)
+
+
+# ----------------------------------------------------------------------------
+# whole frames
+# ----------------------------------------------------------------------------
+
+def splat_records(mu, cov, L, opacity, sh, degree, cam, tw, th):
+    """Project + colour + footprint for a batch of posed Gaussians."""
+    pr = project(mu, cov, cam)
+    fp = footprint(pr["u"], pr["v"], pr["a"], pr["c"], opacity, pr["visible"],
+                   cam.width, cam.height, tw, th)
+    rgb = colour(sh, mu, L, cam.eye, degree)
+    rec = dict(pr)
+    rec.update(fp)
+    rec["opacity"] = np.asarray(opacity, np.float64)
+    rec["rgb"] = rgb
+    return rec
+
+
+def concat_records(parts):
+    out = {}
+    for k in parts[0]:
+        out[k] = np.concatenate([p[k] for p in parts], axis=0)
+    return out
+
+
+def render_records(rec, cam, tw, th, fragile_alpha=1e-4, fragile_t=1e-4):
+    """Bin, sort and composite concatenated splat records (in emission order)."""
+    ntx = (cam.width + tw - 1) // tw
+    nty = (cam.height + th - 1) // th
+    keys, vals = emit_pairs(rec["rect"], rec["count"], rec["visible"], rec["depth"], ntx)
+    skeys, svals = sort_pairs(keys, vals)
+    ranges = tile_ranges(skeys, ntx * nty)
+    img, T, frag = composite_tiled(rec, svals, ranges, cam.width, cam.height, tw, th,
+                                   cam.bg, fragile_alpha, fragile_t)
+    return dict(image=img, T=T, fragile=frag, keys=keys, vals=vals,
+                sorted_keys=skeys, sorted_vals=svals, ranges=ranges)
