@@ -1,0 +1,260 @@
+/*
+ * crowdsplat.h - C ABI of the MI355X (gfx950) crowd-splatting hot path.
+ *
+ * The library renders a crowd of animated 3D-Gaussian avatars into one frame,
+ * the second stage of CrowdSplat (arXiv 2501.17792, §2 and Fig. 2):
+ *   - every character instances one of a few canonical Gaussian templates
+ *     whose attributes are shared across instances (§2, shared attributes);
+ *   - each instance is posed by linear blend skinning of a 24-joint skeleton
+ *     (§2, Fig. 2 stage 2);
+ *   - each instance draws an importance-ordered prefix of its template chosen
+ *     by a level-of-detail rule (§2, last paragraph: levels by camera distance);
+ *   - all instances are splatted together with the 3D Gaussian Splatting
+ *     rasteriser (EWA projection, tile binning, a (tile|depth) sort and
+ *     front-to-back alpha compositing) that CrowdSplat §2 builds on.
+ *
+ * Conventions shared by every call:
+ *   - All functions return cs_status (0 = CS_OK, < 0 = error). Nothing throws
+ *     or aborts across the ABI. cs_last_error() gives a message.
+ *   - "device" pointers are HIP device pointers on the context's device; the
+ *     caller owns every buffer it passes and keeps it alive until the work
+ *     enqueued on the context's stream has finished.
+ *   - Work is enqueued on the context's stream and is asynchronous unless a
+ *     call says otherwise. Host inputs are consumed before the call returns.
+ *   - One context per stream; a context is not thread-safe.
+ *   - Per-frame call order: cs_select_lod -> cs_skin_instances ->
+ *     cs_render_frame [-> cs_render_backward]. Out-of-order calls return
+ *     CS_ERR_STATE.
+ */
+#ifndef CROWDSPLAT_H
+#define CROWDSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cs_status;
+#define CS_OK               0
+#define CS_ERR_INVALID     -1  /* bad argument (null pointer, size, range)       */
+#define CS_ERR_OOM         -2  /* device allocation failed                        */
+#define CS_ERR_DEVICE      -3  /* a HIP call failed; message has hipGetErrorString */
+#define CS_ERR_CAPACITY    -4  /* frame exceeded a fixed capacity (graph mode)    */
+#define CS_ERR_STATE       -5  /* call out of order                               */
+#define CS_ERR_UNSUPPORTED -6  /* valid request the library does not implement    */
+
+#define CS_MEM_HOST   0
+#define CS_MEM_DEVICE 1
+
+#define CS_SKIN_FULL        0  /* Sigma' = L Sigma L^T with L the blended linear part */
+#define CS_SKIN_MEANS_ONLY  1  /* only means skinned; Sigma' = R_y Sigma R_y^T        */
+
+#define CS_LAUNCH_BATCHED       0  /* one launch per stage over all instances   */
+#define CS_LAUNCH_PER_INSTANCE  1  /* one launch per instance per stage (plain) */
+
+#define CS_LOD_FULL    0  /* every instance at level 0                           */
+#define CS_LOD_FIXED   1  /* level = number of distance thresholds <= distance   */
+#define CS_LOD_LEARNED 2  /* coarsest level whose predicted PSNR clears a floor  */
+
+#define CS_MAX_LEVELS     8
+#define CS_MAX_TEMPLATES  64
+#define CS_JOINTS         24
+
+typedef struct cs_ctx cs_ctx;
+
+/* Context options. Zero-initialise and set what you need; zeros mean defaults. */
+typedef struct cs_options {
+  int32_t tile_w;            /* tile width in pixels: 8, 16 or 32 (default 16)  */
+  int32_t tile_h;            /* tile height in pixels: 8, 16 or 32 (default 16) */
+  int32_t skin_mode;         /* CS_SKIN_*                                       */
+  int32_t launch_mode;       /* CS_LAUNCH_*                                     */
+  int32_t fuse_skin_project; /* 1: cs_render_frame skins inline (same numbers)  */
+  int32_t reserved0;
+  int64_t max_splats;        /* fixed splat capacity (0: grow on demand)        */
+  int64_t max_pairs;         /* fixed tile-pair capacity (0: grow on demand)    */
+  int32_t reserved[8];
+} cs_options;
+
+/* One canonical template (CrowdSplat §2: shared template attributes).
+ * Arrays of n_gauss rows; the Gaussians must already be in importance order
+ * so that level l is the prefix [0, level_count[l]). The library copies
+ * everything at upload; quaternions need not be unit length. */
+typedef struct cs_template_desc {
+  int32_t n_gauss;           /* > 0                                             */
+  int32_t sh_degree;         /* 0..3                                            */
+  int32_t n_levels;          /* 1..CS_MAX_LEVELS                                */
+  int32_t reserved0;
+  const int32_t* level_count;/* HOST [n_levels], non-increasing, [0] == n_gauss */
+  const float* mean;         /* [N][3] canonical means (m)                      */
+  const float* log_scale;    /* [N][3] log standard deviations                  */
+  const float* quat;         /* [N][4] rotation (w, x, y, z)                    */
+  const float* opacity;      /* [N] in (0, 1)                                   */
+  const float* sh;           /* [N][(sh_degree+1)^2][3] real SH coefficients    */
+  const uint8_t* skin_idx;   /* [N][4] driving joint of each bone (< 24)        */
+  const float* skin_w;       /* [N][4] blend weights (used as given)            */
+  const float* joints_rest;  /* HOST [24][3] rest joint positions               */
+  const int32_t* parents;    /* HOST [24] parent joint, parents[0] = -1, p < j  */
+} cs_template_desc;
+
+/* One character instance: template id and its placement on the ground plane. */
+typedef struct cs_instance {
+  int32_t tid;               /* template index                                  */
+  float yaw;                 /* rotation about +y (rad)                         */
+  float px, pz;              /* position on the plane y = 0 (m)                 */
+} cs_instance;
+
+/* Pinhole camera. World y is up; camera x right, y down, z forward. */
+typedef struct cs_camera {
+  int32_t width, height;     /* pixels, 1..8192                                 */
+  float fx, fy, cx, cy;      /* focal lengths and principal point (pixels)      */
+  float eye[3];              /* camera centre in the world                      */
+  float R[9];                /* row-major world->camera rotation               */
+  float near_plane;          /* Gaussians with depth <= near are culled (m)     */
+  float bg[3];               /* background colour                               */
+} cs_camera;
+
+/* Level-of-detail rule (CrowdSplat §2, last paragraph). */
+typedef struct cs_lod_params {
+  int32_t mode;              /* CS_LOD_*                                        */
+  int32_t n_thresholds;      /* FIXED: 0..7 increasing distances (m)            */
+  float thresholds[7];
+  float psnr_min;            /* LEARNED: quality floor (dB)                     */
+  float margin;              /* LEARNED: extra dB required of the prediction    */
+  const void* mlp;           /* LEARNED: device pointer, layout of cs_mlp_pack  */
+} cs_lod_params;
+
+typedef struct cs_frame_stats {
+  int64_t n_splats;          /* instance-Gaussians skinned this frame           */
+  int64_t n_visible;         /* splats that emitted at least one tile pair      */
+  int64_t n_pairs;           /* (tile, splat) pairs sorted                      */
+  int32_t overflow;          /* nonzero: a fixed capacity was exceeded          */
+  int32_t n_instances;
+  int32_t level_hist[CS_MAX_LEVELS];
+} cs_frame_stats;
+
+/* Context lifetime. stream: a hipStream_t (NULL = the null stream). */
+cs_status cs_create(int32_t device, void* stream, const cs_options* opt, cs_ctx** out);
+void cs_destroy(cs_ctx* ctx); /* NULL-safe; waits for the stream */
+const char* cs_last_error(const cs_ctx* ctx); /* owned by ctx; valid until the next call */
+const char* cs_version(void);
+
+/*
+ * Upload n_templates canonical templates (CrowdSplat §2: the attributes other
+ * than the posed means are shared by all characters of a template). mem says
+ * whether the per-Gaussian arrays are HOST or DEVICE memory (level_count,
+ * joints_rest and parents are always host). Replaces any earlier templates.
+ * Precomputes each canonical covariance R(q) diag(exp(2 s)) R(q)^T.
+ * Errors: CS_ERR_INVALID (sizes, degrees, level counts), CS_ERR_OOM.
+ */
+cs_status cs_upload_templates(cs_ctx* ctx, const cs_template_desc* t, int32_t n_templates,
+                              int32_t mem);
+
+/*
+ * Choose each instance's level (CrowdSplat §2, last paragraph) and build the
+ * frame's work list: instance i draws the first level_count[level_i] Gaussians
+ * of its template; instance-major concatenation defines every splat's index.
+ *   inst     DEVICE [n_inst] cs_instance
+ *   pose     DEVICE [n_inst][24][3] axis-angle per joint (read by LEARNED only)
+ *   cam      HOST camera (distance and screen features)
+ *   lod      HOST rule; FIXED: level = number of thresholds <= distance from the
+ *            eye to (px, 0, pz); FULL: 0; LEARNED: see cs_mlp_pack.
+ *   level_out DEVICE [n_inst] int32 levels, or NULL.
+ * Errors: CS_ERR_STATE (no templates), CS_ERR_INVALID (n_inst <= 0, bad tid is
+ * reported later as overflow bit 4), CS_ERR_CAPACITY (graph mode: too many
+ * instances).
+ */
+cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, const float* pose,
+                        const cs_camera* cam, const cs_lod_params* lod, int32_t* level_out);
+
+/*
+ * Pose the selected prefixes (CrowdSplat §2, Fig. 2 stage 2): forward
+ * kinematics of each instance's skeleton (Rodrigues rotations composed down the
+ * tree, placed by R_y(yaw) and (px, 0, pz)), then per Gaussian
+ * M = sum_k w_k B_{idx_k}, mu' = M [mu; 1], Sigma' = L Sigma L^T.
+ *   inst, pose as in cs_select_lod (same n_inst).
+ * Writes the posed means and covariances into the context (one slot per
+ * selected instance-Gaussian). Errors: CS_ERR_STATE (no cs_select_lod).
+ */
+cs_status cs_skin_instances(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst,
+                            const float* pose);
+
+/*
+ * Render all posed instances into one frame (3D Gaussian Splatting as used in
+ * CrowdSplat §2): EWA projection with SH colour, opacity-aware footprint and
+ * tile binning, a stable sort by (tile << 31 | float bits of depth), per-tile
+ * ranges, and front-to-back compositing (alpha = min(0.99, o exp(power)),
+ * alpha < 1/255 skipped, stop before T < 1e-4).
+ *   image  DEVICE [3][height][width] float32, written completely.
+ *   stats  HOST, optional; if non-NULL the call synchronises the stream.
+ * Errors: CS_ERR_STATE (no skin), CS_ERR_INVALID (camera), CS_ERR_CAPACITY
+ * (fixed capacity exceeded; needed sizes in stats).
+ */
+cs_status cs_render_frame(cs_ctx* ctx, const cs_camera* cam, float* image, cs_frame_stats* stats);
+
+/* Template gradients, DEVICE buffers owned by the caller, each zero-filled and
+ * then written by cs_render_backward. Any pointer may be NULL (not wanted). */
+typedef struct cs_template_grads {
+  int32_t template_id;       /* which uploaded template                        */
+  int32_t reserved0;
+  float* mean;               /* [N][3]                                         */
+  float* log_scale;          /* [N][3]                                         */
+  float* quat;               /* [N][4] w.r.t. the stored (unnormalised) quat   */
+  float* opacity_logit;      /* [N]    w.r.t. logit(opacity)                   */
+  float* sh;                 /* [N][(d+1)^2][3]                                */
+} cs_template_grads;
+
+/*
+ * Backward of the last cs_render_frame with respect to one template's
+ * attributes (the reconstruction stage of CrowdSplat §2 fits templates by
+ * gradient descent through this renderer). Every discrete decision of the
+ * forward (culls, rects, order, skips, stop, clamp) is held fixed. Per-tile
+ * forward recompute, per-pair contributions reduced in a fixed order
+ * (deterministic). dL_dimage DEVICE [3][H][W].
+ * Errors: CS_ERR_STATE (no forward), CS_ERR_INVALID.
+ */
+cs_status cs_render_backward(cs_ctx* ctx, const float* dL_dimage, cs_template_grads* g);
+
+/* ---- batching: whole-frame graph capture ---------------------------------
+ * Capture select_lod -> skin -> render for fixed pointers and sizes into a
+ * hipGraph on the context's stream, with the capacities currently reserved
+ * (cs_reserve). cs_frame_launch replays it; read overflow with cs_frame_poll.
+ */
+cs_status cs_reserve(cs_ctx* ctx, int64_t max_instances, int64_t max_splats, int64_t max_pairs);
+cs_status cs_frame_capture(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, const float* pose,
+                           const cs_camera* cam, const cs_lod_params* lod, float* image);
+cs_status cs_frame_launch(cs_ctx* ctx);
+cs_status cs_frame_poll(cs_ctx* ctx, cs_frame_stats* stats); /* synchronises */
+
+/* ---- introspection (tests, profiling) ------------------------------------
+ * Copy an internal device buffer of the last frame to host memory (synchronous).
+ * which: one of CS_BUF_*; offset and bytes in bytes. */
+#define CS_BUF_BONES     1  /* float [n_inst][24][12]   row-major 3x4 B_ij          */
+#define CS_BUF_LEVEL     2  /* int32 [n_inst]                                        */
+#define CS_BUF_OFFSET    3  /* uint32 [n_inst+1] splat offset of each instance       */
+#define CS_BUF_SKIN_MU   4  /* float [n_splats][4] posed mean xyz, Sigma'_xx        */
+#define CS_BUF_SKIN_COV  5  /* float [n_splats][4] Sigma'_xy xz yy yz               */
+#define CS_BUF_SKIN_COV2 6  /* float [n_splats] Sigma'_zz                            */
+#define CS_BUF_RECORD    7  /* float [n_splats][12] u v A B | C o r g | b rx ry depth */
+#define CS_BUF_RECT      8  /* uint32 [n_splats] tile rect x0|y0<<8|x1<<16|y1<<24    */
+#define CS_BUF_COUNT     9  /* uint32 [n_splats] pairs emitted (0 = culled)          */
+#define CS_BUF_PAIR_OFF 10  /* uint32 [n_splats] exclusive scan of COUNT             */
+#define CS_BUF_KEYS     11  /* uint64 [n_pairs] emitted keys (emission order)        */
+#define CS_BUF_VALS     12  /* uint32 [n_pairs] emitted splat indices                */
+#define CS_BUF_SKEYS    13  /* uint64 [n_pairs] sorted keys                          */
+#define CS_BUF_SVALS    14  /* uint32 [n_pairs] sorted splat indices                 */
+#define CS_BUF_RANGES   15  /* uint32 [n_tiles][2] [start, end) per tile            */
+#define CS_BUF_FEATURES 16  /* float [n_inst][32] learned-LoD features               */
+#define CS_BUF_PRED     17  /* float [n_inst][8] learned-LoD predicted PSNR          */
+cs_status cs_debug_copy(cs_ctx* ctx, int32_t which, void* host_dst, int64_t offset, int64_t bytes);
+
+/* Stable LSD radix sort of (key, value) pairs by the low key_bits bits of key,
+ * the same onesweep kernels that order the frame's tile pairs. DEVICE buffers;
+ * keys/vals are sorted in place (the context's pair buffers are the scratch). */
+cs_status cs_sort_pairs(cs_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CROWDSPLAT_H */

@@ -1,0 +1,291 @@
+"""ctypes binding of libcrowdsplat.so (the C ABI in include/crowdsplat.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels. torch supplies device memory (tensors) and the stream. If the
+library has not been built, importing the binding raises; there is no other
+implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcrowdsplat.so")
+
+CS_OK = 0
+CS_ERR_INVALID, CS_ERR_OOM, CS_ERR_DEVICE, CS_ERR_CAPACITY, CS_ERR_STATE, CS_ERR_UNSUPPORTED = -1, -2, -3, -4, -5, -6
+CS_MEM_HOST, CS_MEM_DEVICE = 0, 1
+CS_SKIN_FULL, CS_SKIN_MEANS_ONLY = 0, 1
+CS_LAUNCH_BATCHED, CS_LAUNCH_PER_INSTANCE = 0, 1
+CS_LOD_FULL, CS_LOD_FIXED, CS_LOD_LEARNED = 0, 1, 2
+CS_MAX_LEVELS = 8
+
+BUF = dict(BONES=1, LEVEL=2, OFFSET=3, SKIN_MU=4, SKIN_COV=5, SKIN_COV2=6, RECORD=7, RECT=8,
+           COUNT=9, PAIR_OFF=10, KEYS=11, VALS=12, SKEYS=13, SVALS=14, RANGES=15, FEATURES=16,
+           PRED=17)
+
+#: every symbol include/crowdsplat.h declares
+EXPORTS = ["cs_create", "cs_destroy", "cs_last_error", "cs_version", "cs_upload_templates",
+           "cs_select_lod", "cs_skin_instances", "cs_render_frame", "cs_render_backward",
+           "cs_reserve", "cs_frame_capture", "cs_frame_launch", "cs_frame_poll", "cs_debug_copy",
+           "cs_sort_pairs"]
+
+
+class CsOptions(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
+                ("skin_mode", ctypes.c_int32), ("launch_mode", ctypes.c_int32),
+                ("fuse_skin_project", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("max_splats", ctypes.c_int64), ("max_pairs", ctypes.c_int64),
+                ("reserved", ctypes.c_int32 * 8)]
+
+
+class CsTemplateDesc(ctypes.Structure):
+    _fields_ = [("n_gauss", ctypes.c_int32), ("sh_degree", ctypes.c_int32),
+                ("n_levels", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("level_count", ctypes.c_void_p), ("mean", ctypes.c_void_p),
+                ("log_scale", ctypes.c_void_p), ("quat", ctypes.c_void_p),
+                ("opacity", ctypes.c_void_p), ("sh", ctypes.c_void_p),
+                ("skin_idx", ctypes.c_void_p), ("skin_w", ctypes.c_void_p),
+                ("joints_rest", ctypes.c_void_p), ("parents", ctypes.c_void_p)]
+
+
+class CsCamera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float),
+                ("cy", ctypes.c_float), ("eye", ctypes.c_float * 3), ("R", ctypes.c_float * 9),
+                ("near_plane", ctypes.c_float), ("bg", ctypes.c_float * 3)]
+
+
+class CsLodParams(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("n_thresholds", ctypes.c_int32),
+                ("thresholds", ctypes.c_float * 7), ("psnr_min", ctypes.c_float),
+                ("margin", ctypes.c_float), ("mlp", ctypes.c_void_p)]
+
+
+class CsFrameStats(ctypes.Structure):
+    _fields_ = [("n_splats", ctypes.c_int64), ("n_visible", ctypes.c_int64),
+                ("n_pairs", ctypes.c_int64), ("overflow", ctypes.c_int32),
+                ("n_instances", ctypes.c_int32), ("level_hist", ctypes.c_int32 * CS_MAX_LEVELS)]
+
+
+class CsTemplateGrads(ctypes.Structure):
+    _fields_ = [("template_id", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("mean", ctypes.c_void_p), ("log_scale", ctypes.c_void_p),
+                ("quat", ctypes.c_void_p), ("opacity_logit", ctypes.c_void_p),
+                ("sh", ctypes.c_void_p)]
+
+
+INSTANCE_DTYPE = np.dtype([("tid", "<i4"), ("yaw", "<f4"), ("px", "<f4"), ("pz", "<f4")])
+
+
+class CrowdSplatError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"crowdsplat error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the built library (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run paper_2501_17792_amd/build.py "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "cs_create": (i32, [i32, P, ctypes.POINTER(CsOptions), ctypes.POINTER(P)]),
+        "cs_destroy": (None, [P]),
+        "cs_last_error": (ctypes.c_char_p, [P]),
+        "cs_version": (ctypes.c_char_p, []),
+        "cs_upload_templates": (i32, [P, ctypes.POINTER(CsTemplateDesc), i32, i32]),
+        "cs_select_lod": (i32, [P, i32, P, P, ctypes.POINTER(CsCamera), ctypes.POINTER(CsLodParams), P]),
+        "cs_skin_instances": (i32, [P, i32, P, P]),
+        "cs_render_frame": (i32, [P, ctypes.POINTER(CsCamera), P, ctypes.POINTER(CsFrameStats)]),
+        "cs_render_backward": (i32, [P, P, ctypes.POINTER(CsTemplateGrads)]),
+        "cs_reserve": (i32, [P, i64, i64, i64]),
+        "cs_frame_capture": (i32, [P, i32, P, P, ctypes.POINTER(CsCamera), ctypes.POINTER(CsLodParams), P]),
+        "cs_frame_launch": (i32, [P]),
+        "cs_frame_poll": (i32, [P, ctypes.POINTER(CsFrameStats)]),
+        "cs_debug_copy": (i32, [P, i32, P, i64, i64]),
+        "cs_sort_pairs": (i32, [P, P, P, i64, i32]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def camera_struct(cam) -> CsCamera:
+    c = CsCamera()
+    c.width, c.height = int(cam.width), int(cam.height)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.eye[:] = [float(v) for v in np.asarray(cam.eye, np.float32)]
+    c.R[:] = [float(v) for v in np.asarray(cam.R, np.float32).ravel()]
+    c.near_plane = float(cam.near)
+    c.bg[:] = [float(v) for v in np.asarray(cam.bg, np.float32)]
+    return c
+
+
+def lod_struct(mode: int, thresholds: Sequence[float] = (), psnr_min: float = 40.0,
+               margin: float = 1.0, mlp_ptr: int = 0) -> CsLodParams:
+    p = CsLodParams()
+    p.mode = mode
+    p.n_thresholds = len(thresholds)
+    for k, t in enumerate(thresholds):
+        p.thresholds[k] = float(t)
+    p.psnr_min = psnr_min
+    p.margin = margin
+    p.mlp = mlp_ptr or None
+    return p
+
+
+def instance_bytes(crowd) -> np.ndarray:
+    a = np.zeros(crowd.n, INSTANCE_DTYPE)
+    a["tid"] = crowd.tid
+    a["yaw"] = crowd.yaw
+    a["px"] = crowd.pos[:, 0]
+    a["pz"] = crowd.pos[:, 1]
+    return a
+
+
+class Renderer:
+    """One library context on one device and stream."""
+
+    def __init__(self, device: int = 0, stream=None, tile=(16, 16), skin_mode=CS_SKIN_FULL,
+                 launch_mode=CS_LAUNCH_BATCHED, fuse=False, max_splats=0, max_pairs=0):
+        import torch
+        self.torch = torch
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        opt = CsOptions()
+        opt.tile_w, opt.tile_h = tile
+        opt.skin_mode, opt.launch_mode, opt.fuse_skin_project = skin_mode, launch_mode, int(fuse)
+        opt.max_splats, opt.max_pairs = max_splats, max_pairs
+        self.tile = tuple(tile)
+        ctx = ctypes.c_void_p()
+        self._check(self.lib.cs_create(device, ctypes.c_void_p(self.stream.cuda_stream),
+                                       ctypes.byref(opt), ctypes.byref(ctx)), None)
+        self.ctx = ctx
+        self._keep = []
+        self.templates = None
+
+    # ------------------------------------------------------------------ util
+    def _check(self, status: int, ctx=None):
+        if status != CS_OK:
+            c = ctx if ctx is not None else getattr(self, "ctx", None)
+            msg = self.lib.cs_last_error(c).decode() if c else "(no context)"
+            raise CrowdSplatError(status, msg)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.cs_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def to_device(self, arr: np.ndarray):
+        t = self.torch.from_numpy(np.ascontiguousarray(arr).view(np.uint8).reshape(-1).copy())
+        return t.to(self.device)
+
+    # ------------------------------------------------------------------ calls
+    def upload_templates(self, templates, mem=CS_MEM_HOST):
+        descs = (CsTemplateDesc * len(templates))()
+        keep = []
+        for d, t in zip(descs, templates):
+            arrs = dict(level_count=np.ascontiguousarray(t.level_count, np.int32),
+                        mean=np.ascontiguousarray(t.mean, np.float32),
+                        log_scale=np.ascontiguousarray(t.log_scale, np.float32),
+                        quat=np.ascontiguousarray(t.quat, np.float32),
+                        opacity=np.ascontiguousarray(t.opacity, np.float32),
+                        sh=np.ascontiguousarray(t.sh, np.float32),
+                        skin_idx=np.ascontiguousarray(t.skin_idx, np.uint8),
+                        skin_w=np.ascontiguousarray(t.skin_w, np.float32),
+                        joints_rest=np.ascontiguousarray(t.joints_rest, np.float32),
+                        parents=np.ascontiguousarray(t.parents, np.int32))
+            keep.append(arrs)
+            d.n_gauss, d.sh_degree, d.n_levels = t.n, t.sh_degree, len(t.level_count)
+            for k, a in arrs.items():
+                setattr(d, k, a.ctypes.data)
+        self._check(self.lib.cs_upload_templates(self.ctx, descs, len(templates), mem))
+        self.templates = templates
+
+    def set_crowd(self, crowd):
+        """Device copies of the instance table and poses (kept alive here)."""
+        self.inst_dev = self.to_device(instance_bytes(crowd))
+        self.pose_dev = self.torch.from_numpy(np.ascontiguousarray(crowd.pose, np.float32)).to(self.device)
+        self.n_inst = crowd.n
+
+    def select_lod(self, cam, mode=CS_LOD_FIXED, thresholds=(10.0, 25.0), level_out=None,
+                   psnr_min=40.0, margin=1.0, mlp_ptr=0):
+        c = camera_struct(cam)
+        p = lod_struct(mode, thresholds, psnr_min, margin, mlp_ptr)
+        self._check(self.lib.cs_select_lod(self.ctx, self.n_inst, self.inst_dev.data_ptr(),
+                                           self.pose_dev.data_ptr(), ctypes.byref(c), ctypes.byref(p),
+                                           level_out.data_ptr() if level_out is not None else None))
+
+    def skin(self):
+        self._check(self.lib.cs_skin_instances(self.ctx, self.n_inst, self.inst_dev.data_ptr(),
+                                               self.pose_dev.data_ptr()))
+
+    def render(self, cam, image=None, stats: bool = False):
+        torch = self.torch
+        if image is None:
+            image = torch.empty((3, cam.height, cam.width), dtype=torch.float32, device=self.device)
+        c = camera_struct(cam)
+        st = CsFrameStats()
+        self._check(self.lib.cs_render_frame(self.ctx, ctypes.byref(c), image.data_ptr(),
+                                             ctypes.byref(st) if stats else None))
+        self.last_stats = st if stats else None
+        return image
+
+    def frame(self, cam, mode=CS_LOD_FIXED, thresholds=(10.0, 25.0), image=None, stats=False):
+        self.select_lod(cam, mode, thresholds)
+        self.skin()
+        return self.render(cam, image, stats)
+
+    def reserve(self, max_instances=0, max_splats=0, max_pairs=0):
+        self._check(self.lib.cs_reserve(self.ctx, max_instances, max_splats, max_pairs))
+
+    def capture(self, cam, image, mode=CS_LOD_FIXED, thresholds=(10.0, 25.0), mlp_ptr=0,
+                psnr_min=40.0, margin=1.0):
+        c = camera_struct(cam)
+        p = lod_struct(mode, thresholds, psnr_min, margin, mlp_ptr)
+        self._keep = [c, p]
+        self._check(self.lib.cs_frame_capture(self.ctx, self.n_inst, self.inst_dev.data_ptr(),
+                                              self.pose_dev.data_ptr(), ctypes.byref(c),
+                                              ctypes.byref(p), image.data_ptr()))
+
+    def launch(self):
+        self._check(self.lib.cs_frame_launch(self.ctx))
+
+    def poll(self) -> CsFrameStats:
+        st = CsFrameStats()
+        self._check(self.lib.cs_frame_poll(self.ctx, ctypes.byref(st)))
+        return st
+
+    def debug(self, name: str, dtype, count: int, offset: int = 0) -> np.ndarray:
+        out = np.empty(count, dtype)
+        self._check(self.lib.cs_debug_copy(self.ctx, BUF[name], out.ctypes.data,
+                                           offset * out.itemsize, out.nbytes))
+        return out
+
+    def sort_pairs(self, keys, vals, key_bits: int):
+        self._check(self.lib.cs_sort_pairs(self.ctx, keys.data_ptr(), vals.data_ptr(),
+                                           keys.numel(), key_bits))

@@ -1,0 +1,112 @@
+// A9: per-tile front-to-back alpha compositing (3D Gaussian Splatting's
+// rasteriser, used by CrowdSplat §2): for every pixel centre, walk the tile's
+// depth-sorted splats; alpha = min(0.99, o exp(power)) with the exponent
+// clamped to <= 0; alpha < 1/255 is skipped; the splat that would take the
+// transmittance below 1e-4 stops the pixel without being added.
+//
+// One block per tile, one thread per pixel; splat records are staged in LDS
+// in batches of one per thread. A wave skips a splat whose alpha >= 1/255 box
+// misses all of the wave's pixel centres (a decision every pixel would have
+// taken on its own, so the image does not depend on tile or wave shape).
+#include "cs_internal.h"
+
+namespace cs {
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restrict__ ranges,
+                                                       const uint32_t* __restrict__ svals,
+                                                       const float4* __restrict__ rec, CamDev cam,
+                                                       float* __restrict__ image,
+                                                       const FrameHdr* __restrict__ hdr) {
+  constexpr int N = TW * TH;
+  constexpr int ROWS = 64 / TW;  // pixel rows per wave
+  __shared__ float4 s_r0[N], s_r1[N], s_r2[N];
+  const int tile = blockIdx.x;
+  const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+  const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
+  const int px = tx * TW + lx, py = ty * TH + ly;
+  const bool inside = px < cam.W && py < cam.H;
+  const float pcx = (float)px + 0.5f, pcy = (float)py + 0.5f;
+  const int wave = threadIdx.x >> 6;
+  const float wx0 = (float)(tx * TW) + 0.5f, wx1 = (float)(tx * TW + TW - 1) + 0.5f;
+  const float wy0 = (float)(ty * TH + wave * ROWS) + 0.5f, wy1 = wy0 + (float)(ROWS - 1);
+  const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
+  const uint32_t n_splats = hdr->n_splats;
+  float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
+  bool done = !inside;
+  for (uint32_t b = start; b < end; b += N) {
+    const uint32_t idx = b + threadIdx.x;
+    if (idx < end) {
+      const uint32_t s = svals[idx];
+      if (s < n_splats) {
+        s_r0[threadIdx.x] = rec[3 * (size_t)s];
+        s_r1[threadIdx.x] = rec[3 * (size_t)s + 1];
+        s_r2[threadIdx.x] = rec[3 * (size_t)s + 2];
+      } else {  // never produced by a correct sort; drawn as nothing
+        s_r0[threadIdx.x] = make_float4(-1e30f, -1e30f, 0.f, 0.f);
+        s_r1[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_r2[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    }
+    __syncthreads();
+    const int cnt = (int)min((uint32_t)N, end - b);
+    if (__ballot(!done) != 0ull) {
+      for (int j = 0; j < cnt; ++j) {
+        const float4 r0 = s_r0[j];  // u v A B
+        const float4 r2 = s_r2[j];  // b rx ry depth
+        if (r0.x + r2.y < wx0 || r0.x - r2.y > wx1 || r0.y + r2.z < wy0 || r0.y - r2.z > wy1) continue;
+        if (done) continue;
+        const float4 r1 = s_r1[j];  // C o r g
+        const float dx = pcx - r0.x, dy = pcy - r0.y;
+        float power = -0.5f * fmaf(r0.z * dx, dx, r1.x * dy * dy) - r0.w * dx * dy;
+        power = fminf(power, 0.f);
+        const float alpha = fminf(0.99f, r1.y * __expf(power));
+        if (alpha < (1.f / 255.f)) continue;
+        const float Tn = T * (1.f - alpha);
+        if (Tn < 1e-4f) {
+          done = true;
+          continue;
+        }
+        const float wgt = alpha * T;
+        cr = fmaf(r1.z, wgt, cr);
+        cg = fmaf(r1.w, wgt, cg);
+        cb = fmaf(r2.x, wgt, cb);
+        T = Tn;
+      }
+    }
+    if (__syncthreads_count(!done) == 0) break;
+  }
+  if (inside) {
+    const size_t plane = (size_t)cam.W * cam.H;
+    const size_t o = (size_t)py * cam.W + px;
+    image[o] = fmaf(T, cam.bg[0], cr);
+    image[plane + o] = fmaf(T, cam.bg[1], cg);
+    image[2 * plane + o] = fmaf(T, cam.bg[2], cb);
+  }
+}
+
+template <int TW, int TH>
+static hipError_t launch_blend_t(const uint32_t* ranges, const uint32_t* svals, const float4* rec,
+                                 CamDev cam, float* image, const FrameHdr* hdr, hipStream_t st) {
+  blend_kernel<TW, TH><<<cam.tiles_x * cam.tiles_y, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr);
+  return hipGetLastError();
+}
+
+hipError_t launch_blend(const uint32_t* ranges, const uint32_t* svals, const float4* rec, CamDev cam,
+                        float* image, const FrameHdr* hdr, hipStream_t st) {
+#define CS_BLEND_CASE(W_, H_) \
+  if (cam.tw == W_ && cam.th == H_) return launch_blend_t<W_, H_>(ranges, svals, rec, cam, image, hdr, st);
+  CS_BLEND_CASE(8, 8)
+  CS_BLEND_CASE(8, 16)
+  CS_BLEND_CASE(8, 32)
+  CS_BLEND_CASE(16, 8)
+  CS_BLEND_CASE(16, 16)
+  CS_BLEND_CASE(16, 32)
+  CS_BLEND_CASE(32, 8)
+  CS_BLEND_CASE(32, 16)
+  CS_BLEND_CASE(32, 32)
+#undef CS_BLEND_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace cs

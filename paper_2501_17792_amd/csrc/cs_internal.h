@@ -1,0 +1,141 @@
+// Internal declarations shared by the HIP kernel files and the runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "crowdsplat.h"
+
+namespace cs {
+
+constexpr int kJoints = 24;
+constexpr int kChunk = 1024;          // Gaussians per work chunk (one instance each)
+constexpr int kChunkThreads = 256;    // threads per skin / project block
+constexpr int kMaxLevels = CS_MAX_LEVELS;
+constexpr int kMaxTemplates = CS_MAX_TEMPLATES;
+constexpr int kSortBits = 11;         // radix digit width of the onesweep passes
+constexpr int kSortBins = 1 << kSortBits;
+constexpr int kMaxPasses = 5;         // 31 depth bits + up to 24 tile bits
+constexpr int kFeat = 32;             // learned-LoD feature width (31 used + pad)
+constexpr int kMlpHidden = 64;
+constexpr int kMlpOut = 8;            // 5 levels used, padded
+
+// Device-side view of one uploaded template (structure of arrays).
+struct TemplateDev {
+  const float4* mean_idx;  // xyz, w = bit pattern of the 4 packed u8 skin indices
+  const float4* skin_w;    // 4 blend weights
+  const float4* cov_a;     // Sigma xx xy xz yy
+  const float2* cov_b;     // Sigma yz zz
+  const float* opacity;
+  const float4* sh;        // [n_sh4 planes][n] float4 of flattened [(d+1)^2][3] coefficients
+  int32_t n;
+  int32_t sh_degree;
+  int32_t n_sh4;
+  int32_t n_levels;
+  int32_t level_count[kMaxLevels];
+  float joints[kJoints * 3];
+  int32_t parents[kJoints];
+  float pad_radius;        // rest-pose bound: max distance of a mean from its nearest joint + 3 sigma
+  float rest_height;
+};
+
+// Per-frame device header. Counters are reset by a kernel at the start of a frame.
+struct FrameHdr {
+  uint32_t n_inst;
+  uint32_t n_splats;
+  uint32_t n_chunks;
+  uint32_t n_pairs;        // pairs requested (may exceed capacity)
+  uint32_t n_visible;
+  uint32_t overflow;       // bit 0 splats, bit 1 pairs, bit 2 instances, bit 3 chunks, bit 4 bad tid
+  uint32_t epoch;          // incremented per frame; tags look-back entries
+  uint32_t frame;
+  uint32_t ticket[8];      // onesweep partition tickets per pass
+  uint32_t level_hist[kMaxLevels];
+  uint32_t pad[8];
+};
+
+struct Chunk {
+  int32_t inst;
+  int32_t g0;
+};
+
+// Camera constants passed by value to kernels.
+struct CamDev {
+  float R[9];
+  float eye[3];
+  float fx, fy, cx, cy;
+  float near_plane;
+  float lim_x, lim_y;      // guard band on |t_x / t_z|, |t_y / t_z|
+  float bg[3];
+  int32_t W, H, tw, th, tiles_x, tiles_y;
+};
+
+// Everything the per-splat kernels need about the frame's work list.
+struct WorkDev {
+  const cs_instance* inst;
+  const float* bones;      // [n_inst][24][12]
+  const uint32_t* offset;  // [n_inst + 1] splat offsets
+  const Chunk* chunks;
+  const TemplateDev* tpl;
+  FrameHdr* hdr;
+  int32_t skin_mode;
+};
+
+struct SkinOut {
+  float4* mu;              // xyz + Sigma'xx
+  float4* cov;             // xy xz yy yz
+  float* cov_zz;
+};
+
+struct SplatOut {
+  float4* rec;             // [n][3] float4: (u v A B)(C o r g)(b rx ry depth)
+  uint32_t* rect;
+  uint32_t* count;
+};
+
+// ---- launchers (defined in the .hip files) ------------------------------
+hipError_t launch_prepare_template(const float* mean, const float* log_scale, const float* quat,
+                                   const float* opacity, const float* sh, const uint8_t* skin_idx,
+                                   const float* skin_w, int n, int sh_degree, float4* mean_idx,
+                                   float4* skin_w_out, float4* cov_a, float2* cov_b, float* op_out,
+                                   float4* sh_out, hipStream_t st);
+hipError_t launch_frame_reset(FrameHdr* hdr, uint32_t* hist, int hist_len, int clear_overflow,
+                              hipStream_t st);
+hipError_t launch_fk(const cs_instance* inst, const float* pose, const TemplateDev* tpl, int n_inst,
+                     int n_tpl, float* bones, float* joints_out, FrameHdr* hdr, hipStream_t st);
+hipError_t launch_lod_fixed(const cs_instance* inst, const TemplateDev* tpl, int n_inst, int n_tpl,
+                            CamDev cam, const float* thr, int n_thr, int full, int32_t* level,
+                            uint32_t* count, hipStream_t st);
+hipError_t launch_worklist(const int32_t* level, const uint32_t* count, int n_inst,
+                           uint32_t* offset, uint32_t* chunk_off, Chunk* chunks, int max_chunks,
+                           uint32_t max_splats, FrameHdr* hdr, int32_t* level_out,
+                           hipStream_t st);
+hipError_t launch_skin(WorkDev w, SkinOut out, int chunk_lo, int chunk_hi, int grid,
+                       hipStream_t st);
+hipError_t launch_project(WorkDev w, SkinOut skinned, int fused, CamDev cam, SplatOut out,
+                          uint32_t max_splats, int chunk_lo, int chunk_hi, int grid,
+                          hipStream_t st);
+hipError_t launch_scan_counts(const uint32_t* count, uint32_t* pair_off, uint32_t* block_sums,
+                              int max_blocks, FrameHdr* hdr, uint32_t max_pairs, hipStream_t st);
+hipError_t launch_emit(const uint32_t* count, const uint32_t* pair_off, const uint32_t* rect,
+                       const float4* rec, CamDev cam, uint64_t* keys, uint32_t* vals,
+                       uint32_t* hist, int passes, FrameHdr* hdr, uint32_t max_pairs, int grid,
+                       hipStream_t st);
+hipError_t launch_digit_offsets(uint32_t* hist, int passes, hipStream_t st);
+hipError_t launch_onesweep(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout,
+                           const uint32_t* goff, uint64_t* lookback, FrameHdr* hdr, int pass,
+                           int max_parts, uint32_t max_n, const uint32_t* n_override,
+                           int grid, hipStream_t st);
+hipError_t launch_hist_keys(const uint64_t* keys, const uint32_t* n_ptr, uint32_t* hist, int passes,
+                            int grid, hipStream_t st);
+hipError_t launch_ranges(const uint64_t* skeys, FrameHdr* hdr, uint32_t max_pairs, int n_tiles,
+                         uint32_t* ranges, hipStream_t st);
+hipError_t launch_blend(const uint32_t* ranges, const uint32_t* svals, const float4* rec, CamDev cam,
+                        float* image, const FrameHdr* hdr, hipStream_t st);
+
+// Onesweep partition geometry.
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortPart = kSortThreads * kSortItems;
+
+}  // namespace cs

@@ -1,0 +1,190 @@
+// A4-A5: EWA projection with SH colour and opacity-aware tile footprint
+// (3D Gaussian Splatting, the renderer CrowdSplat §2 uses), and the exclusive
+// scan of per-splat tile counts that places every splat's tile pairs.
+#include "cs_internal.h"
+#include "skin_math.h"
+
+namespace cs {
+
+// One block iteration per chunk (one instance, up to kChunk Gaussians). The
+// bone matrices are staged in LDS: in fused mode the Gaussian is skinned
+// here (bit-identical to the skin kernel); otherwise the posed mean and
+// covariance are read back and only the blended linear part is rebuilt for
+// the colour direction.
+__global__ __launch_bounds__(kChunkThreads) void project_kernel(WorkDev w, SkinOut skinned,
+                                                                int fused, CamDev cam, SplatOut out,
+                                                                int chunk_lo, int chunk_hi) {
+  __shared__ float s_bones[kJoints * 12];
+  __shared__ uint32_t s_vis;
+  const int hi = chunk_hi >= 0 ? chunk_hi : (int)w.hdr->n_chunks;
+  for (int c = chunk_lo + blockIdx.x; c < hi; c += gridDim.x) {
+    const Chunk ch = w.chunks[c];
+    const cs_instance in = w.inst[ch.inst];
+    const TemplateDev& T = w.tpl[in.tid];
+    for (int e = threadIdx.x; e < kJoints * 12; e += kChunkThreads)
+      s_bones[e] = w.bones[(size_t)ch.inst * kJoints * 12 + e];
+    if (threadIdx.x == 0) s_vis = 0;
+    __syncthreads();
+    float Ry[9];
+    yaw_rotation(in.yaw, Ry);
+    const uint32_t base = w.offset[ch.inst];
+    const int n_here = min(kChunk, (int)(w.offset[ch.inst + 1] - base) - ch.g0);
+    uint32_t vis = 0;
+    for (int k = threadIdx.x; k < n_here; k += kChunkThreads) {
+      const int g = ch.g0 + k;
+      const size_t s = (size_t)base + g;
+      Posed p;
+      const float4 mi = T.mean_idx[g];
+      const float4 wt = T.skin_w[g];
+      if (fused) {
+        skin_gaussian(s_bones, mi, wt, T.cov_a[g], T.cov_b[g], w.skin_mode, Ry, p);
+      } else {
+        const float4 m = skinned.mu[s];
+        const float4 cv = skinned.cov[s];
+        p.mu[0] = m.x; p.mu[1] = m.y; p.mu[2] = m.z;
+        p.cov[0] = m.w; p.cov[1] = cv.x; p.cov[2] = cv.y; p.cov[3] = cv.z; p.cov[4] = cv.w;
+        p.cov[5] = skinned.cov_zz[s];
+        if (w.skin_mode) {
+#pragma unroll
+          for (int e = 0; e < 9; ++e) p.L[e] = Ry[e];
+        } else {
+          float M[12];
+          blend_bones(s_bones, __float_as_uint(mi.w), wt, M);
+          p.L[0] = M[0]; p.L[1] = M[1]; p.L[2] = M[2];
+          p.L[3] = M[4]; p.L[4] = M[5]; p.L[5] = M[6];
+          p.L[6] = M[8]; p.L[7] = M[9]; p.L[8] = M[10];
+        }
+      }
+      SplatRec r;
+      project_gaussian(p, T.opacity[g], T.sh + g, T.n, T.n_sh4, T.sh_degree, cam, r);
+      out.rec[3 * s + 0] = r.r0;
+      out.rec[3 * s + 1] = r.r1;
+      out.rec[3 * s + 2] = r.r2;
+      out.rect[s] = r.rect;
+      out.count[s] = r.count;
+      vis += r.count ? 1u : 0u;
+    }
+    atomicAdd(&s_vis, vis);
+    __syncthreads();
+    if (threadIdx.x == 0 && s_vis) atomicAdd(&w.hdr->n_visible, s_vis);
+  }
+}
+
+hipError_t launch_project(WorkDev w, SkinOut skinned, int fused, CamDev cam, SplatOut out,
+                          uint32_t /*max_splats*/, int chunk_lo, int chunk_hi, int grid,
+                          hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  project_kernel<<<grid, kChunkThreads, 0, st>>>(w, skinned, fused, cam, out, chunk_lo, chunk_hi);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan of the tile counts (reduce / scan-of-sums / downsweep).
+// Sizes come from the frame header so the same launches work inside a graph.
+// ---------------------------------------------------------------------------
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* s, uint32_t* total) {
+  const int t = threadIdx.x;
+  s[t] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const uint32_t add = t >= off ? s[t - off] : 0u;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  const uint32_t inc = s[t];
+  *total = s[kScanThreads - 1];
+  __syncthreads();
+  return inc - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t* __restrict__ cnt,
+                                                                   uint32_t* __restrict__ sums,
+                                                                   const FrameHdr* hdr) {
+  __shared__ uint32_t s[kScanThreads];
+  const uint32_t n = hdr->n_splats;
+  const uint32_t base = blockIdx.x * (uint32_t)kScanTile;
+  if (base >= n) return;
+  uint32_t acc = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint32_t i = base + k * kScanThreads + threadIdx.x;
+    if (i < n) acc += cnt[i];
+  }
+  uint32_t total;
+  block_excl_scan256(acc, s, &total);
+  if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void scan_sums_kernel(uint32_t* __restrict__ sums, FrameHdr* hdr,
+                                                         uint32_t max_pairs) {
+  __shared__ uint32_t s[1024];
+  const uint32_t n = hdr->n_splats;
+  const uint32_t nb = (n + kScanTile - 1) / kScanTile;
+  uint64_t carry = 0;
+  const int t = threadIdx.x;
+  for (uint32_t b0 = 0; b0 < nb; b0 += 1024) {
+    const uint32_t i = b0 + t;
+    const uint32_t v = i < nb ? sums[i] : 0u;
+    s[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const uint32_t add = t >= off ? s[t - off] : 0u;
+      __syncthreads();
+      s[t] += add;
+      __syncthreads();
+    }
+    if (i < nb) sums[i] = (uint32_t)(carry + s[t] - v);
+    carry += s[1023];
+    __syncthreads();
+  }
+  if (t == 0) {
+    const uint64_t total = carry;
+    hdr->n_pairs = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
+    if (total > (uint64_t)max_pairs) atomicOr(&hdr->overflow, 2u);
+  }
+}
+
+__global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t* __restrict__ cnt,
+                                                                 const uint32_t* __restrict__ sums,
+                                                                 uint32_t* __restrict__ out,
+                                                                 const FrameHdr* hdr) {
+  __shared__ uint32_t s[kScanThreads];
+  const uint32_t n = hdr->n_splats;
+  const uint32_t base = blockIdx.x * (uint32_t)kScanTile;
+  if (base >= n) return;
+  // thread t owns the contiguous items [t*ITEMS, (t+1)*ITEMS) of the tile
+  uint32_t v[kScanItems];
+  uint32_t acc = 0;
+  const uint32_t mine = base + threadIdx.x * kScanItems;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint32_t i = mine + k;
+    v[k] = i < n ? cnt[i] : 0u;
+    acc += v[k];
+  }
+  uint32_t total;
+  uint32_t run = block_excl_scan256(acc, s, &total) + sums[blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const uint32_t i = mine + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+}
+
+hipError_t launch_scan_counts(const uint32_t* count, uint32_t* pair_off, uint32_t* block_sums,
+                              int max_blocks, FrameHdr* hdr, uint32_t max_pairs, hipStream_t st) {
+  if (max_blocks <= 0) return hipSuccess;
+  scan_reduce_kernel<<<max_blocks, kScanThreads, 0, st>>>(count, block_sums, hdr);
+  scan_sums_kernel<<<1, 1024, 0, st>>>(block_sums, hdr, max_pairs);
+  scan_down_kernel<<<max_blocks, kScanThreads, 0, st>>>(count, block_sums, pair_off, hdr);
+  return hipGetLastError();
+}
+
+int scan_tile() { return kScanTile; }
+
+}  // namespace cs

@@ -1,0 +1,787 @@
+// Context, device workspace and the C ABI entry points of the crowd-splatting
+// hot path (see include/crowdsplat.h for the contract of every call).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "cs_internal.h"
+
+namespace cs {
+int scan_tile();
+}
+
+using namespace cs;
+
+namespace {
+
+struct TemplateStore {
+  int n = 0, sh_degree = 0, n_sh4 = 0;
+  float4* mean_idx = nullptr;
+  float4* skin_w = nullptr;
+  float4* cov_a = nullptr;
+  float2* cov_b = nullptr;
+  float* opacity = nullptr;
+  float4* sh = nullptr;
+  float* raw_mean = nullptr;       // [n][3]  kept for the backward
+  float* raw_log_scale = nullptr;  // [n][3]
+  float* raw_quat = nullptr;       // [n][4]
+  TemplateDev dev{};
+};
+
+enum State { kNone = 0, kTemplates = 1, kLod = 2, kSkinned = 3, kRendered = 4 };
+
+constexpr uint32_t kMaxPairsLimit = (1u << 30) - 1u;  // look-back count field
+
+}  // namespace
+
+struct cs_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  cs_options opt{};
+  std::string err;
+
+  std::vector<TemplateStore> tpl;
+  TemplateDev* tpl_dev = nullptr;
+  int max_tpl_n = 0;
+
+  FrameHdr* hdr = nullptr;
+  FrameHdr* hdr_host = nullptr;  // pinned
+  uint32_t* n_dev = nullptr;     // standalone sort size
+
+  // per instance
+  int64_t cap_inst = 0, cap_chunks = 0;
+  int32_t* level = nullptr;
+  uint32_t* count_inst = nullptr;
+  uint32_t* offset = nullptr;
+  uint32_t* chunk_off = nullptr;
+  Chunk* chunks = nullptr;
+  float* bones = nullptr;
+  float* joints = nullptr;
+
+  // per splat
+  int64_t cap_splats = 0;
+  float4* skin_mu = nullptr;
+  float4* skin_cov = nullptr;
+  float* skin_zz = nullptr;
+  float4* rec = nullptr;
+  uint32_t* rect = nullptr;
+  uint32_t* cnt = nullptr;
+  uint32_t* pair_off = nullptr;
+  uint32_t* scan_sums = nullptr;
+
+  // per pair
+  int64_t cap_pairs = 0, cap_parts = 0;
+  uint64_t* keys[2] = {nullptr, nullptr};
+  uint32_t* vals[2] = {nullptr, nullptr};
+  uint64_t* lookback = nullptr;
+  uint32_t* hist = nullptr;  // kMaxPasses * kSortBins
+  int64_t cap_tiles = 0;
+  uint32_t* ranges = nullptr;
+
+  // frame state
+  int state = kNone;
+  int n_inst = 0;
+  const cs_instance* inst = nullptr;
+  const float* pose = nullptr;
+  CamDev cam{};
+  int passes = 0;
+  int sorted = 0;  // which key/val buffer holds the sorted pairs
+  bool capturing = false;
+  bool fixed_capacity = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<uint32_t> chunk_off_host;  // per-instance launch mode
+
+  cs_status fail(cs_status code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+  cs_status hip_fail(const char* what, hipError_t e) {
+    err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? CS_ERR_OOM : CS_ERR_DEVICE;
+  }
+};
+
+#define HIP_TRY(expr)                                 \
+  do {                                                \
+    hipError_t e_ = (expr);                           \
+    if (e_ != hipSuccess) return ctx->hip_fail(#expr, e_); \
+  } while (0)
+
+#define CS_TRY(expr)               \
+  do {                             \
+    cs_status s_ = (expr);         \
+    if (s_ != CS_OK) return s_;    \
+  } while (0)
+
+namespace {
+
+template <class T>
+cs_status dalloc(cs_ctx* ctx, T** p, size_t count) {
+  if (*p) {
+    hipFree(*p);
+    *p = nullptr;
+  }
+  if (count == 0) return CS_OK;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return ctx->hip_fail("hipMalloc", e);
+  }
+  return CS_OK;
+}
+
+template <class T>
+void dfree(T** p) {
+  if (*p) hipFree(*p);
+  *p = nullptr;
+}
+
+cs_status ensure_instances(cs_ctx* ctx, int64_t n_inst) {
+  const int64_t per = (ctx->max_tpl_n + kChunk - 1) / kChunk;
+  if (n_inst <= ctx->cap_inst && n_inst * per <= ctx->cap_chunks) return CS_OK;
+  if (ctx->capturing || ctx->fixed_capacity)
+    return ctx->fail(CS_ERR_CAPACITY, "instance capacity exceeded (reserve more before capture)");
+  const int64_t cap = std::max<int64_t>(n_inst, 64);
+  CS_TRY(dalloc(ctx, &ctx->level, cap));
+  CS_TRY(dalloc(ctx, &ctx->count_inst, cap));
+  CS_TRY(dalloc(ctx, &ctx->offset, cap + 1));
+  CS_TRY(dalloc(ctx, &ctx->chunk_off, cap + 1));
+  CS_TRY(dalloc(ctx, &ctx->chunks, cap * per));
+  CS_TRY(dalloc(ctx, &ctx->bones, cap * kJoints * 12));
+  CS_TRY(dalloc(ctx, &ctx->joints, cap * kJoints * 3));
+  ctx->cap_inst = cap;
+  ctx->cap_chunks = cap * per;
+  return CS_OK;
+}
+
+cs_status ensure_splats(cs_ctx* ctx, int64_t n) {
+  if (n <= ctx->cap_splats) return CS_OK;
+  if (ctx->capturing || ctx->fixed_capacity)
+    return ctx->fail(CS_ERR_CAPACITY, "splat capacity exceeded");
+  if (n >= 0xffffffffll) return ctx->fail(CS_ERR_CAPACITY, "more than 2^32 splats in one frame");
+  const int64_t cap = std::min<int64_t>(0xfffffffell, std::max<int64_t>(n + n / 4, 4096));
+  CS_TRY(dalloc(ctx, &ctx->skin_mu, cap));
+  CS_TRY(dalloc(ctx, &ctx->skin_cov, cap));
+  CS_TRY(dalloc(ctx, &ctx->skin_zz, cap));
+  CS_TRY(dalloc(ctx, &ctx->rec, cap * 3));
+  CS_TRY(dalloc(ctx, &ctx->rect, cap));
+  CS_TRY(dalloc(ctx, &ctx->cnt, cap));
+  CS_TRY(dalloc(ctx, &ctx->pair_off, cap));
+  CS_TRY(dalloc(ctx, &ctx->scan_sums, (cap + scan_tile() - 1) / scan_tile() + 1));
+  ctx->cap_splats = cap;
+  return CS_OK;
+}
+
+cs_status ensure_pairs(cs_ctx* ctx, int64_t n) {
+  if (n <= ctx->cap_pairs) return CS_OK;
+  if (ctx->capturing || ctx->fixed_capacity)
+    return ctx->fail(CS_ERR_CAPACITY, "pair capacity exceeded");
+  if (n > (int64_t)kMaxPairsLimit) return ctx->fail(CS_ERR_CAPACITY, "more than 2^30 tile pairs");
+  const int64_t cap = std::min<int64_t>(kMaxPairsLimit, std::max<int64_t>(n + n / 4, 65536));
+  for (int b = 0; b < 2; ++b) {
+    CS_TRY(dalloc(ctx, &ctx->keys[b], cap));
+    CS_TRY(dalloc(ctx, &ctx->vals[b], cap));
+  }
+  const int64_t parts = (cap + kSortPart - 1) / kSortPart;
+  CS_TRY(dalloc(ctx, &ctx->lookback, parts * kSortBins));
+  HIP_TRY(hipMemsetAsync(ctx->lookback, 0, parts * kSortBins * sizeof(uint64_t), ctx->stream));
+  ctx->cap_pairs = cap;
+  ctx->cap_parts = parts;
+  return CS_OK;
+}
+
+cs_status ensure_tiles(cs_ctx* ctx, int64_t n_tiles) {
+  if (n_tiles <= ctx->cap_tiles) return CS_OK;
+  if (ctx->capturing) return ctx->fail(CS_ERR_CAPACITY, "tile capacity exceeded");
+  CS_TRY(dalloc(ctx, &ctx->ranges, n_tiles * 2));
+  ctx->cap_tiles = n_tiles;
+  return CS_OK;
+}
+
+cs_status read_header(cs_ctx* ctx) {
+  HIP_TRY(hipMemcpyAsync(ctx->hdr_host, ctx->hdr, sizeof(FrameHdr), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return CS_OK;
+}
+
+cs_status make_camera(cs_ctx* ctx, const cs_camera* c, CamDev* out) {
+  if (!c) return ctx->fail(CS_ERR_INVALID, "camera is NULL");
+  if (c->width < 1 || c->height < 1 || c->width > 8192 || c->height > 8192)
+    return ctx->fail(CS_ERR_INVALID, "image size out of range");
+  if (!(c->fx > 0.f) || !(c->fy > 0.f) || !(c->near_plane > 0.f))
+    return ctx->fail(CS_ERR_INVALID, "focal lengths and near plane must be positive");
+  CamDev d{};
+  memcpy(d.R, c->R, sizeof(d.R));
+  memcpy(d.eye, c->eye, sizeof(d.eye));
+  memcpy(d.bg, c->bg, sizeof(d.bg));
+  d.fx = c->fx;
+  d.fy = c->fy;
+  d.cx = c->cx;
+  d.cy = c->cy;
+  d.near_plane = c->near_plane;
+  // guard band: 1.5x the half-extent of the image in normalised coordinates
+  d.lim_x = (float)(1.5 * (double)c->width / (2.0 * (double)c->fx));
+  d.lim_y = (float)(1.5 * (double)c->height / (2.0 * (double)c->fy));
+  d.W = c->width;
+  d.H = c->height;
+  d.tw = ctx->opt.tile_w;
+  d.th = ctx->opt.tile_h;
+  d.tiles_x = (c->width + d.tw - 1) / d.tw;
+  d.tiles_y = (c->height + d.th - 1) / d.th;
+  if (d.tiles_x > 256 || d.tiles_y > 256)
+    return ctx->fail(CS_ERR_INVALID, "more than 256 tiles along an axis (use larger tiles)");
+  *out = d;
+  return CS_OK;
+}
+
+int sort_passes(int n_tiles) {
+  int bits = 1;
+  while ((1 << bits) < n_tiles) ++bits;
+  return (31 + bits + kSortBits - 1) / kSortBits;
+}
+
+WorkDev work_view(cs_ctx* ctx) {
+  WorkDev w{};
+  w.inst = ctx->inst;
+  w.bones = ctx->bones;
+  w.offset = ctx->offset;
+  w.chunks = ctx->chunks;
+  w.tpl = ctx->tpl_dev;
+  w.hdr = ctx->hdr;
+  w.skin_mode = ctx->opt.skin_mode;
+  return w;
+}
+
+int persistent_grid(int64_t work, int cap) { return (int)std::max<int64_t>(1, std::min<int64_t>(work, cap)); }
+
+void free_templates(cs_ctx* ctx) {
+  for (auto& t : ctx->tpl) {
+    dfree(&t.mean_idx);
+    dfree(&t.skin_w);
+    dfree(&t.cov_a);
+    dfree(&t.cov_b);
+    dfree(&t.opacity);
+    dfree(&t.sh);
+    dfree(&t.raw_mean);
+    dfree(&t.raw_log_scale);
+    dfree(&t.raw_quat);
+  }
+  ctx->tpl.clear();
+  dfree(&ctx->tpl_dev);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cs_version(void) { return "crowdsplat-mi355x 0.1 (gfx950)"; }
+
+const char* cs_last_error(const cs_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+cs_status cs_create(int32_t device, void* stream, const cs_options* opt, cs_ctx** out) {
+  if (!out) return CS_ERR_INVALID;
+  *out = nullptr;
+  cs_options o{};
+  if (opt) o = *opt;
+  if (o.tile_w == 0) o.tile_w = 16;
+  if (o.tile_h == 0) o.tile_h = 16;
+  auto ok_tile = [](int v) { return v == 8 || v == 16 || v == 32; };
+  if (!ok_tile(o.tile_w) || !ok_tile(o.tile_h)) return CS_ERR_INVALID;
+  if (o.skin_mode != CS_SKIN_FULL && o.skin_mode != CS_SKIN_MEANS_ONLY) return CS_ERR_INVALID;
+  if (o.launch_mode != CS_LAUNCH_BATCHED && o.launch_mode != CS_LAUNCH_PER_INSTANCE) return CS_ERR_INVALID;
+  if (o.max_splats < 0 || o.max_pairs < 0) return CS_ERR_INVALID;
+  int n_dev = 0;
+  if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev) {
+    (void)hipGetLastError();
+    return CS_ERR_DEVICE;
+  }
+  if (hipSetDevice(device) != hipSuccess) return CS_ERR_DEVICE;
+  cs_ctx* ctx = new cs_ctx();
+  ctx->device = device;
+  ctx->stream = (hipStream_t)stream;
+  ctx->opt = o;
+  cs_status s = dalloc(ctx, &ctx->hdr, 1);
+  if (s == CS_OK) s = dalloc(ctx, &ctx->hist, kMaxPasses * kSortBins);
+  if (s == CS_OK) s = dalloc(ctx, &ctx->n_dev, 1);
+  if (s == CS_OK && hipHostMalloc((void**)&ctx->hdr_host, sizeof(FrameHdr), hipHostMallocDefault) != hipSuccess)
+    s = CS_ERR_OOM;
+  if (s == CS_OK && hipMemsetAsync(ctx->hdr, 0, sizeof(FrameHdr), ctx->stream) != hipSuccess) s = CS_ERR_DEVICE;
+  if (s == CS_OK && (o.max_splats || o.max_pairs)) {
+    s = cs_reserve(ctx, 0, o.max_splats, o.max_pairs);
+  }
+  if (s != CS_OK) {
+    cs_destroy(ctx);
+    return s;
+  }
+  *out = ctx;
+  return CS_OK;
+}
+
+void cs_destroy(cs_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipStreamSynchronize(ctx->stream);
+  if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
+  if (ctx->graph) hipGraphDestroy(ctx->graph);
+  free_templates(ctx);
+  dfree(&ctx->hdr);
+  if (ctx->hdr_host) hipHostFree(ctx->hdr_host);
+  dfree(&ctx->n_dev);
+  dfree(&ctx->level);
+  dfree(&ctx->count_inst);
+  dfree(&ctx->offset);
+  dfree(&ctx->chunk_off);
+  dfree(&ctx->chunks);
+  dfree(&ctx->bones);
+  dfree(&ctx->joints);
+  dfree(&ctx->skin_mu);
+  dfree(&ctx->skin_cov);
+  dfree(&ctx->skin_zz);
+  dfree(&ctx->rec);
+  dfree(&ctx->rect);
+  dfree(&ctx->cnt);
+  dfree(&ctx->pair_off);
+  dfree(&ctx->scan_sums);
+  for (int b = 0; b < 2; ++b) {
+    dfree(&ctx->keys[b]);
+    dfree(&ctx->vals[b]);
+  }
+  dfree(&ctx->lookback);
+  dfree(&ctx->hist);
+  dfree(&ctx->ranges);
+  delete ctx;
+}
+
+cs_status cs_reserve(cs_ctx* ctx, int64_t max_instances, int64_t max_splats, int64_t max_pairs) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (max_instances < 0 || max_splats < 0 || max_pairs < 0)
+    return ctx->fail(CS_ERR_INVALID, "negative capacity");
+  hipSetDevice(ctx->device);
+  ctx->fixed_capacity = false;
+  if (max_instances > 0 && ctx->max_tpl_n > 0) CS_TRY(ensure_instances(ctx, max_instances));
+  if (max_splats > 0) CS_TRY(ensure_splats(ctx, max_splats));
+  if (max_pairs > 0) CS_TRY(ensure_pairs(ctx, max_pairs));
+  return CS_OK;
+}
+
+cs_status cs_upload_templates(cs_ctx* ctx, const cs_template_desc* t, int32_t n_templates, int32_t mem) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (!t || n_templates <= 0 || n_templates > kMaxTemplates)
+    return ctx->fail(CS_ERR_INVALID, "need 1..64 templates");
+  if (mem != CS_MEM_HOST && mem != CS_MEM_DEVICE) return ctx->fail(CS_ERR_INVALID, "mem must be HOST or DEVICE");
+  if (ctx->capturing) return ctx->fail(CS_ERR_STATE, "upload during capture");
+  hipSetDevice(ctx->device);
+  for (int i = 0; i < n_templates; ++i) {
+    const cs_template_desc& d = t[i];
+    if (d.n_gauss <= 0 || d.sh_degree < 0 || d.sh_degree > 3 || d.n_levels < 1 || d.n_levels > kMaxLevels)
+      return ctx->fail(CS_ERR_INVALID, "template " + std::to_string(i) + ": bad size, degree or level count");
+    if (!d.level_count || !d.mean || !d.log_scale || !d.quat || !d.opacity || !d.sh || !d.skin_idx ||
+        !d.skin_w || !d.joints_rest || !d.parents)
+      return ctx->fail(CS_ERR_INVALID, "template " + std::to_string(i) + ": NULL array");
+    if (d.level_count[0] != d.n_gauss)
+      return ctx->fail(CS_ERR_INVALID, "level_count[0] must equal n_gauss");
+    for (int l = 1; l < d.n_levels; ++l)
+      if (d.level_count[l] <= 0 || d.level_count[l] > d.level_count[l - 1])
+        return ctx->fail(CS_ERR_INVALID, "level counts must be positive and non-increasing");
+    if (d.parents[0] != -1) return ctx->fail(CS_ERR_INVALID, "parents[0] must be -1");
+    for (int j = 1; j < kJoints; ++j)
+      if (d.parents[j] < 0 || d.parents[j] >= j) return ctx->fail(CS_ERR_INVALID, "parents[j] must be in [0, j)");
+    if (mem == CS_MEM_HOST)
+      for (int64_t k = 0; k < 4ll * d.n_gauss; ++k)
+        if (d.skin_idx[k] >= kJoints) return ctx->fail(CS_ERR_INVALID, "skin index >= 24");
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  free_templates(ctx);
+  ctx->state = kNone;
+  ctx->max_tpl_n = 0;
+  std::vector<TemplateDev> devs(n_templates);
+  for (int i = 0; i < n_templates; ++i) {
+    const cs_template_desc& d = t[i];
+    TemplateStore st;
+    const int n = d.n_gauss;
+    const int n_coef3 = 3 * (d.sh_degree + 1) * (d.sh_degree + 1);
+    st.n = n;
+    st.sh_degree = d.sh_degree;
+    st.n_sh4 = (n_coef3 + 3) / 4;
+    CS_TRY(dalloc(ctx, &st.mean_idx, n));
+    CS_TRY(dalloc(ctx, &st.skin_w, n));
+    CS_TRY(dalloc(ctx, &st.cov_a, n));
+    CS_TRY(dalloc(ctx, &st.cov_b, n));
+    CS_TRY(dalloc(ctx, &st.opacity, n));
+    CS_TRY(dalloc(ctx, &st.sh, (size_t)st.n_sh4 * n));
+    CS_TRY(dalloc(ctx, &st.raw_mean, 3 * (size_t)n));
+    CS_TRY(dalloc(ctx, &st.raw_log_scale, 3 * (size_t)n));
+    CS_TRY(dalloc(ctx, &st.raw_quat, 4 * (size_t)n));
+    // staging: device copies of every input array
+    float *op = nullptr, *sh = nullptr, *w = nullptr;
+    uint8_t* idx = nullptr;
+    const hipMemcpyKind kind = mem == CS_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    CS_TRY(dalloc(ctx, &op, n));
+    CS_TRY(dalloc(ctx, &sh, (size_t)n_coef3 * n));
+    CS_TRY(dalloc(ctx, &w, 4 * (size_t)n));
+    CS_TRY(dalloc(ctx, &idx, 4 * (size_t)n));
+    HIP_TRY(hipMemcpy(st.raw_mean, d.mean, 12ull * n, kind));
+    HIP_TRY(hipMemcpy(st.raw_log_scale, d.log_scale, 12ull * n, kind));
+    HIP_TRY(hipMemcpy(st.raw_quat, d.quat, 16ull * n, kind));
+    HIP_TRY(hipMemcpy(op, d.opacity, 4ull * n, kind));
+    HIP_TRY(hipMemcpy(sh, d.sh, 4ull * n_coef3 * n, kind));
+    HIP_TRY(hipMemcpy(w, d.skin_w, 16ull * n, kind));
+    HIP_TRY(hipMemcpy(idx, d.skin_idx, 4ull * n, kind));
+    HIP_TRY(launch_prepare_template(st.raw_mean, st.raw_log_scale, st.raw_quat, op, sh, idx, w, n,
+                                    d.sh_degree, st.mean_idx, st.skin_w, st.cov_a, st.cov_b,
+                                    st.opacity, st.sh, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    // rest-pose bound of the means around the joints (learned-LoD screen box)
+    std::vector<float> hm(3ull * n), hs(3ull * n);
+    HIP_TRY(hipMemcpy(hm.data(), st.raw_mean, 12ull * n, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(hs.data(), st.raw_log_scale, 12ull * n, hipMemcpyDeviceToHost));
+    dfree(&op);
+    dfree(&sh);
+    dfree(&w);
+    dfree(&idx);
+    TemplateDev& dv = st.dev;
+    dv.mean_idx = st.mean_idx;
+    dv.skin_w = st.skin_w;
+    dv.cov_a = st.cov_a;
+    dv.cov_b = st.cov_b;
+    dv.opacity = st.opacity;
+    dv.sh = st.sh;
+    dv.n = n;
+    dv.sh_degree = d.sh_degree;
+    dv.n_sh4 = st.n_sh4;
+    dv.n_levels = d.n_levels;
+    for (int l = 0; l < kMaxLevels; ++l) dv.level_count[l] = l < d.n_levels ? d.level_count[l] : d.level_count[d.n_levels - 1];
+    for (int k = 0; k < kJoints * 3; ++k) dv.joints[k] = d.joints_rest[k];
+    for (int j = 0; j < kJoints; ++j) dv.parents[j] = d.parents[j];
+    float pad = 0.f, top = 0.f;
+    for (int g = 0; g < n; ++g) {
+      float best = 1e30f;
+      for (int j = 0; j < kJoints; ++j) {
+        const float dx = hm[3 * g] - dv.joints[3 * j], dy = hm[3 * g + 1] - dv.joints[3 * j + 1],
+                    dz = hm[3 * g + 2] - dv.joints[3 * j + 2];
+        best = std::min(best, dx * dx + dy * dy + dz * dz);
+      }
+      const float smax = expf(std::max(hs[3 * g], std::max(hs[3 * g + 1], hs[3 * g + 2])));
+      pad = std::max(pad, sqrtf(best) + 3.f * smax);
+      top = std::max(top, hm[3 * g + 1]);
+    }
+    dv.pad_radius = pad;
+    dv.rest_height = top;
+    devs[i] = dv;
+    ctx->max_tpl_n = std::max(ctx->max_tpl_n, n);
+    ctx->tpl.push_back(st);
+  }
+  CS_TRY(dalloc(ctx, &ctx->tpl_dev, n_templates));
+  HIP_TRY(hipMemcpy(ctx->tpl_dev, devs.data(), sizeof(TemplateDev) * n_templates, hipMemcpyHostToDevice));
+  ctx->cap_chunks = 0;  // chunk capacity depends on the largest template
+  ctx->state = kTemplates;
+  return CS_OK;
+}
+
+cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, const float* pose,
+                        const cs_camera* cam, const cs_lod_params* lod, int32_t* level_out) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (ctx->state < kTemplates) return ctx->fail(CS_ERR_STATE, "cs_select_lod before cs_upload_templates");
+  if (n_inst <= 0 || !inst) return ctx->fail(CS_ERR_INVALID, "need n_inst > 0 and an instance array");
+  if (!lod) return ctx->fail(CS_ERR_INVALID, "lod params are NULL");
+  if (lod->mode == CS_LOD_FIXED && (lod->n_thresholds < 0 || lod->n_thresholds > 7))
+    return ctx->fail(CS_ERR_INVALID, "0..7 thresholds");
+  if (lod->mode == CS_LOD_LEARNED) return ctx->fail(CS_ERR_UNSUPPORTED, "learned LoD not built yet");
+  if (lod->mode != CS_LOD_FULL && lod->mode != CS_LOD_FIXED) return ctx->fail(CS_ERR_INVALID, "bad lod mode");
+  hipSetDevice(ctx->device);
+  CamDev cd;
+  CS_TRY(make_camera(ctx, cam, &cd));
+  CS_TRY(ensure_instances(ctx, n_inst));
+  HIP_TRY(launch_frame_reset(ctx->hdr, ctx->hist, 0, 1, ctx->stream));
+  HIP_TRY(launch_lod_fixed(inst, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), cd, lod->thresholds,
+                           lod->mode == CS_LOD_FIXED ? lod->n_thresholds : 0, lod->mode == CS_LOD_FULL,
+                           ctx->level, ctx->count_inst, ctx->stream));
+  const uint32_t cap_s = (uint32_t)std::min<int64_t>(ctx->cap_splats, 0xffffffffll);
+  HIP_TRY(launch_worklist(ctx->level, ctx->count_inst, n_inst, ctx->offset, ctx->chunk_off, ctx->chunks,
+                          (int)ctx->cap_chunks, cap_s, ctx->hdr, level_out, ctx->stream));
+  if (!ctx->capturing) {
+    // learn the frame's size, grow the splat arrays, and redo the (tiny) work list
+    CS_TRY(read_header(ctx));
+    uint32_t total = 0;
+    HIP_TRY(hipMemcpy(&total, ctx->offset + n_inst, 4, hipMemcpyDeviceToHost));
+    if ((int64_t)total > ctx->cap_splats) {
+      if (ctx->fixed_capacity) return ctx->fail(CS_ERR_CAPACITY, "splat capacity exceeded");
+      CS_TRY(ensure_splats(ctx, total));
+      HIP_TRY(hipMemsetAsync(&ctx->hdr->overflow, 0, 4, ctx->stream));
+      HIP_TRY(launch_worklist(ctx->level, ctx->count_inst, n_inst, ctx->offset, ctx->chunk_off,
+                              ctx->chunks, (int)ctx->cap_chunks, (uint32_t)ctx->cap_splats, ctx->hdr,
+                              level_out, ctx->stream));
+      CS_TRY(read_header(ctx));
+    }
+    if (ctx->opt.launch_mode == CS_LAUNCH_PER_INSTANCE) {
+      ctx->chunk_off_host.resize(n_inst + 1);
+      HIP_TRY(hipMemcpy(ctx->chunk_off_host.data(), ctx->chunk_off, 4ull * n_inst, hipMemcpyDeviceToHost));
+      ctx->chunk_off_host[n_inst] = ctx->hdr_host->n_chunks;
+    }
+  }
+  ctx->n_inst = n_inst;
+  ctx->inst = inst;
+  ctx->pose = pose;
+  ctx->state = kLod;
+  return CS_OK;
+}
+
+static cs_status run_per_instance(cs_ctx* ctx, bool project, SkinOut so, int fused, SplatOut po) {
+  WorkDev w = work_view(ctx);
+  for (int i = 0; i < ctx->n_inst; ++i) {
+    const int lo = (int)ctx->chunk_off_host[i], hi = (int)ctx->chunk_off_host[i + 1];
+    if (hi <= lo) continue;
+    if (project) {
+      HIP_TRY(launch_project(w, so, fused, ctx->cam, po, 0, lo, hi, hi - lo, ctx->stream));
+    } else {
+      HIP_TRY(launch_skin(w, so, lo, hi, hi - lo, ctx->stream));
+    }
+  }
+  return CS_OK;
+}
+
+cs_status cs_skin_instances(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, const float* pose) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (ctx->state < kLod) return ctx->fail(CS_ERR_STATE, "cs_skin_instances before cs_select_lod");
+  if (n_inst != ctx->n_inst || !inst || !pose)
+    return ctx->fail(CS_ERR_INVALID, "instances must match the last cs_select_lod");
+  hipSetDevice(ctx->device);
+  ctx->inst = inst;
+  ctx->pose = pose;
+  HIP_TRY(launch_fk(inst, pose, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), ctx->bones, ctx->joints,
+                    ctx->hdr, ctx->stream));
+  if (!ctx->opt.fuse_skin_project) {
+    SkinOut so{ctx->skin_mu, ctx->skin_cov, ctx->skin_zz};
+    if (ctx->opt.launch_mode == CS_LAUNCH_PER_INSTANCE && !ctx->capturing) {
+      CS_TRY(run_per_instance(ctx, false, so, 0, SplatOut{}));
+    } else {
+      const int grid = ctx->capturing ? persistent_grid(ctx->cap_chunks, 4096)
+                                      : persistent_grid(ctx->hdr_host->n_chunks, 1 << 20);
+      HIP_TRY(launch_skin(work_view(ctx), so, 0, -1, grid, ctx->stream));
+    }
+  }
+  ctx->state = kSkinned;
+  return CS_OK;
+}
+
+cs_status cs_render_frame(cs_ctx* ctx, const cs_camera* cam, float* image, cs_frame_stats* stats) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (ctx->state < kSkinned) return ctx->fail(CS_ERR_STATE, "cs_render_frame before cs_skin_instances");
+  if (!image) return ctx->fail(CS_ERR_INVALID, "image is NULL");
+  hipSetDevice(ctx->device);
+  CS_TRY(make_camera(ctx, cam, &ctx->cam));
+  const CamDev& cd = ctx->cam;
+  const int n_tiles = cd.tiles_x * cd.tiles_y;
+  CS_TRY(ensure_tiles(ctx, n_tiles));
+  ctx->passes = sort_passes(n_tiles);
+  HIP_TRY(launch_frame_reset(ctx->hdr, ctx->hist, kMaxPasses * kSortBins, 0, ctx->stream));
+  // A4 projection
+  SkinOut so{ctx->skin_mu, ctx->skin_cov, ctx->skin_zz};
+  SplatOut po{ctx->rec, ctx->rect, ctx->cnt};
+  const int fused = ctx->opt.fuse_skin_project;
+  const int64_t n_chunks = ctx->capturing ? ctx->cap_chunks : ctx->hdr_host->n_chunks;
+  if (ctx->opt.launch_mode == CS_LAUNCH_PER_INSTANCE && !ctx->capturing) {
+    CS_TRY(run_per_instance(ctx, true, so, fused, po));
+  } else {
+    const int grid = ctx->capturing ? persistent_grid(n_chunks, 4096) : persistent_grid(n_chunks, 1 << 20);
+    HIP_TRY(launch_project(work_view(ctx), so, fused, cd, po, (uint32_t)ctx->cap_splats, 0, -1, grid,
+                           ctx->stream));
+  }
+  // A5 scan of tile counts
+  const int64_t n_splats = ctx->capturing ? ctx->cap_splats : ctx->hdr_host->n_splats;
+  const int scan_blocks = (int)std::max<int64_t>(1, (n_splats + scan_tile() - 1) / scan_tile());
+  uint32_t cap_p = (uint32_t)std::min<int64_t>(ctx->cap_pairs, kMaxPairsLimit);
+  HIP_TRY(launch_scan_counts(ctx->cnt, ctx->pair_off, ctx->scan_sums, scan_blocks, ctx->hdr,
+                             ctx->capturing ? cap_p : kMaxPairsLimit, ctx->stream));
+  int64_t n_pairs = ctx->cap_pairs;
+  if (!ctx->capturing) {
+    CS_TRY(read_header(ctx));
+    n_pairs = ctx->hdr_host->n_pairs;
+    if (n_pairs > ctx->cap_pairs) {
+      if (ctx->fixed_capacity) return ctx->fail(CS_ERR_CAPACITY, "pair capacity exceeded");
+      CS_TRY(ensure_pairs(ctx, n_pairs));
+    }
+    cap_p = (uint32_t)std::min<int64_t>(ctx->cap_pairs, kMaxPairsLimit);
+  }
+  // A6 emission + digit histograms
+  const int emit_grid = ctx->capturing ? 1024 : persistent_grid((n_splats + 255) / 256, 1024);
+  HIP_TRY(launch_emit(ctx->cnt, ctx->pair_off, ctx->rect, ctx->rec, cd, ctx->keys[0], ctx->vals[0],
+                      ctx->hist, ctx->passes, ctx->hdr, cap_p, emit_grid, ctx->stream));
+  HIP_TRY(launch_digit_offsets(ctx->hist, ctx->passes, ctx->stream));
+  // A7 onesweep passes, ping-pong between the two pair buffers
+  const int64_t parts = ctx->capturing ? ctx->cap_parts : (n_pairs + kSortPart - 1) / kSortPart;
+  const int sort_grid = persistent_grid(parts, 512);
+  int src = 0;
+  for (int p = 0; p < ctx->passes; ++p) {
+    HIP_TRY(launch_onesweep(ctx->keys[src], ctx->vals[src], ctx->keys[1 - src], ctx->vals[1 - src],
+                            ctx->hist + p * kSortBins, ctx->lookback, ctx->hdr, p, (int)ctx->cap_parts,
+                            cap_p, nullptr, sort_grid, ctx->stream));
+    src = 1 - src;
+  }
+  ctx->sorted = src;
+  // A8 ranges, A9 blend
+  HIP_TRY(launch_ranges(ctx->keys[src], ctx->hdr, cap_p, n_tiles, ctx->ranges, ctx->stream));
+  HIP_TRY(launch_blend(ctx->ranges, ctx->vals[src], ctx->rec, cd, image, ctx->hdr, ctx->stream));
+  ctx->state = kRendered;
+  if (stats) {
+    CS_TRY(read_header(ctx));
+    const FrameHdr& h = *ctx->hdr_host;
+    memset(stats, 0, sizeof(*stats));
+    stats->n_splats = h.n_splats;
+    stats->n_visible = h.n_visible;
+    stats->n_pairs = h.n_pairs;
+    stats->overflow = (int32_t)h.overflow;
+    stats->n_instances = (int32_t)h.n_inst;
+    for (int l = 0; l < CS_MAX_LEVELS; ++l) stats->level_hist[l] = (int32_t)h.level_hist[l];
+    if (h.overflow) return ctx->fail(CS_ERR_CAPACITY, "frame exceeded a capacity (see stats)");
+  }
+  return CS_OK;
+}
+
+cs_status cs_render_backward(cs_ctx* ctx, const float* dL_dimage, cs_template_grads* g) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (ctx->state < kRendered) return ctx->fail(CS_ERR_STATE, "cs_render_backward before cs_render_frame");
+  if (!dL_dimage || !g) return ctx->fail(CS_ERR_INVALID, "NULL argument");
+  return ctx->fail(CS_ERR_UNSUPPORTED, "backward not built yet");
+}
+
+cs_status cs_frame_capture(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, const float* pose,
+                           const cs_camera* cam, const cs_lod_params* lod, float* image) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (ctx->state < kTemplates) return ctx->fail(CS_ERR_STATE, "capture before cs_upload_templates");
+  if (!ctx->stream) return ctx->fail(CS_ERR_INVALID, "graph capture needs a non-null stream");
+  if (ctx->opt.launch_mode == CS_LAUNCH_PER_INSTANCE)
+    return ctx->fail(CS_ERR_UNSUPPORTED, "capture uses the batched launches");
+  hipSetDevice(ctx->device);
+  // capacities are whatever is reserved now; the frame must fit in them
+  if (ctx->cap_splats == 0 || ctx->cap_pairs == 0)
+    return ctx->fail(CS_ERR_STATE, "reserve capacities (or render one eager frame) before capture");
+  CS_TRY(ensure_instances(ctx, n_inst));
+  CamDev cd;
+  CS_TRY(make_camera(ctx, cam, &cd));
+  CS_TRY(ensure_tiles(ctx, (int64_t)cd.tiles_x * cd.tiles_y));
+  if (ctx->gexec) {
+    hipGraphExecDestroy(ctx->gexec);
+    ctx->gexec = nullptr;
+  }
+  if (ctx->graph) {
+    hipGraphDestroy(ctx->graph);
+    ctx->graph = nullptr;
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  HIP_TRY(hipMemsetAsync(&ctx->hdr->overflow, 0, 4, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  ctx->capturing = true;
+  cs_status s = cs_select_lod(ctx, n_inst, inst, pose, cam, lod, nullptr);
+  if (s == CS_OK) s = cs_skin_instances(ctx, n_inst, inst, pose);
+  if (s == CS_OK) s = cs_render_frame(ctx, cam, image, nullptr);
+  ctx->capturing = false;
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(ctx->stream, &graph);
+  if (s != CS_OK) {
+    if (graph) hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return ctx->hip_fail("hipStreamEndCapture", e);
+  ctx->graph = graph;
+  HIP_TRY(hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0));
+  ctx->fixed_capacity = true;
+  return CS_OK;
+}
+
+cs_status cs_frame_launch(cs_ctx* ctx) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (!ctx->gexec) return ctx->fail(CS_ERR_STATE, "no captured frame");
+  HIP_TRY(hipGraphLaunch(ctx->gexec, ctx->stream));
+  return CS_OK;
+}
+
+cs_status cs_frame_poll(cs_ctx* ctx, cs_frame_stats* stats) {
+  if (!ctx) return CS_ERR_INVALID;
+  CS_TRY(read_header(ctx));
+  const FrameHdr& h = *ctx->hdr_host;
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->n_splats = h.n_splats;
+    stats->n_visible = h.n_visible;
+    stats->n_pairs = h.n_pairs;
+    stats->overflow = (int32_t)h.overflow;
+    stats->n_instances = (int32_t)h.n_inst;
+    for (int l = 0; l < CS_MAX_LEVELS; ++l) stats->level_hist[l] = (int32_t)h.level_hist[l];
+  }
+  return h.overflow ? ctx->fail(CS_ERR_CAPACITY, "a captured frame exceeded its capacity") : CS_OK;
+}
+
+cs_status cs_debug_copy(cs_ctx* ctx, int32_t which, void* host_dst, int64_t offset, int64_t bytes) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (!host_dst || offset < 0 || bytes < 0) return ctx->fail(CS_ERR_INVALID, "bad copy arguments");
+  const void* src = nullptr;
+  int64_t size = 0;
+  switch (which) {
+    case CS_BUF_BONES: src = ctx->bones; size = ctx->cap_inst * kJoints * 12 * 4; break;
+    case CS_BUF_LEVEL: src = ctx->level; size = ctx->cap_inst * 4; break;
+    case CS_BUF_OFFSET: src = ctx->offset; size = (ctx->cap_inst + 1) * 4; break;
+    case CS_BUF_SKIN_MU: src = ctx->skin_mu; size = ctx->cap_splats * 16; break;
+    case CS_BUF_SKIN_COV: src = ctx->skin_cov; size = ctx->cap_splats * 16; break;
+    case CS_BUF_SKIN_COV2: src = ctx->skin_zz; size = ctx->cap_splats * 4; break;
+    case CS_BUF_RECORD: src = ctx->rec; size = ctx->cap_splats * 48; break;
+    case CS_BUF_RECT: src = ctx->rect; size = ctx->cap_splats * 4; break;
+    case CS_BUF_COUNT: src = ctx->cnt; size = ctx->cap_splats * 4; break;
+    case CS_BUF_PAIR_OFF: src = ctx->pair_off; size = ctx->cap_splats * 4; break;
+    case CS_BUF_KEYS: src = ctx->keys[0]; size = ctx->cap_pairs * 8; break;
+    case CS_BUF_VALS: src = ctx->vals[0]; size = ctx->cap_pairs * 4; break;
+    case CS_BUF_SKEYS: src = ctx->keys[ctx->sorted]; size = ctx->cap_pairs * 8; break;
+    case CS_BUF_SVALS: src = ctx->vals[ctx->sorted]; size = ctx->cap_pairs * 4; break;
+    case CS_BUF_RANGES: src = ctx->ranges; size = ctx->cap_tiles * 8; break;
+    default: return ctx->fail(CS_ERR_INVALID, "unknown buffer");
+  }
+  if (!src || offset + bytes > size) return ctx->fail(CS_ERR_INVALID, "copy out of range");
+  if (bytes == 0) return CS_OK;
+  hipSetDevice(ctx->device);
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  HIP_TRY(hipMemcpy(host_dst, (const char*)src + offset, bytes, hipMemcpyDeviceToHost));
+  return CS_OK;
+}
+
+cs_status cs_sort_pairs(cs_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (!keys || !vals || n < 0 || key_bits < 1 || key_bits > kMaxPasses * kSortBits)
+    return ctx->fail(CS_ERR_INVALID, "bad sort arguments");
+  if (n == 0) return CS_OK;
+  if (ctx->capturing) return ctx->fail(CS_ERR_STATE, "standalone sort during capture");
+  hipSetDevice(ctx->device);
+  CS_TRY(ensure_pairs(ctx, n));
+  const int passes = (key_bits + kSortBits - 1) / kSortBits;
+  const uint32_t nn = (uint32_t)n;
+  HIP_TRY(hipMemcpyAsync(ctx->n_dev, &nn, 4, hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(launch_frame_reset(ctx->hdr, ctx->hist, kMaxPasses * kSortBins, 1, ctx->stream));
+  const int64_t parts = (n + kSortPart - 1) / kSortPart;
+  HIP_TRY(launch_hist_keys(keys, ctx->n_dev, ctx->hist, passes, persistent_grid((n + 255) / 256, 1024),
+                           ctx->stream));
+  HIP_TRY(launch_digit_offsets(ctx->hist, passes, ctx->stream));
+  uint64_t* ks[2] = {keys, ctx->keys[0]};
+  uint32_t* vs[2] = {vals, ctx->vals[0]};
+  int src = 0;
+  for (int p = 0; p < passes; ++p) {
+    HIP_TRY(launch_onesweep(ks[src], vs[src], ks[1 - src], vs[1 - src], ctx->hist + p * kSortBins,
+                            ctx->lookback, ctx->hdr, p, (int)ctx->cap_parts, (uint32_t)ctx->cap_pairs,
+                            ctx->n_dev, persistent_grid(parts, 512), ctx->stream));
+    src = 1 - src;
+  }
+  if (src == 1) {
+    HIP_TRY(hipMemcpyAsync(keys, ctx->keys[0], 8ull * n, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(vals, ctx->vals[0], 4ull * n, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (ctx->state > kSkinned) ctx->state = kSkinned;  // the frame's pair buffers were reused
+  return CS_OK;
+}
+
+}  // extern "C"

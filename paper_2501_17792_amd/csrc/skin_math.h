@@ -1,0 +1,205 @@
+// Device math of the per-Gaussian stages: bone blending, linear blend
+// skinning, EWA projection, SH colour and the opacity-aware footprint.
+// Every function is written with explicit fmaf() and compiled with
+// -ffp-contract=off so that a value computed in two kernels (for example the
+// skinned mean in the skin kernel and again in the fused projection) has the
+// same bits.
+#pragma once
+
+#include "cs_internal.h"
+
+namespace cs {
+
+// M = sum_k w_k B[idx_k] for the 3x4 row-major bone matrices held in LDS.
+__device__ __forceinline__ void blend_bones(const float* __restrict__ bones, uint32_t idx4, float4 w,
+                                            float M[12]) {
+  const float* b0 = bones + 12 * (idx4 & 0xffu);
+  const float* b1 = bones + 12 * ((idx4 >> 8) & 0xffu);
+  const float* b2 = bones + 12 * ((idx4 >> 16) & 0xffu);
+  const float* b3 = bones + 12 * (idx4 >> 24);
+#pragma unroll
+  for (int e = 0; e < 12; ++e) {
+    float m = w.x * b0[e];
+    m = fmaf(w.y, b1[e], m);
+    m = fmaf(w.z, b2[e], m);
+    m = fmaf(w.w, b3[e], m);
+    M[e] = m;
+  }
+}
+
+// Sigma' = L Sigma L^T for symmetric Sigma (xx xy xz yy yz zz); L row-major 3x3.
+__device__ __forceinline__ void congruence(const float L[9], const float S[6], float out[6]) {
+  const float s00 = S[0], s01 = S[1], s02 = S[2], s11 = S[3], s12 = S[4], s22 = S[5];
+  float T[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const float l0 = L[3 * r], l1 = L[3 * r + 1], l2 = L[3 * r + 2];
+    T[3 * r + 0] = fmaf(l0, s00, fmaf(l1, s01, l2 * s02));
+    T[3 * r + 1] = fmaf(l0, s01, fmaf(l1, s11, l2 * s12));
+    T[3 * r + 2] = fmaf(l0, s02, fmaf(l1, s12, l2 * s22));
+  }
+  // rows r <= c of T L^T
+  out[0] = fmaf(T[0], L[0], fmaf(T[1], L[1], T[2] * L[2]));
+  out[1] = fmaf(T[0], L[3], fmaf(T[1], L[4], T[2] * L[5]));
+  out[2] = fmaf(T[0], L[6], fmaf(T[1], L[7], T[2] * L[8]));
+  out[3] = fmaf(T[3], L[3], fmaf(T[4], L[4], T[5] * L[5]));
+  out[4] = fmaf(T[3], L[6], fmaf(T[4], L[7], T[5] * L[8]));
+  out[5] = fmaf(T[6], L[6], fmaf(T[7], L[7], T[8] * L[8]));
+}
+
+// Posed mean, posed covariance and the 3x3 used for the colour direction of
+// one template Gaussian under blended bone matrix M.
+struct Posed {
+  float mu[3];
+  float cov[6];
+  float L[9];
+};
+
+__device__ __forceinline__ void yaw_rotation(float yaw, float Ry[9]) {
+  const float c = cosf(yaw), s = sinf(yaw);
+  Ry[0] = c;    Ry[1] = 0.f; Ry[2] = s;
+  Ry[3] = 0.f;  Ry[4] = 1.f; Ry[5] = 0.f;
+  Ry[6] = -s;   Ry[7] = 0.f; Ry[8] = c;
+}
+
+__device__ __forceinline__ void skin_gaussian(const float* __restrict__ bones, float4 mean_idx,
+                                              float4 w, float4 ca, float2 cb, int means_only,
+                                              const float Ry[9], Posed& p) {
+  float M[12];
+  blend_bones(bones, __float_as_uint(mean_idx.w), w, M);
+  const float x = mean_idx.x, y = mean_idx.y, z = mean_idx.z;
+  p.mu[0] = fmaf(M[0], x, fmaf(M[1], y, fmaf(M[2], z, M[3])));
+  p.mu[1] = fmaf(M[4], x, fmaf(M[5], y, fmaf(M[6], z, M[7])));
+  p.mu[2] = fmaf(M[8], x, fmaf(M[9], y, fmaf(M[10], z, M[11])));
+  if (means_only) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) p.L[e] = Ry[e];
+  } else {
+    p.L[0] = M[0]; p.L[1] = M[1]; p.L[2] = M[2];
+    p.L[3] = M[4]; p.L[4] = M[5]; p.L[5] = M[6];
+    p.L[6] = M[8]; p.L[7] = M[9]; p.L[8] = M[10];
+  }
+  const float S[6] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y};
+  congruence(p.L, S, p.cov);
+}
+
+// Real orthonormal SH basis (no Condon-Shortley phase, polar axis +z) at a
+// unit direction, evaluated against [(deg+1)^2][3] coefficients read from
+// float4 planes (plane j holds flattened coefficients 4j..4j+3).
+__device__ __forceinline__ void sh_colour(const float4* __restrict__ planes, int stride, int n_sh4,
+                                          int deg, float x, float y, float z, float rgb[3]) {
+  float Y[16];
+  Y[0] = 0.28209479177387814f;
+  int nb = 1;
+  if (deg >= 1) {
+    Y[1] = 0.4886025119029199f * y;
+    Y[2] = 0.4886025119029199f * z;
+    Y[3] = 0.4886025119029199f * x;
+    nb = 4;
+  }
+  if (deg >= 2) {
+    const float xx = x * x, yy = y * y, zz = z * z;
+    Y[4] = 1.0925484305920792f * (x * y);
+    Y[5] = 1.0925484305920792f * (y * z);
+    Y[6] = 0.31539156525252005f * fmaf(3.f, zz, -1.f);
+    Y[7] = 1.0925484305920792f * (x * z);
+    Y[8] = 0.5462742152960396f * (xx - yy);
+    nb = 9;
+    if (deg >= 3) {
+      Y[9] = 0.5900435899266435f * y * fmaf(3.f, xx, -yy);
+      Y[10] = 2.890611442640554f * (x * y) * z;
+      Y[11] = 0.4570457994644658f * y * fmaf(5.f, zz, -1.f);
+      Y[12] = 0.3731763325901154f * z * fmaf(5.f, zz, -3.f);
+      Y[13] = 0.4570457994644658f * x * fmaf(5.f, zz, -1.f);
+      Y[14] = 1.445305721320277f * z * (xx - yy);
+      Y[15] = 0.5900435899266435f * x * fmaf(-3.f, yy, xx);
+      nb = 16;
+    }
+  }
+  float acc[3] = {0.f, 0.f, 0.f};
+  // coefficient q = 3k + c lives in plane q/4, lane q%4
+  for (int j = 0; j < n_sh4; ++j) {
+    const float4 v = planes[(size_t)j * stride];
+    const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int q = 4 * j + l;
+      const int k = q / 3;
+      if (k < nb) acc[q - 3 * k] = fmaf(e[l], Y[k], acc[q - 3 * k]);
+    }
+  }
+  rgb[0] = fmaxf(0.f, 0.5f + acc[0]);
+  rgb[1] = fmaxf(0.f, 0.5f + acc[1]);
+  rgb[2] = fmaxf(0.f, 0.5f + acc[2]);
+}
+
+struct SplatRec {
+  float4 r0, r1, r2;   // (u v A B) (C o r g) (b rx ry depth)
+  uint32_t rect;
+  uint32_t count;
+};
+
+// EWA projection + colour + footprint of one posed Gaussian. count = 0 means culled.
+__device__ __forceinline__ void project_gaussian(const Posed& p, float opacity,
+                                                 const float4* __restrict__ sh_planes, int sh_stride,
+                                                 int n_sh4, int deg, const CamDev& cam, SplatRec& out) {
+  out.count = 0u;
+  out.rect = 0u;
+  out.r0 = out.r1 = out.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float dx = p.mu[0] - cam.eye[0], dy = p.mu[1] - cam.eye[1], dz = p.mu[2] - cam.eye[2];
+  const float* R = cam.R;
+  const float tx = fmaf(R[0], dx, fmaf(R[1], dy, R[2] * dz));
+  const float ty = fmaf(R[3], dx, fmaf(R[4], dy, R[5] * dz));
+  const float tz = fmaf(R[6], dx, fmaf(R[7], dy, R[8] * dz));
+  if (!(tz > cam.near_plane)) return;
+  const float xn = tx / tz, yn = ty / tz;
+  if (fabsf(xn) > cam.lim_x || fabsf(yn) > cam.lim_y) return;
+  const float u = fmaf(cam.fx, xn, cam.cx);
+  const float v = fmaf(cam.fy, yn, cam.cy);
+  const float j00 = cam.fx / tz, j11 = cam.fy / tz;
+  const float j02 = -(cam.fx * xn) / tz, j12 = -(cam.fy * yn) / tz;
+  float T0[3], T1[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T0[k] = fmaf(j00, R[k], j02 * R[6 + k]);
+    T1[k] = fmaf(j11, R[3 + k], j12 * R[6 + k]);
+  }
+  const float* S = p.cov;  // xx xy xz yy yz zz
+  const float P00 = fmaf(T0[0], S[0], fmaf(T0[1], S[1], T0[2] * S[2]));
+  const float P01 = fmaf(T0[0], S[1], fmaf(T0[1], S[3], T0[2] * S[4]));
+  const float P02 = fmaf(T0[0], S[2], fmaf(T0[1], S[4], T0[2] * S[5]));
+  const float P10 = fmaf(T1[0], S[0], fmaf(T1[1], S[1], T1[2] * S[2]));
+  const float P11 = fmaf(T1[0], S[1], fmaf(T1[1], S[3], T1[2] * S[4]));
+  const float P12 = fmaf(T1[0], S[2], fmaf(T1[1], S[4], T1[2] * S[5]));
+  const float a = fmaf(P00, T0[0], fmaf(P01, T0[1], P02 * T0[2])) + 0.3f;
+  const float b = fmaf(P00, T1[0], fmaf(P01, T1[1], P02 * T1[2]));
+  const float c = fmaf(P10, T1[0], fmaf(P11, T1[1], P12 * T1[2])) + 0.3f;
+  const float det = a * c - b * b;
+  if (!(det > 0.f)) return;
+  if (opacity < (1.f / 255.f)) return;
+  const float k = 2.f * logf(fmaxf(255.f * opacity, 1.f)) * (1.f + 1e-4f);
+  const float rx = sqrtf(k * a) + 0.01f;
+  const float ry = sqrtf(k * c) + 0.01f;
+  const float fx0 = floorf(u - rx), fx1 = floorf(u + rx);
+  const float fy0 = floorf(v - ry), fy1 = floorf(v + ry);
+  if (fx1 < 0.f || fx0 > (float)(cam.W - 1) || fy1 < 0.f || fy0 > (float)(cam.H - 1)) return;
+  const int px0 = (int)fmaxf(fx0, 0.f), px1 = (int)fminf(fx1, (float)(cam.W - 1));
+  const int py0 = (int)fmaxf(fy0, 0.f), py1 = (int)fminf(fy1, (float)(cam.H - 1));
+  const int x0 = px0 / cam.tw, x1 = px1 / cam.tw, y0 = py0 / cam.th, y1 = py1 / cam.th;
+  // colour: view direction in the canonical frame, L^T (mu' - eye)
+  const float* L = p.L;
+  float d0 = fmaf(L[0], dx, fmaf(L[3], dy, L[6] * dz));
+  float d1 = fmaf(L[1], dx, fmaf(L[4], dy, L[7] * dz));
+  float d2 = fmaf(L[2], dx, fmaf(L[5], dy, L[8] * dz));
+  const float inv = 1.f / sqrtf(fmaf(d0, d0, fmaf(d1, d1, d2 * d2)));
+  d0 *= inv; d1 *= inv; d2 *= inv;
+  float rgb[3];
+  sh_colour(sh_planes, sh_stride, n_sh4, deg, d0, d1, d2, rgb);
+  out.r0 = make_float4(u, v, c / det, -b / det);
+  out.r1 = make_float4(a / det, opacity, rgb[0], rgb[1]);
+  out.r2 = make_float4(rgb[2], rx, ry, tz);
+  out.rect = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) | ((uint32_t)y1 << 24);
+  out.count = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+}
+
+}  // namespace cs

@@ -1,0 +1,254 @@
+"""GPU parity of the HIP path against the FP64 oracle (through the C ABI).
+
+Tolerances (FP32 kernel vs FP64 oracle on the same FP32 inputs):
+* bone matrices, posed means / covariances: relative 2e-5 of the largest
+  entry magnitude (a few FP32 ulps through the 24-joint chain);
+* screen position u, v: 2e-3 px; conic, 2D covariance, depth: relative 1e-4;
+  colour: 1e-4 absolute;
+* tile rects and visibility: equal except where the oracle's footprint bound
+  lies within 2e-3 px of a pixel edge (both decisions are then correct);
+* per-tile splat lists: the same set except those rect-fragile splats, in an
+  order consistent with the FP64 depths except among depths equal to 2e-6
+  relative;
+* pixels: max-abs 2e-3 outside the fragile mask (pixels where some evaluated
+  splat has alpha within 3e-3 relative of 1/255, or T' within 3e-3 relative of
+  1e-4: an FP32 decision may flip there); flagged pixels are counted and
+  bounded by 2 * 1.25/255 + 2e-3.
+"""
+import numpy as np
+import pytest
+
+from oracle import frame as oframe
+from oracle import skinning as oskin
+from oracle import splat as osplat
+from paper_2501_17792_amd import synth
+
+from .gpu_common import (check_sorted_pairs, gpu_frame_buffers, rect_fragile, run_gpu,
+                         unpack_rect)
+
+pytestmark = pytest.mark.gpu
+
+FRAG = 3e-3
+FLAG_BOUND = 2 * 1.25 / 255 + 2e-3
+
+
+def _small_c2_scene(n_inst=12, n_gauss=20000, width=480, height=270):
+    """A slice of the 14-template SH3 crowd: fewer, smaller templates and
+    instances, a 480x270 image (ragged last tile row) and the C2 camera rig."""
+    templates = [synth.make_template(t, n_gauss, 3, synth.C2_LEVELS) for t in range(3)]
+    crowd = synth.make_crowd(100, n_inst, 3, 12.0, 0.3)
+    cam = synth.look_at((6.0, 1.7, -3.0), (6.0, 1.0, 8.0), width, height)
+    return synth.Scene("c2slice", templates, crowd, cam, lod_thresholds=(6.0, 11.0))
+
+
+def _compare_frame(scene, mode, thresholds, tile=(16, 16), **kw):
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    r, img = run_gpu(scene, mode, thresholds, tile=tile, **kw)
+    n_inst = scene.crowd.n
+    g = gpu_frame_buffers(r, n_inst)
+    cam = scene.camera
+    # ---- LoD levels: same decision unless the distance sits on a threshold
+    if mode == cs.CS_LOD_FULL:
+        levels = np.zeros(n_inst, np.int64)
+    else:
+        levels = oframe.fixed_levels(scene.crowd.pos, cam.eye, thresholds)
+        dist = oframe.instance_distance(scene.crowd.pos, cam.eye)
+        near = np.min(np.abs(dist[:, None] - np.asarray(thresholds)[None]), axis=1) < 1e-4
+        assert np.all((g["level"] == levels) | near)
+        levels = g["level"].astype(np.int64)  # decided identically within FP32 ties
+    out = oframe.render_frame(scene.templates, scene.crowd, cam, levels, tile[0], tile[1],
+                              fragile_alpha=FRAG, fragile_t=FRAG)
+    rec = out["records"]
+    # ---- forward kinematics
+    for i in range(n_inst):
+        t = scene.templates[int(scene.crowd.tid[i])]
+        B = oskin.bone_matrices(scene.crowd.pose[i], t.joints_rest, t.parents, scene.crowd.yaw[i],
+                                scene.crowd.pos[i, 0], scene.crowd.pos[i, 1])
+        scale = np.abs(B).max()
+        np.testing.assert_allclose(g["bones"][i], B, atol=2e-5 * scale, rtol=0)
+    # ---- work list
+    np.testing.assert_array_equal(g["offset"].astype(np.int64), rec["offsets"])
+    n = g["n_splats"]
+    assert n == rec["offsets"][-1]
+    # ---- skinning (posed means, covariances)
+    mu = r.debug("SKIN_MU", np.float32, 4 * n).reshape(n, 4) if not kw.get("fuse") else None
+    if mu is not None:
+        scale = np.abs(rec["mu"]).max()
+        np.testing.assert_allclose(mu[:, :3], rec["mu"], atol=2e-5 * scale, rtol=0)
+        cov = r.debug("SKIN_COV", np.float32, 4 * n).reshape(n, 4)
+        czz = r.debug("SKIN_COV2", np.float32, n)
+        gcov = np.stack([mu[:, 3], cov[:, 0], cov[:, 1], cov[:, 2], cov[:, 3], czz], 1)
+        ocov = rec["cov"][:, [0, 0, 0, 1, 1, 2], [0, 1, 2, 1, 2, 2]]
+        cscale = np.abs(ocov).max(axis=1, keepdims=True)
+        assert np.all(np.abs(gcov - ocov) <= 2e-5 * cscale + 1e-12)
+    # ---- projection records
+    frag_rect = rect_fragile(rec, tile[0], tile[1], cam.width, cam.height)
+    gvis = g["count"] > 0
+    ovis = rec["visible"]
+    assert np.all((gvis == ovis) | frag_rect), np.nonzero((gvis != ovis) & ~frag_rect)[0][:10]
+    both = gvis & ovis
+    R = g["rec"][both]
+    np.testing.assert_allclose(R[:, 0], rec["u"][both], atol=2e-3)
+    np.testing.assert_allclose(R[:, 1], rec["v"][both], atol=2e-3)
+    np.testing.assert_allclose(R[:, 11], rec["depth"][both], rtol=1e-5)
+    for k, name in [(2, "A"), (3, "B"), (4, "C")]:
+        ref = rec[name][both]
+        tol = 1e-4 * np.maximum(np.abs(rec["A"][both]), np.abs(rec["C"][both]))
+        assert np.all(np.abs(R[:, k] - ref) <= tol), name
+    np.testing.assert_allclose(R[:, 5], rec["opacity"][both], rtol=0, atol=0)
+    np.testing.assert_allclose(R[:, [6, 7, 8]], rec["rgb"][both], atol=1e-4)
+    np.testing.assert_allclose(R[:, 9], rec["rx"][both], rtol=1e-4)
+    np.testing.assert_allclose(R[:, 10], rec["ry"][both], rtol=1e-4)
+    grect = unpack_rect(g["rect"][both])
+    ok = np.all(grect == rec["rect"][both], axis=1) | frag_rect[both]
+    assert ok.all(), np.nonzero(~ok)[0][:10]
+    # ---- binning and sort
+    if g["n_pairs"]:
+        check_sorted_pairs(g, n)
+        ntx = (cam.width + tile[0] - 1) // tile[0]
+        nty = (cam.height + tile[1] - 1) // tile[1]
+        gt = (g["skeys"] >> np.uint64(31)).astype(np.int64)
+        ot = (out["sorted_keys"] >> np.uint64(31)).astype(np.int64)
+        ov = out["sorted_vals"].astype(np.int64)
+        gv = g["svals"].astype(np.int64)
+        gs, os_ = np.searchsorted(gt, np.arange(ntx * nty + 1)), np.searchsorted(ot, np.arange(ntx * nty + 1))
+        depth = rec["depth"]
+        for tt in range(ntx * nty):
+            a = gv[gs[tt]:gs[tt + 1]]
+            b = ov[os_[tt]:os_[tt + 1]]
+            sa = set(a.tolist()) - set(np.nonzero(frag_rect)[0].tolist())
+            sb = set(b.tolist()) - set(np.nonzero(frag_rect)[0].tolist())
+            assert sa == sb, f"tile {tt}"
+            # order consistent with FP64 depth except near ties
+            d = depth[a]
+            bad = d[1:] < d[:-1] * (1 - 2e-6)
+            assert not bad.any(), f"tile {tt} depth order"
+    # ---- pixels
+    diff = np.abs(img - out["image"]).max(axis=0)
+    frag = out["fragile"]
+    clean = ~frag
+    worst = diff[clean].max() if clean.any() else 0.0
+    assert worst <= 2e-3, f"max-abs {worst} outside the fragile mask"
+    if frag.any():
+        assert diff[frag].max() <= FLAG_BOUND
+    return r, img, out, g, dict(max_abs=float(worst), fragile=int(frag.sum()), pixels=int(frag.size))
+
+
+def test_c1_plain_full_detail():
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    sc = synth.scene_c1()
+    _, img, out, g, info = _compare_frame(sc, cs.CS_LOD_FULL, ())
+    assert g["n_pairs"] > 1000
+    print("C1", info)
+
+
+def test_c2_slice_fixed_lod():
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    sc = _small_c2_scene()
+    _, img, out, g, info = _compare_frame(sc, cs.CS_LOD_FIXED, sc.lod_thresholds)
+    assert len(set(g["level"].tolist())) >= 2  # several levels in play
+    print("C2 slice", info)
+
+
+@pytest.mark.parametrize("tile", [(8, 8), (32, 8), (16, 32)])
+def test_c2_slice_other_tiles(tile):
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    sc = _small_c2_scene(n_inst=6)
+    _compare_frame(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, tile=tile)
+
+
+def test_tile_shape_launch_and_fusion_invariance():
+    """The image is bit-identical across tile shapes, per-instance vs batched
+    launches, and skin+project fused vs separate."""
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    sc = _small_c2_scene(n_inst=8)
+    _, ref = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds)
+    for kw in [dict(tile=(8, 8)), dict(tile=(32, 32)), dict(tile=(8, 32)),
+               dict(launch_mode=cs.CS_LAUNCH_PER_INSTANCE), dict(fuse=True)]:
+        _, img = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, **kw)
+        assert np.array_equal(img, ref), kw
+
+
+def test_determinism_and_graph_replay():
+    import torch
+
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    sc = _small_c2_scene(n_inst=8)
+    r, ref = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds)
+    img2 = r.frame(sc.camera, cs.CS_LOD_FIXED, sc.lod_thresholds).cpu().numpy()
+    assert np.array_equal(img2, ref)
+    # graph capture of the whole frame, replayed with eager work in between
+    stream = torch.cuda.Stream()
+    r2 = cs.Renderer(0, stream=stream)
+    r2.upload_templates(sc.templates)
+    r2.set_crowd(sc.crowd)
+    with torch.cuda.stream(stream):
+        r2.frame(sc.camera, cs.CS_LOD_FIXED, sc.lod_thresholds)
+        out = torch.zeros((3, sc.camera.height, sc.camera.width), device="cuda")
+        r2.capture(sc.camera, out, cs.CS_LOD_FIXED, sc.lod_thresholds)
+        for k in range(3):
+            out.zero_()
+            r2.launch()
+            st = r2.poll()
+            assert st.overflow == 0
+            assert np.array_equal(out.cpu().numpy(), ref), k
+            r.frame(sc.camera, cs.CS_LOD_FIXED, sc.lod_thresholds)  # unrelated eager work
+    stream.synchronize()
+
+
+@pytest.mark.parametrize("n,bits", [(1, 44), (1000, 44), (4096, 44), (4097, 46), (123457, 44),
+                                    (2_000_000, 44), (70000, 13)])
+def test_standalone_sort_bit_exact(n, bits):
+    """The onesweep sort against numpy's stable argsort on tile-pair-shaped keys:
+    few distinct tiles (heavy duplicates), FP32 depth bits, ragged sizes."""
+    import torch
+
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    rng = np.random.default_rng(n + bits)
+    tiles = rng.integers(0, min(1 << max(bits - 31, 1), 300), size=n).astype(np.uint64)
+    depth = rng.uniform(0.2, 90.0, size=n).astype(np.float32)
+    depth[rng.uniform(size=n) < 0.2] = 7.5  # exact ties
+    if bits > 31:
+        keys = (tiles << np.uint64(31)) | depth.view(np.uint32).astype(np.uint64)
+    else:
+        keys = rng.integers(0, 1 << bits, size=n).astype(np.uint64)
+    vals = np.arange(n, dtype=np.uint32)
+    r = cs.Renderer(0)
+    kd = torch.from_numpy(keys.view(np.int64).copy()).cuda()
+    vd = torch.from_numpy(vals.view(np.int32).copy()).cuda()
+    r.sort_pairs(kd, vd, bits)
+    torch.cuda.synchronize()
+    order = np.argsort(keys, kind="stable")
+    assert np.array_equal(kd.cpu().numpy().view(np.uint64), keys[order])
+    assert np.array_equal(vd.cpu().numpy().view(np.uint32), vals[order])
+
+
+def test_empty_frame_and_bad_calls():
+    """A crowd entirely behind the camera renders the background; calls out of
+    order and bad arguments return status codes."""
+    import torch
+
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    sc = synth.scene_c1()
+    sc.camera.bg[:] = (0.25, 0.5, 0.75)
+    sc.crowd.pos[:] = (0.0, -20.0)  # behind the camera
+    r, img = run_gpu(sc, cs.CS_LOD_FULL, ())
+    assert r.last_stats.n_pairs == 0
+    assert np.all(img[0] == 0.25) and np.all(img[1] == 0.5) and np.all(img[2] == 0.75)
+    r2 = cs.Renderer(0)
+    with pytest.raises(cs.CrowdSplatError) as e:
+        r2.set_crowd(sc.crowd)
+        r2.select_lod(sc.camera, cs.CS_LOD_FULL)
+    assert e.value.code == cs.CS_ERR_STATE
+    r2.upload_templates(sc.templates)
+    with pytest.raises(cs.CrowdSplatError) as e:
+        r2.render(sc.camera)
+    assert e.value.code == cs.CS_ERR_STATE
