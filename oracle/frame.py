@@ -69,8 +69,8 @@ def frame_records(templates, crowd, cam, levels, tw, th):
 
 
 def render_frame(templates, crowd, cam, levels, tw=16, th=16,
-                 fragile_alpha=1e-4, fragile_t=1e-4):
+                 fragile_alpha=1e-4, fragile_t=1e-4, tie_impact=None):
     rec = frame_records(templates, crowd, cam, levels, tw, th)
-    out = splat.render_records(rec, cam, tw, th, fragile_alpha, fragile_t)
+    out = splat.render_records(rec, cam, tw, th, fragile_alpha, fragile_t, tie_impact)
     out["records"] = rec
     return out

@@ -185,10 +185,19 @@ def tile_ranges(sorted_keys, n_tiles: int) -> np.ndarray:
 # compositing
 # ----------------------------------------------------------------------------
 
-def _blend_list(px, py, order, sp, bg, fragile_alpha, fragile_t):
+def _blend_list(px, py, order, sp, bg, fragile_alpha, fragile_t, tie_impact=None):
     """Front-to-back compositing of the splats ``order`` at pixel centres
     (px + 1/2, py + 1/2). Returns colour [3,P], final T [P], fragile [P] and
-    the number of splats added per pixel."""
+    the number of splats added per pixel.
+
+    The fragile mask marks pixels where a float32 renderer may legitimately
+    take a different discrete decision: alpha within ``fragile_alpha``
+    (relative) of 1/255, T' within ``fragile_t`` (relative) of 1e-4, and, if
+    ``tie_impact`` is given, two consecutive alpha >= 1/255 splats whose depths
+    agree within their float32 error bound ``sp["depth_eps"]`` (their order is
+    then not fixed by float32 depths) when swapping them would move the pixel
+    by more than ``tie_impact`` (a swap changes it by T a1 a2 |c1 - c2|) or one
+    of them is the splat that stops the pixel."""
     P = px.shape[0]
     T = np.ones(P)
     C = np.zeros((3, P))
@@ -196,6 +205,9 @@ def _blend_list(px, py, order, sp, bg, fragile_alpha, fragile_t):
     fragile = np.zeros(P, bool)
     n_added = np.zeros(P, np.int64)
     cx, cy = px + 0.5, py + 0.5
+    last = np.full(P, -1, np.int64)      # previous alpha >= 1/255 splat
+    last_a = np.zeros(P)
+    last_T = np.ones(P)                  # T before that splat
     for s in order:
         if done.all():
             break
@@ -212,6 +224,19 @@ def _blend_list(px, py, order, sp, bg, fragile_alpha, fragile_t):
         Tn = T * (1.0 - alpha)
         fragile |= use & (np.abs(Tn - T_MIN) <= fragile_t * T_MIN)
         stop = use & (Tn < T_MIN)
+        if tie_impact is not None:
+            has = use & (last >= 0)
+            if has.any():
+                lp = np.where(has, last, 0)
+                tie = has & (np.abs(sp["depth"][lp] - sp["depth"][s])
+                             <= sp["depth_eps"][lp] + sp["depth_eps"][s])
+                if tie.any():
+                    dc = np.abs(sp["rgb"][lp] - sp["rgb"][s][None, :]).max(axis=1)
+                    impact = last_T * last_a * alpha * dc
+                    fragile |= tie & (stop | (impact > tie_impact))
+            last = np.where(use, s, last)
+            last_a = np.where(use, alpha, last_a)
+            last_T = np.where(use, T, last_T)
         done |= stop
         add = use & ~stop
         C += np.where(add, sp["rgb"][s][:, None] * (alpha * T), 0.0)
@@ -222,7 +247,7 @@ def _blend_list(px, py, order, sp, bg, fragile_alpha, fragile_t):
 
 
 def composite_tiled(sp, sorted_vals, ranges, width, height, tw, th, bg,
-                    fragile_alpha=1e-4, fragile_t=1e-4, tiles=None):
+                    fragile_alpha=1e-4, fragile_t=1e-4, tiles=None, tie_impact=None):
     """Per-tile front-to-back compositing over each tile's sorted list.
     Returns image [3,H,W], final transmittance [H,W] and the fragile mask."""
     ntx = (width + tw - 1) // tw
@@ -238,7 +263,8 @@ def composite_tiled(sp, sorted_vals, ranges, width, height, tw, th, bg,
         gy, gx = np.mgrid[y0:y1, x0:x1]
         s0, s1 = ranges[t]
         C, T, f, _ = _blend_list(gx.ravel().astype(np.float64), gy.ravel().astype(np.float64),
-                                 sorted_vals[s0:s1], sp, bg, fragile_alpha, fragile_t)
+                                 sorted_vals[s0:s1], sp, bg, fragile_alpha, fragile_t,
+                                 tie_impact)
         img[:, y0:y1, x0:x1] = C.reshape(3, y1 - y0, x1 - x0)
         Tfin[y0:y1, x0:x1] = T.reshape(y1 - y0, x1 - x0)
         frag[y0:y1, x0:x1] = f.reshape(y1 - y0, x1 - x0)
@@ -267,6 +293,10 @@ def splat_records(mu, cov, L, opacity, sh, degree, cam, tw, th):
                    cam.width, cam.height, tw, th)
     rgb = colour(sh, mu, L, cam.eye, degree)
     rec = dict(pr)
+    # float32 error bound of a depth computed from world coordinates of this size
+    mag = np.linalg.norm(np.asarray(mu, np.float64), axis=1) + np.linalg.norm(
+        np.asarray(cam.eye, np.float64))
+    rec["depth_eps"] = 4e-7 * mag + np.spacing(np.abs(pr["depth"]).astype(np.float32)).astype(np.float64)
     rec.update(fp)
     rec["opacity"] = np.asarray(opacity, np.float64)
     rec["rgb"] = rgb
@@ -280,7 +310,7 @@ def concat_records(parts):
     return out
 
 
-def render_records(rec, cam, tw, th, fragile_alpha=1e-4, fragile_t=1e-4):
+def render_records(rec, cam, tw, th, fragile_alpha=1e-4, fragile_t=1e-4, tie_impact=None):
     """Bin, sort and composite concatenated splat records (in emission order)."""
     ntx = (cam.width + tw - 1) // tw
     nty = (cam.height + th - 1) // th
@@ -288,6 +318,6 @@ def render_records(rec, cam, tw, th, fragile_alpha=1e-4, fragile_t=1e-4):
     skeys, svals = sort_pairs(keys, vals)
     ranges = tile_ranges(skeys, ntx * nty)
     img, T, frag = composite_tiled(rec, svals, ranges, cam.width, cam.height, tw, th,
-                                   cam.bg, fragile_alpha, fragile_t)
+                                   cam.bg, fragile_alpha, fragile_t, tie_impact=tie_impact)
     return dict(image=img, T=T, fragile=frag, keys=keys, vals=vals,
                 sorted_keys=skeys, sorted_vals=svals, ranges=ranges)
