@@ -71,7 +71,7 @@ typedef struct cs_options {
   int32_t skin_mode;         /* CS_SKIN_*                                       */
   int32_t launch_mode;       /* CS_LAUNCH_*                                     */
   int32_t fuse_skin_project; /* 1: cs_render_frame skins inline (same numbers)  */
-  int32_t reserved0;
+  int32_t profile_stages;    /* 1: time every stage with HIP events (eager only) */
   int64_t max_splats;        /* fixed splat capacity (0: grow on demand)        */
   int64_t max_pairs;         /* fixed tile-pair capacity (0: grow on demand)    */
   int32_t reserved[8];
@@ -248,6 +248,21 @@ cs_status cs_frame_poll(cs_ctx* ctx, cs_frame_stats* stats); /* synchronises */
 #define CS_BUF_FEATURES 16  /* float [n_inst][32] learned-LoD features               */
 #define CS_BUF_PRED     17  /* float [n_inst][8] learned-LoD predicted PSNR          */
 cs_status cs_debug_copy(cs_ctx* ctx, int32_t which, void* host_dst, int64_t offset, int64_t bytes);
+
+/* Per-stage GPU time of the last eager frame in milliseconds, from HIP events
+ * recorded on the context's stream around each stage (needs profile_stages).
+ * ms[k] for k < n: CS_STAGE_* order; -1 where a stage did not run. Synchronises. */
+#define CS_STAGE_LOD     0  /* LoD selection + work list                */
+#define CS_STAGE_FK      1  /* forward kinematics                      */
+#define CS_STAGE_SKIN    2  /* linear blend skinning                   */
+#define CS_STAGE_PROJECT 3  /* projection (+ skinning when fused)      */
+#define CS_STAGE_SCAN    4  /* tile-count scan                         */
+#define CS_STAGE_EMIT    5  /* pair emission + digit histograms        */
+#define CS_STAGE_SORT    6  /* all onesweep passes                     */
+#define CS_STAGE_RANGES  7  /* per-tile ranges                         */
+#define CS_STAGE_BLEND   8  /* compositing                             */
+#define CS_STAGE_COUNT   9
+cs_status cs_stage_times(cs_ctx* ctx, float* ms, int32_t n);
 
 /* Stable LSD radix sort of (key, value) pairs by the low key_bits bits of key,
  * the same onesweep kernels that order the frame's tile pairs. DEVICE buffers;

@@ -32,13 +32,14 @@ BUF = dict(BONES=1, LEVEL=2, OFFSET=3, SKIN_MU=4, SKIN_COV=5, SKIN_COV2=6, RECOR
 EXPORTS = ["cs_create", "cs_destroy", "cs_last_error", "cs_version", "cs_upload_templates",
            "cs_select_lod", "cs_skin_instances", "cs_render_frame", "cs_render_backward",
            "cs_reserve", "cs_frame_capture", "cs_frame_launch", "cs_frame_poll", "cs_debug_copy",
-           "cs_sort_pairs"]
+           "cs_sort_pairs", "cs_stage_times"]
+STAGES = ["lod", "fk", "skin", "project", "scan", "emit", "sort", "ranges", "blend"]
 
 
 class CsOptions(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32),
                 ("skin_mode", ctypes.c_int32), ("launch_mode", ctypes.c_int32),
-                ("fuse_skin_project", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("fuse_skin_project", ctypes.c_int32), ("profile_stages", ctypes.c_int32),
                 ("max_splats", ctypes.c_int64), ("max_pairs", ctypes.c_int64),
                 ("reserved", ctypes.c_int32 * 8)]
 
@@ -118,6 +119,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cs_frame_poll": (i32, [P, ctypes.POINTER(CsFrameStats)]),
         "cs_debug_copy": (i32, [P, i32, P, i64, i64]),
         "cs_sort_pairs": (i32, [P, P, P, i64, i32]),
+        "cs_stage_times": (i32, [P, ctypes.POINTER(ctypes.c_float), i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -164,7 +166,8 @@ class Renderer:
     """One library context on one device and stream."""
 
     def __init__(self, device: int = 0, stream=None, tile=(16, 16), skin_mode=CS_SKIN_FULL,
-                 launch_mode=CS_LAUNCH_BATCHED, fuse=False, max_splats=0, max_pairs=0):
+                 launch_mode=CS_LAUNCH_BATCHED, fuse=False, max_splats=0, max_pairs=0,
+                 profile=False):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -173,6 +176,7 @@ class Renderer:
         opt = CsOptions()
         opt.tile_w, opt.tile_h = tile
         opt.skin_mode, opt.launch_mode, opt.fuse_skin_project = skin_mode, launch_mode, int(fuse)
+        opt.profile_stages = int(profile)
         opt.max_splats, opt.max_pairs = max_splats, max_pairs
         self.tile = tuple(tile)
         ctx = ctypes.c_void_p()
@@ -285,6 +289,11 @@ class Renderer:
         self._check(self.lib.cs_debug_copy(self.ctx, BUF[name], out.ctypes.data,
                                            offset * out.itemsize, out.nbytes))
         return out
+
+    def stage_times(self) -> dict:
+        ms = (ctypes.c_float * len(STAGES))()
+        self._check(self.lib.cs_stage_times(self.ctx, ms, len(STAGES)))
+        return {name: float(ms[k]) for k, name in enumerate(STAGES) if ms[k] >= 0}
 
     def sort_pairs(self, keys, vals, key_bits: int):
         self._check(self.lib.cs_sort_pairs(self.ctx, keys.data_ptr(), vals.data_ptr(),

@@ -95,6 +95,15 @@ struct cs_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   std::vector<uint32_t> chunk_off_host;  // per-instance launch mode
+  hipEvent_t ev[CS_STAGE_COUNT][2] = {};
+  bool ev_used[CS_STAGE_COUNT] = {};
+
+  // stage timing (eager frames with profile_stages only)
+  void mark(int stage, int end) {
+    if (!opt.profile_stages || capturing) return;
+    hipEventRecord(ev[stage][end], stream);
+    if (end) ev_used[stage] = true;
+  }
 
   cs_status fail(cs_status code, const std::string& msg) {
     err = msg;
@@ -312,6 +321,11 @@ cs_status cs_create(int32_t device, void* stream, const cs_options* opt, cs_ctx*
   if (s == CS_OK && hipHostMalloc((void**)&ctx->hdr_host, sizeof(FrameHdr), hipHostMallocDefault) != hipSuccess)
     s = CS_ERR_OOM;
   if (s == CS_OK && hipMemsetAsync(ctx->hdr, 0, sizeof(FrameHdr), ctx->stream) != hipSuccess) s = CS_ERR_DEVICE;
+  if (s == CS_OK && o.profile_stages) {
+    for (int k = 0; k < CS_STAGE_COUNT && s == CS_OK; ++k)
+      for (int e = 0; e < 2; ++e)
+        if (hipEventCreate(&ctx->ev[k][e]) != hipSuccess) s = CS_ERR_DEVICE;
+  }
   if (s == CS_OK && (o.max_splats || o.max_pairs)) {
     s = cs_reserve(ctx, 0, o.max_splats, o.max_pairs);
   }
@@ -327,6 +341,9 @@ void cs_destroy(cs_ctx* ctx) {
   if (!ctx) return;
   hipSetDevice(ctx->device);
   hipStreamSynchronize(ctx->stream);
+  for (int k = 0; k < CS_STAGE_COUNT; ++k)
+    for (int e = 0; e < 2; ++e)
+      if (ctx->ev[k][e]) hipEventDestroy(ctx->ev[k][e]);
   if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
   if (ctx->graph) hipGraphDestroy(ctx->graph);
   free_templates(ctx);
@@ -498,6 +515,8 @@ cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, co
   CamDev cd;
   CS_TRY(make_camera(ctx, cam, &cd));
   CS_TRY(ensure_instances(ctx, n_inst));
+  for (int k = 0; k < CS_STAGE_COUNT; ++k) ctx->ev_used[k] = false;
+  ctx->mark(CS_STAGE_LOD, 0);
   HIP_TRY(launch_frame_reset(ctx->hdr, ctx->hist, 0, 1, ctx->stream));
   HIP_TRY(launch_lod_fixed(inst, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), cd, lod->thresholds,
                            lod->mode == CS_LOD_FIXED ? lod->n_thresholds : 0, lod->mode == CS_LOD_FULL,
@@ -505,6 +524,7 @@ cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, co
   const uint32_t cap_s = (uint32_t)std::min<int64_t>(ctx->cap_splats, 0xffffffffll);
   HIP_TRY(launch_worklist(ctx->level, ctx->count_inst, n_inst, ctx->offset, ctx->chunk_off, ctx->chunks,
                           (int)ctx->cap_chunks, cap_s, ctx->hdr, level_out, ctx->stream));
+  ctx->mark(CS_STAGE_LOD, 1);
   if (!ctx->capturing) {
     // learn the frame's size, grow the splat arrays, and redo the (tiny) work list
     CS_TRY(read_header(ctx));
@@ -554,9 +574,12 @@ cs_status cs_skin_instances(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst
   hipSetDevice(ctx->device);
   ctx->inst = inst;
   ctx->pose = pose;
+  ctx->mark(CS_STAGE_FK, 0);
   HIP_TRY(launch_fk(inst, pose, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), ctx->bones, ctx->joints,
                     ctx->hdr, ctx->stream));
+  ctx->mark(CS_STAGE_FK, 1);
   if (!ctx->opt.fuse_skin_project) {
+    ctx->mark(CS_STAGE_SKIN, 0);
     SkinOut so{ctx->skin_mu, ctx->skin_cov, ctx->skin_zz};
     if (ctx->opt.launch_mode == CS_LAUNCH_PER_INSTANCE && !ctx->capturing) {
       CS_TRY(run_per_instance(ctx, false, so, 0, SplatOut{}));
@@ -565,6 +588,7 @@ cs_status cs_skin_instances(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst
                                       : persistent_grid(ctx->hdr_host->n_chunks, 1 << 20);
       HIP_TRY(launch_skin(work_view(ctx), so, 0, -1, grid, ctx->stream));
     }
+    ctx->mark(CS_STAGE_SKIN, 1);
   }
   ctx->state = kSkinned;
   return CS_OK;
@@ -586,6 +610,7 @@ cs_status cs_render_frame(cs_ctx* ctx, const cs_camera* cam, float* image, cs_fr
   SplatOut po{ctx->rec, ctx->rect, ctx->cnt};
   const int fused = ctx->opt.fuse_skin_project;
   const int64_t n_chunks = ctx->capturing ? ctx->cap_chunks : ctx->hdr_host->n_chunks;
+  ctx->mark(CS_STAGE_PROJECT, 0);
   if (ctx->opt.launch_mode == CS_LAUNCH_PER_INSTANCE && !ctx->capturing) {
     CS_TRY(run_per_instance(ctx, true, so, fused, po));
   } else {
@@ -593,12 +618,15 @@ cs_status cs_render_frame(cs_ctx* ctx, const cs_camera* cam, float* image, cs_fr
     HIP_TRY(launch_project(work_view(ctx), so, fused, cd, po, (uint32_t)ctx->cap_splats, 0, -1, grid,
                            ctx->stream));
   }
+  ctx->mark(CS_STAGE_PROJECT, 1);
   // A5 scan of tile counts
   const int64_t n_splats = ctx->capturing ? ctx->cap_splats : ctx->hdr_host->n_splats;
   const int scan_blocks = (int)std::max<int64_t>(1, (n_splats + scan_tile() - 1) / scan_tile());
   uint32_t cap_p = (uint32_t)std::min<int64_t>(ctx->cap_pairs, kMaxPairsLimit);
+  ctx->mark(CS_STAGE_SCAN, 0);
   HIP_TRY(launch_scan_counts(ctx->cnt, ctx->pair_off, ctx->scan_sums, scan_blocks, ctx->hdr,
                              ctx->capturing ? cap_p : kMaxPairsLimit, ctx->stream));
+  ctx->mark(CS_STAGE_SCAN, 1);
   int64_t n_pairs = ctx->cap_pairs;
   if (!ctx->capturing) {
     CS_TRY(read_header(ctx));
@@ -611,23 +639,31 @@ cs_status cs_render_frame(cs_ctx* ctx, const cs_camera* cam, float* image, cs_fr
   }
   // A6 emission + digit histograms
   const int emit_grid = ctx->capturing ? 1024 : persistent_grid((n_splats + 255) / 256, 1024);
+  ctx->mark(CS_STAGE_EMIT, 0);
   HIP_TRY(launch_emit(ctx->cnt, ctx->pair_off, ctx->rect, ctx->rec, cd, ctx->keys[0], ctx->vals[0],
                       ctx->hist, ctx->passes, ctx->hdr, cap_p, emit_grid, ctx->stream));
   HIP_TRY(launch_digit_offsets(ctx->hist, ctx->passes, ctx->stream));
+  ctx->mark(CS_STAGE_EMIT, 1);
   // A7 onesweep passes, ping-pong between the two pair buffers
   const int64_t parts = ctx->capturing ? ctx->cap_parts : (n_pairs + kSortPart - 1) / kSortPart;
   const int sort_grid = persistent_grid(parts, 512);
   int src = 0;
+  ctx->mark(CS_STAGE_SORT, 0);
   for (int p = 0; p < ctx->passes; ++p) {
     HIP_TRY(launch_onesweep(ctx->keys[src], ctx->vals[src], ctx->keys[1 - src], ctx->vals[1 - src],
                             ctx->hist + p * kSortBins, ctx->lookback, ctx->hdr, p, (int)ctx->cap_parts,
                             cap_p, nullptr, sort_grid, ctx->stream));
     src = 1 - src;
   }
+  ctx->mark(CS_STAGE_SORT, 1);
   ctx->sorted = src;
   // A8 ranges, A9 blend
+  ctx->mark(CS_STAGE_RANGES, 0);
   HIP_TRY(launch_ranges(ctx->keys[src], ctx->hdr, cap_p, n_tiles, ctx->ranges, ctx->stream));
+  ctx->mark(CS_STAGE_RANGES, 1);
+  ctx->mark(CS_STAGE_BLEND, 0);
   HIP_TRY(launch_blend(ctx->ranges, ctx->vals[src], ctx->rec, cd, image, ctx->hdr, ctx->stream));
+  ctx->mark(CS_STAGE_BLEND, 1);
   ctx->state = kRendered;
   if (stats) {
     CS_TRY(read_header(ctx));
@@ -747,6 +783,23 @@ cs_status cs_debug_copy(cs_ctx* ctx, int32_t which, void* host_dst, int64_t offs
   hipSetDevice(ctx->device);
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   HIP_TRY(hipMemcpy(host_dst, (const char*)src + offset, bytes, hipMemcpyDeviceToHost));
+  return CS_OK;
+}
+
+cs_status cs_stage_times(cs_ctx* ctx, float* ms, int32_t n) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (!ms || n < 0) return ctx->fail(CS_ERR_INVALID, "bad output");
+  if (!ctx->opt.profile_stages) return ctx->fail(CS_ERR_STATE, "context made without profile_stages");
+  hipSetDevice(ctx->device);
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  for (int k = 0; k < n; ++k) {
+    ms[k] = -1.f;
+    if (k < CS_STAGE_COUNT && ctx->ev_used[k]) {
+      float t = 0.f;
+      HIP_TRY(hipEventElapsedTime(&t, ctx->ev[k][0], ctx->ev[k][1]));
+      ms[k] = t;
+    }
+  }
   return CS_OK;
 }
 
