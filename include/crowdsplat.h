@@ -57,6 +57,7 @@ typedef int32_t cs_status;
 #define CS_LOD_FULL    0  /* every instance at level 0                           */
 #define CS_LOD_FIXED   1  /* level = number of distance thresholds <= distance   */
 #define CS_LOD_LEARNED 2  /* coarsest level whose predicted PSNR clears a floor  */
+#define CS_LOD_CONSTANT 3 /* every instance at lod->level                        */
 
 #define CS_MAX_LEVELS     8
 #define CS_MAX_TEMPLATES  64
@@ -120,10 +121,31 @@ typedef struct cs_lod_params {
   int32_t mode;              /* CS_LOD_*                                        */
   int32_t n_thresholds;      /* FIXED: 0..7 increasing distances (m)            */
   float thresholds[7];
+  int32_t level;             /* CONSTANT: the level of every instance           */
   float psnr_min;            /* LEARNED: quality floor (dB)                     */
   float margin;              /* LEARNED: extra dB required of the prediction    */
-  const void* mlp;           /* LEARNED: device pointer, layout of cs_mlp_pack  */
+  const void* mlp;           /* LEARNED: device pointer to a cs_mlp             */
 } cs_lod_params;
+
+/* The learned-LoD network (device memory, laid out exactly as below).
+ * Inputs: 32 features (31 used, see cs_lod_features) z-scored with mu and
+ * inv_sd; 31 -> 64 -> ReLU -> 64 -> ReLU -> 5 predicted PSNR values (dB), one
+ * per level. Layer inputs and weights enter the matrix cores as bfloat16
+ * (round to nearest even); accumulation and biases are FP32. params holds the
+ * FP32 master weights, each layer out-major: w1[64][32] b1[64] w2[64][64]
+ * b2[64] w3[16][64] b3[16] (rows 5..15 of w3 and b3 unused, kept zero);
+ * w_bf16 holds their bfloat16 copies (w1, w2, w3), refreshed by
+ * cs_mlp_sync and by every training step. */
+#define CS_MLP_NPARAM 7312
+#define CS_MLP_NBF16  7168
+typedef struct cs_mlp {
+  float mu[32];
+  float inv_sd[32];
+  float pca_mean[72];          /* pose PCA: coordinates = basis (pose - mean) */
+  float pca_basis[8 * 72];
+  float params[CS_MLP_NPARAM];
+  uint16_t w_bf16[CS_MLP_NBF16];
+} cs_mlp;
 
 typedef struct cs_frame_stats {
   int64_t n_splats;          /* instance-Gaussians skinned this frame           */
@@ -246,8 +268,48 @@ cs_status cs_frame_poll(cs_ctx* ctx, cs_frame_stats* stats); /* synchronises */
 #define CS_BUF_SVALS    14  /* uint32 [n_pairs] sorted splat indices                 */
 #define CS_BUF_RANGES   15  /* uint32 [n_tiles][2] [start, end) per tile            */
 #define CS_BUF_FEATURES 16  /* float [n_inst][32] learned-LoD features               */
-#define CS_BUF_PRED     17  /* float [n_inst][8] learned-LoD predicted PSNR          */
+#define CS_BUF_PRED     17  /* float [n_inst][16] learned-LoD predicted PSNR         */
+#define CS_BUF_VIEWS    18  /* int64 [n_inst][6] window x0 y0 w h (px), tile base, atlas offset */
+#define CS_BUF_JOINTS   19  /* float [n_inst][24][3] posed joint positions           */
 cs_status cs_debug_copy(cs_ctx* ctx, int32_t which, void* host_dst, int64_t offset, int64_t bytes);
+
+/* ---- learned LoD ----------------------------------------------------------
+ * Features of every instance (posed joints from forward kinematics, then the
+ * screen box covering them padded by the template's rest pad radius):
+ *  [0] distance |(px,0,pz) - eye|   [1] clipped box area / (W H)
+ *  [2..9] pose PCA coordinates (net->pca_*)   [10..23] template one-hot
+ *  [24] log distance  [25] log(area + 1e-6)  [26,27] box centre / (W, H)
+ *  [28,29] cos, sin of the facing relative to the direction to the camera
+ *  [30] visible fraction of the box   [31] 0
+ * feat DEVICE [n_inst][32] float. net DEVICE cs_mlp (only its PCA is read). */
+cs_status cs_lod_features(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, const float* pose,
+                          const cs_camera* cam, const cs_mlp* net, float* feat);
+/* Network outputs for raw features: pred DEVICE [n][16] float (5 used). */
+cs_status cs_mlp_predict(cs_ctx* ctx, const cs_mlp* net, const float* feat, int32_t n, float* pred);
+/* Refresh net->w_bf16 from net->params (after writing params from the host). */
+cs_status cs_mlp_sync(cs_ctx* ctx, cs_mlp* net);
+/* One Adam step (lr, beta 0.9/0.999, eps 1e-8, bias correction with step >= 1)
+ * on the mean squared error over a batch: feat DEVICE [batch][32] raw
+ * features, target DEVICE [batch][5] PSNR labels, batch in [16, 1024] and a
+ * multiple of 16. adam_m, adam_v DEVICE [CS_MLP_NPARAM] float moments.
+ * loss DEVICE float or NULL. Deterministic (one workgroup, fixed order). */
+cs_status cs_mlp_train_step(cs_ctx* ctx, cs_mlp* net, float* adam_m, float* adam_v,
+                            const float* feat, const float* target, int32_t batch, int32_t step,
+                            float lr, float* loss);
+
+/* ---- views: every instance rendered alone into its own window -------------
+ * After cs_select_lod and cs_skin_instances, render each instance by itself
+ * into the whole-tile window around its screen box (the box of
+ * cs_lod_features widened to tiles and clipped to the image). The pixels
+ * equal those of a full frame holding only that instance. Windows are stored
+ * one after another in atlas (DEVICE float), each [3][h][w]; layout via
+ * CS_BUF_VIEWS. atlas_floats is its capacity; *needed (host) receives the
+ * size used. Errors: CS_ERR_CAPACITY if the atlas is too small. */
+cs_status cs_render_views(cs_ctx* ctx, const cs_camera* cam, float* atlas, int64_t atlas_floats,
+                          int64_t* needed);
+/* PSNR (dB, clamped to 60) of each view of atlas against atlas_ref, both laid
+ * out by the last cs_render_views. psnr DEVICE [n_inst] float. */
+cs_status cs_view_psnr(cs_ctx* ctx, const float* atlas_ref, const float* atlas, float* psnr);
 
 /* Per-stage GPU time of the last eager frame in milliseconds, from HIP events
  * recorded on the context's stream around each stage (needs profile_stages).

@@ -21,18 +21,23 @@ CS_ERR_INVALID, CS_ERR_OOM, CS_ERR_DEVICE, CS_ERR_CAPACITY, CS_ERR_STATE, CS_ERR
 CS_MEM_HOST, CS_MEM_DEVICE = 0, 1
 CS_SKIN_FULL, CS_SKIN_MEANS_ONLY = 0, 1
 CS_LAUNCH_BATCHED, CS_LAUNCH_PER_INSTANCE = 0, 1
-CS_LOD_FULL, CS_LOD_FIXED, CS_LOD_LEARNED = 0, 1, 2
+CS_LOD_FULL, CS_LOD_FIXED, CS_LOD_LEARNED, CS_LOD_CONSTANT = 0, 1, 2, 3
+CS_MLP_NPARAM, CS_MLP_NBF16 = 7312, 7168
+#: offsets of the layers inside cs_mlp.params (out-major weights)
+MLP_OFF = dict(w1=(0, (64, 32)), b1=(2048, (64,)), w2=(2112, (64, 64)), b2=(6208, (64,)),
+               w3=(6272, (16, 64)), b3=(7296, (16,)))
 CS_MAX_LEVELS = 8
 
 BUF = dict(BONES=1, LEVEL=2, OFFSET=3, SKIN_MU=4, SKIN_COV=5, SKIN_COV2=6, RECORD=7, RECT=8,
            COUNT=9, PAIR_OFF=10, KEYS=11, VALS=12, SKEYS=13, SVALS=14, RANGES=15, FEATURES=16,
-           PRED=17)
+           PRED=17, VIEWS=18, JOINTS=19)
 
 #: every symbol include/crowdsplat.h declares
 EXPORTS = ["cs_create", "cs_destroy", "cs_last_error", "cs_version", "cs_upload_templates",
            "cs_select_lod", "cs_skin_instances", "cs_render_frame", "cs_render_backward",
            "cs_reserve", "cs_frame_capture", "cs_frame_launch", "cs_frame_poll", "cs_debug_copy",
-           "cs_sort_pairs", "cs_stage_times"]
+           "cs_sort_pairs", "cs_stage_times", "cs_lod_features", "cs_mlp_predict", "cs_mlp_sync",
+           "cs_mlp_train_step", "cs_render_views", "cs_view_psnr"]
 STAGES = ["lod", "fk", "skin", "project", "scan", "emit", "sort", "ranges", "blend"]
 
 
@@ -63,8 +68,14 @@ class CsCamera(ctypes.Structure):
 
 class CsLodParams(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("n_thresholds", ctypes.c_int32),
-                ("thresholds", ctypes.c_float * 7), ("psnr_min", ctypes.c_float),
-                ("margin", ctypes.c_float), ("mlp", ctypes.c_void_p)]
+                ("thresholds", ctypes.c_float * 7), ("level", ctypes.c_int32),
+                ("psnr_min", ctypes.c_float), ("margin", ctypes.c_float), ("mlp", ctypes.c_void_p)]
+
+
+class CsMlp(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_float * 32), ("inv_sd", ctypes.c_float * 32),
+                ("pca_mean", ctypes.c_float * 72), ("pca_basis", ctypes.c_float * (8 * 72)),
+                ("params", ctypes.c_float * CS_MLP_NPARAM), ("w_bf16", ctypes.c_uint16 * CS_MLP_NBF16)]
 
 
 class CsFrameStats(ctypes.Structure):
@@ -120,6 +131,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cs_debug_copy": (i32, [P, i32, P, i64, i64]),
         "cs_sort_pairs": (i32, [P, P, P, i64, i32]),
         "cs_stage_times": (i32, [P, ctypes.POINTER(ctypes.c_float), i32]),
+        "cs_lod_features": (i32, [P, i32, P, P, ctypes.POINTER(CsCamera), P, P]),
+        "cs_mlp_predict": (i32, [P, P, P, i32, P]),
+        "cs_mlp_sync": (i32, [P, P]),
+        "cs_mlp_train_step": (i32, [P, P, P, P, P, P, i32, i32, ctypes.c_float, P]),
+        "cs_render_views": (i32, [P, ctypes.POINTER(CsCamera), P, i64, ctypes.POINTER(i64)]),
+        "cs_view_psnr": (i32, [P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -141,9 +158,10 @@ def camera_struct(cam) -> CsCamera:
 
 
 def lod_struct(mode: int, thresholds: Sequence[float] = (), psnr_min: float = 40.0,
-               margin: float = 1.0, mlp_ptr: int = 0) -> CsLodParams:
+               margin: float = 1.0, mlp_ptr: int = 0, level: int = 0) -> CsLodParams:
     p = CsLodParams()
     p.mode = mode
+    p.level = level
     p.n_thresholds = len(thresholds)
     for k, t in enumerate(thresholds):
         p.thresholds[k] = float(t)
@@ -237,9 +255,9 @@ class Renderer:
         self.n_inst = crowd.n
 
     def select_lod(self, cam, mode=CS_LOD_FIXED, thresholds=(10.0, 25.0), level_out=None,
-                   psnr_min=40.0, margin=1.0, mlp_ptr=0):
+                   psnr_min=40.0, margin=1.0, mlp_ptr=0, level=0):
         c = camera_struct(cam)
-        p = lod_struct(mode, thresholds, psnr_min, margin, mlp_ptr)
+        p = lod_struct(mode, thresholds, psnr_min, margin, mlp_ptr, level)
         self._check(self.lib.cs_select_lod(self.ctx, self.n_inst, self.inst_dev.data_ptr(),
                                            self.pose_dev.data_ptr(), ctypes.byref(c), ctypes.byref(p),
                                            level_out.data_ptr() if level_out is not None else None))
@@ -269,6 +287,7 @@ class Renderer:
 
     def capture(self, cam, image, mode=CS_LOD_FIXED, thresholds=(10.0, 25.0), mlp_ptr=0,
                 psnr_min=40.0, margin=1.0):
+        """Capture select_lod -> skin -> render for fixed pointers into a graph."""
         c = camera_struct(cam)
         p = lod_struct(mode, thresholds, psnr_min, margin, mlp_ptr)
         self._keep = [c, p]
@@ -294,6 +313,53 @@ class Renderer:
         ms = (ctypes.c_float * len(STAGES))()
         self._check(self.lib.cs_stage_times(self.ctx, ms, len(STAGES)))
         return {name: float(ms[k]) for k, name in enumerate(STAGES) if ms[k] >= 0}
+
+    # ------------------------------------------------------------ learned LoD
+    def lod_features(self, cam, net, feat=None):
+        torch = self.torch
+        if feat is None:
+            feat = torch.empty((self.n_inst, 32), dtype=torch.float32, device=self.device)
+        c = camera_struct(cam)
+        self._check(self.lib.cs_lod_features(self.ctx, self.n_inst, self.inst_dev.data_ptr(),
+                                             self.pose_dev.data_ptr(), ctypes.byref(c), net.data_ptr(),
+                                             feat.data_ptr()))
+        return feat
+
+    def mlp_predict(self, net, feat):
+        pred = self.torch.empty((feat.shape[0], 16), dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.cs_mlp_predict(self.ctx, net.data_ptr(), feat.data_ptr(), feat.shape[0],
+                                            pred.data_ptr()))
+        return pred
+
+    def mlp_sync(self, net):
+        self._check(self.lib.cs_mlp_sync(self.ctx, net.data_ptr()))
+
+    def mlp_train_step(self, net, m, v, feat, target, step, lr=1e-3, loss=None):
+        self._check(self.lib.cs_mlp_train_step(self.ctx, net.data_ptr(), m.data_ptr(), v.data_ptr(),
+                                               feat.data_ptr(), target.data_ptr(), feat.shape[0], step,
+                                               lr, loss.data_ptr() if loss is not None else None))
+
+    def render_views(self, cam, atlas=None):
+        """Render each instance alone into its window; returns (atlas, views [n,6])."""
+        torch = self.torch
+        c = camera_struct(cam)
+        need = ctypes.c_int64(0)
+        if atlas is None:
+            atlas = torch.empty(1, dtype=torch.float32, device=self.device)
+        st = self.lib.cs_render_views(self.ctx, ctypes.byref(c), atlas.data_ptr(), atlas.numel(),
+                                      ctypes.byref(need))
+        if st == CS_ERR_CAPACITY and need.value > atlas.numel():
+            atlas = torch.empty(max(need.value, 1), dtype=torch.float32, device=self.device)
+            st = self.lib.cs_render_views(self.ctx, ctypes.byref(c), atlas.data_ptr(), atlas.numel(),
+                                          ctypes.byref(need))
+        self._check(st)
+        views = self.debug("VIEWS", np.int64, 6 * self.n_inst).reshape(self.n_inst, 6)
+        return atlas, views
+
+    def view_psnr(self, atlas_ref, atlas):
+        out = self.torch.empty(self.n_inst, dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.cs_view_psnr(self.ctx, atlas_ref.data_ptr(), atlas.data_ptr(), out.data_ptr()))
+        return out
 
     def sort_pairs(self, keys, vals, key_bits: int):
         self._check(self.lib.cs_sort_pairs(self.ctx, keys.data_ptr(), vals.data_ptr(),

@@ -12,17 +12,42 @@
 
 namespace cs {
 
-template <int TW, int TH>
+template <int TW, int TH, bool VIEW>
 __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restrict__ ranges,
                                                        const uint32_t* __restrict__ svals,
                                                        const float4* __restrict__ rec, CamDev cam,
                                                        float* __restrict__ image,
-                                                       const FrameHdr* __restrict__ hdr) {
+                                                       const FrameHdr* __restrict__ hdr, ViewDev view) {
   constexpr int N = TW * TH;
   constexpr int ROWS = 64 / TW;  // pixel rows per wave
   __shared__ float4 s_r0[N], s_r1[N], s_r2[N];
   const int tile = blockIdx.x;
-  const int tx = tile % cam.tiles_x, ty = tile / cam.tiles_x;
+  int tx, ty;
+  float* out = image;
+  int out_x0 = 0, out_y0 = 0, out_w = cam.W, out_h = cam.H;
+  if (VIEW) {  // tile of one instance's window; output into that window of the atlas
+    int lo = 0, hi = view.n_inst;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (view.views[(size_t)mid * 6 + 4] <= tile) lo = mid;
+      else hi = mid;
+    }
+    // skip windows with no tiles that share this base
+    while (lo + 1 < view.n_inst && view.views[(size_t)(lo + 1) * 6 + 4] <= tile) ++lo;
+    const int4 cw = view.crop[lo];
+    const int local = tile - (int)view.views[(size_t)lo * 6 + 4];
+    tx = cw.x + local % (cw.z - cw.x);
+    ty = cw.y + local / (cw.z - cw.x);
+    const int64_t* v = view.views + (size_t)lo * 6;
+    out = image + v[5];
+    out_x0 = (int)v[0];
+    out_y0 = (int)v[1];
+    out_w = (int)v[2];
+    out_h = (int)v[3];
+  } else {
+    tx = tile % cam.tiles_x;
+    ty = tile / cam.tiles_x;
+  }
   const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
   const int px = tx * TW + lx, py = ty * TH + ly;
   const bool inside = px < cam.W && py < cam.H;
@@ -77,25 +102,32 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
     if (__syncthreads_count(!done) == 0) break;
   }
   if (inside) {
-    const size_t plane = (size_t)cam.W * cam.H;
-    const size_t o = (size_t)py * cam.W + px;
-    image[o] = fmaf(T, cam.bg[0], cr);
-    image[plane + o] = fmaf(T, cam.bg[1], cg);
-    image[2 * plane + o] = fmaf(T, cam.bg[2], cb);
+    const size_t plane = (size_t)out_w * out_h;
+    const size_t o = (size_t)(py - out_y0) * out_w + (px - out_x0);
+    out[o] = fmaf(T, cam.bg[0], cr);
+    out[plane + o] = fmaf(T, cam.bg[1], cg);
+    out[2 * plane + o] = fmaf(T, cam.bg[2], cb);
   }
 }
 
 template <int TW, int TH>
 static hipError_t launch_blend_t(const uint32_t* ranges, const uint32_t* svals, const float4* rec,
-                                 CamDev cam, float* image, const FrameHdr* hdr, hipStream_t st) {
-  blend_kernel<TW, TH><<<cam.tiles_x * cam.tiles_y, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr);
+                                 CamDev cam, float* image, const FrameHdr* hdr, const ViewDev* view,
+                                 hipStream_t st) {
+  if (view) {
+    if (view->n_tiles > 0)
+      blend_kernel<TW, TH, true><<<view->n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr, *view);
+  } else {
+    blend_kernel<TW, TH, false><<<cam.tiles_x * cam.tiles_y, TW * TH, 0, st>>>(ranges, svals, rec, cam, image,
+                                                                                hdr, ViewDev{});
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_blend(const uint32_t* ranges, const uint32_t* svals, const float4* rec, CamDev cam,
-                        float* image, const FrameHdr* hdr, hipStream_t st) {
+                        float* image, const FrameHdr* hdr, const ViewDev* view, hipStream_t st) {
 #define CS_BLEND_CASE(W_, H_) \
-  if (cam.tw == W_ && cam.th == H_) return launch_blend_t<W_, H_>(ranges, svals, rec, cam, image, hdr, st);
+  if (cam.tw == W_ && cam.th == H_) return launch_blend_t<W_, H_>(ranges, svals, rec, cam, image, hdr, view, st);
   CS_BLEND_CASE(8, 8)
   CS_BLEND_CASE(8, 16)
   CS_BLEND_CASE(8, 32)

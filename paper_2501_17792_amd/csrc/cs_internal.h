@@ -79,6 +79,16 @@ struct WorkDev {
   const TemplateDev* tpl;
   FrameHdr* hdr;
   int32_t skin_mode;
+  const int4* crop;        // view mode: per-instance tile window [x0,y0,x1,y1), else null
+};
+
+// View mode (every instance alone in its own window), see cs_render_views.
+struct ViewDev {
+  const int64_t* views;    // [n_inst][6] x0 y0 w h tile_base atlas_offset
+  const int4* crop;        // [n_inst] tile window
+  const uint32_t* offset;  // [n_inst + 1] splat offsets
+  int32_t n_inst;
+  int32_t n_tiles;         // total view tiles
 };
 
 struct SkinOut {
@@ -104,8 +114,8 @@ hipError_t launch_frame_reset(FrameHdr* hdr, uint32_t* hist, int hist_len, int c
 hipError_t launch_fk(const cs_instance* inst, const float* pose, const TemplateDev* tpl, int n_inst,
                      int n_tpl, float* bones, float* joints_out, FrameHdr* hdr, hipStream_t st);
 hipError_t launch_lod_fixed(const cs_instance* inst, const TemplateDev* tpl, int n_inst, int n_tpl,
-                            CamDev cam, const float* thr, int n_thr, int full, int32_t* level,
-                            uint32_t* count, hipStream_t st);
+                            CamDev cam, const float* thr, int n_thr, int full, int const_level,
+                            int32_t* level, uint32_t* count, hipStream_t st);
 hipError_t launch_worklist(const int32_t* level, const uint32_t* count, int n_inst,
                            uint32_t* offset, uint32_t* chunk_off, Chunk* chunks, int max_chunks,
                            uint32_t max_splats, FrameHdr* hdr, int32_t* level_out,
@@ -120,7 +130,7 @@ hipError_t launch_scan_counts(const uint32_t* count, uint32_t* pair_off, uint32_
 hipError_t launch_emit(const uint32_t* count, const uint32_t* pair_off, const uint32_t* rect,
                        const float4* rec, CamDev cam, uint64_t* keys, uint32_t* vals,
                        uint32_t* hist, int passes, FrameHdr* hdr, uint32_t max_pairs, int grid,
-                       hipStream_t st);
+                       const ViewDev* view, hipStream_t st);
 hipError_t launch_digit_offsets(uint32_t* hist, int passes, hipStream_t st);
 hipError_t launch_onesweep(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout,
                            const uint32_t* goff, uint64_t* lookback, FrameHdr* hdr, int pass,
@@ -131,7 +141,20 @@ hipError_t launch_hist_keys(const uint64_t* keys, const uint32_t* n_ptr, uint32_
 hipError_t launch_ranges(const uint64_t* skeys, FrameHdr* hdr, uint32_t max_pairs, int n_tiles,
                          uint32_t* ranges, hipStream_t st);
 hipError_t launch_blend(const uint32_t* ranges, const uint32_t* svals, const float4* rec, CamDev cam,
-                        float* image, const FrameHdr* hdr, hipStream_t st);
+                        float* image, const FrameHdr* hdr, const ViewDev* view, hipStream_t st);
+hipError_t launch_features(const cs_instance* inst, const float* pose, const float* joints,
+                           const TemplateDev* tpl, int n_inst, int n_tpl, CamDev cam, const cs_mlp* net,
+                           float* feat, hipStream_t st);
+hipError_t launch_mlp_infer(const cs_mlp* net, const float* feat, int n, float* pred, int select,
+                            const cs_instance* inst, const TemplateDev* tpl, int n_tpl, float floor_db,
+                            int32_t* level, uint32_t* count, hipStream_t st);
+hipError_t launch_mlp_sync(cs_mlp* net, hipStream_t st);
+hipError_t launch_mlp_train(cs_mlp* net, float* m, float* v, const float* feat, const float* target, int batch,
+                            int step, float lr, float* loss, hipStream_t st);
+hipError_t launch_view_layout(const cs_instance* inst, const float* joints, const TemplateDev* tpl, int n_inst,
+                              int n_tpl, CamDev cam, int64_t* views, int4* crop, FrameHdr* hdr, hipStream_t st);
+hipError_t launch_view_psnr(const int64_t* views, int n_inst, const float* ref, const float* img, float* psnr,
+                            hipStream_t st);
 
 // Onesweep partition geometry.
 constexpr int kSortThreads = 256;

@@ -57,6 +57,18 @@ __global__ __launch_bounds__(kChunkThreads) void project_kernel(WorkDev w, SkinO
       }
       SplatRec r;
       project_gaussian(p, T.opacity[g], T.sh + g, T.n, T.n_sh4, T.sh_degree, cam, r);
+      if (w.crop && r.count) {  // view mode: keep the tiles inside the instance's window
+        const int4 cw = w.crop[ch.inst];
+        const int x0 = max((int)(r.rect & 0xffu), cw.x), y0 = max((int)((r.rect >> 8) & 0xffu), cw.y);
+        const int x1 = min((int)((r.rect >> 16) & 0xffu), cw.z - 1), y1 = min((int)(r.rect >> 24), cw.w - 1);
+        if (x1 < x0 || y1 < y0) {
+          r.count = 0u;
+          r.rect = 0u;
+        } else {
+          r.rect = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) | ((uint32_t)y1 << 24);
+          r.count = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+        }
+      }
       out.rec[3 * s + 0] = r.r0;
       out.rec[3 * s + 1] = r.r1;
       out.rec[3 * s + 2] = r.r2;

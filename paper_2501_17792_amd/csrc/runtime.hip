@@ -61,6 +61,12 @@ struct cs_ctx {
   Chunk* chunks = nullptr;
   float* bones = nullptr;
   float* joints = nullptr;
+  float* feat = nullptr;      // [cap_inst][32] learned-LoD features
+  float* pred = nullptr;      // [cap_inst][16] predictions
+  int64_t* views = nullptr;   // [cap_inst][6] view windows
+  int4* crop = nullptr;       // [cap_inst] view tile windows
+  int64_t view_tiles = 0, atlas_floats = 0;
+  bool views_valid = false;
 
   // per splat
   int64_t cap_splats = 0;
@@ -164,6 +170,10 @@ cs_status ensure_instances(cs_ctx* ctx, int64_t n_inst) {
   CS_TRY(dalloc(ctx, &ctx->chunks, cap * per));
   CS_TRY(dalloc(ctx, &ctx->bones, cap * kJoints * 12));
   CS_TRY(dalloc(ctx, &ctx->joints, cap * kJoints * 3));
+  CS_TRY(dalloc(ctx, &ctx->feat, cap * 32));
+  CS_TRY(dalloc(ctx, &ctx->pred, cap * 16));
+  CS_TRY(dalloc(ctx, &ctx->views, cap * 6));
+  CS_TRY(dalloc(ctx, &ctx->crop, cap));
   ctx->cap_inst = cap;
   ctx->cap_chunks = cap * per;
   return CS_OK;
@@ -357,6 +367,10 @@ void cs_destroy(cs_ctx* ctx) {
   dfree(&ctx->chunks);
   dfree(&ctx->bones);
   dfree(&ctx->joints);
+  dfree(&ctx->feat);
+  dfree(&ctx->pred);
+  dfree(&ctx->views);
+  dfree(&ctx->crop);
   dfree(&ctx->skin_mu);
   dfree(&ctx->skin_cov);
   dfree(&ctx->skin_zz);
@@ -509,8 +523,13 @@ cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, co
   if (!lod) return ctx->fail(CS_ERR_INVALID, "lod params are NULL");
   if (lod->mode == CS_LOD_FIXED && (lod->n_thresholds < 0 || lod->n_thresholds > 7))
     return ctx->fail(CS_ERR_INVALID, "0..7 thresholds");
-  if (lod->mode == CS_LOD_LEARNED) return ctx->fail(CS_ERR_UNSUPPORTED, "learned LoD not built yet");
-  if (lod->mode != CS_LOD_FULL && lod->mode != CS_LOD_FIXED) return ctx->fail(CS_ERR_INVALID, "bad lod mode");
+  if (lod->mode != CS_LOD_FULL && lod->mode != CS_LOD_FIXED && lod->mode != CS_LOD_LEARNED &&
+      lod->mode != CS_LOD_CONSTANT)
+    return ctx->fail(CS_ERR_INVALID, "bad lod mode");
+  if (lod->mode == CS_LOD_LEARNED && (!lod->mlp || !pose))
+    return ctx->fail(CS_ERR_INVALID, "learned LoD needs the network and the poses");
+  if (lod->mode == CS_LOD_CONSTANT && (lod->level < 0 || lod->level >= CS_MAX_LEVELS))
+    return ctx->fail(CS_ERR_INVALID, "constant level out of range");
   hipSetDevice(ctx->device);
   CamDev cd;
   CS_TRY(make_camera(ctx, cam, &cd));
@@ -518,9 +537,20 @@ cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, co
   for (int k = 0; k < CS_STAGE_COUNT; ++k) ctx->ev_used[k] = false;
   ctx->mark(CS_STAGE_LOD, 0);
   HIP_TRY(launch_frame_reset(ctx->hdr, ctx->hist, 0, 1, ctx->stream));
-  HIP_TRY(launch_lod_fixed(inst, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), cd, lod->thresholds,
-                           lod->mode == CS_LOD_FIXED ? lod->n_thresholds : 0, lod->mode == CS_LOD_FULL,
-                           ctx->level, ctx->count_inst, ctx->stream));
+  if (lod->mode == CS_LOD_LEARNED) {
+    HIP_TRY(launch_fk(inst, pose, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), ctx->bones, ctx->joints,
+                      ctx->hdr, ctx->stream));
+    const cs_mlp* net = (const cs_mlp*)lod->mlp;
+    HIP_TRY(launch_features(inst, pose, ctx->joints, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), cd, net,
+                            ctx->feat, ctx->stream));
+    HIP_TRY(launch_mlp_infer(net, ctx->feat, n_inst, ctx->pred, 1, inst, ctx->tpl_dev, (int)ctx->tpl.size(),
+                             lod->psnr_min + lod->margin, ctx->level, ctx->count_inst, ctx->stream));
+  } else {
+    HIP_TRY(launch_lod_fixed(inst, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), cd, lod->thresholds,
+                             lod->mode == CS_LOD_FIXED ? lod->n_thresholds : 0, lod->mode == CS_LOD_FULL,
+                             lod->mode == CS_LOD_CONSTANT ? lod->level : -1, ctx->level, ctx->count_inst,
+                             ctx->stream));
+  }
   const uint32_t cap_s = (uint32_t)std::min<int64_t>(ctx->cap_splats, 0xffffffffll);
   HIP_TRY(launch_worklist(ctx->level, ctx->count_inst, n_inst, ctx->offset, ctx->chunk_off, ctx->chunks,
                           (int)ctx->cap_chunks, cap_s, ctx->hdr, level_out, ctx->stream));
@@ -549,6 +579,7 @@ cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, co
   ctx->inst = inst;
   ctx->pose = pose;
   ctx->state = kLod;
+  ctx->views_valid = false;
   return CS_OK;
 }
 
@@ -594,14 +625,23 @@ cs_status cs_skin_instances(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst
   return CS_OK;
 }
 
-cs_status cs_render_frame(cs_ctx* ctx, const cs_camera* cam, float* image, cs_frame_stats* stats) {
-  if (!ctx) return CS_ERR_INVALID;
-  if (ctx->state < kSkinned) return ctx->fail(CS_ERR_STATE, "cs_render_frame before cs_skin_instances");
+static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs_frame_stats* stats,
+                             bool view_mode) {
+  if (ctx->state < kSkinned) return ctx->fail(CS_ERR_STATE, "render before cs_skin_instances");
   if (!image) return ctx->fail(CS_ERR_INVALID, "image is NULL");
   hipSetDevice(ctx->device);
   CS_TRY(make_camera(ctx, cam, &ctx->cam));
   const CamDev& cd = ctx->cam;
-  const int n_tiles = cd.tiles_x * cd.tiles_y;
+  ViewDev vd{};
+  if (view_mode) {
+    vd.views = ctx->views;
+    vd.crop = ctx->crop;
+    vd.offset = ctx->offset;
+    vd.n_inst = ctx->n_inst;
+    vd.n_tiles = (int32_t)ctx->view_tiles;
+  }
+  const ViewDev* vp = view_mode ? &vd : nullptr;
+  const int n_tiles = view_mode ? (int)ctx->view_tiles : cd.tiles_x * cd.tiles_y;
   CS_TRY(ensure_tiles(ctx, n_tiles));
   ctx->passes = sort_passes(n_tiles);
   HIP_TRY(launch_frame_reset(ctx->hdr, ctx->hist, kMaxPasses * kSortBins, 0, ctx->stream));
@@ -611,12 +651,13 @@ cs_status cs_render_frame(cs_ctx* ctx, const cs_camera* cam, float* image, cs_fr
   const int fused = ctx->opt.fuse_skin_project;
   const int64_t n_chunks = ctx->capturing ? ctx->cap_chunks : ctx->hdr_host->n_chunks;
   ctx->mark(CS_STAGE_PROJECT, 0);
-  if (ctx->opt.launch_mode == CS_LAUNCH_PER_INSTANCE && !ctx->capturing) {
+  if (ctx->opt.launch_mode == CS_LAUNCH_PER_INSTANCE && !ctx->capturing && !view_mode) {
     CS_TRY(run_per_instance(ctx, true, so, fused, po));
   } else {
     const int grid = ctx->capturing ? persistent_grid(n_chunks, 4096) : persistent_grid(n_chunks, 1 << 20);
-    HIP_TRY(launch_project(work_view(ctx), so, fused, cd, po, (uint32_t)ctx->cap_splats, 0, -1, grid,
-                           ctx->stream));
+    WorkDev wv = work_view(ctx);
+    if (view_mode) wv.crop = ctx->crop;
+    HIP_TRY(launch_project(wv, so, fused, cd, po, (uint32_t)ctx->cap_splats, 0, -1, grid, ctx->stream));
   }
   ctx->mark(CS_STAGE_PROJECT, 1);
   // A5 scan of tile counts
@@ -641,7 +682,7 @@ cs_status cs_render_frame(cs_ctx* ctx, const cs_camera* cam, float* image, cs_fr
   const int emit_grid = ctx->capturing ? 1024 : persistent_grid((n_splats + 255) / 256, 1024);
   ctx->mark(CS_STAGE_EMIT, 0);
   HIP_TRY(launch_emit(ctx->cnt, ctx->pair_off, ctx->rect, ctx->rec, cd, ctx->keys[0], ctx->vals[0],
-                      ctx->hist, ctx->passes, ctx->hdr, cap_p, emit_grid, ctx->stream));
+                      ctx->hist, ctx->passes, ctx->hdr, cap_p, emit_grid, vp, ctx->stream));
   HIP_TRY(launch_digit_offsets(ctx->hist, ctx->passes, ctx->stream));
   ctx->mark(CS_STAGE_EMIT, 1);
   // A7 onesweep passes, ping-pong between the two pair buffers
@@ -659,10 +700,10 @@ cs_status cs_render_frame(cs_ctx* ctx, const cs_camera* cam, float* image, cs_fr
   ctx->sorted = src;
   // A8 ranges, A9 blend
   ctx->mark(CS_STAGE_RANGES, 0);
-  HIP_TRY(launch_ranges(ctx->keys[src], ctx->hdr, cap_p, n_tiles, ctx->ranges, ctx->stream));
+  if (n_tiles > 0) HIP_TRY(launch_ranges(ctx->keys[src], ctx->hdr, cap_p, n_tiles, ctx->ranges, ctx->stream));
   ctx->mark(CS_STAGE_RANGES, 1);
   ctx->mark(CS_STAGE_BLEND, 0);
-  HIP_TRY(launch_blend(ctx->ranges, ctx->vals[src], ctx->rec, cd, image, ctx->hdr, ctx->stream));
+  if (n_tiles > 0) HIP_TRY(launch_blend(ctx->ranges, ctx->vals[src], ctx->rec, cd, image, ctx->hdr, vp, ctx->stream));
   ctx->mark(CS_STAGE_BLEND, 1);
   ctx->state = kRendered;
   if (stats) {
@@ -677,6 +718,86 @@ cs_status cs_render_frame(cs_ctx* ctx, const cs_camera* cam, float* image, cs_fr
     for (int l = 0; l < CS_MAX_LEVELS; ++l) stats->level_hist[l] = (int32_t)h.level_hist[l];
     if (h.overflow) return ctx->fail(CS_ERR_CAPACITY, "frame exceeded a capacity (see stats)");
   }
+  return CS_OK;
+}
+
+cs_status cs_render_frame(cs_ctx* ctx, const cs_camera* cam, float* image, cs_frame_stats* stats) {
+  if (!ctx) return CS_ERR_INVALID;
+  return render_impl(ctx, cam, image, stats, false);
+}
+
+cs_status cs_render_views(cs_ctx* ctx, const cs_camera* cam, float* atlas, int64_t atlas_floats,
+                          int64_t* needed) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (ctx->state < kSkinned) return ctx->fail(CS_ERR_STATE, "cs_render_views before cs_skin_instances");
+  if (!atlas || atlas_floats < 0) return ctx->fail(CS_ERR_INVALID, "bad atlas");
+  if (ctx->capturing) return ctx->fail(CS_ERR_UNSUPPORTED, "views are eager only");
+  hipSetDevice(ctx->device);
+  CamDev cd;
+  CS_TRY(make_camera(ctx, cam, &cd));
+  HIP_TRY(launch_view_layout(ctx->inst, ctx->joints, ctx->tpl_dev, ctx->n_inst, (int)ctx->tpl.size(), cd,
+                             ctx->views, ctx->crop, ctx->hdr, ctx->stream));
+  CS_TRY(read_header(ctx));
+  ctx->view_tiles = ctx->hdr_host->pad[0];
+  ctx->atlas_floats = (int64_t)ctx->hdr_host->pad[1] | ((int64_t)ctx->hdr_host->pad[2] << 32);
+  if (needed) *needed = ctx->atlas_floats;
+  if (ctx->atlas_floats > atlas_floats) return ctx->fail(CS_ERR_CAPACITY, "atlas too small (see needed)");
+  if (ctx->view_tiles >= (1ll << 24)) return ctx->fail(CS_ERR_CAPACITY, "more than 2^24 view tiles");
+  CS_TRY(ensure_tiles(ctx, std::max<int64_t>(ctx->view_tiles, 1)));
+  ctx->views_valid = true;
+  return render_impl(ctx, cam, atlas, nullptr, true);
+}
+
+cs_status cs_view_psnr(cs_ctx* ctx, const float* atlas_ref, const float* atlas, float* psnr) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (!ctx->views_valid) return ctx->fail(CS_ERR_STATE, "cs_view_psnr before cs_render_views");
+  if (!atlas_ref || !atlas || !psnr) return ctx->fail(CS_ERR_INVALID, "NULL argument");
+  hipSetDevice(ctx->device);
+  HIP_TRY(launch_view_psnr(ctx->views, ctx->n_inst, atlas_ref, atlas, psnr, ctx->stream));
+  return CS_OK;
+}
+
+cs_status cs_lod_features(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, const float* pose,
+                          const cs_camera* cam, const cs_mlp* net, float* feat) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (ctx->state < kTemplates) return ctx->fail(CS_ERR_STATE, "features before cs_upload_templates");
+  if (n_inst <= 0 || !inst || !pose || !net || !feat) return ctx->fail(CS_ERR_INVALID, "bad arguments");
+  if (ctx->capturing) return ctx->fail(CS_ERR_STATE, "features during capture");
+  hipSetDevice(ctx->device);
+  CamDev cd;
+  CS_TRY(make_camera(ctx, cam, &cd));
+  CS_TRY(ensure_instances(ctx, n_inst));
+  HIP_TRY(launch_fk(inst, pose, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), ctx->bones, ctx->joints, ctx->hdr,
+                    ctx->stream));
+  HIP_TRY(launch_features(inst, pose, ctx->joints, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), cd, net, feat,
+                          ctx->stream));
+  return CS_OK;
+}
+
+cs_status cs_mlp_predict(cs_ctx* ctx, const cs_mlp* net, const float* feat, int32_t n, float* pred) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (!net || !feat || !pred || n < 0) return ctx->fail(CS_ERR_INVALID, "bad arguments");
+  hipSetDevice(ctx->device);
+  HIP_TRY(launch_mlp_infer(net, feat, n, pred, 0, nullptr, nullptr, 0, 0.f, nullptr, nullptr, ctx->stream));
+  return CS_OK;
+}
+
+cs_status cs_mlp_sync(cs_ctx* ctx, cs_mlp* net) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (!net) return ctx->fail(CS_ERR_INVALID, "NULL network");
+  hipSetDevice(ctx->device);
+  HIP_TRY(launch_mlp_sync(net, ctx->stream));
+  return CS_OK;
+}
+
+cs_status cs_mlp_train_step(cs_ctx* ctx, cs_mlp* net, float* adam_m, float* adam_v, const float* feat,
+                            const float* target, int32_t batch, int32_t step, float lr, float* loss) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (!net || !adam_m || !adam_v || !feat || !target) return ctx->fail(CS_ERR_INVALID, "NULL argument");
+  if (batch < 16 || batch > 1024 || batch % 16) return ctx->fail(CS_ERR_INVALID, "batch must be 16..1024, /16");
+  if (step < 1 || !(lr > 0.f)) return ctx->fail(CS_ERR_INVALID, "step >= 1 and lr > 0");
+  hipSetDevice(ctx->device);
+  HIP_TRY(launch_mlp_train(net, adam_m, adam_v, feat, target, batch, step, lr, loss, ctx->stream));
   return CS_OK;
 }
 
@@ -776,6 +897,10 @@ cs_status cs_debug_copy(cs_ctx* ctx, int32_t which, void* host_dst, int64_t offs
     case CS_BUF_SKEYS: src = ctx->keys[ctx->sorted]; size = ctx->cap_pairs * 8; break;
     case CS_BUF_SVALS: src = ctx->vals[ctx->sorted]; size = ctx->cap_pairs * 4; break;
     case CS_BUF_RANGES: src = ctx->ranges; size = ctx->cap_tiles * 8; break;
+    case CS_BUF_FEATURES: src = ctx->feat; size = ctx->cap_inst * 32 * 4; break;
+    case CS_BUF_PRED: src = ctx->pred; size = ctx->cap_inst * 16 * 4; break;
+    case CS_BUF_VIEWS: src = ctx->views; size = ctx->cap_inst * 6 * 8; break;
+    case CS_BUF_JOINTS: src = ctx->joints; size = ctx->cap_inst * kJoints * 3 * 4; break;
     default: return ctx->fail(CS_ERR_INVALID, "unknown buffer");
   }
   if (!src || offset + bytes > size) return ctx->fail(CS_ERR_INVALID, "copy out of range");

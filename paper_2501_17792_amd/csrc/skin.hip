@@ -238,7 +238,7 @@ struct Thresholds {
 
 __global__ void lod_fixed_kernel(const cs_instance* __restrict__ inst,
                                  const TemplateDev* __restrict__ tpl, int n_inst, int n_tpl,
-                                 CamDev cam, Thresholds thr, int n_thr, int full,
+                                 CamDev cam, Thresholds thr, int n_thr, int full, int const_level,
                                  int32_t* __restrict__ level, uint32_t* __restrict__ count) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_inst) return;
@@ -251,7 +251,9 @@ __global__ void lod_fixed_kernel(const cs_instance* __restrict__ inst,
   }
   const TemplateDev& T = tpl[tid];
   int lvl = 0;
-  if (!full) {
+  if (const_level >= 0) {
+    lvl = min(const_level, T.n_levels - 1);
+  } else if (!full) {
     const float dx = in.px - cam.eye[0], dy = -cam.eye[1], dz = in.pz - cam.eye[2];
     const float dist = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
     for (int k = 0; k < n_thr; ++k) lvl += dist >= thr.t[k] ? 1 : 0;
@@ -262,12 +264,12 @@ __global__ void lod_fixed_kernel(const cs_instance* __restrict__ inst,
 }
 
 hipError_t launch_lod_fixed(const cs_instance* inst, const TemplateDev* tpl, int n_inst, int n_tpl,
-                            CamDev cam, const float* thr, int n_thr, int full, int32_t* level,
-                            uint32_t* count, hipStream_t st) {
+                            CamDev cam, const float* thr, int n_thr, int full, int const_level,
+                            int32_t* level, uint32_t* count, hipStream_t st) {
   Thresholds t{};
   for (int k = 0; k < n_thr && k < 8; ++k) t.t[k] = thr[k];
   lod_fixed_kernel<<<(n_inst + 255) / 256, 256, 0, st>>>(inst, tpl, n_inst, n_tpl, cam, t, n_thr,
-                                                         full, level, count);
+                                                         full, const_level, level, count);
   return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(
     const uint32_t* __restrict__ count, const uint32_t* __restrict__ pair_off,
     const uint32_t* __restrict__ rect, const float4* __restrict__ rec, int tiles_x,
     uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, uint32_t* __restrict__ hist,
-    int passes, const FrameHdr* hdr, uint32_t max_pairs) {
+    int passes, const FrameHdr* hdr, uint32_t max_pairs, ViewDev view, int view_mode) {
   __shared__ uint32_t s_hist[kMaxPasses * kSortBins];
   for (int i = threadIdx.x; i < passes * kSortBins; i += kEmitThreads) s_hist[i] = 0;
   __syncthreads();
@@ -33,6 +33,21 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(
       const uint32_t x0 = r & 0xffu, y0 = (r >> 8) & 0xffu, x1 = (r >> 16) & 0xffu, y1 = r >> 24;
       const uint32_t depth = __float_as_uint(rec[3 * s + 2].w);
       uint32_t o = pair_off[s];
+      // tile id = row-major screen tile, or in view mode the view's own tile
+      uint32_t tbase = 0, tstride = (uint32_t)tiles_x, tx0 = 0, ty0 = 0;
+      if (view_mode) {
+        uint32_t lo = 0, hi = (uint32_t)view.n_inst;  // instance: offset[i] <= s < offset[i+1]
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (view.offset[mid] <= s) lo = mid;
+          else hi = mid;
+        }
+        const int4 cw = view.crop[lo];
+        tbase = (uint32_t)view.views[(size_t)lo * 6 + 4];
+        tstride = (uint32_t)(cw.z - cw.x);
+        tx0 = (uint32_t)cw.x;
+        ty0 = (uint32_t)cw.y;
+      }
       // the depth digits (bits below 31) of passes entirely inside the depth
       // field are the same for all of this splat's pairs
       for (int p = 0; p < passes; ++p) {
@@ -40,7 +55,7 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(
       }
       for (uint32_t ty = y0; ty <= y1; ++ty) {
         for (uint32_t tx = x0; tx <= x1; ++tx) {
-          const uint64_t key = ((uint64_t)(ty * (uint32_t)tiles_x + tx) << 31) | depth;
+          const uint64_t key = ((uint64_t)(tbase + (ty - ty0) * tstride + (tx - tx0)) << 31) | depth;
           keys[o] = key;
           vals[o] = s;
           ++o;
@@ -62,9 +77,11 @@ __global__ __launch_bounds__(kEmitThreads) void emit_kernel(
 hipError_t launch_emit(const uint32_t* count, const uint32_t* pair_off, const uint32_t* rect,
                        const float4* rec, CamDev cam, uint64_t* keys, uint32_t* vals,
                        uint32_t* hist, int passes, FrameHdr* hdr, uint32_t max_pairs, int grid,
-                       hipStream_t st) {
+                       const ViewDev* view, hipStream_t st) {
+  ViewDev v{};
+  if (view) v = *view;
   emit_kernel<<<grid, kEmitThreads, 0, st>>>(count, pair_off, rect, rec, cam.tiles_x, keys, vals,
-                                             hist, passes, hdr, max_pairs);
+                                             hist, passes, hdr, max_pairs, v, view ? 1 : 0);
   return hipGetLastError();
 }
 

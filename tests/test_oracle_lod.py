@@ -1,0 +1,120 @@
+"""Pins of the learned-LoD oracle: bfloat16 rounding against torch, the MLP
+gradient against central finite differences, Adam's closed-form first step,
+the selection rule, the view box and features in closed-form set-ups."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import lod
+from paper_2501_17792_amd import synth
+
+
+def test_bf16_rounding_matches_torch():
+    import torch
+
+    rng = np.random.default_rng(0)
+    x = np.concatenate([rng.normal(0, 3, 5000), rng.normal(0, 1e-3, 1000),
+                        [0.0, -0.0, 1.0, 1.00390625, 1.005859375, 65504.0, -3.0e-5]])
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(lod.bf16(x), ref)
+
+
+def _params(rng):
+    return dict(W1=rng.normal(0, 0.3, (32, 64)), b1=rng.normal(0, 0.1, 64),
+                W2=rng.normal(0, 0.2, (64, 64)), b2=rng.normal(0, 0.1, 64),
+                W3=rng.normal(0, 0.2, (64, 5)), b3=rng.normal(0, 0.1, 5),
+                mu=rng.normal(0, 1, 32), sd=rng.uniform(0.5, 2.0, 32))
+
+
+def test_mlp_gradient_matches_central_differences():
+    rng = np.random.default_rng(1)
+    p = _params(rng)
+    x = rng.normal(0, 1, (16, 32))
+    t = rng.normal(40, 5, (16, 5))
+    loss, g = lod.mlp_loss_grad(p, x, t, rounded=False)
+    h = 1e-6
+    for name in ["W1", "b1", "W2", "b2", "W3", "b3"]:
+        flat = p[name].reshape(-1)
+        for idx in rng.choice(flat.size, size=min(12, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = lod.mlp_loss_grad(p, x, t, rounded=False)
+            flat[idx] = old - h
+            lm, _ = lod.mlp_loss_grad(p, x, t, rounded=False)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[name].reshape(-1)[idx]) <= 1e-6 * max(1.0, abs(fd)), (name, idx)
+
+
+def test_mlp_forward_is_the_layered_definition():
+    rng = np.random.default_rng(2)
+    p = _params(rng)
+    x = rng.normal(0, 1, (4, 32))
+    y, _ = lod.mlp_forward(p, x, rounded=False)
+    z = (x - p["mu"]) / p["sd"]
+    ref = np.zeros((4, 5))
+    for b in range(4):  # plain loops over the units
+        h1 = [max(0.0, sum(z[b, i] * p["W1"][i, j] for i in range(32)) + p["b1"][j]) for j in range(64)]
+        h2 = [max(0.0, sum(h1[i] * p["W2"][i, j] for i in range(64)) + p["b2"][j]) for j in range(64)]
+        ref[b] = [sum(h2[i] * p["W3"][i, k] for i in range(64)) + p["b3"][k] for k in range(5)]
+    np.testing.assert_allclose(y, ref, rtol=1e-12, atol=1e-12)
+
+
+def test_adam_first_step_closed_form():
+    g = np.array([0.5, -2.0, 1e-9, 0.0])
+    w = np.ones(4)
+    w1, m, v = lod.adam_step(w, g, np.zeros(4), np.zeros(4), 1, lr=1e-3)
+    np.testing.assert_allclose(w1, 1 - 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+    np.testing.assert_allclose(m, 0.1 * g)
+    np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_select_levels():
+    pred = np.array([[60, 45, 41.5, 39, 30], [60, 40.9, 30, 20, 10], [60, 20, 20, 20, 42],
+                     [10, 10, 10, 10, 10]])
+    np.testing.assert_array_equal(lod.select_levels(pred, 40, 1), [2, 0, 4, 0])
+
+
+def test_view_box_single_joint_closed_form():
+    cam = synth.Camera(width=100, height=80, fx=50.0, fy=50.0, cx=50.0, cy=40.0,
+                       eye=np.zeros(3, np.float32), R=np.eye(3, dtype=np.float32))
+    box, clip = lod.view_box(np.array([[0.2, -0.1, 2.0]]), 0.4, cam)
+    u, v, r = 50 * 0.1 + 50, 50 * -0.05 + 40, 50 * 0.4 / 2
+    np.testing.assert_allclose(box, [u - r, v - r, u + r, v + r])
+    np.testing.assert_allclose(clip, [u - r, v - r, u + r, v + r])
+    box, clip = lod.view_box(np.array([[0.0, 0.0, -1.0]]), 0.4, cam)
+    assert box is None
+    assert lod.crop_window(np.array([3.5, 0.0, 17.2, 9.0]), 8, 8, 100, 80) == (0, 0, 24, 16)
+    assert lod.crop_window(np.array([95.0, 70.0, 100.0, 80.0]), 16, 16, 100, 80) == (80, 64, 100, 80)
+
+
+def test_features_closed_forms():
+    t = synth.make_template(0, 512, 0)
+    cam = synth.look_at((0.0, 1.7, -3.0), (0.0, 1.0, 10.0), 320, 180)
+    pose = np.zeros((24, 3))
+    basis = np.eye(72)[:8]
+    # facing the camera: +z after R_y(pi) points to -z, towards the eye
+    f = lod.instance_features(t, 3, 14, pose, math.pi, 0.0, 7.0, 0.3, cam, np.zeros(72), basis)
+    np.testing.assert_allclose(f[0], math.sqrt(10 ** 2 + 1.7 ** 2))
+    np.testing.assert_allclose(f[24], math.log(f[0]))
+    np.testing.assert_allclose([f[28], f[29]], [1.0, 0.0], atol=1e-12)
+    assert f[13] == 1.0 and f[10:24].sum() == 1.0
+    assert 0 < f[1] < 1 and f[30] == 1.0 and f[31] == 0.0
+    np.testing.assert_allclose(f[25], math.log(f[1] + 1e-6))
+    # facing away, offset to the side: relative yaw turns
+    f2 = lod.instance_features(t, 3, 14, pose, 0.0, 3.0, 7.0, 0.3, cam, np.zeros(72), basis)
+    to_cam = np.array([-3.0, -10.0]) / math.hypot(3, 10)
+    np.testing.assert_allclose([f2[28], f2[29]], [to_cam[1], to_cam[0]], atol=1e-12)
+    # PCA coordinates are the projection on the basis
+    pose3 = np.random.default_rng(3).normal(0, 0.3, (24, 3))
+    f3 = lod.instance_features(t, 0, 14, pose3, 0.0, 0.0, 7.0, 0.3, cam, np.zeros(72), basis)
+    np.testing.assert_allclose(f3[2:10], pose3.reshape(-1)[:8])
+
+
+def test_psnr_labels_known_mse():
+    a = np.zeros((3, 4, 4))
+    b = a.copy()
+    b[:, 1:3, 1:3] = 0.1  # MSE over the 4x4 window = 0.01 * 4/16
+    lab = lod.psnr_labels([a, b, a], (0, 0, 4, 4))
+    np.testing.assert_allclose(lab, [60.0, -10 * math.log10(0.0025), 60.0])
