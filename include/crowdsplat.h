@@ -238,6 +238,24 @@ typedef struct cs_template_grads {
  */
 cs_status cs_render_backward(cs_ctx* ctx, const float* dL_dimage, cs_template_grads* g);
 
+/* Replace the attributes of uploaded template tid in place (same n_gauss and
+ * sh_degree; level counts, joints and parents are kept). The arrays are
+ * DEVICE memory. If opacity_is_logit, desc->opacity holds logits and the
+ * library applies the sigmoid. Used by the template fit between steps. */
+cs_status cs_update_template(cs_ctx* ctx, int32_t tid, const cs_template_desc* desc, int32_t opacity_is_logit);
+
+/* Fit loss of a render against a target, both DEVICE [3][H][W]:
+ * L = mean|x - y| + lambda (1 - SSIM(x, y)), SSIM with an 11x11 Gaussian window
+ * (sigma 1.5), C1 = 0.01^2, C2 = 0.03^2, zero padding, per channel, averaged.
+ * loss DEVICE float (or NULL), dL_dx DEVICE [3][H][W] (or NULL). */
+cs_status cs_fit_loss(cs_ctx* ctx, const float* x, const float* y, int32_t width, int32_t height, float lambda,
+                      float* loss, float* dL_dx);
+
+/* Adam with bias correction (beta 0.9 / 0.999, eps 1e-8) on n DEVICE floats;
+ * step >= 1. */
+cs_status cs_adam(cs_ctx* ctx, float* param, const float* grad, float* m, float* v, int64_t n, int32_t step,
+                  float lr);
+
 /* ---- batching: whole-frame graph capture ---------------------------------
  * Capture select_lod -> skin -> render for fixed pointers and sizes into a
  * hipGraph on the context's stream, with the capacities currently reserved

@@ -37,7 +37,8 @@ EXPORTS = ["cs_create", "cs_destroy", "cs_last_error", "cs_version", "cs_upload_
            "cs_select_lod", "cs_skin_instances", "cs_render_frame", "cs_render_backward",
            "cs_reserve", "cs_frame_capture", "cs_frame_launch", "cs_frame_poll", "cs_debug_copy",
            "cs_sort_pairs", "cs_stage_times", "cs_lod_features", "cs_mlp_predict", "cs_mlp_sync",
-           "cs_mlp_train_step", "cs_render_views", "cs_view_psnr"]
+           "cs_mlp_train_step", "cs_render_views", "cs_view_psnr", "cs_update_template", "cs_fit_loss",
+           "cs_adam"]
 STAGES = ["lod", "fk", "skin", "project", "scan", "emit", "sort", "ranges", "blend"]
 
 
@@ -137,6 +138,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cs_mlp_train_step": (i32, [P, P, P, P, P, P, i32, i32, ctypes.c_float, P]),
         "cs_render_views": (i32, [P, ctypes.POINTER(CsCamera), P, i64, ctypes.POINTER(i64)]),
         "cs_view_psnr": (i32, [P, P, P, P]),
+        "cs_update_template": (i32, [P, i32, ctypes.POINTER(CsTemplateDesc), i32]),
+        "cs_fit_loss": (i32, [P, P, P, i32, i32, ctypes.c_float, P, P]),
+        "cs_adam": (i32, [P, P, P, P, P, i64, i32, ctypes.c_float]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -360,6 +364,43 @@ class Renderer:
         out = self.torch.empty(self.n_inst, dtype=self.torch.float32, device=self.device)
         self._check(self.lib.cs_view_psnr(self.ctx, atlas_ref.data_ptr(), atlas.data_ptr(), out.data_ptr()))
         return out
+
+    # ------------------------------------------------------------ backward / fit
+    def render_backward(self, dimg, tid: int = 0):
+        """Template gradients of sum(dimg * last image): dict of device tensors."""
+        torch = self.torch
+        t = self.templates[tid]
+        K = (t.sh_degree + 1) ** 2
+        out = dict(mean=torch.empty((t.n, 3), device=self.device), log_scale=torch.empty((t.n, 3), device=self.device),
+                   quat=torch.empty((t.n, 4), device=self.device), opacity_logit=torch.empty(t.n, device=self.device),
+                   sh=torch.empty((t.n, K, 3), device=self.device))
+        g = CsTemplateGrads()
+        g.template_id = tid
+        for k, v in out.items():
+            setattr(g, k, v.data_ptr())
+        self._check(self.lib.cs_render_backward(self.ctx, dimg.contiguous().data_ptr(), ctypes.byref(g)))
+        return out
+
+    def update_template(self, tid, mean, log_scale, quat, opacity, sh, skin_idx, skin_w, opacity_is_logit=True):
+        d = CsTemplateDesc()
+        t = self.templates[tid]
+        d.n_gauss, d.sh_degree, d.n_levels = t.n, t.sh_degree, len(t.level_count)
+        for k, v in dict(mean=mean, log_scale=log_scale, quat=quat, opacity=opacity, sh=sh, skin_idx=skin_idx,
+                         skin_w=skin_w).items():
+            setattr(d, k, v.contiguous().data_ptr())
+        self._check(self.lib.cs_update_template(self.ctx, tid, ctypes.byref(d), int(opacity_is_logit)))
+
+    def fit_loss(self, x, y, lam=0.2, want_grad=True):
+        torch = self.torch
+        loss = torch.empty(1, device=self.device)
+        dx = torch.empty_like(x) if want_grad else None
+        self._check(self.lib.cs_fit_loss(self.ctx, x.data_ptr(), y.data_ptr(), x.shape[2], x.shape[1], lam,
+                                          loss.data_ptr(), dx.data_ptr() if dx is not None else None))
+        return loss, dx
+
+    def adam(self, p, g, m, v, step, lr):
+        self._check(self.lib.cs_adam(self.ctx, p.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), p.numel(),
+                                     step, lr))
 
     def sort_pairs(self, keys, vals, key_bits: int):
         self._check(self.lib.cs_sort_pairs(self.ctx, keys.data_ptr(), vals.data_ptr(),

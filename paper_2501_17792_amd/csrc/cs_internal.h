@@ -153,6 +153,19 @@ hipError_t launch_mlp_train(cs_mlp* net, float* m, float* v, const float* feat, 
                             int step, float lr, float* loss, hipStream_t st);
 hipError_t launch_view_layout(const cs_instance* inst, const float* joints, const TemplateDev* tpl, int n_inst,
                               int n_tpl, CamDev cam, int64_t* views, int4* crop, FrameHdr* hdr, hipStream_t st);
+hipError_t launch_blend_backward(const uint32_t* ranges, const uint32_t* svals, const uint64_t* skeys,
+                                 const float4* rec, const uint32_t* rect, const uint32_t* pair_off, CamDev cam,
+                                 const float* dimg, float* gpair, const FrameHdr* hdr, hipStream_t st);
+hipError_t launch_splat_backward(WorkDev w, const float* raw_log_scale, const float* raw_quat, int tid, CamDev cam,
+                                 const float4* rec, const uint32_t* count, const uint32_t* pair_off,
+                                 const float* gpair, float* gsplat, uint32_t stride, int grid, hipStream_t st);
+hipError_t launch_template_reduce(const cs_instance* inst, const uint32_t* offset, int n_inst, int tid, int n,
+                                  int n_coef3, const float* gsplat, uint32_t stride, float* gmean, float* gls,
+                                  float* gq, float* glogit, float* gsh, hipStream_t st);
+hipError_t launch_fit_loss(const float* x, const float* y, int H, int W, float lam, float* loss, float* dx,
+                           float* work, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, int step, float lr, hipStream_t st);
+hipError_t launch_sigmoid(const float* logit, float* o, int n, hipStream_t st);
 hipError_t launch_view_psnr(const int64_t* views, int n_inst, const float* ref, const float* img, float* psnr,
                             hipStream_t st);
 

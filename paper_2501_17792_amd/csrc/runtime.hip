@@ -67,6 +67,13 @@ struct cs_ctx {
   int4* crop = nullptr;       // [cap_inst] view tile windows
   int64_t view_tiles = 0, atlas_floats = 0;
   bool views_valid = false;
+  bool last_was_views = false;
+  float* gpair = nullptr;     // [cap][9] per-pair gradients (backward)
+  int64_t cap_gpair = 0;
+  float* gsplat = nullptr;    // [59][cap] per-splat template gradients
+  int64_t cap_gsplat = 0;
+  float* loss_work = nullptr; // SSIM maps
+  int64_t cap_loss = 0;
 
   // per splat
   int64_t cap_splats = 0;
@@ -369,6 +376,9 @@ void cs_destroy(cs_ctx* ctx) {
   dfree(&ctx->joints);
   dfree(&ctx->feat);
   dfree(&ctx->pred);
+  dfree(&ctx->gpair);
+  dfree(&ctx->gsplat);
+  dfree(&ctx->loss_work);
   dfree(&ctx->views);
   dfree(&ctx->crop);
   dfree(&ctx->skin_mu);
@@ -723,6 +733,7 @@ static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs
 
 cs_status cs_render_frame(cs_ctx* ctx, const cs_camera* cam, float* image, cs_frame_stats* stats) {
   if (!ctx) return CS_ERR_INVALID;
+  ctx->last_was_views = false;
   return render_impl(ctx, cam, image, stats, false);
 }
 
@@ -745,6 +756,7 @@ cs_status cs_render_views(cs_ctx* ctx, const cs_camera* cam, float* atlas, int64
   if (ctx->view_tiles >= (1ll << 24)) return ctx->fail(CS_ERR_CAPACITY, "more than 2^24 view tiles");
   CS_TRY(ensure_tiles(ctx, std::max<int64_t>(ctx->view_tiles, 1)));
   ctx->views_valid = true;
+  ctx->last_was_views = true;
   return render_impl(ctx, cam, atlas, nullptr, true);
 }
 
@@ -803,9 +815,89 @@ cs_status cs_mlp_train_step(cs_ctx* ctx, cs_mlp* net, float* adam_m, float* adam
 
 cs_status cs_render_backward(cs_ctx* ctx, const float* dL_dimage, cs_template_grads* g) {
   if (!ctx) return CS_ERR_INVALID;
-  if (ctx->state < kRendered) return ctx->fail(CS_ERR_STATE, "cs_render_backward before cs_render_frame");
+  if (ctx->state < kRendered || ctx->last_was_views)
+    return ctx->fail(CS_ERR_STATE, "cs_render_backward needs a preceding cs_render_frame");
   if (!dL_dimage || !g) return ctx->fail(CS_ERR_INVALID, "NULL argument");
-  return ctx->fail(CS_ERR_UNSUPPORTED, "backward not built yet");
+  if (g->template_id < 0 || g->template_id >= (int)ctx->tpl.size())
+    return ctx->fail(CS_ERR_INVALID, "template_id out of range");
+  if (ctx->capturing) return ctx->fail(CS_ERR_STATE, "backward during capture");
+  hipSetDevice(ctx->device);
+  CS_TRY(read_header(ctx));
+  const int64_t n_pairs = ctx->hdr_host->n_pairs, n_splats = ctx->hdr_host->n_splats;
+  if (ctx->hdr_host->overflow) return ctx->fail(CS_ERR_CAPACITY, "the forward frame overflowed");
+  if (n_pairs > ctx->cap_gpair) {
+    CS_TRY(dalloc(ctx, &ctx->gpair, (size_t)std::max<int64_t>(n_pairs, 1) * 9));
+    ctx->cap_gpair = n_pairs;
+  }
+  if (n_splats > ctx->cap_gsplat) {
+    CS_TRY(dalloc(ctx, &ctx->gsplat, (size_t)std::max<int64_t>(n_splats, 1) * 59));
+    ctx->cap_gsplat = n_splats;
+  }
+  const CamDev& cd = ctx->cam;
+  const uint32_t cap_p = (uint32_t)std::min<int64_t>(ctx->cap_pairs, kMaxPairsLimit);
+  (void)cap_p;
+  if (n_pairs > 0)
+    HIP_TRY(launch_blend_backward(ctx->ranges, ctx->vals[ctx->sorted], ctx->keys[ctx->sorted], ctx->rec, ctx->rect,
+                                  ctx->pair_off, cd, dL_dimage, ctx->gpair, ctx->hdr, ctx->stream));
+  const TemplateStore& T = ctx->tpl[g->template_id];
+  const int grid = persistent_grid(ctx->hdr_host->n_chunks, 4096);
+  HIP_TRY(launch_splat_backward(work_view(ctx), T.raw_log_scale, T.raw_quat, g->template_id, cd, ctx->rec, ctx->cnt,
+                                ctx->pair_off, ctx->gpair, ctx->gsplat, (uint32_t)std::max<int64_t>(ctx->cap_gsplat, 1),
+                                grid, ctx->stream));
+  HIP_TRY(launch_template_reduce(ctx->inst, ctx->offset, ctx->n_inst, g->template_id, T.n,
+                                 3 * (T.sh_degree + 1) * (T.sh_degree + 1), ctx->gsplat,
+                                 (uint32_t)std::max<int64_t>(ctx->cap_gsplat, 1), g->mean, g->log_scale, g->quat,
+                                 g->opacity_logit, g->sh, ctx->stream));
+  return CS_OK;
+}
+
+cs_status cs_update_template(cs_ctx* ctx, int32_t tid, const cs_template_desc* d, int32_t opacity_is_logit) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (tid < 0 || tid >= (int)ctx->tpl.size()) return ctx->fail(CS_ERR_INVALID, "template id out of range");
+  if (!d || !d->mean || !d->log_scale || !d->quat || !d->opacity || !d->sh || !d->skin_idx || !d->skin_w)
+    return ctx->fail(CS_ERR_INVALID, "NULL array");
+  TemplateStore& st = ctx->tpl[tid];
+  if (d->n_gauss != st.n || d->sh_degree != st.sh_degree)
+    return ctx->fail(CS_ERR_INVALID, "size and SH degree must match the uploaded template");
+  if (ctx->capturing) return ctx->fail(CS_ERR_STATE, "update during capture");
+  hipSetDevice(ctx->device);
+  const int n = st.n;
+  HIP_TRY(hipMemcpyAsync(st.raw_mean, d->mean, 12ull * n, hipMemcpyDeviceToDevice, ctx->stream));
+  HIP_TRY(hipMemcpyAsync(st.raw_log_scale, d->log_scale, 12ull * n, hipMemcpyDeviceToDevice, ctx->stream));
+  HIP_TRY(hipMemcpyAsync(st.raw_quat, d->quat, 16ull * n, hipMemcpyDeviceToDevice, ctx->stream));
+  const float* op = d->opacity;
+  if (opacity_is_logit) {
+    HIP_TRY(launch_sigmoid(d->opacity, st.opacity, n, ctx->stream));
+    op = st.opacity;
+  }
+  HIP_TRY(launch_prepare_template(st.raw_mean, st.raw_log_scale, st.raw_quat, op, d->sh, d->skin_idx, d->skin_w, n,
+                                  st.sh_degree, st.mean_idx, st.skin_w, st.cov_a, st.cov_b, st.opacity, st.sh,
+                                  ctx->stream));
+  if (ctx->state > kTemplates) ctx->state = kTemplates;  // the frame must be redone
+  return CS_OK;
+}
+
+cs_status cs_fit_loss(cs_ctx* ctx, const float* x, const float* y, int32_t width, int32_t height, float lambda,
+                      float* loss, float* dL_dx) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (!x || !y || width <= 0 || height <= 0) return ctx->fail(CS_ERR_INVALID, "bad images");
+  hipSetDevice(ctx->device);
+  const int64_t need = 17ll * 3 * width * height;
+  if (need > ctx->cap_loss) {
+    CS_TRY(dalloc(ctx, &ctx->loss_work, (size_t)need));
+    ctx->cap_loss = need;
+  }
+  HIP_TRY(launch_fit_loss(x, y, height, width, lambda, loss, dL_dx, ctx->loss_work, ctx->stream));
+  return CS_OK;
+}
+
+cs_status cs_adam(cs_ctx* ctx, float* param, const float* grad, float* m, float* v, int64_t n, int32_t step,
+                  float lr) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (!param || !grad || !m || !v || n < 0 || step < 1) return ctx->fail(CS_ERR_INVALID, "bad Adam arguments");
+  hipSetDevice(ctx->device);
+  HIP_TRY(launch_adam(param, grad, m, v, n, step, lr, ctx->stream));
+  return CS_OK;
 }
 
 cs_status cs_frame_capture(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, const float* pose,
