@@ -1,12 +1,17 @@
 """Benchmark of the crowd-splatting hot path on one MI355X.
 
 Workload: 3,500 animated avatars instancing 14 synthetic templates of 100k
-Gaussians (SH degree 3), 1920x1080, fixed 3-level LoD (100/25/6.25 % at
-10 m / 25 m), a 300-frame keyframed animation (poses interpolated at 30 Hz).
+Gaussians (SH degree 3) with 5 importance-ordered levels (100/50/25/12.5/6.25 %),
+1920x1080, a 300-frame keyframed animation (poses interpolated at 30 Hz).
 A step is one whole frame: pose upload (device copy), LoD selection and work
-list, forward kinematics, skinning + projection, tile-count scan, pair
-emission, the onesweep (tile|depth) sort, tile ranges and compositing, all
-replayed as one captured hipGraph.
+list (learned network, or distance thresholds), forward kinematics, skinning +
+projection, tile-count scan, pair emission, the onesweep (tile|depth) sort,
+tile ranges and compositing, all replayed as one captured hipGraph.
+
+The headline value is the learned-LoD frame rate when a trained network is
+present (paper_2501_17792_amd/lod_net.npz, written by train_lod.py), else the
+10 m / 25 m fixed rule; every LoD rule is reported with its frame PSNR against
+the full-detail frame.
 
 Prints one JSON line (rank 0). ``--gpus`` above 1 is refused: this build
 measures one GPU.
@@ -74,10 +79,11 @@ def cpu_baseline(scene, levels, n_splats, n_pairs, budget_s=25.0):
 
     rng = np.random.default_rng(7)
     pick = []
-    for lvl, k in ((0, 1), (1, 3), (2, 12)):
+    present = sorted(set(int(l) for l in levels))
+    for j, lvl in enumerate(present):
+        k = 1 if j == 0 else (12 if j == len(present) - 1 else 3)
         cand = np.nonzero(levels == lvl)[0]
-        if cand.size:
-            pick += list(rng.choice(cand, size=min(k, cand.size), replace=False))
+        pick += list(rng.choice(cand, size=min(k, cand.size), replace=False))
     pick = np.array(sorted(pick))
     sub = synth.Crowd(tid=scene.crowd.tid[pick], yaw=scene.crowd.yaw[pick],
                       pos=scene.crowd.pos[pick], pose=scene.crowd.pose[pick])
@@ -99,6 +105,58 @@ def cpu_baseline(scene, levels, n_splats, n_pairs, budget_s=25.0):
                        f"and {n_pairs} pairs = {frame_s:.0f} s/frame; single-threaded numpy")}
 
 
+def load_net(path):
+    if not os.path.exists(path):
+        return None
+    z = np.load(path, allow_pickle=False)
+    return dict(net=z["net"], margin=float(z["margin"]), thresholds=[float(t) for t in z["thresholds"]],
+                floor=float(z["floor"]))
+
+
+def time_mode(torch, r, scene, poses_all, img, stream, lod, steps, warmup):
+    """Size the frame eagerly, reserve capacity, capture the whole frame as a
+    graph and time ``steps`` replays (pose copy + graph launch per step)."""
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    mode, thr, mlp_ptr, margin = lod
+    max_pairs = max_splats = 0
+    for f in (0, 100, 200, 299):
+        r.pose_dev.copy_(poses_all[f])
+        r.select_lod(scene.camera, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
+        r.skin()
+        r.render(scene.camera, img, stats=True)
+        max_pairs = max(max_pairs, int(r.last_stats.n_pairs))
+        max_splats = max(max_splats, int(r.last_stats.n_splats))
+    r.pose_dev.copy_(poses_all[0])
+    r.select_lod(scene.camera, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
+    r.skin()
+    r.render(scene.camera, img, stats=True)
+    st0 = r.last_stats
+    frame0 = img.clone()
+    r.reserve(0, int(max_splats * 1.05) + 1024, int(max_pairs * 1.3) + 65536)
+    r.capture(scene.camera, img, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
+    for k in range(warmup):
+        r.pose_dev.copy_(poses_all[k % 300])
+        r.launch()
+    stream.synchronize()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    evs[0].record(stream)
+    for k in range(steps):
+        r.pose_dev.copy_(poses_all[(warmup + k) % 300])
+        r.launch()
+        evs[k + 1].record(stream)
+    stream.synchronize()
+    per = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(steps)])
+    total = evs[0].elapsed_time(evs[-1])
+    stf = r.poll()
+    return dict(ms=total / steps, per=per, stats=st0, frame0=frame0, overflow=int(stf.overflow))
+
+
+def psnr(a, b):
+    mse = float(np.mean((a.astype(np.float64) - b.astype(np.float64)) ** 2))
+    return float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +166,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-full", action="store_true", help="skip the full-detail comparison")
     ap.add_argument("--instances", type=int, default=3500)
+    ap.add_argument("--net", default=os.path.join(ROOT, "paper_2501_17792_amd", "lod_net.npz"))
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1",
@@ -120,51 +179,35 @@ def main():
     from paper_2501_17792_amd import synth
 
     t0 = time.perf_counter()
-    frames = max(args.steps + args.warmup, 1)
-    scene = synth.scene_c3(n_frames=300, n_inst=args.instances)
+    templates = [synth.make_template(t, 100_000, 3, synth.C4_LEVELS) for t in range(14)]
+    scene = synth.scene_c3(templates=templates, n_frames=300, n_inst=args.instances)
     log(f"inputs generated in {time.perf_counter() - t0:.1f} s")
-    thr = scene.lod_thresholds
     stream = torch.cuda.Stream()
     dev = torch.device("cuda", 0)
+    netinfo = load_net(args.net)
+    modes = {"fixed_10_25m": (cs.CS_LOD_FIXED, (10.0, 10.0, 25.0, 25.0), 0, 0.0)}
+    results = {}
     with torch.cuda.stream(stream):
         poses_all = torch.from_numpy(scene.frame_poses).to(dev)
         r = cs.Renderer(0, stream=stream, fuse=True)
         r.upload_templates(scene.templates)
         r.set_crowd(scene.crowd)
         img = torch.zeros((3, scene.camera.height, scene.camera.width), device=dev)
-        # an eager frame sizes the work; then reserve headroom and capture the frame
-        max_pairs = 0
-        max_splats = 0
-        for f in (0, 100, 200, 299):
-            r.pose_dev.copy_(poses_all[f])
-            r.frame(scene.camera, cs.CS_LOD_FIXED, thr, image=img, stats=True)
-            max_pairs = max(max_pairs, int(r.last_stats.n_pairs))
-            max_splats = max(max_splats, int(r.last_stats.n_splats))
-        st0 = r.last_stats
-        r.reserve(0, int(max_splats * 1.05) + 1024, int(max_pairs * 1.3) + 65536)
-        r.capture(scene.camera, img, cs.CS_LOD_FIXED, thr)
-        for k in range(args.warmup):
-            r.pose_dev.copy_(poses_all[k % 300])
-            r.launch()
-        stream.synchronize()
-        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-        torch.cuda.synchronize()
-        evs[0].record(stream)
-        for k in range(args.steps):
-            r.pose_dev.copy_(poses_all[(args.warmup + k) % 300])
-            r.launch()
-            evs[k + 1].record(stream)
-        stream.synchronize()
-        torch.cuda.synchronize()
-        per = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)])
-        total_ms = evs[0].elapsed_time(evs[-1])
-        stf = r.poll()
-        if stf.overflow:
-            log("WARNING: a captured frame overflowed its capacity")
-    ms = total_ms / args.steps
+        if netinfo is not None:
+            net_dev = torch.from_numpy(netinfo["net"]).to(dev)
+            modes["learned"] = (cs.CS_LOD_LEARNED, (), net_dev.data_ptr(), netinfo["margin"])
+            modes["fixed_tuned"] = (cs.CS_LOD_FIXED, tuple(netinfo["thresholds"]), 0, 0.0)
+        for name, lod in modes.items():
+            results[name] = time_mode(torch, r, scene, poses_all, img, stream, lod, args.steps, args.warmup)
+            log(f"{name}: {1000.0 / results[name]['ms']:.1f} FPS, {results[name]['stats'].n_splats} splats, "
+                f"{results[name]['stats'].n_pairs} pairs")
+    head = "learned" if "learned" in results else "fixed_10_25m"
+    res = results[head]
+    ms = res["ms"]
     fps = 1000.0 / ms
+    st0 = res["stats"]
     n_splats, n_pairs = int(st0.n_splats), int(st0.n_pairs)
-    levels = np.array([0] * 0)
+    lod_head = modes[head]
 
     # ---- per-stage timing: unfused kernels, eager frames, HIP events on the launch stream
     with torch.cuda.stream(stream):
@@ -175,7 +218,8 @@ def main():
         acc = {}
         for k in range(args.stage_frames + 1):
             rp.pose_dev.copy_(poses_all[k % 300])
-            rp.select_lod(scene.camera, cs.CS_LOD_FIXED, thr, level_out=lvl_out)
+            rp.select_lod(scene.camera, lod_head[0], lod_head[1], level_out=lvl_out, mlp_ptr=lod_head[2],
+                          margin=lod_head[3])
             rp.skin()
             rp.render(scene.camera, img, stats=True)
             t = rp.stage_times()
@@ -185,13 +229,15 @@ def main():
         stream.synchronize()
         levels = lvl_out.cpu().numpy().astype(np.int64)
         stp = rp.last_stats
+        rp.close()
     stage_ms = {k: float(np.mean(v)) for k, v in acc.items()}
     uniq = unique_template_gaussians(scene, levels)
     stats = dict(n_splats=int(stp.n_splats), n_pairs=int(stp.n_pairs))
-    passes = 4 if (scene.camera.width // 16 + 1) * (scene.camera.height // 16 + 1) <= 8192 else 5
+    n_tiles = ((scene.camera.width + 15) // 16) * ((scene.camera.height + 15) // 16)
+    tile_bits = max(1, int(np.ceil(np.log2(n_tiles))))
+    passes = (31 + tile_bits + 10) // 11
     stage_gbs = {}
-    for name, launches in (("skin", 1), ("project", 1), ("scan", 1), ("emit", 1), ("sort", passes),
-                           ("blend", 1)):
+    for name, launches in (("skin", 1), ("project", 1), ("scan", 1), ("emit", 1), ("sort", passes)):
         if name in stage_ms and stage_ms[name] > 0:
             b = algorithmic_bytes(name, stats, scene, passes, uniq) * launches
             stage_gbs[name] = b / (stage_ms[name] * 1e-3) / 1e9
@@ -207,7 +253,7 @@ def main():
                            "emit": "emit_kernel", "scan": "scan kernels"}[dom],
                 "launch_ms": round(per_launch_ms, 4), "bytes_per_launch": int(per_launch_bytes)}
 
-    # ---- full detail (every instance at level 0) for the LoD comparison
+    # ---- full detail (every instance at level 0): FPS and the reference frame for PSNR
     full = None
     if not args.no_full:
         with torch.cuda.stream(stream):
@@ -215,12 +261,7 @@ def main():
             rf.upload_templates(scene.templates)
             rf.set_crowd(scene.crowd)
             img_full = torch.zeros_like(img)
-            img_fixed = torch.zeros_like(img)
             rf.pose_dev.copy_(poses_all[0])
-            r.pose_dev.copy_(poses_all[0])
-            r.launch()
-            stream.synchronize()
-            img_fixed.copy_(img)
             rf.frame(scene.camera, cs.CS_LOD_FULL, (), image=img_full, stats=True)
             nf = 5
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -230,33 +271,37 @@ def main():
             e1.record(stream)
             stream.synchronize()
             full_ms = e0.elapsed_time(e1) / nf
-            a = img_fixed.cpu().numpy().astype(np.float64)
-            b = img_full.cpu().numpy().astype(np.float64)
-            mse = float(np.mean((a - b) ** 2))
-            psnr = 10 * np.log10(1.0 / mse) if mse > 0 else float("inf")
-            full = {"fps_full_eager": round(1000.0 / full_ms, 2), "psnr_fixed_vs_full_db": round(psnr, 2),
-                    "full_n_splats": int(rf.last_stats.n_splats), "full_n_pairs": int(rf.last_stats.n_pairs)}
+            ref = img_full.cpu().numpy()
+            full = {"fps_full_eager": round(1000.0 / full_ms, 2), "full_n_splats": int(rf.last_stats.n_splats),
+                    "full_n_pairs": int(rf.last_stats.n_pairs)}
+            for name, rr in results.items():
+                rr["psnr"] = psnr(rr["frame0"].cpu().numpy(), ref)
             rf.close()
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scene, levels, n_splats, n_pairs)
 
+    lod_cmp = {name: {"fps": round(1000.0 / rr["ms"], 2), "n_splats": int(rr["stats"].n_splats),
+                      "n_pairs": int(rr["stats"].n_pairs), "psnr_vs_full_db": (round(rr["psnr"], 2) if "psnr" in rr else None),
+                      "overflow": rr["overflow"]} for name, rr in results.items()}
     out = {
         "metric": METRIC, "value": round(fps, 2), "unit": "FPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "3,500 animated avatars, 14 templates x 100k Gaussians SH3, 1920x1080, "
-                               "fixed 3-level LoD (100/25/6.25% at 10/25 m), 300-frame keyframed animation, "
+        "config": {"workload": "3,500 animated avatars, 14 templates x 100k Gaussians SH3 with 5 LoD levels "
+                               "(100/50/25/12.5/6.25%), 1920x1080, 300-frame keyframed animation, "
                                "hipGraph-captured frame",
-                   "lod": "fixed", "instances": scene.crowd.n, "width": scene.camera.width,
+                   "lod": head, "instances": scene.crowd.n, "width": scene.camera.width,
                    "height": scene.camera.height, "tile": [16, 16]},
-        "frame_ms_median": round(float(np.median(per)), 4), "frame_ms_p95": round(float(np.percentile(per, 95)), 4),
+        "frame_ms_median": round(float(np.median(res["per"])), 4),
+        "frame_ms_p95": round(float(np.percentile(res["per"], 95)), 4),
         "gaussians_per_s": round(n_splats * fps, 1), "n_splats": n_splats, "n_pairs": n_pairs,
-        "n_visible": int(st0.n_visible), "level_hist": list(st0.level_hist)[:3],
+        "n_visible": int(st0.n_visible), "level_hist": list(st0.level_hist)[:5],
+        "lod_comparison": lod_cmp, "full_detail": full,
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "stage_gbs": {k: round(v, 1) for k, v in stage_gbs.items()},
-        "roofline": roofline, "cpu_baseline": cpu, "full_detail": full,
+        "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
