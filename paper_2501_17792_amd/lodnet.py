@@ -99,6 +99,7 @@ class LabelSet:
 
 
 def view_crowd(seed: int, n: int, n_templates: int = 14, extent: float = 80.0, sigma: float = 0.3):
+    """Instance-views placed, posed and oriented like the crowd's instances."""
     """Training instance-views drawn like the 3,500-avatar crowd."""
     return synth.make_crowd(seed, n, n_templates, extent, sigma)
 

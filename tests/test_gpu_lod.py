@@ -201,3 +201,37 @@ def test_view_psnr_labels_match_oracle():
     assert checked >= 3
     # quality falls with coarser levels (Fig. 4's trend), on average
     assert np.all(np.diff(labels.psnr.mean(0)) <= 0.5)
+
+
+def test_trained_network_beats_fixed_distance_lod():
+    """The trained network draws fewer Gaussians than the best fixed-distance
+    5-level rule while meeting the same per-instance floor (true PSNR >= 40 dB
+    for at least 97 % of held-out instance-views): both rules are tuned on one
+    split and judged on another."""
+    from paper_2501_17792_amd import lodnet, train_lod
+
+    templates, _, cam = _scene(n_inst=4)
+    views = lodnet.view_crowd(410, 6000, n_templates=3, extent=40.0)
+    pca_mean, basis = lodnet.fit_pca(views.pose[:4000])
+    r = _renderer(templates, synth.Crowd(tid=views.tid[:4], yaw=views.yaw[:4], pos=views.pos[:4],
+                                         pose=views.pose[:4]))
+    lab = lodnet.generate_labels(r, templates, cam, views, pca_mean, basis, batch=2000)
+    assert lab.psnr.shape == (6000, 5)
+    net, losses = lodnet.train(r, lab.features[:4000], lab.psnr[:4000], pca_mean, basis, epochs=60, batch=512,
+                               lr=2e-3)
+    assert losses[-1] < 0.2 * losses[0]
+    tune, hold = slice(4000, 5000), slice(5000, 6000)
+    pred_t = lodnet.predict(r, net, lab.features[tune])
+    pred_h = lodnet.predict(r, net, lab.features[hold])
+    margin = train_lod.tune_margin(pred_t, lab.psnr[tune], 40.0, 0.99)
+    th = train_lod.tune_fixed(lab.features[:5000, 0], lab.psnr[:5000], 40.0, 0.99)
+    counts = np.array(templates[0].level_count, np.float64)
+    lv_l = train_lod.select(pred_h, 40.0, margin)
+    lv_f = train_lod.fixed_levels(lab.features[hold, 0], th)
+    ps = lab.psnr[hold]
+    ok_l = (ps[np.arange(1000), lv_l] >= 40).mean()
+    ok_f = (ps[np.arange(1000), lv_f] >= 40).mean()
+    g_l, g_f = counts[lv_l].mean(), counts[lv_f].mean()
+    print(f"learned {g_l:.0f} G/instance ({ok_l:.3f} ok), fixed {g_f:.0f} G/instance ({ok_f:.3f} ok)")
+    assert ok_l >= 0.97 and ok_f >= 0.97
+    assert g_l < g_f
