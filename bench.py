@@ -167,6 +167,7 @@ def main():
     ap.add_argument("--no-full", action="store_true", help="skip the full-detail comparison")
     ap.add_argument("--instances", type=int, default=3500)
     ap.add_argument("--net", default=os.path.join(ROOT, "paper_2501_17792_amd", "lod_net.npz"))
+    ap.add_argument("--tile", default="auto", help="WxH or 'auto' (autotuned per run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1",
@@ -189,19 +190,28 @@ def main():
     results = {}
     with torch.cuda.stream(stream):
         poses_all = torch.from_numpy(scene.frame_poses).to(dev)
-        r = cs.Renderer(0, stream=stream, fuse=True)
-        r.upload_templates(scene.templates)
-        r.set_crowd(scene.crowd)
-        img = torch.zeros((3, scene.camera.height, scene.camera.width), device=dev)
         if netinfo is not None:
             net_dev = torch.from_numpy(netinfo["net"]).to(dev)
             modes["learned"] = (cs.CS_LOD_LEARNED, (), net_dev.data_ptr(), netinfo["margin"])
             modes["fixed_tuned"] = (cs.CS_LOD_FIXED, tuple(netinfo["thresholds"]), 0, 0.0)
+    head = "learned" if "learned" in modes else "fixed_10_25m"
+    tile_timing = None
+    if args.tile == "auto":
+        from paper_2501_17792_amd import autotune
+
+        tile, tile_timing = autotune.tune(torch, scene, poses_all, stream, modes[head], frames=20, log=log)
+    else:
+        tile = tuple(int(x) for x in args.tile.split("x"))
+    log(f"tile {tile}")
+    with torch.cuda.stream(stream):
+        r = cs.Renderer(0, stream=stream, fuse=True, tile=tile)
+        r.upload_templates(scene.templates)
+        r.set_crowd(scene.crowd)
+        img = torch.zeros((3, scene.camera.height, scene.camera.width), device=dev)
         for name, lod in modes.items():
             results[name] = time_mode(torch, r, scene, poses_all, img, stream, lod, args.steps, args.warmup)
             log(f"{name}: {1000.0 / results[name]['ms']:.1f} FPS, {results[name]['stats'].n_splats} splats, "
                 f"{results[name]['stats'].n_pairs} pairs")
-    head = "learned" if "learned" in results else "fixed_10_25m"
     res = results[head]
     ms = res["ms"]
     fps = 1000.0 / ms
@@ -211,7 +221,7 @@ def main():
 
     # ---- per-stage timing: unfused kernels, eager frames, HIP events on the launch stream
     with torch.cuda.stream(stream):
-        rp = cs.Renderer(0, stream=stream, fuse=False, profile=True)
+        rp = cs.Renderer(0, stream=stream, fuse=False, profile=True, tile=tile)
         rp.upload_templates(scene.templates)
         rp.set_crowd(scene.crowd)
         lvl_out = torch.zeros(scene.crowd.n, dtype=torch.int32, device=dev)
@@ -233,7 +243,7 @@ def main():
     stage_ms = {k: float(np.mean(v)) for k, v in acc.items()}
     uniq = unique_template_gaussians(scene, levels)
     stats = dict(n_splats=int(stp.n_splats), n_pairs=int(stp.n_pairs))
-    n_tiles = ((scene.camera.width + 15) // 16) * ((scene.camera.height + 15) // 16)
+    n_tiles = ((scene.camera.width + tile[0] - 1) // tile[0]) * ((scene.camera.height + tile[1] - 1) // tile[1])
     tile_bits = max(1, int(np.ceil(np.log2(n_tiles))))
     passes = (31 + tile_bits + 10) // 11
     stage_gbs = {}
@@ -257,7 +267,7 @@ def main():
     full = None
     if not args.no_full:
         with torch.cuda.stream(stream):
-            rf = cs.Renderer(0, stream=stream, fuse=True)
+            rf = cs.Renderer(0, stream=stream, fuse=True, tile=tile)
             rf.upload_templates(scene.templates)
             rf.set_crowd(scene.crowd)
             img_full = torch.zeros_like(img)
@@ -293,7 +303,8 @@ def main():
                                "(100/50/25/12.5/6.25%), 1920x1080, 300-frame keyframed animation, "
                                "hipGraph-captured frame",
                    "lod": head, "instances": scene.crowd.n, "width": scene.camera.width,
-                   "height": scene.camera.height, "tile": [16, 16]},
+                   "height": scene.camera.height, "tile": list(tile)},
+        "tile_autotune_ms": tile_timing,
         "frame_ms_median": round(float(np.median(res["per"])), 4),
         "frame_ms_p95": round(float(np.percentile(res["per"], 95)), 4),
         "gaussians_per_s": round(n_splats * fps, 1), "n_splats": n_splats, "n_pairs": n_pairs,
