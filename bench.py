@@ -273,6 +273,7 @@ def main():
             img_full = torch.zeros_like(img)
             rf.pose_dev.copy_(poses_all[0])
             rf.frame(scene.camera, cs.CS_LOD_FULL, (), image=img_full, stats=True)
+            stf = rf.last_stats
             nf = 5
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
@@ -282,8 +283,8 @@ def main():
             stream.synchronize()
             full_ms = e0.elapsed_time(e1) / nf
             ref = img_full.cpu().numpy()
-            full = {"fps_full_eager": round(1000.0 / full_ms, 2), "full_n_splats": int(rf.last_stats.n_splats),
-                    "full_n_pairs": int(rf.last_stats.n_pairs)}
+            full = {"fps_full_eager": round(1000.0 / full_ms, 2), "full_n_splats": int(stf.n_splats),
+                    "full_n_pairs": int(stf.n_pairs)}
             for name, rr in results.items():
                 rr["psnr"] = psnr(rr["frame0"].cpu().numpy(), ref)
             rf.close()

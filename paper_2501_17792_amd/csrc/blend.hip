@@ -20,7 +20,10 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
                                                        const FrameHdr* __restrict__ hdr, ViewDev view) {
   constexpr int N = TW * TH;
   constexpr int ROWS = 64 / TW;  // pixel rows per wave
+  constexpr int WAVES = N / 64;
   __shared__ float4 s_r0[N], s_r1[N], s_r2[N];
+  __shared__ uint8_t s_mask[N];             // waves whose pixel centres a splat's box reaches
+  __shared__ uint16_t s_list[WAVES][N];     // per wave: the batch's splats it must evaluate, in order
   const int tile = blockIdx.x;
   int tx, ty;
   float* out = image;
@@ -52,34 +55,50 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
   const int px = tx * TW + lx, py = ty * TH + ly;
   const bool inside = px < cam.W && py < cam.H;
   const float pcx = (float)px + 0.5f, pcy = (float)py + 0.5f;
-  const int wave = threadIdx.x >> 6;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const float wx0 = (float)(tx * TW) + 0.5f, wx1 = (float)(tx * TW + TW - 1) + 0.5f;
-  const float wy0 = (float)(ty * TH + wave * ROWS) + 0.5f, wy1 = wy0 + (float)(ROWS - 1);
+  const float ty0 = (float)(ty * TH) + 0.5f;
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
   const uint32_t n_splats = hdr->n_splats;
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
   bool done = !inside;
   for (uint32_t b = start; b < end; b += N) {
     const uint32_t idx = b + threadIdx.x;
+    uint32_t mask = 0;
     if (idx < end) {
       const uint32_t s = svals[idx];
       if (s < n_splats) {
-        s_r0[threadIdx.x] = rec[3 * (size_t)s];
+        const float4 r0 = rec[3 * (size_t)s], r2 = rec[3 * (size_t)s + 2];
+        s_r0[threadIdx.x] = r0;
         s_r1[threadIdx.x] = rec[3 * (size_t)s + 1];
-        s_r2[threadIdx.x] = rec[3 * (size_t)s + 2];
-      } else {  // never produced by a correct sort; drawn as nothing
-        s_r0[threadIdx.x] = make_float4(-1e30f, -1e30f, 0.f, 0.f);
-        s_r1[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
-        s_r2[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+        s_r2[threadIdx.x] = r2;
+        // the alpha >= 1/255 box against each wave's rows of pixel centres
+        if (!(r0.x + r2.y < wx0 || r0.x - r2.y > wx1)) {
+#pragma unroll
+          for (int w = 0; w < WAVES; ++w) {
+            const float wy0 = ty0 + (float)(w * ROWS), wy1 = wy0 + (float)(ROWS - 1);
+            if (!(r0.y + r2.z < wy0 || r0.y - r2.z > wy1)) mask |= 1u << w;
+          }
+        }
       }
     }
+    s_mask[threadIdx.x] = (uint8_t)mask;
     __syncthreads();
     const int cnt = (int)min((uint32_t)N, end - b);
     if (__ballot(!done) != 0ull) {
-      for (int j = 0; j < cnt; ++j) {
+      // this wave's splats of the batch, compacted in list order
+      int n_w = 0;
+      for (int j0 = 0; j0 < cnt; j0 += 64) {
+        const int j = j0 + lane;
+        const bool hit = j < cnt && ((s_mask[j] >> wave) & 1u);
+        const uint64_t bal = __ballot(hit);
+        if (hit) s_list[wave][n_w + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)j;
+        n_w += __popcll(bal);
+      }
+      for (int k = 0; k < n_w; ++k) {
+        const int j = s_list[wave][k];
         const float4 r0 = s_r0[j];  // u v A B
         const float4 r2 = s_r2[j];  // b rx ry depth
-        if (r0.x + r2.y < wx0 || r0.x - r2.y > wx1 || r0.y + r2.z < wy0 || r0.y - r2.z > wy1) continue;
         if (done) continue;
         const float4 r1 = s_r1[j];  // C o r g
         const float dx = pcx - r0.x, dy = pcy - r0.y;

@@ -169,9 +169,15 @@ hipError_t launch_sigmoid(const float* logit, float* o, int n, hipStream_t st);
 hipError_t launch_view_psnr(const int64_t* views, int n_inst, const float* ref, const float* img, float* psnr,
                             hipStream_t st);
 
-// Onesweep partition geometry.
-constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+// Onesweep partition geometry (items per partition = threads x items).
+#ifndef CS_SORT_THREADS
+#define CS_SORT_THREADS 256
+#endif
+#ifndef CS_SORT_ITEMS
+#define CS_SORT_ITEMS 16
+#endif
+constexpr int kSortThreads = CS_SORT_THREADS;
+constexpr int kSortItems = CS_SORT_ITEMS;
 constexpr int kSortPart = kSortThreads * kSortItems;
 
 }  // namespace cs

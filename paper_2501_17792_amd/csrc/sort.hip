@@ -251,27 +251,48 @@ __global__ __launch_bounds__(kSortThreads, 2) void onesweep_kernel(
       __hip_atomic_store(slot, lb_pack(epoch, part == 0 ? kFlagInc : kFlagAgg, run),
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    // look-back: exclusive prefix of each digit over earlier partitions
-    for (int d = threadIdx.x; d < kSortBins; d += kSortThreads) {
-      uint32_t prefix = 0;
-      if (part > 0) {
-        int j = (int)part - 1;
-        for (;;) {
-          const uint64_t e = __hip_atomic_load(lookback + (size_t)j * kSortBins + d, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
-          if ((uint32_t)(e >> 32) != epoch || (e & (3ull << 30)) == 0) {
-            __builtin_amdgcn_s_sleep(1);
-            continue;
-          }
-          prefix += (uint32_t)(e & 0x3fffffffull);
-          if (e & kFlagInc) break;
-          --j;
-        }
-        __hip_atomic_store(lookback + (size_t)part * kSortBins + d,
-                           lb_pack(epoch, kFlagInc, prefix + s_cnt[d]), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+    // look-back: exclusive prefix of each digit over earlier partitions. A
+    // thread walks back for all of its digits in lock step, so their loads
+    // are in flight together.
+    {
+      constexpr int PER = kSortBins / kSortThreads;
+      uint32_t pre[PER];
+      int jj[PER];
+      uint32_t pending = 0;
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        pre[i] = 0;
+        jj[i] = (int)part - 1;
+        if (part > 0) pending |= 1u << i;
       }
-      s_gbase[d] = goff[d] + prefix;
+      while (pending) {
+        uint64_t e[PER];
+#pragma unroll
+        for (int i = 0; i < PER; ++i)
+          e[i] = (pending >> i) & 1u
+                     ? __hip_atomic_load(lookback + (size_t)jj[i] * kSortBins + threadIdx.x + i * kSortThreads,
+                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                     : 0ull;
+        bool progressed = false;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+          if (!((pending >> i) & 1u)) continue;
+          if ((uint32_t)(e[i] >> 32) != epoch || (e[i] & (3ull << 30)) == 0) continue;
+          pre[i] += (uint32_t)(e[i] & 0x3fffffffull);
+          progressed = true;
+          if (e[i] & kFlagInc) pending &= ~(1u << i);
+          else --jj[i];
+        }
+        if (!progressed) __builtin_amdgcn_s_sleep(1);
+      }
+#pragma unroll
+      for (int i = 0; i < PER; ++i) {
+        const int d = threadIdx.x + i * kSortThreads;
+        if (part > 0)
+          __hip_atomic_store(lookback + (size_t)part * kSortBins + d, lb_pack(epoch, kFlagInc, pre[i] + s_cnt[d]),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_gbase[d] = goff[d] + pre[i];
+      }
     }
     __syncthreads();
     // local exclusive scan of the digit counts -> digit start within the partition
