@@ -75,8 +75,12 @@ typedef struct cs_options {
   int32_t profile_stages;    /* 1: time every stage with HIP events (eager only) */
   int64_t max_splats;        /* fixed splat capacity (0: grow on demand)        */
   int64_t max_pairs;         /* fixed tile-pair capacity (0: grow on demand)    */
-  int32_t reserved[8];
+  int32_t sort_algo;         /* CS_SORT_REDUCE_SCAN (default) | CS_SORT_ONESWEEP */
+  int32_t reserved[7];
 } cs_options;
+
+#define CS_SORT_REDUCE_SCAN 0  /* per-pass digit counts over contiguous ranges, scan, ordered scatter */
+#define CS_SORT_ONESWEEP    1  /* single-kernel passes with decoupled look-back                   */
 
 /* One canonical template (CrowdSplat §2: shared template attributes).
  * Arrays of n_gauss rows; the Gaussians must already be in importance order

@@ -21,6 +21,7 @@ CS_ERR_INVALID, CS_ERR_OOM, CS_ERR_DEVICE, CS_ERR_CAPACITY, CS_ERR_STATE, CS_ERR
 CS_MEM_HOST, CS_MEM_DEVICE = 0, 1
 CS_SKIN_FULL, CS_SKIN_MEANS_ONLY = 0, 1
 CS_LAUNCH_BATCHED, CS_LAUNCH_PER_INSTANCE = 0, 1
+CS_SORT_REDUCE_SCAN, CS_SORT_ONESWEEP = 0, 1
 CS_LOD_FULL, CS_LOD_FIXED, CS_LOD_LEARNED, CS_LOD_CONSTANT = 0, 1, 2, 3
 CS_MLP_NPARAM, CS_MLP_NBF16 = 7312, 7168
 #: offsets of the layers inside cs_mlp.params (out-major weights)
@@ -47,7 +48,7 @@ class CsOptions(ctypes.Structure):
                 ("skin_mode", ctypes.c_int32), ("launch_mode", ctypes.c_int32),
                 ("fuse_skin_project", ctypes.c_int32), ("profile_stages", ctypes.c_int32),
                 ("max_splats", ctypes.c_int64), ("max_pairs", ctypes.c_int64),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("sort_algo", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
 
 
 class CsTemplateDesc(ctypes.Structure):
@@ -189,7 +190,7 @@ class Renderer:
 
     def __init__(self, device: int = 0, stream=None, tile=(16, 16), skin_mode=CS_SKIN_FULL,
                  launch_mode=CS_LAUNCH_BATCHED, fuse=False, max_splats=0, max_pairs=0,
-                 profile=False):
+                 profile=False, sort_algo=CS_SORT_REDUCE_SCAN):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -199,6 +200,7 @@ class Renderer:
         opt.tile_w, opt.tile_h = tile
         opt.skin_mode, opt.launch_mode, opt.fuse_skin_project = skin_mode, launch_mode, int(fuse)
         opt.profile_stages = int(profile)
+        opt.sort_algo = sort_algo
         opt.max_splats, opt.max_pairs = max_splats, max_pairs
         self.tile = tuple(tile)
         ctx = ctypes.c_void_p()

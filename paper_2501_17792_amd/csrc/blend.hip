@@ -22,7 +22,7 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
   constexpr int ROWS = 64 / TW;  // pixel rows per wave
   constexpr int WAVES = N / 64;
   __shared__ float4 s_r0[N], s_r1[N], s_r2[N];
-  __shared__ uint8_t s_mask[N];             // waves whose pixel centres a splat's box reaches
+  __shared__ uint16_t s_mask[N];            // waves whose pixel centres a splat's box reaches
   __shared__ uint16_t s_list[WAVES][N];     // per wave: the batch's splats it must evaluate, in order
   const int tile = blockIdx.x;
   int tx, ty;
@@ -82,7 +82,7 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
         }
       }
     }
-    s_mask[threadIdx.x] = (uint8_t)mask;
+    s_mask[threadIdx.x] = (uint16_t)mask;
     __syncthreads();
     const int cnt = (int)min((uint32_t)N, end - b);
     if (__ballot(!done) != 0ull) {

@@ -136,6 +136,11 @@ hipError_t launch_onesweep(const uint64_t* kin, const uint32_t* vin, uint64_t* k
                            const uint32_t* goff, uint64_t* lookback, FrameHdr* hdr, int pass,
                            int max_parts, uint32_t max_n, const uint32_t* n_override,
                            int grid, hipStream_t st);
+hipError_t launch_rts_pass(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout,
+                           uint32_t* counts, uint32_t* count_sums, const FrameHdr* hdr, uint32_t max_n,
+                           const uint32_t* n_override, int pass, int blocks, hipStream_t st);
+hipError_t launch_scan_inplace(uint32_t* data, uint32_t n, uint32_t* block_sums, hipStream_t st);
+constexpr int kRtsBlocks = 512;  // reduce-then-scan workgroups per pass
 hipError_t launch_hist_keys(const uint64_t* keys, const uint32_t* n_ptr, uint32_t* hist, int passes,
                             int grid, hipStream_t st);
 hipError_t launch_ranges(const uint64_t* skeys, FrameHdr* hdr, uint32_t max_pairs, int n_tiles,

@@ -114,11 +114,16 @@ __device__ __forceinline__ uint32_t block_excl_scan256(uint32_t v, uint32_t* s, 
   return inc - v;
 }
 
+// n is *n_ptr when n_ptr is not null, else n_const.
+__device__ __forceinline__ uint32_t scan_n(const uint32_t* n_ptr, uint32_t n_const) {
+  return n_ptr ? *n_ptr : n_const;
+}
+
 __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_t* __restrict__ cnt,
                                                                    uint32_t* __restrict__ sums,
-                                                                   const FrameHdr* hdr) {
+                                                                   const uint32_t* n_ptr, uint32_t n_const) {
   __shared__ uint32_t s[kScanThreads];
-  const uint32_t n = hdr->n_splats;
+  const uint32_t n = scan_n(n_ptr, n_const);
   const uint32_t base = blockIdx.x * (uint32_t)kScanTile;
   if (base >= n) return;
   uint32_t acc = 0;
@@ -131,10 +136,13 @@ __global__ __launch_bounds__(kScanThreads) void scan_reduce_kernel(const uint32_
   if (threadIdx.x == 0) sums[blockIdx.x] = total;
 }
 
-__global__ __launch_bounds__(1024) void scan_sums_kernel(uint32_t* __restrict__ sums, FrameHdr* hdr,
-                                                         uint32_t max_pairs) {
+// scans the block sums; writes the grand total to *total_out (if given) and
+// flags bit 1 of hdr->overflow when it exceeds max_total
+__global__ __launch_bounds__(1024) void scan_sums_kernel(uint32_t* __restrict__ sums, const uint32_t* n_ptr,
+                                                         uint32_t n_const, uint32_t* total_out, FrameHdr* hdr,
+                                                         uint32_t max_total) {
   __shared__ uint32_t s[1024];
-  const uint32_t n = hdr->n_splats;
+  const uint32_t n = scan_n(n_ptr, n_const);
   const uint32_t nb = (n + kScanTile - 1) / kScanTile;
   uint64_t carry = 0;
   const int t = threadIdx.x;
@@ -155,17 +163,17 @@ __global__ __launch_bounds__(1024) void scan_sums_kernel(uint32_t* __restrict__ 
   }
   if (t == 0) {
     const uint64_t total = carry;
-    hdr->n_pairs = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
-    if (total > (uint64_t)max_pairs) atomicOr(&hdr->overflow, 2u);
+    if (total_out) *total_out = total > 0xffffffffull ? 0xffffffffu : (uint32_t)total;
+    if (hdr && total > (uint64_t)max_total) atomicOr(&hdr->overflow, 2u);
   }
 }
 
-__global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t* __restrict__ cnt,
-                                                                 const uint32_t* __restrict__ sums,
-                                                                 uint32_t* __restrict__ out,
-                                                                 const FrameHdr* hdr) {
+// exclusive scan of cnt into out (out may alias cnt)
+__global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t* cnt, const uint32_t* __restrict__ sums,
+                                                                 uint32_t* out, const uint32_t* n_ptr,
+                                                                 uint32_t n_const) {
   __shared__ uint32_t s[kScanThreads];
-  const uint32_t n = hdr->n_splats;
+  const uint32_t n = scan_n(n_ptr, n_const);
   const uint32_t base = blockIdx.x * (uint32_t)kScanTile;
   if (base >= n) return;
   // thread t owns the contiguous items [t*ITEMS, (t+1)*ITEMS) of the tile
@@ -191,9 +199,19 @@ __global__ __launch_bounds__(kScanThreads) void scan_down_kernel(const uint32_t*
 hipError_t launch_scan_counts(const uint32_t* count, uint32_t* pair_off, uint32_t* block_sums,
                               int max_blocks, FrameHdr* hdr, uint32_t max_pairs, hipStream_t st) {
   if (max_blocks <= 0) return hipSuccess;
-  scan_reduce_kernel<<<max_blocks, kScanThreads, 0, st>>>(count, block_sums, hdr);
-  scan_sums_kernel<<<1, 1024, 0, st>>>(block_sums, hdr, max_pairs);
-  scan_down_kernel<<<max_blocks, kScanThreads, 0, st>>>(count, block_sums, pair_off, hdr);
+  const uint32_t* n_ptr = &hdr->n_splats;
+  scan_reduce_kernel<<<max_blocks, kScanThreads, 0, st>>>(count, block_sums, n_ptr, 0u);
+  scan_sums_kernel<<<1, 1024, 0, st>>>(block_sums, n_ptr, 0u, &hdr->n_pairs, hdr, max_pairs);
+  scan_down_kernel<<<max_blocks, kScanThreads, 0, st>>>(count, block_sums, pair_off, n_ptr, 0u);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_inplace(uint32_t* data, uint32_t n, uint32_t* block_sums, hipStream_t st) {
+  const int blocks = (int)((n + kScanTile - 1) / kScanTile);
+  if (blocks <= 0) return hipSuccess;
+  scan_reduce_kernel<<<blocks, kScanThreads, 0, st>>>(data, block_sums, nullptr, n);
+  scan_sums_kernel<<<1, 1024, 0, st>>>(block_sums, nullptr, n, nullptr, nullptr, 0u);
+  scan_down_kernel<<<blocks, kScanThreads, 0, st>>>(data, block_sums, data, nullptr, n);
   return hipGetLastError();
 }
 

@@ -92,6 +92,8 @@ struct cs_ctx {
   uint32_t* vals[2] = {nullptr, nullptr};
   uint64_t* lookback = nullptr;
   uint32_t* hist = nullptr;  // kMaxPasses * kSortBins
+  uint32_t* rts_counts = nullptr;  // kRtsBlocks * kSortBins digit-major counts
+  uint32_t* rts_sums = nullptr;
   int64_t cap_tiles = 0;
   uint32_t* ranges = nullptr;
 
@@ -322,6 +324,7 @@ cs_status cs_create(int32_t device, void* stream, const cs_options* opt, cs_ctx*
   if (o.skin_mode != CS_SKIN_FULL && o.skin_mode != CS_SKIN_MEANS_ONLY) return CS_ERR_INVALID;
   if (o.launch_mode != CS_LAUNCH_BATCHED && o.launch_mode != CS_LAUNCH_PER_INSTANCE) return CS_ERR_INVALID;
   if (o.max_splats < 0 || o.max_pairs < 0) return CS_ERR_INVALID;
+  if (o.sort_algo != CS_SORT_REDUCE_SCAN && o.sort_algo != CS_SORT_ONESWEEP) return CS_ERR_INVALID;
   int n_dev = 0;
   if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev) {
     (void)hipGetLastError();
@@ -335,6 +338,8 @@ cs_status cs_create(int32_t device, void* stream, const cs_options* opt, cs_ctx*
   cs_status s = dalloc(ctx, &ctx->hdr, 1);
   if (s == CS_OK) s = dalloc(ctx, &ctx->hist, kMaxPasses * kSortBins);
   if (s == CS_OK) s = dalloc(ctx, &ctx->n_dev, 1);
+  if (s == CS_OK) s = dalloc(ctx, &ctx->rts_counts, (size_t)kRtsBlocks * kSortBins);
+  if (s == CS_OK) s = dalloc(ctx, &ctx->rts_sums, (size_t)kRtsBlocks * kSortBins / 4096 + 2);
   if (s == CS_OK && hipHostMalloc((void**)&ctx->hdr_host, sizeof(FrameHdr), hipHostMallocDefault) != hipSuccess)
     s = CS_ERR_OOM;
   if (s == CS_OK && hipMemsetAsync(ctx->hdr, 0, sizeof(FrameHdr), ctx->stream) != hipSuccess) s = CS_ERR_DEVICE;
@@ -395,6 +400,8 @@ void cs_destroy(cs_ctx* ctx) {
   }
   dfree(&ctx->lookback);
   dfree(&ctx->hist);
+  dfree(&ctx->rts_counts);
+  dfree(&ctx->rts_sums);
   dfree(&ctx->ranges);
   delete ctx;
 }
@@ -690,20 +697,27 @@ static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs
   }
   // A6 emission + digit histograms
   const int emit_grid = ctx->capturing ? 1024 : persistent_grid((n_splats + 255) / 256, 1024);
+  const bool onesweep = ctx->opt.sort_algo == CS_SORT_ONESWEEP;
   ctx->mark(CS_STAGE_EMIT, 0);
   HIP_TRY(launch_emit(ctx->cnt, ctx->pair_off, ctx->rect, ctx->rec, cd, ctx->keys[0], ctx->vals[0],
-                      ctx->hist, ctx->passes, ctx->hdr, cap_p, emit_grid, vp, ctx->stream));
-  HIP_TRY(launch_digit_offsets(ctx->hist, ctx->passes, ctx->stream));
+                      ctx->hist, onesweep ? ctx->passes : 0, ctx->hdr, cap_p, emit_grid, vp, ctx->stream));
+  if (onesweep) HIP_TRY(launch_digit_offsets(ctx->hist, ctx->passes, ctx->stream));
   ctx->mark(CS_STAGE_EMIT, 1);
-  // A7 onesweep passes, ping-pong between the two pair buffers
+  // A7 LSD radix passes, ping-pong between the two pair buffers
   const int64_t parts = ctx->capturing ? ctx->cap_parts : (n_pairs + kSortPart - 1) / kSortPart;
   const int sort_grid = persistent_grid(parts, 512);
   int src = 0;
   ctx->mark(CS_STAGE_SORT, 0);
   for (int p = 0; p < ctx->passes; ++p) {
-    HIP_TRY(launch_onesweep(ctx->keys[src], ctx->vals[src], ctx->keys[1 - src], ctx->vals[1 - src],
-                            ctx->hist + p * kSortBins, ctx->lookback, ctx->hdr, p, (int)ctx->cap_parts,
-                            cap_p, nullptr, sort_grid, ctx->stream));
+    if (onesweep) {
+      HIP_TRY(launch_onesweep(ctx->keys[src], ctx->vals[src], ctx->keys[1 - src], ctx->vals[1 - src],
+                              ctx->hist + p * kSortBins, ctx->lookback, ctx->hdr, p, (int)ctx->cap_parts,
+                              cap_p, nullptr, sort_grid, ctx->stream));
+    } else {
+      HIP_TRY(launch_rts_pass(ctx->keys[src], ctx->vals[src], ctx->keys[1 - src], ctx->vals[1 - src],
+                              ctx->rts_counts, ctx->rts_sums, ctx->hdr, cap_p, nullptr, p, kRtsBlocks,
+                              ctx->stream));
+    }
     src = 1 - src;
   }
   ctx->mark(CS_STAGE_SORT, 1);
@@ -1033,16 +1047,24 @@ cs_status cs_sort_pairs(cs_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, 
   HIP_TRY(hipMemcpyAsync(ctx->n_dev, &nn, 4, hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(launch_frame_reset(ctx->hdr, ctx->hist, kMaxPasses * kSortBins, 1, ctx->stream));
   const int64_t parts = (n + kSortPart - 1) / kSortPart;
-  HIP_TRY(launch_hist_keys(keys, ctx->n_dev, ctx->hist, passes, persistent_grid((n + 255) / 256, 1024),
-                           ctx->stream));
-  HIP_TRY(launch_digit_offsets(ctx->hist, passes, ctx->stream));
+  const bool onesweep = ctx->opt.sort_algo == CS_SORT_ONESWEEP;
+  if (onesweep) {
+    HIP_TRY(launch_hist_keys(keys, ctx->n_dev, ctx->hist, passes, persistent_grid((n + 255) / 256, 1024),
+                             ctx->stream));
+    HIP_TRY(launch_digit_offsets(ctx->hist, passes, ctx->stream));
+  }
   uint64_t* ks[2] = {keys, ctx->keys[0]};
   uint32_t* vs[2] = {vals, ctx->vals[0]};
   int src = 0;
   for (int p = 0; p < passes; ++p) {
-    HIP_TRY(launch_onesweep(ks[src], vs[src], ks[1 - src], vs[1 - src], ctx->hist + p * kSortBins,
-                            ctx->lookback, ctx->hdr, p, (int)ctx->cap_parts, (uint32_t)ctx->cap_pairs,
-                            ctx->n_dev, persistent_grid(parts, 512), ctx->stream));
+    if (onesweep) {
+      HIP_TRY(launch_onesweep(ks[src], vs[src], ks[1 - src], vs[1 - src], ctx->hist + p * kSortBins,
+                              ctx->lookback, ctx->hdr, p, (int)ctx->cap_parts, (uint32_t)ctx->cap_pairs,
+                              ctx->n_dev, persistent_grid(parts, 512), ctx->stream));
+    } else {
+      HIP_TRY(launch_rts_pass(ks[src], vs[src], ks[1 - src], vs[1 - src], ctx->rts_counts, ctx->rts_sums,
+                              ctx->hdr, (uint32_t)ctx->cap_pairs, ctx->n_dev, p, kRtsBlocks, ctx->stream));
+    }
     src = 1 - src;
   }
   if (src == 1) {

@@ -360,6 +360,176 @@ hipError_t launch_onesweep(const uint64_t* kin, const uint32_t* vin, uint64_t* k
 }
 
 // ---------------------------------------------------------------------------
+// Reduce-then-scan digit pass (no waiting between workgroups). The item array
+// is cut into B contiguous ranges of whole 4,096-item tiles, one per
+// workgroup. (1) every workgroup counts the digits of its range into
+// counts[digit][B]; (2) one flat exclusive scan of that digit-major table
+// gives each (digit, workgroup) its first output position; (3) every
+// workgroup walks its range tile by tile in order, ranks each tile stably in
+// LDS exactly as the onesweep pass does, writes digit runs coalesced, and
+// advances its per-digit running positions. The sizes are read on the
+// device, so the same launches work inside a captured graph.
+// ---------------------------------------------------------------------------
+constexpr int kRtsThreads = 256;
+constexpr int kRtsItems = 16;
+constexpr int kRtsTile = kRtsThreads * kRtsItems;
+
+__device__ __forceinline__ uint32_t rts_n(const FrameHdr* hdr, uint32_t max_n, const uint32_t* n_override) {
+  return n_override ? *n_override : (hdr->n_pairs <= max_n ? hdr->n_pairs : 0u);
+}
+
+// range of workgroup b: whole tiles, ceil(tiles / B) per workgroup
+__device__ __forceinline__ void rts_range(uint32_t n, int b, int B, uint32_t& lo, uint32_t& hi) {
+  const uint32_t tiles = (n + kRtsTile - 1) / kRtsTile;
+  const uint32_t per = (tiles + B - 1) / B;
+  lo = min((uint32_t)b * per * kRtsTile, n);
+  hi = min(((uint32_t)b + 1u) * per * kRtsTile, n);
+}
+
+__global__ __launch_bounds__(256) void rts_upsweep_kernel(const uint64_t* __restrict__ keys, const FrameHdr* hdr,
+                                                          uint32_t max_n, const uint32_t* __restrict__ n_override,
+                                                          int shift, uint32_t* __restrict__ counts) {
+  __shared__ uint32_t s_h[kSortBins];
+  const int B = gridDim.x, b = blockIdx.x;
+  for (int d = threadIdx.x; d < kSortBins; d += 256) s_h[d] = 0;
+  __syncthreads();
+  uint32_t lo, hi;
+  rts_range(rts_n(hdr, max_n, n_override), b, B, lo, hi);
+  for (uint32_t i = lo + threadIdx.x; i < hi; i += 256)
+    atomicAdd(&s_h[(uint32_t)(keys[i] >> shift) & (kSortBins - 1)], 1u);
+  __syncthreads();
+  for (int d = threadIdx.x; d < kSortBins; d += 256) counts[(size_t)d * B + b] = s_h[d];
+}
+
+__global__ __launch_bounds__(kRtsThreads, 2) void rts_downsweep_kernel(
+    const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin, uint64_t* __restrict__ kout,
+    uint32_t* __restrict__ vout, const uint32_t* __restrict__ offsets, const FrameHdr* hdr, uint32_t max_n,
+    const uint32_t* __restrict__ n_override, int shift) {
+  constexpr int WAVES = kRtsThreads / 64;
+  constexpr int WAVE_ITEMS = 64 * kRtsItems;
+  constexpr int PER = kSortBins / kRtsThreads;
+  __shared__ uint16_t s_whist[WAVES * kSortBins];
+  __shared__ uint32_t s_cnt[kSortBins + 1];   // counts, then local digit starts
+  __shared__ uint32_t s_base[kSortBins];      // next output position of each digit
+  __shared__ uint32_t s_scan[kRtsThreads];
+  __shared__ uint64_t s_keys[kRtsTile];
+  __shared__ uint16_t s_dig[kRtsTile];
+  const int B = gridDim.x, b = blockIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t lt_mask = (1ull << lane) - 1ull;
+  uint32_t lo, hi;
+  rts_range(rts_n(hdr, max_n, n_override), b, B, lo, hi);
+  for (int d = threadIdx.x; d < kSortBins; d += kRtsThreads) s_base[d] = offsets[(size_t)d * B + b];
+  for (uint32_t t0 = lo; t0 < hi; t0 += kRtsTile) {
+    const uint32_t nvalid = min((uint32_t)kRtsTile, hi - t0);
+    for (int i = threadIdx.x; i < WAVES * kSortBins; i += kRtsThreads) s_whist[i] = 0;
+    __syncthreads();
+    uint64_t key[kRtsItems];
+    uint32_t val[kRtsItems];
+    uint16_t rank[kRtsItems];
+    const uint32_t wbase = wave * WAVE_ITEMS;
+#pragma unroll
+    for (int k = 0; k < kRtsItems; ++k) {
+      const uint32_t li = wbase + k * 64 + lane;
+      if (li < nvalid) {
+        key[k] = kin[t0 + li];
+        val[k] = vin[t0 + li];
+      } else {
+        key[k] = ~0ull;
+        val[k] = 0u;
+      }
+    }
+    uint16_t* wh = s_whist + wave * kSortBins;
+#pragma unroll
+    for (int k = 0; k < kRtsItems; ++k) {
+      const uint32_t d = (uint32_t)(key[k] >> shift) & (kSortBins - 1);
+      const uint64_t peers = match_digit(d);
+      const int leader = __ffsll((unsigned long long)peers) - 1;
+      const uint32_t cur = wh[d];
+      rank[k] = (uint16_t)(cur + __popcll(peers & lt_mask));
+      if (lane == leader) wh[d] = (uint16_t)(cur + __popcll(peers));
+    }
+    __syncthreads();
+    for (int d = threadIdx.x; d < kSortBins; d += kRtsThreads) {
+      uint32_t run = 0;
+#pragma unroll
+      for (int w = 0; w < WAVES; ++w) {
+        const uint32_t c = s_whist[w * kSortBins + d];
+        s_whist[w * kSortBins + d] = (uint16_t)run;
+        run += c;
+      }
+      s_cnt[d] = run;
+    }
+    __syncthreads();
+    {  // exclusive scan of the digit counts -> local digit starts
+      uint32_t v[PER];
+      uint32_t acc = 0;
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        v[k] = s_cnt[threadIdx.x * PER + k];
+        acc += v[k];
+      }
+      s_scan[threadIdx.x] = acc;
+      __syncthreads();
+      for (int off = 1; off < kRtsThreads; off <<= 1) {
+        const uint32_t a = threadIdx.x >= off ? s_scan[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s_scan[threadIdx.x] += a;
+        __syncthreads();
+      }
+      uint32_t run = s_scan[threadIdx.x] - acc;
+#pragma unroll
+      for (int k = 0; k < PER; ++k) {
+        s_cnt[threadIdx.x * PER + k] = run;
+        run += v[k];
+      }
+      if (threadIdx.x == kRtsThreads - 1) s_cnt[kSortBins] = run;
+    }
+    __syncthreads();
+    uint16_t lpos[kRtsItems];
+#pragma unroll
+    for (int k = 0; k < kRtsItems; ++k) {
+      const uint32_t d = (uint32_t)(key[k] >> shift) & (kSortBins - 1);
+      lpos[k] = (uint16_t)(s_cnt[d] + s_whist[wave * kSortBins + d] + rank[k]);
+      s_keys[lpos[k]] = key[k];
+      s_dig[lpos[k]] = (uint16_t)d;
+    }
+    __syncthreads();
+    // invalid items carry the largest digit and come last: positions >= nvalid
+    for (int p = threadIdx.x; p < (int)nvalid; p += kRtsThreads) {
+      const uint32_t d = s_dig[p];
+      kout[s_base[d] + (uint32_t)p - s_cnt[d]] = s_keys[p];
+    }
+    __syncthreads();
+    uint32_t* s_vals = reinterpret_cast<uint32_t*>(s_keys);
+#pragma unroll
+    for (int k = 0; k < kRtsItems; ++k) s_vals[lpos[k]] = val[k];
+    __syncthreads();
+    for (int p = threadIdx.x; p < (int)nvalid; p += kRtsThreads) {
+      const uint32_t d = s_dig[p];
+      vout[s_base[d] + (uint32_t)p - s_cnt[d]] = s_vals[p];
+    }
+    __syncthreads();
+    // advance the running positions by this tile's (valid) digit counts
+    for (int d = threadIdx.x; d < kSortBins; d += kRtsThreads) s_base[d] += s_cnt[d + 1] - s_cnt[d];
+    __syncthreads();
+  }
+}
+
+hipError_t launch_scan_inplace(uint32_t* data, uint32_t n, uint32_t* block_sums, hipStream_t st);
+
+hipError_t launch_rts_pass(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout,
+                           uint32_t* counts, uint32_t* count_sums, const FrameHdr* hdr, uint32_t max_n,
+                           const uint32_t* n_override, int pass, int blocks, hipStream_t st) {
+  const int shift = pass * kSortBits;
+  rts_upsweep_kernel<<<blocks, 256, 0, st>>>(kin, hdr, max_n, n_override, shift, counts);
+  hipError_t e = launch_scan_inplace(counts, (uint32_t)blocks * kSortBins, count_sums, st);
+  if (e != hipSuccess) return e;
+  rts_downsweep_kernel<<<blocks, kRtsThreads, 0, st>>>(kin, vin, kout, vout, counts, hdr, max_n, n_override, shift);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Per-tile [start, end) by binary search of the sorted keys.
 // ---------------------------------------------------------------------------
 __global__ void ranges_kernel(const uint64_t* __restrict__ skeys, const FrameHdr* hdr,

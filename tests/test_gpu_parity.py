@@ -170,7 +170,8 @@ def test_tile_shape_launch_and_fusion_invariance():
     sc = _small_c2_scene(n_inst=8)
     _, ref = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds)
     for kw in [dict(tile=(8, 8)), dict(tile=(32, 32)), dict(tile=(8, 32)),
-               dict(launch_mode=cs.CS_LAUNCH_PER_INSTANCE), dict(fuse=True)]:
+               dict(launch_mode=cs.CS_LAUNCH_PER_INSTANCE), dict(fuse=True),
+               dict(sort_algo=cs.CS_SORT_ONESWEEP)]:
         _, img = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, **kw)
         assert np.array_equal(img, ref), kw
 
@@ -203,9 +204,10 @@ def test_determinism_and_graph_replay():
     stream.synchronize()
 
 
+@pytest.mark.parametrize("algo", [0, 1])
 @pytest.mark.parametrize("n,bits", [(1, 44), (1000, 44), (4096, 44), (4097, 46), (123457, 44),
-                                    (2_000_000, 44), (70000, 13)])
-def test_standalone_sort_bit_exact(n, bits):
+                                    (2_000_000, 44), (70000, 13), (8192 * 512 + 77, 44)])
+def test_standalone_sort_bit_exact(n, bits, algo):
     """The onesweep sort against numpy's stable argsort on tile-pair-shaped keys:
     few distinct tiles (heavy duplicates), FP32 depth bits, ragged sizes."""
     import torch
@@ -221,7 +223,7 @@ def test_standalone_sort_bit_exact(n, bits):
     else:
         keys = rng.integers(0, 1 << bits, size=n).astype(np.uint64)
     vals = np.arange(n, dtype=np.uint32)
-    r = cs.Renderer(0)
+    r = cs.Renderer(0, sort_algo=algo)
     kd = torch.from_numpy(keys.view(np.int64).copy()).cuda()
     vd = torch.from_numpy(vals.view(np.int32).copy()).cuda()
     r.sort_pairs(kd, vd, bits)
