@@ -68,7 +68,9 @@ def render_targets(r, cams):
 def fit(truth: synth.Template, start: synth.Template, crowd, cams, steps=2000, lr=1e-3, lam=0.2, seed=503,
         log=None, log_every=100):
     """Fit ``start`` to renders of ``truth`` from ``cams``; returns the fitted
-    tensors and the loss history."""
+    tensors and the loss history. ``lr`` is one rate for every attribute or a
+    dict per attribute (mean, log_scale, quat, opacity_logit, sh)."""
+    lrs = lr if isinstance(lr, dict) else {k: lr for k in PARAMS}
     torch = _torch()
     r = cs.Renderer(0)
     r.upload_templates([truth])
@@ -91,7 +93,7 @@ def fit(truth: synth.Template, start: synth.Template, crowd, cams, steps=2000, l
         img.backward(dimg)
         with torch.no_grad():
             for k in PARAMS:
-                r.adam(params[k], params[k].grad.contiguous(), m[k], v[k], step, lr)
+                r.adam(params[k], params[k].grad.contiguous(), m[k], v[k], step, lrs[k])
         if step % log_every == 0 or step == 1:
             losses.append((step, float(loss.item())))
             if log:
