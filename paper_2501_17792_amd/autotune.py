@@ -43,12 +43,19 @@ def tune(torch, scene, poses_all, stream, lod, frames: int = 20, candidates=CAND
             r.set_crowd(scene.crowd)
             img = torch.zeros((3, scene.camera.height, scene.camera.width), device=poses_all.device)
             r.pose_dev.copy_(poses_all[0])
-            r.select_lod(scene.camera, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
-            r.skin()
-            r.render(scene.camera, img, stats=True)
-            st = r.last_stats
-            r.reserve(0, int(st.n_splats * 1.1) + 1024, int(st.n_pairs * 1.5) + 65536)
-            r.capture(scene.camera, img, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
+            try:
+                r.select_lod(scene.camera, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
+                r.skin()
+                r.render(scene.camera, img, stats=True)
+                st = r.last_stats
+                r.reserve(0, int(st.n_splats * 1.05) + 1024, int(st.n_pairs * 1.2) + 65536)
+                r.capture(scene.camera, img, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
+            except cs.CrowdSplatError as e:  # the shape does not fit (e.g. too many tile pairs)
+                r.close()
+                timing[f"{tile[0]}x{tile[1]}"] = None
+                if log:
+                    log(f"tile {tile}: skipped ({e})")
+                continue
             for k in range(3):
                 r.launch()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
