@@ -204,12 +204,13 @@ def main():
         tile = tuple(int(x) for x in args.tile.split("x"))
     log(f"tile {tile}")
     with torch.cuda.stream(stream):
-        r = cs.Renderer(0, stream=stream, fuse=True, tile=tile)
-        r.upload_templates(scene.templates)
-        r.set_crowd(scene.crowd)
         img = torch.zeros((3, scene.camera.height, scene.camera.width), device=dev)
-        for name, lod in modes.items():
+        for name, lod in modes.items():  # a fresh context per mode: capacities are fixed at capture
+            r = cs.Renderer(0, stream=stream, fuse=True, tile=tile)
+            r.upload_templates(scene.templates)
+            r.set_crowd(scene.crowd)
             results[name] = time_mode(torch, r, scene, poses_all, img, stream, lod, args.steps, args.warmup)
+            r.close()
             log(f"{name}: {1000.0 / results[name]['ms']:.1f} FPS, {results[name]['stats'].n_splats} splats, "
                 f"{results[name]['stats'].n_pairs} pairs")
     res = results[head]

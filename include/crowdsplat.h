@@ -75,12 +75,22 @@ typedef struct cs_options {
   int32_t profile_stages;    /* 1: time every stage with HIP events (eager only) */
   int64_t max_splats;        /* fixed splat capacity (0: grow on demand)        */
   int64_t max_pairs;         /* fixed tile-pair capacity (0: grow on demand)    */
-  int32_t sort_algo;         /* CS_SORT_REDUCE_SCAN (default) | CS_SORT_ONESWEEP */
+  int32_t sort_algo;         /* CS_SORT_TILE_BUCKET (default) | _ONESWEEP | _REDUCE_SCAN */
   int32_t reserved[7];
 } cs_options;
 
-#define CS_SORT_REDUCE_SCAN 0  /* per-pass digit counts over contiguous ranges, scan, ordered scatter */
-#define CS_SORT_ONESWEEP    1  /* single-kernel passes with decoupled look-back                   */
+/* How frames bin and order their tile pairs. All three give the same ranges
+ * and the same per-tile order (the stable sort of the emitted keys).
+ * TILE_BUCKET: pairs go straight into per-tile segments that are then sorted
+ *   by depth (for frames of at most 8192 tiles, not in view mode; otherwise,
+ *   and in cs_sort_pairs, the reduce-then-scan radix sort is used). Pair
+ *   offsets and emission-order pairs are then built only on demand
+ *   (cs_render_backward, cs_debug_copy).
+ * ONESWEEP: emission, then 11-bit LSD passes with decoupled look-back.
+ * REDUCE_SCAN: emission, then 11-bit LSD passes of count / scan / scatter. */
+#define CS_SORT_TILE_BUCKET 0
+#define CS_SORT_ONESWEEP    1
+#define CS_SORT_REDUCE_SCAN 2
 
 /* One canonical template (CrowdSplat §2: shared template attributes).
  * Arrays of n_gauss rows; the Gaussians must already be in importance order

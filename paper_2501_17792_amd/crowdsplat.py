@@ -21,7 +21,7 @@ CS_ERR_INVALID, CS_ERR_OOM, CS_ERR_DEVICE, CS_ERR_CAPACITY, CS_ERR_STATE, CS_ERR
 CS_MEM_HOST, CS_MEM_DEVICE = 0, 1
 CS_SKIN_FULL, CS_SKIN_MEANS_ONLY = 0, 1
 CS_LAUNCH_BATCHED, CS_LAUNCH_PER_INSTANCE = 0, 1
-CS_SORT_REDUCE_SCAN, CS_SORT_ONESWEEP = 0, 1
+CS_SORT_TILE_BUCKET, CS_SORT_ONESWEEP, CS_SORT_REDUCE_SCAN = 0, 1, 2
 CS_LOD_FULL, CS_LOD_FIXED, CS_LOD_LEARNED, CS_LOD_CONSTANT = 0, 1, 2, 3
 CS_MLP_NPARAM, CS_MLP_NBF16 = 7312, 7168
 #: offsets of the layers inside cs_mlp.params (out-major weights)
@@ -190,7 +190,7 @@ class Renderer:
 
     def __init__(self, device: int = 0, stream=None, tile=(16, 16), skin_mode=CS_SKIN_FULL,
                  launch_mode=CS_LAUNCH_BATCHED, fuse=False, max_splats=0, max_pairs=0,
-                 profile=False, sort_algo=CS_SORT_REDUCE_SCAN):
+                 profile=False, sort_algo=CS_SORT_TILE_BUCKET):
         import torch
         self.torch = torch
         self.lib = load_library()

@@ -116,10 +116,10 @@ hipError_t launch_fk(const cs_instance* inst, const float* pose, const TemplateD
 hipError_t launch_lod_fixed(const cs_instance* inst, const TemplateDev* tpl, int n_inst, int n_tpl,
                             CamDev cam, const float* thr, int n_thr, int full, int const_level,
                             int32_t* level, uint32_t* count, hipStream_t st);
-hipError_t launch_worklist(const int32_t* level, const uint32_t* count, int n_inst,
-                           uint32_t* offset, uint32_t* chunk_off, Chunk* chunks, int max_chunks,
-                           uint32_t max_splats, FrameHdr* hdr, int32_t* level_out,
-                           hipStream_t st);
+hipError_t launch_worklist(const int32_t* level, const uint32_t* count, const cs_instance* inst, int n_inst,
+                           int n_tpl, int tpl_chunks, uint32_t* offset, uint32_t* chunk_off, Chunk* chunks,
+                           Chunk* chunks_t, int max_chunks, uint32_t max_splats, FrameHdr* hdr,
+                           int32_t* level_out, hipStream_t st);
 hipError_t launch_skin(WorkDev w, SkinOut out, int chunk_lo, int chunk_hi, int grid,
                        hipStream_t st);
 hipError_t launch_project(WorkDev w, SkinOut skinned, int fused, CamDev cam, SplatOut out,
@@ -158,9 +158,8 @@ hipError_t launch_mlp_train(cs_mlp* net, float* m, float* v, const float* feat, 
                             int step, float lr, float* loss, hipStream_t st);
 hipError_t launch_view_layout(const cs_instance* inst, const float* joints, const TemplateDev* tpl, int n_inst,
                               int n_tpl, CamDev cam, int64_t* views, int4* crop, FrameHdr* hdr, hipStream_t st);
-hipError_t launch_blend_backward(const uint32_t* ranges, const uint32_t* svals, const uint64_t* skeys,
-                                 const float4* rec, const uint32_t* rect, const uint32_t* pair_off, CamDev cam,
-                                 const float* dimg, float* gpair, const FrameHdr* hdr, hipStream_t st);
+hipError_t launch_blend_backward(const uint32_t* ranges, const uint32_t* svals, const float4* rec,
+                                 const uint32_t* rect, const uint32_t* pair_off, CamDev cam, const float* dimg, float* gpair, const FrameHdr* hdr, hipStream_t st);
 hipError_t launch_splat_backward(WorkDev w, const float* raw_log_scale, const float* raw_quat, int tid, CamDev cam,
                                  const float4* rec, const uint32_t* count, const uint32_t* pair_off,
                                  const float* gpair, float* gsplat, uint32_t stride, int grid, hipStream_t st);
@@ -173,6 +172,48 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 hipError_t launch_sigmoid(const float* logit, float* o, int n, hipStream_t st);
 hipError_t launch_view_psnr(const int64_t* views, int n_inst, const float* ref, const float* img, float* psnr,
                             hipStream_t st);
+
+// ---- tile-bucket sort -----------------------------------------------------
+constexpr int kBucketMaxTiles = 8192;  // frames with more tiles use the LSD radix sort
+constexpr int kSplitLevels = 7;        // 8-bit splits: 63 key bits down to the LDS capacity
+constexpr int kSegCap = 16384;         // keys one workgroup sorts in LDS
+// u32 offsets inside the bucket region of the per-frame cleared counter buffer
+constexpr int kBucketCnt = 0;                        // [tiles] pairs per tile
+constexpr int kBucketMinC = kBucketMaxTiles;         // [tiles] ~(min depth bits)
+constexpr int kBucketMax = 2 * kBucketMaxTiles;      // [tiles] max depth bits
+constexpr int kBucketCtr = 3 * kBucketMaxTiles;      // counters below
+constexpr int kBucketRegion = 3 * kBucketMaxTiles + 32;
+constexpr int kCtrBase = 0;          // entries in the base list
+constexpr int kCtrSortTicket = 1;    // work ticket of the LDS sort
+constexpr int kCtrSplitTicket = 2;   // + level: work tickets of the splits
+constexpr int kCtrBig = 2 + kSplitLevels;  // + level: entries in the big list of that level
+constexpr int kHistLen = kMaxPasses * kSortBins + kBucketRegion;
+
+// A key segment [start, start + len) of key buffer `buf`: K_lo <= K < K_lo + 2^dbits.
+struct SegEntry {
+  uint64_t klo;
+  uint32_t start, len, dbits, buf;
+};
+
+struct SegLists {
+  SegEntry* base;      // segments that fit one workgroup's LDS
+  SegEntry* big[2];    // segments to split, by level parity
+  uint32_t* counters;  // kCtr* (inside the cleared bucket region)
+  uint32_t cap_base, cap_big;
+};
+
+hipError_t launch_bucket_count(const uint32_t* count, const uint32_t* rect, const float4* rec, CamDev cam,
+                               const FrameHdr* hdr, uint32_t* region, int grid, hipStream_t st);
+hipError_t launch_bucket_scan(const uint32_t* region, int n_tiles, FrameHdr* hdr, uint32_t max_pairs,
+                              uint32_t* ranges, uint32_t* cursor, hipStream_t st);
+hipError_t launch_bucket_scatter(const uint32_t* count, const uint32_t* rect, const float4* rec, CamDev cam,
+                                 const FrameHdr* hdr, uint32_t max_pairs, uint32_t* cursor, uint64_t* items,
+                                 int grid, hipStream_t st);
+hipError_t launch_seg_sort(const uint32_t* ranges, const uint32_t* region, int n_tiles, FrameHdr* hdr,
+                           uint32_t max_pairs, uint64_t* keys0, uint64_t* keys1, SegLists lists, uint32_t* vals,
+                           int grid, hipStream_t st);
+hipError_t launch_bucket_keys(const uint32_t* ranges, const uint32_t* vals, const float4* rec, int n_tiles,
+                              uint64_t* keys, hipStream_t st);
 
 // Onesweep partition geometry (items per partition = threads x items).
 #ifndef CS_SORT_THREADS

@@ -25,8 +25,7 @@ constexpr int kGT = 59;    // per-splat template gradient: mean3 ls3 q4 logit1 s
 // ---------------------------------------------------------------------------
 template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void blend_backward_kernel(
-    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ svals, const uint64_t* __restrict__ skeys,
-    const float4* __restrict__ rec, const uint32_t* __restrict__ rect, const uint32_t* __restrict__ pair_off,
+    const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ svals, const float4* __restrict__ rec, const uint32_t* __restrict__ rect, const uint32_t* __restrict__ pair_off,
     CamDev cam, const float* __restrict__ dimg, float* __restrict__ gpair, const FrameHdr* __restrict__ hdr) {
   constexpr int N = TW * TH;
   constexpr int WAVES = N / 64;
@@ -98,9 +97,7 @@ __global__ __launch_bounds__(TW* TH) void blend_backward_kernel(
       if (ok) {  // emission slot: pair_off[s] + row-major index of this tile in s's rect
         const uint32_t r = rect[s];
         const uint32_t x0 = r & 0xffu, y0 = (r >> 8) & 0xffu, x1 = (r >> 16) & 0xffu;
-        const uint32_t t = (uint32_t)(skeys[idx] >> 31);
-        const uint32_t ttx = t % (uint32_t)cam.tiles_x, tty = t / (uint32_t)cam.tiles_x;
-        slot = pair_off[s] + (tty - y0) * (x1 - x0 + 1) + (ttx - x0);
+        slot = pair_off[s] + ((uint32_t)ty - y0) * (x1 - x0 + 1) + ((uint32_t)tx - x0);
       }
       s_slot[threadIdx.x] = slot;
     }
@@ -178,13 +175,13 @@ __global__ __launch_bounds__(TW* TH) void blend_backward_kernel(
   }
 }
 
-hipError_t launch_blend_backward(const uint32_t* ranges, const uint32_t* svals, const uint64_t* skeys,
-                                 const float4* rec, const uint32_t* rect, const uint32_t* pair_off, CamDev cam,
+hipError_t launch_blend_backward(const uint32_t* ranges, const uint32_t* svals, const float4* rec,
+                                 const uint32_t* rect, const uint32_t* pair_off, CamDev cam,
                                  const float* dimg, float* gpair, const FrameHdr* hdr, hipStream_t st) {
   const int grid = cam.tiles_x * cam.tiles_y;
 #define CS_BB_CASE(W_, H_)                                                                                   \
   if (cam.tw == W_ && cam.th == H_) {                                                                        \
-    blend_backward_kernel<W_, H_><<<grid, W_ * H_, 0, st>>>(ranges, svals, skeys, rec, rect, pair_off, cam, \
+    blend_backward_kernel<W_, H_><<<grid, W_ * H_, 0, st>>>(ranges, svals, rec, rect, pair_off, cam,        \
                                                             dimg, gpair, hdr);                              \
     return hipGetLastError();                                                                                \
   }

@@ -58,7 +58,8 @@ struct cs_ctx {
   uint32_t* count_inst = nullptr;
   uint32_t* offset = nullptr;
   uint32_t* chunk_off = nullptr;
-  Chunk* chunks = nullptr;
+  Chunk* chunks = nullptr;     // work list, instance-major (per-instance launches)
+  Chunk* chunks_t = nullptr;   // the same chunks, template-major (batched launches)
   float* bones = nullptr;
   float* joints = nullptr;
   float* feat = nullptr;      // [cap_inst][32] learned-LoD features
@@ -91,11 +92,18 @@ struct cs_ctx {
   uint64_t* keys[2] = {nullptr, nullptr};
   uint32_t* vals[2] = {nullptr, nullptr};
   uint64_t* lookback = nullptr;
-  uint32_t* hist = nullptr;  // kMaxPasses * kSortBins
+  uint32_t* hist = nullptr;  // kHistLen: onesweep digit counts, then the tile-bucket region
   uint32_t* rts_counts = nullptr;  // kRtsBlocks * kSortBins digit-major counts
   uint32_t* rts_sums = nullptr;
   int64_t cap_tiles = 0;
   uint32_t* ranges = nullptr;
+  uint32_t* cursor = nullptr;        // [kBucketMaxTiles] tile write cursors (tile-bucket sort)
+  SegEntry* seg_base = nullptr;      // key segments sorted in LDS
+  SegEntry* seg_big[2] = {nullptr, nullptr};  // key segments to split
+  int64_t cap_seg_base = 0, cap_seg_big = 0;
+  bool bucket_frame = false;         // the last frame was binned into tile buckets
+  bool pair_off_valid = false;       // pair_off holds the scan of this frame's tile counts
+  bool debug_pairs = false;          // emission-order pairs and sorted keys rebuilt for inspection
 
   // frame state
   int state = kNone;
@@ -177,6 +185,7 @@ cs_status ensure_instances(cs_ctx* ctx, int64_t n_inst) {
   CS_TRY(dalloc(ctx, &ctx->offset, cap + 1));
   CS_TRY(dalloc(ctx, &ctx->chunk_off, cap + 1));
   CS_TRY(dalloc(ctx, &ctx->chunks, cap * per));
+  CS_TRY(dalloc(ctx, &ctx->chunks_t, cap * per));
   CS_TRY(dalloc(ctx, &ctx->bones, cap * kJoints * 12));
   CS_TRY(dalloc(ctx, &ctx->joints, cap * kJoints * 3));
   CS_TRY(dalloc(ctx, &ctx->feat, cap * 32));
@@ -216,6 +225,15 @@ cs_status ensure_pairs(cs_ctx* ctx, int64_t n) {
     CS_TRY(dalloc(ctx, &ctx->keys[b], cap));
     CS_TRY(dalloc(ctx, &ctx->vals[b], cap));
   }
+  // tile-bucket segment lists: a split turns a segment of more than kSegCap
+  // keys into at most 256, so every level adds fewer than cap / 64 entries
+  const int64_t cap_base = kBucketMaxTiles + cap / 8 + 1024;
+  const int64_t cap_big = cap / kSegCap + kBucketMaxTiles + 64;
+  CS_TRY(dalloc(ctx, &ctx->seg_base, cap_base));
+  CS_TRY(dalloc(ctx, &ctx->seg_big[0], cap_big));
+  CS_TRY(dalloc(ctx, &ctx->seg_big[1], cap_big));
+  ctx->cap_seg_base = cap_base;
+  ctx->cap_seg_big = cap_big;
   const int64_t parts = (cap + kSortPart - 1) / kSortPart;
   CS_TRY(dalloc(ctx, &ctx->lookback, parts * kSortBins));
   HIP_TRY(hipMemsetAsync(ctx->lookback, 0, parts * kSortBins * sizeof(uint64_t), ctx->stream));
@@ -274,12 +292,12 @@ int sort_passes(int n_tiles) {
   return (31 + bits + kSortBits - 1) / kSortBits;
 }
 
-WorkDev work_view(cs_ctx* ctx) {
+WorkDev work_view(cs_ctx* ctx, bool template_major = true) {
   WorkDev w{};
   w.inst = ctx->inst;
   w.bones = ctx->bones;
   w.offset = ctx->offset;
-  w.chunks = ctx->chunks;
+  w.chunks = template_major ? ctx->chunks_t : ctx->chunks;
   w.tpl = ctx->tpl_dev;
   w.hdr = ctx->hdr;
   w.skin_mode = ctx->opt.skin_mode;
@@ -324,7 +342,8 @@ cs_status cs_create(int32_t device, void* stream, const cs_options* opt, cs_ctx*
   if (o.skin_mode != CS_SKIN_FULL && o.skin_mode != CS_SKIN_MEANS_ONLY) return CS_ERR_INVALID;
   if (o.launch_mode != CS_LAUNCH_BATCHED && o.launch_mode != CS_LAUNCH_PER_INSTANCE) return CS_ERR_INVALID;
   if (o.max_splats < 0 || o.max_pairs < 0) return CS_ERR_INVALID;
-  if (o.sort_algo != CS_SORT_REDUCE_SCAN && o.sort_algo != CS_SORT_ONESWEEP) return CS_ERR_INVALID;
+  if (o.sort_algo != CS_SORT_TILE_BUCKET && o.sort_algo != CS_SORT_REDUCE_SCAN && o.sort_algo != CS_SORT_ONESWEEP)
+    return CS_ERR_INVALID;
   int n_dev = 0;
   if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev) {
     (void)hipGetLastError();
@@ -336,7 +355,8 @@ cs_status cs_create(int32_t device, void* stream, const cs_options* opt, cs_ctx*
   ctx->stream = (hipStream_t)stream;
   ctx->opt = o;
   cs_status s = dalloc(ctx, &ctx->hdr, 1);
-  if (s == CS_OK) s = dalloc(ctx, &ctx->hist, kMaxPasses * kSortBins);
+  if (s == CS_OK) s = dalloc(ctx, &ctx->hist, kHistLen);
+  if (s == CS_OK) s = dalloc(ctx, &ctx->cursor, kBucketMaxTiles);
   if (s == CS_OK) s = dalloc(ctx, &ctx->n_dev, 1);
   if (s == CS_OK) s = dalloc(ctx, &ctx->rts_counts, (size_t)kRtsBlocks * kSortBins);
   if (s == CS_OK) s = dalloc(ctx, &ctx->rts_sums, (size_t)kRtsBlocks * kSortBins / 4096 + 2);
@@ -377,6 +397,7 @@ void cs_destroy(cs_ctx* ctx) {
   dfree(&ctx->offset);
   dfree(&ctx->chunk_off);
   dfree(&ctx->chunks);
+  dfree(&ctx->chunks_t);
   dfree(&ctx->bones);
   dfree(&ctx->joints);
   dfree(&ctx->feat);
@@ -400,6 +421,10 @@ void cs_destroy(cs_ctx* ctx) {
   }
   dfree(&ctx->lookback);
   dfree(&ctx->hist);
+  dfree(&ctx->cursor);
+  dfree(&ctx->seg_base);
+  dfree(&ctx->seg_big[0]);
+  dfree(&ctx->seg_big[1]);
   dfree(&ctx->rts_counts);
   dfree(&ctx->rts_sums);
   dfree(&ctx->ranges);
@@ -569,8 +594,10 @@ cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, co
                              ctx->stream));
   }
   const uint32_t cap_s = (uint32_t)std::min<int64_t>(ctx->cap_splats, 0xffffffffll);
-  HIP_TRY(launch_worklist(ctx->level, ctx->count_inst, n_inst, ctx->offset, ctx->chunk_off, ctx->chunks,
-                          (int)ctx->cap_chunks, cap_s, ctx->hdr, level_out, ctx->stream));
+  const int tpl_chunks = (int)((ctx->max_tpl_n + kChunk - 1) / kChunk);
+  HIP_TRY(launch_worklist(ctx->level, ctx->count_inst, inst, n_inst, (int)ctx->tpl.size(), tpl_chunks, ctx->offset,
+                          ctx->chunk_off, ctx->chunks, ctx->chunks_t, (int)ctx->cap_chunks, cap_s, ctx->hdr,
+                          level_out, ctx->stream));
   ctx->mark(CS_STAGE_LOD, 1);
   if (!ctx->capturing) {
     // learn the frame's size, grow the splat arrays, and redo the (tiny) work list
@@ -581,9 +608,9 @@ cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, co
       if (ctx->fixed_capacity) return ctx->fail(CS_ERR_CAPACITY, "splat capacity exceeded");
       CS_TRY(ensure_splats(ctx, total));
       HIP_TRY(hipMemsetAsync(&ctx->hdr->overflow, 0, 4, ctx->stream));
-      HIP_TRY(launch_worklist(ctx->level, ctx->count_inst, n_inst, ctx->offset, ctx->chunk_off,
-                              ctx->chunks, (int)ctx->cap_chunks, (uint32_t)ctx->cap_splats, ctx->hdr,
-                              level_out, ctx->stream));
+      HIP_TRY(launch_worklist(ctx->level, ctx->count_inst, inst, n_inst, (int)ctx->tpl.size(), tpl_chunks,
+                              ctx->offset, ctx->chunk_off, ctx->chunks, ctx->chunks_t, (int)ctx->cap_chunks,
+                              (uint32_t)ctx->cap_splats, ctx->hdr, level_out, ctx->stream));
       CS_TRY(read_header(ctx));
     }
     if (ctx->opt.launch_mode == CS_LAUNCH_PER_INSTANCE) {
@@ -601,7 +628,7 @@ cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, co
 }
 
 static cs_status run_per_instance(cs_ctx* ctx, bool project, SkinOut so, int fused, SplatOut po) {
-  WorkDev w = work_view(ctx);
+  WorkDev w = work_view(ctx, false);
   for (int i = 0; i < ctx->n_inst; ++i) {
     const int lo = (int)ctx->chunk_off_host[i], hi = (int)ctx->chunk_off_host[i + 1];
     if (hi <= lo) continue;
@@ -642,6 +669,47 @@ cs_status cs_skin_instances(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst
   return CS_OK;
 }
 
+constexpr int kBucketGrid = 512;  // workgroups of the tile-bucket count and scatter kernels
+constexpr int kSegGrid = 512;     // workgroups of the split and LDS sort kernels
+
+static cs_status lsd_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles, const ViewDev* vp);
+
+// A6-A8 in tile-bucket form: count and scan per tile (ranges come out of the
+// scan), scatter the pairs into their tiles, sort every tile by depth.
+static cs_status bucket_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles) {
+  uint32_t* region = ctx->hist + kMaxPasses * kSortBins;
+  uint32_t cap_p = (uint32_t)std::min<int64_t>(ctx->cap_pairs, kMaxPairsLimit);
+  ctx->mark(CS_STAGE_EMIT, 0);
+  HIP_TRY(launch_bucket_count(ctx->cnt, ctx->rect, ctx->rec, cd, ctx->hdr, region, kBucketGrid, ctx->stream));
+  HIP_TRY(launch_bucket_scan(region, n_tiles, ctx->hdr, ctx->capturing ? cap_p : kMaxPairsLimit, ctx->ranges,
+                             ctx->cursor, ctx->stream));
+  if (!ctx->capturing) {
+    CS_TRY(read_header(ctx));
+    const int64_t n_pairs = ctx->hdr_host->n_pairs;
+    if (n_pairs > ctx->cap_pairs) {
+      if (ctx->fixed_capacity) return ctx->fail(CS_ERR_CAPACITY, "pair capacity exceeded");
+      CS_TRY(ensure_pairs(ctx, n_pairs));
+    }
+    cap_p = (uint32_t)std::min<int64_t>(ctx->cap_pairs, kMaxPairsLimit);
+  }
+  HIP_TRY(launch_bucket_scatter(ctx->cnt, ctx->rect, ctx->rec, cd, ctx->hdr, cap_p, ctx->cursor, ctx->keys[0],
+                                kBucketGrid, ctx->stream));
+  ctx->mark(CS_STAGE_EMIT, 1);
+  ctx->mark(CS_STAGE_SORT, 0);
+  SegLists lists{};
+  lists.base = ctx->seg_base;
+  lists.big[0] = ctx->seg_big[0];
+  lists.big[1] = ctx->seg_big[1];
+  lists.counters = region + kBucketCtr;
+  lists.cap_base = (uint32_t)std::min<int64_t>(ctx->cap_seg_base, 0xffffffffll);
+  lists.cap_big = (uint32_t)std::min<int64_t>(ctx->cap_seg_big, 0xffffffffll);
+  HIP_TRY(launch_seg_sort(ctx->ranges, region, n_tiles, ctx->hdr, cap_p, ctx->keys[0], ctx->keys[1], lists,
+                          ctx->vals[0], kSegGrid, ctx->stream));
+  ctx->mark(CS_STAGE_SORT, 1);
+  ctx->sorted = 0;
+  return CS_OK;
+}
+
 static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs_frame_stats* stats,
                              bool view_mode) {
   if (ctx->state < kSkinned) return ctx->fail(CS_ERR_STATE, "render before cs_skin_instances");
@@ -661,7 +729,12 @@ static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs
   const int n_tiles = view_mode ? (int)ctx->view_tiles : cd.tiles_x * cd.tiles_y;
   CS_TRY(ensure_tiles(ctx, n_tiles));
   ctx->passes = sort_passes(n_tiles);
-  HIP_TRY(launch_frame_reset(ctx->hdr, ctx->hist, kMaxPasses * kSortBins, 0, ctx->stream));
+  const bool bucket =
+      !view_mode && ctx->opt.sort_algo == CS_SORT_TILE_BUCKET && n_tiles > 0 && n_tiles <= kBucketMaxTiles;
+  ctx->bucket_frame = bucket;
+  ctx->pair_off_valid = !bucket;
+  ctx->debug_pairs = false;
+  HIP_TRY(launch_frame_reset(ctx->hdr, ctx->hist, kHistLen, 0, ctx->stream));
   // A4 projection
   SkinOut so{ctx->skin_mu, ctx->skin_cov, ctx->skin_zz};
   SplatOut po{ctx->rec, ctx->rect, ctx->cnt};
@@ -677,7 +750,33 @@ static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs
     HIP_TRY(launch_project(wv, so, fused, cd, po, (uint32_t)ctx->cap_splats, 0, -1, grid, ctx->stream));
   }
   ctx->mark(CS_STAGE_PROJECT, 1);
-  // A5 scan of tile counts
+  if (bucket) {
+    CS_TRY(bucket_bin_sort(ctx, cd, n_tiles));
+  } else {
+    CS_TRY(lsd_bin_sort(ctx, cd, n_tiles, vp));
+  }
+  ctx->mark(CS_STAGE_BLEND, 0);
+  if (n_tiles > 0) HIP_TRY(launch_blend(ctx->ranges, ctx->vals[ctx->sorted], ctx->rec, cd, image, ctx->hdr, vp, ctx->stream));
+  ctx->mark(CS_STAGE_BLEND, 1);
+  ctx->state = kRendered;
+  if (stats) {
+    CS_TRY(read_header(ctx));
+    const FrameHdr& h = *ctx->hdr_host;
+    memset(stats, 0, sizeof(*stats));
+    stats->n_splats = h.n_splats;
+    stats->n_visible = h.n_visible;
+    stats->n_pairs = h.n_pairs;
+    stats->overflow = (int32_t)h.overflow;
+    stats->n_instances = (int32_t)h.n_inst;
+    for (int l = 0; l < CS_MAX_LEVELS; ++l) stats->level_hist[l] = (int32_t)h.level_hist[l];
+    if (h.overflow) return ctx->fail(CS_ERR_CAPACITY, "frame exceeded a capacity (see stats)");
+  }
+  return CS_OK;
+}
+
+// A5-A8 in emission form: scan of the per-splat tile counts, pair emission,
+// LSD radix passes over the (tile | depth) keys, per-tile ranges.
+static cs_status lsd_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles, const ViewDev* vp) {
   const int64_t n_splats = ctx->capturing ? ctx->cap_splats : ctx->hdr_host->n_splats;
   const int scan_blocks = (int)std::max<int64_t>(1, (n_splats + scan_tile() - 1) / scan_tile());
   uint32_t cap_p = (uint32_t)std::min<int64_t>(ctx->cap_pairs, kMaxPairsLimit);
@@ -722,26 +821,10 @@ static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs
   }
   ctx->mark(CS_STAGE_SORT, 1);
   ctx->sorted = src;
-  // A8 ranges, A9 blend
+  // A8 ranges
   ctx->mark(CS_STAGE_RANGES, 0);
   if (n_tiles > 0) HIP_TRY(launch_ranges(ctx->keys[src], ctx->hdr, cap_p, n_tiles, ctx->ranges, ctx->stream));
   ctx->mark(CS_STAGE_RANGES, 1);
-  ctx->mark(CS_STAGE_BLEND, 0);
-  if (n_tiles > 0) HIP_TRY(launch_blend(ctx->ranges, ctx->vals[src], ctx->rec, cd, image, ctx->hdr, vp, ctx->stream));
-  ctx->mark(CS_STAGE_BLEND, 1);
-  ctx->state = kRendered;
-  if (stats) {
-    CS_TRY(read_header(ctx));
-    const FrameHdr& h = *ctx->hdr_host;
-    memset(stats, 0, sizeof(*stats));
-    stats->n_splats = h.n_splats;
-    stats->n_visible = h.n_visible;
-    stats->n_pairs = h.n_pairs;
-    stats->overflow = (int32_t)h.overflow;
-    stats->n_instances = (int32_t)h.n_inst;
-    for (int l = 0; l < CS_MAX_LEVELS; ++l) stats->level_hist[l] = (int32_t)h.level_hist[l];
-    if (h.overflow) return ctx->fail(CS_ERR_CAPACITY, "frame exceeded a capacity (see stats)");
-  }
   return CS_OK;
 }
 
@@ -827,6 +910,18 @@ cs_status cs_mlp_train_step(cs_ctx* ctx, cs_mlp* net, float* adam_m, float* adam
   return CS_OK;
 }
 
+// The tile-bucket binning needs no per-splat pair offsets; the backward pass
+// (per-pair gradient slots) and inspection compute them on demand.
+static cs_status ensure_pair_offsets(cs_ctx* ctx) {
+  if (ctx->pair_off_valid) return CS_OK;
+  const int64_t n_splats = ctx->hdr_host->n_splats;
+  const int scan_blocks = (int)std::max<int64_t>(1, (n_splats + scan_tile() - 1) / scan_tile());
+  HIP_TRY(launch_scan_counts(ctx->cnt, ctx->pair_off, ctx->scan_sums, scan_blocks, ctx->hdr, kMaxPairsLimit,
+                             ctx->stream));
+  ctx->pair_off_valid = true;
+  return CS_OK;
+}
+
 cs_status cs_render_backward(cs_ctx* ctx, const float* dL_dimage, cs_template_grads* g) {
   if (!ctx) return CS_ERR_INVALID;
   if (ctx->state < kRendered || ctx->last_was_views)
@@ -848,11 +943,10 @@ cs_status cs_render_backward(cs_ctx* ctx, const float* dL_dimage, cs_template_gr
     ctx->cap_gsplat = n_splats;
   }
   const CamDev& cd = ctx->cam;
-  const uint32_t cap_p = (uint32_t)std::min<int64_t>(ctx->cap_pairs, kMaxPairsLimit);
-  (void)cap_p;
+  CS_TRY(ensure_pair_offsets(ctx));
   if (n_pairs > 0)
-    HIP_TRY(launch_blend_backward(ctx->ranges, ctx->vals[ctx->sorted], ctx->keys[ctx->sorted], ctx->rec, ctx->rect,
-                                  ctx->pair_off, cd, dL_dimage, ctx->gpair, ctx->hdr, ctx->stream));
+    HIP_TRY(launch_blend_backward(ctx->ranges, ctx->vals[ctx->sorted], ctx->rec, ctx->rect, ctx->pair_off, cd,
+                                  dL_dimage, ctx->gpair, ctx->hdr, ctx->stream));
   const TemplateStore& T = ctx->tpl[g->template_id];
   const int grid = persistent_grid(ctx->hdr_host->n_chunks, 4096);
   HIP_TRY(launch_splat_backward(work_view(ctx), T.raw_log_scale, T.raw_quat, g->template_id, cd, ctx->rec, ctx->cnt,
@@ -963,6 +1057,8 @@ cs_status cs_frame_launch(cs_ctx* ctx) {
   if (!ctx) return CS_ERR_INVALID;
   if (!ctx->gexec) return ctx->fail(CS_ERR_STATE, "no captured frame");
   HIP_TRY(hipGraphLaunch(ctx->gexec, ctx->stream));
+  ctx->pair_off_valid = !ctx->bucket_frame;  // a new frame: on-demand buffers are stale
+  ctx->debug_pairs = false;
   return CS_OK;
 }
 
@@ -987,6 +1083,23 @@ cs_status cs_debug_copy(cs_ctx* ctx, int32_t which, void* host_dst, int64_t offs
   if (!host_dst || offset < 0 || bytes < 0) return ctx->fail(CS_ERR_INVALID, "bad copy arguments");
   const void* src = nullptr;
   int64_t size = 0;
+  const bool pair_buf = which == CS_BUF_PAIR_OFF || which == CS_BUF_KEYS || which == CS_BUF_VALS ||
+                        which == CS_BUF_SKEYS;
+  if (pair_buf && ctx->bucket_frame && ctx->state >= kRendered && !ctx->debug_pairs) {
+    // rebuild what the emission form keeps: pair offsets, emission-order
+    // pairs (second buffers) and the sorted keys (first key buffer)
+    hipSetDevice(ctx->device);
+    CS_TRY(read_header(ctx));
+    CS_TRY(ensure_pair_offsets(ctx));
+    const uint32_t cap_p = (uint32_t)std::min<int64_t>(ctx->cap_pairs, kMaxPairsLimit);
+    const int grid = persistent_grid((ctx->hdr_host->n_splats + 255) / 256, 1024);
+    HIP_TRY(launch_emit(ctx->cnt, ctx->pair_off, ctx->rect, ctx->rec, ctx->cam, ctx->keys[1], ctx->vals[1],
+                        ctx->hist, 0, ctx->hdr, cap_p, grid, nullptr, ctx->stream));
+    HIP_TRY(launch_bucket_keys(ctx->ranges, ctx->vals[0], ctx->rec, ctx->cam.tiles_x * ctx->cam.tiles_y,
+                               ctx->keys[0], ctx->stream));
+    ctx->debug_pairs = true;
+  }
+  const int eb = ctx->bucket_frame ? 1 : 0;  // buffers holding the emission-order pairs
   switch (which) {
     case CS_BUF_BONES: src = ctx->bones; size = ctx->cap_inst * kJoints * 12 * 4; break;
     case CS_BUF_LEVEL: src = ctx->level; size = ctx->cap_inst * 4; break;
@@ -998,8 +1111,8 @@ cs_status cs_debug_copy(cs_ctx* ctx, int32_t which, void* host_dst, int64_t offs
     case CS_BUF_RECT: src = ctx->rect; size = ctx->cap_splats * 4; break;
     case CS_BUF_COUNT: src = ctx->cnt; size = ctx->cap_splats * 4; break;
     case CS_BUF_PAIR_OFF: src = ctx->pair_off; size = ctx->cap_splats * 4; break;
-    case CS_BUF_KEYS: src = ctx->keys[0]; size = ctx->cap_pairs * 8; break;
-    case CS_BUF_VALS: src = ctx->vals[0]; size = ctx->cap_pairs * 4; break;
+    case CS_BUF_KEYS: src = ctx->keys[eb]; size = ctx->cap_pairs * 8; break;
+    case CS_BUF_VALS: src = ctx->vals[eb]; size = ctx->cap_pairs * 4; break;
     case CS_BUF_SKEYS: src = ctx->keys[ctx->sorted]; size = ctx->cap_pairs * 8; break;
     case CS_BUF_SVALS: src = ctx->vals[ctx->sorted]; size = ctx->cap_pairs * 4; break;
     case CS_BUF_RANGES: src = ctx->ranges; size = ctx->cap_tiles * 8; break;

@@ -295,12 +295,16 @@ __device__ __forceinline__ uint32_t block_inclusive_scan_1024(uint32_t v, uint32
   return r;
 }
 
+constexpr int kMaxTplChunks = 8192;  // (template, chunk) groups of the template-major order
+
 __global__ __launch_bounds__(kWlThreads) void worklist_kernel(
-    const int32_t* __restrict__ level, const uint32_t* __restrict__ count, int n_inst,
-    uint32_t* __restrict__ offset, uint32_t* __restrict__ chunk_off, Chunk* __restrict__ chunks,
-    int max_chunks, uint32_t max_splats, FrameHdr* hdr, int32_t* __restrict__ level_out) {
+    const int32_t* __restrict__ level, const uint32_t* __restrict__ count, const cs_instance* __restrict__ inst,
+    int n_inst, int n_tpl, int tpl_chunks, uint32_t* __restrict__ offset, uint32_t* __restrict__ chunk_off,
+    Chunk* __restrict__ chunks, Chunk* __restrict__ chunks_t, int max_chunks, uint32_t max_splats, FrameHdr* hdr,
+    int32_t* __restrict__ level_out) {
   __shared__ uint32_t s_scan[kWlThreads];
   __shared__ uint32_t s_hist[kMaxLevels];
+  __shared__ uint32_t s_tk[kMaxTplChunks];
   const int t = threadIdx.x;
   if (t < kMaxLevels) s_hist[t] = 0;
   __syncthreads();
@@ -346,14 +350,61 @@ __global__ __launch_bounds__(kWlThreads) void worklist_kernel(
     const uint32_t c0 = chunk_off[i];
     for (uint32_t k = 0; k < nc; ++k) chunks[c0 + k] = Chunk{i, (int32_t)(k * kChunk)};
   }
+  // The same chunks in template-major order: (template, chunk k) groups, each
+  // holding every instance that draws chunk k of that template, so that the
+  // workgroups running at one time read the same template attributes (shared
+  // through the caches) instead of one template chunk per instance. Splat
+  // indices do not depend on this order. Inside a group the order is that of
+  // the LDS atomics.
+  const int n_tk = n_tpl * tpl_chunks;
+  if (n_tk <= 0 || n_tk > kMaxTplChunks) {
+    for (uint32_t c = t; c < (uint32_t)carry_c; c += kWlThreads) chunks_t[c] = chunks[c];
+    return;
+  }
+  for (int k = t; k < n_tk; k += kWlThreads) s_tk[k] = 0;
+  __syncthreads();
+  // (a group index only orders the work: every chunk is placed exactly once)
+  for (int i = t; i < n_inst; i += kWlThreads) {
+    const uint32_t nc = (count[i] + kChunk - 1) / kChunk;
+    const int g0 = min(max(inst[i].tid, 0), n_tpl - 1) * tpl_chunks;
+    for (uint32_t k = 0; k < nc; ++k) atomicAdd(&s_tk[g0 + (int)min(k, (uint32_t)tpl_chunks - 1)], 1u);
+  }
+  __syncthreads();
+  {  // exclusive scan of the group sizes, kMaxTplChunks / kWlThreads per thread
+    constexpr int PER = kMaxTplChunks / kWlThreads;
+    uint32_t v[PER], sum = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int k = t * PER + j;
+      v[j] = k < n_tk ? s_tk[k] : 0u;
+      sum += v[j];
+    }
+    const uint32_t inc = block_inclusive_scan_1024(sum, s_scan);
+    uint32_t run = inc - sum;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int k = t * PER + j;
+      if (k < n_tk) s_tk[k] = run;
+      run += v[j];
+    }
+  }
+  __syncthreads();
+  for (int i = t; i < n_inst; i += kWlThreads) {
+    const uint32_t nc = (count[i] + kChunk - 1) / kChunk;
+    const int g0 = min(max(inst[i].tid, 0), n_tpl - 1) * tpl_chunks;
+    for (uint32_t k = 0; k < nc; ++k) {
+      const uint32_t pos = atomicAdd(&s_tk[g0 + (int)min(k, (uint32_t)tpl_chunks - 1)], 1u);
+      chunks_t[pos] = Chunk{i, (int32_t)(k * kChunk)};
+    }
+  }
 }
 
-hipError_t launch_worklist(const int32_t* level, const uint32_t* count, int n_inst,
-                            uint32_t* offset, uint32_t* chunk_off, Chunk* chunks, int max_chunks,
-                            uint32_t max_splats, FrameHdr* hdr, int32_t* level_out,
-                            hipStream_t st) {
-  worklist_kernel<<<1, kWlThreads, 0, st>>>(level, count, n_inst, offset, chunk_off, chunks,
-                                            max_chunks, max_splats, hdr, level_out);
+hipError_t launch_worklist(const int32_t* level, const uint32_t* count, const cs_instance* inst, int n_inst,
+                           int n_tpl, int tpl_chunks, uint32_t* offset, uint32_t* chunk_off, Chunk* chunks,
+                           Chunk* chunks_t, int max_chunks, uint32_t max_splats, FrameHdr* hdr,
+                           int32_t* level_out, hipStream_t st) {
+  worklist_kernel<<<1, kWlThreads, 0, st>>>(level, count, inst, n_inst, n_tpl, tpl_chunks, offset, chunk_off,
+                                            chunks, chunks_t, max_chunks, max_splats, hdr, level_out);
   return hipGetLastError();
 }
 

@@ -171,7 +171,7 @@ def test_tile_shape_launch_and_fusion_invariance():
     _, ref = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds)
     for kw in [dict(tile=(8, 8)), dict(tile=(32, 32)), dict(tile=(8, 32)),
                dict(launch_mode=cs.CS_LAUNCH_PER_INSTANCE), dict(fuse=True),
-               dict(sort_algo=cs.CS_SORT_ONESWEEP)]:
+               dict(sort_algo=cs.CS_SORT_ONESWEEP), dict(sort_algo=cs.CS_SORT_REDUCE_SCAN)]:
         _, img = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, **kw)
         assert np.array_equal(img, ref), kw
 
