@@ -8,10 +8,12 @@
 // order inside tile t is the order of the 64-bit key
 //     K = depth_bits << 32 | s,
 // which is unique inside a tile. The pipeline:
-//   1. count: pairs, min and max depth bits per tile (LDS, one flush per block)
-//   2. scan: tile starts -> ranges, per-tile write cursors, n_pairs
-//   3. scatter: every pair's K into its tile's segment; slots inside a tile are
-//      handed out by wave-aggregated atomics, so the order there is arbitrary
+//   1. count: pairs per (tile, workgroup) and the depth-bit range per tile
+//   2. scan of the tile-major count matrix -> every workgroup's first slot in
+//      every tile, n_pairs, per-tile ranges
+//   3. scatter: every pair's K into its tile's segment; slots inside a
+//      workgroup's share of a tile are handed out by LDS atomics, so the order
+//      there is arbitrary
 //   4. split (up to 7 levels): segments longer than one workgroup's LDS
 //      capacity are partitioned by the top 8 bits of K - K_lo into sub-segments
 //   5. base: each segment of at most kSegCap keys is sorted in LDS by a stable
@@ -24,8 +26,11 @@ namespace cs {
 
 constexpr int kBkThreads = 1024;           // threads of every bucket-sort workgroup
 constexpr int kBkWaves = kBkThreads / 64;
-constexpr int kSegItems = 16;              // keys per thread in the LDS sort
-static_assert(kBkThreads * kSegItems == kSegCap, "LDS segment capacity");
+constexpr int kSegItems = 16;              // keys per thread in the LDS sort and per split load
+constexpr int kSegWaves = kSegThreads / 64;
+constexpr int kSplitChunk = kBkThreads * kSegItems;  // keys one split workgroup loads at a time
+static_assert(kSegThreads * kSegItems == kSegCap, "LDS segment capacity");
+static_assert(kSegThreads >= 256, "digit scans need 256 threads");
 constexpr int kSplitBits = 8;
 constexpr int kSplitBins = 1 << kSplitBits;
 
@@ -33,35 +38,26 @@ __device__ __forceinline__ int bk_lane() { return (int)(threadIdx.x & 63); }
 
 __device__ __forceinline__ uint64_t lanes_below() { return (1ull << bk_lane()) - 1ull; }
 
-__device__ __forceinline__ uint32_t readlane_u32(uint32_t v, int lane) {
-  return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+// LDS slot counter: every active lane takes one slot of counter[key] (the
+// counter's value before its increment). Lanes of one wave that share a key
+// are serialised by the LDS unit; that measured faster than electing one
+// lane per key first.
+__device__ __forceinline__ uint32_t lds_slot(uint32_t* counter, uint32_t key, bool active) {
+  return active ? atomicAdd(&counter[key], 1u) : 0u;
 }
 
-// LDS slot counter: every active lane takes one slot of counter[key]. When
-// the whole wave shares one key (the common case: consecutive splats of one
-// instance in one tile) a single atomic serves it and slots follow lane
-// order; otherwise each lane takes its own slot. Returns the counter's value
-// before the lane's increment. With TOUCH, whoever takes slot 0 of a counter
-// appends the key to `touch`.
-template <bool TOUCH>
-__device__ __forceinline__ uint32_t agg_slot(uint32_t* counter, uint32_t key, bool active, uint16_t* touch,
-                                             uint32_t* n_touch) {
+// As lds_slot, but when every active lane of the wave has the same key one
+// lane takes all the slots (split passes: consecutive keys of a segment
+// mostly fall in one bin).
+__device__ __forceinline__ uint32_t lds_slot_wave(uint32_t* counter, uint32_t key, bool active) {
   const uint64_t act = __ballot(active);
   if (act == 0) return 0;
   const int leader = __ffsll((unsigned long long)act) - 1;
-  const uint32_t k0 = readlane_u32(key, leader);
-  uint32_t slot = 0;
-  if (__ballot(active && key == k0) == act) {
-    if (bk_lane() == leader) {
-      slot = atomicAdd(&counter[k0], (uint32_t)__popcll(act));
-      if (TOUCH && slot == 0) touch[atomicAdd(n_touch, 1u)] = (uint16_t)k0;
-    }
-    slot = readlane_u32(slot, leader) + (uint32_t)__popcll(act & lanes_below());
-  } else if (active) {
-    slot = atomicAdd(&counter[key], 1u);
-    if (TOUCH && slot == 0) touch[atomicAdd(n_touch, 1u)] = (uint16_t)key;
-  }
-  return slot;
+  const uint32_t k0 = (uint32_t)__builtin_amdgcn_readlane((int)key, leader);
+  if (__ballot(active && key == k0) != act) return active ? atomicAdd(&counter[key], 1u) : 0u;
+  uint32_t base = 0;
+  if (bk_lane() == leader) base = atomicAdd(&counter[k0], (uint32_t)__popcll(act));
+  return (uint32_t)__builtin_amdgcn_readlane((int)base, leader) + (uint32_t)__popcll(act & lanes_below());
 }
 
 // contiguous splat range of workgroup b, a multiple of the workgroup size
@@ -71,6 +67,17 @@ __device__ __forceinline__ void bk_range(uint32_t n, uint32_t& lo, uint32_t& hi)
   lo = min((uint32_t)blockIdx.x * per, n);
   hi = min(lo + per, n);
 }
+
+struct SplatIn {  // what binning reads of one splat: tile count, rect, depth bits
+  uint32_t c, r, db;
+  __device__ __forceinline__ void load(const uint32_t* count, const uint32_t* rect, const float4* rec, uint64_t s,
+                                       uint32_t hi) {
+    const bool in = s < (uint64_t)hi;
+    c = in ? count[s] : 0u;
+    r = in ? rect[s] : 0u;
+    db = in ? __float_as_uint(rec[3 * (size_t)s + 2].w) : 0u;
+  }
+};
 
 struct PairIter {  // walks one splat's tile rect row-major
   uint32_t x0, x1, y1, tx, ty;
@@ -110,17 +117,17 @@ __global__ __launch_bounds__(kBkThreads) void bucket_count_kernel(
   __syncthreads();
   uint32_t lo, hi;
   bk_range(hdr->n_splats, lo, hi);
+  SplatIn nx;
+  nx.load(count, rect, rec, (uint64_t)lo + threadIdx.x, hi);
   for (uint32_t b = lo; b < hi; b += kBkThreads) {
-    const uint32_t s = b + threadIdx.x;
-    const bool in = s < hi;  // the three loads issue together
-    const uint32_t c = in ? count[s] : 0u;
-    const uint32_t r = in ? rect[s] : 0u;
-    const uint32_t db = in ? __float_as_uint(rec[3 * (size_t)s + 2].w) : 0u;
+    const SplatIn cur = nx;
+    nx.load(count, rect, rec, (uint64_t)b + kBkThreads + threadIdx.x, hi);  // next round in flight
+    const uint32_t db = cur.db;
     PairIter it;
-    it.init(c > 0, r);
+    it.init(cur.c > 0, cur.r);
     while (__ballot(it.more)) {
       const uint32_t t = it.ty * (uint32_t)tiles_x + it.tx;
-      agg_slot<false>(s_cnt, t, it.more, nullptr, nullptr);
+      lds_slot(s_cnt, t, it.more);
       if (it.more) {
         atomicMax(&s_max[t], db);
         atomicMax(&s_minc[t], ~db);
@@ -129,10 +136,11 @@ __global__ __launch_bounds__(kBkThreads) void bucket_count_kernel(
     }
   }
   __syncthreads();
+  // this workgroup's column of the tile-major count matrix; depth ranges by atomics
   for (int t = threadIdx.x; t < n_tiles; t += kBkThreads) {
     const uint32_t c = s_cnt[t];
+    g_cnt[(size_t)t * gridDim.x + blockIdx.x] = c;
     if (c) {
-      atomicAdd(&g_cnt[t], c);
       atomicMax(&g_max[t], s_max[t]);
       atomicMax(&g_minc[t], s_minc[t]);
     }
@@ -140,99 +148,49 @@ __global__ __launch_bounds__(kBkThreads) void bucket_count_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// 2. tile starts (one workgroup): ranges, write cursors, n_pairs, overflow
+// 2. after the exclusive scan of the tile-major count matrix (entry (t, b) is
+// now the first slot of workgroup b in tile t): per-tile ranges
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBkThreads) void bucket_scan_kernel(const uint32_t* __restrict__ g_cnt, int n_tiles,
-                                                                 FrameHdr* hdr, uint32_t max_pairs,
-                                                                 uint32_t* __restrict__ ranges,
-                                                                 uint32_t* __restrict__ cursor) {
-  constexpr int PER = kBucketMaxTiles / kBkThreads;
-  __shared__ uint64_t s_part[kBkThreads];
-  uint32_t c[PER];
-  uint64_t sum = 0;
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int t = threadIdx.x * PER + k;
-    c[k] = t < n_tiles ? g_cnt[t] : 0u;
-    sum += c[k];
-  }
-  s_part[threadIdx.x] = sum;
-  __syncthreads();
-  for (int off = 1; off < kBkThreads; off <<= 1) {
-    const uint64_t a = threadIdx.x >= off ? s_part[threadIdx.x - off] : 0ull;
-    __syncthreads();
-    s_part[threadIdx.x] += a;
-    __syncthreads();
-  }
-  const uint64_t total = s_part[kBkThreads - 1];
-  const bool ok = total <= (uint64_t)max_pairs;
-  uint64_t run = s_part[threadIdx.x] - sum;
-#pragma unroll
-  for (int k = 0; k < PER; ++k) {
-    const int t = threadIdx.x * PER + k;
-    if (t < n_tiles) {
-      ranges[2 * t] = ok ? (uint32_t)run : 0u;
-      ranges[2 * t + 1] = ok ? (uint32_t)(run + c[k]) : 0u;
-      cursor[t] = (uint32_t)run;
-    }
-    run += c[k];
-  }
-  if (threadIdx.x == 0) {
-    hdr->n_pairs = total < 0xffffffffull ? (uint32_t)total : 0xffffffffu;
-    if (!ok) atomicOr(&hdr->overflow, 2u);
-  }
+__global__ void bucket_ranges_kernel(const uint32_t* __restrict__ base, int n_tiles, int blocks,
+                                     const FrameHdr* __restrict__ hdr, uint32_t max_pairs,
+                                     uint32_t* __restrict__ ranges) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const uint32_t n = hdr->n_pairs;
+  const bool ok = n <= max_pairs;
+  ranges[2 * t] = ok ? base[(size_t)t * blocks] : 0u;
+  ranges[2 * t + 1] = ok ? (t + 1 < n_tiles ? base[(size_t)(t + 1) * blocks] : n) : 0u;
 }
 
 // ---------------------------------------------------------------------------
-// 3. scatter K = depth_bits << 32 | s into the tile segments. Per chunk of
-// kBkThreads splats: count per tile in LDS, reserve each touched tile's slots
-// with one global atomic, then hand the reserved slots out.
+// 3. scatter K = depth_bits << 32 | s into the tile segments: workgroup b owns
+// the slots [base(t, b), base(t, b) + count(t, b)) of every tile t and hands
+// them out with LDS counters (the same splat range as in the count kernel).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBkThreads) void bucket_scatter_kernel(
     const uint32_t* __restrict__ count, const uint32_t* __restrict__ rect, const float4* __restrict__ rec,
-    int tiles_x, int n_tiles, const FrameHdr* __restrict__ hdr, uint32_t max_pairs, uint32_t* __restrict__ cursor,
-    uint64_t* __restrict__ items) {
+    int tiles_x, int n_tiles, const FrameHdr* __restrict__ hdr, uint32_t max_pairs,
+    const uint32_t* __restrict__ base, uint64_t* __restrict__ items) {
   extern __shared__ uint32_t s_dyn[];
-  uint32_t* s_cnt = s_dyn;
-  uint16_t* s_touch = reinterpret_cast<uint16_t*>(s_dyn + n_tiles);
-  __shared__ uint32_t s_nt;
+  uint32_t* s_cur = s_dyn;
   if (hdr->n_pairs > max_pairs) return;
-  for (int i = threadIdx.x; i < n_tiles; i += kBkThreads) s_cnt[i] = 0;
-  if (threadIdx.x == 0) s_nt = 0;
+  for (int t = threadIdx.x; t < n_tiles; t += kBkThreads) s_cur[t] = base[(size_t)t * gridDim.x + blockIdx.x];
   __syncthreads();
   uint32_t lo, hi;
   bk_range(hdr->n_splats, lo, hi);
+  SplatIn nx;
+  nx.load(count, rect, rec, (uint64_t)lo + threadIdx.x, hi);
   for (uint32_t b = lo; b < hi; b += kBkThreads) {
-    const uint32_t s = b + threadIdx.x;
-    const bool in = s < hi;
-    const uint32_t c = in ? count[s] : 0u;
-    const uint32_t r = in ? rect[s] : 0u;
-    const uint64_t K = in ? ((uint64_t)__float_as_uint(rec[3 * (size_t)s + 2].w) << 32) | s : 0ull;
-    const bool valid = c > 0;
+    const SplatIn cur = nx;
+    nx.load(count, rect, rec, (uint64_t)b + kBkThreads + threadIdx.x, hi);  // next round in flight
+    const uint64_t K = ((uint64_t)cur.db << 32) | (b + threadIdx.x);
     PairIter it;
-    it.init(valid, r);
-    while (__ballot(it.more)) {  // per-chunk counts
-      agg_slot<true>(s_cnt, it.ty * (uint32_t)tiles_x + it.tx, it.more, s_touch, &s_nt);
-      it.next();
-    }
-    __syncthreads();
-    const uint32_t nt = s_nt;
-    for (uint32_t i = threadIdx.x; i < nt; i += kBkThreads) {
-      const uint32_t t = s_touch[i];
-      s_cnt[t] = atomicAdd(&cursor[t], s_cnt[t]);
-    }
-    __syncthreads();
-    it.init(valid, r);
+    it.init(cur.c > 0, cur.r);
     while (__ballot(it.more)) {
-      const uint32_t pos = agg_slot<false>(s_cnt, it.ty * (uint32_t)tiles_x + it.tx, it.more, nullptr, nullptr);
+      const uint32_t pos = lds_slot(s_cur, it.ty * (uint32_t)tiles_x + it.tx, it.more);
       if (it.more && pos < max_pairs) items[pos] = K;
       it.next();
     }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nt; i += kBkThreads) s_cnt[s_touch[i]] = 0;
-    __syncthreads();
-    if (threadIdx.x == 0) s_nt = 0;
-    __syncthreads();
   }
 }
 
@@ -306,7 +264,7 @@ __global__ __launch_bounds__(kBkThreads) void seg_split_kernel(int level, const 
     uint64_t* dst = e.buf ? keys0 : keys1;
     for (int i = threadIdx.x; i < kSplitBins; i += kBkThreads) s_h[i] = 0;
     __syncthreads();
-    for (uint32_t i0 = 0; i0 < e.len; i0 += kSegCap) {  // kSegItems loads in flight per thread
+    for (uint32_t i0 = 0; i0 < e.len; i0 += kSplitChunk) {  // kSegItems loads in flight per thread
       uint64_t K[kSegItems];
 #pragma unroll
       for (int k = 0; k < kSegItems; ++k) {
@@ -317,7 +275,7 @@ __global__ __launch_bounds__(kBkThreads) void seg_split_kernel(int level, const 
       for (int k = 0; k < kSegItems; ++k) {
         const bool act = i0 + (uint32_t)(k * kBkThreads) + threadIdx.x < e.len;
         const uint32_t bin = act ? (uint32_t)min((K[k] - e.klo) >> sh, (uint64_t)kSplitBins - 1) : 0u;
-        agg_slot<false>(s_h, bin, act, nullptr, nullptr);
+        lds_slot_wave(s_h, bin, act);
       }
     }
     __syncthreads();
@@ -376,7 +334,7 @@ __global__ __launch_bounds__(kBkThreads) void seg_split_kernel(int level, const 
       close((uint32_t)kSplitBins);
     }
     __syncthreads();
-    for (uint32_t i0 = 0; i0 < e.len; i0 += kSegCap) {
+    for (uint32_t i0 = 0; i0 < e.len; i0 += kSplitChunk) {
       uint64_t K[kSegItems];
 #pragma unroll
       for (int k = 0; k < kSegItems; ++k) {
@@ -387,7 +345,7 @@ __global__ __launch_bounds__(kBkThreads) void seg_split_kernel(int level, const 
       for (int k = 0; k < kSegItems; ++k) {
         const bool act = i0 + (uint32_t)(k * kBkThreads) + threadIdx.x < e.len;
         const uint32_t bin = act ? (uint32_t)min((K[k] - e.klo) >> sh, (uint64_t)kSplitBins - 1) : 0u;
-        const uint32_t p = agg_slot<false>(s_pos, bin, act, nullptr, nullptr);
+        const uint32_t p = lds_slot_wave(s_pos, bin, act);
         if (act) dst[e.start + p] = K[k];
       }
     }
@@ -400,7 +358,7 @@ __global__ __launch_bounds__(kBkThreads) void seg_split_kernel(int level, const 
 // digits stably (match over the digit bits inside a wave, per-wave digit
 // counts in LDS) and exchanges the keys through LDS.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t match8(uint32_t d) {
+__device__ __forceinline__ uint64_t match8(uint32_t d) {  // lanes holding the same 8-bit digit
   uint64_t m = ~0ull;
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
@@ -413,7 +371,7 @@ __device__ __forceinline__ uint64_t match8(uint32_t d) {
 
 struct SegSmem {
   uint64_t items[kSegCap];
-  uint16_t whist[kBkWaves * 256];
+  uint16_t whist[kSegWaves * 256];
   uint32_t tot[256];
   uint32_t w;
   uint32_t flag;
@@ -426,7 +384,7 @@ __device__ __forceinline__ uint32_t seg_digit(uint64_t K, uint64_t klo, int shif
 // one stable pass on the digit at `shift` of K - klo
 __device__ void lsd_pass(SegSmem& sm, uint64_t (&K)[kSegItems], uint32_t len, uint64_t klo, int shift) {
   const int lane = bk_lane(), wave = (int)(threadIdx.x >> 6);
-  for (int i = threadIdx.x; i < kBkWaves * 256; i += kBkThreads) sm.whist[i] = 0;
+  for (int i = threadIdx.x; i < kSegWaves * 256; i += kSegThreads) sm.whist[i] = 0;
   __syncthreads();
   uint16_t* wh = sm.whist + wave * 256;
   uint32_t rank[kSegItems];
@@ -451,7 +409,7 @@ __device__ void lsd_pass(SegSmem& sm, uint64_t (&K)[kSegItems], uint32_t len, ui
   if (threadIdx.x < 256) {  // offsets of each wave inside each digit
     uint32_t run = 0;
 #pragma unroll
-    for (int w = 0; w < kBkWaves; ++w) {
+    for (int w = 0; w < kSegWaves; ++w) {
       const uint32_t c = sm.whist[w * 256 + threadIdx.x];
       sm.whist[w * 256 + threadIdx.x] = (uint16_t)run;
       run += c;
@@ -490,7 +448,7 @@ __device__ void lsd_pass(SegSmem& sm, uint64_t (&K)[kSegItems], uint32_t len, ui
   }
 }
 
-__global__ __launch_bounds__(kBkThreads) void seg_sort_kernel(const uint32_t* __restrict__ ranges,
+__global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(const uint32_t* __restrict__ ranges,
                                                               const uint32_t* __restrict__ g_minc,
                                                               const uint32_t* __restrict__ g_max, int n_tiles,
                                                               const FrameHdr* __restrict__ hdr, uint32_t max_pairs,
@@ -538,7 +496,7 @@ __global__ __launch_bounds__(kBkThreads) void seg_sort_kernel(const uint32_t* __
     if (hi_only) {
       // runs of equal (K - klo) >> 32: insertion sort of short runs by one
       // thread each; a run longer than 32 sends the segment to a full sort
-      for (uint32_t i = threadIdx.x; i + 1 < e.len; i += kBkThreads) {
+      for (uint32_t i = threadIdx.x; i + 1 < e.len; i += kSegThreads) {
         const uint64_t hi_i = (sm.items[i] - e.klo) >> 32;
         const bool starts = i == 0 || ((sm.items[i - 1] - e.klo) >> 32) != hi_i;
         if (!starts || ((sm.items[i + 1] - e.klo) >> 32) != hi_i) continue;
@@ -571,7 +529,7 @@ __global__ __launch_bounds__(kBkThreads) void seg_sort_kernel(const uint32_t* __
         __syncthreads();
       }
     }
-    for (uint32_t i = threadIdx.x; i < e.len; i += kBkThreads) vals[e.start + i] = (uint32_t)sm.items[i];
+    for (uint32_t i = threadIdx.x; i < e.len; i += kSegThreads) vals[e.start + i] = (uint32_t)sm.items[i];
   }
 }
 
@@ -589,7 +547,7 @@ __global__ void bucket_keys_kernel(const uint32_t* __restrict__ ranges, const ui
 
 // ---------------------------------------------------------------------------
 hipError_t launch_bucket_count(const uint32_t* count, const uint32_t* rect, const float4* rec, CamDev cam,
-                               const FrameHdr* hdr, uint32_t* region, int grid, hipStream_t st) {
+                               const FrameHdr* hdr, uint32_t* region, uint32_t* counts, hipStream_t st) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   if (n_tiles > kBucketMaxTiles) return hipErrorInvalidValue;
   static bool lds_set[64] = {};
@@ -600,24 +558,24 @@ hipError_t launch_bucket_count(const uint32_t* count, const uint32_t* rect, cons
     if (e != hipSuccess) return e;
     lds_set[dev] = true;
   }
-  bucket_count_kernel<<<grid, kBkThreads, 12 * n_tiles, st>>>(count, rect, rec, cam.tiles_x, n_tiles, hdr,
-                                                              region + kBucketCnt, region + kBucketMinC,
-                                                              region + kBucketMax);
+  bucket_count_kernel<<<kBucketBlocks, kBkThreads, 12 * n_tiles, st>>>(
+      count, rect, rec, cam.tiles_x, n_tiles, hdr, counts, region + kBucketMinC, region + kBucketMax);
   return hipGetLastError();
 }
 
-hipError_t launch_bucket_scan(const uint32_t* region, int n_tiles, FrameHdr* hdr, uint32_t max_pairs,
-                              uint32_t* ranges, uint32_t* cursor, hipStream_t st) {
-  bucket_scan_kernel<<<1, kBkThreads, 0, st>>>(region + kBucketCnt, n_tiles, hdr, max_pairs, ranges, cursor);
+hipError_t launch_bucket_ranges(const uint32_t* base, int n_tiles, const FrameHdr* hdr, uint32_t max_pairs,
+                                uint32_t* ranges, hipStream_t st) {
+  if (n_tiles > 0)
+    bucket_ranges_kernel<<<(n_tiles + 255) / 256, 256, 0, st>>>(base, n_tiles, kBucketBlocks, hdr, max_pairs, ranges);
   return hipGetLastError();
 }
 
 hipError_t launch_bucket_scatter(const uint32_t* count, const uint32_t* rect, const float4* rec, CamDev cam,
-                                 const FrameHdr* hdr, uint32_t max_pairs, uint32_t* cursor, uint64_t* items,
-                                 int grid, hipStream_t st) {
+                                 const FrameHdr* hdr, uint32_t max_pairs, const uint32_t* base, uint64_t* items,
+                                 hipStream_t st) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
-  bucket_scatter_kernel<<<grid, kBkThreads, 6 * n_tiles + 4, st>>>(count, rect, rec, cam.tiles_x, n_tiles, hdr,
-                                                                   max_pairs, cursor, items);
+  bucket_scatter_kernel<<<kBucketBlocks, kBkThreads, 4 * n_tiles, st>>>(count, rect, rec, cam.tiles_x, n_tiles, hdr,
+                                                                       max_pairs, base, items);
   return hipGetLastError();
 }
 
@@ -630,7 +588,7 @@ hipError_t launch_seg_sort(const uint32_t* ranges, const uint32_t* region, int n
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  seg_sort_kernel<<<grid, kBkThreads, 0, st>>>(ranges, region + kBucketMinC, region + kBucketMax, n_tiles, hdr,
+  seg_sort_kernel<<<grid, kSegThreads, 0, st>>>(ranges, region + kBucketMinC, region + kBucketMax, n_tiles, hdr,
                                                max_pairs, keys0, keys1, lists, vals);
   return hipGetLastError();
 }

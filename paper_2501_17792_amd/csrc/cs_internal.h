@@ -176,9 +176,12 @@ hipError_t launch_view_psnr(const int64_t* views, int n_inst, const float* ref, 
 // ---- tile-bucket sort -----------------------------------------------------
 constexpr int kBucketMaxTiles = 8192;  // frames with more tiles use the LSD radix sort
 constexpr int kSplitLevels = 7;        // 8-bit splits: 63 key bits down to the LDS capacity
-constexpr int kSegCap = 16384;         // keys one workgroup sorts in LDS
+#ifndef CS_SEG_THREADS
+#define CS_SEG_THREADS 1024
+#endif
+constexpr int kSegThreads = CS_SEG_THREADS;  // threads of the LDS segment sort
+constexpr int kSegCap = kSegThreads * 16;    // keys one workgroup sorts in LDS
 // u32 offsets inside the bucket region of the per-frame cleared counter buffer
-constexpr int kBucketCnt = 0;                        // [tiles] pairs per tile
 constexpr int kBucketMinC = kBucketMaxTiles;         // [tiles] ~(min depth bits)
 constexpr int kBucketMax = 2 * kBucketMaxTiles;      // [tiles] max depth bits
 constexpr int kBucketCtr = 3 * kBucketMaxTiles;      // counters below
@@ -202,13 +205,16 @@ struct SegLists {
   uint32_t cap_base, cap_big;
 };
 
+constexpr int kBucketBlocks = 512;  // workgroups of the count and scatter kernels (columns of the count matrix)
 hipError_t launch_bucket_count(const uint32_t* count, const uint32_t* rect, const float4* rec, CamDev cam,
-                               const FrameHdr* hdr, uint32_t* region, int grid, hipStream_t st);
-hipError_t launch_bucket_scan(const uint32_t* region, int n_tiles, FrameHdr* hdr, uint32_t max_pairs,
-                              uint32_t* ranges, uint32_t* cursor, hipStream_t st);
+                               const FrameHdr* hdr, uint32_t* region, uint32_t* counts, hipStream_t st);
+hipError_t launch_bucket_ranges(const uint32_t* base, int n_tiles, const FrameHdr* hdr, uint32_t max_pairs,
+                                uint32_t* ranges, hipStream_t st);
 hipError_t launch_bucket_scatter(const uint32_t* count, const uint32_t* rect, const float4* rec, CamDev cam,
-                                 const FrameHdr* hdr, uint32_t max_pairs, uint32_t* cursor, uint64_t* items,
-                                 int grid, hipStream_t st);
+                                 const FrameHdr* hdr, uint32_t max_pairs, const uint32_t* base, uint64_t* items,
+                                 hipStream_t st);
+hipError_t launch_scan_total(uint32_t* data, uint32_t n, uint32_t* block_sums, uint32_t* total_out, FrameHdr* hdr,
+                             uint32_t max_total, hipStream_t st);
 hipError_t launch_seg_sort(const uint32_t* ranges, const uint32_t* region, int n_tiles, FrameHdr* hdr,
                            uint32_t max_pairs, uint64_t* keys0, uint64_t* keys1, SegLists lists, uint32_t* vals,
                            int grid, hipStream_t st);

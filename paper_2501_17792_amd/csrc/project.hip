@@ -6,6 +6,63 @@
 
 namespace cs {
 
+// The Gaussians of one chunk; DEG is the template's SH degree (a compile-time
+// constant so that every SH plane load of a Gaussian is issued at once).
+template <int DEG>
+__device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOut& skinned, int fused,
+                                                  const CamDev& cam, const SplatOut& out, const TemplateDev& T,
+                                                  const float* s_bones, const float Ry[9], const Chunk ch,
+                                                  uint32_t base, int n_here) {
+  uint32_t vis = 0;
+  for (int k = threadIdx.x; k < n_here; k += kChunkThreads) {
+    const int g = ch.g0 + k;
+    const size_t s = (size_t)base + g;
+    Posed p;
+    const float4 mi = T.mean_idx[g];
+    const float4 wt = T.skin_w[g];
+    if (fused) {
+      skin_gaussian(s_bones, mi, wt, T.cov_a[g], T.cov_b[g], w.skin_mode, Ry, p);
+    } else {
+      const float4 m = skinned.mu[s];
+      const float4 cv = skinned.cov[s];
+      p.mu[0] = m.x; p.mu[1] = m.y; p.mu[2] = m.z;
+      p.cov[0] = m.w; p.cov[1] = cv.x; p.cov[2] = cv.y; p.cov[3] = cv.z; p.cov[4] = cv.w;
+      p.cov[5] = skinned.cov_zz[s];
+      if (w.skin_mode) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) p.L[e] = Ry[e];
+      } else {
+        float M[12];
+        blend_bones(s_bones, __float_as_uint(mi.w), wt, M);
+        p.L[0] = M[0]; p.L[1] = M[1]; p.L[2] = M[2];
+        p.L[3] = M[4]; p.L[4] = M[5]; p.L[5] = M[6];
+        p.L[6] = M[8]; p.L[7] = M[9]; p.L[8] = M[10];
+      }
+    }
+    SplatRec r;
+    project_gaussian<DEG>(p, T.opacity[g], T.sh + g, T.n, cam, r);
+    if (w.crop && r.count) {  // view mode: keep the tiles inside the instance's window
+      const int4 cw = w.crop[ch.inst];
+      const int x0 = max((int)(r.rect & 0xffu), cw.x), y0 = max((int)((r.rect >> 8) & 0xffu), cw.y);
+      const int x1 = min((int)((r.rect >> 16) & 0xffu), cw.z - 1), y1 = min((int)(r.rect >> 24), cw.w - 1);
+      if (x1 < x0 || y1 < y0) {
+        r.count = 0u;
+        r.rect = 0u;
+      } else {
+        r.rect = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) | ((uint32_t)y1 << 24);
+        r.count = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+      }
+    }
+    out.rec[3 * s + 0] = r.r0;
+    out.rec[3 * s + 1] = r.r1;
+    out.rec[3 * s + 2] = r.r2;
+    out.rect[s] = r.rect;
+    out.count[s] = r.count;
+    vis += r.count ? 1u : 0u;
+  }
+  return vis;
+}
+
 // One block iteration per chunk (one instance, up to kChunk Gaussians). The
 // bone matrices are staged in LDS: in fused mode the Gaussian is skinned
 // here (bit-identical to the skin kernel); otherwise the posed mean and
@@ -29,52 +86,12 @@ __global__ __launch_bounds__(kChunkThreads) void project_kernel(WorkDev w, SkinO
     yaw_rotation(in.yaw, Ry);
     const uint32_t base = w.offset[ch.inst];
     const int n_here = min(kChunk, (int)(w.offset[ch.inst + 1] - base) - ch.g0);
-    uint32_t vis = 0;
-    for (int k = threadIdx.x; k < n_here; k += kChunkThreads) {
-      const int g = ch.g0 + k;
-      const size_t s = (size_t)base + g;
-      Posed p;
-      const float4 mi = T.mean_idx[g];
-      const float4 wt = T.skin_w[g];
-      if (fused) {
-        skin_gaussian(s_bones, mi, wt, T.cov_a[g], T.cov_b[g], w.skin_mode, Ry, p);
-      } else {
-        const float4 m = skinned.mu[s];
-        const float4 cv = skinned.cov[s];
-        p.mu[0] = m.x; p.mu[1] = m.y; p.mu[2] = m.z;
-        p.cov[0] = m.w; p.cov[1] = cv.x; p.cov[2] = cv.y; p.cov[3] = cv.z; p.cov[4] = cv.w;
-        p.cov[5] = skinned.cov_zz[s];
-        if (w.skin_mode) {
-#pragma unroll
-          for (int e = 0; e < 9; ++e) p.L[e] = Ry[e];
-        } else {
-          float M[12];
-          blend_bones(s_bones, __float_as_uint(mi.w), wt, M);
-          p.L[0] = M[0]; p.L[1] = M[1]; p.L[2] = M[2];
-          p.L[3] = M[4]; p.L[4] = M[5]; p.L[5] = M[6];
-          p.L[6] = M[8]; p.L[7] = M[9]; p.L[8] = M[10];
-        }
-      }
-      SplatRec r;
-      project_gaussian(p, T.opacity[g], T.sh + g, T.n, T.n_sh4, T.sh_degree, cam, r);
-      if (w.crop && r.count) {  // view mode: keep the tiles inside the instance's window
-        const int4 cw = w.crop[ch.inst];
-        const int x0 = max((int)(r.rect & 0xffu), cw.x), y0 = max((int)((r.rect >> 8) & 0xffu), cw.y);
-        const int x1 = min((int)((r.rect >> 16) & 0xffu), cw.z - 1), y1 = min((int)(r.rect >> 24), cw.w - 1);
-        if (x1 < x0 || y1 < y0) {
-          r.count = 0u;
-          r.rect = 0u;
-        } else {
-          r.rect = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) | ((uint32_t)y1 << 24);
-          r.count = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
-        }
-      }
-      out.rec[3 * s + 0] = r.r0;
-      out.rec[3 * s + 1] = r.r1;
-      out.rec[3 * s + 2] = r.r2;
-      out.rect[s] = r.rect;
-      out.count[s] = r.count;
-      vis += r.count ? 1u : 0u;
+    uint32_t vis;
+    switch (T.sh_degree) {
+      case 0: vis = project_chunk<0>(w, skinned, fused, cam, out, T, s_bones, Ry, ch, base, n_here); break;
+      case 1: vis = project_chunk<1>(w, skinned, fused, cam, out, T, s_bones, Ry, ch, base, n_here); break;
+      case 2: vis = project_chunk<2>(w, skinned, fused, cam, out, T, s_bones, Ry, ch, base, n_here); break;
+      default: vis = project_chunk<3>(w, skinned, fused, cam, out, T, s_bones, Ry, ch, base, n_here); break;
     }
     atomicAdd(&s_vis, vis);
     __syncthreads();
@@ -211,6 +228,18 @@ hipError_t launch_scan_inplace(uint32_t* data, uint32_t n, uint32_t* block_sums,
   if (blocks <= 0) return hipSuccess;
   scan_reduce_kernel<<<blocks, kScanThreads, 0, st>>>(data, block_sums, nullptr, n);
   scan_sums_kernel<<<1, 1024, 0, st>>>(block_sums, nullptr, n, nullptr, nullptr, 0u);
+  scan_down_kernel<<<blocks, kScanThreads, 0, st>>>(data, block_sums, data, nullptr, n);
+  return hipGetLastError();
+}
+
+// in-place exclusive scan of n values; the total goes to *total_out and sets
+// bit 1 of hdr->overflow when it exceeds max_total
+hipError_t launch_scan_total(uint32_t* data, uint32_t n, uint32_t* block_sums, uint32_t* total_out, FrameHdr* hdr,
+                             uint32_t max_total, hipStream_t st) {
+  const int blocks = (int)((n + kScanTile - 1) / kScanTile);
+  if (blocks <= 0) return hipSuccess;
+  scan_reduce_kernel<<<blocks, kScanThreads, 0, st>>>(data, block_sums, nullptr, n);
+  scan_sums_kernel<<<1, 1024, 0, st>>>(block_sums, nullptr, n, total_out, hdr, max_total);
   scan_down_kernel<<<blocks, kScanThreads, 0, st>>>(data, block_sums, data, nullptr, n);
   return hipGetLastError();
 }

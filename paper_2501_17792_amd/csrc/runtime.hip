@@ -97,7 +97,8 @@ struct cs_ctx {
   uint32_t* rts_sums = nullptr;
   int64_t cap_tiles = 0;
   uint32_t* ranges = nullptr;
-  uint32_t* cursor = nullptr;        // [kBucketMaxTiles] tile write cursors (tile-bucket sort)
+  uint32_t* bk_counts = nullptr;     // [kBucketMaxTiles][kBucketBlocks] pair counts, then first slots
+  uint32_t* bk_sums = nullptr;       // block sums of their scan
   SegEntry* seg_base = nullptr;      // key segments sorted in LDS
   SegEntry* seg_big[2] = {nullptr, nullptr};  // key segments to split
   int64_t cap_seg_base = 0, cap_seg_big = 0;
@@ -356,7 +357,8 @@ cs_status cs_create(int32_t device, void* stream, const cs_options* opt, cs_ctx*
   ctx->opt = o;
   cs_status s = dalloc(ctx, &ctx->hdr, 1);
   if (s == CS_OK) s = dalloc(ctx, &ctx->hist, kHistLen);
-  if (s == CS_OK) s = dalloc(ctx, &ctx->cursor, kBucketMaxTiles);
+  if (s == CS_OK) s = dalloc(ctx, &ctx->bk_counts, (size_t)kBucketMaxTiles * kBucketBlocks);
+  if (s == CS_OK) s = dalloc(ctx, &ctx->bk_sums, (size_t)kBucketMaxTiles * kBucketBlocks / scan_tile() + 2);
   if (s == CS_OK) s = dalloc(ctx, &ctx->n_dev, 1);
   if (s == CS_OK) s = dalloc(ctx, &ctx->rts_counts, (size_t)kRtsBlocks * kSortBins);
   if (s == CS_OK) s = dalloc(ctx, &ctx->rts_sums, (size_t)kRtsBlocks * kSortBins / 4096 + 2);
@@ -421,7 +423,8 @@ void cs_destroy(cs_ctx* ctx) {
   }
   dfree(&ctx->lookback);
   dfree(&ctx->hist);
-  dfree(&ctx->cursor);
+  dfree(&ctx->bk_counts);
+  dfree(&ctx->bk_sums);
   dfree(&ctx->seg_base);
   dfree(&ctx->seg_big[0]);
   dfree(&ctx->seg_big[1]);
@@ -669,7 +672,6 @@ cs_status cs_skin_instances(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst
   return CS_OK;
 }
 
-constexpr int kBucketGrid = 512;  // workgroups of the tile-bucket count and scatter kernels
 constexpr int kSegGrid = 512;     // workgroups of the split and LDS sort kernels
 
 static cs_status lsd_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles, const ViewDev* vp);
@@ -679,10 +681,12 @@ static cs_status lsd_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles, const 
 static cs_status bucket_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles) {
   uint32_t* region = ctx->hist + kMaxPasses * kSortBins;
   uint32_t cap_p = (uint32_t)std::min<int64_t>(ctx->cap_pairs, kMaxPairsLimit);
+  const uint32_t max_p = ctx->capturing ? cap_p : kMaxPairsLimit;
   ctx->mark(CS_STAGE_EMIT, 0);
-  HIP_TRY(launch_bucket_count(ctx->cnt, ctx->rect, ctx->rec, cd, ctx->hdr, region, kBucketGrid, ctx->stream));
-  HIP_TRY(launch_bucket_scan(region, n_tiles, ctx->hdr, ctx->capturing ? cap_p : kMaxPairsLimit, ctx->ranges,
-                             ctx->cursor, ctx->stream));
+  HIP_TRY(launch_bucket_count(ctx->cnt, ctx->rect, ctx->rec, cd, ctx->hdr, region, ctx->bk_counts, ctx->stream));
+  HIP_TRY(launch_scan_total(ctx->bk_counts, (uint32_t)n_tiles * kBucketBlocks, ctx->bk_sums, &ctx->hdr->n_pairs,
+                            ctx->hdr, max_p, ctx->stream));
+  HIP_TRY(launch_bucket_ranges(ctx->bk_counts, n_tiles, ctx->hdr, max_p, ctx->ranges, ctx->stream));
   if (!ctx->capturing) {
     CS_TRY(read_header(ctx));
     const int64_t n_pairs = ctx->hdr_host->n_pairs;
@@ -692,8 +696,8 @@ static cs_status bucket_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles) {
     }
     cap_p = (uint32_t)std::min<int64_t>(ctx->cap_pairs, kMaxPairsLimit);
   }
-  HIP_TRY(launch_bucket_scatter(ctx->cnt, ctx->rect, ctx->rec, cd, ctx->hdr, cap_p, ctx->cursor, ctx->keys[0],
-                                kBucketGrid, ctx->stream));
+  HIP_TRY(launch_bucket_scatter(ctx->cnt, ctx->rect, ctx->rec, cd, ctx->hdr, cap_p, ctx->bk_counts, ctx->keys[0],
+                                ctx->stream));
   ctx->mark(CS_STAGE_EMIT, 1);
   ctx->mark(CS_STAGE_SORT, 0);
   SegLists lists{};

@@ -86,26 +86,29 @@ __device__ __forceinline__ void skin_gaussian(const float* __restrict__ bones, f
 // Real orthonormal SH basis (no Condon-Shortley phase, polar axis +z) at a
 // unit direction, evaluated against [(deg+1)^2][3] coefficients read from
 // float4 planes (plane j holds flattened coefficients 4j..4j+3).
-__device__ __forceinline__ void sh_colour(const float4* __restrict__ planes, int stride, int n_sh4,
-                                          int deg, float x, float y, float z, float rgb[3]) {
-  float Y[16];
+template <int DEG>
+__device__ __forceinline__ void sh_colour(const float4* __restrict__ planes, int stride, float x, float y,
+                                          float z, float rgb[3]) {
+  constexpr int NB = (DEG + 1) * (DEG + 1);  // basis functions
+  constexpr int N4 = (3 * NB + 3) / 4;       // float4 planes of the 3*NB coefficients
+  float4 v[N4];
+#pragma unroll
+  for (int j = 0; j < N4; ++j) v[j] = planes[(size_t)j * stride];  // every plane in flight at once
+  float Y[NB];
   Y[0] = 0.28209479177387814f;
-  int nb = 1;
-  if (deg >= 1) {
+  if constexpr (DEG >= 1) {
     Y[1] = 0.4886025119029199f * y;
     Y[2] = 0.4886025119029199f * z;
     Y[3] = 0.4886025119029199f * x;
-    nb = 4;
   }
-  if (deg >= 2) {
+  if constexpr (DEG >= 2) {
     const float xx = x * x, yy = y * y, zz = z * z;
     Y[4] = 1.0925484305920792f * (x * y);
     Y[5] = 1.0925484305920792f * (y * z);
     Y[6] = 0.31539156525252005f * fmaf(3.f, zz, -1.f);
     Y[7] = 1.0925484305920792f * (x * z);
     Y[8] = 0.5462742152960396f * (xx - yy);
-    nb = 9;
-    if (deg >= 3) {
+    if constexpr (DEG >= 3) {
       Y[9] = 0.5900435899266435f * y * fmaf(3.f, xx, -yy);
       Y[10] = 2.890611442640554f * (x * y) * z;
       Y[11] = 0.4570457994644658f * y * fmaf(5.f, zz, -1.f);
@@ -113,19 +116,18 @@ __device__ __forceinline__ void sh_colour(const float4* __restrict__ planes, int
       Y[13] = 0.4570457994644658f * x * fmaf(5.f, zz, -1.f);
       Y[14] = 1.445305721320277f * z * (xx - yy);
       Y[15] = 0.5900435899266435f * x * fmaf(-3.f, yy, xx);
-      nb = 16;
     }
   }
   float acc[3] = {0.f, 0.f, 0.f};
   // coefficient q = 3k + c lives in plane q/4, lane q%4
-  for (int j = 0; j < n_sh4; ++j) {
-    const float4 v = planes[(size_t)j * stride];
-    const float e[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int j = 0; j < N4; ++j) {
+    const float e[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
       const int q = 4 * j + l;
       const int k = q / 3;
-      if (k < nb) acc[q - 3 * k] = fmaf(e[l], Y[k], acc[q - 3 * k]);
+      if (k < NB) acc[q - 3 * k] = fmaf(e[l], Y[k], acc[q - 3 * k]);
     }
   }
   rgb[0] = fmaxf(0.f, 0.5f + acc[0]);
@@ -140,9 +142,10 @@ struct SplatRec {
 };
 
 // EWA projection + colour + footprint of one posed Gaussian. count = 0 means culled.
+template <int DEG>
 __device__ __forceinline__ void project_gaussian(const Posed& p, float opacity,
                                                  const float4* __restrict__ sh_planes, int sh_stride,
-                                                 int n_sh4, int deg, const CamDev& cam, SplatRec& out) {
+                                                 const CamDev& cam, SplatRec& out) {
   out.count = 0u;
   out.rect = 0u;
   out.r0 = out.r1 = out.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -194,7 +197,7 @@ __device__ __forceinline__ void project_gaussian(const Posed& p, float opacity,
   const float inv = 1.f / sqrtf(fmaf(d0, d0, fmaf(d1, d1, d2 * d2)));
   d0 *= inv; d1 *= inv; d2 *= inv;
   float rgb[3];
-  sh_colour(sh_planes, sh_stride, n_sh4, deg, d0, d1, d2, rgb);
+  sh_colour<DEG>(sh_planes, sh_stride, d0, d1, d2, rgb);
   out.r0 = make_float4(u, v, c / det, -b / det);
   out.r1 = make_float4(a / det, opacity, rgb[0], rgb[1]);
   out.r2 = make_float4(rgb[2], rx, ry, tz);
