@@ -37,23 +37,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def algorithmic_bytes(stage, st, scene, passes, uniq):
-    """Algorithmic HBM bytes of one launch of a stage."""
+def algorithmic_bytes(stage, st, scene, uniq):
+    """Algorithmic HBM bytes of one frame's pass through a stage (the byte
+    model is stated per stage in the design doc): N splats, P tile pairs, U unique
+    template Gaussians drawn this frame."""
     n, p = float(st["n_splats"]), float(st["n_pairs"])
     W, H = scene.camera.width, scene.camera.height
     sh_bytes = 16 * 12  # SH3: 48 floats per Gaussian
-    if stage == "skin":
+    if stage == "skin":  # template geometry in, posed mean + covariance out
         return 36 * n + 56 * uniq
-    if stage == "project_fused":
+    if stage == "project_fused":  # template in, record + rect + count out
         return 56 * n + (56 + 4 + sh_bytes) * uniq
-    if stage == "project":
+    if stage == "project":  # posed Gaussians + template appearance in, record out
         return (36 + 56) * n + (32 + 4 + sh_bytes) * uniq
-    if stage == "sort":  # one pass
-        return 24 * p
-    if stage == "emit":
-        return 16 * n + 12 * p
-    if stage == "scan":
-        return 12 * n
+    if stage == "emit":  # tile-bucket binning: count + scatter read 12 B/splat each, 8 B per pair out
+        return 24 * n + 8 * p
+    if stage == "sort":  # per-tile depth order: every pair's key in, its splat index out
+        return 12 * p
     if stage == "blend":
         return 52 * p + 12 * W * H
     return 0.0
@@ -168,6 +168,7 @@ def main():
     ap.add_argument("--instances", type=int, default=3500)
     ap.add_argument("--net", default=os.path.join(ROOT, "paper_2501_17792_amd", "lod_net.npz"))
     ap.add_argument("--tile", default="auto", help="WxH or 'auto' (autotuned per run)")
+    ap.add_argument("--modes", default="", help="comma list of LoD modes to time (default: all)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1",
@@ -195,6 +196,9 @@ def main():
             modes["learned"] = (cs.CS_LOD_LEARNED, (), net_dev.data_ptr(), netinfo["margin"])
             modes["fixed_tuned"] = (cs.CS_LOD_FIXED, tuple(netinfo["thresholds"]), 0, 0.0)
     head = "learned" if "learned" in modes else "fixed_10_25m"
+    if args.modes:  # timing a subset (e.g. for a profiler run); the headline mode is always kept
+        keep = set(args.modes.split(",")) | {head}
+        modes = {k: v for k, v in modes.items() if k in keep}
     tile_timing = None
     if args.tile == "auto":
         from paper_2501_17792_amd import autotune
@@ -220,48 +224,53 @@ def main():
     n_splats, n_pairs = int(st0.n_splats), int(st0.n_pairs)
     lod_head = modes[head]
 
-    # ---- per-stage timing: unfused kernels, eager frames, HIP events on the launch stream
-    with torch.cuda.stream(stream):
-        rp = cs.Renderer(0, stream=stream, fuse=False, profile=True, tile=tile)
-        rp.upload_templates(scene.templates)
-        rp.set_crowd(scene.crowd)
-        lvl_out = torch.zeros(scene.crowd.n, dtype=torch.int32, device=dev)
-        acc = {}
-        for k in range(args.stage_frames + 1):
-            rp.pose_dev.copy_(poses_all[k % 300])
-            rp.select_lod(scene.camera, lod_head[0], lod_head[1], level_out=lvl_out, mlp_ptr=lod_head[2],
-                          margin=lod_head[3])
-            rp.skin()
-            rp.render(scene.camera, img, stats=True)
-            t = rp.stage_times()
-            if k > 0:
-                for name, v in t.items():
-                    acc.setdefault(name, []).append(v)
-        stream.synchronize()
-        levels = lvl_out.cpu().numpy().astype(np.int64)
-        stp = rp.last_stats
-        rp.close()
-    stage_ms = {k: float(np.mean(v)) for k, v in acc.items()}
+    # ---- per-stage timing: eager frames, HIP events on the launch stream around
+    # each stage. The first pass uses the timed configuration (skinning fused
+    # into projection); the second separates skinning from projection.
+    def stage_profile(fuse):
+        with torch.cuda.stream(stream):
+            rp = cs.Renderer(0, stream=stream, fuse=fuse, profile=True, tile=tile)
+            rp.upload_templates(scene.templates)
+            rp.set_crowd(scene.crowd)
+            lvl_out = torch.zeros(scene.crowd.n, dtype=torch.int32, device=dev)
+            acc = {}
+            for k in range(args.stage_frames + 1):
+                rp.pose_dev.copy_(poses_all[k % 300])
+                rp.select_lod(scene.camera, lod_head[0], lod_head[1], level_out=lvl_out, mlp_ptr=lod_head[2],
+                              margin=lod_head[3])
+                rp.skin()
+                rp.render(scene.camera, img, stats=True)
+                t = rp.stage_times()
+                if k > 0:
+                    for name, v in t.items():
+                        acc.setdefault(name, []).append(v)
+            stream.synchronize()
+            stp = rp.last_stats
+            rp.close()
+        return {k: float(np.mean(v)) for k, v in acc.items()}, lvl_out.cpu().numpy().astype(np.int64), stp
+
+    stage_ms, levels, stp = stage_profile(True)
+    stage_unfused, _, _ = stage_profile(False)
     uniq = unique_template_gaussians(scene, levels)
     stats = dict(n_splats=int(stp.n_splats), n_pairs=int(stp.n_pairs))
-    n_tiles = ((scene.camera.width + tile[0] - 1) // tile[0]) * ((scene.camera.height + tile[1] - 1) // tile[1])
-    tile_bits = max(1, int(np.ceil(np.log2(n_tiles))))
-    passes = (31 + tile_bits + 10) // 11
+    stage_ms = {("project_fused" if k == "project" else k): v for k, v in stage_ms.items()}
+    stage_ms["skin"] = stage_unfused.get("skin", 0.0)
+    stage_ms["project"] = stage_unfused.get("project", 0.0)
     stage_gbs = {}
-    for name, launches in (("skin", 1), ("project", 1), ("scan", 1), ("emit", 1), ("sort", passes)):
-        if name in stage_ms and stage_ms[name] > 0:
-            b = algorithmic_bytes(name, stats, scene, passes, uniq) * launches
-            stage_gbs[name] = b / (stage_ms[name] * 1e-3) / 1e9
-    hbm_stages = {k: v for k, v in stage_ms.items() if k in ("skin", "project", "sort", "emit", "scan")}
+    for name in ("skin", "project", "project_fused", "emit", "sort", "blend"):
+        if stage_ms.get(name, 0.0) > 0:
+            stage_gbs[name] = algorithmic_bytes(name, stats, scene, uniq) / (stage_ms[name] * 1e-3) / 1e9
+    # the dominant memory-bound stage of the timed (fused) frame
+    hbm_stages = {k: stage_ms[k] for k in ("project_fused", "emit", "sort") if k in stage_ms}
     dom = max(hbm_stages, key=hbm_stages.get)
-    launches = passes if dom == "sort" else 1
-    per_launch_ms = stage_ms[dom] / launches
-    per_launch_bytes = algorithmic_bytes(dom, stats, scene, passes, uniq)
+    per_launch_ms = stage_ms[dom]
+    per_launch_bytes = algorithmic_bytes(dom, stats, scene, uniq)
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": {"sort": "onesweep_kernel", "project": "project_kernel", "skin": "skin_kernel",
-                           "emit": "emit_kernel", "scan": "scan kernels"}[dom],
+                "kernel": {"project_fused": "project_kernel (skinning fused)",
+                           "emit": "bucket_count_kernel + bucket_scatter_kernel",
+                           "sort": "seg_split_kernel + seg_sort_kernel"}[dom],
                 "launch_ms": round(per_launch_ms, 4), "bytes_per_launch": int(per_launch_bytes)}
 
     # ---- full detail (every instance at level 0): FPS and the reference frame for PSNR

@@ -31,7 +31,7 @@ constexpr int kSegWaves = kSegThreads / 64;
 constexpr int kSplitChunk = kBkThreads * kSegItems;  // keys one split workgroup loads at a time
 static_assert(kSegThreads * kSegItems == kSegCap, "LDS segment capacity");
 static_assert(kSegThreads >= 256, "digit scans need 256 threads");
-constexpr int kSplitBits = 8;
+constexpr int kSplitBits = 11;
 constexpr int kSplitBins = 1 << kSplitBits;
 
 __device__ __forceinline__ int bk_lane() { return (int)(threadIdx.x & 63); }
@@ -235,9 +235,39 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
   return v;
 }
 
+// Exclusive scans over the workgroup's threads (thread order), through the
+// waves' inclusive scans and a scan of the wave totals.
+template <class Op>
+__device__ __forceinline__ int block_excl_scan(int v, int* s_red, Op op, int identity) {
+  const int lane = bk_lane(), wave = (int)(threadIdx.x >> 6);
+  int inc = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int a = __shfl_up(inc, o);
+    if (lane >= o) inc = op(inc, a);
+  }
+  __syncthreads();  // s_red may still be read by a previous scan
+  if (lane == 63) s_red[wave] = inc;
+  __syncthreads();
+  int before = identity;
+  for (int w = 0; w < wave; ++w) before = op(before, s_red[w]);
+  int excl = __shfl_up(inc, 1);
+  if (lane == 0) excl = identity;
+  return op(before, excl);
+}
+
+__device__ __forceinline__ uint32_t block_excl_scan_sum(uint32_t v, int* s_red) {
+  return (uint32_t)block_excl_scan((int)v, s_red, [](int a, int b) { return a + b; }, 0);
+}
+
+__device__ __forceinline__ int block_excl_scan_max(int v, int* s_red) {
+  return block_excl_scan(v, s_red, [](int a, int b) { return a > b ? a : b; }, -1);
+}
+
 // ---------------------------------------------------------------------------
 // 4. split one level: every segment longer than kSegCap is partitioned by the
-// top 8 of its dbits bits into up to 256 sub-segments in the other buffer.
+// top kSplitBits of its dbits bits, bins packed into sub-segments, into the
+// other buffer.
 // Level 0 reads the tiles, level L > 0 the big list of level L.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBkThreads) void seg_split_kernel(int level, const uint32_t* __restrict__ ranges,
@@ -247,7 +277,10 @@ __global__ __launch_bounds__(kBkThreads) void seg_split_kernel(int level, const 
                                                                uint64_t* keys1, SegLists lists) {
   __shared__ uint32_t s_h[kSplitBins];
   __shared__ uint32_t s_pos[kSplitBins];
-  __shared__ uint32_t s_w;
+  __shared__ uint16_t s_lead[kSplitBins];
+  __shared__ uint32_t s_last[kSplitBins];
+  __shared__ int s_red[kBkWaves + 1];
+  __shared__ uint32_t s_w, s_ngroups;
   if (hdr->n_pairs > max_pairs) return;
   uint32_t* ctr = lists.counters;
   const uint32_t n_work = level == 0 ? (uint32_t)n_tiles : min(ctr[kCtrBig + level], lists.cap_big);
@@ -258,11 +291,17 @@ __global__ __launch_bounds__(kBkThreads) void seg_split_kernel(int level, const 
     SegEntry e;
     if (level == 0) tile_segment((int)w, ranges, g_minc, g_max, e);
     else e = in_list[w];
-    if (e.len <= (uint32_t)kSegCap) continue;  // uniform over the workgroup
+    if (e.len <= (uint32_t)kSegCap) {  // uniform over the workgroup
+      if (level == 0 && e.len > 0 && threadIdx.x == 0) push_entry(lists.base, &ctr[kCtrBase], lists.cap_base, e, hdr);
+      continue;
+    }
     const int sh = (int)e.dbits - kSplitBits;  // len > 2^14 keys imply dbits >= 15
     const uint64_t* src = e.buf ? keys1 : keys0;
     uint64_t* dst = e.buf ? keys0 : keys1;
-    for (int i = threadIdx.x; i < kSplitBins; i += kBkThreads) s_h[i] = 0;
+    for (int i = threadIdx.x; i < kSplitBins; i += kBkThreads) {
+      s_h[i] = 0;
+      s_last[i] = 0;
+    }
     __syncthreads();
     for (uint32_t i0 = 0; i0 < e.len; i0 += kSplitChunk) {  // kSegItems loads in flight per thread
       uint64_t K[kSegItems];
@@ -279,59 +318,71 @@ __global__ __launch_bounds__(kBkThreads) void seg_split_kernel(int level, const 
       }
     }
     __syncthreads();
-    if (threadIdx.x < 64) {  // exclusive scan of the 256 bins, 4 per lane
-      uint32_t v[4], sum = 0;
+    // Group consecutive bins into sub-segments of at most kSegCap keys: a bin
+    // of more than H = kSegCap / 2 keys is a group of its own; the others
+    // group by floor(first key index / H), so a group holds < 2H keys. The
+    // group id (even for those, odd for the large bins) grows along the bins.
+    constexpr int BPT = kSplitBins / kBkThreads;  // bins per thread
+    constexpr uint32_t H = kSegCap / 2;
+    uint32_t c[BPT], sum = 0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        v[j] = s_h[4 * threadIdx.x + j];
-        sum += v[j];
-      }
-      uint32_t run = wave_incl_scan(sum) - sum;
+    for (int j = 0; j < BPT; ++j) {
+      c[j] = s_h[BPT * threadIdx.x + j];
+      sum += c[j];
+    }
+    uint32_t run = block_excl_scan_sum(sum, s_red);
+    int gid[BPT];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        s_pos[4 * threadIdx.x + j] = run;
-        run += v[j];
+    for (int j = 0; j < BPT; ++j) {
+      s_pos[BPT * threadIdx.x + j] = run;
+      gid[j] = c[j] == 0 ? -1 : 2 * (int)(run / H) + (c[j] > H ? 1 : 0);
+      run += c[j];
+    }
+    // a non-empty bin starts a group when its id differs from that of the
+    // last non-empty bin before it (ids only grow: an exclusive max-scan)
+    int gmax = -1;
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) gmax = max(gmax, gid[j]);
+    const int prev0 = block_excl_scan_max(gmax, s_red);
+    int prev = prev0;
+    uint32_t starts = 0;
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      const bool st = gid[j] >= 0 && gid[j] != prev;
+      starts += st ? 1u : 0u;
+      if (gid[j] >= 0) prev = gid[j];
+    }
+    uint32_t ord = block_excl_scan_sum(starts, s_red);
+    prev = prev0;
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      if (gid[j] >= 0 && gid[j] != prev) s_lead[ord++] = (uint16_t)(BPT * threadIdx.x + j);
+      if (gid[j] >= 0) {
+        prev = gid[j];
+        atomicMax(&s_last[ord - 1], (uint32_t)(BPT * threadIdx.x + j));  // last non-empty bin of the group
       }
     }
+    if (threadIdx.x == kBkThreads - 1) s_ngroups = ord;
     __syncthreads();
-    if (threadIdx.x == 0) {
-      // Consecutive bins are packed into sub-segments of at most kSegCap keys
-      // (key order is bin order); a bin above kSegCap alone is split again.
-      uint32_t g0 = 0, acc = 0;  // first bin and key count of the open group
-      auto close = [&](uint32_t b_end) {  // bins [g0, b_end)
-        if (acc == 0) return;
-        SegEntry sub;
-        sub.klo = e.klo + ((uint64_t)g0 << sh);
-        const uint64_t khi = e.klo + ((uint64_t)b_end << sh) - 1ull;
-        sub.dbits = bitlen64(khi - sub.klo);
-        sub.start = e.start + s_pos[g0];
-        sub.len = acc;
-        sub.buf = 1u - e.buf;
-        if (acc > (uint32_t)kSegCap) {
-          if (level + 1 < kSplitLevels)
-            push_entry(lists.big[(level + 1) & 1], &ctr[kCtrBig + level + 1], lists.cap_big, sub, hdr);
-          else
-            atomicOr(&hdr->overflow, 32u);  // cannot happen: keys are unique inside a tile
-        } else {
-          push_entry(lists.base, &ctr[kCtrBase], lists.cap_base, sub, hdr);
-        }
-      };
-      for (uint32_t b = 0; b < (uint32_t)kSplitBins; ++b) {
-        const uint32_t c = s_h[b];
-        if (c == 0) continue;
-        if (acc > 0 && acc + c > (uint32_t)kSegCap) {
-          close(b);
-          g0 = b;
-          acc = 0;
-        }
-        if (acc == 0) g0 = b;
-        acc += c;
-        if (acc > (uint32_t)kSegCap) {  // a single oversized bin
-          close(b + 1);
-          acc = 0;
-        }
+    for (uint32_t gi = threadIdx.x; gi < s_ngroups; gi += kBkThreads) {
+      const uint32_t b0 = s_lead[gi];
+      const uint32_t b1 = gi + 1 < s_ngroups ? s_lead[gi + 1] : (uint32_t)kSplitBins;
+      SegEntry sub;
+      sub.klo = e.klo + ((uint64_t)b0 << sh);
+      // the key range ends with the group's last non-empty bin, so a single
+      // large bin comes out kSplitBits narrower than its parent
+      sub.dbits = bitlen64(((uint64_t)(s_last[gi] + 1u - b0) << sh) - 1ull);
+      sub.start = e.start + s_pos[b0];
+      sub.len = (b1 < (uint32_t)kSplitBins ? s_pos[b1] : e.len) - s_pos[b0];
+      sub.buf = 1u - e.buf;
+      if (sub.len > (uint32_t)kSegCap) {  // only a single large bin
+        if (level + 1 < kSplitLevels)
+          push_entry(lists.big[(level + 1) & 1], &ctr[kCtrBig + level + 1], lists.cap_big, sub, hdr);
+        else
+          atomicOr(&hdr->overflow, 32u);  // cannot happen: keys are unique inside a tile
+      } else {
+        push_entry(lists.base, &ctr[kCtrBase], lists.cap_base, sub, hdr);
       }
-      close((uint32_t)kSplitBins);
     }
     __syncthreads();
     for (uint32_t i0 = 0; i0 < e.len; i0 += kSplitChunk) {
@@ -457,19 +508,16 @@ __global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(const uint32_t* _
                                                               uint32_t* __restrict__ vals) {
   __shared__ SegSmem sm;
   if (hdr->n_pairs > max_pairs) return;
-  uint32_t* ctr = lists.counters;
-  const uint32_t n_work = (uint32_t)n_tiles + min(ctr[kCtrBase], lists.cap_base);
+  const uint32_t n_work = min(lists.counters[kCtrBase], lists.cap_base);
   const int lane = bk_lane(), wave = (int)(threadIdx.x >> 6);
-  for (;;) {
-    const uint32_t w = block_ticket(&ctr[kCtrSortTicket], &sm.w);
-    if (w >= n_work) break;
-    SegEntry e;
-    if (w < (uint32_t)n_tiles) {
-      tile_segment((int)w, ranges, g_minc, g_max, e);
-      if (e.len > (uint32_t)kSegCap) continue;  // split into the base list
-    } else {
-      e = lists.base[w - (uint32_t)n_tiles];
-    }
+  // static round-robin over the base list (segments are of similar size);
+  // the next entry is read while the current segment is sorted
+  SegEntry nxt{};
+  if (blockIdx.x < n_work) nxt = lists.base[blockIdx.x];
+  for (uint32_t w = blockIdx.x; w < n_work; w += gridDim.x) {
+    const SegEntry e = nxt;
+    if (w + gridDim.x < n_work) nxt = lists.base[w + gridDim.x];
+    __syncthreads();  // the previous segment's LDS is no longer read
     if (e.len == 0 || e.len > (uint32_t)kSegCap) continue;
     const uint64_t* src = e.buf ? keys1 : keys0;
     uint64_t K[kSegItems];

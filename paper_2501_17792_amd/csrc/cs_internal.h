@@ -175,7 +175,7 @@ hipError_t launch_view_psnr(const int64_t* views, int n_inst, const float* ref, 
 
 // ---- tile-bucket sort -----------------------------------------------------
 constexpr int kBucketMaxTiles = 8192;  // frames with more tiles use the LSD radix sort
-constexpr int kSplitLevels = 7;        // 8-bit splits: 63 key bits down to the LDS capacity
+constexpr int kSplitLevels = 5;        // 11-bit splits: 63 key bits down to the LDS capacity
 #ifndef CS_SEG_THREADS
 #define CS_SEG_THREADS 1024
 #endif
