@@ -290,7 +290,7 @@ cs_status cs_frame_poll(cs_ctx* ctx, cs_frame_stats* stats); /* synchronises */
 #define CS_BUF_SKIN_MU   4  /* float [n_splats][4] posed mean xyz, Sigma'_xx        */
 #define CS_BUF_SKIN_COV  5  /* float [n_splats][4] Sigma'_xy xz yy yz               */
 #define CS_BUF_SKIN_COV2 6  /* float [n_splats] Sigma'_zz                            */
-#define CS_BUF_RECORD    7  /* float [n_splats][12] u v A B | C o r g | b rx ry depth */
+#define CS_BUF_RECORD    7  /* float [n_splats][12] u v rx ry | A B C o | r g b depth */
 #define CS_BUF_RECT      8  /* uint32 [n_splats] tile rect x0|y0<<8|x1<<16|y1<<24    */
 #define CS_BUF_COUNT     9  /* uint32 [n_splats] pairs emitted (0 = culled)          */
 #define CS_BUF_PAIR_OFF 10  /* uint32 [n_splats] exclusive scan of COUNT             */

@@ -8,23 +8,58 @@
 // in batches of one per thread. A wave skips a splat whose alpha >= 1/255 box
 // misses all of the wave's pixel centres (a decision every pixel would have
 // taken on its own, so the image does not depend on tile or wave shape).
+// Record layout: (u v rx ry) (A B C o) (r g b depth).
 #include "cs_internal.h"
 
 namespace cs {
+
+// Launch order of the tiles: longest lists first (by the top two bits of the
+// pair count), so that the tiles that take longest do not start last. The
+// order inside a magnitude class is that of the LDS atomics; it only changes
+// when a tile is composited, never its pixels.
+constexpr int kOrderClasses = 64;
+
+__global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t* __restrict__ ranges, int n_tiles,
+                                                          uint32_t* __restrict__ order) {
+  __shared__ uint32_t s_cnt[kOrderClasses];
+  if (threadIdx.x < kOrderClasses) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  auto cls = [&](int t) -> int {  // descending pair count -> ascending class
+    const uint32_t c = ranges[2 * t + 1] - ranges[2 * t];
+    const int bl = c ? 32 - __clz((int)c) : 0;
+    const int second = bl >= 2 ? (int)((c >> (bl - 2)) & 1u) : 0;
+    return kOrderClasses - 1 - (2 * bl + second);
+  };
+  for (int t = threadIdx.x; t < n_tiles; t += 1024) atomicAdd(&s_cnt[cls(t)], 1u);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int k = 0; k < kOrderClasses; ++k) {
+      const uint32_t c = s_cnt[k];
+      s_cnt[k] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += 1024) order[atomicAdd(&s_cnt[cls(t)], 1u)] = (uint32_t)t;
+}
 
 template <int TW, int TH, bool VIEW>
 __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restrict__ ranges,
                                                        const uint32_t* __restrict__ svals,
                                                        const float4* __restrict__ rec, CamDev cam,
                                                        float* __restrict__ image,
-                                                       const FrameHdr* __restrict__ hdr, ViewDev view) {
+                                                       const FrameHdr* __restrict__ hdr, ViewDev view,
+                                                       const uint32_t* __restrict__ order) {
   constexpr int N = TW * TH;
   constexpr int ROWS = 64 / TW;  // pixel rows per wave
   constexpr int WAVES = N / 64;
-  __shared__ float4 s_r0[N], s_r1[N], s_r2[N];
+  __shared__ float2 s_uv[N];
+  __shared__ float4 s_r1[N], s_r2[N];
+  __shared__ uint32_t s_live[WAVES];
   __shared__ uint16_t s_mask[N];            // waves whose pixel centres a splat's box reaches
   __shared__ uint16_t s_list[WAVES][N];     // per wave: the batch's splats it must evaluate, in order
-  const int tile = blockIdx.x;
+  const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
   int tx, ty;
   float* out = image;
   int out_x0 = 0, out_y0 = 0, out_w = cam.W, out_h = cam.H;
@@ -62,28 +97,67 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
   const uint32_t n_splats = hdr->n_splats;
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
   bool done = !inside;
-  for (uint32_t b = start; b < end; b += N) {
-    const uint32_t idx = b + threadIdx.x;
-    uint32_t mask = 0;
-    if (idx < end) {
-      const uint32_t s = svals[idx];
-      if (s < n_splats) {
-        const float4 r0 = rec[3 * (size_t)s], r2 = rec[3 * (size_t)s + 2];
-        s_r0[threadIdx.x] = r0;
-        s_r1[threadIdx.x] = rec[3 * (size_t)s + 1];
-        s_r2[threadIdx.x] = r2;
-        // the alpha >= 1/255 box against each wave's rows of pixel centres
-        if (!(r0.x + r2.y < wx0 || r0.x - r2.y > wx1)) {
+  // Software pipeline over batches (see the prefetch ring below). A record's
+  // first float4 (u v rx ry) decides which waves its alpha >= 1/255 box
+  // reaches; the other two are only fetched when one of those waves still has
+  // unfinished pixels (finished waves stay finished, so the activity of the
+  // batch before is a safe superset).
+  auto load_index = [&](uint32_t idx) -> uint32_t {
+    if (idx >= end) return 0xffffffffu;
+    const uint32_t s = svals[idx];
+    return s < n_splats ? s : 0xffffffffu;
+  };
+  auto wave_mask = [&](const float4& q) -> uint32_t {
+    uint32_t m = 0;
+    if (!(q.x + q.z < wx0 || q.x - q.z > wx1)) {
 #pragma unroll
-          for (int w = 0; w < WAVES; ++w) {
-            const float wy0 = ty0 + (float)(w * ROWS), wy1 = wy0 + (float)(ROWS - 1);
-            if (!(r0.y + r2.z < wy0 || r0.y - r2.z > wy1)) mask |= 1u << w;
-          }
-        }
+      for (int w = 0; w < WAVES; ++w) {
+        const float wy0 = ty0 + (float)(w * ROWS), wy1 = wy0 + (float)(ROWS - 1);
+        if (!(q.y + q.w < wy0 || q.y - q.w > wy1)) m |= 1u << w;
       }
     }
+    return m;
+  };
+  // prefetch ring: splat indices 4 batches ahead, first float4s 3 ahead, the
+  // rest of a record 1 ahead (once its wave mask is known)
+  auto load_q0 = [&](uint32_t s) -> float4 {
+    return s != 0xffffffffu ? rec[3 * (size_t)s] : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+  uint32_t i0 = load_index(start + threadIdx.x), i1 = load_index(start + N + threadIdx.x);
+  uint32_t i2 = load_index(start + 2 * N + threadIdx.x), i3 = load_index(start + 3 * N + threadIdx.x);
+  float4 q0 = load_q0(i0), p1 = load_q0(i1), p2 = load_q0(i2);
+  float4 q1 = make_float4(0.f, 0.f, 0.f, 0.f), q2 = q1;
+  uint32_t mask = i0 != 0xffffffffu ? wave_mask(q0) : 0u;
+  if (mask) {
+    q1 = rec[3 * (size_t)i0 + 1];
+    q2 = rec[3 * (size_t)i0 + 2];
+  }
+  for (uint32_t b = start; b < end; b += N) {
+    if (mask) {
+      s_uv[threadIdx.x] = make_float2(q0.x, q0.y);
+      s_r1[threadIdx.x] = q1;
+      s_r2[threadIdx.x] = q2;
+    }
     s_mask[threadIdx.x] = (uint16_t)mask;
+    const uint64_t live = __ballot(!done);
+    if (lane == 0) s_live[wave] = live != 0ull ? 1u : 0u;
     __syncthreads();
+    uint32_t active = 0;
+#pragma unroll
+    for (int w = 0; w < WAVES; ++w) active |= s_live[w] << w;
+    // advance the ring by one batch and start its loads
+    i0 = i1;
+    i1 = i2;
+    i2 = i3;
+    i3 = load_index(b + 4 * N + threadIdx.x);
+    q0 = p1;
+    p1 = p2;
+    p2 = load_q0(i2);
+    mask = i0 != 0xffffffffu ? wave_mask(q0) & active : 0u;
+    if (mask) {
+      q1 = rec[3 * (size_t)i0 + 1];
+      q2 = rec[3 * (size_t)i0 + 2];
+    }
     const int cnt = (int)min((uint32_t)N, end - b);
     if (__ballot(!done) != 0ull) {
       // this wave's splats of the batch, compacted in list order
@@ -97,24 +171,24 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
       }
       for (int k = 0; k < n_w; ++k) {
         const int j = s_list[wave][k];
-        const float4 r0 = s_r0[j];  // u v A B
-        const float4 r2 = s_r2[j];  // b rx ry depth
         if (done) continue;
-        const float4 r1 = s_r1[j];  // C o r g
-        const float dx = pcx - r0.x, dy = pcy - r0.y;
-        float power = -0.5f * fmaf(r0.z * dx, dx, r1.x * dy * dy) - r0.w * dx * dy;
+        const float4 r1 = s_r1[j];  // A B C o
+        const float2 uv = s_uv[j];
+        const float dx = pcx - uv.x, dy = pcy - uv.y;
+        float power = -0.5f * fmaf(r1.x * dx, dx, r1.z * dy * dy) - r1.y * dx * dy;
         power = fminf(power, 0.f);
-        const float alpha = fminf(0.99f, r1.y * __expf(power));
+        const float alpha = fminf(0.99f, r1.w * __expf(power));
         if (alpha < (1.f / 255.f)) continue;
         const float Tn = T * (1.f - alpha);
         if (Tn < 1e-4f) {
           done = true;
           continue;
         }
+        const float4 r2 = s_r2[j];  // r g b depth
         const float wgt = alpha * T;
-        cr = fmaf(r1.z, wgt, cr);
-        cg = fmaf(r1.w, wgt, cg);
-        cb = fmaf(r2.x, wgt, cb);
+        cr = fmaf(r2.x, wgt, cr);
+        cg = fmaf(r2.y, wgt, cg);
+        cb = fmaf(r2.z, wgt, cb);
         T = Tn;
       }
     }
@@ -132,21 +206,28 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
 template <int TW, int TH>
 static hipError_t launch_blend_t(const uint32_t* ranges, const uint32_t* svals, const float4* rec,
                                  CamDev cam, float* image, const FrameHdr* hdr, const ViewDev* view,
-                                 hipStream_t st) {
+                                 uint32_t* order, hipStream_t st) {
   if (view) {
     if (view->n_tiles > 0)
-      blend_kernel<TW, TH, true><<<view->n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr, *view);
+      blend_kernel<TW, TH, true><<<view->n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr, *view,
+                                                                      nullptr);
   } else {
-    blend_kernel<TW, TH, false><<<cam.tiles_x * cam.tiles_y, TW * TH, 0, st>>>(ranges, svals, rec, cam, image,
-                                                                                hdr, ViewDev{});
+    const int n_tiles = cam.tiles_x * cam.tiles_y;
+    if (order) tile_order_kernel<<<1, 1024, 0, st>>>(ranges, n_tiles, order);
+    blend_kernel<TW, TH, false><<<n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr, ViewDev{},
+                                                              order);
   }
   return hipGetLastError();
 }
 
+// order: scratch of cam.tiles_x * cam.tiles_y entries for the longest-first
+// launch order, or null for tile-index order.
 hipError_t launch_blend(const uint32_t* ranges, const uint32_t* svals, const float4* rec, CamDev cam,
-                        float* image, const FrameHdr* hdr, const ViewDev* view, hipStream_t st) {
+                        float* image, const FrameHdr* hdr, const ViewDev* view, uint32_t* order,
+                        hipStream_t st) {
 #define CS_BLEND_CASE(W_, H_) \
-  if (cam.tw == W_ && cam.th == H_) return launch_blend_t<W_, H_>(ranges, svals, rec, cam, image, hdr, view, st);
+  if (cam.tw == W_ && cam.th == H_)      \
+    return launch_blend_t<W_, H_>(ranges, svals, rec, cam, image, hdr, view, order, st);
   CS_BLEND_CASE(8, 8)
   CS_BLEND_CASE(8, 16)
   CS_BLEND_CASE(8, 32)

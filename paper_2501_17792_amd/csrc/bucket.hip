@@ -68,14 +68,12 @@ __device__ __forceinline__ void bk_range(uint32_t n, uint32_t& lo, uint32_t& hi)
   hi = min(lo + per, n);
 }
 
-struct SplatIn {  // what binning reads of one splat: tile count, rect, depth bits
-  uint32_t c, r, db;
-  __device__ __forceinline__ void load(const uint32_t* count, const uint32_t* rect, const float4* rec, uint64_t s,
-                                       uint32_t hi) {
-    const bool in = s < (uint64_t)hi;
-    c = in ? count[s] : 0u;
-    r = in ? rect[s] : 0u;
-    db = in ? __float_as_uint(rec[3 * (size_t)s + 2].w) : 0u;
+struct SplatIn {  // what binning reads of one splat: rect and depth bits (0: culled)
+  uint32_t r, db;
+  __device__ __forceinline__ void load(const uint2* rd, uint64_t s, uint32_t hi) {
+    const uint2 v = s < (uint64_t)hi ? rd[s] : make_uint2(0u, 0u);
+    r = v.x;
+    db = v.y;
   }
 };
 
@@ -106,8 +104,7 @@ struct PairIter {  // walks one splat's tile rect row-major
 // 1. per-tile pair count and depth-bit range
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBkThreads) void bucket_count_kernel(
-    const uint32_t* __restrict__ count, const uint32_t* __restrict__ rect, const float4* __restrict__ rec,
-    int tiles_x, int n_tiles, const FrameHdr* __restrict__ hdr, uint32_t* __restrict__ g_cnt,
+    const uint2* __restrict__ rd, int tiles_x, int n_tiles, const FrameHdr* __restrict__ hdr, uint32_t* __restrict__ g_cnt,
     uint32_t* __restrict__ g_minc, uint32_t* __restrict__ g_max) {
   extern __shared__ uint32_t s_dyn[];
   uint32_t* s_cnt = s_dyn;
@@ -118,13 +115,13 @@ __global__ __launch_bounds__(kBkThreads) void bucket_count_kernel(
   uint32_t lo, hi;
   bk_range(hdr->n_splats, lo, hi);
   SplatIn nx;
-  nx.load(count, rect, rec, (uint64_t)lo + threadIdx.x, hi);
+  nx.load(rd, (uint64_t)lo + threadIdx.x, hi);
   for (uint32_t b = lo; b < hi; b += kBkThreads) {
     const SplatIn cur = nx;
-    nx.load(count, rect, rec, (uint64_t)b + kBkThreads + threadIdx.x, hi);  // next round in flight
+    nx.load(rd, (uint64_t)b + kBkThreads + threadIdx.x, hi);  // next round in flight
     const uint32_t db = cur.db;
     PairIter it;
-    it.init(cur.c > 0, cur.r);
+    it.init(cur.db != 0u, cur.r);
     while (__ballot(it.more)) {
       const uint32_t t = it.ty * (uint32_t)tiles_x + it.tx;
       lds_slot(s_cnt, t, it.more);
@@ -168,8 +165,7 @@ __global__ void bucket_ranges_kernel(const uint32_t* __restrict__ base, int n_ti
 // them out with LDS counters (the same splat range as in the count kernel).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBkThreads) void bucket_scatter_kernel(
-    const uint32_t* __restrict__ count, const uint32_t* __restrict__ rect, const float4* __restrict__ rec,
-    int tiles_x, int n_tiles, const FrameHdr* __restrict__ hdr, uint32_t max_pairs,
+    const uint2* __restrict__ rd, int tiles_x, int n_tiles, const FrameHdr* __restrict__ hdr, uint32_t max_pairs,
     const uint32_t* __restrict__ base, uint64_t* __restrict__ items) {
   extern __shared__ uint32_t s_dyn[];
   uint32_t* s_cur = s_dyn;
@@ -179,13 +175,13 @@ __global__ __launch_bounds__(kBkThreads) void bucket_scatter_kernel(
   uint32_t lo, hi;
   bk_range(hdr->n_splats, lo, hi);
   SplatIn nx;
-  nx.load(count, rect, rec, (uint64_t)lo + threadIdx.x, hi);
+  nx.load(rd, (uint64_t)lo + threadIdx.x, hi);
   for (uint32_t b = lo; b < hi; b += kBkThreads) {
     const SplatIn cur = nx;
-    nx.load(count, rect, rec, (uint64_t)b + kBkThreads + threadIdx.x, hi);  // next round in flight
+    nx.load(rd, (uint64_t)b + kBkThreads + threadIdx.x, hi);  // next round in flight
     const uint64_t K = ((uint64_t)cur.db << 32) | (b + threadIdx.x);
     PairIter it;
-    it.init(cur.c > 0, cur.r);
+    it.init(cur.db != 0u, cur.r);
     while (__ballot(it.more)) {
       const uint32_t pos = lds_slot(s_cur, it.ty * (uint32_t)tiles_x + it.tx, it.more);
       if (it.more && pos < max_pairs) items[pos] = K;
@@ -594,8 +590,8 @@ __global__ void bucket_keys_kernel(const uint32_t* __restrict__ ranges, const ui
 }
 
 // ---------------------------------------------------------------------------
-hipError_t launch_bucket_count(const uint32_t* count, const uint32_t* rect, const float4* rec, CamDev cam,
-                               const FrameHdr* hdr, uint32_t* region, uint32_t* counts, hipStream_t st) {
+hipError_t launch_bucket_count(const uint2* rd, CamDev cam, const FrameHdr* hdr, uint32_t* region, uint32_t* counts,
+                               hipStream_t st) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   if (n_tiles > kBucketMaxTiles) return hipErrorInvalidValue;
   static bool lds_set[64] = {};
@@ -607,7 +603,7 @@ hipError_t launch_bucket_count(const uint32_t* count, const uint32_t* rect, cons
     lds_set[dev] = true;
   }
   bucket_count_kernel<<<kBucketBlocks, kBkThreads, 12 * n_tiles, st>>>(
-      count, rect, rec, cam.tiles_x, n_tiles, hdr, counts, region + kBucketMinC, region + kBucketMax);
+      rd, cam.tiles_x, n_tiles, hdr, counts, region + kBucketMinC, region + kBucketMax);
   return hipGetLastError();
 }
 
@@ -618,12 +614,11 @@ hipError_t launch_bucket_ranges(const uint32_t* base, int n_tiles, const FrameHd
   return hipGetLastError();
 }
 
-hipError_t launch_bucket_scatter(const uint32_t* count, const uint32_t* rect, const float4* rec, CamDev cam,
-                                 const FrameHdr* hdr, uint32_t max_pairs, const uint32_t* base, uint64_t* items,
-                                 hipStream_t st) {
+hipError_t launch_bucket_scatter(const uint2* rd, CamDev cam, const FrameHdr* hdr, uint32_t max_pairs,
+                                 const uint32_t* base, uint64_t* items, hipStream_t st) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
-  bucket_scatter_kernel<<<kBucketBlocks, kBkThreads, 4 * n_tiles, st>>>(count, rect, rec, cam.tiles_x, n_tiles, hdr,
-                                                                       max_pairs, base, items);
+  bucket_scatter_kernel<<<kBucketBlocks, kBkThreads, 4 * n_tiles, st>>>(rd, cam.tiles_x, n_tiles, hdr, max_pairs,
+                                                                       base, items);
   return hipGetLastError();
 }
 

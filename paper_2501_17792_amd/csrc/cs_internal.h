@@ -98,9 +98,10 @@ struct SkinOut {
 };
 
 struct SplatOut {
-  float4* rec;             // [n][3] float4: (u v A B)(C o r g)(b rx ry depth)
+  float4* rec;             // [n][3] float4: (u v rx ry)(A B C o)(r g b depth)
   uint32_t* rect;
   uint32_t* count;
+  uint2* rd;               // [n] (rect, depth bits), depth bits 0 = culled: what binning reads
 };
 
 // ---- launchers (defined in the .hip files) ------------------------------
@@ -146,7 +147,8 @@ hipError_t launch_hist_keys(const uint64_t* keys, const uint32_t* n_ptr, uint32_
 hipError_t launch_ranges(const uint64_t* skeys, FrameHdr* hdr, uint32_t max_pairs, int n_tiles,
                          uint32_t* ranges, hipStream_t st);
 hipError_t launch_blend(const uint32_t* ranges, const uint32_t* svals, const float4* rec, CamDev cam,
-                        float* image, const FrameHdr* hdr, const ViewDev* view, hipStream_t st);
+                        float* image, const FrameHdr* hdr, const ViewDev* view, uint32_t* order,
+                        hipStream_t st);
 hipError_t launch_features(const cs_instance* inst, const float* pose, const float* joints,
                            const TemplateDev* tpl, int n_inst, int n_tpl, CamDev cam, const cs_mlp* net,
                            float* feat, hipStream_t st);
@@ -174,6 +176,7 @@ hipError_t launch_view_psnr(const int64_t* views, int n_inst, const float* ref, 
                             hipStream_t st);
 
 // ---- tile-bucket sort -----------------------------------------------------
+constexpr int kMaxFrameTiles = 256 * 256;  // tiles along each axis are at most 256 (8-bit rect edges)
 constexpr int kBucketMaxTiles = 8192;  // frames with more tiles use the LSD radix sort
 constexpr int kSplitLevels = 5;        // 11-bit splits: 63 key bits down to the LDS capacity
 #ifndef CS_SEG_THREADS
@@ -206,13 +209,12 @@ struct SegLists {
 };
 
 constexpr int kBucketBlocks = 512;  // workgroups of the count and scatter kernels (columns of the count matrix)
-hipError_t launch_bucket_count(const uint32_t* count, const uint32_t* rect, const float4* rec, CamDev cam,
-                               const FrameHdr* hdr, uint32_t* region, uint32_t* counts, hipStream_t st);
+hipError_t launch_bucket_count(const uint2* rd, CamDev cam, const FrameHdr* hdr, uint32_t* region, uint32_t* counts,
+                               hipStream_t st);
 hipError_t launch_bucket_ranges(const uint32_t* base, int n_tiles, const FrameHdr* hdr, uint32_t max_pairs,
                                 uint32_t* ranges, hipStream_t st);
-hipError_t launch_bucket_scatter(const uint32_t* count, const uint32_t* rect, const float4* rec, CamDev cam,
-                                 const FrameHdr* hdr, uint32_t max_pairs, const uint32_t* base, uint64_t* items,
-                                 hipStream_t st);
+hipError_t launch_bucket_scatter(const uint2* rd, CamDev cam, const FrameHdr* hdr, uint32_t max_pairs,
+                                 const uint32_t* base, uint64_t* items, hipStream_t st);
 hipError_t launch_scan_total(uint32_t* data, uint32_t n, uint32_t* block_sums, uint32_t* total_out, FrameHdr* hdr,
                              uint32_t max_total, hipStream_t st);
 hipError_t launch_seg_sort(const uint32_t* ranges, const uint32_t* region, int n_tiles, FrameHdr* hdr,

@@ -58,9 +58,9 @@ __global__ __launch_bounds__(TW* TH) void blend_backward_kernel(
     for (int j = 0; j < cnt && !done; ++j) {
       const float4 r0 = s_r0[j], r1 = s_r1[j];
       const float dx = pcx - r0.x, dy = pcy - r0.y;
-      float power = -0.5f * fmaf(r0.z * dx, dx, r1.x * dy * dy) - r0.w * dx * dy;
+      float power = -0.5f * fmaf(r1.x * dx, dx, r1.z * dy * dy) - r1.y * dx * dy;
       power = fminf(power, 0.f);
-      const float alpha = fminf(0.99f, r1.y * __expf(power));
+      const float alpha = fminf(0.99f, r1.w * __expf(power));
       if (alpha < (1.f / 255.f)) continue;
       const float Tn = T * (1.f - alpha);
       if (Tn < 1e-4f) {
@@ -115,10 +115,10 @@ __global__ __launch_bounds__(TW* TH) void blend_backward_kernel(
         if (k <= last) {
           const float4 r0 = s_r0[j], r1 = s_r1[j], r2 = s_r2[j];
           const float dx = pcx - r0.x, dy = pcy - r0.y;
-          const float praw = -0.5f * fmaf(r0.z * dx, dx, r1.x * dy * dy) - r0.w * dx * dy;
+          const float praw = -0.5f * fmaf(r1.x * dx, dx, r1.z * dy * dy) - r1.y * dx * dy;
           const float power = fminf(praw, 0.f);
           const float e = __expf(power);
-          const float raw = r1.y * e;
+          const float raw = r1.w * e;
           const float alpha = fminf(0.99f, raw);
           if (alpha >= (1.f / 255.f)) {
             contrib = true;
@@ -128,16 +128,16 @@ __global__ __launch_bounds__(TW* TH) void blend_backward_kernel(
             gv[7] = dpg * w;
             gv[8] = dpb * w;
             const float ia = 1.f / (1.f - alpha);
-            const float dLda = dpr * (r1.z * T - Sr * ia) + dpg * (r1.w * T - Sg * ia) + dpb * (r2.x * T - Sb * ia);
-            Sr = fmaf(r1.z, w, Sr);
-            Sg = fmaf(r1.w, w, Sg);
-            Sb = fmaf(r2.x, w, Sb);
+            const float dLda = dpr * (r2.x * T - Sr * ia) + dpg * (r2.y * T - Sg * ia) + dpb * (r2.z * T - Sb * ia);
+            Sr = fmaf(r2.x, w, Sr);
+            Sg = fmaf(r2.y, w, Sg);
+            Sb = fmaf(r2.z, w, Sb);
             if (raw <= 0.99f) {
               gv[5] = dLda * e;
               if (praw <= 0.f) {
                 const float dLdp = dLda * alpha;
-                gv[0] = dLdp * fmaf(r0.z, dx, r0.w * dy);
-                gv[1] = dLdp * fmaf(r0.w, dx, r1.x * dy);
+                gv[0] = dLdp * fmaf(r1.x, dx, r1.y * dy);
+                gv[1] = dLdp * fmaf(r1.y, dx, r1.z * dy);
                 gv[2] = -0.5f * dLdp * dx * dx;
                 gv[3] = -dLdp * dx * dy;
                 gv[4] = -0.5f * dLdp * dy * dy;
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kChunkThreads) void splat_backward_kernel(
         Posed P;
         skin_gaussian(s_bones, T.mean_idx[g], T.skin_w[g], T.cov_a[g], T.cov_b[g], w.skin_mode, Ry, P);
         const float4 r0 = recs[3 * s], r1 = recs[3 * s + 1];
-        const float A = r0.z, B = r0.w, C = r1.x, o = r1.y;
+        const float A = r1.x, B = r1.y, C = r1.z, o = r1.w;
         // conic -> 2D covariance: dS = -Q G Q, G = [[gA, gB/2], [gB/2, gC]]
         const float gA = gs[2], gB = 0.5f * gs[3], gC = gs[4];
         const float QG00 = A * gA + B * gB, QG01 = A * gB + B * gC, QG10 = B * gA + C * gB, QG11 = B * gB + C * gC;

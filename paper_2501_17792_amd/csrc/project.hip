@@ -58,6 +58,7 @@ __device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOu
     out.rec[3 * s + 2] = r.r2;
     out.rect[s] = r.rect;
     out.count[s] = r.count;
+    out.rd[s] = make_uint2(r.rect, r.count ? __float_as_uint(r.r2.w) : 0u);
     vis += r.count ? 1u : 0u;
   }
   return vis;

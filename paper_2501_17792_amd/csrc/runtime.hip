@@ -84,6 +84,7 @@ struct cs_ctx {
   float4* rec = nullptr;
   uint32_t* rect = nullptr;
   uint32_t* cnt = nullptr;
+  uint2* rd = nullptr;        // (rect, depth bits) per splat for binning
   uint32_t* pair_off = nullptr;
   uint32_t* scan_sums = nullptr;
 
@@ -97,6 +98,7 @@ struct cs_ctx {
   uint32_t* rts_sums = nullptr;
   int64_t cap_tiles = 0;
   uint32_t* ranges = nullptr;
+  uint32_t* tile_order = nullptr;    // [kMaxFrameTiles] blend launch order
   uint32_t* bk_counts = nullptr;     // [kBucketMaxTiles][kBucketBlocks] pair counts, then first slots
   uint32_t* bk_sums = nullptr;       // block sums of their scan
   SegEntry* seg_base = nullptr;      // key segments sorted in LDS
@@ -210,6 +212,7 @@ cs_status ensure_splats(cs_ctx* ctx, int64_t n) {
   CS_TRY(dalloc(ctx, &ctx->rec, cap * 3));
   CS_TRY(dalloc(ctx, &ctx->rect, cap));
   CS_TRY(dalloc(ctx, &ctx->cnt, cap));
+  CS_TRY(dalloc(ctx, &ctx->rd, cap));
   CS_TRY(dalloc(ctx, &ctx->pair_off, cap));
   CS_TRY(dalloc(ctx, &ctx->scan_sums, (cap + scan_tile() - 1) / scan_tile() + 1));
   ctx->cap_splats = cap;
@@ -357,6 +360,7 @@ cs_status cs_create(int32_t device, void* stream, const cs_options* opt, cs_ctx*
   ctx->opt = o;
   cs_status s = dalloc(ctx, &ctx->hdr, 1);
   if (s == CS_OK) s = dalloc(ctx, &ctx->hist, kHistLen);
+  if (s == CS_OK) s = dalloc(ctx, &ctx->tile_order, kMaxFrameTiles);
   if (s == CS_OK) s = dalloc(ctx, &ctx->bk_counts, (size_t)kBucketMaxTiles * kBucketBlocks);
   if (s == CS_OK) s = dalloc(ctx, &ctx->bk_sums, (size_t)kBucketMaxTiles * kBucketBlocks / scan_tile() + 2);
   if (s == CS_OK) s = dalloc(ctx, &ctx->n_dev, 1);
@@ -416,6 +420,7 @@ void cs_destroy(cs_ctx* ctx) {
   dfree(&ctx->rect);
   dfree(&ctx->cnt);
   dfree(&ctx->pair_off);
+  dfree(&ctx->rd);
   dfree(&ctx->scan_sums);
   for (int b = 0; b < 2; ++b) {
     dfree(&ctx->keys[b]);
@@ -424,6 +429,7 @@ void cs_destroy(cs_ctx* ctx) {
   dfree(&ctx->lookback);
   dfree(&ctx->hist);
   dfree(&ctx->bk_counts);
+  dfree(&ctx->tile_order);
   dfree(&ctx->bk_sums);
   dfree(&ctx->seg_base);
   dfree(&ctx->seg_big[0]);
@@ -683,7 +689,7 @@ static cs_status bucket_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles) {
   uint32_t cap_p = (uint32_t)std::min<int64_t>(ctx->cap_pairs, kMaxPairsLimit);
   const uint32_t max_p = ctx->capturing ? cap_p : kMaxPairsLimit;
   ctx->mark(CS_STAGE_EMIT, 0);
-  HIP_TRY(launch_bucket_count(ctx->cnt, ctx->rect, ctx->rec, cd, ctx->hdr, region, ctx->bk_counts, ctx->stream));
+  HIP_TRY(launch_bucket_count(ctx->rd, cd, ctx->hdr, region, ctx->bk_counts, ctx->stream));
   HIP_TRY(launch_scan_total(ctx->bk_counts, (uint32_t)n_tiles * kBucketBlocks, ctx->bk_sums, &ctx->hdr->n_pairs,
                             ctx->hdr, max_p, ctx->stream));
   HIP_TRY(launch_bucket_ranges(ctx->bk_counts, n_tiles, ctx->hdr, max_p, ctx->ranges, ctx->stream));
@@ -696,8 +702,7 @@ static cs_status bucket_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles) {
     }
     cap_p = (uint32_t)std::min<int64_t>(ctx->cap_pairs, kMaxPairsLimit);
   }
-  HIP_TRY(launch_bucket_scatter(ctx->cnt, ctx->rect, ctx->rec, cd, ctx->hdr, cap_p, ctx->bk_counts, ctx->keys[0],
-                                ctx->stream));
+  HIP_TRY(launch_bucket_scatter(ctx->rd, cd, ctx->hdr, cap_p, ctx->bk_counts, ctx->keys[0], ctx->stream));
   ctx->mark(CS_STAGE_EMIT, 1);
   ctx->mark(CS_STAGE_SORT, 0);
   SegLists lists{};
@@ -741,7 +746,7 @@ static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs
   HIP_TRY(launch_frame_reset(ctx->hdr, ctx->hist, kHistLen, 0, ctx->stream));
   // A4 projection
   SkinOut so{ctx->skin_mu, ctx->skin_cov, ctx->skin_zz};
-  SplatOut po{ctx->rec, ctx->rect, ctx->cnt};
+  SplatOut po{ctx->rec, ctx->rect, ctx->cnt, ctx->rd};
   const int fused = ctx->opt.fuse_skin_project;
   const int64_t n_chunks = ctx->capturing ? ctx->cap_chunks : ctx->hdr_host->n_chunks;
   ctx->mark(CS_STAGE_PROJECT, 0);
@@ -760,7 +765,9 @@ static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs
     CS_TRY(lsd_bin_sort(ctx, cd, n_tiles, vp));
   }
   ctx->mark(CS_STAGE_BLEND, 0);
-  if (n_tiles > 0) HIP_TRY(launch_blend(ctx->ranges, ctx->vals[ctx->sorted], ctx->rec, cd, image, ctx->hdr, vp, ctx->stream));
+  if (n_tiles > 0)
+    HIP_TRY(launch_blend(ctx->ranges, ctx->vals[ctx->sorted], ctx->rec, cd, image, ctx->hdr, vp,
+                         view_mode ? nullptr : ctx->tile_order, ctx->stream));
   ctx->mark(CS_STAGE_BLEND, 1);
   ctx->state = kRendered;
   if (stats) {

@@ -136,7 +136,7 @@ __device__ __forceinline__ void sh_colour(const float4* __restrict__ planes, int
 }
 
 struct SplatRec {
-  float4 r0, r1, r2;   // (u v A B) (C o r g) (b rx ry depth)
+  float4 r0, r1, r2;   // (u v rx ry) (A B C o) (r g b depth)
   uint32_t rect;
   uint32_t count;
 };
@@ -198,9 +198,9 @@ __device__ __forceinline__ void project_gaussian(const Posed& p, float opacity,
   d0 *= inv; d1 *= inv; d2 *= inv;
   float rgb[3];
   sh_colour<DEG>(sh_planes, sh_stride, d0, d1, d2, rgb);
-  out.r0 = make_float4(u, v, c / det, -b / det);
-  out.r1 = make_float4(a / det, opacity, rgb[0], rgb[1]);
-  out.r2 = make_float4(rgb[2], rx, ry, tz);
+  out.r0 = make_float4(u, v, rx, ry);
+  out.r1 = make_float4(c / det, -b / det, a / det, opacity);
+  out.r2 = make_float4(rgb[0], rgb[1], rgb[2], tz);
   out.rect = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) | ((uint32_t)y1 << 24);
   out.count = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
 }

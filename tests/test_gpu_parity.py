@@ -94,14 +94,15 @@ def _compare_frame(scene, mode, thresholds, tile=(16, 16), **kw):
     np.testing.assert_allclose(R[:, 0], rec["u"][both], atol=2e-3)
     np.testing.assert_allclose(R[:, 1], rec["v"][both], atol=2e-3)
     np.testing.assert_allclose(R[:, 11], rec["depth"][both], rtol=1e-5)
-    for k, name in [(2, "A"), (3, "B"), (4, "C")]:
+    # record columns: u v rx ry | A B C o | r g b depth
+    for k, name in [(4, "A"), (5, "B"), (6, "C")]:
         ref = rec[name][both]
         tol = 1e-4 * np.maximum(np.abs(rec["A"][both]), np.abs(rec["C"][both]))
         assert np.all(np.abs(R[:, k] - ref) <= tol), name
-    np.testing.assert_allclose(R[:, 5], rec["opacity"][both], rtol=0, atol=0)
-    np.testing.assert_allclose(R[:, [6, 7, 8]], rec["rgb"][both], atol=1e-4)
-    np.testing.assert_allclose(R[:, 9], rec["rx"][both], rtol=1e-4)
-    np.testing.assert_allclose(R[:, 10], rec["ry"][both], rtol=1e-4)
+    np.testing.assert_allclose(R[:, 7], rec["opacity"][both], rtol=0, atol=0)
+    np.testing.assert_allclose(R[:, [8, 9, 10]], rec["rgb"][both], atol=1e-4)
+    np.testing.assert_allclose(R[:, 2], rec["rx"][both], rtol=1e-4)
+    np.testing.assert_allclose(R[:, 3], rec["ry"][both], rtol=1e-4)
     grect = unpack_rect(g["rect"][both])
     ok = np.all(grect == rec["rect"][both], axis=1) | frag_rect[both]
     assert ok.all(), np.nonzero(~ok)[0][:10]
