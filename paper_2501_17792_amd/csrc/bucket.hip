@@ -418,7 +418,7 @@ __device__ __forceinline__ uint64_t match8(uint32_t d) {  // lanes holding the s
 
 struct SegSmem {
   uint64_t items[kSegCap];
-  uint16_t whist[kSegWaves * 256];
+  uint32_t whist[kSegWaves * 256];
   uint32_t tot[256];
   uint32_t w;
   uint32_t flag;
@@ -433,24 +433,33 @@ __device__ void lsd_pass(SegSmem& sm, uint64_t (&K)[kSegItems], uint32_t len, ui
   const int lane = bk_lane(), wave = (int)(threadIdx.x >> 6);
   for (int i = threadIdx.x; i < kSegWaves * 256; i += kSegThreads) sm.whist[i] = 0;
   __syncthreads();
-  uint16_t* wh = sm.whist + wave * 256;
-  uint32_t rank[kSegItems];
+  uint32_t* wh = sm.whist + wave * 256;
+  // Rank inside the wave: per item slot, one lane per digit (the leader)
+  // takes the digit's running count with an atomic add that returns it. A
+  // wave's LDS atomics are applied in issue order, so all slots' atomics can
+  // be in flight at once; the other lanes get their leader's value after.
+  uint32_t ret[kSegItems], info[kSegItems / 2];  // info: leader | prefix << 8, two per register
+#pragma unroll
+  for (int k = 0; k < kSegItems / 2; ++k) info[k] = 0;
 #pragma unroll
   for (int k = 0; k < kSegItems; ++k) {
     const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
     const bool v = idx < len;
     const uint64_t vmask = __ballot(v);
-    rank[k] = 0;
+    ret[k] = 0;
     if (vmask) {  // uniform
       const uint32_t d = seg_digit(K[k], klo, shift);
       const uint64_t peers = match8(d) & vmask;
-      if (v) {
-        const int leader = __ffsll((unsigned long long)peers) - 1;
-        const uint32_t cur = wh[d];
-        rank[k] = cur + (uint32_t)__popcll(peers & lanes_below());
-        if (lane == leader) wh[d] = (uint16_t)(cur + (uint32_t)__popcll(peers));
-      }
+      const int leader = v ? __ffsll((unsigned long long)peers) - 1 : 0;
+      if (v && lane == leader) ret[k] = atomicAdd(&wh[d], (uint32_t)__popcll(peers));
+      info[k / 2] |= ((uint32_t)leader | ((uint32_t)__popcll(peers & lanes_below()) << 8)) << (16 * (k & 1));
     }
+  }
+  uint32_t rank[kSegItems];
+#pragma unroll
+  for (int k = 0; k < kSegItems; ++k) {
+    const uint32_t in = (info[k / 2] >> (16 * (k & 1))) & 0xffffu;
+    rank[k] = (uint32_t)__shfl((int)ret[k], (int)(in & 63u)) + (in >> 8);
   }
   __syncthreads();
   if (threadIdx.x < 256) {  // offsets of each wave inside each digit
@@ -458,7 +467,7 @@ __device__ void lsd_pass(SegSmem& sm, uint64_t (&K)[kSegItems], uint32_t len, ui
 #pragma unroll
     for (int w = 0; w < kSegWaves; ++w) {
       const uint32_t c = sm.whist[w * 256 + threadIdx.x];
-      sm.whist[w * 256 + threadIdx.x] = (uint16_t)run;
+      sm.whist[w * 256 + threadIdx.x] = run;
       run += c;
     }
     sm.tot[threadIdx.x] = run;
@@ -538,14 +547,24 @@ __global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(const uint32_t* _
     if (threadIdx.x == 0) sm.flag = 0;
     __syncthreads();
     if (hi_only) {
-      // runs of equal (K - klo) >> 32: insertion sort of short runs by one
-      // thread each; a run longer than 32 sends the segment to a full sort
-      for (uint32_t i = threadIdx.x; i + 1 < e.len; i += kSegThreads) {
-        const uint64_t hi_i = (sm.items[i] - e.klo) >> 32;
-        const bool starts = i == 0 || ((sm.items[i - 1] - e.klo) >> 32) != hi_i;
-        if (!starts || ((sm.items[i + 1] - e.klo) >> 32) != hi_i) continue;
+      // Runs of equal (K - klo) >> 32 (equal depth bits) are put in key
+      // order: positions i = threadIdx.x + j * kSegThreads, so neighbours in
+      // the list are neighbouring lanes (one LDS read per position, the rest
+      // by shuffles); the first position of a run insertion-sorts a run of at
+      // most 32, a longer run sends the segment to a stable LSD over every bit.
+      auto hi_of = [&](uint64_t key) { return (uint32_t)((key - e.klo) >> 32); };
+      const uint32_t rounds = (e.len + kSegThreads - 1) / kSegThreads;
+      for (uint32_t j = 0; j < rounds; ++j) {  // uniform
+        const uint32_t i = threadIdx.x + j * kSegThreads;
+        const bool in = i < e.len;
+        const uint32_t h = in ? hi_of(sm.items[i]) : 0xffffffffu;
+        uint32_t nx = (uint32_t)__shfl_down((int)h, 1), pv = (uint32_t)__shfl_up((int)h, 1);
+        if (lane == 63) nx = i + 1 < e.len ? hi_of(sm.items[i + 1]) : 0xfffffffeu;
+        if (lane == 0) pv = i > 0 && in ? hi_of(sm.items[i - 1]) : 0xfffffffdu;
+        const bool run_start = in && i + 1 < e.len && h == nx && (i == 0 || h != pv);
+        if (!run_start) continue;
         uint32_t end = i + 2;
-        while (end < e.len && end - i <= 32 && ((sm.items[end] - e.klo) >> 32) == hi_i) ++end;
+        while (end < e.len && end - i <= 32 && hi_of(sm.items[end]) == h) ++end;
         if (end - i > 32) {
           sm.flag = 1;
           continue;
@@ -565,7 +584,7 @@ __global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(const uint32_t* _
 #pragma unroll
         for (int k = 0; k < kSegItems; ++k) {
           const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
-          if (idx < e.len) K[k] = sm.items[idx];
+          K[k] = idx < e.len ? sm.items[idx] : 0ull;
         }
         __syncthreads();
         const int full = ((int)e.dbits + 7) / 8;
