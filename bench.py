@@ -32,6 +32,26 @@ sys.path.insert(0, ROOT)
 METRIC = "FPS @3,500 avatars 1080p, learned-LoD vs fixed-LoD at ≥40 dB PSNR vs full"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per frame of each stage in the learned-LoD frame at 16x16 tiles, from two rocprofv3 --pmc runs
+# (FETCH_SIZE scaled by 2.000 and WRITE_SIZE by 1.000, the factors a plain 1 GiB copy gives), summarised in
+# profiles/crowd3500_1080p_learned_lod_kernels.md. They hold only for the kernel sources they were taken on
+# (digest below) and that workload; otherwise the bench reports null.
+MEASURED_TRAFFIC = {"digest": "253bd59091ef565d", "tile": (16, 16), "lod": "learned",
+                    "bytes": {"sort": 21.53e9, "emit": 8.68e9, "project_fused": 21.36e9, "blend": 3.28e9}}
+
+
+def kernel_digest():
+    import hashlib
+
+    d = os.path.join(ROOT, "paper_2501_17792_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -266,8 +286,12 @@ def main():
     per_launch_ms = stage_ms[dom]
     per_launch_bytes = algorithmic_bytes(dom, stats, scene, uniq)
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
+    traffic = None
+    mt = MEASURED_TRAFFIC
+    if kernel_digest() == mt["digest"] and tuple(tile) == mt["tile"] and head == mt["lod"]:
+        traffic = mt["bytes"].get(dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": {"project_fused": "project_kernel (skinning fused)",
                            "emit": "bucket_count_kernel + bucket_scatter_kernel",
                            "sort": "seg_split_kernel + seg_sort_kernel"}[dom],
