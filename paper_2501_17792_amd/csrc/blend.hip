@@ -54,11 +54,18 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
   constexpr int N = TW * TH;
   constexpr int ROWS = 64 / TW;  // pixel rows per wave
   constexpr int WAVES = N / 64;
+  // A wave is split into G groups of whole pixel rows (16 lanes, or 32 for
+  // 32-wide tiles); each group walks its own list of the splats whose box
+  // reaches its rows, so a small splat occupies one group, not the wave.
+  constexpr int GL = TW > 16 ? TW : 16;  // lanes per group
+  constexpr int G = 64 / GL;
+  constexpr int GROWS = GL / TW;         // pixel rows per group
+  static_assert(WAVES * G <= 32, "group mask is 32 bits");
   __shared__ float2 s_uv[N];
   __shared__ float4 s_r1[N], s_r2[N];
   __shared__ uint32_t s_live[WAVES];
-  __shared__ uint16_t s_mask[N];            // waves whose pixel centres a splat's box reaches
-  __shared__ uint16_t s_list[WAVES][N];     // per wave: the batch's splats it must evaluate, in order
+  __shared__ uint32_t s_mask[N];            // bit wave * G + g: the splat's box reaches group g of the wave
+  __shared__ uint16_t s_list[WAVES][G][N];  // per group: the batch's splats it must evaluate, in order
   const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
   int tx, ty;
   float* out = image;
@@ -107,16 +114,17 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
     const uint32_t s = svals[idx];
     return s < n_splats ? s : 0xffffffffu;
   };
+  // Groups (all waves) whose pixel-centre rows the box reaches: group r holds
+  // rows ty0 + r * GROWS .. + GROWS - 1. A superset is harmless (those pixels
+  // see alpha < 1/255 and skip), so the bounds are widened by a little slack.
   auto wave_mask = [&](const float4& q) -> uint32_t {
-    uint32_t m = 0;
-    if (!(q.x + q.z < wx0 || q.x - q.z > wx1)) {
-#pragma unroll
-      for (int w = 0; w < WAVES; ++w) {
-        const float wy0 = ty0 + (float)(w * ROWS), wy1 = wy0 + (float)(ROWS - 1);
-        if (!(q.y + q.w < wy0 || q.y - q.w > wy1)) m |= 1u << w;
-      }
-    }
-    return m;
+    if (q.x + q.z < wx0 || q.x - q.z > wx1) return 0u;
+    const float lo = (q.y - q.w - ty0 - (float)(GROWS - 1)) * (1.f / GROWS) - 0.01f;
+    const float hi = (q.y + q.w - ty0) * (1.f / GROWS) + 0.01f;
+    const int r0 = max(0, (int)ceilf(lo)), r1 = min(WAVES * G - 1, (int)floorf(hi));
+    if (r0 > r1) return 0u;
+    const uint32_t upto = r1 >= 31 ? 0xffffffffu : ((1u << (r1 + 1)) - 1u);
+    return upto & ~((1u << r0) - 1u);
   };
   // prefetch ring: splat indices 4 batches ahead, first float4s 3 ahead, the
   // rest of a record 1 ahead (once its wave mask is known)
@@ -138,7 +146,7 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
       s_r1[threadIdx.x] = q1;
       s_r2[threadIdx.x] = q2;
     }
-    s_mask[threadIdx.x] = (uint16_t)mask;
+    s_mask[threadIdx.x] = mask;
     const uint64_t live = __ballot(!done);
     if (lane == 0) s_live[wave] = live != 0ull ? 1u : 0u;
     __syncthreads();
@@ -153,25 +161,45 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
     q0 = p1;
     p1 = p2;
     p2 = load_q0(i2);
-    mask = i0 != 0xffffffffu ? wave_mask(q0) & active : 0u;
+    mask = 0u;
+    if (i0 != 0xffffffffu) {
+      const uint32_t m = wave_mask(q0);
+      uint32_t keep = 0;  // groups of the waves still compositing
+#pragma unroll
+      for (int i = 0; i < WAVES; ++i) keep |= ((active >> i) & 1u) ? (((1u << G) - 1u) << (i * G)) : 0u;
+      mask = m & keep;
+    }
     if (mask) {
       q1 = rec[3 * (size_t)i0 + 1];
       q2 = rec[3 * (size_t)i0 + 2];
     }
     const int cnt = (int)min((uint32_t)N, end - b);
     if (__ballot(!done) != 0ull) {
-      // this wave's splats of the batch, compacted in list order
-      int n_w = 0;
+      // each group's splats of the batch, compacted in list order
+      const int grp = lane / GL;
+      int n_g[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) n_g[g] = 0;
       for (int j0 = 0; j0 < cnt; j0 += 64) {
         const int j = j0 + lane;
-        const bool hit = j < cnt && ((s_mask[j] >> wave) & 1u);
-        const uint64_t bal = __ballot(hit);
-        if (hit) s_list[wave][n_w + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)j;
-        n_w += __popcll(bal);
+        const uint32_t m = j < cnt ? (s_mask[j] >> (wave * G)) : 0u;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          const bool hit = (m >> g) & 1u;
+          const uint64_t bal = __ballot(hit);
+          if (hit) s_list[wave][g][n_g[g] + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)j;
+          n_g[g] += __popcll(bal);
+        }
       }
-      for (int k = 0; k < n_w; ++k) {
-        const int j = s_list[wave][k];
-        if (done) continue;
+      int n_max = 0, n_mine = 0;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        n_max = max(n_max, n_g[g]);
+        if (g == grp) n_mine = n_g[g];
+      }
+      for (int k = 0; k < n_max; ++k) {
+        if (done || k >= n_mine) continue;
+        const int j = s_list[wave][grp][k];
         const float4 r1 = s_r1[j];  // A B C o
         const float2 uv = s_uv[j];
         const float dx = pcx - uv.x, dy = pcy - uv.y;

@@ -99,9 +99,9 @@ struct SkinOut {
 
 struct SplatOut {
   float4* rec;             // [n][3] float4: (u v rx ry)(A B C o)(r g b depth)
-  uint32_t* rect;
-  uint32_t* count;
-  uint2* rd;               // [n] (rect, depth bits), depth bits 0 = culled: what binning reads
+  uint32_t* rect;          // [n] tile rect, emission form only (null: not written)
+  uint32_t* count;         // [n] tile count, emission form only (null: not written)
+  uint2* rd;               // [n] (rect, depth bits), depth bits 0 = culled: what bucket binning reads
 };
 
 // ---- launchers (defined in the .hip files) ------------------------------
@@ -126,6 +126,8 @@ hipError_t launch_skin(WorkDev w, SkinOut out, int chunk_lo, int chunk_hi, int g
 hipError_t launch_project(WorkDev w, SkinOut skinned, int fused, CamDev cam, SplatOut out,
                           uint32_t max_splats, int chunk_lo, int chunk_hi, int grid,
                           hipStream_t st);
+hipError_t launch_expand_rd(const uint2* rd, const uint32_t* n_ptr, uint32_t* rect, uint32_t* count, int grid,
+                            hipStream_t st);
 hipError_t launch_scan_counts(const uint32_t* count, uint32_t* pair_off, uint32_t* block_sums,
                               int max_blocks, FrameHdr* hdr, uint32_t max_pairs, hipStream_t st);
 hipError_t launch_emit(const uint32_t* count, const uint32_t* pair_off, const uint32_t* rect,

@@ -56,9 +56,11 @@ __device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOu
     out.rec[3 * s + 0] = r.r0;
     out.rec[3 * s + 1] = r.r1;
     out.rec[3 * s + 2] = r.r2;
-    out.rect[s] = r.rect;
-    out.count[s] = r.count;
-    out.rd[s] = make_uint2(r.rect, r.count ? __float_as_uint(r.r2.w) : 0u);
+    if (out.rect) {  // emission form
+      out.rect[s] = r.rect;
+      out.count[s] = r.count;
+    }
+    if (out.rd) out.rd[s] = make_uint2(r.rect, r.count ? __float_as_uint(r.r2.w) : 0u);  // bucket form
     vis += r.count ? 1u : 0u;
   }
   return vis;
@@ -105,6 +107,27 @@ hipError_t launch_project(WorkDev w, SkinOut skinned, int fused, CamDev cam, Spl
                           hipStream_t st) {
   if (grid <= 0) return hipSuccess;
   project_kernel<<<grid, kChunkThreads, 0, st>>>(w, skinned, fused, cam, out, chunk_lo, chunk_hi);
+  return hipGetLastError();
+}
+
+// Rect and tile count per splat from the (rect, depth bits) pairs binning
+// reads (depth bits 0 = culled), for the consumers of the emission-form
+// arrays after a frame binned in bucket form.
+__global__ __launch_bounds__(256) void expand_rd_kernel(const uint2* __restrict__ rd, const uint32_t* n_ptr,
+                                                        uint32_t* __restrict__ rect, uint32_t* __restrict__ count) {
+  const uint32_t n = *n_ptr;
+  for (uint32_t s = blockIdx.x * 256u + threadIdx.x; s < n; s += gridDim.x * 256u) {
+    const uint2 e = rd[s];
+    const uint32_t x0 = e.x & 0xffu, y0 = (e.x >> 8) & 0xffu, x1 = (e.x >> 16) & 0xffu, y1 = e.x >> 24;
+    rect[s] = e.x;
+    count[s] = e.y ? (x1 - x0 + 1u) * (y1 - y0 + 1u) : 0u;
+  }
+}
+
+hipError_t launch_expand_rd(const uint2* rd, const uint32_t* n_ptr, uint32_t* rect, uint32_t* count, int grid,
+                            hipStream_t st) {
+  if (grid <= 0) return hipSuccess;
+  expand_rd_kernel<<<grid, 256, 0, st>>>(rd, n_ptr, rect, count);
   return hipGetLastError();
 }
 

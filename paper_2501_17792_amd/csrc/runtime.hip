@@ -746,7 +746,9 @@ static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs
   HIP_TRY(launch_frame_reset(ctx->hdr, ctx->hist, kHistLen, 0, ctx->stream));
   // A4 projection
   SkinOut so{ctx->skin_mu, ctx->skin_cov, ctx->skin_zz};
-  SplatOut po{ctx->rec, ctx->rect, ctx->cnt, ctx->rd};
+  // bucket frames write only the (rect, depth) pairs their binning reads;
+  // the emission-form arrays are rebuilt from them on demand
+  SplatOut po{ctx->rec, bucket ? nullptr : ctx->rect, bucket ? nullptr : ctx->cnt, bucket ? ctx->rd : nullptr};
   const int fused = ctx->opt.fuse_skin_project;
   const int64_t n_chunks = ctx->capturing ? ctx->cap_chunks : ctx->hdr_host->n_chunks;
   ctx->mark(CS_STAGE_PROJECT, 0);
@@ -923,10 +925,14 @@ cs_status cs_mlp_train_step(cs_ctx* ctx, cs_mlp* net, float* adam_m, float* adam
 
 // The tile-bucket binning needs no per-splat pair offsets; the backward pass
 // (per-pair gradient slots) and inspection compute them on demand.
+// Rects, tile counts and their scan for a frame binned in bucket form (the
+// emission form writes them in every frame).
 static cs_status ensure_pair_offsets(cs_ctx* ctx) {
   if (ctx->pair_off_valid) return CS_OK;
   const int64_t n_splats = ctx->hdr_host->n_splats;
   const int scan_blocks = (int)std::max<int64_t>(1, (n_splats + scan_tile() - 1) / scan_tile());
+  HIP_TRY(launch_expand_rd(ctx->rd, &ctx->hdr->n_splats, ctx->rect, ctx->cnt,
+                           persistent_grid((n_splats + 255) / 256, 2048), ctx->stream));
   HIP_TRY(launch_scan_counts(ctx->cnt, ctx->pair_off, ctx->scan_sums, scan_blocks, ctx->hdr, kMaxPairsLimit,
                              ctx->stream));
   ctx->pair_off_valid = true;
@@ -1095,7 +1101,7 @@ cs_status cs_debug_copy(cs_ctx* ctx, int32_t which, void* host_dst, int64_t offs
   const void* src = nullptr;
   int64_t size = 0;
   const bool pair_buf = which == CS_BUF_PAIR_OFF || which == CS_BUF_KEYS || which == CS_BUF_VALS ||
-                        which == CS_BUF_SKEYS;
+                        which == CS_BUF_SKEYS || which == CS_BUF_RECT || which == CS_BUF_COUNT;
   if (pair_buf && ctx->bucket_frame && ctx->state >= kRendered && !ctx->debug_pairs) {
     // rebuild what the emission form keeps: pair offsets, emission-order
     // pairs (second buffers) and the sorted keys (first key buffer)

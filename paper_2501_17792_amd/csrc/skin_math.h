@@ -155,12 +155,15 @@ __device__ __forceinline__ void project_gaussian(const Posed& p, float opacity,
   const float ty = fmaf(R[3], dx, fmaf(R[4], dy, R[5] * dz));
   const float tz = fmaf(R[6], dx, fmaf(R[7], dy, R[8] * dz));
   if (!(tz > cam.near_plane)) return;
-  const float xn = tx / tz, yn = ty / tz;
+  // One hardware reciprocal (1 ulp) serves the perspective divide and the
+  // Jacobian; tz > near > 0, so no special cases arise.
+  const float itz = __builtin_amdgcn_rcpf(tz);
+  const float xn = tx * itz, yn = ty * itz;
   if (fabsf(xn) > cam.lim_x || fabsf(yn) > cam.lim_y) return;
   const float u = fmaf(cam.fx, xn, cam.cx);
   const float v = fmaf(cam.fy, yn, cam.cy);
-  const float j00 = cam.fx / tz, j11 = cam.fy / tz;
-  const float j02 = -(cam.fx * xn) / tz, j12 = -(cam.fy * yn) / tz;
+  const float j00 = cam.fx * itz, j11 = cam.fy * itz;
+  const float j02 = -(cam.fx * xn) * itz, j12 = -(cam.fy * yn) * itz;
   float T0[3], T1[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
@@ -180,9 +183,11 @@ __device__ __forceinline__ void project_gaussian(const Posed& p, float opacity,
   const float det = a * c - b * b;
   if (!(det > 0.f)) return;
   if (opacity < (1.f / 255.f)) return;
-  const float k = 2.f * logf(fmaxf(255.f * opacity, 1.f)) * (1.f + 1e-4f);
-  const float rx = sqrtf(k * a) + 0.01f;
-  const float ry = sqrtf(k * c) + 0.01f;
+  // k = 2 ln(255 o) (1 + 1e-4); hardware log2 and sqrt (1 ulp each) sit far
+  // inside the 1e-4 relative and 0.01 px margins of the box
+  const float k = (2.f * 0.6931471805599453f) * __builtin_amdgcn_logf(fmaxf(255.f * opacity, 1.f)) * (1.f + 1e-4f);
+  const float rx = __builtin_amdgcn_sqrtf(k * a) + 0.01f;
+  const float ry = __builtin_amdgcn_sqrtf(k * c) + 0.01f;
   const float fx0 = floorf(u - rx), fx1 = floorf(u + rx);
   const float fy0 = floorf(v - ry), fy1 = floorf(v + ry);
   if (fx1 < 0.f || fx0 > (float)(cam.W - 1) || fy1 < 0.f || fy0 > (float)(cam.H - 1)) return;
@@ -194,12 +199,13 @@ __device__ __forceinline__ void project_gaussian(const Posed& p, float opacity,
   float d0 = fmaf(L[0], dx, fmaf(L[3], dy, L[6] * dz));
   float d1 = fmaf(L[1], dx, fmaf(L[4], dy, L[7] * dz));
   float d2 = fmaf(L[2], dx, fmaf(L[5], dy, L[8] * dz));
-  const float inv = 1.f / sqrtf(fmaf(d0, d0, fmaf(d1, d1, d2 * d2)));
+  const float inv = __builtin_amdgcn_rsqf(fmaf(d0, d0, fmaf(d1, d1, d2 * d2)));
   d0 *= inv; d1 *= inv; d2 *= inv;
   float rgb[3];
   sh_colour<DEG>(sh_planes, sh_stride, d0, d1, d2, rgb);
   out.r0 = make_float4(u, v, rx, ry);
-  out.r1 = make_float4(c / det, -b / det, a / det, opacity);
+  const float idet = __builtin_amdgcn_rcpf(det);  // det >= 0.09 (the 0.3 px^2 low-pass)
+  out.r1 = make_float4(c * idet, -b * idet, a * idet, opacity);
   out.r2 = make_float4(rgb[0], rgb[1], rgb[2], tz);
   out.rect = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) | ((uint32_t)y1 << 24);
   out.count = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
