@@ -197,27 +197,40 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
         n_max = max(n_max, n_g[g]);
         if (g == grp) n_mine = n_g[g];
       }
+      // Software pipeline: while entry k is evaluated, the record of entry
+      // k + 1 and the list index of entry k + 3 are read, and the evaluation
+      // is branch-free (selects), so no LDS latency sits on the loop's path.
+      // Lanes past their list (or finished) read slot 0 and discard it; for
+      // live lanes the arithmetic is that of a plain walk of the list.
+      const uint16_t* my_list = s_list[wave][grp];
+      const int j0 = n_mine > 0 ? my_list[0] : 0;
+      int j1 = n_mine > 1 ? my_list[1] : 0, j2 = n_mine > 2 ? my_list[2] : 0;
+      float4 pf_r1 = s_r1[j0], pf_r2 = s_r2[j0];
+      float2 pf_uv = s_uv[j0];
       for (int k = 0; k < n_max; ++k) {
-        if (done || k >= n_mine) continue;
-        const int j = s_list[wave][grp][k];
-        const float4 r1 = s_r1[j];  // A B C o
-        const float2 uv = s_uv[j];
+        const float4 r1 = pf_r1;  // A B C o
+        const float2 uv = pf_uv;
+        const float4 r2 = pf_r2;  // r g b depth
+        pf_r1 = s_r1[j1];
+        pf_uv = s_uv[j1];
+        pf_r2 = s_r2[j1];
+        j1 = j2;
+        j2 = k + 3 < n_mine ? my_list[k + 3] : 0;
+        const bool live = !done && k < n_mine;
         const float dx = pcx - uv.x, dy = pcy - uv.y;
         float power = -0.5f * fmaf(r1.x * dx, dx, r1.z * dy * dy) - r1.y * dx * dy;
         power = fminf(power, 0.f);
         const float alpha = fminf(0.99f, r1.w * __expf(power));
-        if (alpha < (1.f / 255.f)) continue;
         const float Tn = T * (1.f - alpha);
-        if (Tn < 1e-4f) {
-          done = true;
-          continue;
-        }
-        const float4 r2 = s_r2[j];  // r g b depth
+        const bool hit = live && alpha >= (1.f / 255.f);
+        const bool stop = hit && Tn < 1e-4f;  // stops without adding this splat
+        const bool add = hit && !stop;
         const float wgt = alpha * T;
-        cr = fmaf(r2.x, wgt, cr);
-        cg = fmaf(r2.y, wgt, cg);
-        cb = fmaf(r2.z, wgt, cb);
-        T = Tn;
+        cr = add ? fmaf(r2.x, wgt, cr) : cr;
+        cg = add ? fmaf(r2.y, wgt, cg) : cg;
+        cb = add ? fmaf(r2.z, wgt, cb) : cb;
+        T = add ? Tn : T;
+        done = done || stop;
       }
     }
     if (__syncthreads_count(!done) == 0) break;

@@ -39,12 +39,17 @@ def pack(params: dict, mu, sd, pca_mean, pca_basis) -> cs.CsMlp:
     put("w3", np.asarray(params["W3"]).T)
     put("b3", params["b3"])
     ctypes.memmove(net.params, flat.ctypes.data, flat.nbytes)
-    mu = np.asarray(mu, np.float32)
+    # every source array is held in a name until its copy is done: a
+    # temporary's buffer may be freed (and reused) before memmove reads it
+    mu = np.ascontiguousarray(mu, np.float32)
     isd = (1.0 / np.asarray(sd, np.float64)).astype(np.float32)
+    pm = np.ascontiguousarray(pca_mean, np.float32)
+    pb = np.ascontiguousarray(pca_basis, np.float32)
+    assert mu.size == 32 and isd.size == 32 and pm.size == 72 and pb.size == 8 * 72
     ctypes.memmove(net.mu, mu.ctypes.data, 128)
     ctypes.memmove(net.inv_sd, isd.ctypes.data, 128)
-    ctypes.memmove(net.pca_mean, np.asarray(pca_mean, np.float32).ctypes.data, 72 * 4)
-    ctypes.memmove(net.pca_basis, np.ascontiguousarray(pca_basis, np.float32).ctypes.data, 8 * 72 * 4)
+    ctypes.memmove(net.pca_mean, pm.ctypes.data, 72 * 4)
+    ctypes.memmove(net.pca_basis, pb.ctypes.data, 8 * 72 * 4)
     return net
 
 
