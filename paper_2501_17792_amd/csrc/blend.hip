@@ -54,18 +54,20 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
   constexpr int N = TW * TH;
   constexpr int ROWS = 64 / TW;  // pixel rows per wave
   constexpr int WAVES = N / 64;
-  // A wave is split into G groups of whole pixel rows (16 lanes, or 32 for
-  // 32-wide tiles); each group walks its own list of the splats whose box
-  // reaches its rows, so a small splat occupies one group, not the wave.
-  constexpr int GL = TW > 16 ? TW : 16;  // lanes per group
+  // A wave is split into G groups of 8 lanes, each 8 neighbouring pixels of
+  // one row (lane l is in group l / 8). Every group walks its own list of the
+  // batch's splats whose box reaches one of its still-unfinished pixels, so a
+  // small splat occupies the few groups it touches, not the whole wave.
+  constexpr int GL = 8;
   constexpr int G = 64 / GL;
-  constexpr int GROWS = GL / TW;         // pixel rows per group
-  static_assert(WAVES * G <= 32, "group mask is 32 bits");
-  __shared__ float2 s_uv[N];
-  __shared__ float4 s_r1[N], s_r2[N];
+  constexpr int SEGS = TW / GL;                 // groups per pixel row
+  constexpr int SUB = N < 256 ? N : 256;        // batch entries listed at a time (8-bit list offsets)
+  static_assert(TW % GL == 0 && TH <= 32, "tile shape");
+  __shared__ float4 s_q[N];                     // u v rx ry
+  __shared__ float4 s_r1[N], s_r2[N];           // A B C o | r g b depth
   __shared__ uint32_t s_live[WAVES];
-  __shared__ uint32_t s_mask[N];            // bit wave * G + g: the splat's box reaches group g of the wave
-  __shared__ uint16_t s_list[WAVES][G][N];  // per group: the batch's splats it must evaluate, in order
+  __shared__ uint32_t s_mask[N];                // bit r: the splat's box reaches pixel row r of the tile
+  __shared__ uint8_t s_list[WAVES][G][SUB];     // per group: offsets of the splats it must evaluate, in order
   const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
   int tx, ty;
   float* out = image;
@@ -104,136 +106,162 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
   const uint32_t n_splats = hdr->n_splats;
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
   bool done = !inside;
-  // Software pipeline over batches (see the prefetch ring below). A record's
-  // first float4 (u v rx ry) decides which waves its alpha >= 1/255 box
-  // reaches; the other two are only fetched when one of those waves still has
-  // unfinished pixels (finished waves stay finished, so the activity of the
-  // batch before is a safe superset).
-  auto load_index = [&](uint32_t idx) -> uint32_t {
-    if (idx >= end) return 0xffffffffu;
-    const uint32_t s = svals[idx];
-    return s < n_splats ? s : 0xffffffffu;
+  // Software pipeline over batches: the tile's list entries are read 4
+  // batches ahead and whole records 2 ahead, into two-slot register rings
+  // (the loop is unrolled twice with the slots swapped, so no register a load
+  // is still filling is ever copied). Every load is unconditional: a lane
+  // past the list reads the last entry, an invalid entry reads splat 0's
+  // record, and validity is applied where the value is used, so no wait for
+  // a load sits early in the batch.
+  auto load_entry = [&](uint32_t pos) -> uint32_t { return svals[min(pos, end - 1u)]; };
+  auto splat_of = [&](uint32_t pos, uint32_t e) -> uint32_t {
+    return pos < end && e < n_splats ? e : 0xffffffffu;
   };
-  // Groups (all waves) whose pixel-centre rows the box reaches: group r holds
-  // rows ty0 + r * GROWS .. + GROWS - 1. A superset is harmless (those pixels
-  // see alpha < 1/255 and skip), so the bounds are widened by a little slack.
-  auto wave_mask = [&](const float4& q) -> uint32_t {
+  auto load_rec = [&](uint32_t s, float4& r0, float4& r1, float4& r2) {
+    const size_t o = 3 * (size_t)(s != 0xffffffffu ? s : 0u);
+    r0 = rec[o];
+    r1 = rec[o + 1];
+    r2 = rec[o + 2];
+  };
+  // Pixel rows of the tile whose centres the alpha >= 1/255 box reaches
+  // (none if it misses the tile's columns). A superset is harmless (those
+  // pixels see alpha < 1/255 and skip), so the bounds get a little slack.
+  auto row_mask = [&](const float4& q) -> uint32_t {
     if (q.x + q.z < wx0 || q.x - q.z > wx1) return 0u;
-    const float lo = (q.y - q.w - ty0 - (float)(GROWS - 1)) * (1.f / GROWS) - 0.01f;
-    const float hi = (q.y + q.w - ty0) * (1.f / GROWS) + 0.01f;
-    const int r0 = max(0, (int)ceilf(lo)), r1 = min(WAVES * G - 1, (int)floorf(hi));
+    const int r0 = max(0, (int)ceilf(q.y - q.w - ty0 - 0.01f));
+    const int r1 = min(TH - 1, (int)floorf(q.y + q.w - ty0 + 0.01f));
     if (r0 > r1) return 0u;
     const uint32_t upto = r1 >= 31 ? 0xffffffffu : ((1u << (r1 + 1)) - 1u);
     return upto & ~((1u << r0) - 1u);
   };
-  // prefetch ring: splat indices 4 batches ahead, first float4s 3 ahead, the
-  // rest of a record 1 ahead (once its wave mask is known)
-  auto load_q0 = [&](uint32_t s) -> float4 {
-    return s != 0xffffffffu ? rec[3 * (size_t)s] : make_float4(0.f, 0.f, 0.f, 0.f);
-  };
-  uint32_t i0 = load_index(start + threadIdx.x), i1 = load_index(start + N + threadIdx.x);
-  uint32_t i2 = load_index(start + 2 * N + threadIdx.x), i3 = load_index(start + 3 * N + threadIdx.x);
-  float4 q0 = load_q0(i0), p1 = load_q0(i1), p2 = load_q0(i2);
-  float4 q1 = make_float4(0.f, 0.f, 0.f, 0.f), q2 = q1;
-  uint32_t mask = i0 != 0xffffffffu ? wave_mask(q0) : 0u;
-  if (mask) {
-    q1 = rec[3 * (size_t)i0 + 1];
-    q2 = rec[3 * (size_t)i0 + 2];
-  }
-  for (uint32_t b = start; b < end; b += N) {
-    if (mask) {
-      s_uv[threadIdx.x] = make_float2(q0.x, q0.y);
-      s_r1[threadIdx.x] = q1;
-      s_r2[threadIdx.x] = q2;
-    }
-    s_mask[threadIdx.x] = mask;
-    const uint64_t live = __ballot(!done);
-    if (lane == 0) s_live[wave] = live != 0ull ? 1u : 0u;
-    __syncthreads();
-    uint32_t active = 0;
+  if (start < end) {  // uniform; an empty tile reads nothing
+    const uint32_t tid = threadIdx.x;
+    // loads issued in the loop's own order (record, then entry, per slot)
+    const uint32_t e0 = load_entry(start + tid), e1 = load_entry(start + N + tid);
+    float4 ra0, ra1, ra2, rb0, rb1, rb2;
+    uint32_t sa = splat_of(start + tid, e0);
+    asm volatile("" : "+v"(sa));
+    load_rec(sa, ra0, ra1, ra2);
+    uint32_t ea = load_entry(start + 2 * N + tid);
+    uint32_t sb = splat_of(start + N + tid, e1);
+    asm volatile("" : "+v"(sb));
+    load_rec(sb, rb0, rb1, rb2);
+    uint32_t eb = load_entry(start + 3 * N + tid);
+    uint32_t active = (1u << WAVES) - 1u;  // waves with unfinished pixels at the last barrier
+    // One batch b. In: S, R = splat index and record of this lane's entry of
+    // batch b, E = raw list entry of batch b + 2. Out: S, R of batch b + 2,
+    // E of batch b + 4. Returns whether any pixel of the tile is unfinished.
+    auto step = [&](uint32_t b, uint32_t& E, uint32_t& S, float4& R0, float4& R1, float4& R2) -> bool {
+      uint32_t mask = 0u;
+      if (S != 0xffffffffu) {
+        uint32_t keep = 0;  // rows of the waves still compositing (finished waves stay finished)
 #pragma unroll
-    for (int w = 0; w < WAVES; ++w) active |= s_live[w] << w;
-    // advance the ring by one batch and start its loads
-    i0 = i1;
-    i1 = i2;
-    i2 = i3;
-    i3 = load_index(b + 4 * N + threadIdx.x);
-    q0 = p1;
-    p1 = p2;
-    p2 = load_q0(i2);
-    mask = 0u;
-    if (i0 != 0xffffffffu) {
-      const uint32_t m = wave_mask(q0);
-      uint32_t keep = 0;  // groups of the waves still compositing
+        for (int i = 0; i < WAVES; ++i) keep |= ((active >> i) & 1u) ? (((1u << ROWS) - 1u) << (i * ROWS)) : 0u;
+        mask = row_mask(R0) & keep;
+      }
+      if (mask) {
+        s_q[tid] = R0;
+        s_r1[tid] = R1;
+        s_r2[tid] = R2;
+      }
+      s_mask[tid] = mask;
+      const uint64_t live = __ballot(!done);
+      if (lane == 0) s_live[wave] = live != 0ull ? 1u : 0u;
+      __syncthreads();
+      active = 0;
 #pragma unroll
-      for (int i = 0; i < WAVES; ++i) keep |= ((active >> i) & 1u) ? (((1u << G) - 1u) << (i * G)) : 0u;
-      mask = m & keep;
-    }
-    if (mask) {
-      q1 = rec[3 * (size_t)i0 + 1];
-      q2 = rec[3 * (size_t)i0 + 2];
-    }
-    const int cnt = (int)min((uint32_t)N, end - b);
-    if (__ballot(!done) != 0ull) {
-      // each group's splats of the batch, compacted in list order
-      const int grp = lane / GL;
-      int n_g[G];
-#pragma unroll
-      for (int g = 0; g < G; ++g) n_g[g] = 0;
-      for (int j0 = 0; j0 < cnt; j0 += 64) {
-        const int j = j0 + lane;
-        const uint32_t m = j < cnt ? (s_mask[j] >> (wave * G)) : 0u;
+      for (int w = 0; w < WAVES; ++w) active |= s_live[w] << w;
+      S = splat_of(b + 2 * N + tid, E);
+      asm volatile("" : "+v"(S));  // the select happens here, so E's old value dies before its reload
+      load_rec(S, R0, R1, R2);
+      const int cnt = (int)min((uint32_t)N, end - b);
+      const uint64_t livem = __ballot(!done);
+      if (livem != 0ull) {
+        // Each group's live pixel-centre span (wave-uniform): a splat whose
+        // box misses it cannot change any unfinished pixel of the group.
+        float gx0[G], gx1[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-          const bool hit = (m >> g) & 1u;
-          const uint64_t bal = __ballot(hit);
-          if (hit) s_list[wave][g][n_g[g] + __popcll(bal & ((1ull << lane) - 1ull))] = (uint16_t)j;
-          n_g[g] += __popcll(bal);
+          const uint32_t bits = (uint32_t)(livem >> (GL * g)) & 0xffu;
+          const float xg = (float)(tx * TW + (g % SEGS) * GL) + 0.5f;
+          gx0[g] = bits ? xg + (float)(__builtin_ctz(bits)) : 3.0e38f;
+          gx1[g] = bits ? xg + (float)(31 - __builtin_clz(bits)) : -3.0e38f;
+        }
+        const int grp = lane / GL;
+        const uint32_t wrow0 = (uint32_t)(wave * ROWS);
+        for (int sb = 0; sb < cnt; sb += SUB) {
+          const int sn = min(SUB, cnt - sb);
+          // each group's splats of this part of the batch, compacted in list order
+          int n_g[G];
+#pragma unroll
+          for (int g = 0; g < G; ++g) n_g[g] = 0;
+          for (int j0 = 0; j0 < sn; j0 += 64) {
+            const int j = j0 + lane;
+            const uint32_t rows = j < sn ? (s_mask[sb + j] >> wrow0) & ((1u << ROWS) - 1u) : 0u;
+            float u = 0.f, rx = -1.f;
+            if (rows) {
+              const float4 q = s_q[sb + j];
+              u = q.x;
+              rx = q.z;
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+              const bool hit = ((rows >> (g / SEGS)) & 1u) && !(u + rx < gx0[g] || u - rx > gx1[g]);
+              const uint64_t bal = __ballot(hit);
+              if (hit) s_list[wave][g][n_g[g] + __popcll(bal & ((1ull << lane) - 1ull))] = (uint8_t)j;
+              n_g[g] += __popcll(bal);
+            }
+          }
+          int n_max = 0, n_mine = 0;
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            n_max = max(n_max, n_g[g]);
+            if (g == grp) n_mine = n_g[g];
+          }
+          // Software pipeline: while entry k is evaluated, the record of entry
+          // k + 1 and the list offset of entry k + 3 are read, and the
+          // evaluation is branch-free (selects), so no LDS latency sits on the
+          // loop's path. Lanes past their list (or finished) read slot sb and
+          // discard it; for live lanes the arithmetic is that of a plain walk.
+          const uint8_t* my_list = s_list[wave][grp];
+          const int j0 = sb + (n_mine > 0 ? my_list[0] : 0);
+          int j1 = sb + (n_mine > 1 ? my_list[1] : 0), j2 = sb + (n_mine > 2 ? my_list[2] : 0);
+          float4 pf_r1 = s_r1[j0], pf_r2 = s_r2[j0];
+          float2 pf_uv = make_float2(s_q[j0].x, s_q[j0].y);
+          for (int k = 0; k < n_max; ++k) {
+            const float4 r1 = pf_r1;  // A B C o
+            const float2 uv = pf_uv;
+            const float4 r2 = pf_r2;  // r g b depth
+            pf_r1 = s_r1[j1];
+            pf_uv = make_float2(s_q[j1].x, s_q[j1].y);
+            pf_r2 = s_r2[j1];
+            j1 = j2;
+            j2 = sb + (k + 3 < n_mine ? my_list[k + 3] : 0);
+            const bool live = !done && k < n_mine;
+            const float dx = pcx - uv.x, dy = pcy - uv.y;
+            float power = -0.5f * fmaf(r1.x * dx, dx, r1.z * dy * dy) - r1.y * dx * dy;
+            power = fminf(power, 0.f);
+            const float alpha = fminf(0.99f, r1.w * __expf(power));
+            const float Tn = T * (1.f - alpha);
+            const bool hit = live && alpha >= (1.f / 255.f);
+            const bool stop = hit && Tn < 1e-4f;  // stops without adding this splat
+            const bool add = hit && !stop;
+            const float wgt = alpha * T;
+            cr = add ? fmaf(r2.x, wgt, cr) : cr;
+            cg = add ? fmaf(r2.y, wgt, cg) : cg;
+            cb = add ? fmaf(r2.z, wgt, cb) : cb;
+            T = add ? Tn : T;
+            done = done || stop;
+          }
         }
       }
-      int n_max = 0, n_mine = 0;
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        n_max = max(n_max, n_g[g]);
-        if (g == grp) n_mine = n_g[g];
-      }
-      // Software pipeline: while entry k is evaluated, the record of entry
-      // k + 1 and the list index of entry k + 3 are read, and the evaluation
-      // is branch-free (selects), so no LDS latency sits on the loop's path.
-      // Lanes past their list (or finished) read slot 0 and discard it; for
-      // live lanes the arithmetic is that of a plain walk of the list.
-      const uint16_t* my_list = s_list[wave][grp];
-      const int j0 = n_mine > 0 ? my_list[0] : 0;
-      int j1 = n_mine > 1 ? my_list[1] : 0, j2 = n_mine > 2 ? my_list[2] : 0;
-      float4 pf_r1 = s_r1[j0], pf_r2 = s_r2[j0];
-      float2 pf_uv = s_uv[j0];
-      for (int k = 0; k < n_max; ++k) {
-        const float4 r1 = pf_r1;  // A B C o
-        const float2 uv = pf_uv;
-        const float4 r2 = pf_r2;  // r g b depth
-        pf_r1 = s_r1[j1];
-        pf_uv = s_uv[j1];
-        pf_r2 = s_r2[j1];
-        j1 = j2;
-        j2 = k + 3 < n_mine ? my_list[k + 3] : 0;
-        const bool live = !done && k < n_mine;
-        const float dx = pcx - uv.x, dy = pcy - uv.y;
-        float power = -0.5f * fmaf(r1.x * dx, dx, r1.z * dy * dy) - r1.y * dx * dy;
-        power = fminf(power, 0.f);
-        const float alpha = fminf(0.99f, r1.w * __expf(power));
-        const float Tn = T * (1.f - alpha);
-        const bool hit = live && alpha >= (1.f / 255.f);
-        const bool stop = hit && Tn < 1e-4f;  // stops without adding this splat
-        const bool add = hit && !stop;
-        const float wgt = alpha * T;
-        cr = add ? fmaf(r2.x, wgt, cr) : cr;
-        cg = add ? fmaf(r2.y, wgt, cg) : cg;
-        cb = add ? fmaf(r2.z, wgt, cb) : cb;
-        T = add ? Tn : T;
-        done = done || stop;
-      }
+      E = load_entry(b + 4 * N + tid);  // issued last: E's old value is dead by now
+      return __syncthreads_count(!done) != 0;
+    };
+    for (uint32_t b = start;;) {
+      if (!step(b, ea, sa, ra0, ra1, ra2) || (b += N) >= end) break;
+      if (!step(b, eb, sb, rb0, rb1, rb2) || (b += N) >= end) break;
     }
-    if (__syncthreads_count(!done) == 0) break;
   }
   if (inside) {
     const size_t plane = (size_t)out_w * out_h;
