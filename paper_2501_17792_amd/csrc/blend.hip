@@ -62,7 +62,7 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
   constexpr int G = 64 / GL;
   constexpr int SEGS = TW / GL;                 // groups per pixel row
   constexpr int SUB = N < 256 ? N : 256;        // batch entries listed at a time (8-bit list offsets)
-  static_assert(TW % GL == 0 && TH <= 32, "tile shape");
+  static_assert(TW % GL == 0 && TH <= 32 && (SUB & (SUB - 1)) == 0, "tile shape");
   __shared__ float4 s_q[N];                     // u v rx ry
   __shared__ float4 s_r1[N], s_r2[N];           // A B C o | r g b depth
   __shared__ uint32_t s_live[WAVES];
@@ -218,25 +218,22 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
             n_max = max(n_max, n_g[g]);
             if (g == grp) n_mine = n_g[g];
           }
-          // Software pipeline: while entry k is evaluated, the record of entry
-          // k + 1 and the list offset of entry k + 3 are read, and the
-          // evaluation is branch-free (selects), so no LDS latency sits on the
-          // loop's path. Lanes past their list (or finished) read slot sb and
-          // discard it; for live lanes the arithmetic is that of a plain walk.
+          // Software pipeline over the group's list: two register sets (A, B)
+          // hold the records of entries k and k + 1; each is refilled with
+          // entry k + 2 (k + 3) right after its evaluation, and list offsets
+          // are read two entries before they are needed. The loop is unrolled
+          // twice with the sets swapped, so no register an LDS read is still
+          // filling is copied, and every read is unconditional (offsets past
+          // the list are masked into the batch and their lanes discard the
+          // result). The evaluation is branch-free; for live lanes its
+          // arithmetic is that of a plain front-to-back walk.
           const uint8_t* my_list = s_list[wave][grp];
-          const int j0 = sb + (n_mine > 0 ? my_list[0] : 0);
-          int j1 = sb + (n_mine > 1 ? my_list[1] : 0), j2 = sb + (n_mine > 2 ? my_list[2] : 0);
-          float4 pf_r1 = s_r1[j0], pf_r2 = s_r2[j0];
-          float2 pf_uv = make_float2(s_q[j0].x, s_q[j0].y);
-          for (int k = 0; k < n_max; ++k) {
-            const float4 r1 = pf_r1;  // A B C o
-            const float2 uv = pf_uv;
-            const float4 r2 = pf_r2;  // r g b depth
-            pf_r1 = s_r1[j1];
-            pf_uv = make_float2(s_q[j1].x, s_q[j1].y);
-            pf_r2 = s_r2[j1];
-            j1 = j2;
-            j2 = sb + (k + 3 < n_mine ? my_list[k + 3] : 0);
+          auto off = [&](int k) -> int { return sb + (int)(my_list[min(k, SUB - 1)] & (SUB - 1)); };
+          int jA = off(0), jB = off(1);
+          float4 a1 = s_r1[jA], a2 = s_r2[jA], b1 = s_r1[jB], b2 = s_r2[jB];
+          float2 au = make_float2(s_q[jA].x, s_q[jA].y), bu = make_float2(s_q[jB].x, s_q[jB].y);
+          int oA = off(2), oB = off(3);
+          auto eval = [&](int k, const float4& r1, const float2& uv, const float4& r2) {
             const bool live = !done && k < n_mine;
             const float dx = pcx - uv.x, dy = pcy - uv.y;
             float power = -0.5f * fmaf(r1.x * dx, dx, r1.z * dy * dy) - r1.y * dx * dy;
@@ -252,6 +249,22 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
             cb = add ? fmaf(r2.z, wgt, cb) : cb;
             T = add ? Tn : T;
             done = done || stop;
+          };
+          // (k + 1 = n_max in the last pass: its lanes are all past their
+          // lists, so that half changes nothing)
+          for (int k = 0; k < n_max; k += 2) {
+            eval(k, a1, au, a2);
+            a1 = s_r1[oA];
+            a2 = s_r2[oA];
+            au = make_float2(s_q[oA].x, s_q[oA].y);
+            oA = off(k + 4);
+            __builtin_amdgcn_sched_barrier(0);  // keep the refill ahead of the other set's evaluation
+            eval(k + 1, b1, bu, b2);
+            b1 = s_r1[oB];
+            b2 = s_r2[oB];
+            bu = make_float2(s_q[oB].x, s_q[oB].y);
+            oB = off(k + 5);
+            __builtin_amdgcn_sched_barrier(0);
           }
         }
       }
