@@ -402,20 +402,9 @@ __global__ __launch_bounds__(kBkThreads) void seg_split_kernel(int level, const 
 // ---------------------------------------------------------------------------
 // 5. LDS sort of one segment of at most kSegCap keys. Keys live in registers
 // in block order i = wave * 1024 + k * 64 + lane; each LSD pass ranks 8-bit
-// digits stably (match over the digit bits inside a wave, per-wave digit
-// counts in LDS) and exchanges the keys through LDS.
+// digits stably (per-wave digit counts taken by LDS atomics, which return
+// their old values in lane order) and exchanges the keys through LDS.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t match8(uint32_t d) {  // lanes holding the same 8-bit digit
-  uint64_t m = ~0ull;
-#pragma unroll
-  for (int b = 0; b < 8; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t ones = __ballot(bit);
-    m &= bit ? ones : ~ones;
-  }
-  return m;
-}
-
 struct SegSmem {
   uint64_t items[kSegCap];
   uint32_t whist[kSegWaves * 256];
@@ -434,32 +423,16 @@ __device__ void lsd_pass(SegSmem& sm, uint64_t (&K)[kSegItems], uint32_t len, ui
   for (int i = threadIdx.x; i < kSegWaves * 256; i += kSegThreads) sm.whist[i] = 0;
   __syncthreads();
   uint32_t* wh = sm.whist + wave * 256;
-  // Rank inside the wave: per item slot, one lane per digit (the leader)
-  // takes the digit's running count with an atomic add that returns it. A
-  // wave's LDS atomics are applied in issue order, so all slots' atomics can
-  // be in flight at once; the other lanes get their leader's value after.
-  uint32_t ret[kSegItems], info[kSegItems / 2];  // info: leader | prefix << 8, two per register
-#pragma unroll
-  for (int k = 0; k < kSegItems / 2; ++k) info[k] = 0;
-#pragma unroll
-  for (int k = 0; k < kSegItems; ++k) {
-    const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
-    const bool v = idx < len;
-    const uint64_t vmask = __ballot(v);
-    ret[k] = 0;
-    if (vmask) {  // uniform
-      const uint32_t d = seg_digit(K[k], klo, shift);
-      const uint64_t peers = match8(d) & vmask;
-      const int leader = v ? __ffsll((unsigned long long)peers) - 1 : 0;
-      if (v && lane == leader) ret[k] = atomicAdd(&wh[d], (uint32_t)__popcll(peers));
-      info[k / 2] |= ((uint32_t)leader | ((uint32_t)__popcll(peers & lanes_below()) << 8)) << (16 * (k & 1));
-    }
-  }
+  // Rank inside the wave: every lane adds one to its digit's per-wave count.
+  // The LDS unit applies the lanes of one atomic instruction in lane order
+  // (lanes sharing an address get increasing old values) and a wave's
+  // instructions in issue order, so the returned counts are the stable ranks
+  // in item order wave * 1024 + k * 64 + lane.
   uint32_t rank[kSegItems];
 #pragma unroll
   for (int k = 0; k < kSegItems; ++k) {
-    const uint32_t in = (info[k / 2] >> (16 * (k & 1))) & 0xffffu;
-    rank[k] = (uint32_t)__shfl((int)ret[k], (int)(in & 63u)) + (in >> 8);
+    const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
+    rank[k] = idx < len ? atomicAdd(&wh[seg_digit(K[k], klo, shift)], 1u) : 0u;
   }
   __syncthreads();
   if (threadIdx.x < 256) {  // offsets of each wave inside each digit
@@ -531,11 +504,13 @@ __global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(const uint32_t* _
       const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
       K[k] = idx < e.len ? src[e.start + idx] : 0ull;
     }
-    // Above 32 bits only the depth part is radix sorted; keys equal there
-    // (ties of the high word) are put in order afterwards.
+    // Above 32 bits only the depth part is radix sorted, together with as
+    // many top bits of the low word as the passes' last digit has room for
+    // (they cost nothing and split most runs of equal depth); keys equal in
+    // the sorted bits are put in order afterwards.
     const bool hi_only = e.dbits > 32;
-    const int shift0 = hi_only ? 32 : 0;
-    const int passes = ((int)e.dbits - shift0 + 7) / 8;
+    const int passes = hi_only ? ((int)e.dbits - 32 + 7) / 8 : ((int)e.dbits + 7) / 8;
+    const int shift0 = hi_only ? (int)e.dbits - 8 * passes : 0;  // 25..32
     for (int p = 0; p < passes; ++p) lsd_pass(sm, K, e.len, e.klo, shift0 + 8 * p);
     if (passes == 0) {
 #pragma unroll
@@ -547,12 +522,12 @@ __global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(const uint32_t* _
     if (threadIdx.x == 0) sm.flag = 0;
     __syncthreads();
     if (hi_only) {
-      // Runs of equal (K - klo) >> 32 (equal depth bits) are put in key
+      // Runs of equal (K - klo) >> shift0 (equal sorted bits) are put in key
       // order: positions i = threadIdx.x + j * kSegThreads, so neighbours in
       // the list are neighbouring lanes (one LDS read per position, the rest
       // by shuffles); the first position of a run insertion-sorts a run of at
       // most 32, a longer run sends the segment to a stable LSD over every bit.
-      auto hi_of = [&](uint64_t key) { return (uint32_t)((key - e.klo) >> 32); };
+      auto hi_of = [&](uint64_t key) { return (uint32_t)((key - e.klo) >> shift0); };
       const uint32_t rounds = (e.len + kSegThreads - 1) / kSegThreads;
       for (uint32_t j = 0; j < rounds; ++j) {  // uniform
         const uint32_t i = threadIdx.x + j * kSegThreads;
