@@ -32,7 +32,7 @@ constexpr int kSplitChunk = kBkThreads * kSegItems;  // keys one split workgroup
 static_assert(kSegThreads * kSegItems == kSegCap, "LDS segment capacity");
 static_assert(kSegThreads >= 256, "digit scans need 256 threads");
 constexpr int kSplitBits = 11;
-constexpr int kSplitBins = 1 << kSplitBits;
+static_assert(kSplitBins == 1 << kSplitBits && kWideChunk == 2 * kSplitChunk, "split geometry");
 
 __device__ __forceinline__ int bk_lane() { return (int)(threadIdx.x & 63); }
 
@@ -207,13 +207,6 @@ __device__ __forceinline__ void tile_segment(int t, const uint32_t* ranges, cons
   e.buf = 0;
 }
 
-__device__ __forceinline__ uint32_t block_ticket(uint32_t* ticket, uint32_t* s_w) {
-  __syncthreads();
-  if (threadIdx.x == 0) *s_w = atomicAdd(ticket, 1u);
-  __syncthreads();
-  return *s_w;
-}
-
 __device__ __forceinline__ void push_entry(SegEntry* list, uint32_t* counter, uint32_t cap, const SegEntry& e,
                                            FrameHdr* hdr) {
   const uint32_t i = atomicAdd(counter, 1u);
@@ -262,74 +255,154 @@ __device__ __forceinline__ int block_excl_scan_max(int v, int* s_red) {
 
 // ---------------------------------------------------------------------------
 // 4. split one level: every segment longer than kSegCap is partitioned by the
-// top kSplitBits of its dbits bits, bins packed into sub-segments, into the
-// other buffer.
-// Level 0 reads the tiles, level L > 0 the big list of level L.
+// top kSplitBits of its dbits bits into the other buffer, bins packed into
+// sub-segments. Level 0 reads the tiles, level L > 0 the big list of level L.
+// The work is cut into chunk items of kWideChunk keys so that a long segment
+// (a tile near the horizon holds millions of pairs) is split by many
+// workgroups at once:
+//   plan    (one workgroup) lists the segments to split and their items,
+//   hist    per item: bin counts of its keys,
+//   scan    per segment: bin starts, each item's first slot in each bin, and
+//           the grouping of bins into sub-segments (pushed to the lists),
+//   scatter per item: every key to its slot (LDS cursors; the order inside a
+//           bin is arbitrary, keys are unique inside a tile).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBkThreads) void seg_split_kernel(int level, const uint32_t* __restrict__ ranges,
-                                                               const uint32_t* __restrict__ g_minc,
-                                                               const uint32_t* __restrict__ g_max, int n_tiles,
-                                                               FrameHdr* hdr, uint32_t max_pairs, uint64_t* keys0,
-                                                               uint64_t* keys1, SegLists lists) {
-  __shared__ uint32_t s_h[kSplitBins];
-  __shared__ uint32_t s_pos[kSplitBins];
-  __shared__ uint16_t s_lead[kSplitBins];
-  __shared__ uint32_t s_last[kSplitBins];
+__global__ __launch_bounds__(kBkThreads) void split_plan_kernel(int level, const uint32_t* __restrict__ ranges,
+                                                                const uint32_t* __restrict__ g_minc,
+                                                                const uint32_t* __restrict__ g_max, int n_tiles,
+                                                                FrameHdr* hdr, uint32_t max_pairs, SegLists lists,
+                                                                SplitWork wk) {
   __shared__ int s_red[kBkWaves + 1];
-  __shared__ uint32_t s_w, s_ngroups;
+  __shared__ uint32_t s_tot[2];
   if (hdr->n_pairs > max_pairs) return;
   uint32_t* ctr = lists.counters;
-  const uint32_t n_work = level == 0 ? (uint32_t)n_tiles : min(ctr[kCtrBig + level], lists.cap_big);
+  const uint32_t n_in = level == 0 ? (uint32_t)n_tiles : min(ctr[kCtrBig + level], lists.cap_big);
   const SegEntry* in_list = lists.big[level & 1];
-  for (;;) {
-    const uint32_t w = block_ticket(&ctr[kCtrSplitTicket + level], &s_w);
-    if (w >= n_work) break;
-    SegEntry e;
-    if (level == 0) tile_segment((int)w, ranges, g_minc, g_max, e);
-    else e = in_list[w];
-    if (e.len <= (uint32_t)kSegCap) {  // uniform over the workgroup
-      if (level == 0 && e.len > 0 && threadIdx.x == 0) push_entry(lists.base, &ctr[kCtrBase], lists.cap_base, e, hdr);
-      continue;
+  uint32_t carry_segs = 0, carry_items = 0;
+  bool over = false;
+  for (uint32_t w0 = 0; w0 < n_in; w0 += kBkThreads) {  // uniform
+    const uint32_t w = w0 + threadIdx.x;
+    SegEntry e{};
+    const bool valid = w < n_in;
+    if (valid) {
+      if (level == 0) tile_segment((int)w, ranges, g_minc, g_max, e);
+      else e = in_list[w];
     }
-    const int sh = (int)e.dbits - kSplitBits;  // len > 2^14 keys imply dbits >= 15
-    const uint64_t* src = e.buf ? keys1 : keys0;
-    uint64_t* dst = e.buf ? keys0 : keys1;
-    for (int i = threadIdx.x; i < kSplitBins; i += kBkThreads) {
-      s_h[i] = 0;
-      s_last[i] = 0;
+    const bool big = valid && e.len > (uint32_t)kSegCap;
+    if (level == 0 && valid && !big && e.len > 0) push_entry(lists.base, &ctr[kCtrBase], lists.cap_base, e, hdr);
+    const uint32_t nch = big ? (e.len + kWideChunk - 1) / kWideChunk : 0u;
+    const uint32_t seg = carry_segs + block_excl_scan_sum(big ? 1u : 0u, s_red);
+    const uint32_t item0 = carry_items + block_excl_scan_sum(nch, s_red);
+    if (big) {
+      if (seg < wk.cap_segs && item0 + nch <= wk.cap_items) {
+        wk.segs[seg] = e;
+        wk.seg_item0[seg] = item0;
+        for (uint32_t c = 0; c < nch; ++c) wk.item_seg[item0 + c] = seg;
+      } else {
+        over = true;
+      }
+    }
+    if (threadIdx.x == kBkThreads - 1) {
+      s_tot[0] = seg + (big ? 1u : 0u);
+      s_tot[1] = item0 + nch;
     }
     __syncthreads();
-    for (uint32_t i0 = 0; i0 < e.len; i0 += kSplitChunk) {  // kSegItems loads in flight per thread
+    carry_segs = s_tot[0];
+    carry_items = s_tot[1];
+    __syncthreads();
+  }
+  if (__syncthreads_or(over)) {  // cannot happen within the capacities the runtime sizes
+    if (threadIdx.x == 0) atomicOr(&hdr->overflow, 32u);
+    carry_segs = carry_items = 0;
+  }
+  if (threadIdx.x == 0) {
+    ctr[kCtrSegs + level] = carry_segs;
+    ctr[kCtrItems + level] = carry_items;
+  }
+}
+
+// chunk item -> its segment and key range [lo, hi) inside the segment
+__device__ __forceinline__ void split_item(const SplitWork& wk, uint32_t item, SegEntry& e, uint32_t& lo,
+                                           uint32_t& hi) {
+  const uint32_t g = wk.item_seg[item];
+  e = wk.segs[g];
+  lo = (item - wk.seg_item0[g]) * (uint32_t)kWideChunk;
+  hi = min(e.len, lo + (uint32_t)kWideChunk);
+}
+
+__global__ __launch_bounds__(kBkThreads) void split_hist_kernel(int level, const FrameHdr* __restrict__ hdr,
+                                                                uint32_t max_pairs, const uint64_t* __restrict__ keys0,
+                                                                const uint64_t* __restrict__ keys1, SegLists lists,
+                                                                SplitWork wk) {
+  __shared__ uint32_t s_h[kSplitBins];
+  if (hdr->n_pairs > max_pairs) return;
+  const uint32_t n_items = lists.counters[kCtrItems + level];
+  for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    SegEntry e;
+    uint32_t lo, hi;
+    split_item(wk, item, e, lo, hi);
+    const int sh = (int)e.dbits - kSplitBits;  // len > 2^14 keys imply dbits >= 15
+    const uint64_t* src = e.buf ? keys1 : keys0;
+    for (int i = threadIdx.x; i < kSplitBins; i += kBkThreads) s_h[i] = 0;
+    __syncthreads();
+    for (uint32_t i0 = lo; i0 < hi; i0 += kSplitChunk) {  // kSegItems loads in flight per thread
       uint64_t K[kSegItems];
 #pragma unroll
       for (int k = 0; k < kSegItems; ++k) {
         const uint32_t i = i0 + (uint32_t)(k * kBkThreads) + threadIdx.x;
-        K[k] = i < e.len ? src[e.start + i] : 0ull;
+        K[k] = i < hi ? src[e.start + i] : 0ull;
       }
 #pragma unroll
       for (int k = 0; k < kSegItems; ++k) {
-        const bool act = i0 + (uint32_t)(k * kBkThreads) + threadIdx.x < e.len;
+        const bool act = i0 + (uint32_t)(k * kBkThreads) + threadIdx.x < hi;
         const uint32_t bin = act ? (uint32_t)min((K[k] - e.klo) >> sh, (uint64_t)kSplitBins - 1) : 0u;
         lds_slot_wave(s_h, bin, act);
       }
     }
     __syncthreads();
+    uint32_t* row = wk.hist + (size_t)item * kSplitBins;
+    for (int i = threadIdx.x; i < kSplitBins; i += kBkThreads) row[i] = s_h[i];
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kBkThreads) void split_scan_kernel(int level, FrameHdr* hdr, uint32_t max_pairs,
+                                                                SegLists lists, SplitWork wk) {
+  __shared__ uint32_t s_pos[kSplitBins];
+  __shared__ uint16_t s_lead[kSplitBins];
+  __shared__ uint32_t s_last[kSplitBins];
+  __shared__ int s_red[kBkWaves + 1];
+  __shared__ uint32_t s_ngroups;
+  if (hdr->n_pairs > max_pairs) return;
+  uint32_t* ctr = lists.counters;
+  const uint32_t n_segs = ctr[kCtrSegs + level];
+  constexpr int BPT = kSplitBins / kBkThreads;  // bins per thread
+  for (uint32_t g = blockIdx.x; g < n_segs; g += gridDim.x) {
+    const SegEntry e = wk.segs[g];
+    const uint32_t it0 = wk.seg_item0[g], nit = (e.len + kWideChunk - 1) / kWideChunk;
+    const int sh = (int)e.dbits - kSplitBits;
+    for (int i = threadIdx.x; i < kSplitBins; i += kBkThreads) s_last[i] = 0;
+    uint32_t c[BPT], sum = 0;
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) c[j] = 0;
+    for (uint32_t it = 0; it < nit; ++it) {
+      const uint32_t* row = wk.hist + (size_t)(it0 + it) * kSplitBins;
+#pragma unroll
+      for (int j = 0; j < BPT; ++j) c[j] += row[BPT * threadIdx.x + j];
+    }
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) sum += c[j];
     // Group consecutive bins into sub-segments of at most kSegCap keys: a bin
     // of more than H = kSegCap / 2 keys is a group of its own; the others
     // group by floor(first key index / H), so a group holds < 2H keys. The
     // group id (even for those, odd for the large bins) grows along the bins.
-    constexpr int BPT = kSplitBins / kBkThreads;  // bins per thread
     constexpr uint32_t H = kSegCap / 2;
-    uint32_t c[BPT], sum = 0;
-#pragma unroll
-    for (int j = 0; j < BPT; ++j) {
-      c[j] = s_h[BPT * threadIdx.x + j];
-      sum += c[j];
-    }
     uint32_t run = block_excl_scan_sum(sum, s_red);
     int gid[BPT];
+    uint32_t start[BPT];
 #pragma unroll
     for (int j = 0; j < BPT; ++j) {
+      start[j] = run;
       s_pos[BPT * threadIdx.x + j] = run;
       gid[j] = c[j] == 0 ? -1 : 2 * (int)(run / H) + (c[j] > H ? 1 : 0);
       run += c[j];
@@ -380,22 +453,54 @@ __global__ __launch_bounds__(kBkThreads) void seg_split_kernel(int level, const 
         push_entry(lists.base, &ctr[kCtrBase], lists.cap_base, sub, hdr);
       }
     }
+    // every item's first slot in every bin: the bin start plus the counts of
+    // the segment's earlier items
+#pragma unroll
+    for (int j = 0; j < BPT; ++j) {
+      uint32_t at = start[j];
+      for (uint32_t it = 0; it < nit; ++it) {
+        uint32_t* p = wk.hist + (size_t)(it0 + it) * kSplitBins + BPT * threadIdx.x + j;
+        const uint32_t v = *p;
+        *p = at;
+        at += v;
+      }
+    }
     __syncthreads();
-    for (uint32_t i0 = 0; i0 < e.len; i0 += kSplitChunk) {
+  }
+}
+
+__global__ __launch_bounds__(kBkThreads) void split_scatter_kernel(int level, const FrameHdr* __restrict__ hdr,
+                                                                   uint32_t max_pairs, uint64_t* keys0,
+                                                                   uint64_t* keys1, SegLists lists, SplitWork wk) {
+  __shared__ uint32_t s_cur[kSplitBins];
+  if (hdr->n_pairs > max_pairs) return;
+  const uint32_t n_items = lists.counters[kCtrItems + level];
+  for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    SegEntry e;
+    uint32_t lo, hi;
+    split_item(wk, item, e, lo, hi);
+    const int sh = (int)e.dbits - kSplitBits;
+    const uint64_t* src = e.buf ? keys1 : keys0;
+    uint64_t* dst = e.buf ? keys0 : keys1;
+    const uint32_t* row = wk.hist + (size_t)item * kSplitBins;
+    for (int i = threadIdx.x; i < kSplitBins; i += kBkThreads) s_cur[i] = row[i];
+    __syncthreads();
+    for (uint32_t i0 = lo; i0 < hi; i0 += kSplitChunk) {
       uint64_t K[kSegItems];
 #pragma unroll
       for (int k = 0; k < kSegItems; ++k) {
         const uint32_t i = i0 + (uint32_t)(k * kBkThreads) + threadIdx.x;
-        K[k] = i < e.len ? src[e.start + i] : 0ull;
+        K[k] = i < hi ? src[e.start + i] : 0ull;
       }
 #pragma unroll
       for (int k = 0; k < kSegItems; ++k) {
-        const bool act = i0 + (uint32_t)(k * kBkThreads) + threadIdx.x < e.len;
+        const bool act = i0 + (uint32_t)(k * kBkThreads) + threadIdx.x < hi;
         const uint32_t bin = act ? (uint32_t)min((K[k] - e.klo) >> sh, (uint64_t)kSplitBins - 1) : 0u;
-        const uint32_t p = lds_slot_wave(s_pos, bin, act);
+        const uint32_t p = lds_slot_wave(s_cur, bin, act);
         if (act) dst[e.start + p] = K[k];
       }
     }
+    __syncthreads();
   }
 }
 
@@ -617,11 +722,14 @@ hipError_t launch_bucket_scatter(const uint2* rd, CamDev cam, const FrameHdr* hd
 }
 
 hipError_t launch_seg_sort(const uint32_t* ranges, const uint32_t* region, int n_tiles, FrameHdr* hdr,
-                           uint32_t max_pairs, uint64_t* keys0, uint64_t* keys1, SegLists lists, uint32_t* vals,
-                           int grid, hipStream_t st) {
+                           uint32_t max_pairs, uint64_t* keys0, uint64_t* keys1, SegLists lists, SplitWork wk,
+                           uint32_t* vals, int grid, hipStream_t st) {
   for (int level = 0; level < kSplitLevels; ++level) {
-    seg_split_kernel<<<grid, kBkThreads, 0, st>>>(level, ranges, region + kBucketMinC, region + kBucketMax,
-                                                  n_tiles, hdr, max_pairs, keys0, keys1, lists);
+    split_plan_kernel<<<1, kBkThreads, 0, st>>>(level, ranges, region + kBucketMinC, region + kBucketMax, n_tiles,
+                                                hdr, max_pairs, lists, wk);
+    split_hist_kernel<<<grid, kBkThreads, 0, st>>>(level, hdr, max_pairs, keys0, keys1, lists, wk);
+    split_scan_kernel<<<grid, kBkThreads, 0, st>>>(level, hdr, max_pairs, lists, wk);
+    split_scatter_kernel<<<grid, kBkThreads, 0, st>>>(level, hdr, max_pairs, keys0, keys1, lists, wk);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -191,10 +191,11 @@ constexpr int kBucketMinC = kBucketMaxTiles;         // [tiles] ~(min depth bits
 constexpr int kBucketMax = 2 * kBucketMaxTiles;      // [tiles] max depth bits
 constexpr int kBucketCtr = 3 * kBucketMaxTiles;      // counters below
 constexpr int kBucketRegion = 3 * kBucketMaxTiles + 32;
-constexpr int kCtrBase = 0;          // entries in the base list
-constexpr int kCtrSortTicket = 1;    // work ticket of the LDS sort
-constexpr int kCtrSplitTicket = 2;   // + level: work tickets of the splits
-constexpr int kCtrBig = 2 + kSplitLevels;  // + level: entries in the big list of that level
+constexpr int kCtrBase = 0;                        // entries in the base list
+constexpr int kCtrBig = 1;                         // + level: entries in the big list of that level
+constexpr int kCtrItems = 1 + kSplitLevels;        // + level: chunk items of that level's split
+constexpr int kCtrSegs = 1 + 2 * kSplitLevels;     // + level: segments that level splits
+static_assert(kCtrSegs + kSplitLevels <= 32, "bucket counters");
 constexpr int kHistLen = kMaxPasses * kSortBins + kBucketRegion;
 
 // A key segment [start, start + len) of key buffer `buf`: K_lo <= K < K_lo + 2^dbits.
@@ -210,6 +211,23 @@ struct SegLists {
   uint32_t cap_base, cap_big;
 };
 
+// One split level's work, reused by every level: the segments it splits, cut
+// into chunk items of kWideChunk keys that workgroups take independently.
+constexpr int kSplitBins = 2048;        // 11-bit split digits
+constexpr int kWideChunk = 32768;       // keys per split chunk item
+struct SplitWork {
+  SegEntry* segs;       // [cap_segs] segments of more than kSegCap keys
+  uint32_t* seg_item0;  // [cap_segs] first chunk item of each
+  uint32_t* item_seg;   // [cap_items] segment of each chunk item
+  uint32_t* hist;       // [cap_items][kSplitBins] chunk bin counts, then the chunk's first slot per bin
+  uint32_t cap_segs, cap_items;
+};
+// Every segment a level splits holds more than kSegCap keys and yields at most
+// len / kWideChunk + 1 items, so a level has at most n / kSegCap segments and
+// n (1 / kWideChunk + 1 / kSegCap) items for n pairs.
+inline int64_t split_segs_cap(int64_t pairs) { return pairs / kSegCap + 64; }
+inline int64_t split_items_cap(int64_t pairs) { return pairs / kWideChunk + pairs / kSegCap + 64; }
+
 constexpr int kBucketBlocks = 512;  // workgroups of the count and scatter kernels (columns of the count matrix)
 hipError_t launch_bucket_count(const uint2* rd, CamDev cam, const FrameHdr* hdr, uint32_t* region, uint32_t* counts,
                                hipStream_t st);
@@ -220,8 +238,8 @@ hipError_t launch_bucket_scatter(const uint2* rd, CamDev cam, const FrameHdr* hd
 hipError_t launch_scan_total(uint32_t* data, uint32_t n, uint32_t* block_sums, uint32_t* total_out, FrameHdr* hdr,
                              uint32_t max_total, hipStream_t st);
 hipError_t launch_seg_sort(const uint32_t* ranges, const uint32_t* region, int n_tiles, FrameHdr* hdr,
-                           uint32_t max_pairs, uint64_t* keys0, uint64_t* keys1, SegLists lists, uint32_t* vals,
-                           int grid, hipStream_t st);
+                           uint32_t max_pairs, uint64_t* keys0, uint64_t* keys1, SegLists lists, SplitWork wk,
+                           uint32_t* vals, int grid, hipStream_t st);
 hipError_t launch_bucket_keys(const uint32_t* ranges, const uint32_t* vals, const float4* rec, int n_tiles,
                               uint64_t* keys, hipStream_t st);
 

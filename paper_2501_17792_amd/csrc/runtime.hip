@@ -104,6 +104,11 @@ struct cs_ctx {
   SegEntry* seg_base = nullptr;      // key segments sorted in LDS
   SegEntry* seg_big[2] = {nullptr, nullptr};  // key segments to split
   int64_t cap_seg_base = 0, cap_seg_big = 0;
+  SegEntry* split_segs = nullptr;    // one split level's segments and chunk items
+  uint32_t* split_item0 = nullptr;
+  uint32_t* split_items = nullptr;
+  uint32_t* split_hist = nullptr;
+  int64_t cap_split_segs = 0, cap_split_items = 0;
   bool bucket_frame = false;         // the last frame was binned into tile buckets
   bool pair_off_valid = false;       // pair_off holds the scan of this frame's tile counts
   bool debug_pairs = false;          // emission-order pairs and sorted keys rebuilt for inspection
@@ -238,6 +243,13 @@ cs_status ensure_pairs(cs_ctx* ctx, int64_t n) {
   CS_TRY(dalloc(ctx, &ctx->seg_big[1], cap_big));
   ctx->cap_seg_base = cap_base;
   ctx->cap_seg_big = cap_big;
+  const int64_t cap_ssegs = split_segs_cap(cap), cap_sitems = split_items_cap(cap);
+  CS_TRY(dalloc(ctx, &ctx->split_segs, cap_ssegs));
+  CS_TRY(dalloc(ctx, &ctx->split_item0, cap_ssegs));
+  CS_TRY(dalloc(ctx, &ctx->split_items, cap_sitems));
+  CS_TRY(dalloc(ctx, &ctx->split_hist, cap_sitems * kSplitBins));
+  ctx->cap_split_segs = cap_ssegs;
+  ctx->cap_split_items = cap_sitems;
   const int64_t parts = (cap + kSortPart - 1) / kSortPart;
   CS_TRY(dalloc(ctx, &ctx->lookback, parts * kSortBins));
   HIP_TRY(hipMemsetAsync(ctx->lookback, 0, parts * kSortBins * sizeof(uint64_t), ctx->stream));
@@ -434,6 +446,10 @@ void cs_destroy(cs_ctx* ctx) {
   dfree(&ctx->seg_base);
   dfree(&ctx->seg_big[0]);
   dfree(&ctx->seg_big[1]);
+  dfree(&ctx->split_segs);
+  dfree(&ctx->split_item0);
+  dfree(&ctx->split_items);
+  dfree(&ctx->split_hist);
   dfree(&ctx->rts_counts);
   dfree(&ctx->rts_sums);
   dfree(&ctx->ranges);
@@ -712,7 +728,10 @@ static cs_status bucket_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles) {
   lists.counters = region + kBucketCtr;
   lists.cap_base = (uint32_t)std::min<int64_t>(ctx->cap_seg_base, 0xffffffffll);
   lists.cap_big = (uint32_t)std::min<int64_t>(ctx->cap_seg_big, 0xffffffffll);
-  HIP_TRY(launch_seg_sort(ctx->ranges, region, n_tiles, ctx->hdr, cap_p, ctx->keys[0], ctx->keys[1], lists,
+  SplitWork wk{ctx->split_segs, ctx->split_item0, ctx->split_items, ctx->split_hist,
+               (uint32_t)std::min<int64_t>(ctx->cap_split_segs, 0xffffffffll),
+               (uint32_t)std::min<int64_t>(ctx->cap_split_items, 0xffffffffll)};
+  HIP_TRY(launch_seg_sort(ctx->ranges, region, n_tiles, ctx->hdr, cap_p, ctx->keys[0], ctx->keys[1], lists, wk,
                           ctx->vals[0], kSegGrid, ctx->stream));
   ctx->mark(CS_STAGE_SORT, 1);
   ctx->sorted = 0;
