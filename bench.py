@@ -294,7 +294,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": {"project_fused": "project_kernel (skinning fused)",
                            "emit": "bucket_count_kernel + bucket_scatter_kernel",
-                           "sort": "seg_split_kernel + seg_sort_kernel"}[dom],
+                           "sort": "split_{plan,hist,scan,scatter}_kernel + seg_sort_kernel"}[dom],
                 "launch_ms": round(per_launch_ms, 4), "bytes_per_launch": int(per_launch_bytes)}
 
     # ---- full detail (every instance at level 0): FPS and the reference frame for PSNR

@@ -125,10 +125,10 @@ __global__ __launch_bounds__(kBkThreads) void bucket_count_kernel(
     while (__ballot(it.more)) {
       const uint32_t t = it.ty * (uint32_t)tiles_x + it.tx;
       lds_slot(s_cnt, t, it.more);
-      if (it.more) {
-        atomicMax(&s_max[t], db);
-        atomicMax(&s_minc[t], ~db);
-      }
+      // the range only widens, so an update that a plain read shows to be no
+      // wider is skipped (most pairs of a tile): fewer contended atomics
+      if (it.more && db > s_max[t]) atomicMax(&s_max[t], db);
+      if (it.more && ~db > s_minc[t]) atomicMax(&s_minc[t], ~db);
       it.next();
     }
   }
@@ -512,9 +512,8 @@ __global__ __launch_bounds__(kBkThreads) void split_scatter_kernel(int level, co
 // ---------------------------------------------------------------------------
 struct SegSmem {
   uint64_t items[kSegCap];
-  uint32_t whist[kSegWaves * 256];
-  uint32_t tot[256];
-  uint32_t w;
+  uint32_t whist[kSegWaves * 256];  // per wave and digit: count, then the wave's first slot
+  uint32_t wsum[4];                 // digit-scan totals of the four scanning waves
   uint32_t flag;
 };
 
@@ -522,11 +521,11 @@ __device__ __forceinline__ uint32_t seg_digit(uint64_t K, uint64_t klo, int shif
   return (uint32_t)((K - klo) >> shift) & 255u;
 }
 
-// one stable pass on the digit at `shift` of K - klo
+// One stable pass on the digit at `shift` of K - klo. The per-wave digit
+// rows are zero on entry and are left zero (each wave clears its own row once
+// its scatter has read it), so only the kernel's start clears them.
 __device__ void lsd_pass(SegSmem& sm, uint64_t (&K)[kSegItems], uint32_t len, uint64_t klo, int shift) {
   const int lane = bk_lane(), wave = (int)(threadIdx.x >> 6);
-  for (int i = threadIdx.x; i < kSegWaves * 256; i += kSegThreads) sm.whist[i] = 0;
-  __syncthreads();
   uint32_t* wh = sm.whist + wave * 256;
   // Rank inside the wave: every lane adds one to its digit's per-wave count.
   // The LDS unit applies the lanes of one atomic instruction in lane order
@@ -540,41 +539,35 @@ __device__ void lsd_pass(SegSmem& sm, uint64_t (&K)[kSegItems], uint32_t len, ui
     rank[k] = idx < len ? atomicAdd(&wh[seg_digit(K[k], klo, shift)], 1u) : 0u;
   }
   __syncthreads();
-  if (threadIdx.x < 256) {  // offsets of each wave inside each digit
-    uint32_t run = 0;
+  // Threads 0..255 (four whole waves), one digit each: digit total over the
+  // waves, digit start (scan over digits), then every wave's first slot.
+  uint32_t t = 0, winc = 0;
+  if (threadIdx.x < 256) {
+#pragma unroll
+    for (int w = 0; w < kSegWaves; ++w) t += sm.whist[w * 256 + threadIdx.x];
+    winc = wave_incl_scan(t);
+    if (lane == 63) sm.wsum[wave] = winc;
+  }
+  __syncthreads();
+  if (threadIdx.x < 256) {
+    uint32_t run = winc - t;
+    for (int w = 0; w < wave; ++w) run += sm.wsum[w];
 #pragma unroll
     for (int w = 0; w < kSegWaves; ++w) {
       const uint32_t c = sm.whist[w * 256 + threadIdx.x];
       sm.whist[w * 256 + threadIdx.x] = run;
       run += c;
     }
-    sm.tot[threadIdx.x] = run;
-  }
-  __syncthreads();
-  if (threadIdx.x < 64) {  // digit starts
-    uint32_t v[4], sum = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      v[j] = sm.tot[4 * threadIdx.x + j];
-      sum += v[j];
-    }
-    uint32_t run = wave_incl_scan(sum) - sum;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      sm.tot[4 * threadIdx.x + j] = run;
-      run += v[j];
-    }
   }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < kSegItems; ++k) {
     const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
-    if (idx < len) {
-      const uint32_t d = seg_digit(K[k], klo, shift);
-      sm.items[sm.tot[d] + wh[d] + rank[k]] = K[k];
-    }
+    if (idx < len) sm.items[wh[seg_digit(K[k], klo, shift)] + rank[k]] = K[k];
   }
   __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4; ++j) wh[lane + 64 * j] = 0;  // this wave's row, zero again for the next pass
 #pragma unroll
   for (int k = 0; k < kSegItems; ++k) {
     const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
@@ -591,6 +584,8 @@ __global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(const uint32_t* _
                                                               uint32_t* __restrict__ vals) {
   __shared__ SegSmem sm;
   if (hdr->n_pairs > max_pairs) return;
+  for (int i = threadIdx.x; i < kSegWaves * 256; i += kSegThreads) sm.whist[i] = 0;  // kept zero between passes
+  __syncthreads();
   const uint32_t n_work = min(lists.counters[kCtrBase], lists.cap_base);
   const int lane = bk_lane(), wave = (int)(threadIdx.x >> 6);
   // static round-robin over the base list (segments are of similar size);
