@@ -32,12 +32,14 @@ sys.path.insert(0, ROOT)
 METRIC = "FPS @3,500 avatars 1080p, learned-LoD vs fixed-LoD at ≥40 dB PSNR vs full"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per frame of each stage in the learned-LoD frame at 16x16 tiles, from two rocprofv3 --pmc runs
-# (FETCH_SIZE scaled by 2.000 and WRITE_SIZE by 1.000, the factors a plain 1 GiB copy gives), summarised in
-# profiles/crowd3500_1080p_learned_lod_kernels.md. They hold only for the kernel sources they were taken on
-# (digest below) and that workload; otherwise the bench reports null.
-MEASURED_TRAFFIC = {"digest": "669d5bf7c6283648", "tile": (16, 16), "lod": "learned",
-                    "bytes": {"sort": 21.70e9, "emit": 8.67e9, "project_fused": 19.01e9, "blend": 2.51e9}}
+# HBM bytes per frame of each stage in the learned-LoD frame at the tile shapes the autotuner picks (16x16,
+# 32x16), from two rocprofv3 --pmc runs each (FETCH_SIZE scaled by 2.000 and WRITE_SIZE by 1.000, the
+# factors a plain 1 GiB copy gives), summarised in profiles/crowd3500_1080p_learned_lod_kernels.md and
+# profiles/crowd3500_1080p_learned_lod_32x16_kernels.md. They hold only for the kernel sources they were
+# taken on (digest below) and that workload; otherwise the bench reports null.
+MEASURED_TRAFFIC = {"digest": "669d5bf7c6283648", "lod": "learned",
+                    "bytes": {(16, 16): {"sort": 21.70e9, "emit": 8.67e9, "project_fused": 19.01e9, "blend": 2.51e9},
+                              (32, 16): {"sort": 20.72e9, "emit": 8.00e9, "project_fused": 19.01e9, "blend": 2.82e9}}}
 
 
 def kernel_digest():
@@ -288,8 +290,8 @@ def main():
     achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
     traffic = None
     mt = MEASURED_TRAFFIC
-    if kernel_digest() == mt["digest"] and tuple(tile) == mt["tile"] and head == mt["lod"]:
-        traffic = mt["bytes"].get(dom)
+    if kernel_digest() == mt["digest"] and head == mt["lod"] and tuple(tile) in mt["bytes"]:
+        traffic = mt["bytes"][tuple(tile)].get(dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": {"project_fused": "project_kernel (skinning fused)",
