@@ -198,6 +198,7 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
           for (int j0 = 0; j0 < sn; j0 += 64) {
             const int j = j0 + lane;
             const uint32_t rows = j < sn ? (s_mask[sb + j] >> wrow0) & ((1u << ROWS) - 1u) : 0u;
+            if (__ballot(rows != 0u) == 0ull) continue;  // no splat of this part reaches the wave's rows
             float u = 0.f, rx = -1.f;
             if (rows) {
               const float4 q = s_q[sb + j];
@@ -206,6 +207,7 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
             }
 #pragma unroll
             for (int g = 0; g < G; ++g) {
+              if (!(gx0[g] <= gx1[g])) continue;  // uniform: every pixel of the group is finished
               const bool hit = ((rows >> (g / SEGS)) & 1u) && !(u + rx < gx0[g] || u - rx > gx1[g]);
               const uint64_t bal = __ballot(hit);
               if (hit) s_list[wave][g][n_g[g] + __popcll(bal & ((1ull << lane) - 1ull))] = (uint8_t)j;
