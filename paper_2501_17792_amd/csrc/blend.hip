@@ -63,10 +63,13 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
   constexpr int SEGS = TW / GL;                 // groups per pixel row
   constexpr int SUB = N < 256 ? N : 256;        // batch entries listed at a time (8-bit list offsets)
   static_assert(TW % GL == 0 && TH <= 32 && (SUB & (SUB - 1)) == 0, "tile shape");
-  __shared__ float4 s_q[N];                     // u v rx ry
-  __shared__ float4 s_r1[N], s_r2[N];           // A B C o | r g b depth
-  __shared__ uint32_t s_live[WAVES];
-  __shared__ uint32_t s_mask[N];                // bit r: the splat's box reaches pixel row r of the tile
+  // Staged batches are double-buffered (consecutive batches alternate), so a
+  // wave may stage the next batch while others still evaluate this one: one
+  // barrier per batch.
+  __shared__ float4 s_q[2][N];                  // u v rx ry
+  __shared__ float4 s_r1[2][N], s_r2[2][N];     // A B C o | r g b depth
+  __shared__ uint32_t s_live[2][WAVES];
+  __shared__ uint32_t s_mask[2][N];             // bit r: the splat's box reaches pixel row r of the tile
   __shared__ uint8_t s_list[WAVES][G][SUB];     // per group: offsets of the splats it must evaluate, in order
   const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
   int tx, ty;
@@ -151,7 +154,12 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
     // One batch b. In: S, R = splat index and record of this lane's entry of
     // batch b, E = raw list entry of batch b + 2. Out: S, R of batch b + 2,
     // E of batch b + 4. Returns whether any pixel of the tile is unfinished.
-    auto step = [&](uint32_t b, uint32_t& E, uint32_t& S, float4& R0, float4& R1, float4& R2) -> bool {
+    auto step = [&](const int buf, uint32_t b, uint32_t& E, uint32_t& S, float4& R0, float4& R1,
+                    float4& R2) -> bool {
+      float4* const s_qb = s_q[buf];
+      float4* const s_r1b = s_r1[buf];
+      float4* const s_r2b = s_r2[buf];
+      uint32_t* const s_maskb = s_mask[buf];
       uint32_t mask = 0u;
       if (S != 0xffffffffu) {
         uint32_t keep = 0;  // rows of the waves still compositing (finished waves stay finished)
@@ -160,17 +168,18 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
         mask = row_mask(R0) & keep;
       }
       if (mask) {
-        s_q[tid] = R0;
-        s_r1[tid] = R1;
-        s_r2[tid] = R2;
+        s_qb[tid] = R0;
+        s_r1b[tid] = R1;
+        s_r2b[tid] = R2;
       }
-      s_mask[tid] = mask;
+      s_maskb[tid] = mask;
       const uint64_t live = __ballot(!done);
-      if (lane == 0) s_live[wave] = live != 0ull ? 1u : 0u;
+      if (lane == 0) s_live[buf][wave] = live != 0ull ? 1u : 0u;
       __syncthreads();
       active = 0;
 #pragma unroll
-      for (int w = 0; w < WAVES; ++w) active |= s_live[w] << w;
+      for (int w = 0; w < WAVES; ++w) active |= s_live[buf][w] << w;
+      if (active == 0u) return false;  // uniform: every pixel of the tile is finished
       S = splat_of(b + 2 * N + tid, E);
       asm volatile("" : "+v"(S));  // the select happens here, so E's old value dies before its reload
       load_rec(S, R0, R1, R2);
@@ -197,11 +206,11 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
           for (int g = 0; g < G; ++g) n_g[g] = 0;
           for (int j0 = 0; j0 < sn; j0 += 64) {
             const int j = j0 + lane;
-            const uint32_t rows = j < sn ? (s_mask[sb + j] >> wrow0) & ((1u << ROWS) - 1u) : 0u;
+            const uint32_t rows = j < sn ? (s_maskb[sb + j] >> wrow0) & ((1u << ROWS) - 1u) : 0u;
             if (__ballot(rows != 0u) == 0ull) continue;  // no splat of this part reaches the wave's rows
             float u = 0.f, rx = -1.f;
             if (rows) {
-              const float4 q = s_q[sb + j];
+              const float4 q = s_qb[sb + j];
               u = q.x;
               rx = q.z;
             }
@@ -232,8 +241,8 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
           const uint8_t* my_list = s_list[wave][grp];
           auto off = [&](int k) -> int { return sb + (int)(my_list[min(k, SUB - 1)] & (SUB - 1)); };
           int jA = off(0), jB = off(1);
-          float4 a1 = s_r1[jA], a2 = s_r2[jA], b1 = s_r1[jB], b2 = s_r2[jB];
-          float2 au = make_float2(s_q[jA].x, s_q[jA].y), bu = make_float2(s_q[jB].x, s_q[jB].y);
+          float4 a1 = s_r1b[jA], a2 = s_r2b[jA], b1 = s_r1b[jB], b2 = s_r2b[jB];
+          float2 au = make_float2(s_qb[jA].x, s_qb[jA].y), bu = make_float2(s_qb[jB].x, s_qb[jB].y);
           int oA = off(2), oB = off(3);
           auto eval = [&](int k, const float4& r1, const float2& uv, const float4& r2) {
             const bool live = !done && k < n_mine;
@@ -256,26 +265,26 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
           // lists, so that half changes nothing)
           for (int k = 0; k < n_max; k += 2) {
             eval(k, a1, au, a2);
-            a1 = s_r1[oA];
-            a2 = s_r2[oA];
-            au = make_float2(s_q[oA].x, s_q[oA].y);
+            a1 = s_r1b[oA];
+            a2 = s_r2b[oA];
+            au = make_float2(s_qb[oA].x, s_qb[oA].y);
             oA = off(k + 4);
             __builtin_amdgcn_sched_barrier(0);  // keep the refill ahead of the other set's evaluation
             eval(k + 1, b1, bu, b2);
-            b1 = s_r1[oB];
-            b2 = s_r2[oB];
-            bu = make_float2(s_q[oB].x, s_q[oB].y);
+            b1 = s_r1b[oB];
+            b2 = s_r2b[oB];
+            bu = make_float2(s_qb[oB].x, s_qb[oB].y);
             oB = off(k + 5);
             __builtin_amdgcn_sched_barrier(0);
           }
         }
       }
       E = load_entry(b + 4 * N + tid);  // issued last: E's old value is dead by now
-      return __syncthreads_count(!done) != 0;
+      return true;
     };
     for (uint32_t b = start;;) {
-      if (!step(b, ea, sa, ra0, ra1, ra2) || (b += N) >= end) break;
-      if (!step(b, eb, sb, rb0, rb1, rb2) || (b += N) >= end) break;
+      if (!step(0, b, ea, sa, ra0, ra1, ra2) || (b += N) >= end) break;
+      if (!step(1, b, eb, sb, rb0, rb1, rb2) || (b += N) >= end) break;
     }
   }
   if (inside) {
