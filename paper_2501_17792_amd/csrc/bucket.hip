@@ -14,8 +14,8 @@
 //   3. scatter: every pair's K into its tile's segment; slots inside a
 //      workgroup's share of a tile are handed out by LDS atomics, so the order
 //      there is arbitrary
-//   4. split (up to 7 levels): segments longer than one workgroup's LDS
-//      capacity are partitioned by the top 8 bits of K - K_lo into sub-segments
+//   4. split (up to 5 levels): segments longer than one workgroup's LDS
+//      capacity are partitioned by the top 11 bits of K - K_lo into sub-segments
 //   5. base: each segment of at most kSegCap keys is sorted in LDS by a stable
 //      LSD radix sort on K - K_lo, and the splat indices are written out.
 // Keys are unique inside a tile, so the result does not depend on the order
