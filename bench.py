@@ -5,8 +5,10 @@ Gaussians (SH degree 3) with 5 importance-ordered levels (100/50/25/12.5/6.25 %)
 1920x1080, a 300-frame keyframed animation (poses interpolated at 30 Hz).
 A step is one whole frame: pose upload (device copy), LoD selection and work
 list (learned network, or distance thresholds), forward kinematics, skinning +
-projection, tile-count scan, pair emission, the onesweep (tile|depth) sort,
-tile ranges and compositing, all replayed as one captured hipGraph.
+projection, tile binning, the per-tile depth sort and compositing, all
+replayed as one captured hipGraph. Consecutive frames alternate between
+``--inflight`` contexts (one stream and one set of buffers each), so that
+that many frames are in flight; the head mode is also timed with one.
 
 The headline value is the learned-LoD frame rate when a trained network is
 present (paper_2501_17792_amd/lod_net.npz, written by train_lod.py), else the
@@ -135,43 +137,71 @@ def load_net(path):
                 floor=float(z["floor"]))
 
 
-def time_mode(torch, r, scene, poses_all, img, stream, lod, steps, warmup):
+def time_mode(torch, rs, scene, poses_all, imgs, streams, lod, steps, warmup):
     """Size the frame eagerly, reserve capacity, capture the whole frame as a
-    graph and time ``steps`` replays (pose copy + graph launch per step)."""
+    graph and time ``steps`` replays (pose copy + graph launch per step).
+    With several contexts (one stream each) consecutive frames alternate
+    between them, so that many frames are in flight; every frame still runs
+    the whole path into its own image."""
     from paper_2501_17792_amd import crowdsplat as cs
 
     mode, thr, mlp_ptr, margin = lod
+    r, img, stream = rs[0], imgs[0], streams[0]
     max_pairs = max_splats = 0
-    for f in (0, 100, 200, 299):
-        r.pose_dev.copy_(poses_all[f])
+    with torch.cuda.stream(stream):
+        for f in (0, 100, 200, 299):
+            r.pose_dev.copy_(poses_all[f])
+            r.select_lod(scene.camera, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
+            r.skin()
+            r.render(scene.camera, img, stats=True)
+            max_pairs = max(max_pairs, int(r.last_stats.n_pairs))
+            max_splats = max(max_splats, int(r.last_stats.n_splats))
+        r.pose_dev.copy_(poses_all[0])
         r.select_lod(scene.camera, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
         r.skin()
         r.render(scene.camera, img, stats=True)
-        max_pairs = max(max_pairs, int(r.last_stats.n_pairs))
-        max_splats = max(max_splats, int(r.last_stats.n_splats))
-    r.pose_dev.copy_(poses_all[0])
-    r.select_lod(scene.camera, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
-    r.skin()
-    r.render(scene.camera, img, stats=True)
-    st0 = r.last_stats
-    frame0 = img.clone()
-    r.reserve(0, int(max_splats * 1.05) + 1024, int(max_pairs * 1.3) + 65536)
-    r.capture(scene.camera, img, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
+        st0 = r.last_stats
+        frame0 = img.clone()
+    for ri, im, st in zip(rs, imgs, streams):
+        with torch.cuda.stream(st):
+            ri.reserve(0, int(max_splats * 1.05) + 1024, int(max_pairs * 1.3) + 65536)
+            ri.capture(scene.camera, im, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
+    n = len(rs)
+
+    def frame(k):
+        i = k % n
+        with torch.cuda.stream(streams[i]):
+            rs[i].pose_dev.copy_(poses_all[k % 300])
+            rs[i].launch()
+        return i
+
     for k in range(warmup):
-        r.pose_dev.copy_(poses_all[k % 300])
-        r.launch()
-    stream.synchronize()
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
-    evs[0].record(stream)
+        frame(k)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for st in streams[1:]:
+        st.wait_event(start)
+    evs = []
     for k in range(steps):
-        r.pose_dev.copy_(poses_all[(warmup + k) % 300])
-        r.launch()
-        evs[k + 1].record(stream)
-    stream.synchronize()
-    per = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(steps)])
-    total = evs[0].elapsed_time(evs[-1])
-    stf = r.poll()
-    return dict(ms=total / steps, per=per, stats=st0, frame0=frame0, overflow=int(stf.overflow))
+        i = frame(warmup + k)
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(streams[i])
+        evs.append(e)
+    for st in streams[1:]:
+        e = torch.cuda.Event()
+        e.record(st)
+        stream.wait_event(e)
+    end = torch.cuda.Event(enable_timing=True)
+    end.record(stream)
+    torch.cuda.synchronize()
+    total = start.elapsed_time(end)
+    # per-frame period: a stream's consecutive frames are n apart
+    per = np.array([evs[k].elapsed_time(evs[k + n]) / n for k in range(steps - n)]) if steps > n else np.array([total])
+    overflow = 0
+    for ri in rs:
+        overflow |= int(ri.poll().overflow)
+    return dict(ms=total / steps, per=per, stats=st0, frame0=frame0, overflow=overflow)
 
 
 def psnr(a, b):
@@ -191,6 +221,8 @@ def main():
     ap.add_argument("--net", default=os.path.join(ROOT, "paper_2501_17792_amd", "lod_net.npz"))
     ap.add_argument("--tile", default="auto", help="WxH or 'auto' (autotuned per run)")
     ap.add_argument("--modes", default="", help="comma list of LoD modes to time (default: all)")
+    ap.add_argument("--inflight", type=int, default=3,
+                    help="frames in flight: contexts (one stream each) that consecutive frames alternate between")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1",
@@ -229,16 +261,31 @@ def main():
     else:
         tile = tuple(int(x) for x in args.tile.split("x"))
     log(f"tile {tile}")
+    streams = [stream] + [torch.cuda.Stream(dev) for _ in range(args.inflight - 1)]
     with torch.cuda.stream(stream):
-        img = torch.zeros((3, scene.camera.height, scene.camera.width), device=dev)
-        for name, lod in modes.items():  # a fresh context per mode: capacities are fixed at capture
-            r = cs.Renderer(0, stream=stream, fuse=True, tile=tile)
-            r.upload_templates(scene.templates)
-            r.set_crowd(scene.crowd)
-            results[name] = time_mode(torch, r, scene, poses_all, img, stream, lod, args.steps, args.warmup)
-            r.close()
+        imgs = [torch.zeros((3, scene.camera.height, scene.camera.width), device=dev) for _ in streams]
+        img = imgs[0]
+
+        def run(name, lod, n):  # fresh contexts per run: capacities are fixed at capture
+            rs = []
+            for st in streams[:n]:
+                r = cs.Renderer(0, stream=st, fuse=True, tile=tile)
+                r.upload_templates(scene.templates)
+                r.set_crowd(scene.crowd)
+                rs.append(r)
+            torch.cuda.synchronize()
+            out = time_mode(torch, rs, scene, poses_all, imgs[:n], streams[:n], lod, args.steps, args.warmup)
+            for r in rs:
+                r.close()
+            return out
+
+        for name, lod in modes.items():
+            results[name] = run(name, lod, len(streams))
             log(f"{name}: {1000.0 / results[name]['ms']:.1f} FPS, {results[name]['stats'].n_splats} splats, "
                 f"{results[name]['stats'].n_pairs} pairs")
+        # the head mode once more with one frame in flight: a single frame's latency
+        single = run(head, modes[head], 1) if len(streams) > 1 else results[head]
+        log(f"{head}, one frame in flight: {1000.0 / single['ms']:.1f} FPS")
     res = results[head]
     ms = res["ms"]
     fps = 1000.0 / ms
@@ -338,12 +385,14 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "3,500 animated avatars, 14 templates x 100k Gaussians SH3 with 5 LoD levels "
                                "(100/50/25/12.5/6.25%), 1920x1080, 300-frame keyframed animation, "
-                               "hipGraph-captured frame",
+                               "hipGraph-captured frame, frames in flight on separate contexts",
                    "lod": head, "instances": scene.crowd.n, "width": scene.camera.width,
                    "height": scene.camera.height, "tile": list(tile)},
         "tile_autotune_ms": tile_timing,
+        "frames_in_flight": len(streams),
         "frame_ms_median": round(float(np.median(res["per"])), 4),
         "frame_ms_p95": round(float(np.percentile(res["per"], 95)), 4),
+        "one_frame_in_flight": {"fps": round(1000.0 / single["ms"], 2), "frame_ms": round(single["ms"], 4)},
         "gaussians_per_s": round(n_splats * fps, 1), "n_splats": n_splats, "n_pairs": n_pairs,
         "n_visible": int(st0.n_visible), "level_hist": list(st0.level_hist)[:5],
         "lod_comparison": lod_cmp, "full_detail": full,

@@ -152,3 +152,50 @@ def test_bucket_graph_replay_and_backward_offsets():
             assert r2.poll().overflow == 0
             assert np.array_equal(out.cpu().numpy(), ref), k
     stream.synchronize()
+
+
+def test_frames_in_flight_on_separate_contexts():
+    """Contexts on separate streams replay their captured frames concurrently
+    (the bench's frames in flight) and each draws exactly what one context
+    draws alone for the same pose."""
+    import torch
+
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    templates = [synth.make_template(t, 12000, 0, (1.0, 0.25)) for t in range(2)]
+    crowd = synth.make_crowd(11, 24, 2, 10.0, 0.3)
+    cam = synth.look_at((5.0, 1.7, -4.0), (5.0, 1.0, 6.0), 320, 240)
+    rng = np.random.default_rng(5)
+    poses = [torch.from_numpy(rng.normal(0, 0.3, (crowd.n, 24, 3)).astype(np.float32)).cuda() for _ in range(4)]
+    ref = []
+    r0 = cs.Renderer(0)
+    r0.upload_templates(templates)
+    r0.set_crowd(crowd)
+    for p in poses:
+        r0.pose_dev.copy_(p)
+        ref.append(r0.frame(cam, cs.CS_LOD_FIXED, (6.0,)).cpu().numpy())
+    r0.close()
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    rs, outs = [], []
+    for st in streams:
+        with torch.cuda.stream(st):
+            r = cs.Renderer(0, stream=st)
+            r.upload_templates(templates)
+            r.set_crowd(crowd)
+            r.frame(cam, cs.CS_LOD_FIXED, (6.0,))
+            out = torch.zeros((3, cam.height, cam.width), device="cuda")
+            r.capture(cam, out, cs.CS_LOD_FIXED, (6.0,))
+            rs.append(r)
+            outs.append(out)
+    torch.cuda.synchronize()
+    for rnd in range(2):
+        for i, (r, st) in enumerate(zip(rs, streams)):
+            with torch.cuda.stream(st):
+                r.pose_dev.copy_(poses[2 * rnd + i])
+                r.launch()
+        torch.cuda.synchronize()
+        for i, r in enumerate(rs):
+            assert r.poll().overflow == 0
+            assert np.array_equal(outs[i].cpu().numpy(), ref[2 * rnd + i]), (rnd, i)
+    for r in rs:
+        r.close()
