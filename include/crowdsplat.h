@@ -346,16 +346,17 @@ cs_status cs_view_psnr(cs_ctx* ctx, const float* atlas_ref, const float* atlas, 
 /* Per-stage GPU time of the last eager frame in milliseconds, from HIP events
  * recorded on the context's stream around each stage (needs profile_stages).
  * ms[k] for k < n: CS_STAGE_* order; -1 where a stage did not run. Synchronises. */
-#define CS_STAGE_LOD     0  /* LoD selection + work list                */
-#define CS_STAGE_FK      1  /* forward kinematics                      */
-#define CS_STAGE_SKIN    2  /* linear blend skinning                   */
-#define CS_STAGE_PROJECT 3  /* projection (+ skinning when fused)      */
-#define CS_STAGE_SCAN    4  /* tile-count scan                         */
-#define CS_STAGE_EMIT    5  /* pair emission + digit histograms        */
-#define CS_STAGE_SORT    6  /* all onesweep passes                     */
-#define CS_STAGE_RANGES  7  /* per-tile ranges                         */
-#define CS_STAGE_BLEND   8  /* compositing                             */
-#define CS_STAGE_COUNT   9
+#define CS_STAGE_LOD     0  /* LoD selection + work list                                    */
+#define CS_STAGE_FK      1  /* forward kinematics                                          */
+#define CS_STAGE_SKIN    2  /* linear blend skinning                                       */
+#define CS_STAGE_PROJECT 3  /* projection (+ skinning when fused)                          */
+#define CS_STAGE_SCAN    4  /* tile-count scan (emission form)                             */
+#define CS_STAGE_EMIT    5  /* pair emission (emission form) / binning (tile-bucket form)   */
+#define CS_STAGE_SORT    6  /* radix passes / key splits + LDS segment sort                */
+#define CS_STAGE_RANGES  7  /* per-tile ranges (emission form)                             */
+#define CS_STAGE_BLEND   8  /* compositing                                                 */
+#define CS_STAGE_SEGSORT 9  /* the LDS segment sort alone (tile-bucket form, within SORT)  */
+#define CS_STAGE_COUNT   10
 cs_status cs_stage_times(cs_ctx* ctx, float* ms, int32_t n);
 
 /* Stable LSD radix sort of (key, value) pairs by the low key_bits bits of key,

@@ -40,7 +40,7 @@ EXPORTS = ["cs_create", "cs_destroy", "cs_last_error", "cs_version", "cs_upload_
            "cs_sort_pairs", "cs_stage_times", "cs_lod_features", "cs_mlp_predict", "cs_mlp_sync",
            "cs_mlp_train_step", "cs_render_views", "cs_view_psnr", "cs_update_template", "cs_fit_loss",
            "cs_adam"]
-STAGES = ["lod", "fk", "skin", "project", "scan", "emit", "sort", "ranges", "blend"]
+STAGES = ["lod", "fk", "skin", "project", "scan", "emit", "sort", "ranges", "blend", "segsort"]
 
 
 class CsOptions(ctypes.Structure):

@@ -716,9 +716,9 @@ hipError_t launch_bucket_scatter(const uint2* rd, CamDev cam, const FrameHdr* hd
   return hipGetLastError();
 }
 
-hipError_t launch_seg_sort(const uint32_t* ranges, const uint32_t* region, int n_tiles, FrameHdr* hdr,
-                           uint32_t max_pairs, uint64_t* keys0, uint64_t* keys1, SegLists lists, SplitWork wk,
-                           uint32_t* vals, int grid, hipStream_t st) {
+hipError_t launch_seg_split(const uint32_t* ranges, const uint32_t* region, int n_tiles, FrameHdr* hdr,
+                            uint32_t max_pairs, uint64_t* keys0, uint64_t* keys1, SegLists lists, SplitWork wk,
+                            int grid, hipStream_t st) {
   for (int level = 0; level < kSplitLevels; ++level) {
     split_plan_kernel<<<1, kBkThreads, 0, st>>>(level, ranges, region + kBucketMinC, region + kBucketMax, n_tiles,
                                                 hdr, max_pairs, lists, wk);
@@ -728,6 +728,12 @@ hipError_t launch_seg_sort(const uint32_t* ranges, const uint32_t* region, int n
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
+  return hipSuccess;
+}
+
+hipError_t launch_seg_sort(const uint32_t* ranges, const uint32_t* region, int n_tiles, FrameHdr* hdr,
+                           uint32_t max_pairs, const uint64_t* keys0, const uint64_t* keys1, SegLists lists,
+                           uint32_t* vals, int grid, hipStream_t st) {
   seg_sort_kernel<<<grid, kSegThreads, 0, st>>>(ranges, region + kBucketMinC, region + kBucketMax, n_tiles, hdr,
                                                max_pairs, keys0, keys1, lists, vals);
   return hipGetLastError();

@@ -237,8 +237,13 @@ hipError_t launch_bucket_scatter(const uint2* rd, CamDev cam, const FrameHdr* hd
                                  const uint32_t* base, uint64_t* items, hipStream_t st);
 hipError_t launch_scan_total(uint32_t* data, uint32_t n, uint32_t* block_sums, uint32_t* total_out, FrameHdr* hdr,
                              uint32_t max_total, hipStream_t st);
+// key splits of the tiles longer than one workgroup's LDS capacity, then the
+// LDS sort of every segment that fits it
+hipError_t launch_seg_split(const uint32_t* ranges, const uint32_t* region, int n_tiles, FrameHdr* hdr,
+                            uint32_t max_pairs, uint64_t* keys0, uint64_t* keys1, SegLists lists, SplitWork wk,
+                            int grid, hipStream_t st);
 hipError_t launch_seg_sort(const uint32_t* ranges, const uint32_t* region, int n_tiles, FrameHdr* hdr,
-                           uint32_t max_pairs, uint64_t* keys0, uint64_t* keys1, SegLists lists, SplitWork wk,
+                           uint32_t max_pairs, const uint64_t* keys0, const uint64_t* keys1, SegLists lists,
                            uint32_t* vals, int grid, hipStream_t st);
 hipError_t launch_bucket_keys(const uint32_t* ranges, const uint32_t* vals, const float4* rec, int n_tiles,
                               uint64_t* keys, hipStream_t st);

@@ -731,8 +731,12 @@ static cs_status bucket_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles) {
   SplitWork wk{ctx->split_segs, ctx->split_item0, ctx->split_items, ctx->split_hist,
                (uint32_t)std::min<int64_t>(ctx->cap_split_segs, 0xffffffffll),
                (uint32_t)std::min<int64_t>(ctx->cap_split_items, 0xffffffffll)};
-  HIP_TRY(launch_seg_sort(ctx->ranges, region, n_tiles, ctx->hdr, cap_p, ctx->keys[0], ctx->keys[1], lists, wk,
+  HIP_TRY(launch_seg_split(ctx->ranges, region, n_tiles, ctx->hdr, cap_p, ctx->keys[0], ctx->keys[1], lists, wk,
+                           kSegGrid, ctx->stream));
+  ctx->mark(CS_STAGE_SEGSORT, 0);
+  HIP_TRY(launch_seg_sort(ctx->ranges, region, n_tiles, ctx->hdr, cap_p, ctx->keys[0], ctx->keys[1], lists,
                           ctx->vals[0], kSegGrid, ctx->stream));
+  ctx->mark(CS_STAGE_SEGSORT, 1);
   ctx->mark(CS_STAGE_SORT, 1);
   ctx->sorted = 0;
   return CS_OK;
