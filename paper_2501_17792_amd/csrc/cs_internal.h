@@ -21,6 +21,29 @@ constexpr int kMlpHidden = 64;
 constexpr int kMlpOut = 8;            // 5 levels used, padded
 
 // Device-side view of one uploaded template (structure of arrays).
+// A pointer read from device memory (a struct field) is generic to the
+// compiler, so loads through it become FLAT instructions, which also count
+// against the LDS wait counter and serialise with LDS reads; these loads of
+// the template columns (all in global memory) use global instructions.
+typedef float cs_f4v __attribute__((ext_vector_type(4)));
+typedef float cs_f2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float4 gload(const float4* p, size_t i) {
+  const cs_f4v v = ((const __attribute__((address_space(1))) cs_f4v*)p)[i];
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ float2 gload(const float2* p, size_t i) {
+  const cs_f2v v = ((const __attribute__((address_space(1))) cs_f2v*)p)[i];
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ float gload(const float* p, size_t i) {
+  return ((const __attribute__((address_space(1))) float*)p)[i];
+}
+// strided float4 column view (the SH planes of a template)
+struct GlobalPlanes {
+  const float4* p;
+  __device__ __forceinline__ float4 operator[](size_t i) const { return gload(p, i); }
+};
+
 struct TemplateDev {
   const float4* mean_idx;  // xyz, w = bit pattern of the 4 packed u8 skin indices
   const float4* skin_w;    // 4 blend weights

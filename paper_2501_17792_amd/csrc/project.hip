@@ -18,10 +18,10 @@ __device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOu
     const int g = ch.g0 + k;
     const size_t s = (size_t)base + g;
     Posed p;
-    const float4 mi = T.mean_idx[g];
-    const float4 wt = T.skin_w[g];
+    const float4 mi = gload(T.mean_idx, g);
+    const float4 wt = gload(T.skin_w, g);
     if (fused) {
-      skin_gaussian(s_bones, mi, wt, T.cov_a[g], T.cov_b[g], w.skin_mode, Ry, p);
+      skin_gaussian(s_bones, mi, wt, gload(T.cov_a, g), gload(T.cov_b, g), w.skin_mode, Ry, p);
     } else {
       const float4 m = skinned.mu[s];
       const float4 cv = skinned.cov[s];
@@ -40,7 +40,7 @@ __device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOu
       }
     }
     SplatRec r;
-    project_gaussian<DEG>(p, T.opacity[g], T.sh + g, T.n, cam, r);
+    project_gaussian<DEG>(p, gload(T.opacity, g), GlobalPlanes{T.sh + g}, T.n, cam, r);
     if (w.crop && r.count) {  // view mode: keep the tiles inside the instance's window
       const int4 cw = w.crop[ch.inst];
       const int x0 = max((int)(r.rect & 0xffu), cw.x), y0 = max((int)((r.rect >> 8) & 0xffu), cw.y);

@@ -432,7 +432,8 @@ __global__ __launch_bounds__(kChunkThreads) void skin_kernel(WorkDev w, SkinOut 
     for (int k = threadIdx.x; k < n_here; k += kChunkThreads) {
       const int g = ch.g0 + k;
       Posed p;
-      skin_gaussian(s_bones, T.mean_idx[g], T.skin_w[g], T.cov_a[g], T.cov_b[g], w.skin_mode, Ry, p);
+      skin_gaussian(s_bones, gload(T.mean_idx, g), gload(T.skin_w, g), gload(T.cov_a, g), gload(T.cov_b, g),
+                    w.skin_mode, Ry, p);
       const size_t s = (size_t)base + g;
       out.mu[s] = make_float4(p.mu[0], p.mu[1], p.mu[2], p.cov[0]);
       out.cov[s] = make_float4(p.cov[1], p.cov[2], p.cov[3], p.cov[4]);

@@ -86,9 +86,8 @@ __device__ __forceinline__ void skin_gaussian(const float* __restrict__ bones, f
 // Real orthonormal SH basis (no Condon-Shortley phase, polar axis +z) at a
 // unit direction, evaluated against [(deg+1)^2][3] coefficients read from
 // float4 planes (plane j holds flattened coefficients 4j..4j+3).
-template <int DEG>
-__device__ __forceinline__ void sh_colour(const float4* __restrict__ planes, int stride, float x, float y,
-                                          float z, float rgb[3]) {
+template <int DEG, class Planes>
+__device__ __forceinline__ void sh_colour(Planes planes, int stride, float x, float y, float z, float rgb[3]) {
   constexpr int NB = (DEG + 1) * (DEG + 1);  // basis functions
   constexpr int N4 = (3 * NB + 3) / 4;       // float4 planes of the 3*NB coefficients
   float4 v[N4];
@@ -142,9 +141,8 @@ struct SplatRec {
 };
 
 // EWA projection + colour + footprint of one posed Gaussian. count = 0 means culled.
-template <int DEG>
-__device__ __forceinline__ void project_gaussian(const Posed& p, float opacity,
-                                                 const float4* __restrict__ sh_planes, int sh_stride,
+template <int DEG, class Planes>
+__device__ __forceinline__ void project_gaussian(const Posed& p, float opacity, Planes sh_planes, int sh_stride,
                                                  const CamDev& cam, SplatRec& out) {
   out.count = 0u;
   out.rect = 0u;
