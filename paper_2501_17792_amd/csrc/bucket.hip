@@ -624,18 +624,28 @@ __global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(const uint32_t* _
     if (hi_only) {
       // Runs of equal (K - klo) >> shift0 (equal sorted bits) are put in key
       // order: positions i = threadIdx.x + j * kSegThreads, so neighbours in
-      // the list are neighbouring lanes (one LDS read per position, the rest
-      // by shuffles); the first position of a run insertion-sorts a run of at
-      // most 32, a longer run sends the segment to a stable LSD over every bit.
+      // the list are neighbouring lanes (one LDS read per position, the
+      // neighbours' sorted bits by DPP moves: wave_shl:1 gives lane + 1's
+      // value, wave_shr:1 lane - 1's, issued on every lane); the first
+      // position of a run insertion-sorts a run of at most 32, a longer run
+      // sends the segment to a stable LSD over every bit.
       auto hi_of = [&](uint64_t key) { return (uint32_t)((key - e.klo) >> shift0); };
       const uint32_t rounds = (e.len + kSegThreads - 1) / kSegThreads;
       for (uint32_t j = 0; j < rounds; ++j) {  // uniform
         const uint32_t i = threadIdx.x + j * kSegThreads;
         const bool in = i < e.len;
         const uint32_t h = in ? hi_of(sm.items[i]) : 0xffffffffu;
-        uint32_t nx = (uint32_t)__shfl_down((int)h, 1), pv = (uint32_t)__shfl_up((int)h, 1);
-        if (lane == 63) nx = i + 1 < e.len ? hi_of(sm.items[i + 1]) : 0xfffffffeu;
-        if (lane == 0) pv = i > 0 && in ? hi_of(sm.items[i - 1]) : 0xfffffffdu;
+        uint32_t nx = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)h, 0x130, 0xf, 0xf, false);
+        uint32_t pv = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)h, 0x138, 0xf, 0xf, false);
+        {
+          // lanes 63 and 0 read the positions past their wave's ends, one LDS read for the wave
+          const bool up = lane == 63, dn = lane == 0;
+          const bool ok = up ? i + 1 < e.len : (dn ? (i > 0 && in) : false);
+          const uint32_t at = ok ? (up ? i + 1 : i - 1) : 0u;
+          const uint32_t eh = hi_of(sm.items[at]);
+          if (up) nx = ok ? eh : 0xfffffffeu;
+          if (dn) pv = ok ? eh : 0xfffffffdu;
+        }
         const bool run_start = in && i + 1 < e.len && h == nx && (i == 0 || h != pv);
         if (!run_start) continue;
         uint32_t end = i + 2;

@@ -109,6 +109,21 @@ def test_short_equal_depth_runs_in_lds():
         _same_as_radix(sc, tile)
 
 
+def test_many_short_equal_depth_runs():
+    """Thousands of small clusters (a few Gaussians on one mean): tie runs of
+    2 to a few dozen keys all through the LDS-sorted segments, next to each
+    other and across wave and segment boundaries."""
+    t = _clustered(synth.make_template(5, 40000, 0, (1.0,)), 4, 4000, 0.6)
+    rng = np.random.default_rng(5)
+    crowd = synth.Crowd(tid=np.zeros(3, np.int32), yaw=np.array([0.0, 0.4, -0.3], np.float32),
+                        pos=np.array([[0.0, 0.0], [0.35, 0.6], [-0.4, 1.1]], np.float32),
+                        pose=rng.normal(0, 0.2, (3, 24, 3)).astype(np.float32))
+    cam = synth.look_at((0.0, 1.0, -3.5), (0.0, 0.9, 0.0), 320, 256)
+    sc = synth.Scene("ties_short", [t], crowd, cam, lod_thresholds=())
+    for tile in [(16, 16), (32, 16)]:
+        _same_as_radix(sc, tile)
+
+
 def test_radix_fallback_beyond_bucket_tiles():
     """A frame with more than 8192 tiles takes the radix path by itself and
     draws the same image as with 16x16 tiles."""
