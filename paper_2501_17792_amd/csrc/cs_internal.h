@@ -62,6 +62,37 @@ struct TemplateDev {
   float rest_height;
 };
 
+// The per-Gaussian columns of one template, copied out of the device
+// template table into registers once per work chunk. A reference into the
+// table would be read again after every global store of the Gaussian loop
+// (the stores may alias it), each time a dependent load before the data.
+struct TplCols {
+  const float4* mean_idx;
+  const float4* skin_w;
+  const float4* cov_a;
+  const float2* cov_b;
+  const float* opacity;
+  const float4* sh;
+  int32_t n;
+  int32_t sh_degree;
+  int32_t n_sh4;
+  // t is the same for the whole workgroup: every field is taken from the
+  // first lane, so the copy lives in scalar registers
+  __device__ __forceinline__ static TplCols of(const TemplateDev& t) {
+    return TplCols{uniform(t.mean_idx), uniform(t.skin_w), uniform(t.cov_a),
+                   uniform(t.cov_b),    uniform(t.opacity), uniform(t.sh),
+                   __builtin_amdgcn_readfirstlane(t.n), __builtin_amdgcn_readfirstlane(t.sh_degree),
+                   __builtin_amdgcn_readfirstlane(t.n_sh4)};
+  }
+  template <class P>
+  __device__ __forceinline__ static const P* uniform(const P* p) {
+    const uint64_t v = (uint64_t)(uintptr_t)p;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (const P*)(uintptr_t)(((uint64_t)hi << 32) | lo);
+  }
+};
+
 // Per-frame device header. Counters are reset by a kernel at the start of a frame.
 struct FrameHdr {
   uint32_t n_inst;

@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kChunkThreads) void splat_backward_kernel(
     const Chunk ch = w.chunks[c];
     const cs_instance in = w.inst[ch.inst];
     if (in.tid != tid_want) continue;  // uniform per block
-    const TemplateDev& T = w.tpl[in.tid];
+    const TplCols T = TplCols::of(w.tpl[in.tid]);
     __syncthreads();
     for (int e = threadIdx.x; e < kJoints * 12; e += kChunkThreads)
       s_bones[e] = w.bones[(size_t)ch.inst * kJoints * 12 + e];
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kChunkThreads) void splat_backward_kernel(
 #pragma unroll
           for (int e = 0; e < kGP; ++e) gs[e] += gpair[(size_t)(p0 + p) * kGP + e];
         Posed P;
-        skin_gaussian(s_bones, T.mean_idx[g], T.skin_w[g], T.cov_a[g], T.cov_b[g], w.skin_mode, Ry, P);
+        skin_gaussian(s_bones, gload(T.mean_idx, g), gload(T.skin_w, g), gload(T.cov_a, g), gload(T.cov_b, g), w.skin_mode, Ry, P);
         const float4 r0 = recs[3 * s], r1 = recs[3 * s + 1];
         const float A = r1.x, B = r1.y, C = r1.z, o = r1.w;
         // conic -> 2D covariance: dS = -Q G Q, G = [[gA, gB/2], [gB/2, gC]]
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(kChunkThreads) void splat_backward_kernel(
         float coef[48];
         for (int q = 0; q < 48; ++q) coef[q] = 0.f;
         for (int j = 0; j < T.n_sh4; ++j) {
-          const float4 v = T.sh[(size_t)j * T.n + g];
+          const float4 v = gload(T.sh, (size_t)j * T.n + g);
           const float ev[4] = {v.x, v.y, v.z, v.w};
           for (int l = 0; l < 4; ++l)
             if (4 * j + l < 3 * nb) coef[4 * j + l] = ev[l];

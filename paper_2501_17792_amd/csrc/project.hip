@@ -10,7 +10,7 @@ namespace cs {
 // constant so that every SH plane load of a Gaussian is issued at once).
 template <int DEG>
 __device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOut& skinned, int fused,
-                                                  const CamDev& cam, const SplatOut& out, const TemplateDev& T,
+                                                  const CamDev& cam, const SplatOut& out, const TplCols& T,
                                                   const float* s_bones, const float Ry[9], const Chunk ch,
                                                   uint32_t base, int n_here) {
   uint32_t vis = 0;
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kChunkThreads) void project_kernel(WorkDev w, SkinO
   for (int c = chunk_lo + blockIdx.x; c < hi; c += gridDim.x) {
     const Chunk ch = w.chunks[c];
     const cs_instance in = w.inst[ch.inst];
-    const TemplateDev& T = w.tpl[in.tid];
+    const TplCols T = TplCols::of(w.tpl[in.tid]);
     for (int e = threadIdx.x; e < kJoints * 12; e += kChunkThreads)
       s_bones[e] = w.bones[(size_t)ch.inst * kJoints * 12 + e];
     if (threadIdx.x == 0) s_vis = 0;

@@ -421,7 +421,7 @@ __global__ __launch_bounds__(kChunkThreads) void skin_kernel(WorkDev w, SkinOut 
   for (int c = chunk_lo + blockIdx.x; c < hi; c += gridDim.x) {
     const Chunk ch = w.chunks[c];
     const cs_instance in = w.inst[ch.inst];
-    const TemplateDev& T = w.tpl[in.tid];
+    const TplCols T = TplCols::of(w.tpl[in.tid]);
     for (int e = threadIdx.x; e < kJoints * 12; e += kChunkThreads)
       s_bones[e] = w.bones[(size_t)ch.inst * kJoints * 12 + e];
     __syncthreads();
