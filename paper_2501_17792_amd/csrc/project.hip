@@ -6,8 +6,17 @@
 
 namespace cs {
 
+// SH planes already loaded into registers (plane j at index j, stride 1).
+template <int N4>
+struct RegPlanes {
+  const float4* v;
+  __device__ __forceinline__ float4 operator[](size_t j) const { return v[j]; }
+};
+
 // The Gaussians of one chunk; DEG is the template's SH degree (a compile-time
-// constant so that every SH plane load of a Gaussian is issued at once).
+// constant so that every SH plane load of a Gaussian is issued at once). The
+// SH planes and the opacity are loaded first, so that their latency overlaps
+// skinning and the EWA projection instead of sitting in front of the colour.
 template <int DEG>
 __device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOut& skinned, int fused,
                                                   const CamDev& cam, const SplatOut& out, const TplCols& T,
@@ -18,10 +27,19 @@ __device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOu
     const int g = ch.g0 + k;
     const size_t s = (size_t)base + g;
     Posed p;
+    // geometry first: the loads complete in issue order, so the wait for
+    // them does not include the SH planes issued after them
     const float4 mi = gload(T.mean_idx, g);
     const float4 wt = gload(T.skin_w, g);
+    const float4 ca = fused ? gload(T.cov_a, g) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float2 cb = fused ? gload(T.cov_b, g) : make_float2(0.f, 0.f);
+    constexpr int N4 = (3 * (DEG + 1) * (DEG + 1) + 3) / 4;
+    float4 shv[N4];
+#pragma unroll
+    for (int j = 0; j < N4; ++j) shv[j] = gload(T.sh, (size_t)j * T.n + g);
+    const float op = gload(T.opacity, g);
     if (fused) {
-      skin_gaussian(s_bones, mi, wt, gload(T.cov_a, g), gload(T.cov_b, g), w.skin_mode, Ry, p);
+      skin_gaussian(s_bones, mi, wt, ca, cb, w.skin_mode, Ry, p);
     } else {
       const float4 m = skinned.mu[s];
       const float4 cv = skinned.cov[s];
@@ -40,7 +58,7 @@ __device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOu
       }
     }
     SplatRec r;
-    project_gaussian<DEG>(p, gload(T.opacity, g), GlobalPlanes{T.sh + g}, T.n, cam, r);
+    project_gaussian<DEG>(p, op, RegPlanes<N4>{shv}, 1, cam, r);
     if (w.crop && r.count) {  // view mode: keep the tiles inside the instance's window
       const int4 cw = w.crop[ch.inst];
       const int x0 = max((int)(r.rect & 0xffu), cw.x), y0 = max((int)((r.rect >> 8) & 0xffu), cw.y);
@@ -71,7 +89,7 @@ __device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOu
 // here (bit-identical to the skin kernel); otherwise the posed mean and
 // covariance are read back and only the blended linear part is rebuilt for
 // the colour direction.
-__global__ __launch_bounds__(kChunkThreads) void project_kernel(WorkDev w, SkinOut skinned,
+__global__ __launch_bounds__(kChunkThreads) __attribute__((amdgpu_waves_per_eu(3))) void project_kernel(WorkDev w, SkinOut skinned,
                                                                 int fused, CamDev cam, SplatOut out,
                                                                 int chunk_lo, int chunk_hi) {
   __shared__ float s_bones[kJoints * 12];
