@@ -39,11 +39,11 @@ HBM_PEAK_GBS = 8000.0
 # factors a plain 1 GiB copy gives), summarised in profiles/crowd3500_1080p_learned_lod_kernels.md and
 # profiles/crowd3500_1080p_learned_lod_32x16_kernels.md. They hold only for the kernel sources they were
 # taken on (digest below) and that workload; otherwise the bench reports null.
-MEASURED_TRAFFIC = {"digest": "0c3627fc50b0b0e7", "lod": "learned",
+MEASURED_TRAFFIC = {"digest": "1e520ee49f2114a8", "lod": "learned",
                     "bytes": {(16, 16): {"sort": 21.70e9, "segsort": 5.69e9, "emit": 8.67e9,
-                                         "project_fused": 18.97e9, "blend": 2.51e9},
-                              (32, 16): {"sort": 20.74e9, "segsort": 4.96e9, "emit": 8.00e9,
-                                         "project_fused": 18.97e9, "blend": 2.83e9}}}
+                                         "project_fused": 18.95e9, "blend": 2.51e9},
+                              (32, 16): {"sort": 20.75e9, "segsort": 4.96e9, "emit": 8.00e9,
+                                         "project_fused": 18.96e9, "blend": 2.83e9}}}
 
 
 def kernel_digest():

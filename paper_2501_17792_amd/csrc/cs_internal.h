@@ -9,7 +9,7 @@
 namespace cs {
 
 constexpr int kJoints = 24;
-constexpr int kChunk = 1024;          // Gaussians per work chunk (one instance each)
+constexpr int kChunk = 2048;          // Gaussians per work chunk (one instance each)
 constexpr int kChunkThreads = 256;    // threads per skin / project block
 constexpr int kMaxLevels = CS_MAX_LEVELS;
 constexpr int kMaxTemplates = CS_MAX_TEMPLATES;
