@@ -64,9 +64,9 @@ def log(*a):
 
 
 def algorithmic_bytes(stage, st, scene, uniq):
-    """Algorithmic HBM bytes of one frame's pass through a stage (the byte
-    model is stated per stage in the design doc): N splats, P tile pairs, U unique
-    template Gaussians drawn this frame."""
+    """Algorithmic HBM bytes of one frame's pass through a stage: what the
+    stage must read and write at least, from N splats, P tile pairs and U
+    unique template Gaussians drawn this frame (the per-stage terms below)."""
     n, p = float(st["n_splats"]), float(st["n_pairs"])
     W, H = scene.camera.width, scene.camera.height
     sh_bytes = 16 * 12  # SH3: 48 floats per Gaussian

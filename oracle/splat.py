@@ -8,7 +8,7 @@ list front to back, and alpha-composite per pixel. The constants are that
 renderer's: alpha clamped to 0.99, contributions below 1/255 skipped, and a
 pixel stops before its transmittance would fall below 1e-4.
 
-Readings where the paper is silent (listed in the design doc):
+Readings where the paper is silent (the same ones the GPU library takes):
 * pinhole camera, vertical field of view, pixel centres at +1/2, near plane
   0.2 m, a 1.5x guard band on the normalised image coordinates;
 * the screen-space covariance gets +0.3 px^2 on its diagonal (low-pass
