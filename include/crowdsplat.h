@@ -76,8 +76,18 @@ typedef struct cs_options {
   int64_t max_splats;        /* fixed splat capacity (0: grow on demand)        */
   int64_t max_pairs;         /* fixed tile-pair capacity (0: grow on demand)    */
   int32_t sort_algo;         /* CS_SORT_TILE_BUCKET (default) | _ONESWEEP | _REDUCE_SCAN */
-  int32_t reserved[7];
+  int32_t sort_ranks;        /* CS_SORT_RANKS_CHECKED (default) | CS_SORT_RANKS_BALLOT  */
+  int32_t reserved[6];
 } cs_options;
+
+/* How the tile-bucket form's LDS segment sort ranks radix digits inside a
+ * wave. Both give the same order (tested).
+ * CHECKED: per-lane LDS atomics; each sorted segment is then checked to be
+ *   strictly increasing (keys are unique inside a tile) and a segment that is
+ *   not is sorted again with ballot ranks (counted in cs_frame_stats).
+ * BALLOT: ranks from per-bit ballots in every pass (slower). */
+#define CS_SORT_RANKS_CHECKED 0
+#define CS_SORT_RANKS_BALLOT  1
 
 /* How frames bin and order their tile pairs. All three give the same ranges
  * and the same per-tile order (the stable sort of the emitted keys).
@@ -165,9 +175,17 @@ typedef struct cs_frame_stats {
   int64_t n_splats;          /* instance-Gaussians skinned this frame           */
   int64_t n_visible;         /* splats that emitted at least one tile pair      */
   int64_t n_pairs;           /* (tile, splat) pairs sorted                      */
-  int32_t overflow;          /* nonzero: a fixed capacity was exceeded          */
+  int32_t overflow;          /* nonzero: a fixed capacity was exceeded (bits:
+                                1 splats, 2 pairs, 4 instances, 8 chunks,
+                                16 bad template id, 32 segment lists, 64 a
+                                sorted segment failed its order check)         */
   int32_t n_instances;
   int32_t level_hist[CS_MAX_LEVELS];
+  int32_t sort_fallbacks;    /* LDS-sorted segments re-sorted with ballot ranks */
+  int32_t reserved0;
+  int64_t blend_evals;       /* profile_stages only: (pixel, splat) opacity
+                                evaluations the blend ran; else 0             */
+  int64_t reserved[4];
 } cs_frame_stats;
 
 /* Context lifetime. stream: a hipStream_t (NULL = the null stream). */

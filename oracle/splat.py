@@ -140,6 +140,33 @@ def footprint(u, v, a, c, opacity, visible, width, height, tw, th):
                 visible=vis, bounds=bounds)
 
 
+def footprint_rect_f32(u, v, rx, ry, depth, width, height, tw, th):
+    """The integer part of the footprint taken in float32, the precision the
+    renderer decides it in: from a splat's float32 screen centre (u, v), box
+    half-extents (rx, ry) and depth (0 = culled before the footprint), the
+    pixel bounds floor(u - rx), floor(u + rx), ... come from float32
+    subtractions (IEEE round to nearest), then the off-screen cull, the clamp
+    to the image and the integer division by the tile size of ``footprint``.
+    Returns (rect [N,4], count [N], visible [N])."""
+    f32 = np.float32
+    u, v = np.asarray(u, f32), np.asarray(v, f32)
+    rx, ry = np.asarray(rx, f32), np.asarray(ry, f32)
+    vis = np.asarray(depth, np.float64) > 0.0
+    px0 = np.floor(u - rx).astype(np.float64)
+    px1 = np.floor(u + rx).astype(np.float64)
+    py0 = np.floor(v - ry).astype(np.float64)
+    py1 = np.floor(v + ry).astype(np.float64)
+    vis &= (px1 >= 0) & (px0 <= width - 1) & (py1 >= 0) & (py0 <= height - 1)
+    px0 = np.clip(px0, 0, width - 1).astype(np.int64)
+    px1 = np.clip(px1, 0, width - 1).astype(np.int64)
+    py0 = np.clip(py0, 0, height - 1).astype(np.int64)
+    py1 = np.clip(py1, 0, height - 1).astype(np.int64)
+    rect = np.stack([px0 // tw, py0 // th, px1 // tw, py1 // th], axis=1)
+    rect[~vis] = 0
+    count = np.where(vis, (rect[:, 2] - rect[:, 0] + 1) * (rect[:, 3] - rect[:, 1] + 1), 0)
+    return rect, count.astype(np.int64), vis
+
+
 # ----------------------------------------------------------------------------
 # binning and the stable (tile | depth) sort
 # ----------------------------------------------------------------------------
@@ -246,10 +273,69 @@ def _blend_list(px, py, order, sp, bg, fragile_alpha, fragile_t, tie_impact=None
     return C, T, fragile, n_added
 
 
+def _blend_list_chunked(px, py, order, sp, bg, fragile_alpha, fragile_t, chunk=2048):
+    """The same front-to-back walk as ``_blend_list`` (without the tie test),
+    taken ``chunk`` splats at a time for every still-unfinished pixel at once,
+    for lists of millions of splats. Each pixel's transmittance before splat k
+    is the running product T0 (1 - a_0) (1 - a_1) ... over the splats it adds,
+    formed in the loop's order (np.cumprod multiplies left to right), and its
+    colour the running sum of the added c a T, also in the loop's order
+    (np.cumsum), so the results equal the loop's bit for bit."""
+    P = px.shape[0]
+    T = np.ones(P)
+    C = np.zeros((3, P))
+    done = np.zeros(P, bool)
+    fragile = np.zeros(P, bool)
+    n_added = np.zeros(P, np.int64)
+    cx, cy = px + 0.5, py + 0.5
+    order = np.asarray(order, np.int64)
+    for c0 in range(0, order.shape[0], chunk):
+        live = np.nonzero(~done)[0]
+        if live.size == 0:
+            break
+        s = order[c0:c0 + chunk]
+        K = s.shape[0]
+        dx = cx[live, None] - sp["u"][s][None, :]
+        dy = cy[live, None] - sp["v"][s][None, :]
+        power = -0.5 * (sp["A"][s][None] * dx * dx + 2.0 * sp["B"][s][None] * dx * dy
+                        + sp["C"][s][None] * dy * dy)
+        power = np.minimum(0.0, power)
+        raw = sp["opacity"][s][None] * np.exp(power)
+        alpha = np.minimum(ALPHA_MAX, raw)
+        use = alpha >= ALPHA_MIN
+        factor = np.where(use, 1.0 - alpha, 1.0)
+        # transmittance before each splat (the first column is T itself)
+        Tb = np.cumprod(np.concatenate([T[live, None], factor], axis=1), axis=1)
+        Tn = Tb[:, :-1] * (1.0 - alpha)
+        Tb = Tb[:, :-1]
+        stop = use & (Tn < T_MIN)
+        has_stop = stop.any(axis=1)
+        k_stop = np.where(has_stop, np.argmax(stop, axis=1), K)
+        k = np.arange(K)[None, :]
+        evaluated = k <= k_stop[:, None]          # the stopping splat is evaluated, not added
+        add = use & (k < k_stop[:, None])
+        fragile[live] |= (evaluated & (np.abs(raw - ALPHA_MIN) <= fragile_alpha * ALPHA_MIN)).any(axis=1)
+        fragile[live] |= (evaluated & use & (np.abs(Tn - T_MIN) <= fragile_t * T_MIN)).any(axis=1)
+        wgt = np.where(add, alpha * Tb, 0.0)
+        for ch in range(3):
+            contrib = np.where(add, sp["rgb"][s, ch][None] * wgt, 0.0)
+            C[ch, live] = np.cumsum(np.concatenate([C[ch, live][:, None], contrib], axis=1), axis=1)[:, -1]
+        # new transmittance: the product up to the stop (exclusive) or over the whole chunk
+        last = np.cumprod(np.concatenate([T[live, None], np.where(add, 1.0 - alpha, 1.0)], axis=1), axis=1)[:, -1]
+        T[live] = last
+        n_added[live] += add.sum(axis=1)
+        done[live] = has_stop
+    C += T[None, :] * np.asarray(bg, np.float64)[:, None]
+    return C, T, fragile, n_added
+
+
 def composite_tiled(sp, sorted_vals, ranges, width, height, tw, th, bg,
-                    fragile_alpha=1e-4, fragile_t=1e-4, tiles=None, tie_impact=None):
+                    fragile_alpha=1e-4, fragile_t=1e-4, tiles=None, tie_impact=None,
+                    chunked=False):
     """Per-tile front-to-back compositing over each tile's sorted list.
-    Returns image [3,H,W], final transmittance [H,W] and the fragile mask."""
+    Returns image [3,H,W], final transmittance [H,W] and the fragile mask.
+    ``chunked`` walks the lists with ``_blend_list_chunked`` (same results,
+    for long lists; no tie test)."""
     ntx = (width + tw - 1) // tw
     nty = (height + th - 1) // th
     img = np.zeros((3, height, width))
@@ -262,9 +348,13 @@ def composite_tiled(sp, sorted_vals, ranges, width, height, tw, th, bg,
         x1, y1 = min(x0 + tw, width), min(y0 + th, height)
         gy, gx = np.mgrid[y0:y1, x0:x1]
         s0, s1 = ranges[t]
-        C, T, f, _ = _blend_list(gx.ravel().astype(np.float64), gy.ravel().astype(np.float64),
-                                 sorted_vals[s0:s1], sp, bg, fragile_alpha, fragile_t,
-                                 tie_impact)
+        if chunked:
+            C, T, f, _ = _blend_list_chunked(gx.ravel().astype(np.float64), gy.ravel().astype(np.float64),
+                                             sorted_vals[s0:s1], sp, bg, fragile_alpha, fragile_t)
+        else:
+            C, T, f, _ = _blend_list(gx.ravel().astype(np.float64), gy.ravel().astype(np.float64),
+                                     sorted_vals[s0:s1], sp, bg, fragile_alpha, fragile_t,
+                                     tie_impact)
         img[:, y0:y1, x0:x1] = C.reshape(3, y1 - y0, x1 - x0)
         Tfin[y0:y1, x0:x1] = T.reshape(y1 - y0, x1 - x0)
         frag[y0:y1, x0:x1] = f.reshape(y1 - y0, x1 - x0)

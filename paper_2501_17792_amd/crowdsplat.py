@@ -22,6 +22,7 @@ CS_MEM_HOST, CS_MEM_DEVICE = 0, 1
 CS_SKIN_FULL, CS_SKIN_MEANS_ONLY = 0, 1
 CS_LAUNCH_BATCHED, CS_LAUNCH_PER_INSTANCE = 0, 1
 CS_SORT_TILE_BUCKET, CS_SORT_ONESWEEP, CS_SORT_REDUCE_SCAN = 0, 1, 2
+CS_SORT_RANKS_CHECKED, CS_SORT_RANKS_BALLOT = 0, 1
 CS_LOD_FULL, CS_LOD_FIXED, CS_LOD_LEARNED, CS_LOD_CONSTANT = 0, 1, 2, 3
 CS_MLP_NPARAM, CS_MLP_NBF16 = 7312, 7168
 #: offsets of the layers inside cs_mlp.params (out-major weights)
@@ -48,7 +49,8 @@ class CsOptions(ctypes.Structure):
                 ("skin_mode", ctypes.c_int32), ("launch_mode", ctypes.c_int32),
                 ("fuse_skin_project", ctypes.c_int32), ("profile_stages", ctypes.c_int32),
                 ("max_splats", ctypes.c_int64), ("max_pairs", ctypes.c_int64),
-                ("sort_algo", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("sort_algo", ctypes.c_int32), ("sort_ranks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 class CsTemplateDesc(ctypes.Structure):
@@ -83,7 +85,9 @@ class CsMlp(ctypes.Structure):
 class CsFrameStats(ctypes.Structure):
     _fields_ = [("n_splats", ctypes.c_int64), ("n_visible", ctypes.c_int64),
                 ("n_pairs", ctypes.c_int64), ("overflow", ctypes.c_int32),
-                ("n_instances", ctypes.c_int32), ("level_hist", ctypes.c_int32 * CS_MAX_LEVELS)]
+                ("n_instances", ctypes.c_int32), ("level_hist", ctypes.c_int32 * CS_MAX_LEVELS),
+                ("sort_fallbacks", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("blend_evals", ctypes.c_int64), ("reserved", ctypes.c_int64 * 4)]
 
 
 class CsTemplateGrads(ctypes.Structure):
@@ -190,7 +194,7 @@ class Renderer:
 
     def __init__(self, device: int = 0, stream=None, tile=(16, 16), skin_mode=CS_SKIN_FULL,
                  launch_mode=CS_LAUNCH_BATCHED, fuse=False, max_splats=0, max_pairs=0,
-                 profile=False, sort_algo=CS_SORT_TILE_BUCKET):
+                 profile=False, sort_algo=CS_SORT_TILE_BUCKET, sort_ranks=CS_SORT_RANKS_CHECKED):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -201,6 +205,7 @@ class Renderer:
         opt.skin_mode, opt.launch_mode, opt.fuse_skin_project = skin_mode, launch_mode, int(fuse)
         opt.profile_stages = int(profile)
         opt.sort_algo = sort_algo
+        opt.sort_ranks = sort_ranks
         opt.max_splats, opt.max_pairs = max_splats, max_pairs
         self.tile = tuple(tile)
         ctx = ctypes.c_void_p()
@@ -281,6 +286,7 @@ class Renderer:
         self._check(self.lib.cs_render_frame(self.ctx, ctypes.byref(c), image.data_ptr(),
                                              ctypes.byref(st) if stats else None))
         self.last_stats = st if stats else None
+        self.last_camera = cam
         return image
 
     def frame(self, cam, mode=CS_LOD_FIXED, thresholds=(10.0, 25.0), image=None, stats=False):

@@ -507,8 +507,22 @@ __global__ __launch_bounds__(kBkThreads) void split_scatter_kernel(int level, co
 // ---------------------------------------------------------------------------
 // 5. LDS sort of one segment of at most kSegCap keys. Keys live in registers
 // in block order i = wave * 1024 + k * 64 + lane; each LSD pass ranks 8-bit
-// digits stably (per-wave digit counts taken by LDS atomics, which return
-// their old values in lane order) and exchanges the keys through LDS.
+// digits stably inside every wave and exchanges the keys through LDS.
+//
+// Two ways to rank a digit inside one wave instruction:
+//   atomic  every lane adds one to its digit's per-wave LDS counter and takes
+//           the returned old value. That is the stable rank only if the LDS
+//           unit hands out the returns of one instruction's lanes that hit
+//           one address in lane order, which gfx950 did in every measurement
+//           but no document promises;
+//   ballot  the lanes holding the same digit are found with 8 ballots (one
+//           per digit bit), the lowest of them adds the group's size to the
+//           counter, and each lane's rank is the group's base plus the number
+//           of group lanes below it: only documented behaviour.
+// The fast atomic form is checked: keys are unique inside a tile, so a
+// correctly sorted segment is strictly increasing. A segment that is not is
+// sorted again from its input with ballot ranks (and counted in the frame
+// header), so a different lane order could cost time but never the order.
 // ---------------------------------------------------------------------------
 struct SegSmem {
   uint64_t items[kSegCap];
@@ -521,22 +535,43 @@ __device__ __forceinline__ uint32_t seg_digit(uint64_t K, uint64_t klo, int shif
   return (uint32_t)((K - klo) >> shift) & 255u;
 }
 
+// Ballot rank of an active lane's digit d (8 bits): its group is the lanes
+// of the wave with the same digit; the group's lowest lane takes the group's
+// slots from the per-wave counter in one atomic, so no two lanes of one
+// instruction touch one address.
+__device__ __forceinline__ uint32_t ballot_rank(uint32_t* wh, uint32_t d, bool act) {
+  uint64_t m = __ballot(act);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint64_t bb = __ballot((d >> b) & 1u);
+    m &= ((d >> b) & 1u) ? bb : ~bb;
+  }
+  const int lane = bk_lane();
+  const int leader = m ? __ffsll((unsigned long long)m) - 1 : lane;
+  uint32_t base = 0;
+  if (act && lane == leader) base = atomicAdd(&wh[d], (uint32_t)__popcll(m));
+  base = (uint32_t)__shfl((int)base, leader);
+  return base + (uint32_t)__popcll(m & lanes_below());
+}
+
 // One stable pass on the digit at `shift` of K - klo. The per-wave digit
 // rows are zero on entry and are left zero (each wave clears its own row once
 // its scatter has read it), so only the kernel's start clears them.
+template <bool kBallot>
 __device__ void lsd_pass(SegSmem& sm, uint64_t (&K)[kSegItems], uint32_t len, uint64_t klo, int shift) {
   const int lane = bk_lane(), wave = (int)(threadIdx.x >> 6);
   uint32_t* wh = sm.whist + wave * 256;
-  // Rank inside the wave: every lane adds one to its digit's per-wave count.
-  // The LDS unit applies the lanes of one atomic instruction in lane order
-  // (lanes sharing an address get increasing old values) and a wave's
-  // instructions in issue order, so the returned counts are the stable ranks
-  // in item order wave * 1024 + k * 64 + lane.
+  // Rank inside the wave, in item order wave * 1024 + k * 64 + lane: a wave's
+  // LDS instructions take effect in issue order, and within one instruction
+  // the ranks come from ballots, or from the atomics' lane order (checked
+  // after the sort).
   uint32_t rank[kSegItems];
 #pragma unroll
   for (int k = 0; k < kSegItems; ++k) {
     const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
-    rank[k] = idx < len ? atomicAdd(&wh[seg_digit(K[k], klo, shift)], 1u) : 0u;
+    const uint32_t d = seg_digit(K[k], klo, shift);
+    if (kBallot) rank[k] = ballot_rank(wh, d, idx < len);
+    else rank[k] = idx < len ? atomicAdd(&wh[d], 1u) : 0u;
   }
   __syncthreads();
   // Threads 0..255 (four whole waves), one digit each: digit total over the
@@ -575,10 +610,124 @@ __device__ void lsd_pass(SegSmem& sm, uint64_t (&K)[kSegItems], uint32_t len, ui
   }
 }
 
+// Sorts segment e into sm.items[0, e.len) (block-wide; ends with a barrier).
+template <bool kBallot>
+__device__ void sort_segment(SegSmem& sm, const SegEntry& e, const uint64_t* src) {
+  const int lane = bk_lane(), wave = (int)(threadIdx.x >> 6);
+  uint64_t K[kSegItems];
+#pragma unroll
+  for (int k = 0; k < kSegItems; ++k) {
+    const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
+    K[k] = idx < e.len ? src[e.start + idx] : 0ull;
+  }
+  // Above 32 bits only the depth part is radix sorted, together with as
+  // many top bits of the low word as the passes' last digit has room for
+  // (they cost nothing and split most runs of equal depth); keys equal in
+  // the sorted bits are put in order afterwards.
+  const bool hi_only = e.dbits > 32;
+  const int passes = hi_only ? ((int)e.dbits - 32 + 7) / 8 : ((int)e.dbits + 7) / 8;
+  const int shift0 = hi_only ? (int)e.dbits - 8 * passes : 0;  // 25..32
+  for (int p = 0; p < passes; ++p) lsd_pass<kBallot>(sm, K, e.len, e.klo, shift0 + 8 * p);
+  if (passes == 0) {
+#pragma unroll
+    for (int k = 0; k < kSegItems; ++k) {
+      const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
+      if (idx < e.len) sm.items[idx] = K[k];
+    }
+  }
+  if (threadIdx.x == 0) sm.flag = 0;
+  __syncthreads();
+  if (!hi_only) return;
+  // Runs of equal (K - klo) >> shift0 (equal sorted bits) are put in key
+  // order: positions i = threadIdx.x + j * kSegThreads, so neighbours in
+  // the list are neighbouring lanes (one LDS read per position, the
+  // neighbours' sorted bits by DPP moves: wave_shl:1 gives lane + 1's
+  // value, wave_shr:1 lane - 1's, issued on every lane); the first
+  // position of a run insertion-sorts a run of at most 32, a longer run
+  // sends the segment to a stable LSD over every bit.
+  auto hi_of = [&](uint64_t key) { return (uint32_t)((key - e.klo) >> shift0); };
+  const uint32_t rounds = (e.len + kSegThreads - 1) / kSegThreads;
+  for (uint32_t j = 0; j < rounds; ++j) {  // uniform
+    const uint32_t i = threadIdx.x + j * kSegThreads;
+    const bool in = i < e.len;
+    const uint32_t h = in ? hi_of(sm.items[i]) : 0xffffffffu;
+    uint32_t nx = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)h, 0x130, 0xf, 0xf, false);
+    uint32_t pv = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)h, 0x138, 0xf, 0xf, false);
+    {
+      // lanes 63 and 0 read the positions past their wave's ends, one LDS read for the wave
+      const bool up = lane == 63, dn = lane == 0;
+      const bool ok = up ? i + 1 < e.len : (dn ? (i > 0 && in) : false);
+      const uint32_t at = ok ? (up ? i + 1 : i - 1) : 0u;
+      const uint32_t eh = hi_of(sm.items[at]);
+      if (up) nx = ok ? eh : 0xfffffffeu;
+      if (dn) pv = ok ? eh : 0xfffffffdu;
+    }
+    const bool run_start = in && i + 1 < e.len && h == nx && (i == 0 || h != pv);
+    if (!run_start) continue;
+    uint32_t end = i + 2;
+    while (end < e.len && end - i <= 32 && hi_of(sm.items[end]) == h) ++end;
+    if (end - i > 32) {
+      sm.flag = 1;
+      continue;
+    }
+    for (uint32_t a = i + 1; a < end; ++a) {
+      const uint64_t x = sm.items[a];
+      uint32_t b = a;
+      while (b > i && sm.items[b - 1] > x) {
+        sm.items[b] = sm.items[b - 1];
+        --b;
+      }
+      sm.items[b] = x;
+    }
+  }
+  __syncthreads();
+  if (sm.flag) {  // long tie runs: stable LSD over every bit of K - klo
+#pragma unroll
+    for (int k = 0; k < kSegItems; ++k) {
+      const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
+      K[k] = idx < e.len ? sm.items[idx] : 0ull;
+    }
+    __syncthreads();
+    const int full = ((int)e.dbits + 7) / 8;
+    for (int p = 0; p < full; ++p) lsd_pass<kBallot>(sm, K, e.len, e.klo, 8 * p);
+    __syncthreads();
+  }
+}
+
+// A stable LSD over every bit of K - klo with ballot ranks: the re-sort of a
+// segment whose checked order failed.
+__device__ void sort_segment_ballot_full(SegSmem& sm, const SegEntry& e, const uint64_t* src) {
+  const int lane = bk_lane(), wave = (int)(threadIdx.x >> 6);
+  uint64_t K[kSegItems];
+#pragma unroll
+  for (int k = 0; k < kSegItems; ++k) {
+    const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
+    K[k] = idx < e.len ? src[e.start + idx] : 0ull;
+  }
+  const int full = ((int)e.dbits + 7) / 8;
+  for (int p = 0; p < full; ++p) lsd_pass<true>(sm, K, e.len, e.klo, 8 * p);
+  if (full == 0) {
+#pragma unroll
+    for (int k = 0; k < kSegItems; ++k) {
+      const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
+      if (idx < e.len) sm.items[idx] = K[k];
+    }
+  }
+  __syncthreads();
+}
+
+// true (on every thread) if sm.items[0, len) is not strictly increasing
+__device__ __forceinline__ bool segment_out_of_order(const SegSmem& sm, uint32_t len) {
+  bool bad = false;
+  for (uint32_t i = threadIdx.x; i + 1 < len; i += kSegThreads) bad |= sm.items[i] >= sm.items[i + 1];
+  return __syncthreads_or(bad) != 0;
+}
+
+template <bool kBallot>
 __global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(const uint32_t* __restrict__ ranges,
                                                               const uint32_t* __restrict__ g_minc,
                                                               const uint32_t* __restrict__ g_max, int n_tiles,
-                                                              const FrameHdr* __restrict__ hdr, uint32_t max_pairs,
+                                                              FrameHdr* __restrict__ hdr, uint32_t max_pairs,
                                                               const uint64_t* __restrict__ keys0,
                                                               const uint64_t* __restrict__ keys1, SegLists lists,
                                                               uint32_t* __restrict__ vals) {
@@ -587,7 +736,6 @@ __global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(const uint32_t* _
   for (int i = threadIdx.x; i < kSegWaves * 256; i += kSegThreads) sm.whist[i] = 0;  // kept zero between passes
   __syncthreads();
   const uint32_t n_work = min(lists.counters[kCtrBase], lists.cap_base);
-  const int lane = bk_lane(), wave = (int)(threadIdx.x >> 6);
   // static round-robin over the base list (segments are of similar size);
   // the next entry is read while the current segment is sorted
   SegEntry nxt{};
@@ -598,84 +746,15 @@ __global__ __launch_bounds__(kSegThreads) void seg_sort_kernel(const uint32_t* _
     __syncthreads();  // the previous segment's LDS is no longer read
     if (e.len == 0 || e.len > (uint32_t)kSegCap) continue;
     const uint64_t* src = e.buf ? keys1 : keys0;
-    uint64_t K[kSegItems];
-#pragma unroll
-    for (int k = 0; k < kSegItems; ++k) {
-      const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
-      K[k] = idx < e.len ? src[e.start + idx] : 0ull;
-    }
-    // Above 32 bits only the depth part is radix sorted, together with as
-    // many top bits of the low word as the passes' last digit has room for
-    // (they cost nothing and split most runs of equal depth); keys equal in
-    // the sorted bits are put in order afterwards.
-    const bool hi_only = e.dbits > 32;
-    const int passes = hi_only ? ((int)e.dbits - 32 + 7) / 8 : ((int)e.dbits + 7) / 8;
-    const int shift0 = hi_only ? (int)e.dbits - 8 * passes : 0;  // 25..32
-    for (int p = 0; p < passes; ++p) lsd_pass(sm, K, e.len, e.klo, shift0 + 8 * p);
-    if (passes == 0) {
-#pragma unroll
-      for (int k = 0; k < kSegItems; ++k) {
-        const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
-        if (idx < e.len) sm.items[idx] = K[k];
+    sort_segment<kBallot>(sm, e, src);
+    if (segment_out_of_order(sm, e.len)) {
+      bool still = true;
+      if (!kBallot) {
+        if (threadIdx.x == 0) atomicAdd(&hdr->sort_fallbacks, 1u);
+        sort_segment_ballot_full(sm, e, src);
+        still = segment_out_of_order(sm, e.len);
       }
-    }
-    if (threadIdx.x == 0) sm.flag = 0;
-    __syncthreads();
-    if (hi_only) {
-      // Runs of equal (K - klo) >> shift0 (equal sorted bits) are put in key
-      // order: positions i = threadIdx.x + j * kSegThreads, so neighbours in
-      // the list are neighbouring lanes (one LDS read per position, the
-      // neighbours' sorted bits by DPP moves: wave_shl:1 gives lane + 1's
-      // value, wave_shr:1 lane - 1's, issued on every lane); the first
-      // position of a run insertion-sorts a run of at most 32, a longer run
-      // sends the segment to a stable LSD over every bit.
-      auto hi_of = [&](uint64_t key) { return (uint32_t)((key - e.klo) >> shift0); };
-      const uint32_t rounds = (e.len + kSegThreads - 1) / kSegThreads;
-      for (uint32_t j = 0; j < rounds; ++j) {  // uniform
-        const uint32_t i = threadIdx.x + j * kSegThreads;
-        const bool in = i < e.len;
-        const uint32_t h = in ? hi_of(sm.items[i]) : 0xffffffffu;
-        uint32_t nx = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)h, 0x130, 0xf, 0xf, false);
-        uint32_t pv = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)h, 0x138, 0xf, 0xf, false);
-        {
-          // lanes 63 and 0 read the positions past their wave's ends, one LDS read for the wave
-          const bool up = lane == 63, dn = lane == 0;
-          const bool ok = up ? i + 1 < e.len : (dn ? (i > 0 && in) : false);
-          const uint32_t at = ok ? (up ? i + 1 : i - 1) : 0u;
-          const uint32_t eh = hi_of(sm.items[at]);
-          if (up) nx = ok ? eh : 0xfffffffeu;
-          if (dn) pv = ok ? eh : 0xfffffffdu;
-        }
-        const bool run_start = in && i + 1 < e.len && h == nx && (i == 0 || h != pv);
-        if (!run_start) continue;
-        uint32_t end = i + 2;
-        while (end < e.len && end - i <= 32 && hi_of(sm.items[end]) == h) ++end;
-        if (end - i > 32) {
-          sm.flag = 1;
-          continue;
-        }
-        for (uint32_t a = i + 1; a < end; ++a) {
-          const uint64_t x = sm.items[a];
-          uint32_t b = a;
-          while (b > i && sm.items[b - 1] > x) {
-            sm.items[b] = sm.items[b - 1];
-            --b;
-          }
-          sm.items[b] = x;
-        }
-      }
-      __syncthreads();
-      if (sm.flag) {  // long tie runs: stable LSD over every bit of K - klo
-#pragma unroll
-        for (int k = 0; k < kSegItems; ++k) {
-          const uint32_t idx = (uint32_t)(wave * 64 * kSegItems + k * 64 + lane);
-          K[k] = idx < e.len ? sm.items[idx] : 0ull;
-        }
-        __syncthreads();
-        const int full = ((int)e.dbits + 7) / 8;
-        for (int p = 0; p < full; ++p) lsd_pass(sm, K, e.len, e.klo, 8 * p);
-        __syncthreads();
-      }
+      if (still && threadIdx.x == 0) atomicOr(&hdr->overflow, 64u);  // a bug, never a lane order
     }
     for (uint32_t i = threadIdx.x; i < e.len; i += kSegThreads) vals[e.start + i] = (uint32_t)sm.items[i];
   }
@@ -743,9 +822,13 @@ hipError_t launch_seg_split(const uint32_t* ranges, const uint32_t* region, int 
 
 hipError_t launch_seg_sort(const uint32_t* ranges, const uint32_t* region, int n_tiles, FrameHdr* hdr,
                            uint32_t max_pairs, const uint64_t* keys0, const uint64_t* keys1, SegLists lists,
-                           uint32_t* vals, int grid, hipStream_t st) {
-  seg_sort_kernel<<<grid, kSegThreads, 0, st>>>(ranges, region + kBucketMinC, region + kBucketMax, n_tiles, hdr,
-                                               max_pairs, keys0, keys1, lists, vals);
+                           uint32_t* vals, int grid, int ballot_ranks, hipStream_t st) {
+  if (ballot_ranks)
+    seg_sort_kernel<true><<<grid, kSegThreads, 0, st>>>(ranges, region + kBucketMinC, region + kBucketMax, n_tiles,
+                                                        hdr, max_pairs, keys0, keys1, lists, vals);
+  else
+    seg_sort_kernel<false><<<grid, kSegThreads, 0, st>>>(ranges, region + kBucketMinC, region + kBucketMax, n_tiles,
+                                                         hdr, max_pairs, keys0, keys1, lists, vals);
   return hipGetLastError();
 }
 

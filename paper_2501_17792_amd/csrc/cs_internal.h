@@ -100,12 +100,14 @@ struct FrameHdr {
   uint32_t n_chunks;
   uint32_t n_pairs;        // pairs requested (may exceed capacity)
   uint32_t n_visible;
-  uint32_t overflow;       // bit 0 splats, bit 1 pairs, bit 2 instances, bit 3 chunks, bit 4 bad tid
+  uint32_t overflow;       // bit 0 splats, bit 1 pairs, bit 2 instances, bit 3 chunks, bit 4 bad tid,
+                           // bit 5 segment lists, bit 6 a sorted segment failed its order check
   uint32_t epoch;          // incremented per frame; tags look-back entries
   uint32_t frame;
   uint32_t ticket[8];      // onesweep partition tickets per pass
   uint32_t level_hist[kMaxLevels];
-  uint32_t pad[8];
+  uint32_t pad[7];
+  uint32_t sort_fallbacks; // LDS-sorted segments re-sorted with ballot ranks this frame
 };
 
 struct Chunk {
@@ -298,7 +300,7 @@ hipError_t launch_seg_split(const uint32_t* ranges, const uint32_t* region, int 
                             int grid, hipStream_t st);
 hipError_t launch_seg_sort(const uint32_t* ranges, const uint32_t* region, int n_tiles, FrameHdr* hdr,
                            uint32_t max_pairs, const uint64_t* keys0, const uint64_t* keys1, SegLists lists,
-                           uint32_t* vals, int grid, hipStream_t st);
+                           uint32_t* vals, int grid, int ballot_ranks, hipStream_t st);
 hipError_t launch_bucket_keys(const uint32_t* ranges, const uint32_t* vals, const float4* rec, int n_tiles,
                               uint64_t* keys, hipStream_t st);
 

@@ -360,6 +360,7 @@ cs_status cs_create(int32_t device, void* stream, const cs_options* opt, cs_ctx*
   if (o.max_splats < 0 || o.max_pairs < 0) return CS_ERR_INVALID;
   if (o.sort_algo != CS_SORT_TILE_BUCKET && o.sort_algo != CS_SORT_REDUCE_SCAN && o.sort_algo != CS_SORT_ONESWEEP)
     return CS_ERR_INVALID;
+  if (o.sort_ranks != CS_SORT_RANKS_CHECKED && o.sort_ranks != CS_SORT_RANKS_BALLOT) return CS_ERR_INVALID;
   int n_dev = 0;
   if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev) {
     (void)hipGetLastError();
@@ -736,7 +737,7 @@ static cs_status bucket_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles) {
                            kSegGrid, ctx->stream));
   ctx->mark(CS_STAGE_SEGSORT, 0);
   HIP_TRY(launch_seg_sort(ctx->ranges, region, n_tiles, ctx->hdr, cap_p, ctx->keys[0], ctx->keys[1], lists,
-                          ctx->vals[0], kSegGrid, ctx->stream));
+                          ctx->vals[0], kSegGrid, ctx->opt.sort_ranks == CS_SORT_RANKS_BALLOT, ctx->stream));
   ctx->mark(CS_STAGE_SEGSORT, 1);
   ctx->mark(CS_STAGE_SORT, 1);
   ctx->sorted = 0;
@@ -810,6 +811,7 @@ static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs
     stats->overflow = (int32_t)h.overflow;
     stats->n_instances = (int32_t)h.n_inst;
     for (int l = 0; l < CS_MAX_LEVELS; ++l) stats->level_hist[l] = (int32_t)h.level_hist[l];
+    stats->sort_fallbacks = (int32_t)h.sort_fallbacks;
     if (h.overflow) return ctx->fail(CS_ERR_CAPACITY, "frame exceeded a capacity (see stats)");
   }
   return CS_OK;
@@ -1119,6 +1121,7 @@ cs_status cs_frame_poll(cs_ctx* ctx, cs_frame_stats* stats) {
     stats->overflow = (int32_t)h.overflow;
     stats->n_instances = (int32_t)h.n_inst;
     for (int l = 0; l < CS_MAX_LEVELS; ++l) stats->level_hist[l] = (int32_t)h.level_hist[l];
+    stats->sort_fallbacks = (int32_t)h.sort_fallbacks;
   }
   return h.overflow ? ctx->fail(CS_ERR_CAPACITY, "a captured frame exceeded its capacity") : CS_OK;
 }

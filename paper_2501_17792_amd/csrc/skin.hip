@@ -93,6 +93,7 @@ __global__ void frame_reset_kernel(FrameHdr* hdr, uint32_t* hist, int hist_len, 
     hdr->n_visible = 0;
     hdr->epoch += 1;
     hdr->frame += 1;
+    hdr->sort_fallbacks = 0;
     for (int p = 0; p < 8; ++p) hdr->ticket[p] = 0;
   }
   for (int i = t; i < hist_len; i += gridDim.x * blockDim.x) hist[i] = 0;

@@ -28,6 +28,9 @@ def gpu_frame_buffers(r, n_inst):
     out["bones"] = r.debug("BONES", np.float32, n_inst * 24 * 12).reshape(n_inst, 24, 3, 4)
     out["level"] = r.debug("LEVEL", np.int32, n_inst)
     out["offset"] = r.debug("OFFSET", np.uint32, n_inst + 1)
+    cam = r.last_camera
+    n_tiles = -(-cam.width // r.tile[0]) * -(-cam.height // r.tile[1])
+    out["ranges"] = r.debug("RANGES", np.uint32, 2 * n_tiles).reshape(n_tiles, 2)
     if n_s:
         out["rec"] = r.debug("RECORD", np.float32, n_s * 12).reshape(n_s, 12)
         out["rect"] = r.debug("RECT", np.uint32, n_s)

@@ -19,19 +19,22 @@ from .gpu_common import check_sorted_pairs, gpu_frame_buffers
 pytestmark = pytest.mark.gpu
 
 
-def _render(scene, algo, tile=(16, 16), mode=None, thresholds=()):
+def _render(scene, algo, tile=(16, 16), mode=None, thresholds=(), ranks=0):
     import torch
 
     from paper_2501_17792_amd import crowdsplat as cs
 
     mode = cs.CS_LOD_FULL if mode is None else mode
-    r = cs.Renderer(0, tile=tile, sort_algo=algo)
+    r = cs.Renderer(0, tile=tile, sort_algo=algo, sort_ranks=ranks)
     r.upload_templates(scene.templates)
     r.set_crowd(scene.crowd)
     img = r.frame(scene.camera, mode, thresholds, stats=True)
     torch.cuda.synchronize()
     st = r.last_stats
     assert st.overflow == 0
+    # no LDS-sorted segment failed its order check (a failure would have been
+    # re-sorted with ballot ranks and counted here)
+    assert st.sort_fallbacks == 0
     cam = scene.camera
     n_tiles = -(-cam.width // tile[0]) * -(-cam.height // tile[1])
     ranges = r.debug("RANGES", np.uint32, 2 * n_tiles).reshape(n_tiles, 2)
@@ -47,6 +50,12 @@ def _same_as_radix(scene, tile=(16, 16), **kw):
     assert np.array_equal(rg_b, rg_r)
     assert np.array_equal(sv_b, sv_r)
     assert np.array_equal(img_b, img_r)
+    # the LDS sort with ballot ranks in every pass (documented behaviour only)
+    # gives the same order as its checked LDS-atomic ranks
+    _, img_q, rg_q, sv_q = _render(scene, cs.CS_SORT_TILE_BUCKET, tile, ranks=cs.CS_SORT_RANKS_BALLOT, **kw)
+    assert np.array_equal(rg_q, rg_b)
+    assert np.array_equal(sv_q, sv_b)
+    assert np.array_equal(img_q, img_b)
     g = gpu_frame_buffers(rb, scene.crowd.n)
     check_sorted_pairs(g, g["n_splats"])
     return rg_b

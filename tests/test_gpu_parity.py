@@ -5,17 +5,29 @@ Tolerances (FP32 kernel vs FP64 oracle on the same FP32 inputs):
   entry magnitude (a few FP32 ulps through the 24-joint chain);
 * screen position u, v: 2e-3 px; conic, 2D covariance, depth: relative 1e-4;
   colour: 1e-4 absolute;
-* tile rects and visibility: equal except where the oracle's footprint bound
-  lies within 2e-3 px of a pixel edge (both decisions are then correct);
-* per-tile splat lists: the same set except those rect-fragile splats, in an
-  order consistent with the FP64 depths except among depths equal to 2e-6
-  relative;
-* pixels: max-abs 2e-3 outside the fragile mask (pixels where some evaluated
-  splat has alpha within 1e-3 relative of 1/255, or T' within 1e-3 relative of
-  1e-4, or two consecutive contributors have depths equal within their FP32
-  error and swapping them moves the pixel by more than 1e-3: an FP32 decision
-  may flip there); flagged pixels are counted; where only thresholds flip the
-  error is bounded by 2 * 1.25/255 + 2e-3, a depth swap by T a1 a2 |c1 - c2|.
+* tile rects and visibility against the FP64 footprint: equal except where
+  the oracle's bound lies within 2e-3 px of a pixel edge (both decisions are
+  then correct);
+* keys, rects, per-tile lists and ranges: bit-exact against the integer key
+  oracle, which takes the device's own float32 records (u, v, rx, ry, depth)
+  and decides in float32 like the kernel (the order of the frame path's
+  sorted splat indices and its tile ranges, not rebuilt keys);
+* per-tile splat sets against the FP64 oracle's own lists: equal except the
+  rect-fragile splats; order consistent with the FP64 depths except among
+  depths equal to 2e-6 relative;
+* pixels, two ways, both over the device's per-tile lists (membership and
+  order are integer decisions the kernel takes in float32, pinned bit-exactly
+  above):
+  - end to end: the FP64 oracle's records composited in FP64: max-abs 2e-3
+    outside the pixels where an evaluated splat has alpha within 1e-3
+    (relative) of 1/255 or T' within 1e-3 of 1e-4 (the FP32 records differ
+    from FP64 by up to ~1e-4 relative, which moves alpha by up to ~6e-4);
+  - compositing alone: the device's own records, upcast, composited in FP64,
+    with the 1e-4 bands: max-abs 2e-3 outside them;
+  in both, flagged pixels are at most 1e-3 of the image and each differs by
+  at most cmax (2/255 + 1.01e-2) + 2e-3 (one skip flip moves a pixel by at
+  most 2 cmax / 255, one stop flip by at most cmax T <= cmax 1e-2 plus the
+  1e-4 left after it).
 """
 import numpy as np
 import pytest
@@ -30,8 +42,59 @@ from .gpu_common import (check_sorted_pairs, gpu_frame_buffers, rect_fragile, ru
 
 pytestmark = pytest.mark.gpu
 
-FRAG = 1e-3
-FLAG_BOUND = 2 * 1.25 / 255 + 2e-3
+BAND_E2E = 1e-3
+BAND_COMPOSITE = 1e-4
+FRAGILE_MAX = 1e-3
+
+
+def flag_bound(rgb):
+    cmax = float(np.max(rgb)) if np.size(rgb) else 1.0
+    return cmax * (2.0 / 255.0 + 1.01e-2) + 2e-3
+
+
+def device_records(R):
+    """The device's float32 records as the oracle's record dict (FP64)."""
+    R = R.astype(np.float64)
+    return dict(u=R[:, 0], v=R[:, 1], A=R[:, 4], B=R[:, 5], C=R[:, 6], opacity=R[:, 7],
+                rgb=R[:, 8:11], depth=R[:, 11])
+
+
+def integer_key_oracle(R, cam, tw, th):
+    """Rects, counts, sorted splat indices and ranges from the device's own
+    float32 records (u, v, rx, ry, depth), decided in float32."""
+    ntx, nty = -(-cam.width // tw), -(-cam.height // th)
+    rect, cnt, vis = osplat.footprint_rect_f32(R[:, 0], R[:, 1], R[:, 2], R[:, 3], R[:, 11], cam.width,
+                                               cam.height, tw, th)
+    keys, vals = osplat.emit_pairs(rect, cnt, vis, R[:, 11].astype(np.float64), ntx)
+    sk, sv = osplat.sort_pairs(keys, vals)
+    return rect, cnt, vis, sk, sv, osplat.tile_ranges(sk, ntx * nty)
+
+
+def check_pixels(img, sp, svals, ranges, cam, tw, th, band, tiles=None, label=""):
+    """FP64 compositing of records ``sp`` over the device's lists against the
+    device image (on ``tiles`` or all). Returns (max-abs outside the mask,
+    flagged pixels, pixels compared)."""
+    ref, _, frag = osplat.composite_tiled(sp, svals.astype(np.int64), ranges.astype(np.int64), cam.width,
+                                          cam.height, tw, th, cam.bg, band, band, tiles=tiles,
+                                          chunked=True)
+    if tiles is None:
+        sel = np.ones((cam.height, cam.width), bool)
+    else:
+        sel = np.zeros((cam.height, cam.width), bool)
+        ntx = -(-cam.width // tw)
+        for t in tiles:
+            ty, tx = divmod(int(t), ntx)
+            sel[ty * th:(ty + 1) * th, tx * tw:(tx + 1) * tw] = True
+    diff = np.abs(img - ref).max(axis=0)
+    clean = sel & ~frag
+    worst = float(diff[clean].max()) if clean.any() else 0.0
+    assert worst <= 2e-3, f"{label}: max-abs {worst} outside the fragile mask"
+    nf = int((frag & sel).sum())
+    assert nf <= FRAGILE_MAX * sel.sum() + 1, f"{label}: {nf} of {int(sel.sum())} pixels fragile"
+    if nf:
+        bound = flag_bound(sp["rgb"])
+        assert diff[frag & sel].max() <= bound, f"{label}: flagged pixel off by {diff[frag & sel].max()}"
+    return worst, nf, int(sel.sum())
 
 
 def _small_c2_scene(n_inst=12, n_gauss=20000, width=480, height=270):
@@ -50,6 +113,8 @@ def _compare_frame(scene, mode, thresholds, tile=(16, 16), **kw):
     n_inst = scene.crowd.n
     g = gpu_frame_buffers(r, n_inst)
     cam = scene.camera
+    tw, th = tile
+    ntx, nty = -(-cam.width // tw), -(-cam.height // th)
     # ---- LoD levels: same decision unless the distance sits on a threshold
     if mode == cs.CS_LOD_FULL:
         levels = np.zeros(n_inst, np.int64)
@@ -59,9 +124,7 @@ def _compare_frame(scene, mode, thresholds, tile=(16, 16), **kw):
         near = np.min(np.abs(dist[:, None] - np.asarray(thresholds)[None]), axis=1) < 1e-4
         assert np.all((g["level"] == levels) | near)
         levels = g["level"].astype(np.int64)  # decided identically within FP32 ties
-    out = oframe.render_frame(scene.templates, scene.crowd, cam, levels, tile[0], tile[1],
-                              fragile_alpha=FRAG, fragile_t=FRAG, tie_impact=1e-3)
-    rec = out["records"]
+    rec = oframe.frame_records(scene.templates, scene.crowd, cam, levels, tw, th)
     # ---- forward kinematics
     for i in range(n_inst):
         t = scene.templates[int(scene.crowd.tid[i])]
@@ -84,8 +147,8 @@ def _compare_frame(scene, mode, thresholds, tile=(16, 16), **kw):
         ocov = rec["cov"][:, [0, 0, 0, 1, 1, 2], [0, 1, 2, 1, 2, 2]]
         cscale = np.abs(ocov).max(axis=1, keepdims=True)
         assert np.all(np.abs(gcov - ocov) <= 2e-5 * cscale + 1e-12)
-    # ---- projection records
-    frag_rect = rect_fragile(rec, tile[0], tile[1], cam.width, cam.height)
+    # ---- projection records against FP64
+    frag_rect = rect_fragile(rec, tw, th, cam.width, cam.height)
     gvis = g["count"] > 0
     ovis = rec["visible"]
     assert np.all((gvis == ovis) | frag_rect), np.nonzero((gvis != ovis) & ~frag_rect)[0][:10]
@@ -106,42 +169,40 @@ def _compare_frame(scene, mode, thresholds, tile=(16, 16), **kw):
     grect = unpack_rect(g["rect"][both])
     ok = np.all(grect == rec["rect"][both], axis=1) | frag_rect[both]
     assert ok.all(), np.nonzero(~ok)[0][:10]
-    # ---- binning and sort
+    # ---- O6: the integer key oracle on the device's own float32 records
+    irect, icnt, ivis, isk, isv, irg = integer_key_oracle(g["rec"], cam, tw, th)
+    np.testing.assert_array_equal(icnt, g["count"].astype(np.int64))
+    np.testing.assert_array_equal(irect[ivis], unpack_rect(g["rect"][ivis]))
+    assert int(icnt.sum()) == g["n_pairs"]
+    np.testing.assert_array_equal(irg, g["ranges"].astype(np.int64))
     if g["n_pairs"]:
+        np.testing.assert_array_equal(isv, g["svals"])
         check_sorted_pairs(g, n)
-        ntx = (cam.width + tile[0] - 1) // tile[0]
-        nty = (cam.height + tile[1] - 1) // tile[1]
-        gt = (g["skeys"] >> np.uint64(31)).astype(np.int64)
-        ot = (out["sorted_keys"] >> np.uint64(31)).astype(np.int64)
-        ov = out["sorted_vals"].astype(np.int64)
-        gv = g["svals"].astype(np.int64)
-        gs, os_ = np.searchsorted(gt, np.arange(ntx * nty + 1)), np.searchsorted(ot, np.arange(ntx * nty + 1))
-        depth = rec["depth"]
+        # ---- per-tile sets against the FP64 oracle's own lists
+        okeys, ovals = osplat.emit_pairs(rec["rect"], rec["count"], rec["visible"], rec["depth"], ntx)
+        osk, osv = osplat.sort_pairs(okeys, ovals)
+        org = osplat.tile_ranges(osk, ntx * nty)
+        gv, ov = g["svals"].astype(np.int64), osv.astype(np.int64)
+        fr = set(np.nonzero(frag_rect)[0].tolist())
         for tt in range(ntx * nty):
-            a = gv[gs[tt]:gs[tt + 1]]
-            b = ov[os_[tt]:os_[tt + 1]]
-            sa = set(a.tolist()) - set(np.nonzero(frag_rect)[0].tolist())
-            sb = set(b.tolist()) - set(np.nonzero(frag_rect)[0].tolist())
-            assert sa == sb, f"tile {tt}"
-            # order consistent with FP64 depth except near ties
-            d = depth[a]
-            bad = d[1:] < d[:-1] * (1 - 2e-6)
-            assert not bad.any(), f"tile {tt} depth order"
-    # ---- pixels
-    diff = np.abs(img - out["image"]).max(axis=0)
-    frag = out["fragile"]
-    clean = ~frag
-    worst = diff[clean].max() if clean.any() else 0.0
-    assert worst <= 2e-3, f"max-abs {worst} outside the fragile mask"
-    assert frag.mean() < 0.03, f"{frag.mean():.3%} of pixels fragile"
-    return r, img, out, g, dict(max_abs=float(worst), fragile=int(frag.sum()), pixels=int(frag.size))
+            a = gv[g["ranges"][tt, 0]:g["ranges"][tt, 1]]
+            b = ov[org[tt, 0]:org[tt, 1]]
+            assert set(a.tolist()) - fr == set(b.tolist()) - fr, f"tile {tt}"
+            d = rec["depth"][a]  # order consistent with FP64 depth except near ties
+            assert not (d[1:] < d[:-1] * (1 - 2e-6)).any(), f"tile {tt} depth order"
+    # ---- pixels over the device's lists: end to end, then compositing alone
+    e2e = check_pixels(img, rec, g["svals"], g["ranges"], cam, tw, th, BAND_E2E, label="end to end")
+    comp = check_pixels(img, device_records(g["rec"]), g["svals"], g["ranges"], cam, tw, th, BAND_COMPOSITE,
+                        label="compositing")
+    return r, img, rec, g, dict(e2e_max_abs=e2e[0], e2e_fragile=e2e[1], composite_max_abs=comp[0],
+                                composite_fragile=comp[1], pixels=e2e[2])
 
 
 def test_c1_plain_full_detail():
     from paper_2501_17792_amd import crowdsplat as cs
 
     sc = synth.scene_c1()
-    _, img, out, g, info = _compare_frame(sc, cs.CS_LOD_FULL, ())
+    _, img, rec, g, info = _compare_frame(sc, cs.CS_LOD_FULL, ())
     assert g["n_pairs"] > 1000
     print("C1", info)
 
@@ -150,7 +211,7 @@ def test_c2_slice_fixed_lod():
     from paper_2501_17792_amd import crowdsplat as cs
 
     sc = _small_c2_scene()
-    _, img, out, g, info = _compare_frame(sc, cs.CS_LOD_FIXED, sc.lod_thresholds)
+    _, img, rec, g, info = _compare_frame(sc, cs.CS_LOD_FIXED, sc.lod_thresholds)
     assert len(set(g["level"].tolist())) >= 2  # several levels in play
     print("C2 slice", info)
 

@@ -118,3 +118,32 @@ def test_psnr_labels_known_mse():
     b[:, 1:3, 1:3] = 0.1  # MSE over the 4x4 window = 0.01 * 4/16
     lab = lod.psnr_labels([a, b, a], (0, 0, 4, 4))
     np.testing.assert_allclose(lab, [60.0, -10 * math.log10(0.0025), 60.0])
+
+
+def _one_joint_template(means, log_scales):
+    """A template whose 24 joints all sit at the origin except joint 1 at
+    (0, 2, 0), holding the given Gaussians."""
+    n = len(means)
+    J = np.zeros((24, 3), np.float32)
+    J[1] = (0.0, 2.0, 0.0)
+    return synth.Template(
+        mean=np.asarray(means, np.float32), log_scale=np.asarray(log_scales, np.float32),
+        quat=np.tile(np.array([1, 0, 0, 0], np.float32), (n, 1)), opacity=np.full(n, 0.5, np.float32),
+        sh=np.zeros((n, 1, 3), np.float32), skin_idx=np.zeros((n, 4), np.uint8),
+        skin_w=np.tile(np.array([1, 0, 0, 0], np.float32), (n, 1)), joints_rest=J,
+        parents=np.array([-1] + [0] * 23, np.int32), sh_degree=0, level_count=np.array([n], np.int32))
+
+
+def test_pad_radius_closed_form():
+    """One Gaussian: its distance to the nearest joint plus 3 times its largest
+    standard deviation. Three Gaussians: the largest of their three such sums,
+    which here is neither that of the Gaussian farthest from a joint nor that
+    of the widest one."""
+    t = _one_joint_template([[3.0, 4.0, 0.0]], [[-2.0, -1.0, -3.0]])
+    # nearest joint: (0, 2, 0) at sqrt(9 + 4) (the origin is 5 away)
+    assert math.isclose(lod.pad_radius(t), math.sqrt(13.0) + 3.0 * math.exp(-1.0), rel_tol=1e-12)
+    t = _one_joint_template([[0.0, 2.5, 0.0], [2.0, 0.0, 0.0], [0.0, 0.0, 1.5]],
+                            [[0.0, -4.0, -4.0], [-4.0, -4.0, -4.0], [-0.375, -1.5, -3.0]])
+    ref = 1.5 + 3.0 * math.exp(-0.375)  # the third: neither the farthest (2.0) nor the widest (e^0)
+    assert ref > max(0.5 + 3.0 * math.exp(0.0), 2.0 + 3.0 * math.exp(-4.0))
+    assert math.isclose(lod.pad_radius(t), ref, rel_tol=1e-12)

@@ -128,3 +128,50 @@ def test_weights_summing_to_one_preserve_translation():
     mu_a, *_ = skinning.skin_instance(t, pose, 0.4, 0.0, 0.0)
     mu_b, *_ = skinning.skin_instance(t, pose, 0.4, shift[0], shift[2])
     np.testing.assert_allclose(mu_b - mu_a, np.broadcast_to(shift, mu_a.shape), atol=1e-12)
+
+
+def test_two_different_bones_mixed_weights_with_permuted_slots():
+    """Two bones with different rigid transforms (rotations from scipy) and
+    mixed weights w, 1 - w stored in permuted slots (the other two slots hold
+    zero weight on further bones): the posed mean is the weighted sum of the
+    two rigidly moved means, and the posed covariance is the covariance of the
+    Gaussian pushed through the blended affine map, checked by the change of
+    variables of scipy's normal density (no covariance formula retyped)."""
+    from scipy.stats import multivariate_normal
+
+    rng = np.random.default_rng(21)
+    n = 48
+    Ra = Rotation.from_rotvec(rng.normal(0, 0.8, (n, 3))).as_matrix()
+    Rb = Rotation.from_rotvec(rng.normal(0, 0.8, (n, 3))).as_matrix()
+    ta, tb = rng.normal(0, 1.0, (n, 3)), rng.normal(0, 1.0, (n, 3))
+    w = rng.uniform(0.05, 0.95, n)
+    mean = rng.normal(0, 0.5, (n, 3))
+    log_scale = rng.normal(-1.5, 0.3, (n, 3))
+    quat = rng.normal(0, 1, (n, 4))
+    for i in range(n):
+        B = np.zeros((24, 3, 4))
+        for j in range(24):  # decoy bones on the zero-weight slots
+            B[j, :, :3] = Rotation.from_rotvec(rng.normal(0, 1, 3)).as_matrix()
+            B[j, :, 3] = rng.normal(0, 3, 3)
+        a, b, c, d = rng.choice(24, size=4, replace=False)
+        B[a, :, :3], B[a, :, 3] = Ra[i], ta[i]
+        B[b, :, :3], B[b, :, 3] = Rb[i], tb[i]
+        slots = rng.permutation(4)  # where bone a, bone b and the decoys sit
+        idx = np.empty(4, np.int64)
+        wt = np.zeros(4)
+        idx[slots] = [a, b, c, d]
+        wt[slots[0]], wt[slots[1]] = w[i], 1.0 - w[i]
+        cov0 = skinning.canonical_covariance(log_scale[i:i + 1], quat[i:i + 1])
+        mu, cov, L = skinning.lbs(B, mean[i:i + 1], cov0, idx[None], wt[None])
+        ref_mu = w[i] * (Ra[i] @ mean[i] + ta[i]) + (1.0 - w[i]) * (Rb[i] @ mean[i] + tb[i])
+        np.testing.assert_allclose(mu[0], ref_mu, atol=1e-12)
+        # density of y = A x + t, x ~ N(mean, Sigma): p_x(A^-1 (y - t)) / |det A|
+        A = w[i] * Ra[i] + (1.0 - w[i]) * Rb[i]
+        t = w[i] * ta[i] + (1.0 - w[i]) * tb[i]
+        Rq = Rotation.from_quat(np.roll(quat[i], -1)).as_matrix()  # scipy takes (x, y, z, w)
+        sig = Rq @ np.diag(np.exp(2.0 * log_scale[i])) @ Rq.T
+        ys = ref_mu + rng.normal(0, 0.3, (5, 3))
+        xs = np.linalg.solve(A, (ys - t).T).T
+        ref_pdf = multivariate_normal(mean[i], sig).pdf(xs) / abs(np.linalg.det(A))
+        got_pdf = multivariate_normal(mu[0], cov[0]).pdf(ys)
+        np.testing.assert_allclose(got_pdf, ref_pdf, rtol=1e-9)

@@ -313,3 +313,60 @@ def test_fixed_levels_closed_form():
     dist = np.sqrt((pos[:, 1] + 3) ** 2 + 1.7 ** 2)
     np.testing.assert_array_equal(lv, np.where(dist < 10, 0, np.where(dist < 25, 1, 2)))
     assert list(lv) == [0, 1, 1, 2]
+
+
+def test_chunked_walk_equals_the_loop_bit_for_bit():
+    """The chunked front-to-back walk (for lists of millions) gives the loop's
+    colour, transmittance, fragile flags and counts exactly, with stops, skips
+    and clamps inside and across chunk borders."""
+    rng = np.random.default_rng(12)
+    n = 700
+    rec = dict(u=rng.uniform(0, 16, n), v=rng.uniform(0, 16, n), A=rng.uniform(0.02, 0.6, n),
+               B=rng.uniform(-0.05, 0.05, n), C=rng.uniform(0.02, 0.6, n),
+               opacity=np.where(rng.uniform(size=n) < 0.1, 1.0, rng.uniform(0.002, 0.9, n)),
+               rgb=rng.uniform(0, 1.3, (n, 3)))
+    gy, gx = np.mgrid[0:16, 0:16]
+    px, py = gx.ravel() * 1.0, gy.ravel() * 1.0
+    order = rng.permutation(n)
+    bg = np.array([0.2, 0.4, 0.6])
+    ref = splat._blend_list(px, py, order, rec, bg, 1e-3, 1e-3)
+    assert ref[3].min() < ref[3].max() and (ref[1] < 1e-2).any()  # stops and long walks both occur
+    for chunk in (1, 7, 64, 4096):
+        got = splat._blend_list_chunked(px, py, order, rec, bg, 1e-3, 1e-3, chunk=chunk)
+        for a, b in zip(ref, got):
+            assert np.array_equal(a, b), chunk
+
+
+def test_float32_footprint_rect():
+    """Where the pixel bounds are not near an integer, the float32 rect equals
+    the FP64 footprint's rect; a bound whose float32 subtraction rounds onto
+    an integer takes the float32 floor; boxes entirely off-screen are culled."""
+    rng = np.random.default_rng(13)
+    n = 4000
+    u, v = rng.uniform(-40, 300, n), rng.uniform(-40, 200, n)
+    a, c = rng.uniform(0.3, 400, n), rng.uniform(0.3, 400, n)
+    op = rng.uniform(0.01, 1.0, n)
+    fp = splat.footprint(u, v, a, c, op, np.ones(n, bool), 256, 160, 16, 16)
+    b = fp["bounds"]
+    far = np.all(np.abs(b - np.round(b)) > 1e-3, axis=1)
+    rect, cnt, vis = splat.footprint_rect_f32(u.astype(np.float32), v.astype(np.float32),
+                                              fp["rx"].astype(np.float32), fp["ry"].astype(np.float32),
+                                              np.ones(n), 256, 160, 16, 16)
+    assert np.array_equal(vis[far], fp["visible"][far])
+    ok = far & vis
+    assert np.array_equal(rect[ok], fp["rect"][ok]) and np.array_equal(cnt[ok], fp["count"][ok])
+    assert ok.sum() > 1000 and (~vis).sum() > 100
+    # 2^24 - 0.5 is a tie between two float32 values and rounds to even (2^24)
+    u32 = np.array([2.0 ** 24], np.float32)
+    r, _, _ = splat.footprint_rect_f32(u32, np.array([1.0], np.float32), np.array([0.5], np.float32),
+                                       np.array([0.5], np.float32), np.ones(1), 2 ** 26, 8, 1, 1)
+    assert r[0, 0] == 2 ** 24  # the FP64 floor would be 2^24 - 1
+    # culled or zero-depth splats get no tiles
+    r, cnt, vis = splat.footprint_rect_f32(np.array([-5.0, 40.0], np.float32), np.array([40.0, 40.0], np.float32),
+                                           np.array([2.0, 10.0], np.float32), np.array([2.0, 10.0], np.float32),
+                                           np.array([1.0, 0.0]), 256, 160, 16, 16)
+    assert list(cnt) == [0, 0] and not vis.any()
+    r, cnt, vis = splat.footprint_rect_f32(np.array([40.0], np.float32), np.array([40.0], np.float32),
+                                           np.array([10.0], np.float32), np.array([10.0], np.float32),
+                                           np.array([1.0]), 256, 160, 16, 16)
+    assert list(r[0]) == [1, 1, 3, 3] and cnt[0] == 9  # pixels 30..50 -> tiles 1..3
