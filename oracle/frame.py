@@ -35,16 +35,19 @@ def instance_counts(templates, tid, levels) -> np.ndarray:
                      for t, l in zip(tid, levels)], np.int64)
 
 
-def skin_crowd(templates, crowd, levels):
+def skin_crowd(templates, crowd, levels, mean_fn=None):
     """Posed means / covariances / linear parts of every selected Gaussian,
-    instance-major. Returns (mu, cov, L, opacity, sh(list), template ids)."""
+    instance-major. Returns (mu, cov, L, opacity, sh(list), template ids).
+    ``mean_fn(i, n)`` gives instance i's canonical means of its first n
+    Gaussians when they depend on the instance (pose-dependent offsets)."""
     mus, covs, Ls, ops, shs = [], [], [], [], []
     counts = instance_counts(templates, crowd.tid, levels)
     for i in range(crowd.n):
         t = templates[int(crowd.tid[i])]
         n = int(counts[i])
+        mean = mean_fn(i, n) if mean_fn is not None else None
         mu, cov, L, _ = skinning.skin_instance(t, crowd.pose[i], crowd.yaw[i],
-                                               crowd.pos[i, 0], crowd.pos[i, 1], n)
+                                               crowd.pos[i, 0], crowd.pos[i, 1], n, mean=mean)
         mus.append(mu)
         covs.append(cov)
         Ls.append(L)
@@ -53,9 +56,9 @@ def skin_crowd(templates, crowd, levels):
     return mus, covs, Ls, ops, shs, counts
 
 
-def frame_records(templates, crowd, cam, levels, tw, th):
+def frame_records(templates, crowd, cam, levels, tw, th, mean_fn=None):
     """Splat records of a whole frame in emission order."""
-    mus, covs, Ls, ops, shs, counts = skin_crowd(templates, crowd, levels)
+    mus, covs, Ls, ops, shs, counts = skin_crowd(templates, crowd, levels, mean_fn)
     parts = []
     for i in range(crowd.n):
         deg = templates[int(crowd.tid[i])].sh_degree

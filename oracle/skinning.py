@@ -130,11 +130,13 @@ def lbs(B, mean, cov, skin_idx, skin_w):
     return mu, cov_p, L
 
 
-def skin_instance(template, pose, yaw, px, pz, n: int | None = None):
-    """Skin the first ``n`` Gaussians of ``template`` for one instance."""
+def skin_instance(template, pose, yaw, px, pz, n: int | None = None, mean=None):
+    """Skin the first ``n`` Gaussians of ``template`` for one instance;
+    ``mean`` [n, 3] replaces the canonical means (pose-dependent offsets
+    added before skinning)."""
     n = template.n if n is None else n
     B = bone_matrices(pose, template.joints_rest, template.parents, yaw, px, pz)
     cov = canonical_covariance(template.log_scale[:n], template.quat[:n])
-    mu, cov_p, L = lbs(B, template.mean[:n], cov, template.skin_idx[:n],
-                       template.skin_w[:n])
+    m = template.mean[:n] if mean is None else mean
+    mu, cov_p, L = lbs(B, m, cov, template.skin_idx[:n], template.skin_w[:n])
     return mu, cov_p, L, B
