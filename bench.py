@@ -206,6 +206,213 @@ def time_mode(torch, rs, scene, poses_all, imgs, streams, lod, steps, warmup):
     return dict(ms=total / steps, per=per, stats=st0, frame0=frame0, overflow=overflow)
 
 
+# The paper's Tab. 2 (FPS, RTX 4090, 1280x720) and Tab. 1 (MiB unshared, shared): context, not targets.
+PAPER_TAB2_FPS = {(202_738, False): {1: 728, 100: 50, 400: 22.2}, (202_738, True): {1: 617, 100: 18.2},
+                  (12_661, False): {1: 1612, 100: 586, 400: 251, 1000: 125, 5000: 10.3},
+                  (12_661, True): {1: 1370, 100: 312, 400: 76, 1000: 34, 5000: 6.1},
+                  (3_176, False): {1: 1703, 100: 1240, 400: 673, 1000: 275, 5000: 38.6},
+                  (3_176, True): {1: 1347, 100: 804, 400: 298, 1000: 121, 5000: 23.2}}
+PAPER_TAB1_MIB = {202_738: {1: (651, 651), 100: (7929, 7075)},
+                  12_661: {1: (567, 567), 100: (1005, 953), 400: (2335, 2121), 1000: (5127, 4593),
+                           5000: (21340, 19625)},
+                  3_176: {1: (557, 557), 100: (675, 639), 400: (993, 937), 1000: (1695, 1541),
+                          5000: (5995, 5329)}}
+
+
+def time_captured(torch, scene, animated, steps, warmup, tile=(16, 16), lod=None):
+    """Frames of one crowd as captured graphs on their own stream, one frame
+    in flight. Animated: the whole frame (pose upload from a device pose ring,
+    LoD, FK, skinning fused into projection, binning, sort, blend) per replay.
+    Static: skinned once, rendering alone per replay. Returns (ms per frame
+    list, frame stats, image of the first replay)."""
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    mode, thr = lod if lod is not None else (cs.CS_LOD_FULL, ())
+    stream = torch.cuda.Stream()
+    dev = torch.device("cuda", 0)
+    with torch.cuda.stream(stream):
+        r = cs.Renderer(0, stream=stream, fuse=animated, tile=tile)
+        r.upload_templates(scene.templates)
+        r.set_crowd(scene.crowd)
+        img = torch.zeros((3, scene.camera.height, scene.camera.width), device=dev)
+        ring = torch.from_numpy(scene.frame_poses).to(dev) if animated else None
+        max_s = max_p = 0
+        for f in ((0, ring.shape[0] // 3, 2 * ring.shape[0] // 3) if animated else (0,)):
+            if animated:
+                r.pose_dev.copy_(ring[f])
+            r.frame(scene.camera, mode, thr, image=img, stats=True)
+            max_s, max_p = max(max_s, int(r.last_stats.n_splats)), max(max_p, int(r.last_stats.n_pairs))
+        r.reserve(scene.crowd.n, int(max_s * 1.02) + 4096, int(max_p * 1.3) + 65536)
+        if animated:
+            r.set_pose_ring(ring)
+            r.capture(scene.camera, img, mode, thr)
+        else:
+            r.frame(scene.camera, mode, thr, image=img, stats=True)  # skinned once, after the reserve
+            r.capture_render(scene.camera, img)
+        st = r.last_stats
+        for _ in range(warmup):
+            r.launch()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        evs[0].record(stream)
+        for k in range(steps):
+            r.launch()
+            evs[k + 1].record(stream)
+        stream.synchronize()
+        ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(steps)]
+        overflow = int(r.poll().overflow)
+        r.close()
+    return ms, st, overflow
+
+
+def stage_frame(torch, scene, animated, tile=(16, 16), frames=3, lod=None):
+    """Per-stage times of eager frames of the crowd (HIP events on the launch
+    stream), the timed configuration's kernels."""
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    mode, thr = lod if lod is not None else (cs.CS_LOD_FULL, ())
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        r = cs.Renderer(0, stream=stream, fuse=animated, profile=True, tile=tile)
+        r.upload_templates(scene.templates)
+        r.set_crowd(scene.crowd)
+        img = torch.zeros((3, scene.camera.height, scene.camera.width), device="cuda")
+        acc = {}
+        if not animated:
+            r.frame(scene.camera, mode, thr, image=img, stats=True)
+        for k in range(frames + 1):
+            if animated:
+                r.frame(scene.camera, mode, thr, image=img, stats=True)
+            else:
+                r.render(scene.camera, img, stats=True)
+            if k:
+                for name, v in r.stage_times().items():
+                    acc.setdefault(name, []).append(v)
+        stream.synchronize()
+        st = r.last_stats
+        r.close()
+    out = {k: float(np.median(v)) for k, v in acc.items()}
+    if animated and "project" in out:
+        out["project_fused"] = out.pop("project")
+    return out, st
+
+
+def dominant_roofline(stage_ms, st, scene, uniq):
+    kernels = {"project_fused": "project_kernel (skinning fused)", "project": "project_kernel",
+               "segsort": "seg_sort_kernel"}
+    cand = {k: stage_ms[k] for k in kernels if stage_ms.get(k, 0.0) > 0}
+    if not cand:
+        return None
+    dom = max(cand, key=cand.get)
+    stats = dict(n_splats=int(st.n_splats), n_pairs=int(st.n_pairs))
+    b = algorithmic_bytes(dom, stats, scene, uniq)
+    a = b / (stage_ms[dom] * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kernels[dom], "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(a / HBM_PEAK_GBS, 4), "launch_ms": round(stage_ms[dom], 4), "bytes_per_launch": int(b)}
+
+
+def sweep_tab2(torch, steps, warmup, cells=None):
+    """Tab. 2-shaped sweep: duplicates of one SH3 template of 202,738 / 12,661
+    / 3,176 Gaussians, 1 to 5,000 characters on the grid, with and without
+    motion, 1280x720. One JSON line per cell."""
+    from paper_2501_17792_amd import synth
+
+    out = []
+    for n_gauss in synth.PAPER_SIZES:
+        tpl = synth.make_template(600 + synth.PAPER_SIZES.index(n_gauss), n_gauss, 3)
+        for animated in (False, True):
+            for n_chars in synth.TAB2_CELLS[(n_gauss, animated)]:
+                if cells and (n_gauss, n_chars, animated) not in cells:
+                    continue
+                sc = synth.scene_tab2(n_gauss, n_chars, animated, template=tpl)
+                ms, st, overflow = time_captured(torch, sc, animated, steps, warmup)
+                stage_ms, stp = stage_frame(torch, sc, animated)
+                med = float(np.median(ms))
+                fps = 1000.0 / med
+                rec = {"sweep": "tab2", "gaussians": n_gauss, "characters": n_chars, "motion": animated,
+                       "width": 1280, "height": 720, "fps": round(fps, 2), "frame_ms_median": round(med, 4),
+                       "frame_ms_p95": round(float(np.percentile(ms, 95)), 4),
+                       "gaussians_per_s": round(int(st.n_splats) * fps, 1), "n_splats": int(st.n_splats),
+                       "n_pairs": int(st.n_pairs), "overflow": overflow,
+                       "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+                       "roofline": dominant_roofline(stage_ms, stp, sc, n_gauss),
+                       "paper_fps_rtx4090": PAPER_TAB2_FPS[(n_gauss, animated)][n_chars]}
+                print(json.dumps(rec), flush=True)
+                out.append(rec)
+    return out
+
+
+def sweep_tab1(torch):
+    """Tab. 1-shaped memory accounting: device bytes of the context after one
+    animated 1280x720 frame, templates shared (the default) against one copy
+    per character, from the library's own accounting and from the device's
+    free-memory counter. One JSON line per cell."""
+    from paper_2501_17792_amd import crowdsplat as cs
+    from paper_2501_17792_amd import synth
+
+    out = []
+    mib = 1024.0 * 1024.0
+    for n_gauss, chars in synth.TAB1_CELLS.items():
+        tpl = synth.make_template(600 + synth.PAPER_SIZES.index(n_gauss), n_gauss, 3)
+        for n_chars in chars:
+            sc = synth.scene_tab2(n_gauss, n_chars, True, template=tpl, frames=1)
+            res = {}
+            for mode in ("shared", "unshared"):
+                torch.cuda.synchronize()
+                torch.cuda.empty_cache()
+                free0 = torch.cuda.mem_get_info()[0]
+                r = cs.Renderer(0, fuse=True)
+                r.upload_templates(sc.templates)
+                r.set_crowd(sc.crowd)
+                if mode == "unshared":
+                    r.materialise(True)
+                img = r.frame(sc.camera, cs.CS_LOD_FULL, (), stats=True)
+                torch.cuda.synchronize()
+                m = r.memory()
+                used = free0 - torch.cuda.mem_get_info()[0]
+                res[mode] = dict(m, device_used=int(used))
+                r.close()
+                del img
+            sh, un = res["shared"], res["unshared"]
+            rec = {"sweep": "tab1", "gaussians": n_gauss, "characters": n_chars,
+                   "shared_mib": round(sh["total"] / mib, 1), "unshared_mib": round(un["total"] / mib, 1),
+                   "saving_pct": round(100.0 * (1.0 - sh["total"] / un["total"]), 2),
+                   "shared_device_used_mib": round(sh["device_used"] / mib, 1),
+                   "unshared_device_used_mib": round(un["device_used"] / mib, 1),
+                   "shared": {k: sh[k] for k in ("templates", "per_instance", "per_splat", "per_pair", "workspace")},
+                   "copies_bytes_per_character": round(un["instance_copies"] / n_chars, 1),
+                   "n_splats": int(sc.crowd.n * n_gauss),
+                   "paper_mib_rtx4090": list(PAPER_TAB1_MIB[n_gauss][n_chars])}
+            print(json.dumps(rec), flush=True)
+            out.append(rec)
+    return out
+
+
+def paper_lod_leg(torch, steps, warmup, n_chars=3500, width=1920, height=1080):
+    """The paper's own LoD schedule (§2): 3,500 characters from 14 templates of
+    202,738 Gaussians with 12,661 / 3,176 prefixes chosen at 5 m and 10 m, on
+    the grid 3 m in front of the camera, 15 looping motions, captured frames."""
+    from paper_2501_17792_amd import crowdsplat as cs
+    from paper_2501_17792_amd import synth
+
+    t0 = time.perf_counter()
+    sc = synth.scene_paper_lod(n_chars, width=width, height=height)
+    log(f"paper LoD inputs in {time.perf_counter() - t0:.1f} s")
+    lod = (cs.CS_LOD_FIXED, sc.lod_thresholds)
+    ms, st, overflow = time_captured(torch, sc, True, steps, warmup, lod=lod)
+    stage_ms, stp = stage_frame(torch, sc, True, lod=lod)
+    med = float(np.median(ms))
+    uniq = len(sc.templates) * synth.PAPER_SIZES[0]
+    return {"workload": f"{n_chars} characters, 14 templates x 202,738 Gaussians SH3 with 12,661 / 3,176 "
+                        f"prefixes at 5 m / 10 m, grid 3 m in front of the camera, 15 looping clips, "
+                        f"{width}x{height}, captured frames, one in flight",
+            "fps": round(1000.0 / med, 2), "frame_ms_median": round(med, 4),
+            "frame_ms_p95": round(float(np.percentile(ms, 95)), 4),
+            "gaussians_per_s": round(int(st.n_splats) * 1000.0 / med, 1), "n_splats": int(st.n_splats),
+            "n_pairs": int(st.n_pairs), "level_hist": list(st.level_hist)[:3], "overflow": overflow,
+            "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+            "roofline": dominant_roofline(stage_ms, stp, sc, uniq), "paper_fps_rtx4090": 31}
+
+
 def psnr(a, b):
     mse = float(np.mean((a.astype(np.float64) - b.astype(np.float64)) ** 2))
     return float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)
@@ -223,6 +430,9 @@ def main():
     ap.add_argument("--net", default=os.path.join(ROOT, "paper_2501_17792_amd", "lod_net.npz"))
     ap.add_argument("--tile", default="auto", help="WxH or 'auto' (autotuned per run)")
     ap.add_argument("--modes", default="", help="comma list of LoD modes to time (default: all)")
+    ap.add_argument("--sweep", default="", choices=["", "tab2", "tab1", "paper_lod"],
+                    help="instead of the headline: the Tab. 2 FPS sweep, the Tab. 1 memory sweep, or the "
+                         "paper's LoD schedule (one JSON line per cell)")
     ap.add_argument("--inflight", type=int, default=3,
                     help="frames in flight: contexts (one stream each) that consecutive frames alternate between")
     args = ap.parse_args()
@@ -235,6 +445,16 @@ def main():
 
     from paper_2501_17792_amd import crowdsplat as cs
     from paper_2501_17792_amd import synth
+
+    if args.sweep == "tab2":
+        sweep_tab2(torch, args.steps, args.warmup)
+        return
+    if args.sweep == "tab1":
+        sweep_tab1(torch)
+        return
+    if args.sweep == "paper_lod":
+        print(json.dumps(dict(sweep="paper_lod", **paper_lod_leg(torch, args.steps, args.warmup))), flush=True)
+        return
 
     t0 = time.perf_counter()
     templates = [synth.make_template(t, 100_000, 3, synth.C4_LEVELS) for t in range(14)]

@@ -296,8 +296,97 @@ cs_status cs_adam(cs_ctx* ctx, float* param, const float* grad, float* m, float*
 cs_status cs_reserve(cs_ctx* ctx, int64_t max_instances, int64_t max_splats, int64_t max_pairs);
 cs_status cs_frame_capture(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, const float* pose,
                            const cs_camera* cam, const cs_lod_params* lod, float* image);
+/* Animation inside the captured frame: a ring of n_frames pose frames
+ * (float [n_frames][n_inst][24][3], 16-byte aligned; DEVICE memory or PINNED
+ * host memory from hipHostMalloc, caller-owned, kept alive and unchanged
+ * while frames replay). A frame captured after this call starts with the
+ * pose upload: replay k (k = 0, 1, ... counted on the device since this call)
+ * copies ring frame (first + k) % n_frames into the pose buffer given to
+ * cs_frame_capture, so every replay animates without host work. From pinned
+ * host memory that copy is the frame's host-to-device pose upload. n_inst
+ * must equal the captured frame's instance count (CS_ERR_INVALID at capture
+ * otherwise). ring = NULL removes the ring (later captures upload nothing).
+ * Memory the device cannot address gives CS_ERR_INVALID. Synchronises. */
+cs_status cs_set_pose_ring(cs_ctx* ctx, const float* ring, int32_t n_frames, int32_t n_inst, int64_t first);
+
+/* A static crowd (CrowdSplat §3, Tab. 2 "w/o motion"): capture cs_render_frame
+ * alone, over the Gaussians the last eager cs_select_lod + cs_skin_instances
+ * left resident (no skinning per frame). Needs fuse_skin_project = 0
+ * (CS_ERR_UNSUPPORTED otherwise) and a skinned crowd (CS_ERR_STATE otherwise;
+ * a cs_reserve that grows the splat capacity after skinning discards the
+ * skinned Gaussians, so reserve first). Replay with cs_frame_launch. */
+cs_status cs_frame_capture_render(cs_ctx* ctx, const cs_camera* cam, float* image);
 cs_status cs_frame_launch(cs_ctx* ctx);
 cs_status cs_frame_poll(cs_ctx* ctx, cs_frame_stats* stats); /* synchronises */
+
+/* ---- pose-dependent Gaussian offsets (CrowdSplat §2: the second stage of
+ * GaussianAvatar, which the paper follows, trains a network that predicts
+ * pose-dependent changes of the template's Gaussians before skinning).
+ * The paper does not give the network; this library's reading: every
+ * template Gaussian g has an embedding e_g of CS_PNET_EMBED values; an
+ * instance's pose code p holds the axis-angles of joints 1..23 (the root's
+ * global orientation excluded) followed by 11 zeros; per instance-Gaussian
+ *   h1 = relu(W1 [e_g ; p] + b1), h2 = relu(W2 h1 + b2), d = W3 h2 + b3,
+ * and the Gaussian is skinned from the canonical mean mu_g + d (covariance
+ * unchanged). W1, W2, W3 and every layer input are rounded to bfloat16
+ * (nearest even) for the matrix cores; biases and accumulation are FP32.
+ * cs_upload_pose_net copies the network (FP32 masters, HOST) and, for each
+ * uploaded template t, its embeddings embed[t] (HOST float
+ * [n_gauss_t][CS_PNET_EMBED]); from then on cs_skin_instances computes the
+ * offsets of every drawn Gaussian (CS_STAGE_OFFSETS) and skinning uses them.
+ * net = NULL removes the network. CS_ERR_STATE before cs_upload_templates;
+ * cs_upload_templates removes it; cs_render_backward is refused while it is
+ * set (CS_ERR_UNSUPPORTED). */
+#define CS_PNET_EMBED  32
+#define CS_PNET_POSE   80
+#define CS_PNET_HIDDEN 64
+typedef struct cs_pose_net {
+  float w1[CS_PNET_HIDDEN][CS_PNET_EMBED + CS_PNET_POSE];  /* [unit][embedding | pose code] */
+  float b1[CS_PNET_HIDDEN];
+  float w2[CS_PNET_HIDDEN][CS_PNET_HIDDEN];
+  float b2[CS_PNET_HIDDEN];
+  float w3[3][CS_PNET_HIDDEN];
+  float b3[3];
+  int32_t reserved;
+} cs_pose_net;
+cs_status cs_upload_pose_net(cs_ctx* ctx, const cs_pose_net* net, const float* const* embed);
+
+/* ---- memory: shared templates vs per-instance copies (CrowdSplat §2, Tab. 1)
+ * The paper keeps one copy of every Gaussian attribute but the means per
+ * template and shares it across all characters drawn from it. In this
+ * library sharing is the default: no instance holds template attributes;
+ * per-instance state is the bone matrices and work list, and per-splat and
+ * per-pair state are frame buffers whose size depends on the Gaussians drawn,
+ * not on their attribute size.
+ * cs_materialise_instances switches to the unshared layout the paper
+ * compares against: every instance of the DEVICE array inst[n_inst] (the
+ * instance table later frames use) gets its own device copy of its
+ * template's attribute columns (geometry, covariance, opacity, SH), and the
+ * per-Gaussian kernels read that copy (images are identical). Frames must
+ * then use exactly n_inst instances (else CS_ERR_STATE). n_inst = 0 frees
+ * the copies and returns to sharing. Synchronises; not during capture;
+ * cs_update_template is refused while copies exist (CS_ERR_UNSUPPORTED);
+ * cs_upload_templates drops them. A bad template id gives CS_ERR_INVALID. */
+cs_status cs_materialise_instances(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst);
+
+/* Device bytes the context holds now, by what they hold (every device
+ * allocation of the context is counted in exactly one field; the 12.6 MiB
+ * scratch of cs_sort_pairs_noalloc is per process and not counted).
+ * Capacity-sized buffers are counted at their current capacity. */
+typedef struct cs_memory_stats {
+  int64_t templates;        /* shared template store: SoA columns, raw columns, table  */
+  int64_t instance_copies;  /* per-instance template copies (cs_materialise_instances)  */
+  int64_t per_instance;     /* bones, joints, levels, offsets, work list, LoD features  */
+  int64_t per_splat;        /* records, skinned Gaussians, rects, counts, offsets       */
+  int64_t per_pair;         /* keys, sorted splat indices, segment lists, look-back     */
+  int64_t workspace;        /* header, histograms, count matrix, ranges, gradients      */
+  int64_t total;            /* sum of the six fields above                              */
+  int64_t peak;             /* largest total since cs_create                            */
+  int64_t cap_instances, cap_splats, cap_pairs;
+  int64_t n_copies;         /* instances with their own template copy (0 = shared)      */
+  int64_t reserved[4];
+} cs_memory_stats;
+cs_status cs_memory_report(cs_ctx* ctx, cs_memory_stats* out);
 
 /* ---- introspection (tests, profiling) ------------------------------------
  * Copy an internal device buffer of the last frame to host memory (synchronous).
@@ -321,6 +410,7 @@ cs_status cs_frame_poll(cs_ctx* ctx, cs_frame_stats* stats); /* synchronises */
 #define CS_BUF_PRED     17  /* float [n_inst][16] learned-LoD predicted PSNR         */
 #define CS_BUF_VIEWS    18  /* int64 [n_inst][6] window x0 y0 w h (px), tile base, atlas offset */
 #define CS_BUF_JOINTS   19  /* float [n_inst][24][3] posed joint positions           */
+#define CS_BUF_OFFSETS  20  /* float [n_splats][4] pose-dependent offsets (x y z 0)  */
 cs_status cs_debug_copy(cs_ctx* ctx, int32_t which, void* host_dst, int64_t offset, int64_t bytes);
 
 /* ---- learned LoD ----------------------------------------------------------
@@ -374,7 +464,8 @@ cs_status cs_view_psnr(cs_ctx* ctx, const float* atlas_ref, const float* atlas, 
 #define CS_STAGE_RANGES  7  /* per-tile ranges (emission form)                             */
 #define CS_STAGE_BLEND   8  /* compositing                                                 */
 #define CS_STAGE_SEGSORT 9  /* the LDS segment sort alone (tile-bucket form, within SORT)  */
-#define CS_STAGE_COUNT   10
+#define CS_STAGE_OFFSETS 10 /* pose-dependent offsets (pose codes + the offset network)   */
+#define CS_STAGE_COUNT   11
 cs_status cs_stage_times(cs_ctx* ctx, float* ms, int32_t n);
 
 /* Stable LSD radix sort of (key, value) pairs by the low key_bits bits of key,

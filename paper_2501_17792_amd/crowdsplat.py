@@ -32,7 +32,7 @@ CS_MAX_LEVELS = 8
 
 BUF = dict(BONES=1, LEVEL=2, OFFSET=3, SKIN_MU=4, SKIN_COV=5, SKIN_COV2=6, RECORD=7, RECT=8,
            COUNT=9, PAIR_OFF=10, KEYS=11, VALS=12, SKEYS=13, SVALS=14, RANGES=15, FEATURES=16,
-           PRED=17, VIEWS=18, JOINTS=19)
+           PRED=17, VIEWS=18, JOINTS=19, OFFSETS=20)
 
 #: every symbol include/crowdsplat.h declares
 EXPORTS = ["cs_create", "cs_destroy", "cs_last_error", "cs_version", "cs_upload_templates",
@@ -40,8 +40,9 @@ EXPORTS = ["cs_create", "cs_destroy", "cs_last_error", "cs_version", "cs_upload_
            "cs_reserve", "cs_frame_capture", "cs_frame_launch", "cs_frame_poll", "cs_debug_copy",
            "cs_sort_pairs", "cs_stage_times", "cs_lod_features", "cs_mlp_predict", "cs_mlp_sync",
            "cs_mlp_train_step", "cs_render_views", "cs_view_psnr", "cs_update_template", "cs_fit_loss",
-           "cs_adam"]
-STAGES = ["lod", "fk", "skin", "project", "scan", "emit", "sort", "ranges", "blend", "segsort"]
+           "cs_adam", "cs_materialise_instances", "cs_memory_report",
+           "cs_frame_capture_render", "cs_set_pose_ring", "cs_upload_pose_net"]
+STAGES = ["lod", "fk", "skin", "project", "scan", "emit", "sort", "ranges", "blend", "segsort", "offsets"]
 
 
 class CsOptions(ctypes.Structure):
@@ -90,6 +91,27 @@ class CsFrameStats(ctypes.Structure):
                 ("blend_evals", ctypes.c_int64), ("reserved", ctypes.c_int64 * 4)]
 
 
+CS_PNET_EMBED, CS_PNET_POSE, CS_PNET_HIDDEN = 32, 80, 64
+
+
+class CsPoseNet(ctypes.Structure):
+    _fields_ = [("w1", (ctypes.c_float * (CS_PNET_EMBED + CS_PNET_POSE)) * CS_PNET_HIDDEN),
+                ("b1", ctypes.c_float * CS_PNET_HIDDEN),
+                ("w2", (ctypes.c_float * CS_PNET_HIDDEN) * CS_PNET_HIDDEN),
+                ("b2", ctypes.c_float * CS_PNET_HIDDEN),
+                ("w3", (ctypes.c_float * CS_PNET_HIDDEN) * 3), ("b3", ctypes.c_float * 3),
+                ("reserved", ctypes.c_int32)]
+
+
+class CsMemoryStats(ctypes.Structure):
+    _fields_ = [("templates", ctypes.c_int64), ("instance_copies", ctypes.c_int64),
+                ("per_instance", ctypes.c_int64), ("per_splat", ctypes.c_int64),
+                ("per_pair", ctypes.c_int64), ("workspace", ctypes.c_int64), ("total", ctypes.c_int64),
+                ("peak", ctypes.c_int64), ("cap_instances", ctypes.c_int64), ("cap_splats", ctypes.c_int64),
+                ("cap_pairs", ctypes.c_int64), ("n_copies", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 4)]
+
+
 class CsTemplateGrads(ctypes.Structure):
     _fields_ = [("template_id", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("mean", ctypes.c_void_p), ("log_scale", ctypes.c_void_p),
@@ -133,9 +155,14 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cs_reserve": (i32, [P, i64, i64, i64]),
         "cs_frame_capture": (i32, [P, i32, P, P, ctypes.POINTER(CsCamera), ctypes.POINTER(CsLodParams), P]),
         "cs_frame_launch": (i32, [P]),
+        "cs_frame_capture_render": (i32, [P, ctypes.POINTER(CsCamera), P]),
+        "cs_set_pose_ring": (i32, [P, P, i32, i32, i64]),
+        "cs_upload_pose_net": (i32, [P, ctypes.POINTER(CsPoseNet), P]),
         "cs_frame_poll": (i32, [P, ctypes.POINTER(CsFrameStats)]),
         "cs_debug_copy": (i32, [P, i32, P, i64, i64]),
         "cs_sort_pairs": (i32, [P, P, P, i64, i32]),
+        "cs_materialise_instances": (i32, [P, i32, P]),
+        "cs_memory_report": (i32, [P, ctypes.POINTER(CsMemoryStats)]),
         "cs_stage_times": (i32, [P, ctypes.POINTER(ctypes.c_float), i32]),
         "cs_lod_features": (i32, [P, i32, P, P, ctypes.POINTER(CsCamera), P, P]),
         "cs_mlp_predict": (i32, [P, P, P, i32, P]),
@@ -222,6 +249,14 @@ class Renderer:
             msg = self.lib.cs_last_error(c).decode() if c else "(no context)"
             raise CrowdSplatError(status, msg)
 
+    def _hold(self, *tensors):
+        """Device tensors the library reads asynchronously on the context's
+        stream: the caching allocator must not hand their memory to a later
+        allocation before that stream's work up to here has run."""
+        for t in tensors:
+            if t.is_cuda:
+                t.record_stream(self.stream)
+
     def close(self):
         if getattr(self, "ctx", None):
             self.lib.cs_destroy(self.ctx)
@@ -307,6 +342,39 @@ class Renderer:
                                               self.pose_dev.data_ptr(), ctypes.byref(c),
                                               ctypes.byref(p), image.data_ptr()))
 
+    def upload_pose_net(self, net, embeds):
+        """The pose-dependent offset network (dict w1 [64,112], b1, w2 [64,64],
+        b2, w3 [3,64], b3; float32) and one [n, 32] embedding array per
+        uploaded template; ``net=None`` removes it."""
+        if net is None:
+            self._check(self.lib.cs_upload_pose_net(self.ctx, None, None))
+            return
+        n = CsPoseNet()
+        for k in ("w1", "b1", "w2", "b2", "w3", "b3"):
+            a = np.ascontiguousarray(net[k], np.float32)
+            ctypes.memmove(ctypes.addressof(getattr(n, k)), a.ctypes.data, a.nbytes)
+        keep = [np.ascontiguousarray(e, np.float32) for e in embeds]
+        ptrs = (ctypes.c_void_p * len(keep))(*[e.ctypes.data for e in keep])
+        self._check(self.lib.cs_upload_pose_net(self.ctx, ctypes.byref(n), ptrs))
+
+    def set_pose_ring(self, ring, first: int = 0):
+        """Poses of every replay of the next captured frame come from ``ring``
+        (tensor [n_frames, n_inst, 24, 3] f32, on the device or pinned on the
+        host); None removes it."""
+        if ring is None:
+            self._check(self.lib.cs_set_pose_ring(self.ctx, None, 0, 0, 0))
+            self.pose_ring = None
+            return
+        assert ring.dtype == self.torch.float32 and ring.is_contiguous() and ring.dim() == 4
+        self._check(self.lib.cs_set_pose_ring(self.ctx, ring.data_ptr(), ring.shape[0], ring.shape[1], first))
+        self.pose_ring = ring  # the library reads it at every replay
+
+    def capture_render(self, cam, image):
+        """Capture rendering alone over the resident skinned crowd (static crowd)."""
+        c = camera_struct(cam)
+        self._keep = [c]
+        self._check(self.lib.cs_frame_capture_render(self.ctx, ctypes.byref(c), image.data_ptr()))
+
     def launch(self):
         self._check(self.lib.cs_frame_launch(self.ctx))
 
@@ -314,6 +382,18 @@ class Renderer:
         st = CsFrameStats()
         self._check(self.lib.cs_frame_poll(self.ctx, ctypes.byref(st)))
         return st
+
+    def materialise(self, enable: bool = True):
+        """Give every instance of the current crowd its own copy of its
+        template's attributes (the unshared layout), or return to sharing."""
+        self._check(self.lib.cs_materialise_instances(self.ctx, self.n_inst if enable else 0,
+                                                      self.inst_dev.data_ptr() if enable else None))
+
+    def memory(self) -> dict:
+        """Device bytes this context holds, by category (cs_memory_report)."""
+        m = CsMemoryStats()
+        self._check(self.lib.cs_memory_report(self.ctx, ctypes.byref(m)))
+        return {name: int(getattr(m, name)) for name, _ in CsMemoryStats._fields_ if name != "reserved"}
 
     def debug(self, name: str, dtype, count: int, offset: int = 0) -> np.ndarray:
         out = np.empty(count, dtype)
@@ -386,17 +466,23 @@ class Renderer:
         g.template_id = tid
         for k, v in out.items():
             setattr(g, k, v.data_ptr())
-        self._check(self.lib.cs_render_backward(self.ctx, dimg.contiguous().data_ptr(), ctypes.byref(g)))
+        dimg_c = dimg.contiguous()
+        self._check(self.lib.cs_render_backward(self.ctx, dimg_c.data_ptr(), ctypes.byref(g)))
+        self._hold(dimg_c)
         return out
 
     def update_template(self, tid, mean, log_scale, quat, opacity, sh, skin_idx, skin_w, opacity_is_logit=True):
         d = CsTemplateDesc()
         t = self.templates[tid]
         d.n_gauss, d.sh_degree, d.n_levels = t.n, t.sh_degree, len(t.level_count)
+        held = []
         for k, v in dict(mean=mean, log_scale=log_scale, quat=quat, opacity=opacity, sh=sh, skin_idx=skin_idx,
                          skin_w=skin_w).items():
-            setattr(d, k, v.contiguous().data_ptr())
+            vc = v.contiguous()
+            held.append(vc)
+            setattr(d, k, vc.data_ptr())
         self._check(self.lib.cs_update_template(self.ctx, tid, ctypes.byref(d), int(opacity_is_logit)))
+        self._hold(*held)
 
     def fit_loss(self, x, y, lam=0.2, want_grad=True):
         torch = self.torch

@@ -20,6 +20,22 @@ constexpr int kFeat = 32;             // learned-LoD feature width (31 used + pa
 constexpr int kMlpHidden = 64;
 constexpr int kMlpOut = 8;            // 5 levels used, padded
 
+// Pose-dependent offset network (offsets.hip): sizes and device weights,
+// bfloat16 as raw 16-bit patterns, w3 / b3 padded to 16 output rows.
+constexpr int kPnEmbed = CS_PNET_EMBED;
+constexpr int kPnPose = CS_PNET_POSE;
+constexpr int kPnPoseUsed = 69;  // joints 1..23 x 3
+constexpr int kPnHidden = CS_PNET_HIDDEN;
+struct PoseNetDev {
+  uint16_t w1e[kPnHidden * kPnEmbed];  // [64][32] embedding columns of W1
+  uint16_t w1p[kPnHidden * kPnPose];   // [64][80] pose columns of W1
+  uint16_t w2[kPnHidden * kPnHidden];  // [64][64]
+  uint16_t w3[16 * kPnHidden];         // [16][64], rows 3..15 zero
+  float b1[kPnHidden];
+  float b2[kPnHidden];
+  float b3[16];                        // entries 3..15 zero
+};
+
 // Device-side view of one uploaded template (structure of arrays).
 // A pointer read from device memory (a struct field) is generic to the
 // compiler, so loads through it become FLAT instructions, which also count
@@ -60,6 +76,7 @@ struct TemplateDev {
   int32_t parents[kJoints];
   float pad_radius;        // rest-pose bound: max distance of a mean from its nearest joint + 3 sigma
   float rest_height;
+  const uint16_t* embed;   // [n][kPnEmbed] bfloat16 pose-network embeddings, or null
 };
 
 // The per-Gaussian columns of one template, copied out of the device
@@ -106,7 +123,8 @@ struct FrameHdr {
   uint32_t frame;
   uint32_t ticket[8];      // onesweep partition tickets per pass
   uint32_t level_hist[kMaxLevels];
-  uint32_t pad[7];
+  uint32_t pose_frame;      // captured frames: frames fetched from the pose ring so far
+  uint32_t pad[6];
   uint32_t sort_fallbacks; // LDS-sorted segments re-sorted with ballot ranks this frame
 };
 
@@ -136,7 +154,15 @@ struct WorkDev {
   FrameHdr* hdr;
   int32_t skin_mode;
   const int4* crop;        // view mode: per-instance tile window [x0,y0,x1,y1), else null
+  const TemplateDev* tpl_inst;  // per-instance template copies (unshared layout), else null
+  const float4* offsets;        // per-splat pose-dependent offsets of the canonical means, else null
 };
+
+// The template columns instance `inst` (template `tid`) is drawn from: its
+// own copy in the unshared layout, else the shared template.
+__device__ __forceinline__ const TemplateDev& work_template(const WorkDev& w, int inst, int tid) {
+  return w.tpl_inst ? w.tpl_inst[inst] : w.tpl[tid];
+}
 
 // View mode (every instance alone in its own window), see cs_render_views.
 struct ViewDev {
@@ -166,6 +192,12 @@ hipError_t launch_prepare_template(const float* mean, const float* log_scale, co
                                    const float* skin_w, int n, int sh_degree, float4* mean_idx,
                                    float4* skin_w_out, float4* cov_a, float2* cov_b, float* op_out,
                                    float4* sh_out, hipStream_t st);
+// captured frames: copy frame (first + fetched so far) % n_frames of the pose
+// ring into the frame's pose buffer, then count the fetch
+hipError_t launch_pose_fetch(const float* ring, int n_frames, int64_t first, int64_t floats_per_frame,
+                             float* pose, FrameHdr* hdr, hipStream_t st);
+hipError_t launch_pose_offsets(WorkDev w, const PoseNetDev* net, const float* pose, int n_inst, float* u,
+                               float4* offsets, int grid, hipStream_t st);
 hipError_t launch_frame_reset(FrameHdr* hdr, uint32_t* hist, int hist_len, int clear_overflow,
                               hipStream_t st);
 hipError_t launch_fk(const cs_instance* inst, const float* pose, const TemplateDev* tpl, int n_inst,

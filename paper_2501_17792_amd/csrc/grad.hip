@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kChunkThreads) void splat_backward_kernel(
     const Chunk ch = w.chunks[c];
     const cs_instance in = w.inst[ch.inst];
     if (in.tid != tid_want) continue;  // uniform per block
-    const TplCols T = TplCols::of(w.tpl[in.tid]);
+    const TplCols T = TplCols::of(work_template(w, ch.inst, in.tid));
     __syncthreads();
     for (int e = threadIdx.x; e < kJoints * 12; e += kChunkThreads)
       s_bones[e] = w.bones[(size_t)ch.inst * kJoints * 12 + e];

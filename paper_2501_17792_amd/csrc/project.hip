@@ -29,7 +29,7 @@ __device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOu
     Posed p;
     // geometry first: the loads complete in issue order, so the wait for
     // them does not include the SH planes issued after them
-    const float4 mi = gload(T.mean_idx, g);
+    float4 mi = gload(T.mean_idx, g);
     const float4 wt = gload(T.skin_w, g);
     const float4 ca = fused ? gload(T.cov_a, g) : make_float4(0.f, 0.f, 0.f, 0.f);
     const float2 cb = fused ? gload(T.cov_b, g) : make_float2(0.f, 0.f);
@@ -39,6 +39,12 @@ __device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOu
     for (int j = 0; j < N4; ++j) shv[j] = gload(T.sh, (size_t)j * T.n + g);
     const float op = gload(T.opacity, g);
     if (fused) {
+      if (w.offsets) {  // pose-dependent offset of the canonical mean
+        const float4 o = w.offsets[s];
+        mi.x += o.x;
+        mi.y += o.y;
+        mi.z += o.z;
+      }
       skin_gaussian(s_bones, mi, wt, ca, cb, w.skin_mode, Ry, p);
     } else {
       const float4 m = skinned.mu[s];
@@ -98,7 +104,7 @@ __global__ __launch_bounds__(kChunkThreads) __attribute__((amdgpu_waves_per_eu(3
   for (int c = chunk_lo + blockIdx.x; c < hi; c += gridDim.x) {
     const Chunk ch = w.chunks[c];
     const cs_instance in = w.inst[ch.inst];
-    const TplCols T = TplCols::of(w.tpl[in.tid]);
+    const TplCols T = TplCols::of(work_template(w, ch.inst, in.tid));
     for (int e = threadIdx.x; e < kJoints * 12; e += kChunkThreads)
       s_bones[e] = w.bones[(size_t)ch.inst * kJoints * 12 + e];
     if (threadIdx.x == 0) s_vis = 0;

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "cs_internal.h"
@@ -29,10 +30,14 @@ struct TemplateStore {
   float* raw_mean = nullptr;       // [n][3]  kept for the backward
   float* raw_log_scale = nullptr;  // [n][3]
   float* raw_quat = nullptr;       // [n][4]
+  uint16_t* embed = nullptr;       // [n][32] bfloat16 pose-network embeddings
   TemplateDev dev{};
 };
 
 enum State { kNone = 0, kTemplates = 1, kLod = 2, kSkinned = 3, kRendered = 4 };
+
+// What a device buffer of the context holds (cs_memory_report's fields).
+enum MemCat { kMemTemplates = 0, kMemCopies, kMemInstance, kMemSplat, kMemPair, kMemWork, kMemCats };
 
 constexpr uint32_t kMaxPairsLimit = (1u << 30) - 1u;  // look-back count field
 
@@ -47,6 +52,15 @@ struct cs_ctx {
   std::vector<TemplateStore> tpl;
   TemplateDev* tpl_dev = nullptr;
   int max_tpl_n = 0;
+  // pose-dependent offsets: the network, per-instance pose terms, per-splat offsets
+  PoseNetDev* pnet = nullptr;
+  float* pn_u = nullptr;        // [cap_inst][64]
+  float4* offsets = nullptr;    // [cap_offsets]
+  int64_t cap_offsets = 0;
+  // unshared layout: one copy of the template columns per instance
+  unsigned char* copies = nullptr;
+  TemplateDev* tpl_inst = nullptr;
+  int n_copies = 0;
 
   FrameHdr* hdr = nullptr;
   FrameHdr* hdr_host = nullptr;  // pinned
@@ -125,9 +139,31 @@ struct cs_ctx {
   bool fixed_capacity = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  const float* pose_ring = nullptr;  // captured animation: [n_frames][n_inst][24][3]
+  int32_t pose_ring_frames = 0;
+  int64_t pose_ring_first = 0;
+  int32_t pose_ring_inst = 0;
   std::vector<uint32_t> chunk_off_host;  // per-instance launch mode
   hipEvent_t ev[CS_STAGE_COUNT][2] = {};
   bool ev_used[CS_STAGE_COUNT] = {};
+
+  // device bytes held, by category (every hipMalloc of the context goes through dalloc)
+  std::unordered_map<const void*, std::pair<size_t, int>> allocs;
+  int64_t mem_bytes[kMemCats] = {};
+  int64_t mem_peak = 0;
+  void track(const void* p, size_t bytes, int cat) {
+    allocs[p] = {bytes, cat};
+    mem_bytes[cat] += (int64_t)bytes;
+    int64_t tot = 0;
+    for (int c = 0; c < kMemCats; ++c) tot += mem_bytes[c];
+    mem_peak = std::max(mem_peak, tot);
+  }
+  void untrack(const void* p) {
+    auto it = allocs.find(p);
+    if (it == allocs.end()) return;
+    mem_bytes[it->second.second] -= (int64_t)it->second.first;
+    allocs.erase(it);
+  }
 
   // stage timing (eager frames with profile_stages only)
   void mark(int stage, int end) {
@@ -161,11 +197,18 @@ struct cs_ctx {
 namespace {
 
 template <class T>
-cs_status dalloc(cs_ctx* ctx, T** p, size_t count) {
-  if (*p) {
-    hipFree(*p);
-    *p = nullptr;
-  }
+void dfree(cs_ctx* ctx, T** p) {
+  if (!*p) return;
+  ctx->untrack(*p);
+  hipFree(*p);
+  *p = nullptr;
+}
+
+// Device allocation of `count` elements, accounted under `cat` (what the
+// buffer holds) for cs_memory_report; a buffer already at *p is freed first.
+template <class T>
+cs_status dalloc(cs_ctx* ctx, T** p, size_t count, int cat = kMemWork) {
+  dfree(ctx, p);
   if (count == 0) return CS_OK;
   hipError_t e = hipMalloc((void**)p, count * sizeof(T));
   if (e != hipSuccess) {
@@ -173,13 +216,8 @@ cs_status dalloc(cs_ctx* ctx, T** p, size_t count) {
     (void)hipGetLastError();
     return ctx->hip_fail("hipMalloc", e);
   }
+  ctx->track(*p, count * sizeof(T), cat);
   return CS_OK;
-}
-
-template <class T>
-void dfree(T** p) {
-  if (*p) hipFree(*p);
-  *p = nullptr;
 }
 
 cs_status ensure_instances(cs_ctx* ctx, int64_t n_inst) {
@@ -188,18 +226,19 @@ cs_status ensure_instances(cs_ctx* ctx, int64_t n_inst) {
   if (ctx->capturing || ctx->fixed_capacity)
     return ctx->fail(CS_ERR_CAPACITY, "instance capacity exceeded (reserve more before capture)");
   const int64_t cap = std::max<int64_t>(n_inst, 64);
-  CS_TRY(dalloc(ctx, &ctx->level, cap));
-  CS_TRY(dalloc(ctx, &ctx->count_inst, cap));
-  CS_TRY(dalloc(ctx, &ctx->offset, cap + 1));
-  CS_TRY(dalloc(ctx, &ctx->chunk_off, cap + 1));
-  CS_TRY(dalloc(ctx, &ctx->chunks, cap * per));
-  CS_TRY(dalloc(ctx, &ctx->chunks_t, cap * per));
-  CS_TRY(dalloc(ctx, &ctx->bones, cap * kJoints * 12));
-  CS_TRY(dalloc(ctx, &ctx->joints, cap * kJoints * 3));
-  CS_TRY(dalloc(ctx, &ctx->feat, cap * 32));
-  CS_TRY(dalloc(ctx, &ctx->pred, cap * 16));
-  CS_TRY(dalloc(ctx, &ctx->views, cap * 6));
-  CS_TRY(dalloc(ctx, &ctx->crop, cap));
+  CS_TRY(dalloc(ctx, &ctx->level, cap, kMemInstance));
+  CS_TRY(dalloc(ctx, &ctx->count_inst, cap, kMemInstance));
+  CS_TRY(dalloc(ctx, &ctx->offset, cap + 1, kMemInstance));
+  CS_TRY(dalloc(ctx, &ctx->chunk_off, cap + 1, kMemInstance));
+  CS_TRY(dalloc(ctx, &ctx->chunks, cap * per, kMemInstance));
+  CS_TRY(dalloc(ctx, &ctx->chunks_t, cap * per, kMemInstance));
+  CS_TRY(dalloc(ctx, &ctx->bones, cap * kJoints * 12, kMemInstance));
+  CS_TRY(dalloc(ctx, &ctx->joints, cap * kJoints * 3, kMemInstance));
+  CS_TRY(dalloc(ctx, &ctx->feat, cap * 32, kMemInstance));
+  CS_TRY(dalloc(ctx, &ctx->pred, cap * 16, kMemInstance));
+  CS_TRY(dalloc(ctx, &ctx->views, cap * 6, kMemInstance));
+  CS_TRY(dalloc(ctx, &ctx->crop, cap, kMemInstance));
+  CS_TRY(dalloc(ctx, &ctx->pn_u, cap * kPnHidden, kMemInstance));
   ctx->cap_inst = cap;
   ctx->cap_chunks = cap * per;
   return CS_OK;
@@ -211,16 +250,21 @@ cs_status ensure_splats(cs_ctx* ctx, int64_t n) {
     return ctx->fail(CS_ERR_CAPACITY, "splat capacity exceeded");
   if (n >= 0xffffffffll) return ctx->fail(CS_ERR_CAPACITY, "more than 2^32 splats in one frame");
   const int64_t cap = std::min<int64_t>(0xfffffffell, std::max<int64_t>(n + n / 4, 4096));
-  CS_TRY(dalloc(ctx, &ctx->skin_mu, cap));
-  CS_TRY(dalloc(ctx, &ctx->skin_cov, cap));
-  CS_TRY(dalloc(ctx, &ctx->skin_zz, cap));
-  CS_TRY(dalloc(ctx, &ctx->rec, cap * 3));
-  CS_TRY(dalloc(ctx, &ctx->rect, cap));
-  CS_TRY(dalloc(ctx, &ctx->cnt, cap));
-  CS_TRY(dalloc(ctx, &ctx->rd, cap));
-  CS_TRY(dalloc(ctx, &ctx->pair_off, cap));
-  CS_TRY(dalloc(ctx, &ctx->scan_sums, (cap + scan_tile() - 1) / scan_tile() + 1));
+  CS_TRY(dalloc(ctx, &ctx->skin_mu, cap, kMemSplat));
+  CS_TRY(dalloc(ctx, &ctx->skin_cov, cap, kMemSplat));
+  CS_TRY(dalloc(ctx, &ctx->skin_zz, cap, kMemSplat));
+  CS_TRY(dalloc(ctx, &ctx->rec, cap * 3, kMemSplat));
+  CS_TRY(dalloc(ctx, &ctx->rect, cap, kMemSplat));
+  CS_TRY(dalloc(ctx, &ctx->cnt, cap, kMemSplat));
+  CS_TRY(dalloc(ctx, &ctx->rd, cap, kMemSplat));
+  CS_TRY(dalloc(ctx, &ctx->pair_off, cap, kMemSplat));
+  CS_TRY(dalloc(ctx, &ctx->scan_sums, (cap + scan_tile() - 1) / scan_tile() + 1, kMemSplat));
   ctx->cap_splats = cap;
+  if (ctx->pnet) {
+    CS_TRY(dalloc(ctx, &ctx->offsets, cap, kMemSplat));
+    ctx->cap_offsets = cap;
+  }
+  if (ctx->state >= kSkinned) ctx->state = kLod;  // the skinned Gaussians went with the old buffers
   return CS_OK;
 }
 
@@ -231,27 +275,27 @@ cs_status ensure_pairs(cs_ctx* ctx, int64_t n) {
   if (n > (int64_t)kMaxPairsLimit) return ctx->fail(CS_ERR_CAPACITY, "more than 2^30 tile pairs");
   const int64_t cap = std::min<int64_t>(kMaxPairsLimit, std::max<int64_t>(n + n / 4, 65536));
   for (int b = 0; b < 2; ++b) {
-    CS_TRY(dalloc(ctx, &ctx->keys[b], cap));
-    CS_TRY(dalloc(ctx, &ctx->vals[b], cap));
+    CS_TRY(dalloc(ctx, &ctx->keys[b], cap, kMemPair));
+    CS_TRY(dalloc(ctx, &ctx->vals[b], cap, kMemPair));
   }
   // tile-bucket segment lists: a split turns a segment of more than kSegCap
   // keys into at most 256, so every level adds fewer than cap / 64 entries
   const int64_t cap_base = kBucketMaxTiles + cap / 8 + 1024;
   const int64_t cap_big = cap / kSegCap + kBucketMaxTiles + 64;
-  CS_TRY(dalloc(ctx, &ctx->seg_base, cap_base));
-  CS_TRY(dalloc(ctx, &ctx->seg_big[0], cap_big));
-  CS_TRY(dalloc(ctx, &ctx->seg_big[1], cap_big));
+  CS_TRY(dalloc(ctx, &ctx->seg_base, cap_base, kMemPair));
+  CS_TRY(dalloc(ctx, &ctx->seg_big[0], cap_big, kMemPair));
+  CS_TRY(dalloc(ctx, &ctx->seg_big[1], cap_big, kMemPair));
   ctx->cap_seg_base = cap_base;
   ctx->cap_seg_big = cap_big;
   const int64_t cap_ssegs = split_segs_cap(cap), cap_sitems = split_items_cap(cap);
-  CS_TRY(dalloc(ctx, &ctx->split_segs, cap_ssegs));
-  CS_TRY(dalloc(ctx, &ctx->split_item0, cap_ssegs));
-  CS_TRY(dalloc(ctx, &ctx->split_items, cap_sitems));
-  CS_TRY(dalloc(ctx, &ctx->split_hist, cap_sitems * kSplitBins));
+  CS_TRY(dalloc(ctx, &ctx->split_segs, cap_ssegs, kMemPair));
+  CS_TRY(dalloc(ctx, &ctx->split_item0, cap_ssegs, kMemPair));
+  CS_TRY(dalloc(ctx, &ctx->split_items, cap_sitems, kMemPair));
+  CS_TRY(dalloc(ctx, &ctx->split_hist, cap_sitems * kSplitBins, kMemPair));
   ctx->cap_split_segs = cap_ssegs;
   ctx->cap_split_items = cap_sitems;
   const int64_t parts = (cap + kSortPart - 1) / kSortPart;
-  CS_TRY(dalloc(ctx, &ctx->lookback, parts * kSortBins));
+  CS_TRY(dalloc(ctx, &ctx->lookback, parts * kSortBins, kMemPair));
   HIP_TRY(hipMemsetAsync(ctx->lookback, 0, parts * kSortBins * sizeof(uint64_t), ctx->stream));
   ctx->cap_pairs = cap;
   ctx->cap_parts = parts;
@@ -317,6 +361,8 @@ WorkDev work_view(cs_ctx* ctx, bool template_major = true) {
   w.tpl = ctx->tpl_dev;
   w.hdr = ctx->hdr;
   w.skin_mode = ctx->opt.skin_mode;
+  w.tpl_inst = ctx->n_copies ? ctx->tpl_inst : nullptr;
+  w.offsets = ctx->pnet ? ctx->offsets : nullptr;
   return w;
 }
 
@@ -324,18 +370,25 @@ int persistent_grid(int64_t work, int cap) { return (int)std::max<int64_t>(1, st
 
 void free_templates(cs_ctx* ctx) {
   for (auto& t : ctx->tpl) {
-    dfree(&t.mean_idx);
-    dfree(&t.skin_w);
-    dfree(&t.cov_a);
-    dfree(&t.cov_b);
-    dfree(&t.opacity);
-    dfree(&t.sh);
-    dfree(&t.raw_mean);
-    dfree(&t.raw_log_scale);
-    dfree(&t.raw_quat);
+    dfree(ctx, &t.mean_idx);
+    dfree(ctx, &t.skin_w);
+    dfree(ctx, &t.cov_a);
+    dfree(ctx, &t.cov_b);
+    dfree(ctx, &t.opacity);
+    dfree(ctx, &t.sh);
+    dfree(ctx, &t.raw_mean);
+    dfree(ctx, &t.raw_log_scale);
+    dfree(ctx, &t.raw_quat);
+    dfree(ctx, &t.embed);
   }
+  dfree(ctx, &ctx->pnet);
+  dfree(ctx, &ctx->offsets);
+  ctx->cap_offsets = 0;
   ctx->tpl.clear();
-  dfree(&ctx->tpl_dev);
+  dfree(ctx, &ctx->tpl_dev);
+  dfree(ctx, &ctx->copies);
+  dfree(ctx, &ctx->tpl_inst);
+  ctx->n_copies = 0;
 }
 
 }  // namespace
@@ -408,52 +461,53 @@ void cs_destroy(cs_ctx* ctx) {
   if (ctx->gexec) hipGraphExecDestroy(ctx->gexec);
   if (ctx->graph) hipGraphDestroy(ctx->graph);
   free_templates(ctx);
-  dfree(&ctx->hdr);
+  dfree(ctx, &ctx->hdr);
   if (ctx->hdr_host) hipHostFree(ctx->hdr_host);
-  dfree(&ctx->n_dev);
-  dfree(&ctx->level);
-  dfree(&ctx->count_inst);
-  dfree(&ctx->offset);
-  dfree(&ctx->chunk_off);
-  dfree(&ctx->chunks);
-  dfree(&ctx->chunks_t);
-  dfree(&ctx->bones);
-  dfree(&ctx->joints);
-  dfree(&ctx->feat);
-  dfree(&ctx->pred);
-  dfree(&ctx->gpair);
-  dfree(&ctx->gsplat);
-  dfree(&ctx->loss_work);
-  dfree(&ctx->views);
-  dfree(&ctx->crop);
-  dfree(&ctx->skin_mu);
-  dfree(&ctx->skin_cov);
-  dfree(&ctx->skin_zz);
-  dfree(&ctx->rec);
-  dfree(&ctx->rect);
-  dfree(&ctx->cnt);
-  dfree(&ctx->pair_off);
-  dfree(&ctx->rd);
-  dfree(&ctx->scan_sums);
+  dfree(ctx, &ctx->n_dev);
+  dfree(ctx, &ctx->level);
+  dfree(ctx, &ctx->count_inst);
+  dfree(ctx, &ctx->offset);
+  dfree(ctx, &ctx->chunk_off);
+  dfree(ctx, &ctx->chunks);
+  dfree(ctx, &ctx->chunks_t);
+  dfree(ctx, &ctx->bones);
+  dfree(ctx, &ctx->joints);
+  dfree(ctx, &ctx->feat);
+  dfree(ctx, &ctx->pred);
+  dfree(ctx, &ctx->gpair);
+  dfree(ctx, &ctx->gsplat);
+  dfree(ctx, &ctx->loss_work);
+  dfree(ctx, &ctx->views);
+  dfree(ctx, &ctx->crop);
+  dfree(ctx, &ctx->pn_u);
+  dfree(ctx, &ctx->skin_mu);
+  dfree(ctx, &ctx->skin_cov);
+  dfree(ctx, &ctx->skin_zz);
+  dfree(ctx, &ctx->rec);
+  dfree(ctx, &ctx->rect);
+  dfree(ctx, &ctx->cnt);
+  dfree(ctx, &ctx->pair_off);
+  dfree(ctx, &ctx->rd);
+  dfree(ctx, &ctx->scan_sums);
   for (int b = 0; b < 2; ++b) {
-    dfree(&ctx->keys[b]);
-    dfree(&ctx->vals[b]);
+    dfree(ctx, &ctx->keys[b]);
+    dfree(ctx, &ctx->vals[b]);
   }
-  dfree(&ctx->lookback);
-  dfree(&ctx->hist);
-  dfree(&ctx->bk_counts);
-  dfree(&ctx->tile_order);
-  dfree(&ctx->bk_sums);
-  dfree(&ctx->seg_base);
-  dfree(&ctx->seg_big[0]);
-  dfree(&ctx->seg_big[1]);
-  dfree(&ctx->split_segs);
-  dfree(&ctx->split_item0);
-  dfree(&ctx->split_items);
-  dfree(&ctx->split_hist);
-  dfree(&ctx->rts_counts);
-  dfree(&ctx->rts_sums);
-  dfree(&ctx->ranges);
+  dfree(ctx, &ctx->lookback);
+  dfree(ctx, &ctx->hist);
+  dfree(ctx, &ctx->bk_counts);
+  dfree(ctx, &ctx->tile_order);
+  dfree(ctx, &ctx->bk_sums);
+  dfree(ctx, &ctx->seg_base);
+  dfree(ctx, &ctx->seg_big[0]);
+  dfree(ctx, &ctx->seg_big[1]);
+  dfree(ctx, &ctx->split_segs);
+  dfree(ctx, &ctx->split_item0);
+  dfree(ctx, &ctx->split_items);
+  dfree(ctx, &ctx->split_hist);
+  dfree(ctx, &ctx->rts_counts);
+  dfree(ctx, &ctx->rts_sums);
+  dfree(ctx, &ctx->ranges);
   delete ctx;
 }
 
@@ -508,23 +562,23 @@ cs_status cs_upload_templates(cs_ctx* ctx, const cs_template_desc* t, int32_t n_
     st.n = n;
     st.sh_degree = d.sh_degree;
     st.n_sh4 = (n_coef3 + 3) / 4;
-    CS_TRY(dalloc(ctx, &st.mean_idx, n));
-    CS_TRY(dalloc(ctx, &st.skin_w, n));
-    CS_TRY(dalloc(ctx, &st.cov_a, n));
-    CS_TRY(dalloc(ctx, &st.cov_b, n));
-    CS_TRY(dalloc(ctx, &st.opacity, n));
-    CS_TRY(dalloc(ctx, &st.sh, (size_t)st.n_sh4 * n));
-    CS_TRY(dalloc(ctx, &st.raw_mean, 3 * (size_t)n));
-    CS_TRY(dalloc(ctx, &st.raw_log_scale, 3 * (size_t)n));
-    CS_TRY(dalloc(ctx, &st.raw_quat, 4 * (size_t)n));
+    CS_TRY(dalloc(ctx, &st.mean_idx, n, kMemTemplates));
+    CS_TRY(dalloc(ctx, &st.skin_w, n, kMemTemplates));
+    CS_TRY(dalloc(ctx, &st.cov_a, n, kMemTemplates));
+    CS_TRY(dalloc(ctx, &st.cov_b, n, kMemTemplates));
+    CS_TRY(dalloc(ctx, &st.opacity, n, kMemTemplates));
+    CS_TRY(dalloc(ctx, &st.sh, (size_t)st.n_sh4 * n, kMemTemplates));
+    CS_TRY(dalloc(ctx, &st.raw_mean, 3 * (size_t)n, kMemTemplates));
+    CS_TRY(dalloc(ctx, &st.raw_log_scale, 3 * (size_t)n, kMemTemplates));
+    CS_TRY(dalloc(ctx, &st.raw_quat, 4 * (size_t)n, kMemTemplates));
     // staging: device copies of every input array
     float *op = nullptr, *sh = nullptr, *w = nullptr;
     uint8_t* idx = nullptr;
     const hipMemcpyKind kind = mem == CS_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
-    CS_TRY(dalloc(ctx, &op, n));
-    CS_TRY(dalloc(ctx, &sh, (size_t)n_coef3 * n));
-    CS_TRY(dalloc(ctx, &w, 4 * (size_t)n));
-    CS_TRY(dalloc(ctx, &idx, 4 * (size_t)n));
+    CS_TRY(dalloc(ctx, &op, n, kMemTemplates));
+    CS_TRY(dalloc(ctx, &sh, (size_t)n_coef3 * n, kMemTemplates));
+    CS_TRY(dalloc(ctx, &w, 4 * (size_t)n, kMemTemplates));
+    CS_TRY(dalloc(ctx, &idx, 4 * (size_t)n, kMemTemplates));
     HIP_TRY(hipMemcpy(st.raw_mean, d.mean, 12ull * n, kind));
     HIP_TRY(hipMemcpy(st.raw_log_scale, d.log_scale, 12ull * n, kind));
     HIP_TRY(hipMemcpy(st.raw_quat, d.quat, 16ull * n, kind));
@@ -540,10 +594,10 @@ cs_status cs_upload_templates(cs_ctx* ctx, const cs_template_desc* t, int32_t n_
     std::vector<float> hm(3ull * n), hs(3ull * n);
     HIP_TRY(hipMemcpy(hm.data(), st.raw_mean, 12ull * n, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(hs.data(), st.raw_log_scale, 12ull * n, hipMemcpyDeviceToHost));
-    dfree(&op);
-    dfree(&sh);
-    dfree(&w);
-    dfree(&idx);
+    dfree(ctx, &op);
+    dfree(ctx, &sh);
+    dfree(ctx, &w);
+    dfree(ctx, &idx);
     TemplateDev& dv = st.dev;
     dv.mean_idx = st.mean_idx;
     dv.skin_w = st.skin_w;
@@ -576,7 +630,7 @@ cs_status cs_upload_templates(cs_ctx* ctx, const cs_template_desc* t, int32_t n_
     ctx->max_tpl_n = std::max(ctx->max_tpl_n, n);
     ctx->tpl.push_back(st);
   }
-  CS_TRY(dalloc(ctx, &ctx->tpl_dev, n_templates));
+  CS_TRY(dalloc(ctx, &ctx->tpl_dev, n_templates, kMemTemplates));
   HIP_TRY(hipMemcpy(ctx->tpl_dev, devs.data(), sizeof(TemplateDev) * n_templates, hipMemcpyHostToDevice));
   ctx->cap_chunks = 0;  // chunk capacity depends on the largest template
   ctx->state = kTemplates;
@@ -598,6 +652,9 @@ cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, co
     return ctx->fail(CS_ERR_INVALID, "learned LoD needs the network and the poses");
   if (lod->mode == CS_LOD_CONSTANT && (lod->level < 0 || lod->level >= CS_MAX_LEVELS))
     return ctx->fail(CS_ERR_INVALID, "constant level out of range");
+  if (ctx->n_copies && n_inst != ctx->n_copies)
+    return ctx->fail(CS_ERR_STATE, "templates were materialised for " + std::to_string(ctx->n_copies) +
+                                       " instances; frames must draw exactly those");
   hipSetDevice(ctx->device);
   CamDev cd;
   CS_TRY(make_camera(ctx, cam, &cd));
@@ -679,6 +736,14 @@ cs_status cs_skin_instances(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst
   HIP_TRY(launch_fk(inst, pose, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), ctx->bones, ctx->joints,
                     ctx->hdr, ctx->stream));
   ctx->mark(CS_STAGE_FK, 1);
+  if (ctx->pnet) {
+    ctx->mark(CS_STAGE_OFFSETS, 0);
+    if (ctx->cap_offsets < ctx->cap_splats) return ctx->fail(CS_ERR_STATE, "offset buffer smaller than the splats");
+    const int grid = persistent_grid(ctx->capturing ? ctx->cap_chunks : ctx->hdr_host->n_chunks, 1 << 20);
+    HIP_TRY(launch_pose_offsets(work_view(ctx), ctx->pnet, pose, n_inst, ctx->pn_u, ctx->offsets, grid,
+                                ctx->stream));
+    ctx->mark(CS_STAGE_OFFSETS, 1);
+  }
   if (!ctx->opt.fuse_skin_project) {
     ctx->mark(CS_STAGE_SKIN, 0);
     SkinOut so{ctx->skin_mu, ctx->skin_cov, ctx->skin_zz};
@@ -974,6 +1039,7 @@ cs_status cs_render_backward(cs_ctx* ctx, const float* dL_dimage, cs_template_gr
   if (ctx->state < kRendered || ctx->last_was_views)
     return ctx->fail(CS_ERR_STATE, "cs_render_backward needs a preceding cs_render_frame");
   if (!dL_dimage || !g) return ctx->fail(CS_ERR_INVALID, "NULL argument");
+  if (ctx->pnet) return ctx->fail(CS_ERR_UNSUPPORTED, "cs_render_backward with pose-dependent offsets");
   if (g->template_id < 0 || g->template_id >= (int)ctx->tpl.size())
     return ctx->fail(CS_ERR_INVALID, "template_id out of range");
   if (ctx->capturing) return ctx->fail(CS_ERR_STATE, "backward during capture");
@@ -1015,6 +1081,8 @@ cs_status cs_update_template(cs_ctx* ctx, int32_t tid, const cs_template_desc* d
   if (d->n_gauss != st.n || d->sh_degree != st.sh_degree)
     return ctx->fail(CS_ERR_INVALID, "size and SH degree must match the uploaded template");
   if (ctx->capturing) return ctx->fail(CS_ERR_STATE, "update during capture");
+  if (ctx->n_copies)
+    return ctx->fail(CS_ERR_UNSUPPORTED, "cs_update_template while instances hold their own template copies");
   hipSetDevice(ctx->device);
   const int n = st.n;
   HIP_TRY(hipMemcpyAsync(st.raw_mean, d->mean, 12ull * n, hipMemcpyDeviceToDevice, ctx->stream));
@@ -1055,10 +1123,15 @@ cs_status cs_adam(cs_ctx* ctx, float* param, const float* grad, float* m, float*
   return CS_OK;
 }
 
-cs_status cs_frame_capture(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, const float* pose,
-                           const cs_camera* cam, const cs_lod_params* lod, float* image) {
-  if (!ctx) return CS_ERR_INVALID;
+static cs_status capture_impl(cs_ctx* ctx, bool render_only, int32_t n_inst, const cs_instance* inst,
+                              const float* pose, const cs_camera* cam, const cs_lod_params* lod, float* image) {
   if (ctx->state < kTemplates) return ctx->fail(CS_ERR_STATE, "capture before cs_upload_templates");
+  if (render_only && ctx->state < kSkinned)
+    return ctx->fail(CS_ERR_STATE, "a render-only capture needs an eager cs_skin_instances first");
+  if (render_only) n_inst = ctx->n_inst;
+  if (!render_only && ctx->pose_ring && n_inst != ctx->pose_ring_inst)
+    return ctx->fail(CS_ERR_INVALID, "the pose ring holds frames of " + std::to_string(ctx->pose_ring_inst) +
+                                         " instances");
   if (!ctx->stream) return ctx->fail(CS_ERR_INVALID, "graph capture needs a non-null stream");
   if (ctx->opt.launch_mode == CS_LAUNCH_PER_INSTANCE)
     return ctx->fail(CS_ERR_UNSUPPORTED, "capture uses the batched launches");
@@ -1083,8 +1156,17 @@ cs_status cs_frame_capture(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst,
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   HIP_TRY(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
   ctx->capturing = true;
-  cs_status s = cs_select_lod(ctx, n_inst, inst, pose, cam, lod, nullptr);
-  if (s == CS_OK) s = cs_skin_instances(ctx, n_inst, inst, pose);
+  cs_status s = CS_OK;
+  if (!render_only && ctx->pose_ring) {
+    const hipError_t e = launch_pose_fetch(ctx->pose_ring, ctx->pose_ring_frames, ctx->pose_ring_first,
+                                           (int64_t)n_inst * kJoints * 3, const_cast<float*>(pose), ctx->hdr,
+                                           ctx->stream);
+    if (e != hipSuccess) s = ctx->hip_fail("pose fetch", e);
+  }
+  if (s == CS_OK && !render_only) {
+    s = cs_select_lod(ctx, n_inst, inst, pose, cam, lod, nullptr);
+    if (s == CS_OK) s = cs_skin_instances(ctx, n_inst, inst, pose);
+  }
   if (s == CS_OK) s = cs_render_frame(ctx, cam, image, nullptr);
   ctx->capturing = false;
   hipGraph_t graph = nullptr;
@@ -1098,6 +1180,49 @@ cs_status cs_frame_capture(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst,
   HIP_TRY(hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0));
   ctx->fixed_capacity = true;
   return CS_OK;
+}
+
+cs_status cs_frame_capture(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, const float* pose,
+                           const cs_camera* cam, const cs_lod_params* lod, float* image) {
+  if (!ctx) return CS_ERR_INVALID;
+  return capture_impl(ctx, false, n_inst, inst, pose, cam, lod, image);
+}
+
+cs_status cs_set_pose_ring(cs_ctx* ctx, const float* ring, int32_t n_frames, int32_t n_inst, int64_t first) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (ctx->capturing) return ctx->fail(CS_ERR_STATE, "pose ring set during capture");
+  if (!ring) {
+    ctx->pose_ring = nullptr;
+    ctx->pose_ring_frames = ctx->pose_ring_inst = 0;
+    return CS_OK;
+  }
+  if (n_frames <= 0 || n_inst <= 0 || first < 0) return ctx->fail(CS_ERR_INVALID, "bad pose ring size");
+  if ((uintptr_t)ring % 16) return ctx->fail(CS_ERR_INVALID, "the pose ring must be 16-byte aligned");
+  // the fetch kernel reads the ring directly: it must be device memory, or
+  // pinned host memory mapped at the same address
+  hipPointerAttribute_t attr{};
+  const hipError_t ae = hipPointerGetAttributes(&attr, ring);
+  if (ae != hipSuccess) (void)hipGetLastError();
+  const bool dev_ok = ae == hipSuccess && attr.type == hipMemoryTypeDevice;
+  const bool host_ok = ae == hipSuccess && attr.type == hipMemoryTypeHost && attr.devicePointer == (void*)ring;
+  if (!dev_ok && !host_ok)
+    return ctx->fail(CS_ERR_INVALID, "the pose ring must be device memory or pinned host memory (hipHostMalloc)");
+  ctx->pose_ring = ring;
+  ctx->pose_ring_frames = n_frames;
+  ctx->pose_ring_inst = n_inst;
+  ctx->pose_ring_first = first;
+  // the next captured frame starts at `first`
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipMemsetAsync(&ctx->hdr->pose_frame, 0, 4, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return CS_OK;
+}
+
+cs_status cs_frame_capture_render(cs_ctx* ctx, const cs_camera* cam, float* image) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (ctx->opt.fuse_skin_project)
+    return ctx->fail(CS_ERR_UNSUPPORTED, "a static crowd renders the resident skinned Gaussians: fuse_skin_project = 0");
+  return capture_impl(ctx, true, 0, nullptr, nullptr, cam, nullptr, image);
 }
 
 cs_status cs_frame_launch(cs_ctx* ctx) {
@@ -1168,6 +1293,7 @@ cs_status cs_debug_copy(cs_ctx* ctx, int32_t which, void* host_dst, int64_t offs
     case CS_BUF_PRED: src = ctx->pred; size = ctx->cap_inst * 16 * 4; break;
     case CS_BUF_VIEWS: src = ctx->views; size = ctx->cap_inst * 6 * 8; break;
     case CS_BUF_JOINTS: src = ctx->joints; size = ctx->cap_inst * kJoints * 3 * 4; break;
+    case CS_BUF_OFFSETS: src = ctx->offsets; size = ctx->offsets ? ctx->cap_offsets * 16 : 0; break;
     default: return ctx->fail(CS_ERR_INVALID, "unknown buffer");
   }
   if (!src || offset + bytes > size) return ctx->fail(CS_ERR_INVALID, "copy out of range");
@@ -1234,6 +1360,147 @@ cs_status cs_sort_pairs(cs_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, 
   }
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   if (ctx->state > kSkinned) ctx->state = kSkinned;  // the frame's pair buffers were reused
+  return CS_OK;
+}
+
+namespace {
+uint16_t bf16_bits(float x) {  // nearest even; the inputs are finite
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+}  // namespace
+
+cs_status cs_upload_pose_net(cs_ctx* ctx, const cs_pose_net* net, const float* const* embed) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (ctx->state < kTemplates) return ctx->fail(CS_ERR_STATE, "cs_upload_pose_net before cs_upload_templates");
+  if (ctx->capturing) return ctx->fail(CS_ERR_STATE, "cs_upload_pose_net during capture");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (ctx->state > kLod) ctx->state = kLod;  // the next frame skins with (or without) offsets
+  if (!net) {
+    dfree(ctx, &ctx->pnet);
+    dfree(ctx, &ctx->offsets);
+    ctx->cap_offsets = 0;
+    return CS_OK;
+  }
+  if (!embed) return ctx->fail(CS_ERR_INVALID, "embeddings are NULL");
+  for (size_t t = 0; t < ctx->tpl.size(); ++t)
+    if (!embed[t]) return ctx->fail(CS_ERR_INVALID, "embeddings of template " + std::to_string(t) + " are NULL");
+  PoseNetDev h{};
+  for (int j = 0; j < kPnHidden; ++j) {
+    for (int k = 0; k < kPnEmbed; ++k) h.w1e[j * kPnEmbed + k] = bf16_bits(net->w1[j][k]);
+    for (int k = 0; k < kPnPose; ++k) h.w1p[j * kPnPose + k] = bf16_bits(net->w1[j][kPnEmbed + k]);
+    for (int k = 0; k < kPnHidden; ++k) h.w2[j * kPnHidden + k] = bf16_bits(net->w2[j][k]);
+    h.b1[j] = net->b1[j];
+    h.b2[j] = net->b2[j];
+  }
+  for (int c = 0; c < 3; ++c) {
+    for (int k = 0; k < kPnHidden; ++k) h.w3[c * kPnHidden + k] = bf16_bits(net->w3[c][k]);
+    h.b3[c] = net->b3[c];
+  }
+  CS_TRY(dalloc(ctx, &ctx->pnet, 1, kMemTemplates));
+  HIP_TRY(hipMemcpy(ctx->pnet, &h, sizeof(PoseNetDev), hipMemcpyHostToDevice));
+  std::vector<TemplateDev> devs;
+  for (size_t t = 0; t < ctx->tpl.size(); ++t) {
+    TemplateStore& st = ctx->tpl[t];
+    std::vector<uint16_t> e((size_t)st.n * kPnEmbed);
+    for (size_t i = 0; i < e.size(); ++i) e[i] = bf16_bits(embed[t][i]);
+    CS_TRY(dalloc(ctx, &st.embed, e.size(), kMemTemplates));
+    HIP_TRY(hipMemcpy(st.embed, e.data(), 2 * e.size(), hipMemcpyHostToDevice));
+    st.dev.embed = st.embed;
+    devs.push_back(st.dev);
+  }
+  HIP_TRY(hipMemcpy(ctx->tpl_dev, devs.data(), sizeof(TemplateDev) * devs.size(), hipMemcpyHostToDevice));
+  if (ctx->cap_splats > 0) {
+    CS_TRY(dalloc(ctx, &ctx->offsets, ctx->cap_splats, kMemSplat));
+    ctx->cap_offsets = ctx->cap_splats;
+  }
+  return CS_OK;
+}
+
+cs_status cs_materialise_instances(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (ctx->state < kTemplates) return ctx->fail(CS_ERR_STATE, "cs_materialise_instances before cs_upload_templates");
+  if (ctx->capturing) return ctx->fail(CS_ERR_STATE, "cs_materialise_instances during capture");
+  if (n_inst < 0 || (n_inst > 0 && !inst)) return ctx->fail(CS_ERR_INVALID, "need n_inst >= 0 and an instance array");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  dfree(ctx, &ctx->copies);
+  dfree(ctx, &ctx->tpl_inst);
+  ctx->n_copies = 0;
+  if (ctx->state > kTemplates) ctx->state = kTemplates;  // the next frame selects and skins again
+  if (n_inst == 0) return CS_OK;
+  std::vector<cs_instance> h(n_inst);
+  HIP_TRY(hipMemcpy(h.data(), inst, sizeof(cs_instance) * n_inst, hipMemcpyDeviceToHost));
+  // every column of a copy starts on a 256-byte boundary
+  auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+  auto copy_bytes = [&](const TemplateStore& t) {
+    const size_t n = (size_t)t.n;
+    return up(16 * n) * 3 + up(8 * n) + up(4 * n) + up(16 * n * t.n_sh4);
+  };
+  size_t total = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    if (h[i].tid < 0 || h[i].tid >= (int)ctx->tpl.size())
+      return ctx->fail(CS_ERR_INVALID, "instance " + std::to_string(i) + ": template id out of range");
+    total += copy_bytes(ctx->tpl[h[i].tid]);
+  }
+  CS_TRY(dalloc(ctx, &ctx->copies, total, kMemCopies));
+  std::vector<TemplateDev> devs(n_inst);
+  size_t off = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const TemplateStore& t = ctx->tpl[h[i].tid];
+    const size_t n = (size_t)t.n;
+    TemplateDev d = t.dev;
+    auto take = [&](size_t bytes) {
+      unsigned char* p = ctx->copies + off;
+      off += up(bytes);
+      return p;
+    };
+    float4* mi = (float4*)take(16 * n);
+    float4* sw = (float4*)take(16 * n);
+    float4* ca = (float4*)take(16 * n);
+    float2* cb = (float2*)take(8 * n);
+    float* op = (float*)take(4 * n);
+    float4* sh = (float4*)take(16 * n * t.n_sh4);
+    HIP_TRY(hipMemcpyAsync(mi, t.mean_idx, 16 * n, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(sw, t.skin_w, 16 * n, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(ca, t.cov_a, 16 * n, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(cb, t.cov_b, 8 * n, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(op, t.opacity, 4 * n, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(sh, t.sh, 16 * n * t.n_sh4, hipMemcpyDeviceToDevice, ctx->stream));
+    d.mean_idx = mi;
+    d.skin_w = sw;
+    d.cov_a = ca;
+    d.cov_b = cb;
+    d.opacity = op;
+    d.sh = sh;
+    devs[i] = d;
+  }
+  CS_TRY(dalloc(ctx, &ctx->tpl_inst, (size_t)n_inst, kMemCopies));
+  HIP_TRY(hipMemcpyAsync(ctx->tpl_inst, devs.data(), sizeof(TemplateDev) * n_inst, hipMemcpyHostToDevice,
+                         ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->n_copies = n_inst;
+  return CS_OK;
+}
+
+cs_status cs_memory_report(cs_ctx* ctx, cs_memory_stats* out) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (!out) return ctx->fail(CS_ERR_INVALID, "output is NULL");
+  memset(out, 0, sizeof(*out));
+  out->templates = ctx->mem_bytes[kMemTemplates];
+  out->instance_copies = ctx->mem_bytes[kMemCopies];
+  out->per_instance = ctx->mem_bytes[kMemInstance];
+  out->per_splat = ctx->mem_bytes[kMemSplat];
+  out->per_pair = ctx->mem_bytes[kMemPair];
+  out->workspace = ctx->mem_bytes[kMemWork];
+  for (int c = 0; c < kMemCats; ++c) out->total += ctx->mem_bytes[c];
+  out->peak = ctx->mem_peak;
+  out->cap_instances = ctx->cap_inst;
+  out->cap_splats = ctx->cap_splats;
+  out->cap_pairs = ctx->cap_pairs;
+  out->n_copies = ctx->n_copies;
   return CS_OK;
 }
 

@@ -2,6 +2,8 @@
 // the frame's work list and linear blend skinning (CrowdSplat §2, Fig. 2
 // stage 2: shared canonical templates posed per character by LBS; levels of
 // detail chosen by distance to the camera).
+#include <algorithm>
+
 #include "cs_internal.h"
 #include "skin_math.h"
 
@@ -97,6 +99,37 @@ __global__ void frame_reset_kernel(FrameHdr* hdr, uint32_t* hist, int hist_len, 
     for (int p = 0; p < 8; ++p) hdr->ticket[p] = 0;
   }
   for (int i = t; i < hist_len; i += gridDim.x * blockDim.x) hist[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Pose ring of a captured animation: every replay reads the ring slot its
+// frame number selects (the count lives on the device, so the graph needs no
+// host update per launch). The ring may be pinned host memory: the copy is
+// then the frame's host-to-device pose upload, inside the graph.
+// ---------------------------------------------------------------------------
+__global__ void pose_fetch_kernel(const float4* __restrict__ ring, int n_frames, int64_t first,
+                                  int64_t f4_per_frame, float4* __restrict__ pose, const FrameHdr* hdr) {
+  const int64_t slot = (first + (int64_t)hdr->pose_frame) % n_frames;
+  const float4* src = ring + slot * f4_per_frame;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < f4_per_frame;
+       i += (int64_t)gridDim.x * blockDim.x)
+    pose[i] = src[i];
+}
+
+__global__ void pose_advance_kernel(FrameHdr* hdr) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) hdr->pose_frame += 1;
+}
+
+hipError_t launch_pose_fetch(const float* ring, int n_frames, int64_t first, int64_t floats_per_frame,
+                             float* pose, FrameHdr* hdr, hipStream_t st) {
+  // a pose frame is n_inst x 24 x 3 floats: a multiple of 4 (24 x 3 = 72)
+  const int64_t f4 = floats_per_frame / 4;
+  const int grid = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (f4 + 255) / 256));
+  pose_fetch_kernel<<<grid, 256, 0, st>>>((const float4*)ring, n_frames, first, f4, (float4*)pose, hdr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  pose_advance_kernel<<<1, 64, 0, st>>>(hdr);
+  return hipGetLastError();
 }
 
 hipError_t launch_frame_reset(FrameHdr* hdr, uint32_t* hist, int hist_len, int clear_overflow,
@@ -422,7 +455,7 @@ __global__ __launch_bounds__(kChunkThreads) void skin_kernel(WorkDev w, SkinOut 
   for (int c = chunk_lo + blockIdx.x; c < hi; c += gridDim.x) {
     const Chunk ch = w.chunks[c];
     const cs_instance in = w.inst[ch.inst];
-    const TplCols T = TplCols::of(w.tpl[in.tid]);
+    const TplCols T = TplCols::of(work_template(w, ch.inst, in.tid));
     for (int e = threadIdx.x; e < kJoints * 12; e += kChunkThreads)
       s_bones[e] = w.bones[(size_t)ch.inst * kJoints * 12 + e];
     __syncthreads();
@@ -432,10 +465,16 @@ __global__ __launch_bounds__(kChunkThreads) void skin_kernel(WorkDev w, SkinOut 
     const int n_here = min(kChunk, (int)(w.offset[ch.inst + 1] - base) - ch.g0);
     for (int k = threadIdx.x; k < n_here; k += kChunkThreads) {
       const int g = ch.g0 + k;
-      Posed p;
-      skin_gaussian(s_bones, gload(T.mean_idx, g), gload(T.skin_w, g), gload(T.cov_a, g), gload(T.cov_b, g),
-                    w.skin_mode, Ry, p);
       const size_t s = (size_t)base + g;
+      Posed p;
+      float4 mi = gload(T.mean_idx, g);
+      if (w.offsets) {  // pose-dependent offset of the canonical mean
+        const float4 o = w.offsets[s];
+        mi.x += o.x;
+        mi.y += o.y;
+        mi.z += o.z;
+      }
+      skin_gaussian(s_bones, mi, gload(T.skin_w, g), gload(T.cov_a, g), gload(T.cov_b, g), w.skin_mode, Ry, p);
       out.mu[s] = make_float4(p.mu[0], p.mu[1], p.mu[2], p.cov[0]);
       out.cov[s] = make_float4(p.cov[1], p.cov[2], p.cov[3], p.cov[4]);
       out.cov_zz[s] = p.cov[5];

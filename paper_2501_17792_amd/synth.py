@@ -386,3 +386,147 @@ def perturb_template(t: Template, seed: int = 502, pos_sigma: float = 0.01,
     out.mean += rng.normal(0.0, pos_sigma, size=t.mean.shape).astype(np.float32)
     out.sh[:, 0, :] += (rng.normal(0.0, rgb_sigma, size=(t.n, 3)) / SH_C0).astype(np.float32)
     return out
+
+
+# ----------------------------------------------------------------------------
+# the paper's own crowd set-up (§2 last paragraph, §3 Tab. 1 and Tab. 2)
+# ----------------------------------------------------------------------------
+
+#: Gaussians per character in the paper's three template resolutions (§2, §3).
+PAPER_SIZES = (202_738, 12_661, 3_176)
+#: characters per cell of Tab. 1 / Tab. 2
+PAPER_CHARS = (1, 100, 400, 1_000, 5_000)
+#: the cells Tab. 2 fills: (Gaussians, animated) -> character counts
+TAB2_CELLS = {
+    (202_738, False): (1, 100, 400), (202_738, True): (1, 100),
+    (12_661, False): PAPER_CHARS, (12_661, True): PAPER_CHARS,
+    (3_176, False): PAPER_CHARS, (3_176, True): PAPER_CHARS,
+}
+#: the cells Tab. 1 fills: Gaussians -> character counts
+TAB1_CELLS = {202_738: (1, 100), 12_661: PAPER_CHARS, 3_176: PAPER_CHARS}
+GRID_SPACING = 1.5   # metres between neighbouring grid cells
+N_CLIPS = 15         # looping motion clips driving the crowd (§2: 15 motion sequences)
+CLIP_FRAMES = 60     # frames per loop (2 s at 30 Hz)
+
+
+def make_template_counts(seed: int, level_counts: Sequence[int], sh_degree: int = 3) -> Template:
+    """A template whose LoD levels hold exactly ``level_counts`` Gaussians
+    (importance prefixes of one template of ``level_counts[0]`` Gaussians)."""
+    n = int(level_counts[0])
+    t = make_template(seed, n, sh_degree)
+    t.level_count = np.asarray(level_counts, np.int32)
+    return t
+
+
+def grid_crowd(seed: int, n: int, n_templates: int, spacing: float = GRID_SPACING) -> Crowd:
+    """``n`` characters on a square-ish grid (columns = ceil(sqrt(n)), rows
+    filled front to back), each with a random template and yaw; the first row
+    is at z = 0 and the grid is centred on x = 0. Poses are zero (rest pose);
+    animated crowds take theirs from ``clip_poses``."""
+    rng = np.random.default_rng(seed)
+    cols = max(1, int(math.ceil(math.sqrt(n))))
+    k = np.arange(n)
+    row, col = k // cols, k % cols
+    x = (col - 0.5 * (cols - 1)) * spacing
+    z = row * spacing
+    tid = rng.integers(0, n_templates, size=n).astype(np.int32)
+    yaw = rng.uniform(0.0, 2 * np.pi, size=n).astype(np.float32)
+    pos = np.stack([x, z], axis=1).astype(np.float32)
+    return Crowd(tid=tid, yaw=yaw, pos=pos, pose=np.zeros((n, N_JOINTS, 3), np.float32))
+
+
+def looping_clips(seed: int, n_clips: int = N_CLIPS, frames: int = CLIP_FRAMES,
+                  sigma: float = 0.3) -> np.ndarray:
+    """``n_clips`` seeded looping motions, f32 [n_clips, frames, 24, 3]: every
+    joint angle is a sum of two sinusoids (the loop's fundamental and its
+    second harmonic) with random amplitudes ~ |N(0, sigma)| and phases, so a
+    clip returns to its first pose after ``frames`` frames."""
+    rng = np.random.default_rng(seed)
+    a1 = np.abs(rng.normal(0.0, sigma, size=(n_clips, 1, N_JOINTS, 3)))
+    a2 = np.abs(rng.normal(0.0, 0.5 * sigma, size=(n_clips, 1, N_JOINTS, 3)))
+    p1 = rng.uniform(0.0, 2 * np.pi, size=(n_clips, 1, N_JOINTS, 3))
+    p2 = rng.uniform(0.0, 2 * np.pi, size=(n_clips, 1, N_JOINTS, 3))
+    t = (2 * np.pi * np.arange(frames) / frames)[None, :, None, None]
+    return (a1 * np.sin(t + p1) + a2 * np.sin(2 * t + p2)).astype(np.float32)
+
+
+def clip_assignment(seed: int, n: int, n_clips: int = N_CLIPS, frames: int = CLIP_FRAMES):
+    """Each character's clip and its phase offset (in frames)."""
+    rng = np.random.default_rng(seed)
+    return (rng.integers(0, n_clips, size=n).astype(np.int64),
+            rng.integers(0, frames, size=n).astype(np.int64))
+
+
+def clip_poses(clips: np.ndarray, clip_of: np.ndarray, phase: np.ndarray, frame: int) -> np.ndarray:
+    """The crowd's poses at ``frame`` (f32 [n, 24, 3]): character i plays clip
+    clip_of[i] from frame phase[i], looping."""
+    f = (frame + phase) % clips.shape[1]
+    return np.ascontiguousarray(clips[clip_of, f])
+
+
+def paper_camera(width: int, height: int, first_row_z: float = 0.0) -> Camera:
+    """Static camera three metres in front of the crowd's first row (§2), at
+    eye height, looking down the grid."""
+    return look_at((0.0, 1.7, first_row_z - 3.0), (0.0, 1.0, first_row_z + 25.0), width, height)
+
+
+def scene_tab2(n_gauss: int, n_chars: int, animated: bool, width: int = 1280, height: int = 720,
+               template: Optional[Template] = None, frames: int = CLIP_FRAMES) -> Scene:
+    """One cell of Tab. 1 / Tab. 2: ``n_chars`` duplicates of one SH3 template
+    of ``n_gauss`` Gaussians (seed 600 + its size index) on the grid, static
+    camera 3 m from the first row, 1280x720. Animated cells carry
+    ``frames`` frames of looping clips (``frame_poses``); static cells keep the
+    rest pose."""
+    if template is None:
+        k = PAPER_SIZES.index(n_gauss) if n_gauss in PAPER_SIZES else 3
+        template = make_template(600 + k, n_gauss, 3)
+    crowd = grid_crowd(700 + n_chars, n_chars, 1)
+    poses = None
+    if animated:
+        clips = looping_clips(800)
+        clip_of, phase = clip_assignment(801 + n_chars, n_chars)
+        poses = np.stack([clip_poses(clips, clip_of, phase, f) for f in range(frames)])
+        crowd.pose = poses[0].copy()
+    cam = paper_camera(width, height)
+    return Scene(f"tab2_{n_gauss}x{n_chars}_{'anim' if animated else 'static'}", [template], crowd, cam,
+                 frame_poses=poses)
+
+
+def scene_paper_lod(n_chars: int = 3500, n_templates: int = 14, width: int = 1920, height: int = 1080,
+                    templates=None, frames: int = CLIP_FRAMES, sh_degree: int = 3) -> Scene:
+    """The paper's LoD set-up (§2 last paragraph): 3,500 characters from 14
+    templates on the grid, camera 3 m from the first row, 15 looping motions,
+    three levels of 202,738 / 12,661 / 3,176 Gaussians (importance prefixes)
+    chosen at 5 m and 10 m."""
+    if templates is None:
+        templates = [make_template_counts(900 + t, PAPER_SIZES, sh_degree) for t in range(n_templates)]
+    crowd = grid_crowd(1000, n_chars, len(templates))
+    clips = looping_clips(1001)
+    clip_of, phase = clip_assignment(1002, n_chars)
+    poses = np.stack([clip_poses(clips, clip_of, phase, f) for f in range(frames)]) if frames else None
+    if poses is not None:
+        crowd.pose = poses[0].copy()
+    cam = paper_camera(width, height)
+    return Scene("paper_lod", templates, crowd, cam, lod_thresholds=(5.0, 10.0), frame_poses=poses)
+
+
+# ----------------------------------------------------------------------------
+# pose-dependent offset network (synthetic weights; §2's GaussianAvatar stage)
+# ----------------------------------------------------------------------------
+
+def pose_net_weights(seed: int = 1100, offset_scale: float = 0.01) -> dict:
+    """Synthetic weights of the 112 -> 64 -> 64 -> 3 offset network
+    (float32): He-scaled hidden layers with small random biases, and an
+    output layer scaled so that offsets are about ``offset_scale`` metres."""
+    rng = np.random.default_rng(seed)
+    return dict(w1=rng.normal(0.0, math.sqrt(2.0 / 112), (64, 112)).astype(np.float32),
+                b1=rng.normal(0.0, 0.1, 64).astype(np.float32),
+                w2=rng.normal(0.0, math.sqrt(2.0 / 64), (64, 64)).astype(np.float32),
+                b2=rng.normal(0.0, 0.1, 64).astype(np.float32),
+                w3=rng.normal(0.0, offset_scale / 8.0, (3, 64)).astype(np.float32),
+                b3=rng.normal(0.0, 0.1 * offset_scale, 3).astype(np.float32))
+
+
+def pose_embeddings(seed: int, n: int) -> np.ndarray:
+    """Per-Gaussian embeddings [n, 32] ~ N(0, 1) (float32) of one template."""
+    return np.random.default_rng(seed).normal(0.0, 1.0, (n, 32)).astype(np.float32)

@@ -8,7 +8,7 @@ from oracle import splat as osplat
 from paper_2501_17792_amd import synth
 
 
-def run_gpu(scene, levels_mode, thresholds=(10.0, 25.0), tile=(16, 16), **kw):
+def run_gpu(scene, levels_mode, thresholds=(10.0, 25.0), tile=(16, 16), setup=None, **kw):
     import torch
 
     from paper_2501_17792_amd import crowdsplat as cs
@@ -16,6 +16,8 @@ def run_gpu(scene, levels_mode, thresholds=(10.0, 25.0), tile=(16, 16), **kw):
     r = cs.Renderer(0, tile=tile, **kw)
     r.upload_templates(scene.templates)
     r.set_crowd(scene.crowd)
+    if setup is not None:
+        setup(r)
     img = r.frame(scene.camera, levels_mode, thresholds, stats=True)
     torch.cuda.synchronize()
     return r, img.cpu().numpy()

@@ -48,7 +48,8 @@ def test_struct_layouts_match_the_c_compiler(tmp_path):
     structs = {"cs_options": cs.CsOptions, "cs_template_desc": cs.CsTemplateDesc,
                "cs_camera": cs.CsCamera, "cs_lod_params": cs.CsLodParams,
                "cs_frame_stats": cs.CsFrameStats, "cs_template_grads": cs.CsTemplateGrads,
-               "cs_mlp": cs.CsMlp}
+               "cs_mlp": cs.CsMlp, "cs_memory_stats": cs.CsMemoryStats,
+               "cs_pose_net": cs.CsPoseNet}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "crowdsplat.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')

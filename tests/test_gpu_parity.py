@@ -24,10 +24,13 @@ Tolerances (FP32 kernel vs FP64 oracle on the same FP32 inputs):
     from FP64 by up to ~1e-4 relative, which moves alpha by up to ~6e-4);
   - compositing alone: the device's own records, upcast, composited in FP64,
     with the 1e-4 bands: max-abs 2e-3 outside them;
-  in both, flagged pixels are at most 1e-3 of the image and each differs by
-  at most cmax (2/255 + 1.01e-2) + 2e-3 (one skip flip moves a pixel by at
-  most 2 cmax / 255, one stop flip by at most cmax T <= cmax 1e-2 plus the
-  1e-4 left after it).
+  flagged pixels are at most 1e-3 of the image in the compositing check and
+  at most 1e-2 end to end (its band is ten times wider, so the annuli of
+  pixels near an alpha = 1/255 contour that it flags are about ten times
+  thicker: 67 of 65,536 pixels on the 2,048-Gaussian avatar), and in both
+  each flagged pixel differs by at most cmax (2/255 + 1.01e-2) + 2e-3 (one
+  skip flip moves a pixel by at most 2 cmax / 255, one stop flip by at most
+  cmax T <= cmax 1e-2 plus the 1e-4 left after it).
 """
 import numpy as np
 import pytest
@@ -44,7 +47,7 @@ pytestmark = pytest.mark.gpu
 
 BAND_E2E = 1e-3
 BAND_COMPOSITE = 1e-4
-FRAGILE_MAX = 1e-3
+FRAGILE_MAX = {BAND_E2E: 1e-2, BAND_COMPOSITE: 1e-3}
 
 
 def flag_bound(rgb):
@@ -90,7 +93,7 @@ def check_pixels(img, sp, svals, ranges, cam, tw, th, band, tiles=None, label=""
     worst = float(diff[clean].max()) if clean.any() else 0.0
     assert worst <= 2e-3, f"{label}: max-abs {worst} outside the fragile mask"
     nf = int((frag & sel).sum())
-    assert nf <= FRAGILE_MAX * sel.sum() + 1, f"{label}: {nf} of {int(sel.sum())} pixels fragile"
+    assert nf <= FRAGILE_MAX[band] * sel.sum() + 1, f"{label}: {nf} of {int(sel.sum())} pixels fragile"
     if nf:
         bound = flag_bound(sp["rgb"])
         assert diff[frag & sel].max() <= bound, f"{label}: flagged pixel off by {diff[frag & sel].max()}"
@@ -106,10 +109,13 @@ def _small_c2_scene(n_inst=12, n_gauss=20000, width=480, height=270):
     return synth.Scene("c2slice", templates, crowd, cam, lod_thresholds=(6.0, 11.0))
 
 
-def _compare_frame(scene, mode, thresholds, tile=(16, 16), **kw):
+def _compare_frame(scene, mode, thresholds, tile=(16, 16), setup=None, mean_fn=None, **kw):
+    """The HIP frame against the FP64 oracle, stage by stage. ``setup(r)``
+    runs on the renderer before the frame; ``mean_fn(i, n)`` gives the
+    oracle instance i's canonical means when they depend on the instance."""
     from paper_2501_17792_amd import crowdsplat as cs
 
-    r, img = run_gpu(scene, mode, thresholds, tile=tile, **kw)
+    r, img = run_gpu(scene, mode, thresholds, tile=tile, setup=setup, **kw)
     n_inst = scene.crowd.n
     g = gpu_frame_buffers(r, n_inst)
     cam = scene.camera
@@ -124,7 +130,7 @@ def _compare_frame(scene, mode, thresholds, tile=(16, 16), **kw):
         near = np.min(np.abs(dist[:, None] - np.asarray(thresholds)[None]), axis=1) < 1e-4
         assert np.all((g["level"] == levels) | near)
         levels = g["level"].astype(np.int64)  # decided identically within FP32 ties
-    rec = oframe.frame_records(scene.templates, scene.crowd, cam, levels, tw, th)
+    rec = oframe.frame_records(scene.templates, scene.crowd, cam, levels, tw, th, mean_fn=mean_fn)
     # ---- forward kinematics
     for i in range(n_inst):
         t = scene.templates[int(scene.crowd.tid[i])]
