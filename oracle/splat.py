@@ -273,20 +273,38 @@ def _blend_list(px, py, order, sp, bg, fragile_alpha, fragile_t, tie_impact=None
     return C, T, fragile, n_added
 
 
-def _blend_list_chunked(px, py, order, sp, bg, fragile_alpha, fragile_t, chunk=2048):
+def _alpha_raw(sp, s, cx, cy):
+    """Unclamped opacity o e^power of splats ``s`` at pixel centres (cx, cy)
+    (pixels along axis 0, splats along axis 1)."""
+    dx = cx[:, None] - sp["u"][s][None, :]
+    dy = cy[:, None] - sp["v"][s][None, :]
+    power = -0.5 * (sp["A"][s][None] * dx * dx + 2.0 * sp["B"][s][None] * dx * dy
+                    + sp["C"][s][None] * dy * dy)
+    return sp["opacity"][s][None] * np.exp(np.minimum(0.0, power))
+
+
+def _blend_list_chunked(px, py, order, sp, bg, fragile_alpha, fragile_t, chunk=2048, sp_alt=None):
     """The same front-to-back walk as ``_blend_list`` (without the tie test),
     taken ``chunk`` splats at a time for every still-unfinished pixel at once,
     for lists of millions of splats. Each pixel's transmittance before splat k
     is the running product T0 (1 - a_0) (1 - a_1) ... over the splats it adds,
     formed in the loop's order (np.cumprod multiplies left to right), and its
     colour the running sum of the added c a T, also in the loop's order
-    (np.cumsum), so the results equal the loop's bit for bit."""
+    (np.cumsum), so the results equal the loop's bit for bit.
+
+    ``sp_alt``: a second record set for the same splats (e.g. a float32
+    renderer's records, upcast). The walk follows ``sp``; the fragile bands
+    then widen, splat by splat and pixel by pixel, by how far the two record
+    sets put alpha and T' apart (T' of ``sp_alt`` taken under ``sp``'s
+    decisions): a decision is fragile where the two record sets, or a
+    renderer within the base band of either, could take it differently."""
     P = px.shape[0]
     T = np.ones(P)
     C = np.zeros((3, P))
     done = np.zeros(P, bool)
     fragile = np.zeros(P, bool)
     n_added = np.zeros(P, np.int64)
+    T_alt = np.ones(P)
     cx, cy = px + 0.5, py + 0.5
     order = np.asarray(order, np.int64)
     for c0 in range(0, order.shape[0], chunk):
@@ -314,8 +332,20 @@ def _blend_list_chunked(px, py, order, sp, bg, fragile_alpha, fragile_t, chunk=2
         k = np.arange(K)[None, :]
         evaluated = k <= k_stop[:, None]          # the stopping splat is evaluated, not added
         add = use & (k < k_stop[:, None])
-        fragile[live] |= (evaluated & (np.abs(raw - ALPHA_MIN) <= fragile_alpha * ALPHA_MIN)).any(axis=1)
-        fragile[live] |= (evaluated & use & (np.abs(Tn - T_MIN) <= fragile_t * T_MIN)).any(axis=1)
+        band_a = fragile_alpha * ALPHA_MIN
+        band_t = fragile_t * T_MIN
+        if sp_alt is not None:
+            raw_alt = _alpha_raw(sp_alt, s, cx[live], cy[live])
+            alpha_alt = np.minimum(ALPHA_MAX, raw_alt)
+            fac_alt = np.where(use, 1.0 - alpha_alt, 1.0)
+            Tb_alt = np.cumprod(np.concatenate([T_alt[live, None], fac_alt], axis=1), axis=1)
+            Tn_alt = Tb_alt[:, :-1] * (1.0 - alpha_alt)
+            band_a = band_a + np.abs(raw - raw_alt)
+            band_t = band_t + np.abs(Tn - Tn_alt)
+            T_alt[live] = np.cumprod(np.concatenate([T_alt[live, None], np.where(add, 1.0 - alpha_alt, 1.0)],
+                                                    axis=1), axis=1)[:, -1]
+        fragile[live] |= (evaluated & (np.abs(raw - ALPHA_MIN) <= band_a)).any(axis=1)
+        fragile[live] |= (evaluated & use & (np.abs(Tn - T_MIN) <= band_t)).any(axis=1)
         wgt = np.where(add, alpha * Tb, 0.0)
         for ch in range(3):
             contrib = np.where(add, sp["rgb"][s, ch][None] * wgt, 0.0)
@@ -331,11 +361,12 @@ def _blend_list_chunked(px, py, order, sp, bg, fragile_alpha, fragile_t, chunk=2
 
 def composite_tiled(sp, sorted_vals, ranges, width, height, tw, th, bg,
                     fragile_alpha=1e-4, fragile_t=1e-4, tiles=None, tie_impact=None,
-                    chunked=False):
+                    chunked=False, sp_alt=None):
     """Per-tile front-to-back compositing over each tile's sorted list.
     Returns image [3,H,W], final transmittance [H,W] and the fragile mask.
     ``chunked`` walks the lists with ``_blend_list_chunked`` (same results,
-    for long lists; no tie test)."""
+    for long lists; no tie test), which also takes ``sp_alt`` (a second record
+    set that widens the fragile bands by its distance from ``sp``)."""
     ntx = (width + tw - 1) // tw
     nty = (height + th - 1) // th
     img = np.zeros((3, height, width))
@@ -350,7 +381,8 @@ def composite_tiled(sp, sorted_vals, ranges, width, height, tw, th, bg,
         s0, s1 = ranges[t]
         if chunked:
             C, T, f, _ = _blend_list_chunked(gx.ravel().astype(np.float64), gy.ravel().astype(np.float64),
-                                             sorted_vals[s0:s1], sp, bg, fragile_alpha, fragile_t)
+                                             sorted_vals[s0:s1], sp, bg, fragile_alpha, fragile_t,
+                                             sp_alt=sp_alt)
         else:
             C, T, f, _ = _blend_list(gx.ravel().astype(np.float64), gy.ravel().astype(np.float64),
                                      sorted_vals[s0:s1], sp, bg, fragile_alpha, fragile_t,

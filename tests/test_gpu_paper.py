@@ -41,10 +41,12 @@ def test_tab2_animated_cell_matches_oracle(tab2_template, n_chars):
     # (first + k) % 8, equal to an eager frame of those poses
     poses = torch.from_numpy(sc.frame_poses)
     ring = poses.pin_memory() if n_chars == 1 else poses.cuda()
-    re = cs.Renderer(0, fuse=True)
+    # the eager reference runs on the capturing context's stream: its pose
+    # copy (enqueued on the current stream) is then ordered before its frame
+    stream = torch.cuda.Stream()
+    re = cs.Renderer(0, stream=stream, fuse=True)
     re.upload_templates(sc.templates)
     re.set_crowd(sc.crowd)
-    stream = torch.cuda.Stream()
     rc = cs.Renderer(0, stream=stream, fuse=True)
     rc.upload_templates(sc.templates)
     rc.set_crowd(sc.crowd)

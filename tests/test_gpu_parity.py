@@ -19,17 +19,18 @@ Tolerances (FP32 kernel vs FP64 oracle on the same FP32 inputs):
   order are integer decisions the kernel takes in float32, pinned bit-exactly
   above):
   - end to end: the FP64 oracle's records composited in FP64: max-abs 2e-3
-    outside the pixels where an evaluated splat has alpha within 1e-3
-    (relative) of 1/255 or T' within 1e-3 of 1e-4 (the FP32 records differ
-    from FP64 by up to ~1e-4 relative, which moves alpha by up to ~6e-4);
+    outside the pixels where an evaluated splat has alpha within
+    1e-4 (relative) of 1/255, or T' within 1e-4 of 1e-4, widened splat by
+    splat by how far the FP64 and the device's records put that alpha and
+    T' apart (there the two records may legitimately decide differently);
   - compositing alone: the device's own records, upcast, composited in FP64,
     with the 1e-4 bands: max-abs 2e-3 outside them;
   flagged pixels are at most 1e-3 of the image in the compositing check and
-  at most 1e-2 end to end (its band is ten times wider, so the annuli of
-  pixels near an alpha = 1/255 contour that it flags are about ten times
-  thicker: 67 of 65,536 pixels on the 2,048-Gaussian avatar), and in both
-  each flagged pixel differs by at most cmax (2/255 + 1.01e-2) + 2e-3 (one
-  skip flip moves a pixel by at most 2 cmax / 255, one stop flip by at most
+  5e-3 end to end (its mask holds every pixel where the float32 records
+  could decide differently from FP64; how many there are grows with the
+  splats a pixel evaluates: 0.03% to 0.3% on these scenes), and each flagged
+  pixel differs by at most cmax (2/255 + 1.01e-2) + 2e-3 (one skip flip
+  moves a pixel by at most 2 cmax / 255, one stop flip by at most
   cmax T <= cmax 1e-2 plus the 1e-4 left after it).
 """
 import numpy as np
@@ -45,9 +46,9 @@ from .gpu_common import (check_sorted_pairs, gpu_frame_buffers, rect_fragile, ru
 
 pytestmark = pytest.mark.gpu
 
-BAND_E2E = 1e-3
-BAND_COMPOSITE = 1e-4
-FRAGILE_MAX = {BAND_E2E: 1e-2, BAND_COMPOSITE: 1e-3}
+BAND = 1e-4
+FRAGILE_MAX_COMPOSITE = 1e-3
+FRAGILE_MAX_E2E = 5e-3
 
 
 def flag_bound(rgb):
@@ -73,13 +74,15 @@ def integer_key_oracle(R, cam, tw, th):
     return rect, cnt, vis, sk, sv, osplat.tile_ranges(sk, ntx * nty)
 
 
-def check_pixels(img, sp, svals, ranges, cam, tw, th, band, tiles=None, label=""):
+def check_pixels(img, sp, svals, ranges, cam, tw, th, tiles=None, label="", sp_alt=None,
+                 fragile_max=FRAGILE_MAX_COMPOSITE):
     """FP64 compositing of records ``sp`` over the device's lists against the
-    device image (on ``tiles`` or all). Returns (max-abs outside the mask,
-    flagged pixels, pixels compared)."""
+    device image (on ``tiles`` or all); ``sp_alt`` (the device's records)
+    widens the fragile bands by its distance from ``sp``. Returns (max-abs
+    outside the mask, flagged pixels, pixels compared)."""
     ref, _, frag = osplat.composite_tiled(sp, svals.astype(np.int64), ranges.astype(np.int64), cam.width,
-                                          cam.height, tw, th, cam.bg, band, band, tiles=tiles,
-                                          chunked=True)
+                                          cam.height, tw, th, cam.bg, BAND, BAND, tiles=tiles,
+                                          chunked=True, sp_alt=sp_alt)
     if tiles is None:
         sel = np.ones((cam.height, cam.width), bool)
     else:
@@ -93,7 +96,7 @@ def check_pixels(img, sp, svals, ranges, cam, tw, th, band, tiles=None, label=""
     worst = float(diff[clean].max()) if clean.any() else 0.0
     assert worst <= 2e-3, f"{label}: max-abs {worst} outside the fragile mask"
     nf = int((frag & sel).sum())
-    assert nf <= FRAGILE_MAX[band] * sel.sum() + 1, f"{label}: {nf} of {int(sel.sum())} pixels fragile"
+    assert nf <= fragile_max * sel.sum() + 1, f"{label}: {nf} of {int(sel.sum())} pixels fragile"
     if nf:
         bound = flag_bound(sp["rgb"])
         assert diff[frag & sel].max() <= bound, f"{label}: flagged pixel off by {diff[frag & sel].max()}"
@@ -197,9 +200,10 @@ def _compare_frame(scene, mode, thresholds, tile=(16, 16), setup=None, mean_fn=N
             d = rec["depth"][a]  # order consistent with FP64 depth except near ties
             assert not (d[1:] < d[:-1] * (1 - 2e-6)).any(), f"tile {tt} depth order"
     # ---- pixels over the device's lists: end to end, then compositing alone
-    e2e = check_pixels(img, rec, g["svals"], g["ranges"], cam, tw, th, BAND_E2E, label="end to end")
-    comp = check_pixels(img, device_records(g["rec"]), g["svals"], g["ranges"], cam, tw, th, BAND_COMPOSITE,
-                        label="compositing")
+    drec = device_records(g["rec"])
+    e2e = check_pixels(img, rec, g["svals"], g["ranges"], cam, tw, th, label="end to end", sp_alt=drec,
+                       fragile_max=FRAGILE_MAX_E2E)
+    comp = check_pixels(img, drec, g["svals"], g["ranges"], cam, tw, th, label="compositing")
     return r, img, rec, g, dict(e2e_max_abs=e2e[0], e2e_fragile=e2e[1], composite_max_abs=comp[0],
                                 composite_fragile=comp[1], pixels=e2e[2])
 

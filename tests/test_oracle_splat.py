@@ -337,6 +337,45 @@ def test_chunked_walk_equals_the_loop_bit_for_bit():
             assert np.array_equal(a, b), chunk
 
 
+def test_alternate_records_widen_the_fragile_band():
+    """A second record set widens the fragile bands by its own distance from
+    the first: identical records change nothing; an alpha that the two
+    records put on opposite sides of 1/255, or a T' they put on opposite
+    sides of 1e-4, flags the pixel although the base band alone would not."""
+    px = np.array([0.0])
+    o = 0.5
+    # alpha = (1/255)(1 + 1e-3): outside the 1e-4 band
+    r = math.sqrt(-2 * math.log((1 + 1e-3) / (255 * o)))
+    rec = _records([0.5 + r], [0.5], [1.0], [o], [[1, 1, 1]])
+    base = splat._blend_list_chunked(px, px, [0], rec, np.zeros(3), 1e-4, 1e-4)
+    assert not base[2][0] and base[3][0] == 1
+    same = splat._blend_list_chunked(px, px, [0], rec, np.zeros(3), 1e-4, 1e-4, sp_alt=dict(rec))
+    for a, b in zip(base, same):
+        assert np.array_equal(a, b)
+    alt = dict(rec, opacity=rec["opacity"] * (1 - 2e-3))  # alpha below 1/255 there
+    got = splat._blend_list_chunked(px, px, [0], rec, np.zeros(3), 1e-4, 1e-4, sp_alt=alt)
+    assert got[2][0] and np.array_equal(got[0], base[0]) and got[3][0] == 1  # the walk follows rec
+    alt = dict(rec, opacity=rec["opacity"] * (1 - 5e-4))  # both above: not flagged
+    assert not splat._blend_list_chunked(px, px, [0], rec, np.zeros(3), 1e-4, 1e-4, sp_alt=alt)[2][0]
+    # T': three opaque splats of alpha a with (1 - a)^3 = 1e-4 (1 + 1e-3); the
+    # alternate's last alpha is a little larger, so its T' falls below 1e-4
+    a = 1 - (1e-4 * (1 + 1e-3)) ** (1 / 3)
+    rec = _records([0.5] * 3, [0.5] * 3, [1.0] * 3, [a] * 3, [[1, 0, 0], [0, 1, 0], [0, 0, 1]])
+    base = splat._blend_list_chunked(px, px, [0, 1, 2], rec, np.zeros(3), 1e-4, 1e-4)
+    assert not base[2][0] and base[3][0] == 3
+    ops = rec["opacity"].copy()
+    ops[2] = 1 - (1 - a) * (1 - 2e-3)
+    got = splat._blend_list_chunked(px, px, [0, 1, 2], rec, np.zeros(3), 1e-4, 1e-4,
+                                    sp_alt=dict(rec, opacity=ops))
+    assert got[2][0] and got[3][0] == 3
+    # the first splat's alternate moves T before the third: flagged the same way
+    ops = rec["opacity"].copy()
+    ops[0] = 1 - (1 - a) * (1 - 2e-3)
+    got = splat._blend_list_chunked(px, px, [0, 1, 2], rec, np.zeros(3), 1e-4, 1e-4,
+                                    sp_alt=dict(rec, opacity=ops), chunk=1)
+    assert got[2][0]
+
+
 def test_float32_footprint_rect():
     """Where the pixel bounds are not near an integer, the float32 rect equals
     the FP64 footprint's rect; a bound whose float32 subtraction rounds onto
