@@ -283,7 +283,8 @@ def _alpha_raw(sp, s, cx, cy):
     return sp["opacity"][s][None] * np.exp(np.minimum(0.0, power))
 
 
-def _blend_list_chunked(px, py, order, sp, bg, fragile_alpha, fragile_t, chunk=2048, sp_alt=None):
+def _blend_list_chunked(px, py, order, sp, bg, fragile_alpha, fragile_t, chunk=2048, sp_alt=None,
+                        power_ulps=0.0):
     """The same front-to-back walk as ``_blend_list`` (without the tie test),
     taken ``chunk`` splats at a time for every still-unfinished pixel at once,
     for lists of millions of splats. Each pixel's transmittance before splat k
@@ -297,7 +298,13 @@ def _blend_list_chunked(px, py, order, sp, bg, fragile_alpha, fragile_t, chunk=2
     then widen, splat by splat and pixel by pixel, by how far the two record
     sets put alpha and T' apart (T' of ``sp_alt`` taken under ``sp``'s
     decisions): a decision is fragile where the two record sets, or a
-    renderer within the base band of either, could take it differently."""
+    renderer within the base band of either, could take it differently.
+
+    ``power_ulps``: the alpha band also widens by that many float32 units in
+    the last place (2^-24, relative) of the exponent's terms,
+    (A dx^2 + 2 |B dx dy| + C dy^2) / 2: a float32 evaluation of the exponent
+    errs by about that much, which is far more than the base band for thin
+    splats whose terms cancel."""
     P = px.shape[0]
     T = np.ones(P)
     C = np.zeros((3, P))
@@ -334,6 +341,10 @@ def _blend_list_chunked(px, py, order, sp, bg, fragile_alpha, fragile_t, chunk=2
         add = use & (k < k_stop[:, None])
         band_a = fragile_alpha * ALPHA_MIN
         band_t = fragile_t * T_MIN
+        if power_ulps:
+            mag = 0.5 * (sp["A"][s][None] * dx * dx + 2.0 * np.abs(sp["B"][s][None] * dx * dy)
+                         + sp["C"][s][None] * dy * dy)
+            band_a = band_a + ALPHA_MIN * power_ulps * 2.0 ** -24 * mag
         if sp_alt is not None:
             raw_alt = _alpha_raw(sp_alt, s, cx[live], cy[live])
             alpha_alt = np.minimum(ALPHA_MAX, raw_alt)
@@ -361,12 +372,13 @@ def _blend_list_chunked(px, py, order, sp, bg, fragile_alpha, fragile_t, chunk=2
 
 def composite_tiled(sp, sorted_vals, ranges, width, height, tw, th, bg,
                     fragile_alpha=1e-4, fragile_t=1e-4, tiles=None, tie_impact=None,
-                    chunked=False, sp_alt=None):
+                    chunked=False, sp_alt=None, power_ulps=0.0):
     """Per-tile front-to-back compositing over each tile's sorted list.
     Returns image [3,H,W], final transmittance [H,W] and the fragile mask.
     ``chunked`` walks the lists with ``_blend_list_chunked`` (same results,
     for long lists; no tie test), which also takes ``sp_alt`` (a second record
-    set that widens the fragile bands by its distance from ``sp``)."""
+    set that widens the fragile bands by its distance from ``sp``) and
+    ``power_ulps`` (a float32 error allowance on the exponent)."""
     ntx = (width + tw - 1) // tw
     nty = (height + th - 1) // th
     img = np.zeros((3, height, width))
@@ -382,7 +394,7 @@ def composite_tiled(sp, sorted_vals, ranges, width, height, tw, th, bg,
         if chunked:
             C, T, f, _ = _blend_list_chunked(gx.ravel().astype(np.float64), gy.ravel().astype(np.float64),
                                              sorted_vals[s0:s1], sp, bg, fragile_alpha, fragile_t,
-                                             sp_alt=sp_alt)
+                                             sp_alt=sp_alt, power_ulps=power_ulps)
         else:
             C, T, f, _ = _blend_list(gx.ravel().astype(np.float64), gy.ravel().astype(np.float64),
                                      sorted_vals[s0:s1], sp, bg, fragile_alpha, fragile_t,

@@ -376,6 +376,28 @@ def test_alternate_records_widen_the_fragile_band():
     assert got[2][0]
 
 
+def test_exponent_ulps_widen_the_alpha_band_of_thin_splats():
+    """The float32 allowance on the exponent scales with its terms: a thin
+    splat whose terms cancel (A = C = 1000, B = -999.9 along the diagonal)
+    is flagged at alpha (1 + 2e-5) / 255, a round one at the same alpha is
+    not (its terms are about as large as the exponent itself)."""
+    px = np.array([0.0])
+    o = 0.5
+    target = math.log((1 + 2e-5) / (255 * o))  # power giving that alpha
+    # thin: power = -0.1 d^2 at dx = dy = d
+    d = math.sqrt(-target / 0.1)
+    thin = dict(u=np.array([0.5 - d]), v=np.array([0.5 - d]), A=np.array([1000.0]),
+                B=np.array([-999.9]), C=np.array([1000.0]), opacity=np.array([o]),
+                rgb=np.ones((1, 3)))
+    r = math.sqrt(-2 * target)
+    round_ = _records([0.5 + r], [0.5], [1.0], [o], [[1, 1, 1]])
+    for rec, flagged in [(thin, True), (round_, False)]:
+        got = splat._blend_list_chunked(px, px, [0], rec, np.zeros(3), 1e-5, 1e-4, power_ulps=8.0)
+        assert got[3][0] == 1  # added: alpha is above 1/255
+        assert bool(got[2][0]) == flagged
+        assert not splat._blend_list_chunked(px, px, [0], rec, np.zeros(3), 1e-5, 1e-4)[2][0]
+
+
 def test_float32_footprint_rect():
     """Where the pixel bounds are not near an integer, the float32 rect equals
     the FP64 footprint's rect; a bound whose float32 subtraction rounds onto
