@@ -370,7 +370,7 @@ cs_status cs_upload_pose_net(cs_ctx* ctx, const cs_pose_net* net, const float* c
 cs_status cs_materialise_instances(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst);
 
 /* Device bytes the context holds now, by what they hold (every device
- * allocation of the context is counted in exactly one field; the 12.6 MiB
+ * allocation of the context is counted in exactly one field; the 16.0 MiB
  * scratch of cs_sort_pairs_noalloc is per process and not counted).
  * Capacity-sized buffers are counted at their current capacity. */
 typedef struct cs_memory_stats {
@@ -472,6 +472,22 @@ cs_status cs_stage_times(cs_ctx* ctx, float* ms, int32_t n);
  * the same onesweep kernels that order the frame's tile pairs. DEVICE buffers;
  * keys/vals are sorted in place (the context's pair buffers are the scratch). */
 cs_status cs_sort_pairs(cs_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): cs_sort_pairs
+ * without any allocation. The same stable LSD radix sort (the reduce-then-
+ * scan passes, digit width 11) of DEVICE keys/vals in place by the low
+ * key_bits bits, n <= CS_NOALLOC_MAX_PAIRS (larger n gives CS_ERR_CAPACITY
+ * and enqueues nothing). Its scratch is a fixed 16.0 MiB array per device
+ * (held by every device the library runs on until the process ends), not
+ * the context's buffers, so it leaves the context's frame untouched. Fully
+ * asynchronous on the context's stream (no synchronisation; capturable):
+ * the caller keeps keys/vals alive until the stream has run it. Every call
+ * on one device shares that device's scratch, which keeps the last call's
+ * contents: calls that overlap on one device (several streams or contexts
+ * at once) race and give wrong results. Errors as cs_sort_pairs. */
+#define CS_NOALLOC_MAX_PAIRS (1 << 20)
+cs_status cs_sort_pairs_noalloc(cs_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits);
 
 #ifdef __cplusplus
 }

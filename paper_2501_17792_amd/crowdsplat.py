@@ -22,6 +22,7 @@ CS_MEM_HOST, CS_MEM_DEVICE = 0, 1
 CS_SKIN_FULL, CS_SKIN_MEANS_ONLY = 0, 1
 CS_LAUNCH_BATCHED, CS_LAUNCH_PER_INSTANCE = 0, 1
 CS_SORT_TILE_BUCKET, CS_SORT_ONESWEEP, CS_SORT_REDUCE_SCAN = 0, 1, 2
+CS_NOALLOC_MAX_PAIRS = 1 << 20
 CS_SORT_RANKS_CHECKED, CS_SORT_RANKS_BALLOT = 0, 1
 CS_LOD_FULL, CS_LOD_FIXED, CS_LOD_LEARNED, CS_LOD_CONSTANT = 0, 1, 2, 3
 CS_MLP_NPARAM, CS_MLP_NBF16 = 7312, 7168
@@ -41,7 +42,7 @@ EXPORTS = ["cs_create", "cs_destroy", "cs_last_error", "cs_version", "cs_upload_
            "cs_sort_pairs", "cs_stage_times", "cs_lod_features", "cs_mlp_predict", "cs_mlp_sync",
            "cs_mlp_train_step", "cs_render_views", "cs_view_psnr", "cs_update_template", "cs_fit_loss",
            "cs_adam", "cs_materialise_instances", "cs_memory_report",
-           "cs_frame_capture_render", "cs_set_pose_ring", "cs_upload_pose_net"]
+           "cs_frame_capture_render", "cs_set_pose_ring", "cs_upload_pose_net", "cs_sort_pairs_noalloc"]
 STAGES = ["lod", "fk", "skin", "project", "scan", "emit", "sort", "ranges", "blend", "segsort", "offsets"]
 
 
@@ -161,6 +162,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cs_frame_poll": (i32, [P, ctypes.POINTER(CsFrameStats)]),
         "cs_debug_copy": (i32, [P, i32, P, i64, i64]),
         "cs_sort_pairs": (i32, [P, P, P, i64, i32]),
+        "cs_sort_pairs_noalloc": (i32, [P, P, P, i64, i32]),
         "cs_materialise_instances": (i32, [P, i32, P]),
         "cs_memory_report": (i32, [P, ctypes.POINTER(CsMemoryStats)]),
         "cs_stage_times": (i32, [P, ctypes.POINTER(ctypes.c_float), i32]),
@@ -499,3 +501,10 @@ class Renderer:
     def sort_pairs(self, keys, vals, key_bits: int):
         self._check(self.lib.cs_sort_pairs(self.ctx, keys.data_ptr(), vals.data_ptr(),
                                            keys.numel(), key_bits))
+
+    def sort_pairs_noalloc(self, keys, vals, key_bits: int, n=None):
+        """The same sort with the library's fixed per-device scratch
+        (asynchronous on the context's stream; n <= CS_NOALLOC_MAX_PAIRS)."""
+        self._hold(keys, vals)
+        self._check(self.lib.cs_sort_pairs_noalloc(self.ctx, keys.data_ptr(), vals.data_ptr(),
+                                                   keys.numel() if n is None else n, key_bits))

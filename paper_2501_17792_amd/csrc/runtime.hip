@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -399,6 +400,48 @@ const char* cs_version(void) { return "crowdsplat-mi355x 0.1 (gfx950)"; }
 
 const char* cs_last_error(const cs_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
 
+// ---------------------------------------------------------------------------
+// Scratch of cs_sort_pairs_noalloc: one fixed array per device, so that entry
+// point never allocates. Host code never uses the array's name as an
+// address: cs_create resolves the device address once per device (with that
+// device current) and the sort takes it from noalloc_scratch[device].
+// Layout (256-byte aligned parts): n | reduce-then-scan digit counts | block
+// sums of their scan | ping-pong keys | ping-pong values.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kNoAllocDevices = 64;
+constexpr size_t kNaAlign = 256;
+constexpr size_t na_round(size_t b) { return (b + kNaAlign - 1) / kNaAlign * kNaAlign; }
+constexpr size_t kNaCountsOff = kNaAlign;  // after n
+constexpr size_t kNaSumsOff = kNaCountsOff + na_round((size_t)kRtsBlocks * kSortBins * 4);
+constexpr size_t kNaKeysOff = kNaSumsOff + na_round(((size_t)kRtsBlocks * kSortBins / 4096 + 2) * 4);
+constexpr size_t kNaValsOff = kNaKeysOff + na_round((size_t)CS_NOALLOC_MAX_PAIRS * 8);
+constexpr size_t kNaBytes = kNaValsOff + na_round((size_t)CS_NOALLOC_MAX_PAIRS * 4);
+
+std::mutex noalloc_mu;
+unsigned char* noalloc_scratch[kNoAllocDevices] = {};
+
+__global__ void store_u32_kernel(uint32_t* p, uint32_t v) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
+}
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+// once per device, with ctx->device current
+static cs_status noalloc_scratch_init(cs_ctx* ctx) {
+  if (ctx->device >= kNoAllocDevices)
+    return ctx->fail(CS_ERR_UNSUPPORTED, "device ordinal beyond the scratch table");
+  std::lock_guard<std::mutex> lock(noalloc_mu);
+  if (noalloc_scratch[ctx->device]) return CS_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return ctx->hip_fail("hipGetSymbolAddress(scratch)", e);
+  if (!ptr) return ctx->fail(CS_ERR_DEVICE, "scratch has no device address");
+  noalloc_scratch[ctx->device] = (unsigned char*)ptr;
+  return CS_OK;
+}
+
 cs_status cs_create(int32_t device, void* stream, const cs_options* opt, cs_ctx** out) {
   if (!out) return CS_ERR_INVALID;
   *out = nullptr;
@@ -424,7 +467,8 @@ cs_status cs_create(int32_t device, void* stream, const cs_options* opt, cs_ctx*
   ctx->device = device;
   ctx->stream = (hipStream_t)stream;
   ctx->opt = o;
-  cs_status s = dalloc(ctx, &ctx->hdr, 1);
+  cs_status s = noalloc_scratch_init(ctx);
+  if (s == CS_OK) s = dalloc(ctx, &ctx->hdr, 1);
   if (s == CS_OK) s = dalloc(ctx, &ctx->hist, kHistLen);
   if (s == CS_OK) s = dalloc(ctx, &ctx->tile_order, kMaxFrameTiles);
   if (s == CS_OK) s = dalloc(ctx, &ctx->bk_counts, (size_t)kBucketMaxTiles * kBucketBlocks);
@@ -1360,6 +1404,43 @@ cs_status cs_sort_pairs(cs_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, 
   }
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   if (ctx->state > kSkinned) ctx->state = kSkinned;  // the frame's pair buffers were reused
+  return CS_OK;
+}
+
+cs_status cs_sort_pairs_noalloc(cs_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (!keys || !vals || n < 0 || key_bits < 1 || key_bits > kMaxPasses * kSortBits)
+    return ctx->fail(CS_ERR_INVALID, "bad sort arguments");
+  if (n > CS_NOALLOC_MAX_PAIRS)
+    return ctx->fail(CS_ERR_CAPACITY, std::to_string(n) + " pairs exceed the " +
+                                          std::to_string((long long)CS_NOALLOC_MAX_PAIRS) +
+                                          "-pair scratch of cs_sort_pairs_noalloc");
+  if (n == 0) return CS_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  unsigned char* base = noalloc_scratch[ctx->device];
+  if (!base) return ctx->fail(CS_ERR_STATE, "scratch not set up on this device");
+  uint32_t* n_dev = (uint32_t*)base;
+  uint32_t* counts = (uint32_t*)(base + kNaCountsOff);
+  uint32_t* sums = (uint32_t*)(base + kNaSumsOff);
+  uint64_t* kbuf = (uint64_t*)(base + kNaKeysOff);
+  uint32_t* vbuf = (uint32_t*)(base + kNaValsOff);
+  // the count is a kernel argument (no host buffer for a captured copy to
+  // read later); the digit counts are written whole by every pass
+  store_u32_kernel<<<1, 64, 0, ctx->stream>>>(n_dev, (uint32_t)n);
+  HIP_TRY(hipGetLastError());
+  const int passes = (key_bits + kSortBits - 1) / kSortBits;
+  uint64_t* ks[2] = {keys, kbuf};
+  uint32_t* vs[2] = {vals, vbuf};
+  int src = 0;
+  for (int p = 0; p < passes; ++p) {
+    HIP_TRY(launch_rts_pass(ks[src], vs[src], ks[1 - src], vs[1 - src], counts, sums, nullptr,
+                            (uint32_t)CS_NOALLOC_MAX_PAIRS, n_dev, p, kRtsBlocks, ctx->stream));
+    src = 1 - src;
+  }
+  if (src == 1) {
+    HIP_TRY(hipMemcpyAsync(keys, kbuf, 8ull * n, hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(hipMemcpyAsync(vals, vbuf, 4ull * n, hipMemcpyDeviceToDevice, ctx->stream));
+  }
   return CS_OK;
 }
 
