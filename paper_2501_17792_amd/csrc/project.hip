@@ -17,36 +17,38 @@ struct RegPlanes {
 // constant so that every SH plane load of a Gaussian is issued at once). The
 // SH planes and the opacity are loaded first, so that their latency overlaps
 // skinning and the EWA projection instead of sitting in front of the colour.
-template <int DEG>
-__device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOut& skinned, int fused,
+template <int DEG, bool FUSED>
+__device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOut& skinned,
                                                   const CamDev& cam, const SplatOut& out, const TplCols& T,
-                                                  const float* s_bones, const float Ry[9], const Chunk ch,
-                                                  uint32_t base, int n_here) {
+                                                  const float* s_bones, const float Ry[9], const float c0[3],
+                                                  const Chunk ch, uint32_t base, int n_here) {
   uint32_t vis = 0;
   for (int k = threadIdx.x; k < n_here; k += kChunkThreads) {
     const int g = ch.g0 + k;
     const size_t s = (size_t)base + g;
-    Posed p;
     // geometry first: the loads complete in issue order, so the wait for
     // them does not include the SH planes issued after them
     float4 mi = gload(T.mean_idx, g);
     const float4 wt = gload(T.skin_w, g);
-    const float4 ca = fused ? gload(T.cov_a, g) : make_float4(0.f, 0.f, 0.f, 0.f);
-    const float2 cb = fused ? gload(T.cov_b, g) : make_float2(0.f, 0.f);
+    const float4 ca = FUSED ? gload(T.cov_a, g) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float2 cb = FUSED ? gload(T.cov_b, g) : make_float2(0.f, 0.f);
     constexpr int N4 = (3 * (DEG + 1) * (DEG + 1) + 3) / 4;
     float4 shv[N4];
 #pragma unroll
     for (int j = 0; j < N4; ++j) shv[j] = gload(T.sh, (size_t)j * T.n + g);
     const float op = gload(T.opacity, g);
-    if (fused) {
+    SplatRec r;
+    if constexpr (FUSED) {  // s_bones and Ry are in the camera frame here
       if (w.offsets) {  // pose-dependent offset of the canonical mean
         const float4 o = w.offsets[s];
         mi.x += o.x;
         mi.y += o.y;
         mi.z += o.z;
       }
-      skin_gaussian(s_bones, mi, wt, ca, cb, w.skin_mode, Ry, p);
+      const float S[6] = {ca.x, ca.y, ca.z, ca.w, cb.x, cb.y};
+      project_fused<DEG>(s_bones, mi, wt, S, w.skin_mode, Ry, c0, op, RegPlanes<N4>{shv}, cam, r);
     } else {
+      Posed p;
       const float4 m = skinned.mu[s];
       const float4 cv = skinned.cov[s];
       p.mu[0] = m.x; p.mu[1] = m.y; p.mu[2] = m.z;
@@ -62,9 +64,8 @@ __device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOu
         p.L[3] = M[4]; p.L[4] = M[5]; p.L[5] = M[6];
         p.L[6] = M[8]; p.L[7] = M[9]; p.L[8] = M[10];
       }
+      project_gaussian<DEG>(p, op, RegPlanes<N4>{shv}, 1, cam, r);
     }
-    SplatRec r;
-    project_gaussian<DEG>(p, op, RegPlanes<N4>{shv}, 1, cam, r);
     if (w.crop && r.count) {  // view mode: keep the tiles inside the instance's window
       const int4 cw = w.crop[ch.inst];
       const int x0 = max((int)(r.rect & 0xffu), cw.x), y0 = max((int)((r.rect >> 8) & 0xffu), cw.y);
@@ -91,34 +92,56 @@ __device__ __forceinline__ uint32_t project_chunk(const WorkDev& w, const SkinOu
 }
 
 // One block iteration per chunk (one instance, up to kChunk Gaussians). The
-// bone matrices are staged in LDS: in fused mode the Gaussian is skinned
-// here (bit-identical to the skin kernel); otherwise the posed mean and
-// covariance are read back and only the blended linear part is rebuilt for
-// the colour direction.
-__global__ __launch_bounds__(kChunkThreads) __attribute__((amdgpu_waves_per_eu(3))) void project_kernel(WorkDev w, SkinOut skinned,
-                                                                int fused, CamDev cam, SplatOut out,
-                                                                int chunk_lo, int chunk_hi) {
+// bone matrices are staged in LDS: in fused mode rotated into the camera
+// frame (R_c B_j) and the Gaussian is skinned and projected there; otherwise
+// the posed mean and covariance are read back and only the blended linear
+// part is rebuilt for the colour direction.
+template <bool FUSED>
+__global__ __launch_bounds__(kChunkThreads) __attribute__((amdgpu_waves_per_eu(3))) void project_kernel(
+    WorkDev w, SkinOut skinned, CamDev cam, SplatOut out, int chunk_lo, int chunk_hi) {
   __shared__ float s_bones[kJoints * 12];
   __shared__ uint32_t s_vis;
   const int hi = chunk_hi >= 0 ? chunk_hi : (int)w.hdr->n_chunks;
+  const float* R = cam.R;
+  float c0[3];  // R_c eye
+#pragma unroll
+  for (int r = 0; r < 3; ++r) c0[r] = fmaf(R[3 * r], cam.eye[0], fmaf(R[3 * r + 1], cam.eye[1], R[3 * r + 2] * cam.eye[2]));
   for (int c = chunk_lo + blockIdx.x; c < hi; c += gridDim.x) {
     const Chunk ch = w.chunks[c];
     const cs_instance in = w.inst[ch.inst];
     const TplCols T = TplCols::of(work_template(w, ch.inst, in.tid));
-    for (int e = threadIdx.x; e < kJoints * 12; e += kChunkThreads)
-      s_bones[e] = w.bones[(size_t)ch.inst * kJoints * 12 + e];
+    const float* B = w.bones + (size_t)ch.inst * kJoints * 12;
+    if constexpr (FUSED) {  // (R_c B_j)[row][col] = sum_k R_c[row][k] B_j[k][col]
+      for (int e = threadIdx.x; e < kJoints * 12; e += kChunkThreads) {
+        const int j = e / 12, row = (e % 12) / 4, col = e % 4;
+        const float* b = B + j * 12 + col;
+        s_bones[e] = fmaf(R[3 * row], b[0], fmaf(R[3 * row + 1], b[4], R[3 * row + 2] * b[8]));
+      }
+    } else {
+      for (int e = threadIdx.x; e < kJoints * 12; e += kChunkThreads) s_bones[e] = B[e];
+    }
     if (threadIdx.x == 0) s_vis = 0;
     __syncthreads();
     float Ry[9];
     yaw_rotation(in.yaw, Ry);
+    if constexpr (FUSED) {  // R_c R_y: the linear part when only means are skinned
+      float RcRy[9];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          RcRy[3 * r + k] = fmaf(R[3 * r], Ry[k], fmaf(R[3 * r + 1], Ry[3 + k], R[3 * r + 2] * Ry[6 + k]));
+#pragma unroll
+      for (int e = 0; e < 9; ++e) Ry[e] = RcRy[e];
+    }
     const uint32_t base = w.offset[ch.inst];
     const int n_here = min(kChunk, (int)(w.offset[ch.inst + 1] - base) - ch.g0);
     uint32_t vis;
     switch (T.sh_degree) {
-      case 0: vis = project_chunk<0>(w, skinned, fused, cam, out, T, s_bones, Ry, ch, base, n_here); break;
-      case 1: vis = project_chunk<1>(w, skinned, fused, cam, out, T, s_bones, Ry, ch, base, n_here); break;
-      case 2: vis = project_chunk<2>(w, skinned, fused, cam, out, T, s_bones, Ry, ch, base, n_here); break;
-      default: vis = project_chunk<3>(w, skinned, fused, cam, out, T, s_bones, Ry, ch, base, n_here); break;
+      case 0: vis = project_chunk<0, FUSED>(w, skinned, cam, out, T, s_bones, Ry, c0, ch, base, n_here); break;
+      case 1: vis = project_chunk<1, FUSED>(w, skinned, cam, out, T, s_bones, Ry, c0, ch, base, n_here); break;
+      case 2: vis = project_chunk<2, FUSED>(w, skinned, cam, out, T, s_bones, Ry, c0, ch, base, n_here); break;
+      default: vis = project_chunk<3, FUSED>(w, skinned, cam, out, T, s_bones, Ry, c0, ch, base, n_here); break;
     }
     atomicAdd(&s_vis, vis);
     __syncthreads();
@@ -130,7 +153,10 @@ hipError_t launch_project(WorkDev w, SkinOut skinned, int fused, CamDev cam, Spl
                           uint32_t /*max_splats*/, int chunk_lo, int chunk_hi, int grid,
                           hipStream_t st) {
   if (grid <= 0) return hipSuccess;
-  project_kernel<<<grid, kChunkThreads, 0, st>>>(w, skinned, fused, cam, out, chunk_lo, chunk_hi);
+  if (fused)
+    project_kernel<true><<<grid, kChunkThreads, 0, st>>>(w, skinned, cam, out, chunk_lo, chunk_hi);
+  else
+    project_kernel<false><<<grid, kChunkThreads, 0, st>>>(w, skinned, cam, out, chunk_lo, chunk_hi);
   return hipGetLastError();
 }
 

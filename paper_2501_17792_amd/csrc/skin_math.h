@@ -2,8 +2,9 @@
 // skinning, EWA projection, SH colour and the opacity-aware footprint.
 // Every function is written with explicit fmaf() and compiled with
 // -ffp-contract=off so that a value computed in two kernels (for example the
-// skinned mean in the skin kernel and again in the fused projection) has the
-// same bits.
+// skinned mean in the skin kernel and again in the backward) has the same
+// bits. The fused skinning + projection works in the camera frame and rounds
+// differently from the separate stages (same mathematics).
 #pragma once
 
 #include "cs_internal.h"
@@ -140,7 +141,58 @@ struct SplatRec {
   uint32_t count;
 };
 
-// EWA projection + colour + footprint of one posed Gaussian. count = 0 means culled.
+// Screen-space tail shared by both projection forms: the opacity-aware
+// footprint, the tile rect (tile sides are powers of two: 8, 16 or 32) and
+// the colour along the unnormalised canonical-frame view direction (d0, d1,
+// d2). a, b, c: the 2D covariance with the low-pass added; det = ac - b^2.
+template <int DEG, class Planes>
+__device__ __forceinline__ void finish_splat(float u, float v, float a, float b, float c, float det, float tz,
+                                             float opacity, float d0, float d1, float d2, Planes sh_planes,
+                                             int sh_stride, const CamDev& cam, SplatRec& out) {
+  if (!(det > 0.f)) return;
+  if (opacity < (1.f / 255.f)) return;
+  // k = 2 ln(255 o) (1 + 1e-4); hardware log2 and sqrt (1 ulp each) sit far
+  // inside the 1e-4 relative and 0.01 px margins of the box
+  const float k = (2.f * 0.6931471805599453f) * __builtin_amdgcn_logf(fmaxf(255.f * opacity, 1.f)) * (1.f + 1e-4f);
+  const float rx = __builtin_amdgcn_sqrtf(k * a) + 0.01f;
+  const float ry = __builtin_amdgcn_sqrtf(k * c) + 0.01f;
+  const float fx0 = floorf(u - rx), fx1 = floorf(u + rx);
+  const float fy0 = floorf(v - ry), fy1 = floorf(v + ry);
+  if (fx1 < 0.f || fx0 > (float)(cam.W - 1) || fy1 < 0.f || fy0 > (float)(cam.H - 1)) return;
+  const int px0 = (int)fmaxf(fx0, 0.f), px1 = (int)fminf(fx1, (float)(cam.W - 1));
+  const int py0 = (int)fmaxf(fy0, 0.f), py1 = (int)fminf(fy1, (float)(cam.H - 1));
+  const int sx = __builtin_ctz((unsigned)cam.tw), sy = __builtin_ctz((unsigned)cam.th);
+  const int x0 = px0 >> sx, x1 = px1 >> sx, y0 = py0 >> sy, y1 = py1 >> sy;
+  const float inv = __builtin_amdgcn_rsqf(fmaf(d0, d0, fmaf(d1, d1, d2 * d2)));
+  d0 *= inv; d1 *= inv; d2 *= inv;
+  float rgb[3];
+  sh_colour<DEG>(sh_planes, sh_stride, d0, d1, d2, rgb);
+  out.r0 = make_float4(u, v, rx, ry);
+  const float idet = __builtin_amdgcn_rcpf(det);  // det >= 0.09 (the 0.3 px^2 low-pass)
+  out.r1 = make_float4(c * idet, -b * idet, a * idet, opacity);
+  out.r2 = make_float4(rgb[0], rgb[1], rgb[2], tz);
+  out.rect = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) | ((uint32_t)y1 << 24);
+  out.count = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+}
+
+// 2D covariance (a, b, c, low-pass added) of a Gaussian with 3D covariance S
+// (xx xy xz yy yz zz) under the 2x3 map with rows T0, T1.
+__device__ __forceinline__ void ewa_2d(const float T0[3], const float T1[3], const float S[6], float& a, float& b,
+                                       float& c) {
+  const float P00 = fmaf(T0[0], S[0], fmaf(T0[1], S[1], T0[2] * S[2]));
+  const float P01 = fmaf(T0[0], S[1], fmaf(T0[1], S[3], T0[2] * S[4]));
+  const float P02 = fmaf(T0[0], S[2], fmaf(T0[1], S[4], T0[2] * S[5]));
+  const float P10 = fmaf(T1[0], S[0], fmaf(T1[1], S[1], T1[2] * S[2]));
+  const float P11 = fmaf(T1[0], S[1], fmaf(T1[1], S[3], T1[2] * S[4]));
+  const float P12 = fmaf(T1[0], S[2], fmaf(T1[1], S[4], T1[2] * S[5]));
+  a = fmaf(P00, T0[0], fmaf(P01, T0[1], P02 * T0[2])) + 0.3f;
+  b = fmaf(P00, T1[0], fmaf(P01, T1[1], P02 * T1[2]));
+  c = fmaf(P10, T1[0], fmaf(P11, T1[1], P12 * T1[2])) + 0.3f;
+}
+
+// EWA projection + colour + footprint of one posed Gaussian (world-frame
+// posed mean and covariance, as the separate skinning stage writes them).
+// count = 0 means culled.
 template <int DEG, class Planes>
 __device__ __forceinline__ void project_gaussian(const Posed& p, float opacity, Planes sh_planes, int sh_stride,
                                                  const CamDev& cam, SplatRec& out) {
@@ -168,45 +220,70 @@ __device__ __forceinline__ void project_gaussian(const Posed& p, float opacity, 
     T0[k] = fmaf(j00, R[k], j02 * R[6 + k]);
     T1[k] = fmaf(j11, R[3 + k], j12 * R[6 + k]);
   }
-  const float* S = p.cov;  // xx xy xz yy yz zz
-  const float P00 = fmaf(T0[0], S[0], fmaf(T0[1], S[1], T0[2] * S[2]));
-  const float P01 = fmaf(T0[0], S[1], fmaf(T0[1], S[3], T0[2] * S[4]));
-  const float P02 = fmaf(T0[0], S[2], fmaf(T0[1], S[4], T0[2] * S[5]));
-  const float P10 = fmaf(T1[0], S[0], fmaf(T1[1], S[1], T1[2] * S[2]));
-  const float P11 = fmaf(T1[0], S[1], fmaf(T1[1], S[3], T1[2] * S[4]));
-  const float P12 = fmaf(T1[0], S[2], fmaf(T1[1], S[4], T1[2] * S[5]));
-  const float a = fmaf(P00, T0[0], fmaf(P01, T0[1], P02 * T0[2])) + 0.3f;
-  const float b = fmaf(P00, T1[0], fmaf(P01, T1[1], P02 * T1[2]));
-  const float c = fmaf(P10, T1[0], fmaf(P11, T1[1], P12 * T1[2])) + 0.3f;
+  float a, b, c;
+  ewa_2d(T0, T1, p.cov, a, b, c);
   const float det = a * c - b * b;
-  if (!(det > 0.f)) return;
-  if (opacity < (1.f / 255.f)) return;
-  // k = 2 ln(255 o) (1 + 1e-4); hardware log2 and sqrt (1 ulp each) sit far
-  // inside the 1e-4 relative and 0.01 px margins of the box
-  const float k = (2.f * 0.6931471805599453f) * __builtin_amdgcn_logf(fmaxf(255.f * opacity, 1.f)) * (1.f + 1e-4f);
-  const float rx = __builtin_amdgcn_sqrtf(k * a) + 0.01f;
-  const float ry = __builtin_amdgcn_sqrtf(k * c) + 0.01f;
-  const float fx0 = floorf(u - rx), fx1 = floorf(u + rx);
-  const float fy0 = floorf(v - ry), fy1 = floorf(v + ry);
-  if (fx1 < 0.f || fx0 > (float)(cam.W - 1) || fy1 < 0.f || fy0 > (float)(cam.H - 1)) return;
-  const int px0 = (int)fmaxf(fx0, 0.f), px1 = (int)fminf(fx1, (float)(cam.W - 1));
-  const int py0 = (int)fmaxf(fy0, 0.f), py1 = (int)fminf(fy1, (float)(cam.H - 1));
-  const int x0 = px0 / cam.tw, x1 = px1 / cam.tw, y0 = py0 / cam.th, y1 = py1 / cam.th;
   // colour: view direction in the canonical frame, L^T (mu' - eye)
   const float* L = p.L;
-  float d0 = fmaf(L[0], dx, fmaf(L[3], dy, L[6] * dz));
-  float d1 = fmaf(L[1], dx, fmaf(L[4], dy, L[7] * dz));
-  float d2 = fmaf(L[2], dx, fmaf(L[5], dy, L[8] * dz));
-  const float inv = __builtin_amdgcn_rsqf(fmaf(d0, d0, fmaf(d1, d1, d2 * d2)));
-  d0 *= inv; d1 *= inv; d2 *= inv;
-  float rgb[3];
-  sh_colour<DEG>(sh_planes, sh_stride, d0, d1, d2, rgb);
-  out.r0 = make_float4(u, v, rx, ry);
-  const float idet = __builtin_amdgcn_rcpf(det);  // det >= 0.09 (the 0.3 px^2 low-pass)
-  out.r1 = make_float4(c * idet, -b * idet, a * idet, opacity);
-  out.r2 = make_float4(rgb[0], rgb[1], rgb[2], tz);
-  out.rect = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) | ((uint32_t)y1 << 24);
-  out.count = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+  const float d0 = fmaf(L[0], dx, fmaf(L[3], dy, L[6] * dz));
+  const float d1 = fmaf(L[1], dx, fmaf(L[4], dy, L[7] * dz));
+  const float d2 = fmaf(L[2], dx, fmaf(L[5], dy, L[8] * dz));
+  finish_splat<DEG>(u, v, a, b, c, det, tz, opacity, d0, d1, d2, sh_planes, sh_stride, cam, out);
+}
+
+// Skinning and projection in one step, in the camera frame. The bone
+// matrices are given pre-rotated into the camera frame (Bc_j = R_c B_j), so
+// the blended matrix is Mc = R_c M: the camera-space mean is
+// t = Mc [mu; 1] - R_c eye (c0 = R_c eye), the EWA map J R_c L is J Lc with
+// Lc = Mc[:, :3] (R_c R_y when only means are skinned: RcL), Sigma2D comes
+// from the canonical covariance S directly (Sigma' = L S L^T is never
+// formed), and the canonical-frame view direction L^T (mu' - eye) is Lc^T t
+// (R_c is orthonormal). Same mathematics as skin_gaussian + project_gaussian,
+// rounded differently.
+template <int DEG, class Planes>
+__device__ __forceinline__ void project_fused(const float* __restrict__ bones_cam, float4 mean_idx, float4 w,
+                                              const float S[6], int means_only, const float RcL[9],
+                                              const float c0[3], float opacity, Planes sh_planes,
+                                              const CamDev& cam, SplatRec& out) {
+  out.count = 0u;
+  out.rect = 0u;
+  out.r0 = out.r1 = out.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float M[12];
+  blend_bones(bones_cam, __float_as_uint(mean_idx.w), w, M);
+  const float x = mean_idx.x, y = mean_idx.y, z = mean_idx.z;
+  const float tx = fmaf(M[0], x, fmaf(M[1], y, fmaf(M[2], z, M[3]))) - c0[0];
+  const float ty = fmaf(M[4], x, fmaf(M[5], y, fmaf(M[6], z, M[7]))) - c0[1];
+  const float tz = fmaf(M[8], x, fmaf(M[9], y, fmaf(M[10], z, M[11]))) - c0[2];
+  if (!(tz > cam.near_plane)) return;
+  const float itz = __builtin_amdgcn_rcpf(tz);
+  const float xn = tx * itz, yn = ty * itz;
+  if (fabsf(xn) > cam.lim_x || fabsf(yn) > cam.lim_y) return;
+  const float u = fmaf(cam.fx, xn, cam.cx);
+  const float v = fmaf(cam.fy, yn, cam.cy);
+  const float j00 = cam.fx * itz, j11 = cam.fy * itz;
+  const float j02 = -(cam.fx * xn) * itz, j12 = -(cam.fy * yn) * itz;
+  float L[9];
+  if (means_only) {
+#pragma unroll
+    for (int e = 0; e < 9; ++e) L[e] = RcL[e];
+  } else {
+    L[0] = M[0]; L[1] = M[1]; L[2] = M[2];
+    L[3] = M[4]; L[4] = M[5]; L[5] = M[6];
+    L[6] = M[8]; L[7] = M[9]; L[8] = M[10];
+  }
+  float T0[3], T1[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    T0[k] = fmaf(j00, L[k], j02 * L[6 + k]);
+    T1[k] = fmaf(j11, L[3 + k], j12 * L[6 + k]);
+  }
+  float a, b, c;
+  ewa_2d(T0, T1, S, a, b, c);
+  const float det = a * c - b * b;
+  const float d0 = fmaf(L[0], tx, fmaf(L[3], ty, L[6] * tz));
+  const float d1 = fmaf(L[1], tx, fmaf(L[4], ty, L[7] * tz));
+  const float d2 = fmaf(L[2], tx, fmaf(L[5], ty, L[8] * tz));
+  finish_splat<DEG>(u, v, a, b, c, det, tz, opacity, d0, d1, d2, sh_planes, 1, cam, out);
 }
 
 }  // namespace cs

@@ -243,16 +243,29 @@ def test_c2_slice_other_tiles(tile):
 
 def test_tile_shape_launch_and_fusion_invariance():
     """The image is bit-identical across tile shapes, per-instance vs batched
-    launches, and skin+project fused vs separate."""
+    launches and sort forms, with skinning separate and with skinning fused
+    into projection (which works in the camera frame and rounds differently:
+    it is held to the oracle on its own, below and in the Tab. 2 cells)."""
     from paper_2501_17792_amd import crowdsplat as cs
 
     sc = _small_c2_scene(n_inst=8)
-    _, ref = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds)
-    for kw in [dict(tile=(8, 8)), dict(tile=(32, 32)), dict(tile=(8, 32)),
-               dict(launch_mode=cs.CS_LAUNCH_PER_INSTANCE), dict(fuse=True),
-               dict(sort_algo=cs.CS_SORT_ONESWEEP), dict(sort_algo=cs.CS_SORT_REDUCE_SCAN)]:
-        _, img = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, **kw)
-        assert np.array_equal(img, ref), kw
+    for fuse in (False, True):
+        _, ref = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, fuse=fuse)
+        for kw in [dict(tile=(8, 8)), dict(tile=(32, 32)), dict(tile=(8, 32)),
+                   dict(launch_mode=cs.CS_LAUNCH_PER_INSTANCE),
+                   dict(sort_algo=cs.CS_SORT_ONESWEEP), dict(sort_algo=cs.CS_SORT_REDUCE_SCAN)]:
+            _, img = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, fuse=fuse, **kw)
+            assert np.array_equal(img, ref), (fuse, kw)
+
+
+def test_c2_slice_fused_matches_oracle():
+    """Skinning fused into projection (camera-frame algebra) against the FP64
+    oracle, records to pixels."""
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    sc = _small_c2_scene()
+    _, img, rec, g, info = _compare_frame(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, fuse=True)
+    print("C2 slice fused", info)
 
 
 def test_determinism_and_graph_replay():
