@@ -22,7 +22,15 @@ Definitions (readings listed in the design doc):
   (the view box widened to whole tiles), rendered alone on black, clamped to
   60 dB;
 * selection: the coarsest level whose prediction is at least floor + margin,
-  else level 0.
+  else level 0;
+* frame-budget selection (the floor read as one for the whole frame against
+  the full-detail frame): a level's predicted PSNR over the instance's label
+  window (16x16 tiles, w x h pixels) gives its predicted squared error summed
+  over the window's RGB values, SSE_l = 3 w h 10^(-PSNR_l / 10) (PSNR clamped
+  to [0, 60], none at level 0); instances take the level minimising
+  n_l + lambda SSE_l (ties to the finer level) for the smallest lambda on a
+  30-step bisection of log2(lambda) in [-40, 60] whose summed SSE stays within
+  3 W H 10^(-floor / 10).
 """
 from __future__ import annotations
 
@@ -207,3 +215,69 @@ def select_levels(pred, floor=40.0, margin=1.0) -> np.ndarray:
     ok[:, 0] = True
     L = pred.shape[1]
     return (L - 1) - np.argmax(ok[:, ::-1], axis=1)
+
+
+# ----------------------------------------------------------------------------
+# frame-budget selection
+# ----------------------------------------------------------------------------
+
+LABEL_TILE = 16
+BUDGET_ITERS = 30
+BUDGET_T_LO, BUDGET_T_HI = -40.0, 60.0
+
+
+def label_window_px(clip, width, height) -> float:
+    """Pixels of the label window: the clipped view box widened to whole
+    16x16 tiles (the tiles the labels were rendered with), clipped to the
+    image; 0 if the box is empty."""
+    win = crop_window(clip, LABEL_TILE, LABEL_TILE, width, height)
+    if win is None:
+        return 0.0
+    return float((win[2] - win[0]) * (win[3] - win[1]))
+
+
+def level_sse(pred, window_px, top) -> np.ndarray:
+    """[n, 5] predicted squared error of each level summed over the window's
+    RGB values: the PSNR over the window is 10 log10(1 / MSE) with MSE the
+    mean over its 3 w h values, so SSE = 3 w h 10^(-PSNR / 10); level 0 and
+    levels above the template's top have none."""
+    pred = np.clip(np.asarray(pred, np.float64)[:, :N_LEVELS], 0.0, PSNR_CAP)
+    win = np.asarray(window_px, np.float64)
+    sse = 3.0 * win[:, None] * 10.0 ** (-pred / 10.0)
+    lv = np.arange(N_LEVELS)[None, :]
+    sse[(lv == 0) | (lv > np.asarray(top)[:, None])] = 0.0
+    return sse
+
+
+def frame_budget(width, height, floor_db) -> float:
+    """Summed squared error over the frame's 3 W H values at PSNR = floor."""
+    return 3.0 * width * height * 10.0 ** (-floor_db / 10.0)
+
+
+def choose_levels(sse, counts, top, lam) -> np.ndarray:
+    """argmin over l <= top of counts[l] + lam sse[l], the first (finest) of
+    equal costs."""
+    cost = np.asarray(counts, np.float64) + lam * sse
+    lv = np.arange(N_LEVELS)[None, :]
+    cost = np.where(lv <= np.asarray(top)[:, None], cost, np.inf)
+    return np.argmin(cost, axis=1)
+
+
+def select_budget(sse, counts, top, budget, valid=None):
+    """Levels and t = log2(lambda) of the frame-budget rule: bisection of t
+    in [-40, 60] for 30 steps keeping the upper end feasible (summed SSE
+    within the budget); the levels are those at the upper end. ``valid``
+    marks instances with a template (others draw nothing: level 0, no SSE)."""
+    n = sse.shape[0]
+    valid = np.ones(n, bool) if valid is None else np.asarray(valid, bool)
+    lo, hi = BUDGET_T_LO, BUDGET_T_HI
+    for _ in range(BUDGET_ITERS):
+        mid = 0.5 * (lo + hi)
+        lv = choose_levels(sse, counts, top, 2.0 ** mid)
+        total = sse[np.arange(n), lv][valid].sum()
+        if total <= budget:
+            hi = mid
+        else:
+            lo = mid
+    lv = choose_levels(sse, counts, top, 2.0 ** hi)
+    return np.where(valid, lv, 0), hi

@@ -147,3 +147,96 @@ def test_pad_radius_closed_form():
     ref = 1.5 + 3.0 * math.exp(-0.375)  # the third: neither the farthest (2.0) nor the widest (e^0)
     assert ref > max(0.5 + 3.0 * math.exp(0.0), 2.0 + 3.0 * math.exp(-4.0))
     assert math.isclose(lod.pad_radius(t), ref, rel_tol=1e-12)
+
+
+# ---------------------------------------------------------------- frame budget
+
+def test_level_sse_is_the_windows_squared_error_and_adds_up_to_the_frame_psnr():
+    """SSE from a label equals the summed squared difference over the label
+    window, and for instances whose windows do not overlap the frame's PSNR
+    against full detail is 10 log10(3 W H / sum of their SSE)."""
+    rng = np.random.default_rng(3)
+    W, H = 96, 64
+    frame_full = np.zeros((3, H, W))
+    frame_lod = np.zeros((3, H, W))
+    sse_sum = 0.0
+    for (x0, y0, x1, y1), noise in [((0, 0, 32, 32), 0.01), ((48, 16, 96, 64), 0.003)]:
+        full = rng.uniform(0, 1, (3, H, W))
+        coarse = full + rng.normal(0, noise, full.shape)
+        lab = lod.psnr_labels([full, coarse], (x0, y0, x1, y1))
+        pred = np.array([[lab[0], lab[1], 0, 0, 0]])
+        s = lod.level_sse(pred, [(x1 - x0) * (y1 - y0)], np.array([1]))
+        want = ((coarse - full)[:, y0:y1, x0:x1] ** 2).sum()
+        np.testing.assert_allclose(s[0, 1], want, rtol=1e-12)
+        assert s[0, 0] == 0 and np.all(s[0, 2:] == 0)  # level 0 and levels above the top
+        frame_full[:, y0:y1, x0:x1] = full[:, y0:y1, x0:x1]
+        frame_lod[:, y0:y1, x0:x1] = coarse[:, y0:y1, x0:x1]
+        sse_sum += s[0, 1]
+    psnr = -10 * math.log10(np.mean((frame_lod - frame_full) ** 2))
+    np.testing.assert_allclose(psnr, 10 * math.log10(3 * W * H / sse_sum), rtol=1e-12)
+    np.testing.assert_allclose(lod.frame_budget(W, H, psnr), sse_sum, rtol=1e-12)
+
+
+def test_label_window_is_whole_16_tiles():
+    assert lod.label_window_px(np.array([5.0, 3.0, 17.5, 30.0]), 100, 40) == 32 * 32
+    assert lod.label_window_px(np.array([90.0, 30.0, 100.0, 40.0]), 100, 40) == (100 - 80) * (40 - 16)
+    assert lod.label_window_px(None, 100, 40) == 0.0
+
+
+def _budget_case(seed, n=4, levels=3):
+    rng = np.random.default_rng(seed)
+    counts = np.tile(np.array([1000.0, 500.0, 250.0, 125.0, 62.5])[None], (n, 1))
+    pred = np.zeros((n, 5))
+    pred[:, 0] = 60.0
+    pred[:, 1:] = np.sort(rng.uniform(15, 60, (n, 4)), axis=1)[:, ::-1]
+    win = rng.uniform(50, 5000, n)
+    top = np.full(n, levels - 1)
+    return lod.level_sse(pred, win, top), counts, top
+
+
+def test_budget_selection_against_brute_force():
+    """On tiny crowds (4 instances, 3 levels, every one of the 81 selections
+    enumerated): the result keeps the summed SSE within the budget, no
+    selection with at most its SSE draws fewer Gaussians (it minimises
+    Gaussians + lambda SSE), and half a bisection step lower lambda is
+    infeasible (the smallest such lambda was found)."""
+    import itertools
+
+    for seed in range(20):
+        sse, counts, top = _budget_case(seed)
+        n = sse.shape[0]
+        allsel = np.array(list(itertools.product(range(3), repeat=n)))
+        tot_sse = sse[np.arange(n)[None], allsel].sum(1)
+        tot_n = counts[np.arange(n)[None], allsel].sum(1)
+        for budget in np.quantile(tot_sse, [0.05, 0.3, 0.6, 0.95]):
+            lv, t = lod.select_budget(sse, counts, top, budget)
+            s_res = sse[np.arange(n), lv].sum()
+            n_res = counts[np.arange(n), lv].sum()
+            assert s_res <= budget
+            assert np.all(tot_n[tot_sse <= s_res] >= n_res)
+            step = (lod.BUDGET_T_HI - lod.BUDGET_T_LO) / 2 ** lod.BUDGET_ITERS
+            lower = lod.choose_levels(sse, counts, top, 2.0 ** (t - step))
+            assert t <= lod.BUDGET_T_LO + step or sse[np.arange(n), lower].sum() > budget
+
+
+def test_budget_selection_limits_and_order():
+    sse, counts, top = _budget_case(7, n=6, levels=5)
+    lv, _ = lod.select_budget(sse, counts, top, np.inf)
+    assert np.all(lv == 4)  # no limit: the coarsest level everywhere
+    lv, _ = lod.select_budget(sse, counts, top, 0.0)
+    assert np.all(lv == 0)  # no error allowed: full detail
+    # an instance with no window (nothing on screen) costs nothing at any level
+    sse2 = sse.copy()
+    sse2[0] = 0.0
+    lv, _ = lod.select_budget(sse2, counts, top, 0.0)
+    assert lv[0] == 4 and np.all(lv[1:] == 0)
+    # two equal instances except a 100x larger window: the small one coarsens first
+    pred = np.array([[60.0, 45.0, 40.0, 35.0, 30.0]] * 2)
+    s = lod.level_sse(pred, [100.0, 10000.0], np.array([4, 4]))
+    c = np.tile(np.array([1000.0, 500.0, 250.0, 125.0, 62.5])[None], (2, 1))
+    for budget in np.geomspace(1e-3, 1e2, 30):
+        lv, _ = lod.select_budget(s, c, np.array([4, 4]), budget)
+        assert lv[0] >= lv[1]
+    # instances without a template draw level 0 and add nothing
+    lv, _ = lod.select_budget(sse, counts, top, 0.0, valid=np.array([False] + [True] * 5))
+    assert lv[0] == 0
