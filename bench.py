@@ -34,16 +34,24 @@ sys.path.insert(0, ROOT)
 METRIC = "FPS @3,500 avatars 1080p, learned-LoD vs fixed-LoD at ≥40 dB PSNR vs full"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per frame of each stage in the learned-LoD frame at the tile shapes the autotuner picks (16x16,
-# 32x16), from two rocprofv3 --pmc runs each (FETCH_SIZE scaled by 2.000 and WRITE_SIZE by 1.000, the
-# factors a plain 1 GiB copy gives), summarised in profiles/crowd3500_1080p_learned_lod_kernels.md and
-# profiles/crowd3500_1080p_learned_lod_32x16_kernels.md. They hold only for the kernel sources they were
-# taken on (digest below) and that workload; otherwise the bench reports null.
-MEASURED_TRAFFIC = {"digest": "1e520ee49f2114a8", "lod": "learned",
-                    "bytes": {(16, 16): {"sort": 21.70e9, "segsort": 5.69e9, "emit": 8.67e9,
-                                         "project_fused": 18.95e9, "blend": 2.51e9},
-                              (32, 16): {"sort": 20.75e9, "segsort": 4.96e9, "emit": 8.00e9,
-                                         "project_fused": 18.96e9, "blend": 2.83e9}}}
+N_CU = 256
+CLOCK_HZ = 2.4e9
+# Non-packed FP32 issue peak: 256 CUs x 4 SIMDs x 16 lanes per clock (a wave64
+# VALU instruction occupies its SIMD 4 clocks; packed FP32 is disabled in this
+# build): 39.3e12 lane-instructions/s, 78.6 TFLOP/s counting an FMA as two.
+ISSUE_PEAK = N_CU * 64 * CLOCK_HZ
+FP32_PEAK_TFLOPS = 2 * ISSUE_PEAK / 1e12
+# FP32 operations of one live compositing evaluation (FMA = 2): dx, dy, the
+# quadratic form and its clamp, o e^power and the 0.99 clamp, 1 - alpha,
+# T' = T (1 - alpha), alpha T and three colour FMAs.
+BLEND_FLOPS_PER_EVAL = 24
+
+# Counter measurements of the headline frame (learned LoD, frame budget) for the kernel sources they were
+# taken on (digest) and one tile shape: HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE
+# scaled by 2.000 and WRITE_SIZE by 1.000, the factors a plain 1 GiB copy gives) and VALU lane-instructions
+# per item (SQ_INSTS_VALU x 64 / items: splats for the projection, pairs for the sort), summarised under
+# profiles/. Other sources or workloads report null.
+MEASURED = {"digest": None, "lod": "learned_budget", "tile": None, "traffic": {}, "valu_per_item": {}}
 
 
 def kernel_digest():
@@ -94,41 +102,116 @@ def unique_template_gaussians(scene, levels):
     return tot
 
 
-def cpu_baseline(scene, levels, n_splats, n_pairs, budget_s=25.0):
-    """The FP64 oracle on the host: time skin+project per instance-Gaussian on a
-    seeded sample of instances (stratified by level), and binning + sort +
-    compositing per tile pair on that sample rendered alone; extrapolate to the
-    frame's counts."""
+_CPU_CTX = {}
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cpu_cores():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))  # the host share of one GPU
+
+
+def _cpu_worker(pick):
+    """One oracle worker: records (skin + project) of its instances, then
+    binning + sort + compositing of those records; each timed."""
     from oracle import frame as oframe
     from oracle import splat as osplat
     from paper_2501_17792_amd import synth
 
-    rng = np.random.default_rng(7)
-    pick = []
-    present = sorted(set(int(l) for l in levels))
-    for j, lvl in enumerate(present):
-        k = 1 if j == 0 else (12 if j == len(present) - 1 else 3)
-        cand = np.nonzero(levels == lvl)[0]
-        pick += list(rng.choice(cand, size=min(k, cand.size), replace=False))
-    pick = np.array(sorted(pick))
-    sub = synth.Crowd(tid=scene.crowd.tid[pick], yaw=scene.crowd.yaw[pick],
-                      pos=scene.crowd.pos[pick], pose=scene.crowd.pose[pick])
+    scene, levels = _CPU_CTX["scene"], _CPU_CTX["levels"]
+    pick = np.asarray(pick)
+    sub = synth.Crowd(tid=scene.crowd.tid[pick], yaw=scene.crowd.yaw[pick], pos=scene.crowd.pos[pick],
+                      pose=scene.crowd.pose[pick])
     t0 = time.perf_counter()
     rec = oframe.frame_records(scene.templates, sub, scene.camera, levels[pick], 16, 16)
     t_rec = time.perf_counter() - t0
-    g = int(rec["offsets"][-1])
     t0 = time.perf_counter()
     out = osplat.render_records(rec, scene.camera, 16, 16)
-    t_ras = time.perf_counter() - t0
-    p = int(len(out["keys"]))
-    per_g = t_rec / max(g, 1)
-    per_p = t_ras / max(p, 1)
-    frame_s = per_g * n_splats + per_p * n_pairs
-    return {"value": 1.0 / frame_s, "unit": "FPS", "cores": 1, "kind": "oracle",
-            "sample": (f"FP64 oracle, frame 0: {len(pick)} seeded instances ({g} instance-Gaussians, "
-                       f"{p} tile pairs) timed ({t_rec:.1f} s skin+project, {t_ras:.1f} s bin+sort+blend), "
-                       f"extrapolated per Gaussian and per pair to the frame's {n_splats} Gaussians "
-                       f"and {n_pairs} pairs = {frame_s:.0f} s/frame; single-threaded numpy")}
+    return int(rec["offsets"][-1]), int(len(out["keys"])), t_rec, time.perf_counter() - t0
+
+
+def oracle_levels(scene, host_net, margin, floor=40.0):
+    """The frame-budget LoD selection of the whole crowd by the FP64 oracle
+    (features, network, windows, bisection)."""
+    from oracle import lod as olod
+
+    cam = scene.camera
+    n = scene.crowd.n
+    feats = np.zeros((n, 32))
+    win = np.zeros(n)
+    counts = np.zeros((n, 5))
+    top = np.zeros(n, np.int64)
+    pads = [olod.pad_radius(t) for t in scene.templates]
+    for i in range(n):
+        tid = int(scene.crowd.tid[i])
+        t = scene.templates[tid]
+        yaw, px, pz = float(scene.crowd.yaw[i]), float(scene.crowd.pos[i, 0]), float(scene.crowd.pos[i, 1])
+        feats[i] = olod.instance_features(t, tid, 14, scene.crowd.pose[i], yaw, px, pz, pads[tid], cam,
+                                          host_net["pca_mean"], host_net["pca_basis"])
+        joints = olod.posed_joints(t, scene.crowd.pose[i], yaw, px, pz)
+        _, clip = olod.view_box(joints, pads[tid], cam)
+        win[i] = olod.label_window_px(clip, cam.width, cam.height)
+        lc = np.asarray(t.level_count, np.float64)
+        counts[i, :len(lc)] = lc
+        top[i] = min(len(lc), 5) - 1
+    pred, _ = olod.mlp_forward(host_net, feats, rounded=True)
+    sse = olod.level_sse(pred, win, top)
+    levels, _ = olod.select_budget(sse, counts, top, olod.frame_budget(cam.width, cam.height, floor + margin))
+    return levels, counts
+
+
+def cpu_baseline(scene, host_net, margin, per_worker=21):
+    """The FP64 oracle on the host's cores (at most 16: the host share of one
+    GPU), timed on a bounded sample of the headline frame (frame 0): LoD
+    selection of all instances, then skin + project and binning + sort +
+    compositing of a seeded sample of instances (per_worker per core) in a
+    process pool, each phase's wall time extrapolated per Gaussian and per
+    tile pair to the oracle's own frame. Runs before the GPU is touched (the
+    pool forks)."""
+    import multiprocessing as mp
+
+    cores = _cpu_cores()
+    t0 = time.perf_counter()
+    levels, counts = oracle_levels(scene, host_net, margin)
+    t_lod = time.perf_counter() - t0
+    n_splats = int(counts[np.arange(scene.crowd.n), levels].sum())
+    rng = np.random.default_rng(7)
+    pick = np.sort(rng.choice(scene.crowd.n, size=min(scene.crowd.n, per_worker * cores), replace=False))
+    chunks = [pick[k::cores].tolist() for k in range(cores)]
+    _CPU_CTX.update(scene=scene, levels=levels)
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_cpu_worker, chunks)
+        wall = time.perf_counter() - t0
+    g = sum(r[0] for r in res)
+    p = sum(r[1] for r in res)
+    t_rec, t_ras = sum(r[2] for r in res), sum(r[3] for r in res)
+    # the sample's pairs per Gaussian stand in for the frame's (instances rendered alone)
+    n_pairs = int(round(n_splats * p / max(g, 1)))
+    frame_s = t_lod + wall * n_splats / max(g, 1)
+    return {"value": round(1.0 / frame_s, 8), "unit": "FPS", "cores": cores, "kind": "oracle",
+            "cpu_model": _cpu_model(),
+            "sample": (f"FP64 oracle, frame 0 of the learned-LoD (frame budget) crowd: LoD selection of all "
+                       f"{scene.crowd.n} instances ({t_lod:.1f} s, one core), then {len(pick)} seeded instances "
+                       f"({g} instance-Gaussians, {p} tile pairs) split over a pool of {cores} processes: "
+                       f"{wall:.1f} s wall ({t_rec:.1f} CPU-s skin+project, {t_ras:.1f} CPU-s bin+sort+blend); "
+                       f"extrapolated per Gaussian to the oracle frame's {n_splats} Gaussians "
+                       f"(~{n_pairs} pairs) = {frame_s:.0f} s/frame"),
+            "oracle_levels_hist": np.bincount(levels, minlength=5).tolist()}
 
 
 def load_net(path):
@@ -141,17 +224,19 @@ def load_net(path):
 
 def time_mode(torch, rs, scene, poses_all, imgs, streams, lod, steps, warmup):
     """Size the frame eagerly, reserve capacity, capture the whole frame as a
-    graph and time ``steps`` replays (pose copy + graph launch per step).
-    With several contexts (one stream each) consecutive frames alternate
-    between them, so that many frames are in flight; every frame still runs
-    the whole path into its own image."""
+    graph and time ``steps`` replays. Every replay starts with its pose
+    upload inside the graph, from a pose ring on the device: with n contexts
+    (one stream each) consecutive frames alternate between them, so context i
+    holds the ring of frames i, i + n, i + 2n, ... and many frames are in
+    flight; every frame still runs the whole path into its own image."""
     from paper_2501_17792_amd import crowdsplat as cs
 
     mode, thr, mlp_ptr, margin = lod
     r, img, stream = rs[0], imgs[0], streams[0]
+    n_frames = poses_all.shape[0]
     max_pairs = max_splats = 0
     with torch.cuda.stream(stream):
-        for f in (0, 100, 200, 299):
+        for f in (0, n_frames // 3, 2 * n_frames // 3, n_frames - 1):
             r.pose_dev.copy_(poses_all[f])
             r.select_lod(scene.camera, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
             r.skin()
@@ -164,16 +249,19 @@ def time_mode(torch, rs, scene, poses_all, imgs, streams, lod, steps, warmup):
         r.render(scene.camera, img, stats=True)
         st0 = r.last_stats
         frame0 = img.clone()
-    for ri, im, st in zip(rs, imgs, streams):
+    n = len(rs)
+    rings = []
+    for i, (ri, im, st) in enumerate(zip(rs, imgs, streams)):
         with torch.cuda.stream(st):
             ri.reserve(0, int(max_splats * 1.05) + 1024, int(max_pairs * 1.3) + 65536)
+            ring = poses_all[i::n].contiguous()
+            rings.append(ring)
+            ri.set_pose_ring(ring, first=0)
             ri.capture(scene.camera, im, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
-    n = len(rs)
 
     def frame(k):
         i = k % n
         with torch.cuda.stream(streams[i]):
-            rs[i].pose_dev.copy_(poses_all[k % 300])
             rs[i].launch()
         return i
 
@@ -203,6 +291,8 @@ def time_mode(torch, rs, scene, poses_all, imgs, streams, lod, steps, warmup):
     overflow = 0
     for ri in rs:
         overflow |= int(ri.poll().overflow)
+        ri.set_pose_ring(None)
+    del rings
     return dict(ms=total / steps, per=per, stats=st0, frame0=frame0, overflow=overflow)
 
 
@@ -308,6 +398,48 @@ def dominant_roofline(stage_ms, st, scene, uniq):
     a = b / (stage_ms[dom] * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": kernels[dom], "achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(a / HBM_PEAK_GBS, 4), "launch_ms": round(stage_ms[dom], 4), "bytes_per_launch": int(b)}
+
+
+def frame_roofline(stage_ms, stats, scene, uniq, tile, blend):
+    """Roofline object of the dominant single-launch kernel of the timed
+    frame (fused projection, LDS segment sort or compositing), timed with HIP
+    events on its launch stream in the instrumented frames. Projection and
+    sort: algorithmic HBM bytes against 8 TB/s and, where counters for these
+    sources exist, VALU issue against the non-packed FP32 peak; the bound is
+    the larger fraction. Compositing: FP32 operations of the evaluations it
+    ran against the non-packed FP32 peak."""
+    kernels = {"project_fused": "project_kernel (skinning fused)", "segsort": "seg_sort_kernel",
+               "blend": "blend_kernel"}
+    cand = {k: stage_ms[k] for k in kernels if stage_ms.get(k, 0.0) > 0}
+    dom = max(cand, key=cand.get)
+    t = stage_ms[dom] * 1e-3
+    same = kernel_digest() == MEASURED["digest"] and tuple(tile) == tuple(MEASURED["tile"] or ())
+    out = {"kernel": kernels[dom], "launch_ms": round(stage_ms[dom], 4),
+           "traffic": MEASURED["traffic"].get(dom) if same else None}
+    if dom == "blend":
+        flops = blend["evals_per_frame"] * BLEND_FLOPS_PER_EVAL
+        a = flops / t / 1e12
+        out.update(bound="alu", achieved=round(a, 3), peak=round(FP32_PEAK_TFLOPS, 1), unit="TFLOP/s",
+                   frac=round(a / FP32_PEAK_TFLOPS, 4), flops_per_launch=int(flops))
+        return out
+    b = algorithmic_bytes(dom, stats, scene, uniq)
+    a = b / t / 1e9
+    hbm = {"achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(a / HBM_PEAK_GBS, 4),
+           "bytes_per_launch": int(b)}
+    items = stats["n_splats"] if dom == "project_fused" else stats["n_pairs"]
+    valu = MEASURED["valu_per_item"].get(dom) if same else None
+    issue = None
+    if valu is not None:
+        ai = valu * items / t
+        issue = {"achieved": round(ai / 1e12, 3), "peak": round(ISSUE_PEAK / 1e12, 2), "unit": "Tlane-instr/s",
+                 "frac": round(ai / ISSUE_PEAK, 4), "valu_per_item": valu}
+    if issue is not None and issue["frac"] > hbm["frac"]:
+        out.update(bound="alu", **{k: v for k, v in issue.items() if k != "valu_per_item"})
+    else:
+        out.update(bound="hbm", **{k: v for k, v in hbm.items() if k != "bytes_per_launch"})
+    out["hbm"] = hbm
+    out["issue"] = issue
+    return out
 
 
 def sweep_tab2(torch, steps, warmup, cells=None):
@@ -418,6 +550,13 @@ def psnr(a, b):
     return float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)
 
 
+def load_rules(path):
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -425,9 +564,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--stage-frames", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-full", action="store_true", help="skip the full-detail comparison")
+    ap.add_argument("--no-psnr", action="store_true", help="skip the PSNR of every rule on the held-out frames")
     ap.add_argument("--instances", type=int, default=3500)
     ap.add_argument("--net", default=os.path.join(ROOT, "paper_2501_17792_amd", "lod_net.npz"))
+    ap.add_argument("--rules", default=os.path.join(ROOT, "paper_2501_17792_amd", "lod_frame_rules.json"))
     ap.add_argument("--tile", default="auto", help="WxH or 'auto' (autotuned per run)")
     ap.add_argument("--modes", default="", help="comma list of LoD modes to time (default: all)")
     ap.add_argument("--sweep", default="", choices=["", "tab2", "tab1", "paper_lod"],
@@ -441,37 +581,55 @@ def main():
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
-    import torch
-
-    from paper_2501_17792_amd import crowdsplat as cs
     from paper_2501_17792_amd import synth
 
-    if args.sweep == "tab2":
-        sweep_tab2(torch, args.steps, args.warmup)
-        return
-    if args.sweep == "tab1":
-        sweep_tab1(torch)
-        return
-    if args.sweep == "paper_lod":
-        print(json.dumps(dict(sweep="paper_lod", **paper_lod_leg(torch, args.steps, args.warmup))), flush=True)
+    if args.sweep:
+        import torch
+
+        if args.sweep == "tab2":
+            sweep_tab2(torch, args.steps, args.warmup)
+        elif args.sweep == "tab1":
+            sweep_tab1(torch)
+        else:
+            print(json.dumps(dict(sweep="paper_lod", **paper_lod_leg(torch, args.steps, args.warmup))), flush=True)
         return
 
     t0 = time.perf_counter()
     templates = [synth.make_template(t, 100_000, 3, synth.C4_LEVELS) for t in range(14)]
     scene = synth.scene_c3(templates=templates, n_frames=300, n_inst=args.instances)
     log(f"inputs generated in {time.perf_counter() - t0:.1f} s")
+    netinfo = load_net(args.net)
+    rules = load_rules(args.rules)
+    if netinfo is None or rules is None:
+        raise SystemExit("the trained network and the frame-tuned rules are needed (train_lod.py)")
+    # the oracle baseline first: its process pool forks, before anything touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        from paper_2501_17792_amd import lodnet
+
+        t0 = time.perf_counter()
+        cpu = cpu_baseline(scene, lodnet.unpack(netinfo["net"]), rules["budget_margin"])
+        log(f"cpu baseline in {time.perf_counter() - t0:.1f} s: {cpu['value']:.3g} FPS on {cpu['cores']} cores")
+
+    import torch
+
+    from paper_2501_17792_amd import crowdsplat as cs
+    from paper_2501_17792_amd import train_lod
+
     stream = torch.cuda.Stream()
     dev = torch.device("cuda", 0)
-    netinfo = load_net(args.net)
-    modes = {"fixed_10_25m": (cs.CS_LOD_FIXED, (10.0, 10.0, 25.0, 25.0), 0, 0.0)}
-    results = {}
     with torch.cuda.stream(stream):
         poses_all = torch.from_numpy(scene.frame_poses).to(dev)
-        if netinfo is not None:
-            net_dev = torch.from_numpy(netinfo["net"]).to(dev)
-            modes["learned"] = (cs.CS_LOD_LEARNED, (), net_dev.data_ptr(), netinfo["margin"])
-            modes["fixed_tuned"] = (cs.CS_LOD_FIXED, tuple(netinfo["thresholds"]), 0, 0.0)
-    head = "learned" if "learned" in modes else "fixed_10_25m"
+        net_dev = torch.from_numpy(netinfo["net"]).to(dev)
+    # LoD rules, each at >= 40 dB frame PSNR against full detail on held-out frames
+    modes = {
+        "learned_budget": (cs.CS_LOD_BUDGET, (), net_dev.data_ptr(), rules["budget_margin"]),
+        "fixed_frame_tuned": (cs.CS_LOD_FIXED, tuple(rules["fixed_thresholds"]), 0, 0.0),
+        "learned_instance_floor": (cs.CS_LOD_LEARNED, (), net_dev.data_ptr(), netinfo["margin"]),
+        "fixed_10_25m": (cs.CS_LOD_FIXED, (10.0, 10.0, 25.0, 25.0), 0, 0.0),
+        "full": (cs.CS_LOD_FULL, (), 0, 0.0),
+    }
+    head = "learned_budget"
     if args.modes:  # timing a subset (e.g. for a profiler run); the headline mode is always kept
         keep = set(args.modes.split(",")) | {head}
         modes = {k: v for k, v in modes.items() if k in keep}
@@ -484,30 +642,39 @@ def main():
         tile = tuple(int(x) for x in args.tile.split("x"))
     log(f"tile {tile}")
     streams = [stream] + [torch.cuda.Stream(dev) for _ in range(args.inflight - 1)]
-    with torch.cuda.stream(stream):
-        imgs = [torch.zeros((3, scene.camera.height, scene.camera.width), device=dev) for _ in streams]
-        img = imgs[0]
 
-        def run(name, lod, n):  # fresh contexts per run: capacities are fixed at capture
+    def run(lod, n, sc=scene, poses=poses_all):  # fresh contexts per run: capacities are fixed at capture
+        with torch.cuda.stream(stream):
+            imgs = [torch.zeros((3, sc.camera.height, sc.camera.width), device=dev) for _ in range(n)]
             rs = []
             for st in streams[:n]:
                 r = cs.Renderer(0, stream=st, fuse=True, tile=tile)
-                r.upload_templates(scene.templates)
-                r.set_crowd(scene.crowd)
+                r.upload_templates(sc.templates)
+                r.set_crowd(sc.crowd)
                 rs.append(r)
             torch.cuda.synchronize()
-            out = time_mode(torch, rs, scene, poses_all, imgs[:n], streams[:n], lod, args.steps, args.warmup)
+            out = time_mode(torch, rs, sc, poses, imgs, streams[:n], lod, args.steps, args.warmup)
             for r in rs:
                 r.close()
-            return out
+            del imgs
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+        return out
 
-        for name, lod in modes.items():
-            results[name] = run(name, lod, len(streams))
-            log(f"{name}: {1000.0 / results[name]['ms']:.1f} FPS, {results[name]['stats'].n_splats} splats, "
-                f"{results[name]['stats'].n_pairs} pairs")
-        # the head mode once more with one frame in flight: a single frame's latency
-        single = run(head, modes[head], 1) if len(streams) > 1 else results[head]
-        log(f"{head}, one frame in flight: {1000.0 / single['ms']:.1f} FPS")
+    results = {}
+    for name, lod in modes.items():
+        results[name] = run(lod, len(streams))
+        log(f"{name}: {1000.0 / results[name]['ms']:.1f} FPS, {results[name]['stats'].n_splats} splats, "
+            f"{results[name]['stats'].n_pairs} pairs")
+    single = run(modes[head], 1) if len(streams) > 1 else results[head]
+    log(f"{head}, one frame in flight: {1000.0 / single['ms']:.1f} FPS")
+    # the fixed 10 / 25 m rule on the 500-avatar, 50 x 50 m crowd (3 of the 5 levels: 100 / 25 / 6.25 %)
+    sc2 = synth.scene_c2(templates=templates)
+    with torch.cuda.stream(stream):
+        poses2 = torch.from_numpy(np.ascontiguousarray(sc2.crowd.pose[None], np.float32)).to(dev)
+    c2 = run((cs.CS_LOD_FIXED, (10.0, 10.0, 25.0, 25.0), 0, 0.0), len(streams), sc=sc2, poses=poses2)
+    log(f"500 avatars, 10/25 m: {1000.0 / c2['ms']:.1f} FPS")
+
     res = results[head]
     ms = res["ms"]
     fps = 1000.0 / ms
@@ -515,18 +682,19 @@ def main():
     n_splats, n_pairs = int(st0.n_splats), int(st0.n_pairs)
     lod_head = modes[head]
 
-    # ---- per-stage timing: eager frames, HIP events on the launch stream around
-    # each stage. The first pass uses the timed configuration (skinning fused
-    # into projection); the second separates skinning from projection.
+    # ---- per-stage timing: instrumented eager frames (HIP events on the launch
+    # stream around each stage, blend evaluations counted). First the timed
+    # configuration (skinning fused into projection), then separate skinning.
     def stage_profile(fuse):
         with torch.cuda.stream(stream):
+            img = torch.zeros((3, scene.camera.height, scene.camera.width), device=dev)
             rp = cs.Renderer(0, stream=stream, fuse=fuse, profile=True, tile=tile)
             rp.upload_templates(scene.templates)
             rp.set_crowd(scene.crowd)
             lvl_out = torch.zeros(scene.crowd.n, dtype=torch.int32, device=dev)
-            acc = {}
+            acc, evals = {}, []
             for k in range(args.stage_frames + 1):
-                rp.pose_dev.copy_(poses_all[k % 300])
+                rp.pose_dev.copy_(poses_all[k % poses_all.shape[0]])
                 rp.select_lod(scene.camera, lod_head[0], lod_head[1], level_out=lvl_out, mlp_ptr=lod_head[2],
                               margin=lod_head[3])
                 rp.skin()
@@ -535,82 +703,60 @@ def main():
                 if k > 0:
                     for name, v in t.items():
                         acc.setdefault(name, []).append(v)
+                    evals.append((int(rp.last_stats.blend_evals), int(rp.last_stats.blend_eval_slots),
+                                  int(rp.last_stats.n_pairs), t.get("blend", 0.0)))
             stream.synchronize()
             stp = rp.last_stats
             rp.close()
-        return {k: float(np.mean(v)) for k, v in acc.items()}, lvl_out.cpu().numpy().astype(np.int64), stp
+        return {k: float(np.mean(v)) for k, v in acc.items()}, lvl_out.cpu().numpy().astype(np.int64), stp, evals
 
-    stage_ms, levels, stp = stage_profile(True)
-    stage_unfused, _, _ = stage_profile(False)
+    stage_ms, levels, stp, evals = stage_profile(True)
+    stage_unfused, _, _, _ = stage_profile(False)
     uniq = unique_template_gaussians(scene, levels)
     stats = dict(n_splats=int(stp.n_splats), n_pairs=int(stp.n_pairs))
     stage_ms = {("project_fused" if k == "project" else k): v for k, v in stage_ms.items()}
     stage_ms["skin"] = stage_unfused.get("skin", 0.0)
     stage_ms["project"] = stage_unfused.get("project", 0.0)
     stage_gbs = {}
-    for name in ("skin", "project", "project_fused", "emit", "sort", "segsort", "blend"):
+    for name in ("skin", "project", "project_fused", "emit", "sort", "segsort"):
         if stage_ms.get(name, 0.0) > 0:
             stage_gbs[name] = algorithmic_bytes(name, stats, scene, uniq) / (stage_ms[name] * 1e-3) / 1e9
-    # The roofline object is that of the dominant kernel of the timed (fused)
-    # frame: projection (one launch, skinning fused) or the LDS segment sort
-    # (one launch; the key splits before it are several smaller launches).
-    # Both are bounded by HBM bytes on the roofline model (their arithmetic
-    # intensity is far below MI355X's ridge point); the multi-kernel stages
-    # are in stage_ms / stage_gbs.
-    kernels = {"project_fused": "project_kernel (skinning fused)", "segsort": "seg_sort_kernel"}
-    cand = {k: stage_ms[k] for k in kernels if stage_ms.get(k, 0.0) > 0}
-    dom = max(cand, key=cand.get)
-    per_launch_ms = stage_ms[dom]
-    per_launch_bytes = algorithmic_bytes(dom, stats, scene, uniq)
-    achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9
-    traffic = None
-    mt = MEASURED_TRAFFIC
-    if kernel_digest() == mt["digest"] and head == mt["lod"] and tuple(tile) in mt["bytes"]:
-        traffic = mt["bytes"][tuple(tile)].get(dom)
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernels[dom],
-                "launch_ms": round(per_launch_ms, 4), "bytes_per_launch": int(per_launch_bytes)}
+    ev = np.array(evals, np.float64)
+    blend = {"evals_per_frame": int(ev[:, 0].mean()), "eval_slots_per_frame": int(ev[:, 1].mean()),
+             "pairs_per_frame": int(ev[:, 2].mean()), "blend_ms": round(float(ev[:, 3].mean()), 4),
+             "evals_per_s_per_cu": round(float((ev[:, 0] / (ev[:, 3] * 1e-3)).mean()) / N_CU, 1),
+             "eval_slots_per_s_per_cu": round(float((ev[:, 1] / (ev[:, 3] * 1e-3)).mean()) / N_CU, 1),
+             "live_fraction_of_slots": round(float(ev[:, 0].sum() / max(ev[:, 1].sum(), 1.0)), 4),
+             "evals_per_pair": round(float(ev[:, 0].sum() / max(ev[:, 2].sum(), 1.0)), 3)}
+    roofline = frame_roofline(stage_ms, stats, scene, uniq, tile, blend)
 
-    # ---- full detail (every instance at level 0): FPS and the reference frame for PSNR
-    full = None
-    if not args.no_full:
-        with torch.cuda.stream(stream):
-            rf = cs.Renderer(0, stream=stream, fuse=True, tile=tile)
-            rf.upload_templates(scene.templates)
-            rf.set_crowd(scene.crowd)
-            img_full = torch.zeros_like(img)
-            rf.pose_dev.copy_(poses_all[0])
-            rf.frame(scene.camera, cs.CS_LOD_FULL, (), image=img_full, stats=True)
-            stf = rf.last_stats
-            nf = 5
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for k in range(nf):
-                rf.frame(scene.camera, cs.CS_LOD_FULL, (), image=img_full)
-            e1.record(stream)
-            stream.synchronize()
-            full_ms = e0.elapsed_time(e1) / nf
-            ref = img_full.cpu().numpy()
-            full = {"fps_full_eager": round(1000.0 / full_ms, 2), "full_n_splats": int(stf.n_splats),
-                    "full_n_pairs": int(stf.n_pairs)}
-            for name, rr in results.items():
-                rr["psnr"] = psnr(rr["frame0"].cpu().numpy(), ref)
-            rf.close()
+    # ---- quality: every rule's frames against full-detail frames, on the
+    # frames the rules were not tuned on (and on frame 0)
+    quality = {}
+    if not args.no_psnr:
+        hold = tuple(rules["hold_frames"])
+        judge = train_lod.FrameJudge(torch, scene, hold + (0,), tile)
+        for name, lod in modes.items():
+            p_min, g_mean = judge.evaluate(lod, hold)
+            p0, _ = judge.evaluate(lod, (0,))
+            quality[name] = {"min_psnr_held_out_db": round(p_min, 2), "psnr_frame0_db": round(p0, 2),
+                             "held_out_frames": len(hold)}
+        judge.close()
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(scene, levels, n_splats, n_pairs)
-
-    lod_cmp = {name: {"fps": round(1000.0 / rr["ms"], 2), "n_splats": int(rr["stats"].n_splats),
-                      "n_pairs": int(rr["stats"].n_pairs), "psnr_vs_full_db": (round(rr["psnr"], 2) if "psnr" in rr else None),
-                      "overflow": rr["overflow"]} for name, rr in results.items()}
+    lod_cmp = {}
+    for name, rr in results.items():
+        lod_cmp[name] = {"fps": round(1000.0 / rr["ms"], 2), "frame_ms_p95": round(float(np.percentile(rr["per"], 95)), 4),
+                         "n_splats": int(rr["stats"].n_splats), "n_pairs": int(rr["stats"].n_pairs),
+                         "level_hist": list(rr["stats"].level_hist)[:5], "overflow": rr["overflow"]}
+        lod_cmp[name].update(quality.get(name, {}))
     out = {
         "metric": METRIC, "value": round(fps, 2), "unit": "FPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "3,500 animated avatars, 14 templates x 100k Gaussians SH3 with 5 LoD levels "
-                               "(100/50/25/12.5/6.25%), 1920x1080, 300-frame keyframed animation, "
-                               "hipGraph-captured frame, frames in flight on separate contexts",
+                               "(100/50/25/12.5/6.25%), 1920x1080, 300-frame keyframed animation, learned LoD "
+                               "with a frame budget of 40 dB PSNR against full detail, hipGraph-captured frame "
+                               "(pose upload inside), frames in flight on separate contexts",
                    "lod": head, "instances": scene.crowd.n, "width": scene.camera.width,
                    "height": scene.camera.height, "tile": list(tile)},
         "tile_autotune_ms": tile_timing,
@@ -620,9 +766,15 @@ def main():
         "one_frame_in_flight": {"fps": round(1000.0 / single["ms"], 2), "frame_ms": round(single["ms"], 4)},
         "gaussians_per_s": round(n_splats * fps, 1), "n_splats": n_splats, "n_pairs": n_pairs,
         "n_visible": int(st0.n_visible), "level_hist": list(st0.level_hist)[:5],
-        "lod_comparison": lod_cmp, "full_detail": full,
+        "lod_comparison": lod_cmp,
+        "lod_rules": {"budget_margin_db": rules["budget_margin"], "fixed_thresholds_m": rules["fixed_thresholds"],
+                      "tuned_on_frames": rules["tune_frames"], "target_db": rules.get("target_db")},
+        "c2_500_avatars_fixed_10_25m": {"fps": round(1000.0 / c2["ms"], 2), "n_splats": int(c2["stats"].n_splats),
+                                        "n_pairs": int(c2["stats"].n_pairs), "overflow": c2["overflow"],
+                                        "level_hist": list(c2["stats"].level_hist)[:5]},
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "stage_gbs": {k: round(v, 1) for k, v in stage_gbs.items()},
+        "blend": blend,
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

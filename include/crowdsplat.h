@@ -58,6 +58,8 @@ typedef int32_t cs_status;
 #define CS_LOD_FIXED   1  /* level = number of distance thresholds <= distance   */
 #define CS_LOD_LEARNED 2  /* coarsest level whose predicted PSNR clears a floor  */
 #define CS_LOD_CONSTANT 3 /* every instance at lod->level                        */
+#define CS_LOD_BUDGET  4  /* learned, frame budget: fewest Gaussians whose      */
+                          /* predicted errors keep the frame >= the floor       */
 
 #define CS_MAX_LEVELS     8
 #define CS_MAX_TEMPLATES  64
@@ -146,10 +148,24 @@ typedef struct cs_lod_params {
   int32_t n_thresholds;      /* FIXED: 0..7 increasing distances (m)            */
   float thresholds[7];
   int32_t level;             /* CONSTANT: the level of every instance           */
-  float psnr_min;            /* LEARNED: quality floor (dB)                     */
-  float margin;              /* LEARNED: extra dB required of the prediction    */
-  const void* mlp;           /* LEARNED: device pointer to a cs_mlp             */
+  float psnr_min;            /* LEARNED, BUDGET: quality floor (dB)             */
+  float margin;              /* LEARNED, BUDGET: extra dB required              */
+  const void* mlp;           /* LEARNED, BUDGET: device pointer to a cs_mlp     */
 } cs_lod_params;
+/* LEARNED keeps each instance's own predicted PSNR (over its label window)
+ * >= psnr_min + margin. BUDGET reads the floor as one for the whole frame
+ * against the full-detail frame, which is the quality the paper's LoD trades
+ * (§2 last paragraph, §3 Fig. 4): a level's predicted PSNR over the
+ * instance's label window (its joint box widened to whole 16x16 tiles,
+ * clipped to the image; w x h pixels) gives a predicted squared error
+ * SSE_l = 3 w h 10^(-PSNR_l/10) over the window's RGB values (PSNR clamped
+ * to [0, 60] dB, none at level 0); the frame holds PSNR >= floor while the
+ * sum over instances stays within 3 W H 10^(-(psnr_min + margin)/10). Each
+ * instance takes the level minimising n_l + lambda SSE_l (n_l its Gaussians,
+ * ties to the finer level) for the smallest lambda, on a 30-step bisection
+ * of log2(lambda) in [-40, 60], whose total stays within that budget
+ * (overlaps between instances are ignored; the margin absorbs them).
+ * BUDGET needs psnr_min + margin in (0, 200) dB. */
 
 /* The learned-LoD network (device memory, laid out exactly as below).
  * Inputs: 32 features (31 used, see cs_lod_features) z-scored with mu and
@@ -184,8 +200,13 @@ typedef struct cs_frame_stats {
   int32_t sort_fallbacks;    /* LDS-sorted segments re-sorted with ballot ranks */
   int32_t reserved0;
   int64_t blend_evals;       /* profile_stages only: (pixel, splat) opacity
-                                evaluations the blend ran; else 0             */
-  int64_t reserved[4];
+                                evaluations the blend ran for pixels still
+                                compositing; else 0                           */
+  int64_t blend_eval_slots;  /* profile_stages only: lane evaluation slots the
+                                blend issued (the live ones plus lanes idle
+                                in a wave's step: finished pixels, shorter
+                                group lists); else 0                          */
+  int64_t reserved[3];
 } cs_frame_stats;
 
 /* Context lifetime. stream: a hipStream_t (NULL = the null stream). */
@@ -407,7 +428,9 @@ cs_status cs_memory_report(cs_ctx* ctx, cs_memory_stats* out);
 #define CS_BUF_SVALS    14  /* uint32 [n_pairs] sorted splat indices                 */
 #define CS_BUF_RANGES   15  /* uint32 [n_tiles][2] [start, end) per tile            */
 #define CS_BUF_FEATURES 16  /* float [n_inst][32] learned-LoD features               */
-#define CS_BUF_PRED     17  /* float [n_inst][16] learned-LoD predicted PSNR         */
+#define CS_BUF_PRED     17  /* float [n_inst][16] learned-LoD predicted PSNR [0..4];  */
+                            /* BUDGET also SSE_l [8..12], w h [13], log2 lambda [14], */
+                            /* top level [15]                                        */
 #define CS_BUF_VIEWS    18  /* int64 [n_inst][6] window x0 y0 w h (px), tile base, atlas offset */
 #define CS_BUF_JOINTS   19  /* float [n_inst][24][3] posed joint positions           */
 #define CS_BUF_OFFSETS  20  /* float [n_splats][4] pose-dependent offsets (x y z 0)  */

@@ -24,7 +24,7 @@ CS_LAUNCH_BATCHED, CS_LAUNCH_PER_INSTANCE = 0, 1
 CS_SORT_TILE_BUCKET, CS_SORT_ONESWEEP, CS_SORT_REDUCE_SCAN = 0, 1, 2
 CS_NOALLOC_MAX_PAIRS = 1 << 20
 CS_SORT_RANKS_CHECKED, CS_SORT_RANKS_BALLOT = 0, 1
-CS_LOD_FULL, CS_LOD_FIXED, CS_LOD_LEARNED, CS_LOD_CONSTANT = 0, 1, 2, 3
+CS_LOD_FULL, CS_LOD_FIXED, CS_LOD_LEARNED, CS_LOD_CONSTANT, CS_LOD_BUDGET = 0, 1, 2, 3, 4
 CS_MLP_NPARAM, CS_MLP_NBF16 = 7312, 7168
 #: offsets of the layers inside cs_mlp.params (out-major weights)
 MLP_OFF = dict(w1=(0, (64, 32)), b1=(2048, (64,)), w2=(2112, (64, 64)), b2=(6208, (64,)),
@@ -89,7 +89,8 @@ class CsFrameStats(ctypes.Structure):
                 ("n_pairs", ctypes.c_int64), ("overflow", ctypes.c_int32),
                 ("n_instances", ctypes.c_int32), ("level_hist", ctypes.c_int32 * CS_MAX_LEVELS),
                 ("sort_fallbacks", ctypes.c_int32), ("reserved0", ctypes.c_int32),
-                ("blend_evals", ctypes.c_int64), ("reserved", ctypes.c_int64 * 4)]
+                ("blend_evals", ctypes.c_int64), ("blend_eval_slots", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 3)]
 
 
 CS_PNET_EMBED, CS_PNET_POSE, CS_PNET_HIDDEN = 32, 80, 64

@@ -44,13 +44,14 @@ __global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t* __rest
   for (int t = threadIdx.x; t < n_tiles; t += 1024) order[atomicAdd(&s_cnt[cls(t)], 1u)] = (uint32_t)t;
 }
 
-template <int TW, int TH, bool VIEW>
+template <int TW, int TH, bool VIEW, bool COUNT = false>
 __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restrict__ ranges,
                                                        const uint32_t* __restrict__ svals,
                                                        const float4* __restrict__ rec, CamDev cam,
                                                        float* __restrict__ image,
                                                        const FrameHdr* __restrict__ hdr, ViewDev view,
-                                                       const uint32_t* __restrict__ order) {
+                                                       const uint32_t* __restrict__ order,
+                                                       unsigned long long* __restrict__ counters) {
   constexpr int N = TW * TH;
   constexpr int ROWS = 64 / TW;  // pixel rows per wave
   constexpr int WAVES = N / 64;
@@ -109,6 +110,7 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
   const uint32_t n_splats = hdr->n_splats;
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
   bool done = !inside;
+  uint32_t n_live = 0, n_slots = 0;  // COUNT: live evaluations and lane slots of this lane
   // Software pipeline over batches: the tile's list entries are read 4
   // batches ahead and whole records 2 ahead, into two-slot register rings
   // (the loop is unrolled twice with the slots swapped, so no register a load
@@ -246,6 +248,10 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
           int oA = off(2), oB = off(3);
           auto eval = [&](int k, const float4& r1, const float2& uv, const float4& r2) {
             const bool live = !done && k < n_mine;
+            if constexpr (COUNT) {
+              n_live += live ? 1u : 0u;
+              n_slots += 1u;
+            }
             const float dx = pcx - uv.x, dy = pcy - uv.y;
             float power = -0.5f * fmaf(r1.x * dx, dx, r1.z * dy * dy) - r1.y * dx * dy;
             power = fminf(power, 0.f);
@@ -287,6 +293,18 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
       if (!step(1, b, eb, sb, rb0, rb1, rb2) || (b += N) >= end) break;
     }
   }
+  if constexpr (COUNT) {
+    unsigned long long a = n_live, b = n_slots;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      a += __shfl_xor(a, off);
+      b += __shfl_xor(b, off);
+    }
+    if (lane == 0) {
+      atomicAdd(&counters[0], a);
+      atomicAdd(&counters[1], b);
+    }
+  }
   if (inside) {
     const size_t plane = (size_t)out_w * out_h;
     const size_t o = (size_t)(py - out_y0) * out_w + (px - out_x0);
@@ -299,28 +317,34 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
 template <int TW, int TH>
 static hipError_t launch_blend_t(const uint32_t* ranges, const uint32_t* svals, const float4* rec,
                                  CamDev cam, float* image, const FrameHdr* hdr, const ViewDev* view,
-                                 uint32_t* order, hipStream_t st) {
+                                 uint32_t* order, hipStream_t st, unsigned long long* counters) {
   if (view) {
     if (view->n_tiles > 0)
       blend_kernel<TW, TH, true><<<view->n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr, *view,
-                                                                      nullptr);
+                                                                      nullptr, nullptr);
   } else {
     const int n_tiles = cam.tiles_x * cam.tiles_y;
     if (order) tile_order_kernel<<<1, 1024, 0, st>>>(ranges, n_tiles, order);
-    blend_kernel<TW, TH, false><<<n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr, ViewDev{},
-                                                              order);
+    if (counters)
+      blend_kernel<TW, TH, false, true><<<n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr,
+                                                                      ViewDev{}, order, counters);
+    else
+      blend_kernel<TW, TH, false><<<n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr, ViewDev{},
+                                                                order, nullptr);
   }
   return hipGetLastError();
 }
 
 // order: scratch of cam.tiles_x * cam.tiles_y entries for the longest-first
 // launch order, or null for tile-index order.
+// counters: null, or two zeroed 64-bit counters (live evaluations, lane
+// slots) for an instrumented frame.
 hipError_t launch_blend(const uint32_t* ranges, const uint32_t* svals, const float4* rec, CamDev cam,
                         float* image, const FrameHdr* hdr, const ViewDev* view, uint32_t* order,
-                        hipStream_t st) {
+                        hipStream_t st, unsigned long long* counters) {
 #define CS_BLEND_CASE(W_, H_) \
   if (cam.tw == W_ && cam.th == H_)      \
-    return launch_blend_t<W_, H_>(ranges, svals, rec, cam, image, hdr, view, order, st);
+    return launch_blend_t<W_, H_>(ranges, svals, rec, cam, image, hdr, view, order, st, counters);
   CS_BLEND_CASE(8, 8)
   CS_BLEND_CASE(8, 16)
   CS_BLEND_CASE(8, 32)

@@ -126,6 +126,8 @@ struct FrameHdr {
   uint32_t pose_frame;      // captured frames: frames fetched from the pose ring so far
   uint32_t pad[6];
   uint32_t sort_fallbacks; // LDS-sorted segments re-sorted with ballot ranks this frame
+  unsigned long long blend_evals;  // instrumented frames: live (pixel, splat) evaluations of the blend
+  unsigned long long blend_slots;  // instrumented frames: lane evaluation slots the blend issued
 };
 
 struct Chunk {
@@ -238,13 +240,15 @@ hipError_t launch_ranges(const uint64_t* skeys, FrameHdr* hdr, uint32_t max_pair
                          uint32_t* ranges, hipStream_t st);
 hipError_t launch_blend(const uint32_t* ranges, const uint32_t* svals, const float4* rec, CamDev cam,
                         float* image, const FrameHdr* hdr, const ViewDev* view, uint32_t* order,
-                        hipStream_t st);
+                        hipStream_t st, unsigned long long* counters = nullptr);
 hipError_t launch_features(const cs_instance* inst, const float* pose, const float* joints,
                            const TemplateDev* tpl, int n_inst, int n_tpl, CamDev cam, const cs_mlp* net,
                            float* feat, hipStream_t st);
 hipError_t launch_mlp_infer(const cs_mlp* net, const float* feat, int n, float* pred, int select,
                             const cs_instance* inst, const TemplateDev* tpl, int n_tpl, float floor_db,
                             int32_t* level, uint32_t* count, hipStream_t st);
+hipError_t launch_lod_budget(float* pred, const float* joints, const cs_instance* inst, const TemplateDev* tpl, int n,
+                             int n_tpl, CamDev cam, float budget, int32_t* level, uint32_t* count, hipStream_t st);
 hipError_t launch_mlp_sync(cs_mlp* net, hipStream_t st);
 hipError_t launch_mlp_train(cs_mlp* net, float* m, float* v, const float* feat, const float* target, int batch,
                             int step, float lr, float* loss, hipStream_t st);

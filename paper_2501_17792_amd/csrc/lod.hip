@@ -241,6 +241,117 @@ hipError_t launch_mlp_infer(const cs_mlp* net, const float* feat, int n, float* 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Frame-budget selection (one workgroup). A level's predicted PSNR over the
+// instance's label window (the joint box widened to whole 16x16 tiles, the
+// tiles the labels were rendered with, clipped to the image; w x h pixels)
+// gives its predicted squared error summed over the window's RGB values,
+// SSE_l = 3 w h 10^(-PSNR_l / 10) (PSNR clamped to [0, 60]; level 0 has none).
+// The frame keeps PSNR >= floor when the sum over instances stays within
+// budget = 3 W H 10^(-floor / 10). Each instance takes the level minimising
+// n_l + lambda SSE_l (n_l its Gaussians; ties to the finer level); the
+// smallest lambda on a bisection of t = log2(lambda) in [-40, 60] (30 steps)
+// whose total stays within the budget is used. Sums are per thread in
+// instance order, then a fixed butterfly and the waves in order.
+// pred[i][8 + l] receives SSE_l, pred[i][13] w h, pred[i][14] the chosen t.
+// ---------------------------------------------------------------------------
+constexpr int kBudgetIters = 30;
+constexpr float kBudgetLo = -40.f, kBudgetHi = 60.f;
+
+__device__ __forceinline__ int budget_choose(const float* __restrict__ p, const TemplateDev& T, int top, float lam) {
+  int best = 0;
+  float best_c = (float)T.level_count[0];
+  for (int l = 1; l <= top; ++l) {
+    const float c = fmaf(lam, p[8 + l], (float)T.level_count[l]);
+    if (c < best_c) {
+      best_c = c;
+      best = l;
+    }
+  }
+  return best;
+}
+
+__global__ __launch_bounds__(1024) void lod_budget_kernel(float* __restrict__ pred, const float* __restrict__ joints,
+                                                          const cs_instance* __restrict__ inst,
+                                                          const TemplateDev* __restrict__ tpl, int n, int n_tpl,
+                                                          CamDev cam, float budget, int32_t* __restrict__ level,
+                                                          uint32_t* __restrict__ count) {
+  __shared__ float s_part[16];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  constexpr float kLog2_10_over_10 = 0.33219280948873624f;
+  // every value a thread reads below it wrote itself (instances t, t + 1024, ...)
+  for (int i = t; i < n; i += 1024) {
+    float* p = pred + (size_t)i * 16;
+    const int tid = inst[i].tid;
+    float win = 0.f;
+    int top = 0;
+    if (tid >= 0 && tid < n_tpl) {
+      top = min(tpl[tid].n_levels, 5) - 1;
+      float box[4];
+      if (joint_box(joints + (size_t)i * kJoints * 3, tpl[tid].pad_radius, cam, box)) {
+        const float c0 = fmaxf(box[0], 0.f), c1 = fmaxf(box[1], 0.f);
+        const float c2 = fminf(box[2], (float)cam.W), c3 = fminf(box[3], (float)cam.H);
+        if (c2 > c0 && c3 > c1) {
+          const int x0 = (int)floorf(c0 * (1.f / 16.f)) * 16, y0 = (int)floorf(c1 * (1.f / 16.f)) * 16;
+          const int x1 = min((int)ceilf(c2 * (1.f / 16.f)) * 16, cam.W);
+          const int y1 = min((int)ceilf(c3 * (1.f / 16.f)) * 16, cam.H);
+          if (x1 > x0 && y1 > y0) win = (float)((x1 - x0) * (y1 - y0));
+        }
+      }
+    }
+    p[8] = 0.f;
+    for (int l = 1; l < 5; ++l) {
+      const float db = fminf(fmaxf(p[l], 0.f), 60.f);
+      p[8 + l] = l <= top ? 3.f * win * exp2f(-db * kLog2_10_over_10) : 0.f;
+    }
+    p[13] = win;
+    p[15] = (float)top;
+  }
+  float lo = kBudgetLo, hi = kBudgetHi;
+  for (int it = 0; it < kBudgetIters; ++it) {
+    const float mid = 0.5f * (lo + hi);
+    const float lam = exp2f(mid);
+    float acc = 0.f;
+    for (int i = t; i < n; i += 1024) {
+      const float* p = pred + (size_t)i * 16;
+      const int tid = inst[i].tid;
+      if (tid < 0 || tid >= n_tpl) continue;
+      acc += p[8 + budget_choose(p, tpl[tid], (int)p[15], lam)];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) s_part[wave] = acc;
+    __syncthreads();
+    float total = 0.f;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) total += s_part[w];
+    __syncthreads();
+    if (total <= budget) hi = mid;
+    else lo = mid;
+  }
+  const float lam = exp2f(hi);
+  for (int i = t; i < n; i += 1024) {
+    float* p = pred + (size_t)i * 16;
+    const int tid = inst[i].tid;
+    p[14] = hi;
+    if (tid < 0 || tid >= n_tpl) {
+      level[i] = 0;
+      count[i] = 0;
+      continue;
+    }
+    const int l = budget_choose(p, tpl[tid], (int)p[15], lam);
+    level[i] = l;
+    count[i] = (uint32_t)tpl[tid].level_count[l];
+  }
+}
+
+hipError_t launch_lod_budget(float* pred, const float* joints, const cs_instance* inst, const TemplateDev* tpl, int n,
+                             int n_tpl, CamDev cam, float budget, int32_t* level, uint32_t* count, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  lod_budget_kernel<<<1, 1024, 0, st>>>(pred, joints, inst, tpl, n, n_tpl, cam, budget, level, count);
+  return hipGetLastError();
+}
+
 __global__ void mlp_sync_kernel(cs_mlp* net) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < 2048) net->w_bf16[kH1 + t] = f2bf(net->params[kW1 + t]);

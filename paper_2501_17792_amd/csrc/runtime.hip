@@ -690,10 +690,13 @@ cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, co
   if (lod->mode == CS_LOD_FIXED && (lod->n_thresholds < 0 || lod->n_thresholds > 7))
     return ctx->fail(CS_ERR_INVALID, "0..7 thresholds");
   if (lod->mode != CS_LOD_FULL && lod->mode != CS_LOD_FIXED && lod->mode != CS_LOD_LEARNED &&
-      lod->mode != CS_LOD_CONSTANT)
+      lod->mode != CS_LOD_CONSTANT && lod->mode != CS_LOD_BUDGET)
     return ctx->fail(CS_ERR_INVALID, "bad lod mode");
-  if (lod->mode == CS_LOD_LEARNED && (!lod->mlp || !pose))
+  const bool learned = lod->mode == CS_LOD_LEARNED || lod->mode == CS_LOD_BUDGET;
+  if (learned && (!lod->mlp || !pose))
     return ctx->fail(CS_ERR_INVALID, "learned LoD needs the network and the poses");
+  if (lod->mode == CS_LOD_BUDGET && !(lod->psnr_min + lod->margin > 0.f && lod->psnr_min + lod->margin < 200.f))
+    return ctx->fail(CS_ERR_INVALID, "the frame's PSNR floor plus margin must lie in (0, 200) dB");
   if (lod->mode == CS_LOD_CONSTANT && (lod->level < 0 || lod->level >= CS_MAX_LEVELS))
     return ctx->fail(CS_ERR_INVALID, "constant level out of range");
   if (ctx->n_copies && n_inst != ctx->n_copies)
@@ -706,14 +709,23 @@ cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, co
   for (int k = 0; k < CS_STAGE_COUNT; ++k) ctx->ev_used[k] = false;
   ctx->mark(CS_STAGE_LOD, 0);
   HIP_TRY(launch_frame_reset(ctx->hdr, ctx->hist, 0, 1, ctx->stream));
-  if (lod->mode == CS_LOD_LEARNED) {
+  if (learned) {
     HIP_TRY(launch_fk(inst, pose, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), ctx->bones, ctx->joints,
                       ctx->hdr, ctx->stream));
     const cs_mlp* net = (const cs_mlp*)lod->mlp;
     HIP_TRY(launch_features(inst, pose, ctx->joints, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), cd, net,
                             ctx->feat, ctx->stream));
-    HIP_TRY(launch_mlp_infer(net, ctx->feat, n_inst, ctx->pred, 1, inst, ctx->tpl_dev, (int)ctx->tpl.size(),
-                             lod->psnr_min + lod->margin, ctx->level, ctx->count_inst, ctx->stream));
+    const bool per_instance = lod->mode == CS_LOD_LEARNED;
+    HIP_TRY(launch_mlp_infer(net, ctx->feat, n_inst, ctx->pred, per_instance ? 1 : 0, inst, ctx->tpl_dev,
+                             (int)ctx->tpl.size(), lod->psnr_min + lod->margin, ctx->level, ctx->count_inst,
+                             ctx->stream));
+    if (!per_instance) {
+      // frame MSE over the 3 W H values <= 10^(-floor / 10)
+      const double floor_db = (double)lod->psnr_min + (double)lod->margin;
+      const float budget = (float)(3.0 * (double)cd.W * (double)cd.H * pow(10.0, -floor_db / 10.0));
+      HIP_TRY(launch_lod_budget(ctx->pred, ctx->joints, inst, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), cd,
+                                budget, ctx->level, ctx->count_inst, ctx->stream));
+    }
   } else {
     HIP_TRY(launch_lod_fixed(inst, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), cd, lod->thresholds,
                              lod->mode == CS_LOD_FIXED ? lod->n_thresholds : 0, lod->mode == CS_LOD_FULL,
@@ -907,7 +919,9 @@ static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs
   ctx->mark(CS_STAGE_BLEND, 0);
   if (n_tiles > 0)
     HIP_TRY(launch_blend(ctx->ranges, ctx->vals[ctx->sorted], ctx->rec, cd, image, ctx->hdr, vp,
-                         view_mode ? nullptr : ctx->tile_order, ctx->stream));
+                         view_mode ? nullptr : ctx->tile_order, ctx->stream,
+                         ctx->opt.profile_stages && !ctx->capturing && !view_mode ? &ctx->hdr->blend_evals
+                                                                                    : nullptr));
   ctx->mark(CS_STAGE_BLEND, 1);
   ctx->state = kRendered;
   if (stats) {
@@ -921,6 +935,8 @@ static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs
     stats->n_instances = (int32_t)h.n_inst;
     for (int l = 0; l < CS_MAX_LEVELS; ++l) stats->level_hist[l] = (int32_t)h.level_hist[l];
     stats->sort_fallbacks = (int32_t)h.sort_fallbacks;
+    stats->blend_evals = (int64_t)h.blend_evals;
+    stats->blend_eval_slots = (int64_t)h.blend_slots;
     if (h.overflow) return ctx->fail(CS_ERR_CAPACITY, "frame exceeded a capacity (see stats)");
   }
   return CS_OK;

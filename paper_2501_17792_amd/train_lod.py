@@ -68,6 +68,109 @@ def tune_margin(pred, psnr, floor=FLOOR, coverage=0.99):
     return 20.0
 
 
+# ----------------------------------------------------------------------------
+# rules tuned to the frame's PSNR against the full-detail frame
+# ----------------------------------------------------------------------------
+
+TUNE_FRAMES = tuple(range(0, 300, 10))
+HOLD_FRAMES = tuple(range(5, 300, 10))
+TUNE_EXTRA_DB = 0.5  # tuned to floor + this on the tuning frames, so held-out frames keep the floor
+FIXED_RATIOS = (1.0, 1.25, 1.5, 2.0, 3.0)
+
+
+def frame_psnr(torch, img, ref) -> float:
+    mse = float(torch.mean((img - ref) ** 2).item())
+    return float("inf") if mse == 0.0 else -10.0 * np.log10(mse)
+
+
+class FrameJudge:
+    """Full-detail reference frames of an animated crowd and the PSNR of any
+    LoD rule's frames against them (one fused context, eager frames)."""
+
+    def __init__(self, torch, scene, frames, tile=(32, 16)):
+        self.torch, self.scene = torch, scene
+        self.poses = torch.from_numpy(scene.frame_poses).cuda()
+        self.r = cs.Renderer(0, fuse=True, tile=tile)
+        self.r.upload_templates(scene.templates)
+        self.r.set_crowd(scene.crowd)
+        self.ref = {}
+        for k in frames:
+            self.ref[k] = self.render(k, (cs.CS_LOD_FULL, (), 0, 0.0)).clone()
+
+    def render(self, k, lod, floor=FLOOR):
+        mode, thr, mlp_ptr, margin = lod
+        self.r.pose_dev.copy_(self.poses[k])
+        self.r.select_lod(self.scene.camera, mode, thr, mlp_ptr=mlp_ptr, psnr_min=floor, margin=margin)
+        self.r.skin()
+        return self.r.render(self.scene.camera, stats=True)
+
+    def evaluate(self, lod, frames, floor=FLOOR):
+        """(min PSNR over the frames, mean drawn Gaussians per frame)."""
+        ps, ns = [], []
+        for k in frames:
+            img = self.render(k, lod, floor)
+            ns.append(int(self.r.last_stats.n_splats))
+            ps.append(frame_psnr(self.torch, img, self.ref[k]))
+        return float(min(ps)), float(np.mean(ns))
+
+    def close(self):
+        self.r.close()
+
+
+def tune_frame_rules(torch, scene, mlp_ptr, floor=FLOOR, tune=TUNE_FRAMES, hold=HOLD_FRAMES, tile=(32, 16),
+                     extra_db=TUNE_EXTRA_DB, log=print):
+    """Both rules tuned on the ``tune`` frames so that every one of them keeps
+    PSNR >= floor + extra_db against full detail, then judged on the ``hold``
+    frames (the floor itself):
+    * fixed distance, 5 levels: thresholds d_k = d_1 r^(k-1); for each ratio r
+      the smallest d_1 (bisection, 12 steps in [0.5, 400] m) meeting the
+      target, and of those the one drawing the fewest Gaussians;
+    * learned, frame budget: the smallest margin (bisection, 12 steps in
+      [-40, 10] dB) meeting it. The predicted errors are those of each avatar
+      alone on black over its whole window; in the crowd nearer avatars hide
+      much of that, so the margin that calibrates the predicted total to the
+      frame's error is negative."""
+    judge = FrameJudge(torch, scene, tuple(tune) + tuple(hold), tile)
+    target = floor + extra_db
+    fixed = []
+    for ratio in FIXED_RATIOS:
+        lo, hi = 0.5, 400.0
+        th = lambda d: tuple(float(d * ratio ** k) for k in range(4))  # noqa: E731
+        if judge.evaluate((cs.CS_LOD_FIXED, th(hi), 0, 0.0), tune)[0] < target:
+            continue
+        for _ in range(12):
+            mid = float(np.sqrt(lo * hi))
+            if judge.evaluate((cs.CS_LOD_FIXED, th(mid), 0, 0.0), tune)[0] >= target:
+                hi = mid
+            else:
+                lo = mid
+        p, n = judge.evaluate((cs.CS_LOD_FIXED, th(hi), 0, 0.0), tune)
+        fixed.append(dict(ratio=ratio, thresholds=list(th(hi)), tune_min_psnr=p, tune_gauss=n))
+        log(f"fixed ratio {ratio}: d1 {hi:.2f} m, {n / 1e6:.1f}M Gaussians, min PSNR {p:.2f} dB")
+    best = min(fixed, key=lambda f: f["tune_gauss"])
+    lo, hi = -40.0, 10.0
+    for _ in range(12):
+        mid = 0.5 * (lo + hi)
+        p, n = judge.evaluate((cs.CS_LOD_BUDGET, (), mlp_ptr, mid), tune, floor)
+        log(f"budget margin {mid:.3f} dB: {n / 1e6:.1f}M Gaussians, min PSNR {p:.2f} dB")
+        if p >= target:
+            hi = mid
+        else:
+            lo = mid
+    margin = hi
+    p, n = judge.evaluate((cs.CS_LOD_BUDGET, (), mlp_ptr, margin), tune, floor)
+    out = dict(floor=floor, target_db=target, tune_frames=list(tune), hold_frames=list(hold),
+               fixed_candidates=fixed, fixed_thresholds=best["thresholds"], fixed_tune_gauss=best["tune_gauss"],
+               budget_margin=margin, budget_tune_min_psnr=p, budget_tune_gauss=n)
+    for name, lod in [("fixed", (cs.CS_LOD_FIXED, tuple(best["thresholds"]), 0, 0.0)),
+                      ("budget", (cs.CS_LOD_BUDGET, (), mlp_ptr, margin))]:
+        p, n = judge.evaluate(lod, hold, floor)
+        out[f"{name}_hold_min_psnr"], out[f"{name}_hold_gauss"] = p, n
+    judge.close()
+    log(out)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--views", type=int, default=200_000)
@@ -76,11 +179,29 @@ def main(argv=None):
     ap.add_argument("--gauss", type=int, default=100_000)
     ap.add_argument("--coverage", type=float, default=0.99)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "lod_net.npz"))
+    ap.add_argument("--frame-rules", action="store_true",
+                    help="with the saved network: tune the fixed-distance thresholds and the frame-budget "
+                         "margin to the frame PSNR of the 3,500-avatar animation and write "
+                         "lod_frame_rules.json next to the network")
     args = ap.parse_args(argv)
     import torch
 
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
+
+    if args.frame_rules:
+        import json
+
+        templates = [synth.make_template(t, args.gauss, 3, synth.C4_LEVELS) for t in range(14)]
+        scene = synth.scene_c3(templates=templates, n_frames=300)
+        z = np.load(args.out, allow_pickle=False)
+        net = torch.from_numpy(z["net"]).cuda()
+        rules = tune_frame_rules(torch, scene, net.data_ptr(), log=log)
+        path = os.path.join(os.path.dirname(args.out), "lod_frame_rules.json")
+        with open(path, "w") as f:
+            json.dump(rules, f, indent=1)
+        print(json.dumps(rules), flush=True)
+        return
 
     t0 = time.time()
     templates = [synth.make_template(t, args.gauss, 3, synth.C4_LEVELS) for t in range(14)]

@@ -235,3 +235,68 @@ def test_trained_network_beats_fixed_distance_lod():
     print(f"learned {g_l:.0f} G/instance ({ok_l:.3f} ok), fixed {g_f:.0f} G/instance ({ok_f:.3f} ok)")
     assert ok_l >= 0.97 and ok_f >= 0.97
     assert g_l < g_f
+
+
+def test_frame_budget_selection_matches_oracle():
+    """CS_LOD_BUDGET inside cs_select_lod: label windows and per-level SSE of
+    every instance against the oracle (from the device's own predictions);
+    the levels are the oracle's choice at the device's lambda (except where
+    two levels cost the same within float32 rounding), their summed SSE stays
+    within the frame budget, and the oracle's own bisection finds the same
+    lambda up to where float32 and FP64 sums straddle the budget."""
+    import torch
+
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    templates, crowd, cam = _scene(n_inst=300)
+    r = _renderer(templates, crowd)
+    dev, host = _net(r)
+    n = crowd.n
+    counts = np.zeros((n, 5))
+    top = np.zeros(n, np.int64)
+    win = np.zeros(n)
+    near_edge = np.zeros(n, bool)
+    for i in range(n):
+        t = templates[int(crowd.tid[i])]
+        lc = np.asarray(t.level_count, np.float64)
+        counts[i, :len(lc)] = lc
+        top[i] = min(len(lc), 5) - 1
+        joints = olod.posed_joints(t, crowd.pose[i], float(crowd.yaw[i]), float(crowd.pos[i, 0]),
+                                   float(crowd.pos[i, 1]))
+        box, clip = olod.view_box(joints, olod.pad_radius(t), cam)
+        win[i] = olod.label_window_px(clip, cam.width, cam.height)
+        if clip is not None:  # a clipped edge within float32 reach of a 16-px tile edge
+            e = np.asarray(clip)
+            near_edge[i] = np.any(np.abs(e / 16.0 - np.round(e / 16.0)) * 16.0 < 2e-3)
+    mixed = 0
+    for floor, margin in [(40.0, 0.0), (43.0, 0.0), (38.0, 1.0), (20.0, 0.0)]:
+        print(f"budget selection: floor {floor} margin {margin}", flush=True)
+        lvl = torch.zeros(n, dtype=torch.int32, device="cuda")
+        r.select_lod(cam, cs.CS_LOD_BUDGET, (), level_out=lvl, psnr_min=floor, margin=margin,
+                     mlp_ptr=dev.data_ptr())
+        lv = lvl.cpu().numpy().astype(np.int64)
+        pred = r.debug("PRED", np.float32, n * 16).reshape(n, 16).astype(np.float64)
+        assert np.all((pred[:, 13] == win) | near_edge)
+        sse = olod.level_sse(pred[:, :5], pred[:, 13], top)
+        np.testing.assert_allclose(pred[:, 8:13], sse, rtol=2e-6, atol=0)
+        budget = olod.frame_budget(cam.width, cam.height, floor + margin)
+        t_dev = pred[0, 14]
+        assert np.all(pred[:, 14] == t_dev)
+        got_sse = sse[np.arange(n), lv].sum()
+        assert got_sse <= budget * (1 + 1e-5), (got_sse, budget)
+        want = olod.choose_levels(sse, counts, top, 2.0 ** t_dev)
+        cost = counts + 2.0 ** t_dev * sse
+        cost = np.where(np.arange(5)[None] <= top[:, None], cost, np.inf)
+        srt = np.sort(cost, axis=1)
+        tie = (srt[:, 1] - srt[:, 0]) <= 1e-5 * srt[:, 1]
+        assert np.all((lv == want) | tie)
+        lv_o, t_o = olod.select_budget(sse, counts, top, budget)
+        same = np.mean(lv_o == lv)
+        print(f"  device t {t_dev:.6f}, oracle t {t_o:.6f}, {same:.4f} of the levels equal, "
+              f"level histogram {np.bincount(lv, minlength=5)}")
+        if abs(t_o - t_dev) > 1e-4:  # the bisections parted where a total sat on the budget
+            mid_sse = sse[np.arange(n), olod.choose_levels(sse, counts, top, 2.0 ** min(t_o, t_dev))].sum()
+            assert abs(mid_sse - budget) <= 1e-4 * budget
+        assert same >= 0.99
+        mixed += len(set(lv.tolist())) >= 2
+    assert mixed >= 2  # budgets that are neither all-fine nor all-coarse were exercised

@@ -268,6 +268,45 @@ def test_c2_slice_fused_matches_oracle():
     print("C2 slice fused", info)
 
 
+def test_blend_evaluation_counters():
+    """Instrumented frames count the compositing evaluations without changing
+    the image: every splat a pixel adds was evaluated live for it (the FP64
+    oracle's count over the device's lists bounds the count from below), no
+    pixel evaluates more than its tile's list, and lane slots cover the live
+    evaluations. Uninstrumented frames report none."""
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    sc = _small_c2_scene(n_inst=6)
+    rp, img_p = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, profile=True)
+    st = rp.last_stats
+    _, img = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds)
+    assert np.array_equal(img_p, img)
+    g = gpu_frame_buffers(rp, sc.crowd.n)
+    cam = sc.camera
+    tw, th = 16, 16
+    ntx = -(-cam.width // tw)
+    lens = (g["ranges"][:, 1] - g["ranges"][:, 0]).astype(np.int64)
+    upper = 0
+    for t in range(len(lens)):
+        ty, tx = divmod(t, ntx)
+        w = min(tw, cam.width - tx * tw)
+        h = min(th, cam.height - ty * th)
+        upper += int(lens[t]) * w * h
+    added = 0
+    drec = device_records(g["rec"])
+    for t in np.nonzero(lens)[0]:
+        ty, tx = divmod(int(t), ntx)
+        gy, gx = np.mgrid[ty * th:min((ty + 1) * th, cam.height), tx * tw:min((tx + 1) * tw, cam.width)]
+        s0, s1 = g["ranges"][t]
+        _, _, _, n_added = osplat._blend_list_chunked(gx.ravel() * 1.0, gy.ravel() * 1.0,
+                                                       g["svals"][s0:s1].astype(np.int64), drec, cam.bg, 0, 0)
+        added += int(n_added.sum())
+    print(f"evals {st.blend_evals}, slots {st.blend_eval_slots}, added {added}, list bound {upper}")
+    assert 0 < added <= st.blend_evals <= min(upper, st.blend_eval_slots)
+    r = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds)[0]
+    assert r.last_stats.blend_evals == 0 and r.last_stats.blend_eval_slots == 0
+
+
 def test_determinism_and_graph_replay():
     import torch
 
