@@ -254,7 +254,8 @@ def time_mode(torch, rs, scene, poses_all, imgs, streams, lod, steps, warmup):
     for i, (ri, im, st) in enumerate(zip(rs, imgs, streams)):
         with torch.cuda.stream(st):
             ri.reserve(0, int(max_splats * 1.05) + 1024, int(max_pairs * 1.3) + 65536)
-            ring = poses_all[i::n].contiguous()
+            idx = [(i + n * j) % n_frames for j in range(max(1, n_frames // n))]
+            ring = poses_all[idx].contiguous()
             rings.append(ring)
             ri.set_pose_ring(ring, first=0)
             ri.capture(scene.camera, im, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
@@ -550,6 +551,30 @@ def psnr(a, b):
     return float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)
 
 
+def copy_bandwidth(torch, stream, nbytes=1 << 30, reps=10):
+    """Achievable HBM bandwidth: the library's copy kernel over 1 GiB (read +
+    write bytes per second), HIP events on its stream."""
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    with torch.cuda.stream(stream):
+        r = cs.Renderer(0, stream=stream)
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        r.copy(b, a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            r.copy(b, a)
+        e1.record(stream)
+        stream.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        ok = bool(torch.equal(a, b))
+        r.close()
+        del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9, ok
+
+
 def load_rules(path):
     if not os.path.exists(path):
         return None
@@ -573,6 +598,10 @@ def main():
     ap.add_argument("--sweep", default="", choices=["", "tab2", "tab1", "paper_lod"],
                     help="instead of the headline: the Tab. 2 FPS sweep, the Tab. 1 memory sweep, or the "
                          "paper's LoD schedule (one JSON line per cell)")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 500-avatar crowd")
+    ap.add_argument("--frames", type=int, default=300,
+                    help="frames of the animation the timed replays cycle through (1: every replay draws frame 0, "
+                         "a fixed workload for counter runs)")
     ap.add_argument("--inflight", type=int, default=3,
                     help="frames in flight: contexts (one stream each) that consecutive frames alternate between")
     args = ap.parse_args()
@@ -619,7 +648,7 @@ def main():
     stream = torch.cuda.Stream()
     dev = torch.device("cuda", 0)
     with torch.cuda.stream(stream):
-        poses_all = torch.from_numpy(scene.frame_poses).to(dev)
+        poses_all = torch.from_numpy(scene.frame_poses[:max(1, args.frames)]).to(dev)
         net_dev = torch.from_numpy(netinfo["net"]).to(dev)
     # LoD rules, each at >= 40 dB frame PSNR against full detail on held-out frames
     modes = {
@@ -669,11 +698,13 @@ def main():
     single = run(modes[head], 1) if len(streams) > 1 else results[head]
     log(f"{head}, one frame in flight: {1000.0 / single['ms']:.1f} FPS")
     # the fixed 10 / 25 m rule on the 500-avatar, 50 x 50 m crowd (3 of the 5 levels: 100 / 25 / 6.25 %)
-    sc2 = synth.scene_c2(templates=templates)
-    with torch.cuda.stream(stream):
-        poses2 = torch.from_numpy(np.ascontiguousarray(sc2.crowd.pose[None], np.float32)).to(dev)
-    c2 = run((cs.CS_LOD_FIXED, (10.0, 10.0, 25.0, 25.0), 0, 0.0), len(streams), sc=sc2, poses=poses2)
-    log(f"500 avatars, 10/25 m: {1000.0 / c2['ms']:.1f} FPS")
+    c2 = None
+    if not args.no_c2:
+        sc2 = synth.scene_c2(templates=templates)
+        with torch.cuda.stream(stream):
+            poses2 = torch.from_numpy(np.ascontiguousarray(sc2.crowd.pose[None], np.float32)).to(dev)
+        c2 = run((cs.CS_LOD_FIXED, (10.0, 10.0, 25.0, 25.0), 0, 0.0), len(streams), sc=sc2, poses=poses2)
+        log(f"500 avatars, 10/25 m: {1000.0 / c2['ms']:.1f} FPS")
 
     res = results[head]
     ms = res["ms"]
@@ -685,10 +716,10 @@ def main():
     # ---- per-stage timing: instrumented eager frames (HIP events on the launch
     # stream around each stage, blend evaluations counted). First the timed
     # configuration (skinning fused into projection), then separate skinning.
-    def stage_profile(fuse):
+    def stage_profile(fuse, count=False):
         with torch.cuda.stream(stream):
             img = torch.zeros((3, scene.camera.height, scene.camera.width), device=dev)
-            rp = cs.Renderer(0, stream=stream, fuse=fuse, profile=True, tile=tile)
+            rp = cs.Renderer(0, stream=stream, fuse=fuse, profile=True, tile=tile, count_blend=count)
             rp.upload_templates(scene.templates)
             rp.set_crowd(scene.crowd)
             lvl_out = torch.zeros(scene.crowd.n, dtype=torch.int32, device=dev)
@@ -710,8 +741,9 @@ def main():
             rp.close()
         return {k: float(np.mean(v)) for k, v in acc.items()}, lvl_out.cpu().numpy().astype(np.int64), stp, evals
 
-    stage_ms, levels, stp, evals = stage_profile(True)
+    stage_ms, levels, stp, _ = stage_profile(True)
     stage_unfused, _, _, _ = stage_profile(False)
+    _, _, _, evals = stage_profile(True, count=True)  # the counting blend is slower: only its counts are used
     uniq = unique_template_gaussians(scene, levels)
     stats = dict(n_splats=int(stp.n_splats), n_pairs=int(stp.n_pairs))
     stage_ms = {("project_fused" if k == "project" else k): v for k, v in stage_ms.items()}
@@ -722,13 +754,18 @@ def main():
         if stage_ms.get(name, 0.0) > 0:
             stage_gbs[name] = algorithmic_bytes(name, stats, scene, uniq) / (stage_ms[name] * 1e-3) / 1e9
     ev = np.array(evals, np.float64)
+    blend_ms = stage_ms["blend"]  # the uncounting kernel of the same frames
     blend = {"evals_per_frame": int(ev[:, 0].mean()), "eval_slots_per_frame": int(ev[:, 1].mean()),
-             "pairs_per_frame": int(ev[:, 2].mean()), "blend_ms": round(float(ev[:, 3].mean()), 4),
-             "evals_per_s_per_cu": round(float((ev[:, 0] / (ev[:, 3] * 1e-3)).mean()) / N_CU, 1),
-             "eval_slots_per_s_per_cu": round(float((ev[:, 1] / (ev[:, 3] * 1e-3)).mean()) / N_CU, 1),
+             "pairs_per_frame": int(ev[:, 2].mean()), "blend_ms": round(blend_ms, 4),
+             "evals_per_s_per_cu": round(float(ev[:, 0].mean() / (blend_ms * 1e-3)) / N_CU, 1),
+             "eval_slots_per_s_per_cu": round(float(ev[:, 1].mean() / (blend_ms * 1e-3)) / N_CU, 1),
              "live_fraction_of_slots": round(float(ev[:, 0].sum() / max(ev[:, 1].sum(), 1.0)), 4),
              "evals_per_pair": round(float(ev[:, 0].sum() / max(ev[:, 2].sum(), 1.0)), 3)}
     roofline = frame_roofline(stage_ms, stats, scene, uniq, tile, blend)
+    copy_gbs, copy_ok = copy_bandwidth(torch, stream)
+    if roofline.get("hbm"):
+        roofline["hbm"]["frac_of_copy"] = round(roofline["hbm"]["achieved"] / copy_gbs, 4)
+    stage_copy_frac = {k: round(v / copy_gbs, 4) for k, v in stage_gbs.items()}
 
     # ---- quality: every rule's frames against full-detail frames, on the
     # frames the rules were not tuned on (and on frame 0)
@@ -769,11 +806,13 @@ def main():
         "lod_comparison": lod_cmp,
         "lod_rules": {"budget_margin_db": rules["budget_margin"], "fixed_thresholds_m": rules["fixed_thresholds"],
                       "tuned_on_frames": rules["tune_frames"], "target_db": rules.get("target_db")},
-        "c2_500_avatars_fixed_10_25m": {"fps": round(1000.0 / c2["ms"], 2), "n_splats": int(c2["stats"].n_splats),
-                                        "n_pairs": int(c2["stats"].n_pairs), "overflow": c2["overflow"],
-                                        "level_hist": list(c2["stats"].level_hist)[:5]},
+        "c2_500_avatars_fixed_10_25m": None if c2 is None else {
+            "fps": round(1000.0 / c2["ms"], 2), "n_splats": int(c2["stats"].n_splats),
+            "n_pairs": int(c2["stats"].n_pairs), "overflow": c2["overflow"],
+            "level_hist": list(c2["stats"].level_hist)[:5]},
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "stage_gbs": {k: round(v, 1) for k, v in stage_gbs.items()},
+        "copy_gbs": round(copy_gbs, 1), "copy_ok": copy_ok, "stage_frac_of_copy": stage_copy_frac,
         "blend": blend,
         "roofline": roofline, "cpu_baseline": cpu,
     }

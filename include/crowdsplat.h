@@ -79,7 +79,10 @@ typedef struct cs_options {
   int64_t max_pairs;         /* fixed tile-pair capacity (0: grow on demand)    */
   int32_t sort_algo;         /* CS_SORT_TILE_BUCKET (default) | _ONESWEEP | _REDUCE_SCAN */
   int32_t sort_ranks;        /* CS_SORT_RANKS_CHECKED (default) | CS_SORT_RANKS_BALLOT  */
-  int32_t reserved[6];
+  int32_t count_blend;       /* 1 (with profile_stages): count the compositing
+                                evaluations (cs_frame_stats.blend_evals; a
+                                slower instrumented blend)                      */
+  int32_t reserved[5];
 } cs_options;
 
 /* How the tile-bucket form's LDS segment sort ranks radix digits inside a
@@ -165,7 +168,8 @@ typedef struct cs_lod_params {
  * ties to the finer level) for the smallest lambda, on a 30-step bisection
  * of log2(lambda) in [-40, 60], whose total stays within that budget
  * (overlaps between instances are ignored; the margin absorbs them).
- * BUDGET needs psnr_min + margin in (0, 200) dB. */
+ * BUDGET needs psnr_min + margin in (-200, 200) dB (CS_ERR_INVALID) and at
+ * most 8,192 instances (CS_ERR_UNSUPPORTED). */
 
 /* The learned-LoD network (device memory, laid out exactly as below).
  * Inputs: 32 features (31 used, see cs_lod_features) z-scored with mu and
@@ -199,10 +203,10 @@ typedef struct cs_frame_stats {
   int32_t level_hist[CS_MAX_LEVELS];
   int32_t sort_fallbacks;    /* LDS-sorted segments re-sorted with ballot ranks */
   int32_t reserved0;
-  int64_t blend_evals;       /* profile_stages only: (pixel, splat) opacity
+  int64_t blend_evals;       /* count_blend only: (pixel, splat) opacity
                                 evaluations the blend ran for pixels still
                                 compositing; else 0                           */
-  int64_t blend_eval_slots;  /* profile_stages only: lane evaluation slots the
+  int64_t blend_eval_slots;  /* count_blend only: lane evaluation slots the
                                 blend issued (the live ones plus lanes idle
                                 in a wave's step: finished pixels, shorter
                                 group lists); else 0                          */
@@ -495,6 +499,13 @@ cs_status cs_stage_times(cs_ctx* ctx, float* ms, int32_t n);
  * the same onesweep kernels that order the frame's tile pairs. DEVICE buffers;
  * keys/vals are sorted in place (the context's pair buffers are the scratch). */
 cs_status cs_sort_pairs(cs_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits);
+
+/* Plain device-to-device copy of `bytes` bytes (16-byte loads and stores,
+ * a grid-stride loop of 256-thread workgroups): the achievable-bandwidth
+ * reference for the stages' HBM roofline fractions and the calibration of
+ * the byte counters. DEVICE buffers, 16-byte aligned (CS_ERR_INVALID
+ * otherwise), not overlapping; asynchronous on the context's stream. */
+cs_status cs_copy(cs_ctx* ctx, void* dst, const void* src, int64_t bytes);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, serving loops, harnesses that forbid hipMalloc): cs_sort_pairs

@@ -42,7 +42,7 @@ EXPORTS = ["cs_create", "cs_destroy", "cs_last_error", "cs_version", "cs_upload_
            "cs_sort_pairs", "cs_stage_times", "cs_lod_features", "cs_mlp_predict", "cs_mlp_sync",
            "cs_mlp_train_step", "cs_render_views", "cs_view_psnr", "cs_update_template", "cs_fit_loss",
            "cs_adam", "cs_materialise_instances", "cs_memory_report",
-           "cs_frame_capture_render", "cs_set_pose_ring", "cs_upload_pose_net", "cs_sort_pairs_noalloc"]
+           "cs_frame_capture_render", "cs_set_pose_ring", "cs_upload_pose_net", "cs_sort_pairs_noalloc", "cs_copy"]
 STAGES = ["lod", "fk", "skin", "project", "scan", "emit", "sort", "ranges", "blend", "segsort", "offsets"]
 
 
@@ -52,7 +52,7 @@ class CsOptions(ctypes.Structure):
                 ("fuse_skin_project", ctypes.c_int32), ("profile_stages", ctypes.c_int32),
                 ("max_splats", ctypes.c_int64), ("max_pairs", ctypes.c_int64),
                 ("sort_algo", ctypes.c_int32), ("sort_ranks", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("count_blend", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class CsTemplateDesc(ctypes.Structure):
@@ -164,6 +164,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "cs_debug_copy": (i32, [P, i32, P, i64, i64]),
         "cs_sort_pairs": (i32, [P, P, P, i64, i32]),
         "cs_sort_pairs_noalloc": (i32, [P, P, P, i64, i32]),
+        "cs_copy": (i32, [P, P, P, i64]),
         "cs_materialise_instances": (i32, [P, i32, P]),
         "cs_memory_report": (i32, [P, ctypes.POINTER(CsMemoryStats)]),
         "cs_stage_times": (i32, [P, ctypes.POINTER(ctypes.c_float), i32]),
@@ -224,7 +225,8 @@ class Renderer:
 
     def __init__(self, device: int = 0, stream=None, tile=(16, 16), skin_mode=CS_SKIN_FULL,
                  launch_mode=CS_LAUNCH_BATCHED, fuse=False, max_splats=0, max_pairs=0,
-                 profile=False, sort_algo=CS_SORT_TILE_BUCKET, sort_ranks=CS_SORT_RANKS_CHECKED):
+                 profile=False, sort_algo=CS_SORT_TILE_BUCKET, sort_ranks=CS_SORT_RANKS_CHECKED,
+                 count_blend=False):
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -236,6 +238,7 @@ class Renderer:
         opt.profile_stages = int(profile)
         opt.sort_algo = sort_algo
         opt.sort_ranks = sort_ranks
+        opt.count_blend = int(count_blend)
         opt.max_splats, opt.max_pairs = max_splats, max_pairs
         self.tile = tuple(tile)
         ctx = ctypes.c_void_p()
@@ -502,6 +505,13 @@ class Renderer:
     def sort_pairs(self, keys, vals, key_bits: int):
         self._check(self.lib.cs_sort_pairs(self.ctx, keys.data_ptr(), vals.data_ptr(),
                                            keys.numel(), key_bits))
+
+    def copy(self, dst, src, nbytes=None):
+        """Device copy with the library's copy kernel (bandwidth reference)."""
+        nb = src.numel() * src.element_size() if nbytes is None else nbytes
+        assert dst.numel() * dst.element_size() >= nb
+        self._hold(dst, src)
+        self._check(self.lib.cs_copy(self.ctx, dst.data_ptr(), src.data_ptr(), nb))
 
     def sort_pairs_noalloc(self, keys, vals, key_bits: int, n=None):
         """The same sort with the library's fixed per-device scratch

@@ -11,6 +11,7 @@ namespace cs {
 constexpr int kJoints = 24;
 constexpr int kChunk = 2048;          // Gaussians per work chunk (one instance each)
 constexpr int kChunkThreads = 256;    // threads per skin / project block
+constexpr int kXcds = 8;              // accelerator complex dies, each with its own L2
 constexpr int kMaxLevels = CS_MAX_LEVELS;
 constexpr int kMaxTemplates = CS_MAX_TEMPLATES;
 constexpr int kSortBits = 11;         // radix digit width of the onesweep passes
@@ -134,6 +135,24 @@ struct Chunk {
   int32_t inst;
   int32_t g0;
 };
+
+// XCD-aware order of a persistent launch over n equal work items: the GPU
+// deals workgroups to its XCDs round-robin by workgroup index, so block b
+// (of G) takes the items of one contiguous n/8 range (its XCD's), striding by
+// the number of blocks on that XCD. Consecutive items (the instances that
+// read one template chunk, in the template-major work list) then share one
+// L2 instead of being fetched into all eight.
+struct XcdSpan {
+  int first, step, end;
+};
+__device__ __forceinline__ XcdSpan xcd_span(int b, int G, int n) {
+  if (G < kXcds) return XcdSpan{b, G, n};
+  const int x = b % kXcds, j = b / kXcds;
+  const int nb = (G - x + kXcds - 1) / kXcds;
+  const int per = (n + kXcds - 1) / kXcds;
+  const int lo = min(x * per, n), hi = min(lo + per, n);
+  return XcdSpan{lo + j, nb, hi};
+}
 
 // Camera constants passed by value to kernels.
 struct CamDev {

@@ -258,18 +258,30 @@ hipError_t launch_mlp_infer(const cs_mlp* net, const float* feat, int n, float* 
 constexpr int kBudgetIters = 30;
 constexpr float kBudgetLo = -40.f, kBudgetHi = 60.f;
 
-__device__ __forceinline__ int budget_choose(const float* __restrict__ p, const TemplateDev& T, int top, float lam) {
+// Level of the smallest n_l + lam sse_l over l <= top (the first of equal
+// costs), with its error and Gaussians; fully unrolled so the per-level
+// values stay in registers.
+__device__ __forceinline__ int budget_choose(const float (&cnt)[5], const float (&sse)[5], int top, float lam,
+                                             float& sse_out, float& cnt_out) {
   int best = 0;
-  float best_c = (float)T.level_count[0];
-  for (int l = 1; l <= top; ++l) {
-    const float c = fmaf(lam, p[8 + l], (float)T.level_count[l]);
-    if (c < best_c) {
-      best_c = c;
-      best = l;
-    }
+  float best_c = cnt[0], best_s = sse[0], best_n = cnt[0];
+#pragma unroll
+  for (int l = 1; l < 5; ++l) {
+    const float c = fmaf(lam, sse[l], cnt[l]);
+    const bool better = l <= top && c < best_c;
+    best_c = better ? c : best_c;
+    best_s = better ? sse[l] : best_s;
+    best_n = better ? cnt[l] : best_n;
+    best = better ? l : best;
   }
+  sse_out = best_s;
+  cnt_out = best_n;
   return best;
 }
+
+// Per-level Gaussians and predicted errors of the instances this thread
+// handles (i = t, t + 1024, ...), held in registers for the bisection.
+constexpr int kBudgetPer = 8;  // instances per thread: n <= 8,192
 
 __global__ __launch_bounds__(1024) void lod_budget_kernel(float* __restrict__ pred, const float* __restrict__ joints,
                                                           const cs_instance* __restrict__ inst,
@@ -279,16 +291,26 @@ __global__ __launch_bounds__(1024) void lod_budget_kernel(float* __restrict__ pr
   __shared__ float s_part[16];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   constexpr float kLog2_10_over_10 = 0.33219280948873624f;
-  // every value a thread reads below it wrote itself (instances t, t + 1024, ...)
-  for (int i = t; i < n; i += 1024) {
+  float cnt[kBudgetPer][5], sse[kBudgetPer][5];
+  int top[kBudgetPer];
+#pragma unroll
+  for (int k = 0; k < kBudgetPer; ++k) {
+    const int i = t + 1024 * k;
+    top[k] = -1;  // no instance, or no template: contributes nothing
+#pragma unroll
+    for (int l = 0; l < 5; ++l) cnt[k][l] = sse[k][l] = 0.f;
+    if (i >= n) continue;
     float* p = pred + (size_t)i * 16;
     const int tid = inst[i].tid;
     float win = 0.f;
-    int top = 0;
+    int tp = 0;
     if (tid >= 0 && tid < n_tpl) {
-      top = min(tpl[tid].n_levels, 5) - 1;
+      const TemplateDev& T = tpl[tid];
+      tp = min(T.n_levels, 5) - 1;
+#pragma unroll
+      for (int l = 0; l < 5; ++l) cnt[k][l] = l <= tp ? (float)T.level_count[l] : 0.f;
       float box[4];
-      if (joint_box(joints + (size_t)i * kJoints * 3, tpl[tid].pad_radius, cam, box)) {
+      if (joint_box(joints + (size_t)i * kJoints * 3, T.pad_radius, cam, box)) {
         const float c0 = fmaxf(box[0], 0.f), c1 = fmaxf(box[1], 0.f);
         const float c2 = fminf(box[2], (float)cam.W), c3 = fminf(box[3], (float)cam.H);
         if (c2 > c0 && c3 > c1) {
@@ -298,25 +320,28 @@ __global__ __launch_bounds__(1024) void lod_budget_kernel(float* __restrict__ pr
           if (x1 > x0 && y1 > y0) win = (float)((x1 - x0) * (y1 - y0));
         }
       }
+      top[k] = tp;
     }
     p[8] = 0.f;
+#pragma unroll
     for (int l = 1; l < 5; ++l) {
       const float db = fminf(fmaxf(p[l], 0.f), 60.f);
-      p[8 + l] = l <= top ? 3.f * win * exp2f(-db * kLog2_10_over_10) : 0.f;
+      sse[k][l] = l <= tp ? 3.f * win * exp2f(-db * kLog2_10_over_10) : 0.f;
+      p[8 + l] = sse[k][l];
     }
     p[13] = win;
-    p[15] = (float)top;
+    p[15] = (float)tp;
   }
   float lo = kBudgetLo, hi = kBudgetHi;
   for (int it = 0; it < kBudgetIters; ++it) {
     const float mid = 0.5f * (lo + hi);
     const float lam = exp2f(mid);
     float acc = 0.f;
-    for (int i = t; i < n; i += 1024) {
-      const float* p = pred + (size_t)i * 16;
-      const int tid = inst[i].tid;
-      if (tid < 0 || tid >= n_tpl) continue;
-      acc += p[8 + budget_choose(p, tpl[tid], (int)p[15], lam)];
+#pragma unroll
+    for (int k = 0; k < kBudgetPer; ++k) {
+      float e, c;
+      budget_choose(cnt[k], sse[k], top[k], lam, e, c);
+      acc += top[k] >= 0 ? e : 0.f;
     }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
@@ -330,24 +355,27 @@ __global__ __launch_bounds__(1024) void lod_budget_kernel(float* __restrict__ pr
     else lo = mid;
   }
   const float lam = exp2f(hi);
-  for (int i = t; i < n; i += 1024) {
-    float* p = pred + (size_t)i * 16;
-    const int tid = inst[i].tid;
-    p[14] = hi;
-    if (tid < 0 || tid >= n_tpl) {
+#pragma unroll
+  for (int k = 0; k < kBudgetPer; ++k) {
+    const int i = t + 1024 * k;
+    if (i >= n) continue;
+    pred[(size_t)i * 16 + 14] = hi;
+    if (top[k] < 0) {
       level[i] = 0;
       count[i] = 0;
       continue;
     }
-    const int l = budget_choose(p, tpl[tid], (int)p[15], lam);
+    float e, c;
+    const int l = budget_choose(cnt[k], sse[k], top[k], lam, e, c);
     level[i] = l;
-    count[i] = (uint32_t)tpl[tid].level_count[l];
+    count[i] = (uint32_t)c;
   }
 }
 
 hipError_t launch_lod_budget(float* pred, const float* joints, const cs_instance* inst, const TemplateDev* tpl, int n,
                              int n_tpl, CamDev cam, float budget, int32_t* level, uint32_t* count, hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  if (n > 1024 * kBudgetPer) return hipErrorInvalidValue;
   lod_budget_kernel<<<1, 1024, 0, st>>>(pred, joints, inst, tpl, n, n_tpl, cam, budget, level, count);
   return hipGetLastError();
 }

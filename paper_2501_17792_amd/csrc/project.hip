@@ -106,7 +106,8 @@ __global__ __launch_bounds__(kChunkThreads) __attribute__((amdgpu_waves_per_eu(3
   float c0[3];  // R_c eye
 #pragma unroll
   for (int r = 0; r < 3; ++r) c0[r] = fmaf(R[3 * r], cam.eye[0], fmaf(R[3 * r + 1], cam.eye[1], R[3 * r + 2] * cam.eye[2]));
-  for (int c = chunk_lo + blockIdx.x; c < hi; c += gridDim.x) {
+  const XcdSpan sp = xcd_span(blockIdx.x, gridDim.x, hi - chunk_lo);
+  for (int c = chunk_lo + sp.first; c < chunk_lo + sp.end; c += sp.step) {
     const Chunk ch = w.chunks[c];
     const cs_instance in = w.inst[ch.inst];
     const TplCols T = TplCols::of(work_template(w, ch.inst, in.tid));

@@ -695,8 +695,10 @@ cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, co
   const bool learned = lod->mode == CS_LOD_LEARNED || lod->mode == CS_LOD_BUDGET;
   if (learned && (!lod->mlp || !pose))
     return ctx->fail(CS_ERR_INVALID, "learned LoD needs the network and the poses");
-  if (lod->mode == CS_LOD_BUDGET && !(lod->psnr_min + lod->margin > 0.f && lod->psnr_min + lod->margin < 200.f))
-    return ctx->fail(CS_ERR_INVALID, "the frame's PSNR floor plus margin must lie in (0, 200) dB");
+  if (lod->mode == CS_LOD_BUDGET && !(lod->psnr_min + lod->margin > -200.f && lod->psnr_min + lod->margin < 200.f))
+    return ctx->fail(CS_ERR_INVALID, "the frame's PSNR floor plus margin must lie in (-200, 200) dB");
+  if (lod->mode == CS_LOD_BUDGET && n_inst > 8192)
+    return ctx->fail(CS_ERR_UNSUPPORTED, "the frame-budget LoD selects for at most 8,192 instances");
   if (lod->mode == CS_LOD_CONSTANT && (lod->level < 0 || lod->level >= CS_MAX_LEVELS))
     return ctx->fail(CS_ERR_INVALID, "constant level out of range");
   if (ctx->n_copies && n_inst != ctx->n_copies)
@@ -920,8 +922,9 @@ static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs
   if (n_tiles > 0)
     HIP_TRY(launch_blend(ctx->ranges, ctx->vals[ctx->sorted], ctx->rec, cd, image, ctx->hdr, vp,
                          view_mode ? nullptr : ctx->tile_order, ctx->stream,
-                         ctx->opt.profile_stages && !ctx->capturing && !view_mode ? &ctx->hdr->blend_evals
-                                                                                    : nullptr));
+                         ctx->opt.profile_stages && ctx->opt.count_blend && !ctx->capturing && !view_mode
+                             ? &ctx->hdr->blend_evals
+                             : nullptr));
   ctx->mark(CS_STAGE_BLEND, 1);
   ctx->state = kRendered;
   if (stats) {
@@ -1420,6 +1423,32 @@ cs_status cs_sort_pairs(cs_ctx* ctx, uint64_t* keys, uint32_t* vals, int64_t n, 
   }
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   if (ctx->state > kSkinned) ctx->state = kSkinned;  // the frame's pair buffers were reused
+  return CS_OK;
+}
+
+namespace {
+// 16-byte loads and stores, grid-stride; the tail (bytes % 16) byte by byte
+__global__ __launch_bounds__(256) void copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                   int64_t n16, const unsigned char* __restrict__ src_b,
+                                                   unsigned char* __restrict__ dst_b, int64_t bytes) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+  for (int64_t i = n16 * 16 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < bytes; i += stride)
+    dst_b[i] = src_b[i];
+}
+}  // namespace
+
+cs_status cs_copy(cs_ctx* ctx, void* dst, const void* src, int64_t bytes) {
+  if (!ctx) return CS_ERR_INVALID;
+  if (bytes < 0 || (bytes > 0 && (!dst || !src))) return ctx->fail(CS_ERR_INVALID, "bad copy arguments");
+  if ((uintptr_t)dst % 16 || (uintptr_t)src % 16) return ctx->fail(CS_ERR_INVALID, "copy buffers must be 16-byte aligned");
+  if (bytes == 0) return CS_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  const int64_t n16 = bytes / 16;
+  const int grid = (int)std::min<int64_t>(8192, std::max<int64_t>(1, (n16 + 255) / 256));
+  copy_kernel<<<grid, 256, 0, ctx->stream>>>((const float4*)src, (float4*)dst, n16, (const unsigned char*)src,
+                                             (unsigned char*)dst, bytes);
+  HIP_TRY(hipGetLastError());
   return CS_OK;
 }
 

@@ -454,7 +454,8 @@ __global__ __launch_bounds__(kChunkThreads) void skin_kernel(WorkDev w, SkinOut 
                                                              int chunk_hi) {
   __shared__ float s_bones[kJoints * 12];
   const int hi = chunk_hi >= 0 ? chunk_hi : (int)w.hdr->n_chunks;
-  for (int c = chunk_lo + blockIdx.x; c < hi; c += gridDim.x) {
+  const XcdSpan sp = xcd_span(blockIdx.x, gridDim.x, hi - chunk_lo);
+  for (int c = chunk_lo + sp.first; c < chunk_lo + sp.end; c += sp.step) {
     const Chunk ch = w.chunks[c];
     const cs_instance in = w.inst[ch.inst];
     const TplCols T = TplCols::of(work_template(w, ch.inst, in.tid));

@@ -277,7 +277,7 @@ def test_blend_evaluation_counters():
     from paper_2501_17792_amd import crowdsplat as cs
 
     sc = _small_c2_scene(n_inst=6)
-    rp, img_p = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, profile=True)
+    rp, img_p = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, profile=True, count_blend=True)
     st = rp.last_stats
     _, img = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds)
     assert np.array_equal(img_p, img)
@@ -303,8 +303,9 @@ def test_blend_evaluation_counters():
         added += int(n_added.sum())
     print(f"evals {st.blend_evals}, slots {st.blend_eval_slots}, added {added}, list bound {upper}")
     assert 0 < added <= st.blend_evals <= min(upper, st.blend_eval_slots)
-    r = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds)[0]
-    assert r.last_stats.blend_evals == 0 and r.last_stats.blend_eval_slots == 0
+    for kw in ({}, dict(profile=True)):
+        r = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, **kw)[0]
+        assert r.last_stats.blend_evals == 0 and r.last_stats.blend_eval_slots == 0
 
 
 def test_determinism_and_graph_replay():
@@ -362,6 +363,26 @@ def test_standalone_sort_bit_exact(n, bits, algo):
     order = np.argsort(keys, kind="stable")
     assert np.array_equal(kd.cpu().numpy().view(np.uint64), keys[order])
     assert np.array_equal(vd.cpu().numpy().view(np.uint32), vals[order])
+
+
+def test_copy_kernel():
+    """The bandwidth-reference copy: exact, ragged sizes, misaligned refused."""
+    import torch
+
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    r = cs.Renderer(0)
+    for nb in (16, 1000 * 16 + 7, (1 << 22) + 3):
+        a = torch.randint(0, 255, (nb,), dtype=torch.uint8, device="cuda")
+        b = torch.zeros_like(a)
+        r.copy(b, a)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), nb
+    a = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(cs.CrowdSplatError) as e:
+        r.copy(a[1:], a[:32], 16)
+    assert e.value.code == cs.CS_ERR_INVALID
+    r.close()
 
 
 def test_empty_frame_and_bad_calls():
