@@ -30,13 +30,12 @@ Tolerances (FP32 kernel vs FP64 oracle on the same FP32 inputs):
     outside the same bands widened splat by splat by how far the FP64 and
     the device's records put that alpha and T' apart (there the two records
     may legitimately decide differently);
-  flagged pixels are at most 1e-3 of the image in the compositing check and
-  5e-3 end to end (its mask holds every pixel where the float32 records
-  could decide differently from FP64; how many there are grows with the
-  splats a pixel evaluates: 0.03% to 0.3% on these scenes), and each flagged
-  pixel differs by at most cmax (2/255 + 1.01e-2) + 2e-3 (one skip flip
-  moves a pixel by at most 2 cmax / 255, one stop flip by at most
-  cmax T <= cmax 1e-2 plus the 1e-4 left after it).
+  a flagged pixel may miss the 2e-3 bar, but by at most
+  cmax (2/255 + 1.01e-2) + 2e-3 (one skip flip moves a pixel by at most
+  2 cmax / 255, one stop flip by at most cmax T <= cmax 1e-2 plus the 1e-4
+  left after it), and such pixels are at most 1e-3 of those compared. (How
+  many pixels are flagged grows with the splats a pixel evaluates; nearly
+  all of them still meet 2e-3.)
 """
 import numpy as np
 import pytest
@@ -54,8 +53,7 @@ pytestmark = pytest.mark.gpu
 BAND_ALPHA = 1e-5
 BAND_T = 1e-4
 POWER_ULPS = 8.0
-FRAGILE_MAX_COMPOSITE = 1e-3
-FRAGILE_MAX_E2E = 5e-3
+BEYOND_MAX = 1e-3  # share of the compared pixels that may miss 2e-3 (flagged ones only)
 
 
 def flag_bound(rgb):
@@ -81,33 +79,38 @@ def integer_key_oracle(R, cam, tw, th):
     return rect, cnt, vis, sk, sv, osplat.tile_ranges(sk, ntx * nty)
 
 
-def check_pixels(img, sp, svals, ranges, cam, tw, th, tiles=None, label="", sp_alt=None,
-                 fragile_max=FRAGILE_MAX_COMPOSITE):
+def check_pixels(img, sp, svals, ranges, cam, tw, th, tiles=None, label="", sp_alt=None):
     """FP64 compositing of records ``sp`` over the device's lists against the
     device image (on ``tiles`` or all); ``sp_alt`` (the device's records)
     widens the fragile bands by its distance from ``sp``. Returns (max-abs
-    outside the mask, flagged pixels, pixels compared)."""
+    outside the mask, flagged pixels, pixels beyond 2e-3, pixels compared)."""
     ref, _, frag = osplat.composite_tiled(sp, svals.astype(np.int64), ranges.astype(np.int64), cam.width,
                                           cam.height, tw, th, cam.bg, BAND_ALPHA, BAND_T, tiles=tiles,
                                           chunked=True, sp_alt=sp_alt, power_ulps=POWER_ULPS)
+    return judge_pixels(img, ref, frag, tiles, cam.width, cam.height, tw, th, flag_bound(sp["rgb"]), label)
+
+
+def judge_pixels(img, ref, frag, tiles, W, H, tw, th, bound, label):
     if tiles is None:
-        sel = np.ones((cam.height, cam.width), bool)
+        sel = np.ones((H, W), bool)
     else:
-        sel = np.zeros((cam.height, cam.width), bool)
-        ntx = -(-cam.width // tw)
+        sel = np.zeros((H, W), bool)
+        ntx = -(-W // tw)
         for t in tiles:
             ty, tx = divmod(int(t), ntx)
             sel[ty * th:(ty + 1) * th, tx * tw:(tx + 1) * tw] = True
     diff = np.abs(img - ref).max(axis=0)
     clean = sel & ~frag
     worst = float(diff[clean].max()) if clean.any() else 0.0
-    assert worst <= 2e-3, f"{label}: max-abs {worst} outside the fragile mask"
     nf = int((frag & sel).sum())
-    assert nf <= fragile_max * sel.sum() + 1, f"{label}: {nf} of {int(sel.sum())} pixels fragile"
-    if nf:
-        bound = flag_bound(sp["rgb"])
-        assert diff[frag & sel].max() <= bound, f"{label}: flagged pixel off by {diff[frag & sel].max()}"
-    return worst, nf, int(sel.sum())
+    beyond = int((sel & (diff > 2e-3)).sum())
+    fmax = float(diff[frag & sel].max()) if nf else 0.0
+    print(f"  {label}: max-abs {worst:.2e} outside the mask; {nf} of {int(sel.sum())} pixels flagged "
+          f"(max-abs {fmax:.2e}), {beyond} beyond 2e-3", flush=True)
+    assert worst <= 2e-3, f"{label}: max-abs {worst} outside the fragile mask"
+    assert fmax <= bound, f"{label}: flagged pixel off by {fmax}"
+    assert beyond <= BEYOND_MAX * sel.sum() + 1, f"{label}: {beyond} pixels beyond 2e-3"
+    return worst, nf, beyond, int(sel.sum())
 
 
 def _small_c2_scene(n_inst=12, n_gauss=20000, width=480, height=270):
@@ -208,11 +211,10 @@ def _compare_frame(scene, mode, thresholds, tile=(16, 16), setup=None, mean_fn=N
             assert not (d[1:] < d[:-1] * (1 - 2e-6)).any(), f"tile {tt} depth order"
     # ---- pixels over the device's lists: end to end, then compositing alone
     drec = device_records(g["rec"])
-    e2e = check_pixels(img, rec, g["svals"], g["ranges"], cam, tw, th, label="end to end", sp_alt=drec,
-                       fragile_max=FRAGILE_MAX_E2E)
+    e2e = check_pixels(img, rec, g["svals"], g["ranges"], cam, tw, th, label="end to end", sp_alt=drec)
     comp = check_pixels(img, drec, g["svals"], g["ranges"], cam, tw, th, label="compositing")
-    return r, img, rec, g, dict(e2e_max_abs=e2e[0], e2e_fragile=e2e[1], composite_max_abs=comp[0],
-                                composite_fragile=comp[1], pixels=e2e[2])
+    return r, img, rec, g, dict(e2e_max_abs=e2e[0], e2e_fragile=e2e[1], e2e_beyond=e2e[2], composite_max_abs=comp[0],
+                                composite_fragile=comp[1], composite_beyond=comp[2], pixels=e2e[3])
 
 
 def test_c1_plain_full_detail():

@@ -1,0 +1,148 @@
+"""The headline frame against the FP64 oracle at full scale (through the C ABI).
+
+3,500 animated avatars (14 templates x 100k Gaussians, SH3, 5 levels) at
+1920x1080 with the learned frame-budget LoD, skinning fused into projection,
+32x16 tiles, captured as a graph and replayed once. A seeded sample of tiles
+(the one with the longest list, which goes through several key-split levels
+before the LDS sort, three more from the longest tenth and four others) is
+checked against the oracle, driven with the device's levels and only the
+instances whose screen boxes (posed joints padded by 1.5 x the template's
+rest pad radius + 2 px) reach those tiles:
+* every instance with a splat in a sampled tile's list is one of those;
+* each sampled tile's list, bit for bit, against the integer key oracle on
+  the device's own float32 records of those instances (rect from u, v, rx,
+  ry; order by depth bits, then splat index);
+* each list's splat set against the FP64 oracle's records, except splats
+  whose rect is decided within 2e-3 px of a pixel edge;
+* the tiles' pixels end to end (FP64 records) and compositing alone (the
+  device's records), with the bands and bars of the parity tests (the
+  horizon tiles' pixels each evaluate thousands of sub-pixel splats, so
+  several percent of them are flagged; the bar is on the pixels that miss
+  2e-3).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import frame as oframe
+from oracle import lod as olod
+from oracle import splat as osplat
+from paper_2501_17792_amd import synth
+
+from .gpu_common import rect_fragile
+from .test_gpu_parity import BAND_ALPHA, BAND_T, POWER_ULPS, device_records, flag_bound, judge_pixels
+
+pytestmark = pytest.mark.gpu
+
+PKG = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2501_17792_amd")
+
+
+def test_headline_frame_tiles_match_oracle():
+    import torch
+
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    templates = [synth.make_template(t, 100_000, 3, synth.C4_LEVELS) for t in range(14)]
+    scene = synth.scene_c3(templates=templates, n_frames=300)
+    cam = scene.camera
+    W, H = cam.width, cam.height
+    tw, th = 32, 16
+    ntx, nty = -(-W // tw), -(-H // th)
+    z = np.load(os.path.join(PKG, "lod_net.npz"), allow_pickle=False)
+    with open(os.path.join(PKG, "lod_frame_rules.json")) as f:
+        margin = json.load(f)["budget_margin"]
+    print("headline frame: capture and replay", flush=True)
+    stream = torch.cuda.Stream()
+    r = cs.Renderer(0, stream=stream, fuse=True, tile=(tw, th))
+    r.upload_templates(templates)
+    r.set_crowd(scene.crowd)
+    with torch.cuda.stream(stream):
+        net = torch.from_numpy(z["net"]).cuda()
+        img = torch.zeros((3, H, W), device="cuda")
+        r.select_lod(cam, cs.CS_LOD_BUDGET, (), mlp_ptr=net.data_ptr(), margin=margin)
+        r.skin()
+        r.render(cam, img, stats=True)
+        st = r.last_stats
+        r.reserve(0, int(st.n_splats * 1.05) + 1024, int(st.n_pairs * 1.3) + 65536)
+        r.capture(cam, img, cs.CS_LOD_BUDGET, (), mlp_ptr=net.data_ptr(), margin=margin)
+        img.zero_()
+        r.launch()
+        st = r.poll()
+    assert st.overflow == 0
+    image = img.cpu().numpy()
+    n_inst = scene.crowd.n
+    levels = r.debug("LEVEL", np.int32, n_inst).astype(np.int64)
+    offset = r.debug("OFFSET", np.uint32, n_inst + 1).astype(np.int64)
+    ranges = r.debug("RANGES", np.uint32, 2 * ntx * nty).reshape(-1, 2).astype(np.int64)
+    lens = ranges[:, 1] - ranges[:, 0]
+    assert int(lens.sum()) == int(st.n_pairs) and int(offset[-1]) == int(st.n_splats)
+    # ---- the sample of tiles
+    rng = np.random.default_rng(11)
+    longest = int(np.argmax(lens))
+    long_tiles = np.nonzero(lens >= np.percentile(lens, 90))[0]
+    long_tiles = long_tiles[long_tiles != longest]
+    others = np.setdiff1d(np.nonzero(lens > 0)[0], np.concatenate([long_tiles, [longest]]))
+    tiles = [longest] + rng.choice(long_tiles, 3, replace=False).tolist() + rng.choice(others, 4, replace=False).tolist()
+    print(f"tiles {tiles}, lists {[int(lens[t]) for t in tiles]}", flush=True)
+    lists = {t: r.debug("SVALS", np.uint32, int(lens[t]), int(ranges[t, 0])).astype(np.int64) for t in tiles}
+    # ---- candidate instances: padded joint boxes reaching a sampled tile
+    tile_px = np.array([[(t % ntx) * tw, (t // ntx) * th, (t % ntx + 1) * tw, (t // ntx + 1) * th] for t in tiles])
+    pads = [olod.pad_radius(t) for t in templates]
+    cand = []
+    for i in range(n_inst):
+        tid = int(scene.crowd.tid[i])
+        joints = olod.posed_joints(templates[tid], scene.crowd.pose[i], float(scene.crowd.yaw[i]),
+                                   float(scene.crowd.pos[i, 0]), float(scene.crowd.pos[i, 1]))
+        box, _ = olod.view_box(joints, 1.5 * pads[tid], cam)
+        if box is None:
+            continue
+        b = box + np.array([-2.0, -2.0, 2.0, 2.0])
+        if np.any((b[0] < tile_px[:, 2]) & (b[2] > tile_px[:, 0]) & (b[1] < tile_px[:, 3]) & (b[3] > tile_px[:, 1])):
+            cand.append(i)
+    cand = np.array(cand)
+    in_lists = np.unique(np.searchsorted(offset, np.concatenate(list(lists.values())), side="right") - 1)
+    assert np.all(np.isin(in_lists, cand)), np.setdiff1d(in_lists, cand)[:10]
+    # device splat indices of the candidates and their float32 records
+    spl = np.concatenate([np.arange(offset[i], offset[i + 1]) for i in cand])
+    R = np.concatenate([r.debug("RECORD", np.float32, 12 * int(offset[i + 1] - offset[i]), 12 * int(offset[i]))
+                        .reshape(-1, 12) for i in cand])
+    print(f"{len(cand)} candidate instances, {len(spl)} splats", flush=True)
+    # ---- O6 per tile: the integer key oracle on the device's records
+    rect, cnt, vis = osplat.footprint_rect_f32(R[:, 0], R[:, 1], R[:, 2], R[:, 3], R[:, 11], W, H, tw, th)
+    dbits = R[:, 11].astype(np.float32).view(np.uint32).astype(np.int64)
+    for t in tiles:
+        ty, tx = divmod(t, ntx)
+        inside = vis & (rect[:, 0] <= tx) & (tx <= rect[:, 2]) & (rect[:, 1] <= ty) & (ty <= rect[:, 3])
+        idx = np.nonzero(inside)[0]
+        want = spl[idx[np.lexsort((spl[idx], dbits[idx]))]]
+        np.testing.assert_array_equal(lists[t], want, err_msg=f"tile {t}")
+    # ---- the FP64 oracle's records of the candidates at the device's levels
+    sub = synth.Crowd(tid=scene.crowd.tid[cand], yaw=scene.crowd.yaw[cand], pos=scene.crowd.pos[cand],
+                      pose=scene.crowd.pose[cand])
+    rec = oframe.frame_records(templates, sub, cam, levels[cand], tw, th)
+    assert len(rec["u"]) == len(spl)
+    frag_rect = rect_fragile(rec, tw, th, W, H)
+    pos = {int(s): k for k, s in enumerate(spl)}
+    for t in tiles:
+        ty, tx = divmod(t, ntx)
+        o = rec["rect"]
+        inside = rec["visible"] & (o[:, 0] <= tx) & (tx <= o[:, 2]) & (o[:, 1] <= ty) & (ty <= o[:, 3])
+        a = set(np.nonzero(inside)[0].tolist()) - set(np.nonzero(frag_rect)[0].tolist())
+        b = {pos[int(s)] for s in lists[t]} - set(np.nonzero(frag_rect)[0].tolist())
+        assert a == b, f"tile {t}: {len(a ^ b)} splats differ"
+    # ---- pixels of the sampled tiles over the device's lists
+    order = np.concatenate([[pos[int(s)] for s in lists[t]] for t in tiles]).astype(np.int64)
+    starts = np.cumsum([0] + [len(lists[t]) for t in tiles])
+    rg = np.zeros((ntx * nty, 2), np.int64)
+    for k, t in enumerate(tiles):
+        rg[t] = starts[k], starts[k + 1]
+    drec = device_records(R)
+    bound = flag_bound(rec["rgb"])
+    for label, sp, alt in [("end to end", rec, drec), ("compositing", drec, None)]:
+        print(f"pixels, {label}", flush=True)
+        ref, _, frag = osplat.composite_tiled(sp, order, rg, W, H, tw, th, cam.bg, BAND_ALPHA, BAND_T, tiles=tiles,
+                                              chunked=True, sp_alt=alt, power_ulps=POWER_ULPS)
+        judge_pixels(image, ref, frag, tiles, W, H, tw, th, bound, label)
+    r.close()
