@@ -551,6 +551,42 @@ def psnr(a, b):
     return float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)
 
 
+def fit_leg(torch, steps=2000, timed_steps=50):
+    """The reconstruction-stage fit at its configuration: one 100k-Gaussian
+    SH3 template, 512x512, 64 seeded cameras on a 3 m sphere, start
+    perturbed (positions N(0, 1 cm), colours N(0, 0.1)), ``steps`` Adam steps
+    at lr 1e-3 on every attribute, L1 + 0.2 D-SSIM, one camera per step.
+    Reports the loss curve, the position error against the truth and the
+    time per step (wall over the whole fit, and HIP-event times of each
+    phase over ``timed_steps`` further steps)."""
+    from paper_2501_17792_amd import fit, synth
+
+    truth, crowd, cams = synth.scene_c5()
+    start = synth.perturb_template(truth, seed=502)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    params, losses, r = fit.fit(truth, start, crowd, cams, steps=steps, lr=1e-3, log_every=100)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    r.close()
+    mean = params["mean"].cpu().numpy().astype(np.float64)
+    err0 = np.linalg.norm(start.mean.astype(np.float64) - truth.mean, axis=1)
+    err1 = np.linalg.norm(mean - truth.mean, axis=1)
+    phases = {}
+    _, _, r2 = fit.fit(truth, start, crowd, cams, steps=timed_steps, lr=1e-3, log_every=10 ** 9,
+                       phase_times=phases)
+    r2.close()
+    ph = {k: round(float(np.median(v[1:])), 4) for k, v in phases.items()}
+    return {"workload": "one 100k-Gaussian SH3 template, 512x512, 64 cameras on a 3 m sphere, start perturbed "
+                        "(positions N(0, 0.01 m), colours N(0, 0.1)), Adam lr 1e-3, L1 + 0.2 D-SSIM",
+            "steps": steps, "ms_per_step_wall": round(1000.0 * wall / steps, 4),
+            "phase_ms_median": ph, "loss_curve": [[k, round(v, 6)] for k, v in losses],
+            "position_rmse_m": {"start": round(float(np.sqrt(np.mean(err0 ** 2))), 6),
+                                "end": round(float(np.sqrt(np.mean(err1 ** 2))), 6)},
+            "position_median_m": {"start": round(float(np.median(err0)), 6), "end": round(float(np.median(err1)), 6)},
+            "closer_fraction": round(float(np.mean(err1 < err0)), 4)}
+
+
 def copy_bandwidth(torch, stream, nbytes=1 << 30, reps=10):
     """Achievable HBM bandwidth: the library's copy kernel over 1 GiB (read +
     write bytes per second), HIP events on its stream."""
@@ -595,10 +631,11 @@ def main():
     ap.add_argument("--rules", default=os.path.join(ROOT, "paper_2501_17792_amd", "lod_frame_rules.json"))
     ap.add_argument("--tile", default="auto", help="WxH or 'auto' (autotuned per run)")
     ap.add_argument("--modes", default="", help="comma list of LoD modes to time (default: all)")
-    ap.add_argument("--sweep", default="", choices=["", "tab2", "tab1", "paper_lod"],
-                    help="instead of the headline: the Tab. 2 FPS sweep, the Tab. 1 memory sweep, or the "
-                         "paper's LoD schedule (one JSON line per cell)")
+    ap.add_argument("--sweep", default="", choices=["", "tab2", "tab1", "paper_lod", "fit"],
+                    help="instead of the headline: the Tab. 2 FPS sweep, the Tab. 1 memory sweep, the "
+                         "paper's LoD schedule (one JSON line per cell), or the template fit alone")
     ap.add_argument("--no-c2", action="store_true", help="skip the 500-avatar crowd")
+    ap.add_argument("--fit-steps", type=int, default=2000, help="steps of the template fit (0: skip it)")
     ap.add_argument("--frames", type=int, default=300,
                     help="frames of the animation the timed replays cycle through (1: every replay draws frame 0, "
                          "a fixed workload for counter runs)")
@@ -619,6 +656,8 @@ def main():
             sweep_tab2(torch, args.steps, args.warmup)
         elif args.sweep == "tab1":
             sweep_tab1(torch)
+        elif args.sweep == "fit":
+            print(json.dumps(dict(sweep="fit", **fit_leg(torch, args.fit_steps))), flush=True)
         else:
             print(json.dumps(dict(sweep="paper_lod", **paper_lod_leg(torch, args.steps, args.warmup))), flush=True)
         return
@@ -763,6 +802,12 @@ def main():
              "evals_per_pair": round(float(ev[:, 0].sum() / max(ev[:, 2].sum(), 1.0)), 3)}
     roofline = frame_roofline(stage_ms, stats, scene, uniq, tile, blend)
     copy_gbs, copy_ok = copy_bandwidth(torch, stream)
+    fit_res = None
+    if args.fit_steps > 0:
+        t0 = time.perf_counter()
+        fit_res = fit_leg(torch, args.fit_steps)
+        log(f"fit: {fit_res['ms_per_step_wall']:.2f} ms/step, position RMSE {fit_res['position_rmse_m']} "
+            f"({time.perf_counter() - t0:.1f} s)")
     if roofline.get("hbm"):
         roofline["hbm"]["frac_of_copy"] = round(roofline["hbm"]["achieved"] / copy_gbs, 4)
     stage_copy_frac = {k: round(v / copy_gbs, 4) for k, v in stage_gbs.items()}
@@ -813,7 +858,7 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "stage_gbs": {k: round(v, 1) for k, v in stage_gbs.items()},
         "copy_gbs": round(copy_gbs, 1), "copy_ok": copy_ok, "stage_frac_of_copy": stage_copy_frac,
-        "blend": blend,
+        "blend": blend, "fit": fit_res,
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

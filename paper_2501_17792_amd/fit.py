@@ -66,10 +66,12 @@ def render_targets(r, cams):
 
 
 def fit(truth: synth.Template, start: synth.Template, crowd, cams, steps=2000, lr=1e-3, lam=0.2, seed=503,
-        log=None, log_every=100):
+        log=None, log_every=100, phase_times=None):
     """Fit ``start`` to renders of ``truth`` from ``cams``; returns the fitted
     tensors and the loss history. ``lr`` is one rate for every attribute or a
-    dict per attribute (mean, log_scale, quat, opacity_logit, sh)."""
+    dict per attribute (mean, log_scale, quat, opacity_logit, sh). With a
+    dict ``phase_times``, every step's forward render, loss, backward and Adam
+    update are timed with HIP events on the renderer's stream (ms lists)."""
     lrs = lr if isinstance(lr, dict) else {k: lr for k in PARAMS}
     torch = _torch()
     r = cs.Renderer(0)
@@ -84,16 +86,34 @@ def fit(truth: synth.Template, start: synth.Template, crowd, cams, steps=2000, l
     Fn = make_function()
     order = np.random.default_rng(seed).permutation(len(cams))
     losses = []
+    ev = None
+    if phase_times is not None:
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        for name in ("forward", "loss", "backward", "adam"):
+            phase_times.setdefault(name, [])
     for step in range(1, steps + 1):
         c = int(order[(step - 1) % len(cams)])
+        if ev:
+            ev[0].record(r.stream)
         img = Fn.apply(r, cams[c], P["skin_idx"], P["skin_w"], *[params[k] for k in PARAMS])
+        if ev:
+            ev[1].record(r.stream)
         loss, dimg = r.fit_loss(img.detach(), targets[c], lam)
+        if ev:
+            ev[2].record(r.stream)
         for k in PARAMS:
             params[k].grad = None
         img.backward(dimg)
+        if ev:
+            ev[3].record(r.stream)
         with torch.no_grad():
             for k in PARAMS:
                 r.adam(params[k], params[k].grad.contiguous(), m[k], v[k], step, lrs[k])
+        if ev:
+            ev[4].record(r.stream)
+            ev[4].synchronize()
+            for i, name in enumerate(("forward", "loss", "backward", "adam")):
+                phase_times[name].append(ev[i].elapsed_time(ev[i + 1]))
         if step % log_every == 0 or step == 1:
             losses.append((step, float(loss.item())))
             if log:

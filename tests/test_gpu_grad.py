@@ -105,24 +105,30 @@ def test_fit_loss_matches_oracle():
 
 
 def test_short_fit_reduces_loss_and_position_error():
-    """A short fit from perturbed positions and colours: the loss falls and the
-    means move back towards the truth (Gaussians a few pixels wide, 16 views)."""
-    import dataclasses
-
+    """A short fit through the same code as the bench's fit leg (fit.fit) from
+    positions perturbed by N(0, 1 cm) and colours by N(0, 0.1): the loss falls
+    and the position RMSE of all means falls (4,000 Gaussians of the C5
+    generator, 256x256, 16 cameras, 400 steps). Positions step at lr 1e-4,
+    the other attributes at the configured 1e-3: at 1e-3 Adam moves every mean
+    about 1 mm per step whatever its gradient's size, and the weakly seen ones
+    wander (measured at the fit leg's own configuration: the loss falls 4x
+    while the RMSE grows from 1.7 to 3.9 cm)."""
     from paper_2501_17792_amd import fit
 
     truth = synth.make_template(500, 4000, 3)
-    truth = dataclasses.replace(truth, log_scale=(truth.log_scale + 1.0).astype(np.float32))
     start = synth.perturb_template(truth, seed=502)
     crowd = synth.Crowd(tid=np.zeros(1, np.int32), yaw=np.zeros(1, np.float32), pos=np.zeros((1, 2), np.float32),
                         pose=np.zeros((1, 24, 3), np.float32))
     center = 0.5 * (truth.mean.min(0) + truth.mean.max(0))
     cams = synth.sphere_cameras(501, 16, center, 3.0, 256, 256)
-    lr = dict(mean=2e-4, log_scale=1e-3, quat=1e-3, opacity_logit=1e-3, sh=1e-3)
+    lr = dict(mean=1e-4, log_scale=1e-3, quat=1e-3, opacity_logit=1e-3, sh=1e-3)
     params, losses, r = fit.fit(truth, start, crowd, cams, steps=400, lr=lr, log_every=50)
-    assert losses[-1][1] < 0.7 * losses[0][1], losses
+    r.close()
+    assert losses[-1][1] < 0.3 * losses[0][1], losses
     err0 = np.linalg.norm(start.mean - truth.mean, axis=1)
     err1 = np.linalg.norm(params["mean"].cpu().numpy() - truth.mean, axis=1)
-    moved = np.abs(params["mean"].cpu().numpy() - start.mean).max(1) > 0
-    assert moved.mean() > 0.3
-    assert np.median(err1[moved]) < np.median(err0[moved]), (np.median(err0[moved]), np.median(err1[moved]))
+    rmse0, rmse1 = np.sqrt(np.mean(err0 ** 2)), np.sqrt(np.mean(err1 ** 2))
+    print(f"loss {losses[0][1]:.4f} -> {losses[-1][1]:.4f}, position RMSE {rmse0:.4f} -> {rmse1:.4f} m, "
+          f"{np.mean(err1 < err0):.3f} closer")
+    assert rmse1 < 0.85 * rmse0, (rmse0, rmse1)
+    assert np.mean(err1 < err0) > 0.7
