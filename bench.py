@@ -223,78 +223,11 @@ def load_net(path):
 
 
 def time_mode(torch, rs, scene, poses_all, imgs, streams, lod, steps, warmup):
-    """Size the frame eagerly, reserve capacity, capture the whole frame as a
-    graph and time ``steps`` replays. Every replay starts with its pose
-    upload inside the graph, from a pose ring on the device: with n contexts
-    (one stream each) consecutive frames alternate between them, so context i
-    holds the ring of frames i, i + n, i + 2n, ... and many frames are in
-    flight; every frame still runs the whole path into its own image."""
-    from paper_2501_17792_amd import crowdsplat as cs
+    """Captured frames in flight over the contexts ``rs`` (one stream each):
+    the autotuner's timing procedure, so tuned and reported rates agree."""
+    from paper_2501_17792_amd import autotune
 
-    mode, thr, mlp_ptr, margin = lod
-    r, img, stream = rs[0], imgs[0], streams[0]
-    n_frames = poses_all.shape[0]
-    max_pairs = max_splats = 0
-    with torch.cuda.stream(stream):
-        for f in (0, n_frames // 3, 2 * n_frames // 3, n_frames - 1):
-            r.pose_dev.copy_(poses_all[f])
-            r.select_lod(scene.camera, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
-            r.skin()
-            r.render(scene.camera, img, stats=True)
-            max_pairs = max(max_pairs, int(r.last_stats.n_pairs))
-            max_splats = max(max_splats, int(r.last_stats.n_splats))
-        r.pose_dev.copy_(poses_all[0])
-        r.select_lod(scene.camera, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
-        r.skin()
-        r.render(scene.camera, img, stats=True)
-        st0 = r.last_stats
-        frame0 = img.clone()
-    n = len(rs)
-    rings = []
-    for i, (ri, im, st) in enumerate(zip(rs, imgs, streams)):
-        with torch.cuda.stream(st):
-            ri.reserve(0, int(max_splats * 1.05) + 1024, int(max_pairs * 1.3) + 65536)
-            idx = [(i + n * j) % n_frames for j in range(max(1, n_frames // n))]
-            ring = poses_all[idx].contiguous()
-            rings.append(ring)
-            ri.set_pose_ring(ring, first=0)
-            ri.capture(scene.camera, im, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
-
-    def frame(k):
-        i = k % n
-        with torch.cuda.stream(streams[i]):
-            rs[i].launch()
-        return i
-
-    for k in range(warmup):
-        frame(k)
-    torch.cuda.synchronize()
-    start = torch.cuda.Event(enable_timing=True)
-    start.record(stream)
-    for st in streams[1:]:
-        st.wait_event(start)
-    evs = []
-    for k in range(steps):
-        i = frame(warmup + k)
-        e = torch.cuda.Event(enable_timing=True)
-        e.record(streams[i])
-        evs.append(e)
-    for st in streams[1:]:
-        e = torch.cuda.Event()
-        e.record(st)
-        stream.wait_event(e)
-    end = torch.cuda.Event(enable_timing=True)
-    end.record(stream)
-    torch.cuda.synchronize()
-    total = start.elapsed_time(end)
-    # per-frame period: a stream's consecutive frames are n apart
-    per = np.array([evs[k].elapsed_time(evs[k + n]) / n for k in range(steps - n)]) if steps > n else np.array([total])
-    overflow = 0
-    for ri in rs:
-        overflow |= int(ri.poll().overflow)
-        ri.set_pose_ring(None)
-    del rings
-    return dict(ms=total / steps, per=per, stats=st0, frame0=frame0, overflow=overflow)
+    return autotune.time_frames(torch, rs, scene, poses_all, imgs, streams, lod, steps, warmup)
 
 
 # The paper's Tab. 2 (FPS, RTX 4090, 1280x720) and Tab. 1 (MiB unshared, shared): context, not targets.
@@ -611,6 +544,12 @@ def copy_bandwidth(torch, stream, nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9, ok
 
 
+def autotune_streams(torch, dev, n, first):
+    from paper_2501_17792_amd import autotune
+
+    return autotune.distinct_streams(torch, dev, n, first)
+
+
 def load_rules(path):
     if not os.path.exists(path):
         return None
@@ -639,8 +578,10 @@ def main():
     ap.add_argument("--frames", type=int, default=300,
                     help="frames of the animation the timed replays cycle through (1: every replay draws frame 0, "
                          "a fixed workload for counter runs)")
-    ap.add_argument("--inflight", type=int, default=3,
-                    help="frames in flight: contexts (one stream each) that consecutive frames alternate between")
+    ap.add_argument("--inflight", type=int, default=0,
+                    help="frames in flight: contexts (one stream each) that consecutive frames alternate between "
+                         "(0: from the autotuner)")
+    ap.add_argument("--retune", action="store_true", help="ignore the autotuner's cache (and rewrite it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; --gpus must be 1",
@@ -702,14 +643,23 @@ def main():
         keep = set(args.modes.split(",")) | {head}
         modes = {k: v for k, v in modes.items() if k in keep}
     tile_timing = None
+    inflight = args.inflight
     if args.tile == "auto":
         from paper_2501_17792_amd import autotune
 
-        tile, tile_timing = autotune.tune(torch, scene, poses_all, stream, modes[head], frames=20, log=log)
+        cache = os.path.join(ROOT, "paper_2501_17792_amd", "autotune_cache.json")
+        if args.retune and os.path.exists(cache):
+            os.remove(cache)
+        tile, tuned_inflight, tile_timing = autotune.tune_frame(torch, scene, poses_all, stream, modes[head],
+                                                                rule=head, cache_path=cache, log=log)
+        inflight = inflight or tuned_inflight
     else:
         tile = tuple(int(x) for x in args.tile.split("x"))
-    log(f"tile {tile}")
-    streams = [stream] + [torch.cuda.Stream(dev) for _ in range(args.inflight - 1)]
+    inflight = inflight or 3
+    log(f"tile {tile}, {inflight} frames in flight")
+    # consecutive streams of torch's pool (frames in flight on streams that share a hardware queue wait
+    # for each other)
+    streams = autotune_streams(torch, dev, inflight, None)
 
     def run(lod, n, sc=scene, poses=poses_all):  # fresh contexts per run: capacities are fixed at capture
         with torch.cuda.stream(stream):
@@ -841,7 +791,7 @@ def main():
                                "(pose upload inside), frames in flight on separate contexts",
                    "lod": head, "instances": scene.crowd.n, "width": scene.camera.width,
                    "height": scene.camera.height, "tile": list(tile)},
-        "tile_autotune_ms": tile_timing,
+        "autotune": tile_timing,
         "frames_in_flight": len(streams),
         "frame_ms_median": round(float(np.median(res["per"])), 4),
         "frame_ms_p95": round(float(np.percentile(res["per"], 95)), 4),
