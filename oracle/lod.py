@@ -30,7 +30,9 @@ Definitions (readings listed in the design doc):
   to [0, 60], none at level 0); instances take the level minimising
   n_l + lambda SSE_l (ties to the finer level) for the smallest lambda on a
   30-step bisection of log2(lambda) in [-40, 60] whose summed SSE stays within
-  3 W H 10^(-floor / 10).
+  3 W H 10^(-floor / 10); each instance's errors scaled by the share of its
+  window it was seen in (pixels whose largest contribution it gave) in a
+  previous frame, once one exists.
 """
 from __future__ import annotations
 
@@ -236,14 +238,22 @@ def label_window_px(clip, width, height) -> float:
     return float((win[2] - win[0]) * (win[3] - win[1]))
 
 
-def level_sse(pred, window_px, top) -> np.ndarray:
+def level_sse(pred, window_px, top, visible_px=None) -> np.ndarray:
     """[n, 5] predicted squared error of each level summed over the window's
     RGB values: the PSNR over the window is 10 log10(1 / MSE) with MSE the
     mean over its 3 w h values, so SSE = 3 w h 10^(-PSNR / 10); level 0 and
-    levels above the template's top have none."""
+    levels above the template's top have none. With ``visible_px`` (pixels
+    the instance was seen in, in a previous frame of the crowd) the error is
+    scaled by the visible share of its window, min(1, visible / (w h)): the
+    label measures the avatar alone, and in the crowd only its visible
+    pixels can show its error."""
     pred = np.clip(np.asarray(pred, np.float64)[:, :N_LEVELS], 0.0, PSNR_CAP)
     win = np.asarray(window_px, np.float64)
     sse = 3.0 * win[:, None] * 10.0 ** (-pred / 10.0)
+    if visible_px is not None:
+        vis = np.asarray(visible_px, np.float64)
+        share = np.where(win > 0, np.minimum(1.0, vis / np.where(win > 0, win, 1.0)), 0.0)
+        sse = sse * share[:, None]
     lv = np.arange(N_LEVELS)[None, :]
     sse[(lv == 0) | (lv > np.asarray(top)[:, None])] = 0.0
     return sse

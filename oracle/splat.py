@@ -370,6 +370,60 @@ def _blend_list_chunked(px, py, order, sp, bg, fragile_alpha, fragile_t, chunk=2
     return C, T, fragile, n_added
 
 
+def dominant_splats(px, py, order, sp, chunk=2048):
+    """For each pixel, the splat of ``order`` with the largest contribution
+    weight alpha T among those the front-to-back walk adds (the first of
+    equal ones), or -1 if it adds none; the walk of ``_blend_list``."""
+    P = px.shape[0]
+    T = np.ones(P)
+    done = np.zeros(P, bool)
+    best_w = np.full(P, -1.0)
+    best = np.full(P, -1, np.int64)
+    cx, cy = px + 0.5, py + 0.5
+    order = np.asarray(order, np.int64)
+    for c0 in range(0, order.shape[0], chunk):
+        live = np.nonzero(~done)[0]
+        if live.size == 0:
+            break
+        s = order[c0:c0 + chunk]
+        K = s.shape[0]
+        alpha = np.minimum(ALPHA_MAX, _alpha_raw(sp, s, cx[live], cy[live]))
+        use = alpha >= ALPHA_MIN
+        Tb = np.cumprod(np.concatenate([T[live, None], np.where(use, 1.0 - alpha, 1.0)], axis=1), axis=1)
+        Tn = Tb[:, :-1] * (1.0 - alpha)
+        Tb = Tb[:, :-1]
+        stop = use & (Tn < T_MIN)
+        has_stop = stop.any(axis=1)
+        k_stop = np.where(has_stop, np.argmax(stop, axis=1), K)
+        add = use & (np.arange(K)[None, :] < k_stop[:, None])
+        wgt = np.where(add, alpha * Tb, -1.0)
+        kb = np.argmax(wgt, axis=1)  # the first of equal maxima
+        wb = wgt[np.arange(live.size), kb]
+        better = wb > best_w[live]
+        best_w[live] = np.where(better, wb, best_w[live])
+        best[live] = np.where(better, s[kb], best[live])
+        T[live] = np.cumprod(np.concatenate([T[live, None], np.where(add, 1.0 - alpha, 1.0)], axis=1),
+                             axis=1)[:, -1]
+        done[live] = has_stop
+    return best
+
+
+def dominant_splats_tiled(sp, sorted_vals, ranges, width, height, tw, th, tiles=None):
+    """``dominant_splats`` over each tile's sorted list: [H, W] splat indices."""
+    ntx = (width + tw - 1) // tw
+    nty = (height + th - 1) // th
+    out = np.full((height, width), -1, np.int64)
+    for t in (range(ntx * nty) if tiles is None else tiles):
+        ty, tx = divmod(int(t), ntx)
+        x0, y0 = tx * tw, ty * th
+        x1, y1 = min(x0 + tw, width), min(y0 + th, height)
+        gy, gx = np.mgrid[y0:y1, x0:x1]
+        s0, s1 = ranges[t]
+        out[y0:y1, x0:x1] = dominant_splats(gx.ravel().astype(np.float64), gy.ravel().astype(np.float64),
+                                            sorted_vals[s0:s1], sp).reshape(y1 - y0, x1 - x0)
+    return out
+
+
 def composite_tiled(sp, sorted_vals, ranges, width, height, tw, th, bg,
                     fragile_alpha=1e-4, fragile_t=1e-4, tiles=None, tie_impact=None,
                     chunked=False, sp_alt=None, power_ulps=0.0):

@@ -240,3 +240,22 @@ def test_budget_selection_limits_and_order():
     # instances without a template draw level 0 and add nothing
     lv, _ = lod.select_budget(sse, counts, top, 0.0, valid=np.array([False] + [True] * 5))
     assert lv[0] == 0
+
+
+def test_visible_share_scales_the_errors():
+    """Seen in its whole window: the errors unchanged; never seen: none (the
+    coarsest level is free); seen in a part: scaled by that share; more
+    pixels than the window (a larger window earlier): capped at the whole."""
+    sse, counts, top = _budget_case(3, n=4, levels=5)
+    pred = np.array([[60.0, 45.0, 40.0, 35.0, 30.0]] * 4)
+    win = np.array([1000.0, 1000.0, 1000.0, 0.0])
+    base = lod.level_sse(pred, win, np.full(4, 4))
+    got = lod.level_sse(pred, win, np.full(4, 4), visible_px=np.array([1000.0, 0.0, 250.0, 10.0]))
+    np.testing.assert_allclose(got[0], base[0])
+    assert np.all(got[1] == 0.0)
+    np.testing.assert_allclose(got[2], 0.25 * base[2], rtol=1e-15)
+    assert np.all(got[3] == 0.0)
+    got = lod.level_sse(pred, win, np.full(4, 4), visible_px=np.array([5000.0, 0, 0, 0]))
+    np.testing.assert_allclose(got[0], base[0])
+    lv, _ = lod.select_budget(got, counts, top, 0.0)
+    assert list(lv) == [0, 4, 4, 4]

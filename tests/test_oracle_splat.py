@@ -431,3 +431,50 @@ def test_float32_footprint_rect():
                                            np.array([10.0], np.float32), np.array([10.0], np.float32),
                                            np.array([1.0]), 256, 160, 16, 16)
     assert list(r[0]) == [1, 1, 3, 3] and cnt[0] == 9  # pixels 30..50 -> tiles 1..3
+
+
+def test_dominant_splat_closed_forms():
+    """Splats stacked on one pixel: weights alpha1, alpha2 (1 - alpha1), ...;
+    the larger wins; a skipped or stopping splat never wins."""
+    px = np.array([0.0])
+
+    def dom(ops):
+        rec = _records([0.5] * len(ops), [0.5] * len(ops), [1.0] * len(ops), ops, [[1, 1, 1]] * len(ops))
+        return int(splat.dominant_splats(px, px, list(range(len(ops))), rec)[0])
+
+    assert dom([0.3, 0.5]) == 1    # 0.3 against 0.35
+    assert dom([0.3, 0.4]) == 0    # 0.3 against 0.28
+    assert dom([0.5, 1.0]) == 0    # 0.5 against 0.99 * 0.5 = 0.495
+    assert dom([0.002, 0.003]) == -1  # both below 1/255: nothing added
+    assert dom([0.5, 1.0, 0.5]) == 0  # 0.5, 0.495, then 0.5 * 0.005 = 0.0025
+    assert dom([0.5, 1.0]) == dom([0.5, 1.0, 0.0])  # a zero-opacity splat changes nothing
+    # the splat that would take T below 1e-4 is not added, so it cannot win
+    assert dom([0.99, 0.99, 0.99]) == 0  # T after two is 1e-4 exactly: the third stops the walk
+    assert dom([0.2, 0.2]) == 0  # 0.2 against 0.16
+
+
+def test_dominant_splat_is_the_largest_single_splat_render():
+    """On random scenes the dominant splat of each pixel is the one whose
+    colour alone (every other splat black) gives the pixel the most light:
+    the weight alpha T read off the compositor's own colour output, one
+    render per splat; across chunk sizes the result is the same."""
+    rng = np.random.default_rng(21)
+    for seed in range(3):
+        n = 24
+        rec = dict(u=rng.uniform(0, 8, n), v=rng.uniform(0, 8, n), A=rng.uniform(0.05, 1.0, n),
+                   B=rng.uniform(-0.05, 0.05, n), C=rng.uniform(0.05, 1.0, n),
+                   opacity=rng.uniform(0.05, 0.95, n), rgb=np.zeros((n, 3)))
+        gy, gx = np.mgrid[0:8, 0:8]
+        px, py = gx.ravel() * 1.0, gy.ravel() * 1.0
+        order = rng.permutation(n)
+        W = np.zeros((n, px.size))
+        for k in range(n):
+            r = dict(rec, rgb=np.zeros((n, 3)))
+            r["rgb"][k] = 1.0
+            C, _, _, _ = splat._blend_list(px, py, order, r, np.zeros(3), 0, 0)
+            W[k] = C[0]
+        want = np.where(W.max(0) > 0, np.argmax(W, axis=0), -1)
+        for chunk in (1, 5, 4096):
+            got = splat.dominant_splats(px, py, order, rec, chunk=chunk)
+            ok = (got == want) | (np.sort(W, axis=0)[-1] - np.sort(W, axis=0)[-2] < 1e-12)
+            assert ok.all(), (seed, chunk)
