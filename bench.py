@@ -633,11 +633,15 @@ def main():
     # LoD rules, each at >= 40 dB frame PSNR against full detail on held-out frames
     modes = {
         "learned_budget": (cs.CS_LOD_BUDGET, (), net_dev.data_ptr(), rules["budget_margin"]),
+        "learned_budget_visible": (cs.CS_LOD_BUDGET_VISIBLE, (), net_dev.data_ptr(),
+                                   rules.get("budget_visible_margin")),
         "fixed_frame_tuned": (cs.CS_LOD_FIXED, tuple(rules["fixed_thresholds"]), 0, 0.0),
         "learned_instance_floor": (cs.CS_LOD_LEARNED, (), net_dev.data_ptr(), netinfo["margin"]),
         "fixed_10_25m": (cs.CS_LOD_FIXED, (10.0, 10.0, 25.0, 25.0), 0, 0.0),
         "full": (cs.CS_LOD_FULL, (), 0, 0.0),
     }
+    if modes["learned_budget_visible"][3] is None:  # rules tuned before the visible-share rule existed
+        del modes["learned_budget_visible"]
     head = "learned_budget"
     if args.modes:  # timing a subset (e.g. for a profiler run); the headline mode is always kept
         keep = set(args.modes.split(",")) | {head}
@@ -767,7 +771,7 @@ def main():
     quality = {}
     if not args.no_psnr:
         hold = tuple(rules["hold_frames"])
-        judge = train_lod.FrameJudge(torch, scene, hold + (0,), tile)
+        judge = train_lod.FrameJudge(torch, scene, hold + (0,), tile, lag=len(streams))
         for name, lod in modes.items():
             p_min, g_mean = judge.evaluate(lod, hold)
             p0, _ = judge.evaluate(lod, (0,))

@@ -60,6 +60,8 @@ typedef int32_t cs_status;
 #define CS_LOD_CONSTANT 3 /* every instance at lod->level                        */
 #define CS_LOD_BUDGET  4  /* learned, frame budget: fewest Gaussians whose      */
                           /* predicted errors keep the frame >= the floor       */
+#define CS_LOD_BUDGET_VISIBLE 5 /* BUDGET with each instance's errors scaled by */
+                                /* its visible share in the last frame          */
 
 #define CS_MAX_LEVELS     8
 #define CS_MAX_TEMPLATES  64
@@ -151,9 +153,9 @@ typedef struct cs_lod_params {
   int32_t n_thresholds;      /* FIXED: 0..7 increasing distances (m)            */
   float thresholds[7];
   int32_t level;             /* CONSTANT: the level of every instance           */
-  float psnr_min;            /* LEARNED, BUDGET: quality floor (dB)             */
-  float margin;              /* LEARNED, BUDGET: extra dB required              */
-  const void* mlp;           /* LEARNED, BUDGET: device pointer to a cs_mlp     */
+  float psnr_min;            /* LEARNED, BUDGET*: quality floor (dB)            */
+  float margin;              /* LEARNED, BUDGET*: extra dB required             */
+  const void* mlp;           /* LEARNED, BUDGET*: device pointer to a cs_mlp    */
 } cs_lod_params;
 /* LEARNED keeps each instance's own predicted PSNR (over its label window)
  * >= psnr_min + margin. BUDGET reads the floor as one for the whole frame
@@ -169,7 +171,22 @@ typedef struct cs_lod_params {
  * of log2(lambda) in [-40, 60], whose total stays within that budget
  * (overlaps between instances are ignored; the margin absorbs them).
  * BUDGET needs psnr_min + margin in (-200, 200) dB (CS_ERR_INVALID) and at
- * most 8,192 instances (CS_ERR_UNSUPPORTED). */
+ * most 8,192 instances (CS_ERR_UNSUPPORTED).
+ * BUDGET_VISIBLE (same requirements) accounts for occlusion, which the labels
+ * (each avatar rendered alone) cannot: the render that follows the selection
+ * counts, per instance, the pixels whose largest-weight splat (alpha T, the
+ * first of equal ones) is one of its Gaussians (CS_BUF_VISIBLE), and the next
+ * BUDGET_VISIBLE selection on this context scales each instance's SSE_l by
+ * min(1, visible / (w h)) (0 for an empty window) before the bisection, then
+ * clears the counts. The counts describe a frame already drawn, so the rule
+ * assumes frames that change little from one to the next (an animation seen
+ * from a steady camera) and that instance i stays the same avatar. Counts
+ * serve the one selection that follows them; share 1 (plain BUDGET) applies
+ * while there are none: on the first frame, when the counted frame drew
+ * another number of instances, and when another selection or a render that
+ * did not count (a view render, an instrumented blend) came in between.
+ * A captured frame carries this across its replays (the tag lives on the
+ * device), so each replay reads the counts of the one before it. */
 
 /* The learned-LoD network (device memory, laid out exactly as below).
  * Inputs: 32 features (31 used, see cs_lod_features) z-scored with mu and
@@ -434,10 +451,14 @@ cs_status cs_memory_report(cs_ctx* ctx, cs_memory_stats* out);
 #define CS_BUF_FEATURES 16  /* float [n_inst][32] learned-LoD features               */
 #define CS_BUF_PRED     17  /* float [n_inst][16] learned-LoD predicted PSNR [0..4];  */
                             /* BUDGET also SSE_l [8..12], w h [13], log2 lambda [14], */
-                            /* top level [15]                                        */
+                            /* top level [15]; BUDGET_VISIBLE also the visible share */
+                            /* [6] and the visible pixels it was read from [7]       */
 #define CS_BUF_VIEWS    18  /* int64 [n_inst][6] window x0 y0 w h (px), tile base, atlas offset */
 #define CS_BUF_JOINTS   19  /* float [n_inst][24][3] posed joint positions           */
 #define CS_BUF_OFFSETS  20  /* float [n_splats][4] pose-dependent offsets (x y z 0)  */
+#define CS_BUF_VISIBLE  21  /* uint32 [n_inst] pixels whose largest-weight splat is */
+                            /* the instance's, counted by the last render after a   */
+                            /* BUDGET_VISIBLE selection (cleared by the next one)   */
 cs_status cs_debug_copy(cs_ctx* ctx, int32_t which, void* host_dst, int64_t offset, int64_t bytes);
 
 /* ---- learned LoD ----------------------------------------------------------

@@ -25,6 +25,7 @@ CS_SORT_TILE_BUCKET, CS_SORT_ONESWEEP, CS_SORT_REDUCE_SCAN = 0, 1, 2
 CS_NOALLOC_MAX_PAIRS = 1 << 20
 CS_SORT_RANKS_CHECKED, CS_SORT_RANKS_BALLOT = 0, 1
 CS_LOD_FULL, CS_LOD_FIXED, CS_LOD_LEARNED, CS_LOD_CONSTANT, CS_LOD_BUDGET = 0, 1, 2, 3, 4
+CS_LOD_BUDGET_VISIBLE = 5
 CS_MLP_NPARAM, CS_MLP_NBF16 = 7312, 7168
 #: offsets of the layers inside cs_mlp.params (out-major weights)
 MLP_OFF = dict(w1=(0, (64, 32)), b1=(2048, (64,)), w2=(2112, (64, 64)), b2=(6208, (64,)),
@@ -33,7 +34,7 @@ CS_MAX_LEVELS = 8
 
 BUF = dict(BONES=1, LEVEL=2, OFFSET=3, SKIN_MU=4, SKIN_COV=5, SKIN_COV2=6, RECORD=7, RECT=8,
            COUNT=9, PAIR_OFF=10, KEYS=11, VALS=12, SKEYS=13, SVALS=14, RANGES=15, FEATURES=16,
-           PRED=17, VIEWS=18, JOINTS=19, OFFSETS=20)
+           PRED=17, VIEWS=18, JOINTS=19, OFFSETS=20, VISIBLE=21)
 
 #: every symbol include/crowdsplat.h declares
 EXPORTS = ["cs_create", "cs_destroy", "cs_last_error", "cs_version", "cs_upload_templates",

@@ -9,6 +9,12 @@
 // misses all of the wave's pixel centres (a decision every pixel would have
 // taken on its own, so the image does not depend on tile or wave shape).
 // Record layout: (u v rx ry) (A B C o) (r g b depth).
+//
+// Variants (MODE): kPlain; kCount adds up live evaluations and lane slots;
+// kVisible also finds, per pixel, the splat the walk adds with the largest
+// weight alpha T (the first of equal ones) and counts the pixel for the
+// instance that splat belongs to (the visible share the frame-budget LoD
+// scales its predicted errors by).
 #include "cs_internal.h"
 
 namespace cs {
@@ -18,6 +24,7 @@ namespace cs {
 // order inside a magnitude class is that of the LDS atomics; it only changes
 // when a tile is composited, never its pixels.
 constexpr int kOrderClasses = 64;
+constexpr int kPlain = 0, kCount = 1, kVisible = 2;
 
 __global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t* __restrict__ ranges, int n_tiles,
                                                           uint32_t* __restrict__ order) {
@@ -44,14 +51,15 @@ __global__ __launch_bounds__(1024) void tile_order_kernel(const uint32_t* __rest
   for (int t = threadIdx.x; t < n_tiles; t += 1024) order[atomicAdd(&s_cnt[cls(t)], 1u)] = (uint32_t)t;
 }
 
-template <int TW, int TH, bool VIEW, bool COUNT = false>
+template <int TW, int TH, bool VIEW, int MODE = kPlain>
 __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restrict__ ranges,
                                                        const uint32_t* __restrict__ svals,
                                                        const float4* __restrict__ rec, CamDev cam,
                                                        float* __restrict__ image,
                                                        const FrameHdr* __restrict__ hdr, ViewDev view,
                                                        const uint32_t* __restrict__ order,
-                                                       unsigned long long* __restrict__ counters) {
+                                                       unsigned long long* __restrict__ counters, VisDev vis) {
+  constexpr bool COUNT = MODE == kCount, VISIBLE = MODE == kVisible;
   constexpr int N = TW * TH;
   constexpr int ROWS = 64 / TW;  // pixel rows per wave
   constexpr int WAVES = N / 64;
@@ -111,6 +119,8 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
   bool done = !inside;
   uint32_t n_live = 0, n_slots = 0;  // COUNT: live evaluations and lane slots of this lane
+  float best_w = -1.f;                // VISIBLE: largest weight added so far and its list position
+  uint32_t best_pos = 0xffffffffu;
   // Software pipeline over batches: the tile's list entries are read 4
   // batches ahead and whole records 2 ahead, into two-slot register rings
   // (the loop is unrolled twice with the slots swapped, so no register a load
@@ -246,7 +256,7 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
           float4 a1 = s_r1b[jA], a2 = s_r2b[jA], b1 = s_r1b[jB], b2 = s_r2b[jB];
           float2 au = make_float2(s_qb[jA].x, s_qb[jA].y), bu = make_float2(s_qb[jB].x, s_qb[jB].y);
           int oA = off(2), oB = off(3);
-          auto eval = [&](int k, const float4& r1, const float2& uv, const float4& r2) {
+          auto eval = [&](int k, const float4& r1, const float2& uv, const float4& r2, int j) {
             const bool live = !done && k < n_mine;
             if constexpr (COUNT) {
               n_live += live ? 1u : 0u;
@@ -266,20 +276,27 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
             cb = add ? fmaf(r2.z, wgt, cb) : cb;
             T = add ? Tn : T;
             done = done || stop;
+            if constexpr (VISIBLE) {
+              const bool better = add && wgt > best_w;
+              best_w = better ? wgt : best_w;
+              best_pos = better ? b + (uint32_t)j : best_pos;
+            }
           };
           // (k + 1 = n_max in the last pass: its lanes are all past their
           // lists, so that half changes nothing)
           for (int k = 0; k < n_max; k += 2) {
-            eval(k, a1, au, a2);
+            eval(k, a1, au, a2, jA);
             a1 = s_r1b[oA];
             a2 = s_r2b[oA];
             au = make_float2(s_qb[oA].x, s_qb[oA].y);
+            if constexpr (VISIBLE) jA = oA;
             oA = off(k + 4);
             __builtin_amdgcn_sched_barrier(0);  // keep the refill ahead of the other set's evaluation
-            eval(k + 1, b1, bu, b2);
+            eval(k + 1, b1, bu, b2, jB);
             b1 = s_r1b[oB];
             b2 = s_r2b[oB];
             bu = make_float2(s_qb[oB].x, s_qb[oB].y);
+            if constexpr (VISIBLE) jB = oB;
             oB = off(k + 5);
             __builtin_amdgcn_sched_barrier(0);
           }
@@ -305,6 +322,31 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
       atomicAdd(&counters[1], b);
     }
   }
+  if constexpr (VISIBLE) {
+    // owner of the pixel's largest-weight splat: the last instance whose
+    // splat offset is <= the splat index
+    int owner = -1;
+    if (inside && best_pos != 0xffffffffu) {
+      const uint32_t s = svals[best_pos];
+      int lo = 0, hi = vis.n_inst;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (vis.offset[mid] <= s) lo = mid;
+        else hi = mid;
+      }
+      owner = lo;
+    }
+    // one atomic per distinct owner in the wave
+    uint64_t pending = __ballot(owner >= 0);
+    while (pending) {
+      const int leader = (int)__builtin_ctzll(pending);
+      const int who = __shfl(owner, leader);
+      const uint64_t same = __ballot(owner == who);
+      if (lane == leader) atomicAdd(&vis.vis[who], (uint32_t)__popcll(same));
+      pending &= ~same;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) *vis.ready = (uint32_t)vis.n_inst;  // the counts' crowd size
+  }
   if (inside) {
     const size_t plane = (size_t)out_w * out_h;
     const size_t o = (size_t)(py - out_y0) * out_w + (px - out_x0);
@@ -317,20 +359,24 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
 template <int TW, int TH>
 static hipError_t launch_blend_t(const uint32_t* ranges, const uint32_t* svals, const float4* rec,
                                  CamDev cam, float* image, const FrameHdr* hdr, const ViewDev* view,
-                                 uint32_t* order, hipStream_t st, unsigned long long* counters) {
+                                 uint32_t* order, hipStream_t st, unsigned long long* counters,
+                                 const VisDev* vis) {
   if (view) {
     if (view->n_tiles > 0)
       blend_kernel<TW, TH, true><<<view->n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr, *view,
-                                                                      nullptr, nullptr);
+                                                                      nullptr, nullptr, VisDev{});
   } else {
     const int n_tiles = cam.tiles_x * cam.tiles_y;
     if (order) tile_order_kernel<<<1, 1024, 0, st>>>(ranges, n_tiles, order);
     if (counters)
-      blend_kernel<TW, TH, false, true><<<n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr,
-                                                                      ViewDev{}, order, counters);
+      blend_kernel<TW, TH, false, kCount><<<n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr,
+                                                                        ViewDev{}, order, counters, VisDev{});
+    else if (vis)
+      blend_kernel<TW, TH, false, kVisible><<<n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr,
+                                                                          ViewDev{}, order, nullptr, *vis);
     else
       blend_kernel<TW, TH, false><<<n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr, ViewDev{},
-                                                                order, nullptr);
+                                                                order, nullptr, VisDev{});
   }
   return hipGetLastError();
 }
@@ -339,12 +385,14 @@ static hipError_t launch_blend_t(const uint32_t* ranges, const uint32_t* svals, 
 // launch order, or null for tile-index order.
 // counters: null, or two zeroed 64-bit counters (live evaluations, lane
 // slots) for an instrumented frame.
+// vis: null, or the visible-pixel counts (zeroed) to accumulate the frame's
+// into (not with counters, nor for view tiles).
 hipError_t launch_blend(const uint32_t* ranges, const uint32_t* svals, const float4* rec, CamDev cam,
                         float* image, const FrameHdr* hdr, const ViewDev* view, uint32_t* order,
-                        hipStream_t st, unsigned long long* counters) {
+                        hipStream_t st, unsigned long long* counters, const VisDev* vis) {
 #define CS_BLEND_CASE(W_, H_) \
   if (cam.tw == W_ && cam.th == H_)      \
-    return launch_blend_t<W_, H_>(ranges, svals, rec, cam, image, hdr, view, order, st, counters);
+    return launch_blend_t<W_, H_>(ranges, svals, rec, cam, image, hdr, view, order, st, counters, vis);
   CS_BLEND_CASE(8, 8)
   CS_BLEND_CASE(8, 16)
   CS_BLEND_CASE(8, 32)

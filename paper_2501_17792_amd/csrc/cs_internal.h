@@ -129,6 +129,8 @@ struct FrameHdr {
   uint32_t sort_fallbacks; // LDS-sorted segments re-sorted with ballot ranks this frame
   unsigned long long blend_evals;  // instrumented frames: live (pixel, splat) evaluations of the blend
   unsigned long long blend_slots;  // instrumented frames: lane evaluation slots the blend issued
+  uint32_t vis_ready;      // instance count of the frame the visible-pixel counts hold (0: none)
+  uint32_t vis_pad;
 };
 
 struct Chunk {
@@ -192,6 +194,15 @@ struct ViewDev {
   const uint32_t* offset;  // [n_inst + 1] splat offsets
   int32_t n_inst;
   int32_t n_tiles;         // total view tiles
+};
+
+// Visible-pixel counting of a composited frame: every pixel adds one to the
+// instance owning the splat with its largest contribution weight alpha T.
+struct VisDev {
+  const uint32_t* offset;  // [n_inst + 1] splat offsets
+  uint32_t* vis;           // [n_inst] visible pixels
+  uint32_t* ready;         // set to n_inst when the frame's counts are complete
+  int32_t n_inst;
 };
 
 struct SkinOut {
@@ -259,7 +270,7 @@ hipError_t launch_ranges(const uint64_t* skeys, FrameHdr* hdr, uint32_t max_pair
                          uint32_t* ranges, hipStream_t st);
 hipError_t launch_blend(const uint32_t* ranges, const uint32_t* svals, const float4* rec, CamDev cam,
                         float* image, const FrameHdr* hdr, const ViewDev* view, uint32_t* order,
-                        hipStream_t st, unsigned long long* counters = nullptr);
+                        hipStream_t st, unsigned long long* counters = nullptr, const VisDev* vis = nullptr);
 hipError_t launch_features(const cs_instance* inst, const float* pose, const float* joints,
                            const TemplateDev* tpl, int n_inst, int n_tpl, CamDev cam, const cs_mlp* net,
                            float* feat, hipStream_t st);
@@ -267,7 +278,8 @@ hipError_t launch_mlp_infer(const cs_mlp* net, const float* feat, int n, float* 
                             const cs_instance* inst, const TemplateDev* tpl, int n_tpl, float floor_db,
                             int32_t* level, uint32_t* count, hipStream_t st);
 hipError_t launch_lod_budget(float* pred, const float* joints, const cs_instance* inst, const TemplateDev* tpl, int n,
-                             int n_tpl, CamDev cam, float budget, int32_t* level, uint32_t* count, hipStream_t st);
+                             int n_tpl, CamDev cam, float budget, int32_t* level, uint32_t* count, uint32_t* vis,
+                             uint32_t* vis_ready, hipStream_t st);
 hipError_t launch_mlp_sync(cs_mlp* net, hipStream_t st);
 hipError_t launch_mlp_train(cs_mlp* net, float* m, float* v, const float* feat, const float* target, int batch,
                             int step, float lr, float* loss, hipStream_t st);

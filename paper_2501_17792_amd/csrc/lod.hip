@@ -287,9 +287,17 @@ __global__ __launch_bounds__(1024) void lod_budget_kernel(float* __restrict__ pr
                                                           const cs_instance* __restrict__ inst,
                                                           const TemplateDev* __restrict__ tpl, int n, int n_tpl,
                                                           CamDev cam, float budget, int32_t* __restrict__ level,
-                                                          uint32_t* __restrict__ count) {
+                                                          uint32_t* __restrict__ count, uint32_t* __restrict__ vis,
+                                                          uint32_t* __restrict__ vis_ready) {
   __shared__ float s_part[16];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  // with vis: each instance's errors are scaled by its visible share of the
+  // window, min(1, visible / (w h)), from the pixels the last composited
+  // frame counted for it, if that frame drew this many instances (its blend
+  // tags the counts with its instance count; share 1 otherwise); the counts
+  // are then cleared for this frame's blend to fill. Either way the tag is
+  // cleared: counts serve the one selection that follows them.
+  const bool scale = vis != nullptr && *vis_ready == (uint32_t)n;
   constexpr float kLog2_10_over_10 = 0.33219280948873624f;
   float cnt[kBudgetPer][5], sse[kBudgetPer][5];
   int top[kBudgetPer];
@@ -322,11 +330,19 @@ __global__ __launch_bounds__(1024) void lod_budget_kernel(float* __restrict__ pr
       }
       top[k] = tp;
     }
+    float share = 1.f, seen = 0.f;
+    if (vis) {
+      seen = (float)vis[i];
+      if (scale) share = win > 0.f ? fminf(1.f, seen / win) : 0.f;
+      vis[i] = 0u;
+    }
+    p[6] = share;
+    p[7] = seen;
     p[8] = 0.f;
 #pragma unroll
     for (int l = 1; l < 5; ++l) {
       const float db = fminf(fmaxf(p[l], 0.f), 60.f);
-      sse[k][l] = l <= tp ? 3.f * win * exp2f(-db * kLog2_10_over_10) : 0.f;
+      sse[k][l] = l <= tp ? 3.f * win * exp2f(-db * kLog2_10_over_10) * share : 0.f;
       p[8 + l] = sse[k][l];
     }
     p[13] = win;
@@ -355,6 +371,7 @@ __global__ __launch_bounds__(1024) void lod_budget_kernel(float* __restrict__ pr
     else lo = mid;
   }
   const float lam = exp2f(hi);
+  if (t == 0) *vis_ready = 0u;  // every thread read it before the bisection's first barrier
 #pragma unroll
   for (int k = 0; k < kBudgetPer; ++k) {
     const int i = t + 1024 * k;
@@ -373,10 +390,12 @@ __global__ __launch_bounds__(1024) void lod_budget_kernel(float* __restrict__ pr
 }
 
 hipError_t launch_lod_budget(float* pred, const float* joints, const cs_instance* inst, const TemplateDev* tpl, int n,
-                             int n_tpl, CamDev cam, float budget, int32_t* level, uint32_t* count, hipStream_t st) {
+                             int n_tpl, CamDev cam, float budget, int32_t* level, uint32_t* count, uint32_t* vis,
+                             uint32_t* vis_ready, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (n > 1024 * kBudgetPer) return hipErrorInvalidValue;
-  lod_budget_kernel<<<1, 1024, 0, st>>>(pred, joints, inst, tpl, n, n_tpl, cam, budget, level, count);
+  lod_budget_kernel<<<1, 1024, 0, st>>>(pred, joints, inst, tpl, n, n_tpl, cam, budget, level, count, vis,
+                                        vis_ready);
   return hipGetLastError();
 }
 

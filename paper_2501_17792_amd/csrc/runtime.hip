@@ -79,6 +79,9 @@ struct cs_ctx {
   float* joints = nullptr;
   float* feat = nullptr;      // [cap_inst][32] learned-LoD features
   float* pred = nullptr;      // [cap_inst][16] predictions
+  uint32_t* vis = nullptr;    // [cap_inst] visible pixels of the last composited frame
+  bool vis_frame = false;     // the next render counts visible pixels (frame-budget LoD on visibility)
+  bool vis_maybe = false;     // a counting render was issued since the device flag was last cleared
   int64_t* views = nullptr;   // [cap_inst][6] view windows
   int4* crop = nullptr;       // [cap_inst] view tile windows
   int64_t view_tiles = 0, atlas_floats = 0;
@@ -237,6 +240,7 @@ cs_status ensure_instances(cs_ctx* ctx, int64_t n_inst) {
   CS_TRY(dalloc(ctx, &ctx->joints, cap * kJoints * 3, kMemInstance));
   CS_TRY(dalloc(ctx, &ctx->feat, cap * 32, kMemInstance));
   CS_TRY(dalloc(ctx, &ctx->pred, cap * 16, kMemInstance));
+  CS_TRY(dalloc(ctx, &ctx->vis, cap, kMemInstance));
   CS_TRY(dalloc(ctx, &ctx->views, cap * 6, kMemInstance));
   CS_TRY(dalloc(ctx, &ctx->crop, cap, kMemInstance));
   CS_TRY(dalloc(ctx, &ctx->pn_u, cap * kPnHidden, kMemInstance));
@@ -518,6 +522,7 @@ void cs_destroy(cs_ctx* ctx) {
   dfree(ctx, &ctx->joints);
   dfree(ctx, &ctx->feat);
   dfree(ctx, &ctx->pred);
+  dfree(ctx, &ctx->vis);
   dfree(ctx, &ctx->gpair);
   dfree(ctx, &ctx->gsplat);
   dfree(ctx, &ctx->loss_work);
@@ -690,14 +695,15 @@ cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, co
   if (lod->mode == CS_LOD_FIXED && (lod->n_thresholds < 0 || lod->n_thresholds > 7))
     return ctx->fail(CS_ERR_INVALID, "0..7 thresholds");
   if (lod->mode != CS_LOD_FULL && lod->mode != CS_LOD_FIXED && lod->mode != CS_LOD_LEARNED &&
-      lod->mode != CS_LOD_CONSTANT && lod->mode != CS_LOD_BUDGET)
+      lod->mode != CS_LOD_CONSTANT && lod->mode != CS_LOD_BUDGET && lod->mode != CS_LOD_BUDGET_VISIBLE)
     return ctx->fail(CS_ERR_INVALID, "bad lod mode");
-  const bool learned = lod->mode == CS_LOD_LEARNED || lod->mode == CS_LOD_BUDGET;
+  const bool budget_mode = lod->mode == CS_LOD_BUDGET || lod->mode == CS_LOD_BUDGET_VISIBLE;
+  const bool learned = lod->mode == CS_LOD_LEARNED || budget_mode;
   if (learned && (!lod->mlp || !pose))
     return ctx->fail(CS_ERR_INVALID, "learned LoD needs the network and the poses");
-  if (lod->mode == CS_LOD_BUDGET && !(lod->psnr_min + lod->margin > -200.f && lod->psnr_min + lod->margin < 200.f))
+  if (budget_mode && !(lod->psnr_min + lod->margin > -200.f && lod->psnr_min + lod->margin < 200.f))
     return ctx->fail(CS_ERR_INVALID, "the frame's PSNR floor plus margin must lie in (-200, 200) dB");
-  if (lod->mode == CS_LOD_BUDGET && n_inst > 8192)
+  if (budget_mode && n_inst > 8192)
     return ctx->fail(CS_ERR_UNSUPPORTED, "the frame-budget LoD selects for at most 8,192 instances");
   if (lod->mode == CS_LOD_CONSTANT && (lod->level < 0 || lod->level >= CS_MAX_LEVELS))
     return ctx->fail(CS_ERR_INVALID, "constant level out of range");
@@ -710,6 +716,7 @@ cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, co
   CS_TRY(ensure_instances(ctx, n_inst));
   for (int k = 0; k < CS_STAGE_COUNT; ++k) ctx->ev_used[k] = false;
   ctx->mark(CS_STAGE_LOD, 0);
+  ctx->vis_frame = false;
   HIP_TRY(launch_frame_reset(ctx->hdr, ctx->hist, 0, 1, ctx->stream));
   if (learned) {
     HIP_TRY(launch_fk(inst, pose, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), ctx->bones, ctx->joints,
@@ -725,10 +732,21 @@ cs_status cs_select_lod(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst, co
       // frame MSE over the 3 W H values <= 10^(-floor / 10)
       const double floor_db = (double)lod->psnr_min + (double)lod->margin;
       const float budget = (float)(3.0 * (double)cd.W * (double)cd.H * pow(10.0, -floor_db / 10.0));
+      // the budget kernel reads (VISIBLE) and clears the device's counts-ready tag
+      const bool visible = lod->mode == CS_LOD_BUDGET_VISIBLE;
       HIP_TRY(launch_lod_budget(ctx->pred, ctx->joints, inst, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), cd,
-                                budget, ctx->level, ctx->count_inst, ctx->stream));
+                                budget, ctx->level, ctx->count_inst, visible ? ctx->vis : nullptr,
+                                &ctx->hdr->vis_ready, ctx->stream));
+      ctx->vis_frame = visible;
+      ctx->vis_maybe = false;
     }
-  } else {
+  }
+  if (ctx->vis_maybe && !budget_mode) {  // counts of an earlier frame must not outlive this one
+    store_u32_kernel<<<1, 64, 0, ctx->stream>>>(&ctx->hdr->vis_ready, 0u);
+    HIP_TRY(hipGetLastError());
+    ctx->vis_maybe = false;
+  }
+  if (!learned) {
     HIP_TRY(launch_lod_fixed(inst, ctx->tpl_dev, n_inst, (int)ctx->tpl.size(), cd, lod->thresholds,
                              lod->mode == CS_LOD_FIXED ? lod->n_thresholds : 0, lod->mode == CS_LOD_FULL,
                              lod->mode == CS_LOD_CONSTANT ? lod->level : -1, ctx->level, ctx->count_inst,
@@ -919,12 +937,18 @@ static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs
     CS_TRY(lsd_bin_sort(ctx, cd, n_tiles, vp));
   }
   ctx->mark(CS_STAGE_BLEND, 0);
+  const bool count = ctx->opt.profile_stages && ctx->opt.count_blend && !ctx->capturing && !view_mode;
+  // the render after a visibility-scaled frame-budget selection counts its
+  // visible pixels per instance (only the first: a second render of the same
+  // selection would count them twice)
+  const VisDev visd{ctx->offset, ctx->vis, &ctx->hdr->vis_ready, (int32_t)ctx->n_inst};
+  const bool count_vis = ctx->vis_frame && !view_mode && !count && ctx->n_inst > 0;
   if (n_tiles > 0)
     HIP_TRY(launch_blend(ctx->ranges, ctx->vals[ctx->sorted], ctx->rec, cd, image, ctx->hdr, vp,
                          view_mode ? nullptr : ctx->tile_order, ctx->stream,
-                         ctx->opt.profile_stages && ctx->opt.count_blend && !ctx->capturing && !view_mode
-                             ? &ctx->hdr->blend_evals
-                             : nullptr));
+                         count ? &ctx->hdr->blend_evals : nullptr, count_vis ? &visd : nullptr));
+  ctx->vis_frame = false;
+  ctx->vis_maybe = ctx->vis_maybe || count_vis;
   ctx->mark(CS_STAGE_BLEND, 1);
   ctx->state = kRendered;
   if (stats) {
@@ -1354,6 +1378,7 @@ cs_status cs_debug_copy(cs_ctx* ctx, int32_t which, void* host_dst, int64_t offs
     case CS_BUF_RANGES: src = ctx->ranges; size = ctx->cap_tiles * 8; break;
     case CS_BUF_FEATURES: src = ctx->feat; size = ctx->cap_inst * 32 * 4; break;
     case CS_BUF_PRED: src = ctx->pred; size = ctx->cap_inst * 16 * 4; break;
+    case CS_BUF_VISIBLE: src = ctx->vis; size = ctx->cap_inst * 4; break;
     case CS_BUF_VIEWS: src = ctx->views; size = ctx->cap_inst * 6 * 8; break;
     case CS_BUF_JOINTS: src = ctx->joints; size = ctx->cap_inst * kJoints * 3 * 4; break;
     case CS_BUF_OFFSETS: src = ctx->offsets; size = ctx->offsets ? ctx->cap_offsets * 16 : 0; break;

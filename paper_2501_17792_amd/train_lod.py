@@ -72,9 +72,10 @@ def tune_margin(pred, psnr, floor=FLOOR, coverage=0.99):
 # rules tuned to the frame's PSNR against the full-detail frame
 # ----------------------------------------------------------------------------
 
-TUNE_FRAMES = tuple(range(0, 300, 10))
 HOLD_FRAMES = tuple(range(5, 300, 10))
+TUNE_FRAMES = tuple(k for k in range(300) if k not in HOLD_FRAMES)  # every frame not held out
 TUNE_EXTRA_DB = 0.5  # tuned to floor + this on the tuning frames, so held-out frames keep the floor
+VISIBLE_LAG = 4  # the visible-share rule reads the counts of the frame this many frames back
 FIXED_RATIOS = (1.0, 1.25, 1.5, 2.0, 3.0)
 
 
@@ -85,10 +86,13 @@ def frame_psnr(torch, img, ref) -> float:
 
 class FrameJudge:
     """Full-detail reference frames of an animated crowd and the PSNR of any
-    LoD rule's frames against them (one fused context, eager frames)."""
+    LoD rule's frames against them (one fused context, eager frames). A
+    frame of the visible-share rule is drawn right after frame k - ``lag``
+    (clamped at 0), whose visible pixels it reads, as it is in a stream of
+    frames with ``lag`` frames in flight on alternating contexts."""
 
-    def __init__(self, torch, scene, frames, tile=(32, 16)):
-        self.torch, self.scene = torch, scene
+    def __init__(self, torch, scene, frames, tile=(32, 16), lag=VISIBLE_LAG):
+        self.torch, self.scene, self.lag = torch, scene, lag
         self.poses = torch.from_numpy(scene.frame_poses).cuda()
         self.r = cs.Renderer(0, fuse=True, tile=tile)
         self.r.upload_templates(scene.templates)
@@ -108,6 +112,8 @@ class FrameJudge:
         """(min PSNR over the frames, mean drawn Gaussians per frame)."""
         ps, ns = [], []
         for k in frames:
+            if lod[0] == cs.CS_LOD_BUDGET_VISIBLE:
+                self.render(max(0, k - self.lag), lod, floor)
             img = self.render(k, lod, floor)
             ns.append(int(self.r.last_stats.n_splats))
             ps.append(frame_psnr(self.torch, img, self.ref[k]))
@@ -129,7 +135,12 @@ def tune_frame_rules(torch, scene, mlp_ptr, floor=FLOOR, tune=TUNE_FRAMES, hold=
       [-40, 10] dB) meeting it. The predicted errors are those of each avatar
       alone on black over its whole window; in the crowd nearer avatars hide
       much of that, so the margin that calibrates the predicted total to the
-      frame's error is negative."""
+      frame's error is negative;
+    * learned, frame budget on the visible share: the same bisection in
+      [-20, 40] dB, the errors scaled by each avatar's visible share of its
+      window. Its margin comes out positive: the label's error is spread over
+      the whole window, background included, while the visible pixels are
+      all on the avatar, where its error lies."""
     judge = FrameJudge(torch, scene, tuple(tune) + tuple(hold), tile)
     target = floor + extra_db
     fixed = []
@@ -148,22 +159,26 @@ def tune_frame_rules(torch, scene, mlp_ptr, floor=FLOOR, tune=TUNE_FRAMES, hold=
         fixed.append(dict(ratio=ratio, thresholds=list(th(hi)), tune_min_psnr=p, tune_gauss=n))
         log(f"fixed ratio {ratio}: d1 {hi:.2f} m, {n / 1e6:.1f}M Gaussians, min PSNR {p:.2f} dB")
     best = min(fixed, key=lambda f: f["tune_gauss"])
-    lo, hi = -40.0, 10.0
-    for _ in range(12):
-        mid = 0.5 * (lo + hi)
-        p, n = judge.evaluate((cs.CS_LOD_BUDGET, (), mlp_ptr, mid), tune, floor)
-        log(f"budget margin {mid:.3f} dB: {n / 1e6:.1f}M Gaussians, min PSNR {p:.2f} dB")
-        if p >= target:
-            hi = mid
-        else:
-            lo = mid
-    margin = hi
-    p, n = judge.evaluate((cs.CS_LOD_BUDGET, (), mlp_ptr, margin), tune, floor)
     out = dict(floor=floor, target_db=target, tune_frames=list(tune), hold_frames=list(hold),
                fixed_candidates=fixed, fixed_thresholds=best["thresholds"], fixed_tune_gauss=best["tune_gauss"],
-               budget_margin=margin, budget_tune_min_psnr=p, budget_tune_gauss=n)
+               visible_lag=judge.lag)
+    margins = {}
+    for name, mode, lo, hi in (("budget", cs.CS_LOD_BUDGET, -40.0, 10.0),
+                               ("budget_visible", cs.CS_LOD_BUDGET_VISIBLE, -20.0, 40.0)):
+        for _ in range(12):
+            mid = 0.5 * (lo + hi)
+            p, n = judge.evaluate((mode, (), mlp_ptr, mid), tune, floor)
+            log(f"{name} margin {mid:.3f} dB: {n / 1e6:.1f}M Gaussians, min PSNR {p:.2f} dB")
+            if p >= target:
+                hi = mid
+            else:
+                lo = mid
+        margins[name] = hi
+        p, n = judge.evaluate((mode, (), mlp_ptr, hi), tune, floor)
+        out.update({f"{name}_margin": hi, f"{name}_tune_min_psnr": p, f"{name}_tune_gauss": n})
     for name, lod in [("fixed", (cs.CS_LOD_FIXED, tuple(best["thresholds"]), 0, 0.0)),
-                      ("budget", (cs.CS_LOD_BUDGET, (), mlp_ptr, margin))]:
+                      ("budget", (cs.CS_LOD_BUDGET, (), mlp_ptr, margins["budget"])),
+                      ("budget_visible", (cs.CS_LOD_BUDGET_VISIBLE, (), mlp_ptr, margins["budget_visible"]))]:
         p, n = judge.evaluate(lod, hold, floor)
         out[f"{name}_hold_min_psnr"], out[f"{name}_hold_gauss"] = p, n
     judge.close()

@@ -300,3 +300,105 @@ def test_frame_budget_selection_matches_oracle():
         assert same >= 0.99
         mixed += len(set(lv.tolist())) >= 2
     assert mixed >= 2  # budgets that are neither all-fine nor all-coarse were exercised
+
+
+@pytest.mark.timeout(400)
+def test_visible_share_budget_matches_oracle():
+    """CS_LOD_BUDGET_VISIBLE. The render after the selection counts, per
+    instance, the pixels whose largest-weight splat (alpha T, the first of
+    equal ones) is one of its Gaussians: against the oracle's dominant splats
+    over the device's own records and lists, equal but for pixels whose two
+    largest weights sit within float32 reach of each other (at most 1e-3 of
+    the pixels move between instances). The next selection scales each
+    instance's SSE by min(1, visible / (w h)) from those counts and picks the
+    levels the oracle picks at the device's lambda; a render that does not
+    count leaves the following selection at share 1."""
+    import time
+
+    import torch
+
+    from oracle import splat as osplat
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    from .gpu_common import gpu_frame_buffers
+
+    templates, crowd, cam = _scene(n_inst=300)
+    r = _renderer(templates, crowd)
+    dev, host = _net(r)
+    n = crowd.n
+    W, H = cam.width, cam.height
+    tw, th = r.tile
+    counts = np.zeros((n, 5))
+    top = np.zeros(n, np.int64)
+    for i in range(n):
+        lc = np.asarray(templates[int(crowd.tid[i])].level_count, np.float64)
+        counts[i, :len(lc)] = lc
+        top[i] = min(len(lc), 5) - 1
+    floor = 40.0
+    img = torch.zeros((3, H, W), device="cuda")
+
+    def select(mode):
+        lvl = torch.zeros(n, dtype=torch.int32, device="cuda")
+        r.select_lod(cam, mode, (), level_out=lvl, psnr_min=floor, margin=0.0, mlp_ptr=dev.data_ptr())
+        pred = r.debug("PRED", np.float32, n * 16).reshape(n, 16).astype(np.float64)
+        return lvl.cpu().numpy().astype(np.int64), pred
+
+    def draw():
+        r.skin()
+        r.render(cam, img, stats=True)
+        torch.cuda.synchronize()
+
+    print("visible share: first frame (no counts yet)", flush=True)
+    lv0, pred0 = select(cs.CS_LOD_BUDGET_VISIBLE)
+    assert np.all(pred0[:, 6] == 1.0)
+    draw()
+    g = gpu_frame_buffers(r, n)
+    vis_dev = r.debug("VISIBLE", np.uint32, n).astype(np.int64)
+    R = g["rec"].astype(np.float64)
+    sp = dict(u=R[:, 0], v=R[:, 1], A=R[:, 4], B=R[:, 5], C=R[:, 6], opacity=R[:, 7], rgb=R[:, 8:11],
+              depth=R[:, 11])
+    t0 = time.time()
+    dom = osplat.dominant_splats_tiled(sp, g["svals"].astype(np.int64), g["ranges"].astype(np.int64), W, H,
+                                       tw, th)
+    owner = np.searchsorted(g["offset"][:n].astype(np.int64), dom, side="right") - 1
+    vis_or = np.bincount(owner[dom >= 0], minlength=n)
+    moved = int(np.abs(vis_dev - vis_or).sum())
+    print(f"  oracle {time.time() - t0:.1f} s: {vis_or.sum()} covered pixels, {np.count_nonzero(vis_or)} "
+          f"instances seen, count differences {moved}", flush=True)
+    # covered pixels (some splat added) agree but for alpha on the 1/255 edge
+    assert abs(int(vis_dev.sum()) - int(vis_or.sum())) <= 1e-4 * W * H
+    assert moved <= 2e-3 * W * H
+    assert np.count_nonzero(vis_or) >= n // 4
+
+    print("visible share: second frame (counts of the first)", flush=True)
+    lv1, pred1 = select(cs.CS_LOD_BUDGET_VISIBLE)
+    assert np.all(r.debug("VISIBLE", np.uint32, n) == 0)  # cleared for this frame's render
+    assert np.array_equal(pred1[:, 7], vis_dev)
+    win = pred1[:, 13]
+    share = np.where(win > 0, np.minimum(1.0, vis_dev / np.where(win > 0, win, 1.0)), 0.0)
+    np.testing.assert_allclose(pred1[:, 6], share, rtol=2e-7, atol=0)
+    sse = olod.level_sse(pred1[:, :5], win, top, visible_px=vis_dev)
+    np.testing.assert_allclose(pred1[:, 8:13], sse, rtol=4e-6, atol=0)
+    budget = olod.frame_budget(W, H, floor)
+    t_dev = pred1[0, 14]
+    assert sse[np.arange(n), lv1].sum() <= budget * (1 + 1e-5)
+    want = olod.choose_levels(sse, counts, top, 2.0 ** t_dev)
+    cost = np.where(np.arange(5)[None] <= top[:, None], counts + 2.0 ** t_dev * sse, np.inf)
+    srt = np.sort(cost, axis=1)
+    tie = (srt[:, 1] - srt[:, 0]) <= 1e-5 * srt[:, 1]
+    assert np.all((lv1 == want) | tie)
+    lv_o, t_o = olod.select_budget(sse, counts, top, budget)
+    same = np.mean(lv_o == lv1)
+    g0 = counts[np.arange(n), lv0].sum()
+    g1 = counts[np.arange(n), lv1].sum()
+    print(f"  device t {t_dev:.5f}, oracle t {t_o:.5f}, {same:.4f} of the levels equal; Gaussians "
+          f"{g0:.0f} at share 1, {g1:.0f} with the visible share", flush=True)
+    assert same >= 0.99
+    assert g1 <= g0  # a share <= 1 never asks for more detail
+
+    print("visible share: a render that does not count", flush=True)
+    draw()  # counts of the second frame
+    select(cs.CS_LOD_BUDGET)
+    draw()  # plain budget: no counts
+    _, pred3 = select(cs.CS_LOD_BUDGET_VISIBLE)
+    assert np.all(pred3[:, 6] == 1.0)
