@@ -30,6 +30,12 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# Frames in flight only overlap on distinct hardware queues. HIP shares its
+# default 4 queues per process among every stream, torch's stream pool
+# included, and in some process states two of the four frame streams landed
+# on one queue (frames then alternated 3.2 / 6.5 ms: 214 instead of 237 FPS).
+# 8 queues, asked for before anything starts HIP, keep them apart.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
 
 METRIC = "FPS @3,500 avatars 1080p, learned-LoD vs fixed-LoD at ≥40 dB PSNR vs full"
 HBM_PEAK_GBS = 8000.0
@@ -49,9 +55,11 @@ BLEND_FLOPS_PER_EVAL = 24
 # Counter measurements of the headline frame (learned LoD, frame budget) for the kernel sources they were
 # taken on (digest) and one tile shape: HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE
 # scaled by 2.000 and WRITE_SIZE by 1.000, the factors a plain 1 GiB copy gives) and VALU lane-instructions
-# per item (SQ_INSTS_VALU x 64 / items: splats for the projection, pairs for the sort), summarised under
-# profiles/. Other sources or workloads report null.
-MEASURED = {"digest": None, "lod": "learned_budget", "tile": None, "traffic": {}, "valu_per_item": {}}
+# per item (SQ_INSTS_VALU x 64 / items: splats for the projection, pairs for the sort and the blend),
+# summarised under profiles/crowd3500_1080p_budget_16x32_*. Other sources or workloads report null.
+MEASURED = {"digest": "b56c73f689bc681f", "lod": "learned_budget", "tile": (16, 32),
+            "traffic": {"blend": 1_768_265_773, "project_fused": 3_172_704_326, "segsort": 1_103_544_995},
+            "valu_per_item": {"blend": 378.8, "project_fused": 423.3, "segsort": 120.2}}
 
 
 def kernel_digest():
@@ -355,6 +363,13 @@ def frame_roofline(stage_ms, stats, scene, uniq, tile, blend):
         a = flops / t / 1e12
         out.update(bound="alu", achieved=round(a, 3), peak=round(FP32_PEAK_TFLOPS, 1), unit="TFLOP/s",
                    frac=round(a / FP32_PEAK_TFLOPS, 4), flops_per_launch=int(flops))
+        # the instruction stream behind those operations: VALU issue (list compaction, staging, lanes of
+        # finished or untouched pixels) against the non-packed issue peak
+        valu = MEASURED["valu_per_item"].get(dom) if same else None
+        if valu is not None:
+            ai = valu * stats["n_pairs"] / t
+            out["issue"] = {"achieved": round(ai / 1e12, 3), "peak": round(ISSUE_PEAK / 1e12, 2),
+                            "unit": "Tlane-instr/s", "frac": round(ai / ISSUE_PEAK, 4), "valu_per_pair": valu}
         return out
     b = algorithmic_bytes(dom, stats, scene, uniq)
     a = b / t / 1e9
@@ -491,7 +506,10 @@ def fit_leg(torch, steps=2000, timed_steps=50):
     at lr 1e-3 on every attribute, L1 + 0.2 D-SSIM, one camera per step.
     Reports the loss curve, the position error against the truth and the
     time per step (wall over the whole fit, and HIP-event times of each
-    phase over ``timed_steps`` further steps)."""
+    phase over ``timed_steps`` further steps). At lr 1e-3 Adam moves every
+    mean about 1 mm per step whatever its gradient's size and the positions
+    drift while the loss falls, so the same fit is run once more with the
+    positions at lr 1e-4 (``positions_lr_1e-4``)."""
     from paper_2501_17792_amd import fit, synth
 
     truth, crowd, cams = synth.scene_c5()
@@ -510,6 +528,14 @@ def fit_leg(torch, steps=2000, timed_steps=50):
                        phase_times=phases)
     r2.close()
     ph = {k: round(float(np.median(v[1:])), 4) for k, v in phases.items()}
+    lr = dict(mean=1e-4, log_scale=1e-3, quat=1e-3, opacity_logit=1e-3, sh=1e-3)
+    params_b, losses_b, r3 = fit.fit(truth, start, crowd, cams, steps=steps, lr=lr, log_every=500)
+    r3.close()
+    err_b = np.linalg.norm(params_b["mean"].cpu().numpy().astype(np.float64) - truth.mean, axis=1)
+    slow_pos = {"loss_curve": [[k, round(v, 6)] for k, v in losses_b],
+                "position_rmse_m": {"start": round(float(np.sqrt(np.mean(err0 ** 2))), 6),
+                                    "end": round(float(np.sqrt(np.mean(err_b ** 2))), 6)},
+                "closer_fraction": round(float(np.mean(err_b < err0)), 4)}
     return {"workload": "one 100k-Gaussian SH3 template, 512x512, 64 cameras on a 3 m sphere, start perturbed "
                         "(positions N(0, 0.01 m), colours N(0, 0.1)), Adam lr 1e-3, L1 + 0.2 D-SSIM",
             "steps": steps, "ms_per_step_wall": round(1000.0 * wall / steps, 4),
@@ -517,7 +543,7 @@ def fit_leg(torch, steps=2000, timed_steps=50):
             "position_rmse_m": {"start": round(float(np.sqrt(np.mean(err0 ** 2))), 6),
                                 "end": round(float(np.sqrt(np.mean(err1 ** 2))), 6)},
             "position_median_m": {"start": round(float(np.median(err0)), 6), "end": round(float(np.median(err1)), 6)},
-            "closer_fraction": round(float(np.mean(err1 < err0)), 4)}
+            "closer_fraction": round(float(np.mean(err1 < err0)), 4), "positions_lr_1e-4": slow_pos}
 
 
 def copy_bandwidth(torch, stream, nbytes=1 << 30, reps=10):
