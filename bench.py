@@ -34,8 +34,10 @@ sys.path.insert(0, ROOT)
 # default 4 queues per process among every stream, torch's stream pool
 # included, and in some process states two of the four frame streams landed
 # on one queue (frames then alternated 3.2 / 6.5 ms: 214 instead of 237 FPS).
-# 8 queues, asked for before anything starts HIP, keep them apart.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# 8 queues (at least: a larger setting is kept), asked for before anything
+# starts HIP, keep them apart.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 METRIC = "FPS @3,500 avatars 1080p, learned-LoD vs fixed-LoD at ≥40 dB PSNR vs full"
 HBM_PEAK_GBS = 8000.0
@@ -298,10 +300,20 @@ def time_captured(torch, scene, animated, steps, warmup, tile=(16, 16), lod=None
 
 def stage_frame(torch, scene, animated, tile=(16, 16), frames=3, lod=None):
     """Per-stage times of eager frames of the crowd (HIP events on the launch
-    stream), the timed configuration's kernels."""
+    stream), the timed configuration's kernels; then one more frame on a
+    context that counts the blend's live evaluations (slower: only its count
+    is used), returned in ``out["blend_evals"]``."""
     from paper_2501_17792_amd import crowdsplat as cs
 
     mode, thr = lod if lod is not None else (cs.CS_LOD_FULL, ())
+    evals = None
+    with torch.cuda.stream(torch.cuda.Stream()):
+        rc = cs.Renderer(0, fuse=animated, profile=True, tile=tile, count_blend=True)
+        rc.upload_templates(scene.templates)
+        rc.set_crowd(scene.crowd)
+        rc.frame(scene.camera, mode, thr, stats=True)
+        evals = int(rc.last_stats.blend_evals)
+        rc.close()
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         r = cs.Renderer(0, stream=stream, fuse=animated, profile=True, tile=tile)
@@ -325,16 +337,26 @@ def stage_frame(torch, scene, animated, tile=(16, 16), frames=3, lod=None):
     out = {k: float(np.median(v)) for k, v in acc.items()}
     if animated and "project" in out:
         out["project_fused"] = out.pop("project")
+    out["blend_evals"] = evals
     return out, st
 
 
 def dominant_roofline(stage_ms, st, scene, uniq):
+    """Roofline of the longest single-launch kernel of a sweep cell: the
+    projection or the LDS segment sort on algorithmic HBM bytes, the blend on
+    its FP32 operations (24 per counted live evaluation)."""
     kernels = {"project_fused": "project_kernel (skinning fused)", "project": "project_kernel",
-               "segsort": "seg_sort_kernel"}
+               "segsort": "seg_sort_kernel", "blend": "blend_kernel"}
     cand = {k: stage_ms[k] for k in kernels if stage_ms.get(k, 0.0) > 0}
     if not cand:
         return None
     dom = max(cand, key=cand.get)
+    if dom == "blend":
+        flops = float(stage_ms.get("blend_evals") or 0) * BLEND_FLOPS_PER_EVAL
+        a = flops / (stage_ms[dom] * 1e-3) / 1e12
+        return {"bound": "alu", "kernel": kernels[dom], "achieved": round(a, 3), "peak": round(FP32_PEAK_TFLOPS, 1),
+                "unit": "TFLOP/s", "frac": round(a / FP32_PEAK_TFLOPS, 4), "launch_ms": round(stage_ms[dom], 4),
+                "flops_per_launch": int(flops)}
     stats = dict(n_splats=int(st.n_splats), n_pairs=int(st.n_pairs))
     b = algorithmic_bytes(dom, stats, scene, uniq)
     a = b / (stage_ms[dom] * 1e-3) / 1e9
@@ -414,7 +436,8 @@ def sweep_tab2(torch, steps, warmup, cells=None):
                        "frame_ms_p95": round(float(np.percentile(ms, 95)), 4),
                        "gaussians_per_s": round(int(st.n_splats) * fps, 1), "n_splats": int(st.n_splats),
                        "n_pairs": int(st.n_pairs), "overflow": overflow,
-                       "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+                       "stage_ms": {k: round(v, 4) for k, v in stage_ms.items() if k != "blend_evals"},
+                       "blend_evals": stage_ms["blend_evals"],
                        "roofline": dominant_roofline(stage_ms, stp, sc, n_gauss),
                        "paper_fps_rtx4090": PAPER_TAB2_FPS[(n_gauss, animated)][n_chars]}
                 print(json.dumps(rec), flush=True)
@@ -490,7 +513,8 @@ def paper_lod_leg(torch, steps, warmup, n_chars=3500, width=1920, height=1080):
             "frame_ms_p95": round(float(np.percentile(ms, 95)), 4),
             "gaussians_per_s": round(int(st.n_splats) * 1000.0 / med, 1), "n_splats": int(st.n_splats),
             "n_pairs": int(st.n_pairs), "level_hist": list(st.level_hist)[:3], "overflow": overflow,
-            "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
+            "stage_ms": {k: round(v, 4) for k, v in stage_ms.items() if k != "blend_evals"},
+            "blend_evals": stage_ms["blend_evals"],
             "roofline": dominant_roofline(stage_ms, stp, sc, uniq), "paper_fps_rtx4090": 31}
 
 
@@ -514,6 +538,9 @@ def fit_leg(torch, steps=2000, timed_steps=50):
 
     truth, crowd, cams = synth.scene_c5()
     start = synth.perturb_template(truth, seed=502)
+    # 8 views on the same sphere that the fit never sees
+    center = 0.5 * (truth.mean.min(axis=0) + truth.mean.max(axis=0))
+    held = synth.sphere_cameras(777, 8, center, 3.0, cams[0].width, cams[0].height)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     params, losses, r = fit.fit(truth, start, crowd, cams, steps=steps, lr=1e-3, log_every=100)
@@ -523,6 +550,7 @@ def fit_leg(torch, steps=2000, timed_steps=50):
     mean = params["mean"].cpu().numpy().astype(np.float64)
     err0 = np.linalg.norm(start.mean.astype(np.float64) - truth.mean, axis=1)
     err1 = np.linalg.norm(mean - truth.mean, axis=1)
+    view0, view1 = fit.view_psnr(truth, params, start, crowd, held)
     phases = {}
     _, _, r2 = fit.fit(truth, start, crowd, cams, steps=timed_steps, lr=1e-3, log_every=10 ** 9,
                        phase_times=phases)
@@ -532,7 +560,9 @@ def fit_leg(torch, steps=2000, timed_steps=50):
     params_b, losses_b, r3 = fit.fit(truth, start, crowd, cams, steps=steps, lr=lr, log_every=500)
     r3.close()
     err_b = np.linalg.norm(params_b["mean"].cpu().numpy().astype(np.float64) - truth.mean, axis=1)
+    _, view_b = fit.view_psnr(truth, params_b, start, crowd, held)
     slow_pos = {"loss_curve": [[k, round(v, 6)] for k, v in losses_b],
+                "held_out_view_psnr_db": {"start": round(view0, 3), "end": round(view_b, 3)},
                 "position_rmse_m": {"start": round(float(np.sqrt(np.mean(err0 ** 2))), 6),
                                     "end": round(float(np.sqrt(np.mean(err_b ** 2))), 6)},
                 "closer_fraction": round(float(np.mean(err_b < err0)), 4)}
@@ -543,7 +573,9 @@ def fit_leg(torch, steps=2000, timed_steps=50):
             "position_rmse_m": {"start": round(float(np.sqrt(np.mean(err0 ** 2))), 6),
                                 "end": round(float(np.sqrt(np.mean(err1 ** 2))), 6)},
             "position_median_m": {"start": round(float(np.median(err0)), 6), "end": round(float(np.median(err1)), 6)},
-            "closer_fraction": round(float(np.mean(err1 < err0)), 4), "positions_lr_1e-4": slow_pos}
+            "closer_fraction": round(float(np.mean(err1 < err0)), 4),
+            "held_out_view_psnr_db": {"start": round(view0, 3), "end": round(view1, 3), "views": len(held)},
+            "positions_lr_1e-4": slow_pos}
 
 
 def copy_bandwidth(torch, stream, nbytes=1 << 30, reps=10):

@@ -119,3 +119,30 @@ def fit(truth: synth.Template, start: synth.Template, crowd, cams, steps=2000, l
             if log:
                 log(f"step {step} loss {losses[-1][1]:.5f}")
     return {k: params[k].detach() for k in PARAMS}, losses, r
+
+
+def view_psnr(truth: synth.Template, fitted, start: synth.Template, crowd, cams):
+    """PSNR (dB, over all pixels of ``cams``) of renders of the fitted
+    attribute tensors ``fitted`` (as ``fit`` returns them) and of ``start``
+    against renders of ``truth``: the image-space measure of a fit, on views
+    it was not fitted to. Returns (start dB, fitted dB)."""
+    torch = _torch()
+    r = cs.Renderer(0)
+    try:
+        r.upload_templates([truth])
+        r.set_crowd(crowd)
+        refs = render_targets(r, cams)
+        r.upload_templates([start])
+        first = render_targets(r, cams)
+        P = template_tensors(start, r.device)
+        r.update_template(0, fitted["mean"], fitted["log_scale"], fitted["quat"], fitted["opacity_logit"],
+                          fitted["sh"], P["skin_idx"], P["skin_w"], opacity_is_logit=True)
+        last = render_targets(r, cams)
+
+        def db(imgs):
+            mse = sum(float(torch.mean((a - b) ** 2).item()) for a, b in zip(imgs, refs)) / len(refs)
+            return float("inf") if mse == 0.0 else -10.0 * math.log10(mse)
+
+        return db(first), db(last)
+    finally:
+        r.close()
