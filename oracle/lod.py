@@ -7,7 +7,7 @@ distance thresholds by a small network that predicts, per instance, the PSNR
 of every level against the full template, and picks the coarsest level whose
 prediction clears a quality floor.
 
-Definitions (readings listed in the design doc):
+Definitions (readings where the paper is silent):
 * view box: the screen rectangle covering every posed joint in front of the
   near plane, each padded by the template's rest pad radius projected at the
   joint's depth (fx * pad / depth); clipped to the image;

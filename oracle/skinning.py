@@ -5,7 +5,7 @@ canonical template; linear blend skinning moves the template's Gaussians.
 Characters of one template share every attribute except the pose (§2, the
 paragraph on shared template attributes).
 
-Conventions (readings listed in the design doc):
+Conventions (readings where the paper is silent):
 * joint rotations are axis-angle vectors turned into matrices by Rodrigues'
   formula; the chain is G_0 = [R_0 | J_0], G_j = G_parent [R_j | J_j - J_parent];
 * the skinning matrix of joint j is A_j = G_j [I | -J_j], placed in the world by

@@ -3,7 +3,7 @@
 The paper's own data (reconstructed avatar templates, AMASS motions, the grid
 crowd of CrowdSplat §2 and §3) is not available, so every workload is drawn
 here from fixed seeds with the shapes and distributions of the five
-workloads described in the design doc:
+workloads below:
 
 * ``c1``  plain method, one 2,048-Gaussian SH0 template, one instance, 256x256;
 * ``c2``  14 templates x 100k Gaussians (SH3), 500 instances, 1920x1080,
