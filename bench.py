@@ -31,11 +31,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 # Frames in flight only overlap on distinct hardware queues. HIP shares its
-# default 4 queues per process among every stream, torch's stream pool
-# included, and in some process states two of the four frame streams landed
-# on one queue (frames then alternated 3.2 / 6.5 ms: 214 instead of 237 FPS).
-# 8 queues (at least: a larger setting is kept), asked for before anything
-# starts HIP, keep them apart.
+# queues (4 per process by default) among every stream, torch's stream pool
+# included, and two of the four frame streams could land on one queue (frames
+# then alternated 3.2 / 6.5 ms: 214 instead of 237 FPS). The frame streams are
+# picked by a concurrency probe (autotune.distinct_streams), from 8 queues
+# (at least: a larger setting is kept), asked for before anything starts HIP.
 if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < 8:
     os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
@@ -55,13 +55,18 @@ FP32_PEAK_TFLOPS = 2 * ISSUE_PEAK / 1e12
 BLEND_FLOPS_PER_EVAL = 24
 
 # Counter measurements of the headline frame (learned LoD, frame budget) for the kernel sources they were
-# taken on (digest) and one tile shape: HBM bytes per launch from two rocprofv3 --pmc runs (FETCH_SIZE
-# scaled by 2.000 and WRITE_SIZE by 1.000, the factors a plain 1 GiB copy gives) and VALU lane-instructions
-# per item (SQ_INSTS_VALU x 64 / items: splats for the projection, pairs for the sort and the blend),
-# summarised under profiles/crowd3500_1080p_budget_16x32_*. Other sources or workloads report null.
-MEASURED = {"digest": "b56c73f689bc681f", "lod": "learned_budget", "tile": (16, 32),
-            "traffic": {"blend": 1_768_265_773, "project_fused": 3_172_704_326, "segsort": 1_103_544_995},
-            "valu_per_item": {"blend": 378.8, "project_fused": 423.3, "segsort": 120.2}}
+# taken on (digest), per tile shape the autotuner may pick: HBM bytes per launch from two rocprofv3 --pmc
+# runs (FETCH_SIZE scaled by 2.000 and WRITE_SIZE by 1.000, the factors a plain 1 GiB copy gives) and VALU
+# lane-instructions per item (SQ_INSTS_VALU x 64 / items: splats for the projection, pairs for the sort and
+# the blend), summarised under profiles/crowd3500_1080p_budget_<tile>_kernels.md. Other sources, tiles or
+# workloads report null.
+MEASURED = {"digest": "fb64304f69bff236", "lod": "learned_budget",
+            "tiles": {(16, 32): {"traffic": {"blend": 1_768_265_772, "project_fused": 3_172_704_326,
+                                             "segsort": 1_103_544_994},
+                                 "valu_per_item": {"blend": 378.8, "project_fused": 423.3, "segsort": 120.2}},
+                      (32, 16): {"traffic": {"blend": 1_769_286_428, "project_fused": 3_174_393_390,
+                                             "segsort": 1_071_544_782},
+                                 "valu_per_item": {"blend": 533.0, "project_fused": 423.3, "segsort": 120.1}}}}
 
 
 def kernel_digest():
@@ -377,9 +382,9 @@ def frame_roofline(stage_ms, stats, scene, uniq, tile, blend):
     cand = {k: stage_ms[k] for k in kernels if stage_ms.get(k, 0.0) > 0}
     dom = max(cand, key=cand.get)
     t = stage_ms[dom] * 1e-3
-    same = kernel_digest() == MEASURED["digest"] and tuple(tile) == tuple(MEASURED["tile"] or ())
+    meas = MEASURED["tiles"].get(tuple(tile)) if kernel_digest() == MEASURED["digest"] else None
     out = {"kernel": kernels[dom], "launch_ms": round(stage_ms[dom], 4),
-           "traffic": MEASURED["traffic"].get(dom) if same else None}
+           "traffic": meas["traffic"].get(dom) if meas else None}
     if dom == "blend":
         flops = blend["evals_per_frame"] * BLEND_FLOPS_PER_EVAL
         a = flops / t / 1e12
@@ -387,7 +392,7 @@ def frame_roofline(stage_ms, stats, scene, uniq, tile, blend):
                    frac=round(a / FP32_PEAK_TFLOPS, 4), flops_per_launch=int(flops))
         # the instruction stream behind those operations: VALU issue (list compaction, staging, lanes of
         # finished or untouched pixels) against the non-packed issue peak
-        valu = MEASURED["valu_per_item"].get(dom) if same else None
+        valu = meas["valu_per_item"].get(dom) if meas else None
         if valu is not None:
             ai = valu * stats["n_pairs"] / t
             out["issue"] = {"achieved": round(ai / 1e12, 3), "peak": round(ISSUE_PEAK / 1e12, 2),
@@ -398,7 +403,7 @@ def frame_roofline(stage_ms, stats, scene, uniq, tile, blend):
     hbm = {"achieved": round(a, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(a / HBM_PEAK_GBS, 4),
            "bytes_per_launch": int(b)}
     items = stats["n_splats"] if dom == "project_fused" else stats["n_pairs"]
-    valu = MEASURED["valu_per_item"].get(dom) if same else None
+    valu = meas["valu_per_item"].get(dom) if meas else None
     issue = None
     if valu is not None:
         ai = valu * items / t
@@ -578,6 +583,54 @@ def fit_leg(torch, steps=2000, timed_steps=50):
             "positions_lr_1e-4": slow_pos}
 
 
+# useful FLOPs of the offset network per instance-Gaussian (its per-Gaussian layers: 32 embedding inputs
+# to 64, 64 to 64, 64 to 3; FMA = 2) and per instance (the pose part of the first layer, 80 to 64)
+OFFSET_FLOPS_PER_SPLAT = 2 * (32 * 64 + 64 * 64 + 64 * 3)
+OFFSET_FLOPS_PER_INSTANCE = 2 * 80 * 64
+BF16_PEAK_TFLOPS = 2500.0  # dense bf16 matrix-core peak of one MI355X
+
+
+def offsets_leg(torch, scene, poses_all, lod, tile, pose_net, timed, frames=3):
+    """The headline frame with pose-dependent offsets: frame rate as timed
+    (``timed``: captured frames in flight), then the offsets stage of eager
+    instrumented frames (HIP events) against the matrix cores' bf16 peak on
+    the network's useful operations, and against HBM on its compulsory bytes
+    (the offsets written, 16 B per instance-Gaussian, and every template's
+    embeddings read once, 64 B per Gaussian)."""
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    mode, thr, mlp_ptr, margin = lod
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        r = cs.Renderer(0, stream=stream, fuse=True, profile=True, tile=tile)
+        r.upload_templates(scene.templates)
+        r.set_crowd(scene.crowd)
+        r.upload_pose_net(*pose_net)
+        img = torch.zeros((3, scene.camera.height, scene.camera.width), device=poses_all.device)
+        ts = []
+        for k in range(frames + 1):
+            r.pose_dev.copy_(poses_all[k % poses_all.shape[0]])
+            r.select_lod(scene.camera, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
+            r.skin()
+            r.render(scene.camera, img, stats=True)
+            if k:
+                ts.append(r.stage_times()["offsets"])
+        stream.synchronize()
+        n_splats = int(r.last_stats.n_splats)
+        r.close()
+    t = float(np.mean(ts)) * 1e-3
+    flops = n_splats * OFFSET_FLOPS_PER_SPLAT + scene.crowd.n * OFFSET_FLOPS_PER_INSTANCE
+    nbytes = 16 * n_splats + 64 * sum(tpl.n for tpl in scene.templates)
+    mfma = flops / t / 1e12
+    hbm = nbytes / t / 1e9
+    return {"fps": round(1000.0 / timed["ms"], 2), "frame_ms_p95": round(float(np.percentile(timed["per"], 95)), 4),
+            "overflow": timed["overflow"], "n_splats": n_splats, "offsets_ms": round(t * 1e3, 4),
+            "mfma": {"achieved": round(mfma, 2), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(mfma / BF16_PEAK_TFLOPS, 4), "flops_per_launch": int(flops)},
+            "hbm": {"achieved": round(hbm, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(hbm / HBM_PEAK_GBS, 4),
+                    "bytes_per_launch": int(nbytes)}}
+
+
 def copy_bandwidth(torch, stream, nbytes=1 << 30, reps=10):
     """Achievable HBM bandwidth: the library's copy kernel over 1 GiB (read +
     write bytes per second), HIP events on its stream."""
@@ -622,6 +675,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--stage-frames", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-offsets", action="store_true", help="skip the headline frame with pose-dependent offsets")
     ap.add_argument("--no-psnr", action="store_true", help="skip the PSNR of every rule on the held-out frames")
     ap.add_argument("--instances", type=int, default=3500)
     ap.add_argument("--net", default=os.path.join(ROOT, "paper_2501_17792_amd", "lod_net.npz"))
@@ -723,7 +777,7 @@ def main():
     # for each other)
     streams = autotune_streams(torch, dev, inflight, None)
 
-    def run(lod, n, sc=scene, poses=poses_all):  # fresh contexts per run: capacities are fixed at capture
+    def run(lod, n, sc=scene, poses=poses_all, pose_net=None):  # fresh contexts: capacities are fixed at capture
         with torch.cuda.stream(stream):
             imgs = [torch.zeros((3, sc.camera.height, sc.camera.width), device=dev) for _ in range(n)]
             rs = []
@@ -731,6 +785,8 @@ def main():
                 r = cs.Renderer(0, stream=st, fuse=True, tile=tile)
                 r.upload_templates(sc.templates)
                 r.set_crowd(sc.crowd)
+                if pose_net is not None:
+                    r.upload_pose_net(*pose_net)
                 rs.append(r)
             torch.cuda.synchronize()
             out = time_mode(torch, rs, sc, poses, imgs, streams[:n], lod, args.steps, args.warmup)
@@ -756,6 +812,14 @@ def main():
             poses2 = torch.from_numpy(np.ascontiguousarray(sc2.crowd.pose[None], np.float32)).to(dev)
         c2 = run((cs.CS_LOD_FIXED, (10.0, 10.0, 25.0, 25.0), 0, 0.0), len(streams), sc=sc2, poses=poses2)
         log(f"500 avatars, 10/25 m: {1000.0 / c2['ms']:.1f} FPS")
+
+    # the headline frame with pose-dependent offsets (synthetic offset network and embeddings)
+    offsets = None
+    if not args.no_offsets:
+        pn = (synth.pose_net_weights(), [synth.pose_embeddings(1200 + t, tpl.n) for t, tpl in enumerate(scene.templates)])
+        ro = run(modes[head], len(streams), pose_net=pn)
+        offsets = offsets_leg(torch, scene, poses_all, modes[head], tile, pn, ro)
+        log(f"{head} with pose-dependent offsets: {offsets['fps']:.1f} FPS, offsets stage {offsets['offsets_ms']:.3f} ms")
 
     res = results[head]
     ms = res["ms"]
@@ -870,7 +934,7 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
         "stage_gbs": {k: round(v, 1) for k, v in stage_gbs.items()},
         "copy_gbs": round(copy_gbs, 1), "copy_ok": copy_ok, "stage_frac_of_copy": stage_copy_frac,
-        "blend": blend, "fit": fit_res,
+        "blend": blend, "fit": fit_res, "pose_offsets": offsets,
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -104,22 +104,48 @@ def tune(torch, scene, poses_all, stream, lod, frames: int = 20, candidates=CAND
     return tile, timing
 
 
-def distinct_streams(torch, dev, n, first=None):
-    """``n`` streams with distinct handles (``first`` leading if given).
-    torch hands out streams from a fixed pool round-robin, so a new Stream()
-    can be one already in use: two frames in flight on one stream would run
-    one after the other."""
+def _overlap_span(torch, dev, streams, cycles):
+    """Milliseconds from a common start until a spin of ``cycles`` clocks has
+    ended on every stream in ``streams`` (all launched at once)."""
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    start.record(torch.cuda.current_stream(dev))
+    ends = []
+    for st in streams:
+        st.wait_event(start)
+        with torch.cuda.stream(st):
+            torch.cuda._sleep(cycles)
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(st)
+        ends.append(e)
+    torch.cuda.synchronize()
+    return max(start.elapsed_time(e) for e in ends)
+
+
+def distinct_streams(torch, dev, n, first=None, cycles=2_000_000):
+    """``n`` streams (``first`` leading if given) that run at the same time.
+    Frames in flight overlap only on distinct hardware queues, and HIP hands
+    its queues to torch's pooled streams in an order that pairs some of them
+    (measured: with 8 queues, pool streams i and 11 - i share one). So each
+    candidate from the pool is tried by launching a short spin kernel on it
+    together with the streams already taken: it is kept if all of them still
+    finish in about the time of one."""
     out = [first] if first is not None else []
     seen = {int(st.cuda_stream) for st in out}
-    for _ in range(256):
+    probe = torch.cuda.Stream(dev)
+    _overlap_span(torch, dev, [probe], cycles)  # first launch: code loading
+    one = _overlap_span(torch, dev, [probe], cycles)
+    for _ in range(64):
         if len(out) >= n:
             break
         st = torch.cuda.Stream(dev)
-        if int(st.cuda_stream) not in seen:
-            seen.add(int(st.cuda_stream))
+        if int(st.cuda_stream) in seen:
+            continue
+        seen.add(int(st.cuda_stream))
+        if _overlap_span(torch, dev, out + [st], cycles) < 1.4 * one:
             out.append(st)
     if len(out) < n:
-        raise RuntimeError(f"could not get {n} distinct streams")
+        raise RuntimeError(f"could not find {n} streams that run at the same time")
     return out
 
 

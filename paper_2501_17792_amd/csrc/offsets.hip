@@ -88,6 +88,13 @@ __global__ __launch_bounds__(256) void pose_offset_kernel(WorkDev w, const PoseN
                                                           int chunk_lo, int chunk_hi) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, g = lane >> 4;
+  // XCD-aware order over the template-major chunks (the instances of one
+  // template read the same embeddings); a captured frame launches the chunk
+  // capacity, and the workgroups past the frame's chunks leave before
+  // fetching the weights
+  const int hi = chunk_hi >= 0 ? chunk_hi : (int)w.hdr->n_chunks;
+  const XcdSpan sp = xcd_span(blockIdx.x, gridDim.x, hi - chunk_lo);
+  if (sp.first >= sp.end) return;
   // weights as A operands, in registers for the whole kernel
   pn_bf16x8 a1[4], a2[4][2], a3[2];
 #pragma unroll
@@ -108,8 +115,7 @@ __global__ __launch_bounds__(256) void pose_offset_kernel(WorkDev w, const PoseN
 #pragma unroll
   for (int j = 0; j < 4; ++j) bias3[j] = net->b3[4 * g + j];
 
-  const int hi = chunk_hi >= 0 ? chunk_hi : (int)w.hdr->n_chunks;
-  for (int c = chunk_lo + blockIdx.x; c < hi; c += gridDim.x) {
+  for (int c = chunk_lo + sp.first; c < chunk_lo + sp.end; c += sp.step) {
     const Chunk ch = w.chunks[c];
     const cs_instance in = w.inst[ch.inst];
     const TemplateDev& T = w.tpl[in.tid];
