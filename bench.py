@@ -33,9 +33,10 @@ sys.path.insert(0, ROOT)
 # Frames in flight only overlap on distinct hardware queues. HIP shares its
 # queues (4 per process by default) among every stream, torch's stream pool
 # included, and two of the four frame streams could land on one queue (frames
-# then alternated 3.2 / 6.5 ms: 214 instead of 237 FPS). The frame streams are
-# picked by a concurrency probe (autotune.distinct_streams), from 8 queues
-# (at least: a larger setting is kept), asked for before anything starts HIP.
+# then alternated 3.5 / 6.7 ms: 215 instead of 237 FPS). The frame streams are
+# picked by a concurrency probe and a short run of the frame that must advance
+# evenly (autotune.pick_streams), from 8 queues (at least: a larger setting is
+# kept), asked for before anything starts HIP.
 if int(os.environ.get("GPU_MAX_HW_QUEUES", "0") or 0) < 8:
     os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
@@ -655,12 +656,6 @@ def copy_bandwidth(torch, stream, nbytes=1 << 30, reps=10):
     return 2.0 * nbytes / (ms * 1e-3) / 1e9, ok
 
 
-def autotune_streams(torch, dev, n, first):
-    from paper_2501_17792_amd import autotune
-
-    return autotune.distinct_streams(torch, dev, n, first)
-
-
 def load_rules(path):
     if not os.path.exists(path):
         return None
@@ -773,9 +768,13 @@ def main():
         tile = tuple(int(x) for x in args.tile.split("x"))
     inflight = inflight or 3
     log(f"tile {tile}, {inflight} frames in flight")
-    # consecutive streams of torch's pool (frames in flight on streams that share a hardware queue wait
-    # for each other)
-    streams = autotune_streams(torch, dev, inflight, None)
+    # frame streams: a set on which the frames in flight advance evenly (short runs of the headline frame)
+    from paper_2501_17792_amd import autotune
+
+    def trial(sts):
+        return autotune.frames_on(torch, scene, poses_all, modes[head], tile, sts, 80, 10)
+
+    streams, stream_sets = autotune.pick_streams(torch, dev, inflight, trial, log=log)
 
     def run(lod, n, sc=scene, poses=poses_all, pose_net=None):  # fresh contexts: capacities are fixed at capture
         with torch.cuda.stream(stream):
@@ -918,7 +917,7 @@ def main():
                    "lod": head, "instances": scene.crowd.n, "width": scene.camera.width,
                    "height": scene.camera.height, "tile": list(tile)},
         "autotune": tile_timing,
-        "frames_in_flight": len(streams),
+        "frames_in_flight": len(streams), "frame_stream_sets_tried": stream_sets,
         "frame_ms_median": round(float(np.median(res["per"])), 4),
         "frame_ms_p95": round(float(np.percentile(res["per"], 95)), 4),
         "one_frame_in_flight": {"fps": round(1000.0 / single["ms"], 2), "frame_ms": round(single["ms"], 4)},
