@@ -23,6 +23,26 @@ constexpr int kGT = 59;    // per-splat template gradient: mean3 ls3 q4 logit1 s
 // ---------------------------------------------------------------------------
 // 1. backward blend
 // ---------------------------------------------------------------------------
+// v plus v of the lane n below it in its row of 16 (0 past the row's start):
+// one step of an inclusive scan inside each row, on the DPP path (no LDS).
+template <int N>
+__device__ __forceinline__ float row_shr_add(float v) {
+  static_assert(N >= 1 && N <= 15, "row shift");
+  return v + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x110 + N, 0xf, 0xf, true));
+}
+
+// Sum over the 64 lanes of a wave (the same on every lane), in a fixed
+// order: scans inside the four rows of 16 lanes, then the rows' totals
+// (their last lanes) added in row order.
+__device__ __forceinline__ float wave_sum(float v) {
+  v = row_shr_add<1>(v);
+  v = row_shr_add<2>(v);
+  v = row_shr_add<4>(v);
+  v = row_shr_add<8>(v);
+  const int b = __float_as_int(v);
+  return (__int_as_float(__builtin_amdgcn_readlane(b, 15)) + __int_as_float(__builtin_amdgcn_readlane(b, 31))) +
+         (__int_as_float(__builtin_amdgcn_readlane(b, 47)) + __int_as_float(__builtin_amdgcn_readlane(b, 63)));
+}
 template <int TW, int TH>
 __global__ __launch_bounds__(TW* TH) void blend_backward_kernel(
     const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ svals, const float4* __restrict__ rec, const uint32_t* __restrict__ rect, const uint32_t* __restrict__ pair_off,
@@ -81,6 +101,12 @@ __global__ __launch_bounds__(TW* TH) void blend_backward_kernel(
   }
   // colour behind the current pair, starting with the background
   float Sr = T * cam.bg[0], Sg = T * cam.bg[1], Sb = T * cam.bg[2];
+  // this wave's pixel centres (rows [wave ROWS, wave ROWS + ROWS) of the
+  // tile), widened by 0.01 px: a pair whose alpha >= 1/255 box misses them
+  // adds nothing to any of the wave's pixels and is skipped by the wave
+  constexpr int ROWS = 64 / TW;
+  const float wx0 = (float)(tx * TW) + 0.49f, wx1 = (float)(tx * TW + TW - 1) + 0.51f;
+  const float wy0 = (float)(ty * TH + wave * ROWS) + 0.49f, wy1 = (float)(ty * TH + wave * ROWS + ROWS - 1) + 0.51f;
   // ---- back to front over the list, batches of N pairs
   const uint32_t len = end - start;
   for (int bb = (int)((len + N - 1) / N) - 1; bb >= 0; --bb) {
@@ -112,8 +138,10 @@ __global__ __launch_bounds__(TW* TH) void blend_backward_kernel(
 #pragma unroll
         for (int e = 0; e < kGP; ++e) gv[e] = 0.f;
         bool contrib = false;
-        if (k <= last) {
-          const float4 r0 = s_r0[j], r1 = s_r1[j], r2 = s_r2[j];
+        const float4 r0 = s_r0[j];
+        const bool near = !(r0.x + r0.z < wx0 || r0.x - r0.z > wx1 || r0.y + r0.w < wy0 || r0.y - r0.w > wy1);
+        if (near && k <= last) {
+          const float4 r1 = s_r1[j], r2 = s_r2[j];
           const float dx = pcx - r0.x, dy = pcy - r0.y;
           const float praw = -0.5f * fmaf(r1.x * dx, dx, r1.z * dy * dy) - r1.y * dx * dy;
           const float power = fminf(praw, 0.f);
@@ -145,12 +173,24 @@ __global__ __launch_bounds__(TW* TH) void blend_backward_kernel(
             }
           }
         }
-        if (__ballot(contrib) != 0ull) {
+        const uint64_t cm = __ballot(contrib);
+        if (cm != 0ull) {
+          if (__popcll(cm) <= 6) {
+            // few pixels: the contributing lanes' values summed in lane order
+            float acc[kGP];
 #pragma unroll
-          for (int e = 0; e < kGP; ++e) {
-            float v = gv[e];
-            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-            gv[e] = v;
+            for (int e = 0; e < kGP; ++e) acc[e] = 0.f;
+            for (uint64_t m = cm; m != 0ull; m &= m - 1ull) {
+              const int l = (int)__builtin_ctzll(m);
+#pragma unroll
+              for (int e = 0; e < kGP; ++e)
+                acc[e] += __int_as_float(__builtin_amdgcn_readlane(__float_as_int(gv[e]), l));
+            }
+#pragma unroll
+            for (int e = 0; e < kGP; ++e) gv[e] = acc[e];
+          } else {
+#pragma unroll
+            for (int e = 0; e < kGP; ++e) gv[e] = wave_sum(gv[e]);
           }
         }
         if (lane == 0) {

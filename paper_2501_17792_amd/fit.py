@@ -66,15 +66,19 @@ def render_targets(r, cams):
 
 
 def fit(truth: synth.Template, start: synth.Template, crowd, cams, steps=2000, lr=1e-3, lam=0.2, seed=503,
-        log=None, log_every=100, phase_times=None):
+        log=None, log_every=100, phase_times=None, tile=(8, 8)):
     """Fit ``start`` to renders of ``truth`` from ``cams``; returns the fitted
     tensors and the loss history. ``lr`` is one rate for every attribute or a
     dict per attribute (mean, log_scale, quat, opacity_logit, sh). With a
     dict ``phase_times``, every step's forward render, loss, backward and Adam
-    update are timed with HIP events on the renderer's stream (ms lists)."""
+    update are timed with HIP events on the renderer's stream (ms lists).
+    ``tile``: the tile shape of the forward and backward rasterisers (8x8:
+    the backward walks each tile's list once per wave, pair after pair, so
+    its longest tiles set the step time; at 512x512 a 100k-Gaussian step
+    measured 4.5 ms at 8x8 against 6.6 ms at 16x16)."""
     lrs = lr if isinstance(lr, dict) else {k: lr for k in PARAMS}
     torch = _torch()
-    r = cs.Renderer(0)
+    r = cs.Renderer(0, tile=tile)
     r.upload_templates([truth])
     r.set_crowd(crowd)
     targets = render_targets(r, cams)
