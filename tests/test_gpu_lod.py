@@ -402,3 +402,41 @@ def test_visible_share_budget_matches_oracle():
     draw()  # plain budget: no counts
     _, pred3 = select(cs.CS_LOD_BUDGET_VISIBLE)
     assert np.all(pred3[:, 6] == 1.0)
+
+
+def test_visible_share_counts_chain_through_graph_replays():
+    """A captured CS_LOD_BUDGET_VISIBLE frame: each replay's selection reads
+    the counts of the frame drawn just before it (the eager frame for the
+    first replay, then the previous replay) and its blend leaves its own."""
+    import torch
+
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    templates, crowd, cam = _scene(n_inst=300)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        r = cs.Renderer(0, stream=stream)
+        r.upload_templates(templates)
+        r.set_crowd(crowd)
+        dev, _ = _net(r)
+        n = crowd.n
+        img = torch.zeros((3, cam.height, cam.width), device="cuda")
+        r.select_lod(cam, cs.CS_LOD_BUDGET_VISIBLE, (), psnr_min=40.0, margin=0.0, mlp_ptr=dev.data_ptr())
+        r.skin()
+        r.render(cam, img)
+        stream.synchronize()
+        before = r.debug("VISIBLE", np.uint32, n).astype(np.float64)
+        assert before.sum() > 0
+        r.capture(cam, img, cs.CS_LOD_BUDGET_VISIBLE, (), mlp_ptr=dev.data_ptr(), psnr_min=40.0, margin=0.0)
+        scaled = 0
+        for k in range(3):
+            r.launch()
+            assert r.poll().overflow == 0
+            stream.synchronize()
+            pred = r.debug("PRED", np.float32, n * 16).reshape(n, 16).astype(np.float64)
+            assert np.array_equal(pred[:, 7], before), k
+            scaled += int(np.sum(pred[:, 6] < 1.0))
+            before = r.debug("VISIBLE", np.uint32, n).astype(np.float64)
+            assert before.sum() > 0
+        assert scaled > 0
+        r.close()

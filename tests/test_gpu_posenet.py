@@ -108,3 +108,43 @@ def test_offsets_move_the_frame_and_can_be_removed():
     again = r.frame(sc.camera, cs.CS_LOD_FIXED, sc.lod_thresholds).cpu().numpy()
     assert np.array_equal(again, plain)
     r.close()
+
+
+def test_captured_frame_with_offsets_equals_eager():
+    """The whole frame with the offset network captured as a graph: every
+    replay (with unrelated eager work in between) gives the eager frame's
+    image and offsets bit for bit. A captured frame launches the offset
+    kernel over the chunk capacity (here several times the frame's chunks);
+    the workgroups past the frame's chunks must leave without effect."""
+    import torch
+
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    sc = _scene()
+    net, embeds = _net_and_embeds(sc)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        r = cs.Renderer(0, stream=stream, fuse=True)
+        r.upload_templates(sc.templates)
+        r.set_crowd(sc.crowd)
+        r.upload_pose_net(net, embeds)
+        ref = r.frame(sc.camera, cs.CS_LOD_FIXED, sc.lod_thresholds, stats=True).clone()
+        n = int(r.last_stats.n_splats)
+        stream.synchronize()
+        off_ref = r.debug("OFFSETS", np.float32, 4 * n)
+        other = cs.Renderer(0, stream=stream)
+        other.upload_templates(sc.templates)
+        other.set_crowd(sc.crowd)
+        out = torch.zeros_like(ref)
+        r.capture(sc.camera, out, cs.CS_LOD_FIXED, sc.lod_thresholds)
+        for k in range(3):
+            out.zero_()
+            r.launch()
+            assert r.poll().overflow == 0
+            stream.synchronize()
+            assert torch.equal(out, ref), k
+            assert np.array_equal(r.debug("OFFSETS", np.float32, 4 * n), off_ref), k
+            other.frame(sc.camera, cs.CS_LOD_FIXED, sc.lod_thresholds)  # unrelated eager work
+        stream.synchronize()
+        other.close()
+        r.close()
