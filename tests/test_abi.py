@@ -77,3 +77,26 @@ def test_null_context_calls_return_invalid():
     assert lib.cs_render_frame(None, None, None, None) == cs.CS_ERR_INVALID
     assert lib.cs_frame_launch(None) == cs.CS_ERR_INVALID
     lib.cs_destroy(None)
+
+
+def test_header_constants_match_the_binding():
+    """Every integer constant of the header that the binding mirrors (LoD
+    modes, debug buffers, sort and launch options, limits) has the header's
+    value, so a new mode or buffer cannot drift between the two."""
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    text = open(HEADER).read()
+    consts = {}
+    for name, val in re.findall(r"^#define\s+(CS_\w+)\s+(\(1 << \d+\)|-?\d+)\b", text, re.M):
+        consts[name] = 1 << int(val[6:-1]) if val.startswith("(") else int(val)
+    checked = 0
+    for name, val in consts.items():
+        if name.startswith("CS_BUF_"):
+            assert cs.BUF[name[len("CS_BUF_"):]] == val, name
+            checked += 1
+        elif hasattr(cs, name):
+            assert getattr(cs, name) == val, name
+            checked += 1
+    assert "CS_LOD_BUDGET_VISIBLE" in consts and cs.CS_LOD_BUDGET_VISIBLE == consts["CS_LOD_BUDGET_VISIBLE"]
+    assert len(cs.BUF) == sum(1 for n in consts if n.startswith("CS_BUF_"))
+    assert checked >= 20
