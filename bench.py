@@ -189,19 +189,31 @@ def oracle_levels(scene, host_net, margin, floor=40.0):
     return levels, counts
 
 
-def cpu_baseline(scene, host_net, margin, per_worker=21):
+def oracle_fixed_levels(scene, thresholds):
+    """The fixed-distance LoD of the whole crowd by the FP64 oracle."""
+    from oracle import frame as oframe
+
+    levels = oframe.fixed_levels(scene.crowd.pos, scene.camera.eye, thresholds)
+    counts = np.zeros((scene.crowd.n, 5))
+    for i in range(scene.crowd.n):
+        lc = np.asarray(scene.templates[int(scene.crowd.tid[i])].level_count, np.float64)
+        counts[i, :len(lc)] = lc
+    return np.asarray(levels, np.int64), counts
+
+
+def cpu_baseline(scene, host_net, margin, per_worker=21, levels_fn=None, what="the learned-LoD (frame budget) crowd"):
     """The FP64 oracle on the host's cores (at most 16: the host share of one
-    GPU), timed on a bounded sample of the headline frame (frame 0): LoD
-    selection of all instances, then skin + project and binning + sort +
-    compositing of a seeded sample of instances (per_worker per core) in a
-    process pool, each phase's wall time extrapolated per Gaussian and per
-    tile pair to the oracle's own frame. Runs before the GPU is touched (the
-    pool forks)."""
+    GPU), timed on a bounded sample of the frame (frame 0): LoD selection of
+    all instances (the frame budget, or ``levels_fn()``), then skin + project
+    and binning + sort + compositing of a seeded sample of instances
+    (per_worker per core) in a process pool, each phase's wall time
+    extrapolated per Gaussian and per tile pair to the oracle's own frame.
+    Runs before the GPU is touched (the pool forks)."""
     import multiprocessing as mp
 
     cores = _cpu_cores()
     t0 = time.perf_counter()
-    levels, counts = oracle_levels(scene, host_net, margin)
+    levels, counts = levels_fn() if levels_fn is not None else oracle_levels(scene, host_net, margin)
     t_lod = time.perf_counter() - t0
     n_splats = int(counts[np.arange(scene.crowd.n), levels].sum())
     rng = np.random.default_rng(7)
@@ -221,7 +233,7 @@ def cpu_baseline(scene, host_net, margin, per_worker=21):
     frame_s = t_lod + wall * n_splats / max(g, 1)
     return {"value": round(1.0 / frame_s, 8), "unit": "FPS", "cores": cores, "kind": "oracle",
             "cpu_model": _cpu_model(),
-            "sample": (f"FP64 oracle, frame 0 of the learned-LoD (frame budget) crowd: LoD selection of all "
+            "sample": (f"FP64 oracle, frame 0 of {what}: LoD selection of all "
                        f"{scene.crowd.n} instances ({t_lod:.1f} s, one core), then {len(pick)} seeded instances "
                        f"({g} instance-Gaussians, {p} tile pairs) split over a pool of {cores} processes: "
                        f"{wall:.1f} s wall ({t_rec:.1f} CPU-s skin+project, {t_ras:.1f} CPU-s bin+sort+blend); "
@@ -719,13 +731,19 @@ def main():
     if netinfo is None or rules is None:
         raise SystemExit("the trained network and the frame-tuned rules are needed (train_lod.py)")
     # the oracle baseline first: its process pool forks, before anything touches the GPU
-    cpu = None
+    cpu = cpu_c2 = None
     if not args.no_cpu_baseline:
         from paper_2501_17792_amd import lodnet
 
         t0 = time.perf_counter()
         cpu = cpu_baseline(scene, lodnet.unpack(netinfo["net"]), rules["budget_margin"])
         log(f"cpu baseline in {time.perf_counter() - t0:.1f} s: {cpu['value']:.3g} FPS on {cpu['cores']} cores")
+        if not args.no_c2:  # the oracle on C2's frame 0 too (500 avatars, fixed 10 / 25 m)
+            sc2c = synth.scene_c2(templates=templates)
+            t0 = time.perf_counter()
+            cpu_c2 = cpu_baseline(sc2c, None, 0.0, levels_fn=lambda: oracle_fixed_levels(sc2c, (10.0, 10.0, 25.0, 25.0)),
+                                  what="the 500-avatar crowd, fixed 10 / 25 m")
+            log(f"cpu baseline (C2) in {time.perf_counter() - t0:.1f} s: {cpu_c2['value']:.3g} FPS")
 
     import torch
 
@@ -934,7 +952,7 @@ def main():
         "stage_gbs": {k: round(v, 1) for k, v in stage_gbs.items()},
         "copy_gbs": round(copy_gbs, 1), "copy_ok": copy_ok, "stage_frac_of_copy": stage_copy_frac,
         "blend": blend, "fit": fit_res, "pose_offsets": offsets,
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "cpu_baseline_c2": cpu_c2,
     }
     print(json.dumps(out), flush=True)
 
