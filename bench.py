@@ -61,7 +61,7 @@ BLEND_FLOPS_PER_EVAL = 24
 # lane-instructions per item (SQ_INSTS_VALU x 64 / items: splats for the projection, pairs for the sort and
 # the blend), summarised under profiles/crowd3500_1080p_budget_<tile>_kernels.md. Other sources, tiles or
 # workloads report null.
-MEASURED = {"digest": "3f0c6749c28b7204", "lod": "learned_budget",
+MEASURED = {"digest": "6abbdb4434f5cd89", "lod": "learned_budget",
             "tiles": {(16, 32): {"traffic": {"blend": 1_768_265_772, "project_fused": 3_172_704_326,
                                              "segsort": 1_103_544_994},
                                  "valu_per_item": {"blend": 378.8, "project_fused": 423.3, "segsort": 120.2}},
@@ -603,7 +603,7 @@ OFFSET_FLOPS_PER_INSTANCE = 2 * 80 * 64
 BF16_PEAK_TFLOPS = 2500.0  # dense bf16 matrix-core peak of one MI355X
 
 
-def offsets_leg(torch, scene, poses_all, lod, tile, pose_net, timed, frames=3):
+def offsets_leg(torch, scene, poses_all, lod, tile, pose_net, timed, frames=3, blocks=(0, 0)):
     """The headline frame with pose-dependent offsets: frame rate as timed
     (``timed``: captured frames in flight), then the offsets stage of eager
     instrumented frames (HIP events) against the matrix cores' bf16 peak on
@@ -615,7 +615,7 @@ def offsets_leg(torch, scene, poses_all, lod, tile, pose_net, timed, frames=3):
     mode, thr, mlp_ptr, margin = lod
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        r = cs.Renderer(0, stream=stream, fuse=True, profile=True, tile=tile)
+        r = cs.Renderer(0, stream=stream, fuse=True, profile=True, tile=tile, blocks=blocks)
         r.upload_templates(scene.templates)
         r.set_crowd(scene.crowd)
         r.upload_pose_net(*pose_net)
@@ -772,6 +772,7 @@ def main():
         keep = set(args.modes.split(",")) | {head}
         modes = {k: v for k, v in modes.items() if k in keep}
     tile_timing = None
+    blocks = (0, 0)  # (bin_blocks, sort_blocks): library defaults unless the autotuner picked others
     inflight = args.inflight
     if args.tile == "auto":
         from paper_2501_17792_amd import autotune
@@ -782,6 +783,7 @@ def main():
         tile, tuned_inflight, tile_timing = autotune.tune_frame(torch, scene, poses_all, stream, modes[head],
                                                                 rule=head, cache_path=cache, log=log)
         inflight = inflight or tuned_inflight
+        blocks = tuple(int(b) for b in tile_timing.get("blocks", (0, 0)))
     else:
         tile = tuple(int(x) for x in args.tile.split("x"))
     inflight = inflight or 3
@@ -790,7 +792,7 @@ def main():
     from paper_2501_17792_amd import autotune
 
     def trial(sts):
-        return autotune.frames_on(torch, scene, poses_all, modes[head], tile, sts, 80, 10)
+        return autotune.frames_on(torch, scene, poses_all, modes[head], tile, sts, 80, 10, blocks)
 
     streams, stream_sets = autotune.pick_streams(torch, dev, inflight, trial, log=log)
 
@@ -799,7 +801,7 @@ def main():
             imgs = [torch.zeros((3, sc.camera.height, sc.camera.width), device=dev) for _ in range(n)]
             rs = []
             for st in streams[:n]:
-                r = cs.Renderer(0, stream=st, fuse=True, tile=tile)
+                r = cs.Renderer(0, stream=st, fuse=True, tile=tile, blocks=blocks)
                 r.upload_templates(sc.templates)
                 r.set_crowd(sc.crowd)
                 if pose_net is not None:
@@ -835,7 +837,7 @@ def main():
     if not args.no_offsets:
         pn = (synth.pose_net_weights(), [synth.pose_embeddings(1200 + t, tpl.n) for t, tpl in enumerate(scene.templates)])
         ro = run(modes[head], len(streams), pose_net=pn)
-        offsets = offsets_leg(torch, scene, poses_all, modes[head], tile, pn, ro)
+        offsets = offsets_leg(torch, scene, poses_all, modes[head], tile, pn, ro, blocks=blocks)
         log(f"{head} with pose-dependent offsets: {offsets['fps']:.1f} FPS, offsets stage {offsets['offsets_ms']:.3f} ms")
 
     res = results[head]
@@ -851,7 +853,7 @@ def main():
     def stage_profile(fuse, count=False):
         with torch.cuda.stream(stream):
             img = torch.zeros((3, scene.camera.height, scene.camera.width), device=dev)
-            rp = cs.Renderer(0, stream=stream, fuse=fuse, profile=True, tile=tile, count_blend=count)
+            rp = cs.Renderer(0, stream=stream, fuse=fuse, profile=True, tile=tile, count_blend=count, blocks=blocks)
             rp.upload_templates(scene.templates)
             rp.set_crowd(scene.crowd)
             lvl_out = torch.zeros(scene.crowd.n, dtype=torch.int32, device=dev)
@@ -933,7 +935,7 @@ def main():
                                "with a frame budget of 40 dB PSNR against full detail, hipGraph-captured frame "
                                "(pose upload inside), frames in flight on separate contexts",
                    "lod": head, "instances": scene.crowd.n, "width": scene.camera.width,
-                   "height": scene.camera.height, "tile": list(tile)},
+                   "height": scene.camera.height, "tile": list(tile), "blocks": list(blocks)},
         "autotune": tile_timing,
         "frames_in_flight": len(streams), "frame_stream_sets_tried": stream_sets,
         "frame_ms_median": round(float(np.median(res["per"])), 4),

@@ -84,7 +84,12 @@ typedef struct cs_options {
   int32_t count_blend;       /* 1 (with profile_stages): count the compositing
                                 evaluations (cs_frame_stats.blend_evals; a
                                 slower instrumented blend)                      */
-  int32_t reserved[5];
+  int32_t bin_blocks;        /* workgroups of the tile-bucket binning kernels
+                                (count, scatter): 0 = 512, else 64..1024; the
+                                result does not depend on it                    */
+  int32_t sort_blocks;       /* workgroups of the key splits and the LDS segment
+                                sort: 0 = 512, else 64..4096 (same result)      */
+  int32_t reserved[3];
 } cs_options;
 
 /* How the tile-bucket form's LDS segment sort ranks radix digits inside a

@@ -9,7 +9,8 @@ then times the best few shapes with 1 to 4 frames in flight (contexts on
 their own streams that consecutive frames alternate between, each replaying
 its captured frame) and keeps the (tile, frames in flight) pair with the
 highest frame rate, timed by the same procedure the benchmark reports
-(``time_frames``). Results are cached in a JSON file keyed by the device,
+(``time_frames``), and then the workgroup counts of the binning and sorting
+kernels at that pair. Results are cached in a JSON file keyed by the device,
 the image size, the instance count bucket, the LoD rule and a digest of the
 kernel sources, so a changed kernel is tuned again.
 """
@@ -23,6 +24,8 @@ import numpy as np
 from . import crowdsplat as cs
 
 CANDIDATES = [(16, 16), (8, 8), (16, 8), (8, 16), (32, 8), (32, 16), (16, 32)]
+# (bin_blocks, sort_blocks) tried at the chosen tile shape and frames in flight
+BLOCK_CANDIDATES = [(256, 512), (1024, 512), (512, 256), (512, 1024)]
 
 
 def sources_digest():
@@ -260,9 +263,10 @@ def time_frames(torch, rs, scene, poses_all, imgs, streams, lod, steps, warmup, 
     return dict(ms=total / steps, per=per, stats=st0, frame0=frame0, overflow=overflow)
 
 
-def frames_on(torch, scene, poses_all, lod, tile, streams, frames, warmup=30):
+def frames_on(torch, scene, poses_all, lod, tile, streams, frames, warmup=30, blocks=(0, 0)):
     """``time_frames`` of captured frames alternating over fresh contexts on
-    ``streams`` (one each)."""
+    ``streams`` (one each); ``blocks``: the contexts' (bin_blocks,
+    sort_blocks)."""
     dev = poses_all.device
     n = len(streams)
     rs = []
@@ -270,7 +274,7 @@ def frames_on(torch, scene, poses_all, lod, tile, streams, frames, warmup=30):
         with torch.cuda.stream(streams[0]):
             imgs = [torch.zeros((3, scene.camera.height, scene.camera.width), device=dev) for _ in range(n)]
             for st in streams:
-                r = cs.Renderer(0, stream=st, fuse=True, tile=tile)
+                r = cs.Renderer(0, stream=st, fuse=True, tile=tile, blocks=blocks)
                 rs.append(r)
                 r.upload_templates(scene.templates)
                 r.set_crowd(scene.crowd)
@@ -283,14 +287,14 @@ def frames_on(torch, scene, poses_all, lod, tile, streams, frames, warmup=30):
         torch.cuda.empty_cache()
 
 
-def _frame_rate(torch, scene, poses_all, lod, tile, n, frames, warmup=30):
+def _frame_rate(torch, scene, poses_all, lod, tile, n, frames, warmup=30, blocks=(0, 0)):
     """Frames per second of captured frames alternating over ``n`` fresh
     contexts (one stream each, a set whose frames advance evenly), timed by
     ``time_frames``; None on overflow."""
     dev = poses_all.device
     out = None
     for _ in range(4):
-        out = frames_on(torch, scene, poses_all, lod, tile, distinct_streams(torch, dev, n), frames, warmup)
+        out = frames_on(torch, scene, poses_all, lod, tile, distinct_streams(torch, dev, n), frames, warmup, blocks)
         if out["overflow"] or balanced(out, n):
             break
     return None if out["overflow"] else 1000.0 / out["ms"]
@@ -336,7 +340,23 @@ def tune_frame(torch, scene, poses_all, stream, lod, rule="", inflights=(1, 2, 3
     best = max((v, k) for k, v in judged.items())[1]
     name, n = best.split("/")
     tile = tuple(int(x) for x in name.split("x"))
-    rec = {"tile": list(tile), "inflight": int(n), "single_frame_ms": single, "fps": fps, "fps_again": again}
+    # then the workgroup counts of the binning kernels and of the key splits /
+    # LDS segment sort at that shape; another count than the default (512,
+    # 512) is kept only if it is faster in two measurements by more than 1%
+    base = judged[best]
+    blocks_fps = {}
+    chosen, chosen_v = (0, 0), base
+    for b in BLOCK_CANDIDATES:
+        v = _frame_rate(torch, scene, poses_all, lod, tile, int(n), frames, blocks=b)
+        if v is not None and v > 1.01 * base:
+            v = min(v, _frame_rate(torch, scene, poses_all, lod, tile, int(n), frames, blocks=b) or 0.0)
+        blocks_fps[f"{b[0]}/{b[1]}"] = round(v, 2) if v is not None else None
+        if log:
+            log(f"tile {name}, {n} in flight, blocks {b}: {v} FPS")
+        if v is not None and v > 1.01 * base and v > chosen_v:
+            chosen, chosen_v = b, v
+    rec = {"tile": list(tile), "inflight": int(n), "blocks": list(chosen), "single_frame_ms": single, "fps": fps,
+           "fps_again": again, "blocks_fps": blocks_fps}
     if cache_path:
         cache[key] = rec
         with open(cache_path, "w") as f:

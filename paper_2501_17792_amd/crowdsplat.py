@@ -53,7 +53,8 @@ class CsOptions(ctypes.Structure):
                 ("fuse_skin_project", ctypes.c_int32), ("profile_stages", ctypes.c_int32),
                 ("max_splats", ctypes.c_int64), ("max_pairs", ctypes.c_int64),
                 ("sort_algo", ctypes.c_int32), ("sort_ranks", ctypes.c_int32),
-                ("count_blend", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("count_blend", ctypes.c_int32), ("bin_blocks", ctypes.c_int32), ("sort_blocks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class CsTemplateDesc(ctypes.Structure):
@@ -227,7 +228,8 @@ class Renderer:
     def __init__(self, device: int = 0, stream=None, tile=(16, 16), skin_mode=CS_SKIN_FULL,
                  launch_mode=CS_LAUNCH_BATCHED, fuse=False, max_splats=0, max_pairs=0,
                  profile=False, sort_algo=CS_SORT_TILE_BUCKET, sort_ranks=CS_SORT_RANKS_CHECKED,
-                 count_blend=False):
+                 count_blend=False, blocks=(0, 0)):
+        """``blocks``: (bin_blocks, sort_blocks) of cs_options (0: defaults)."""
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -240,6 +242,7 @@ class Renderer:
         opt.sort_algo = sort_algo
         opt.sort_ranks = sort_ranks
         opt.count_blend = int(count_blend)
+        opt.bin_blocks, opt.sort_blocks = (int(b) for b in blocks)
         opt.max_splats, opt.max_pairs = max_splats, max_pairs
         self.tile = tuple(tile)
         ctx = ctypes.c_void_p()

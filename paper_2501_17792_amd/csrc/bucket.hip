@@ -774,7 +774,7 @@ __global__ void bucket_keys_kernel(const uint32_t* __restrict__ ranges, const ui
 
 // ---------------------------------------------------------------------------
 hipError_t launch_bucket_count(const uint2* rd, CamDev cam, const FrameHdr* hdr, uint32_t* region, uint32_t* counts,
-                               hipStream_t st) {
+                               int blocks, hipStream_t st) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
   if (n_tiles > kBucketMaxTiles) return hipErrorInvalidValue;
   static bool lds_set[64] = {};
@@ -785,23 +785,25 @@ hipError_t launch_bucket_count(const uint2* rd, CamDev cam, const FrameHdr* hdr,
     if (e != hipSuccess) return e;
     lds_set[dev] = true;
   }
-  bucket_count_kernel<<<kBucketBlocks, kBkThreads, 12 * n_tiles, st>>>(
+  if (blocks < 1 || blocks > kBucketMaxBlocks) return hipErrorInvalidValue;
+  bucket_count_kernel<<<blocks, kBkThreads, 12 * n_tiles, st>>>(
       rd, cam.tiles_x, n_tiles, hdr, counts, region + kBucketMinC, region + kBucketMax);
   return hipGetLastError();
 }
 
 hipError_t launch_bucket_ranges(const uint32_t* base, int n_tiles, const FrameHdr* hdr, uint32_t max_pairs,
-                                uint32_t* ranges, hipStream_t st) {
+                                uint32_t* ranges, int blocks, hipStream_t st) {
   if (n_tiles > 0)
-    bucket_ranges_kernel<<<(n_tiles + 255) / 256, 256, 0, st>>>(base, n_tiles, kBucketBlocks, hdr, max_pairs, ranges);
+    bucket_ranges_kernel<<<(n_tiles + 255) / 256, 256, 0, st>>>(base, n_tiles, blocks, hdr, max_pairs, ranges);
   return hipGetLastError();
 }
 
 hipError_t launch_bucket_scatter(const uint2* rd, CamDev cam, const FrameHdr* hdr, uint32_t max_pairs,
-                                 const uint32_t* base, uint64_t* items, hipStream_t st) {
+                                 const uint32_t* base, uint64_t* items, int blocks, hipStream_t st) {
   const int n_tiles = cam.tiles_x * cam.tiles_y;
-  bucket_scatter_kernel<<<kBucketBlocks, kBkThreads, 4 * n_tiles, st>>>(rd, cam.tiles_x, n_tiles, hdr, max_pairs,
-                                                                       base, items);
+  if (blocks < 1 || blocks > kBucketMaxBlocks) return hipErrorInvalidValue;
+  bucket_scatter_kernel<<<blocks, kBkThreads, 4 * n_tiles, st>>>(rd, cam.tiles_x, n_tiles, hdr, max_pairs, base,
+                                                                items);
   return hipGetLastError();
 }
 

@@ -351,13 +351,17 @@ struct SplitWork {
 inline int64_t split_segs_cap(int64_t pairs) { return pairs / kSegCap + 64; }
 inline int64_t split_items_cap(int64_t pairs) { return pairs / kWideChunk + pairs / kSegCap + 64; }
 
-constexpr int kBucketBlocks = 512;  // workgroups of the count and scatter kernels (columns of the count matrix)
+// workgroups of the count and scatter kernels (columns of the count matrix):
+// the default and the most a context may ask for (cs_options.bin_blocks)
+constexpr int kBucketBlocks = 512;
+constexpr int kBucketMaxBlocks = 1024;
+constexpr int kSegGrid = 512;  // workgroups of the key splits and the LDS segment sort (cs_options.sort_blocks)
 hipError_t launch_bucket_count(const uint2* rd, CamDev cam, const FrameHdr* hdr, uint32_t* region, uint32_t* counts,
-                               hipStream_t st);
+                               int blocks, hipStream_t st);
 hipError_t launch_bucket_ranges(const uint32_t* base, int n_tiles, const FrameHdr* hdr, uint32_t max_pairs,
-                                uint32_t* ranges, hipStream_t st);
+                                uint32_t* ranges, int blocks, hipStream_t st);
 hipError_t launch_bucket_scatter(const uint2* rd, CamDev cam, const FrameHdr* hdr, uint32_t max_pairs,
-                                 const uint32_t* base, uint64_t* items, hipStream_t st);
+                                 const uint32_t* base, uint64_t* items, int blocks, hipStream_t st);
 hipError_t launch_scan_total(uint32_t* data, uint32_t n, uint32_t* block_sums, uint32_t* total_out, FrameHdr* hdr,
                              uint32_t max_total, hipStream_t st);
 // key splits of the tiles longer than one workgroup's LDS capacity, then the

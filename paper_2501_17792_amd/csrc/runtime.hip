@@ -117,7 +117,8 @@ struct cs_ctx {
   int64_t cap_tiles = 0;
   uint32_t* ranges = nullptr;
   uint32_t* tile_order = nullptr;    // [kMaxFrameTiles] blend launch order
-  uint32_t* bk_counts = nullptr;     // [kBucketMaxTiles][kBucketBlocks] pair counts, then first slots
+  int bin_blocks = kBucketBlocks;    // workgroups of the binning kernels (cs_options.bin_blocks)
+  uint32_t* bk_counts = nullptr;     // [kBucketMaxTiles][bin_blocks] pair counts, then first slots
   uint32_t* bk_sums = nullptr;       // block sums of their scan
   SegEntry* seg_base = nullptr;      // key segments sorted in LDS
   SegEntry* seg_big[2] = {nullptr, nullptr};  // key segments to split
@@ -461,6 +462,10 @@ cs_status cs_create(int32_t device, void* stream, const cs_options* opt, cs_ctx*
   if (o.sort_algo != CS_SORT_TILE_BUCKET && o.sort_algo != CS_SORT_REDUCE_SCAN && o.sort_algo != CS_SORT_ONESWEEP)
     return CS_ERR_INVALID;
   if (o.sort_ranks != CS_SORT_RANKS_CHECKED && o.sort_ranks != CS_SORT_RANKS_BALLOT) return CS_ERR_INVALID;
+  if (o.bin_blocks == 0) o.bin_blocks = kBucketBlocks;
+  if (o.sort_blocks == 0) o.sort_blocks = kSegGrid;
+  if (o.bin_blocks < 64 || o.bin_blocks > kBucketMaxBlocks || o.sort_blocks < 64 || o.sort_blocks > 4096)
+    return CS_ERR_INVALID;
   int n_dev = 0;
   if (hipGetDeviceCount(&n_dev) != hipSuccess || device < 0 || device >= n_dev) {
     (void)hipGetLastError();
@@ -471,12 +476,13 @@ cs_status cs_create(int32_t device, void* stream, const cs_options* opt, cs_ctx*
   ctx->device = device;
   ctx->stream = (hipStream_t)stream;
   ctx->opt = o;
+  ctx->bin_blocks = o.bin_blocks;
   cs_status s = noalloc_scratch_init(ctx);
   if (s == CS_OK) s = dalloc(ctx, &ctx->hdr, 1);
   if (s == CS_OK) s = dalloc(ctx, &ctx->hist, kHistLen);
   if (s == CS_OK) s = dalloc(ctx, &ctx->tile_order, kMaxFrameTiles);
-  if (s == CS_OK) s = dalloc(ctx, &ctx->bk_counts, (size_t)kBucketMaxTiles * kBucketBlocks);
-  if (s == CS_OK) s = dalloc(ctx, &ctx->bk_sums, (size_t)kBucketMaxTiles * kBucketBlocks / scan_tile() + 2);
+  if (s == CS_OK) s = dalloc(ctx, &ctx->bk_counts, (size_t)kBucketMaxTiles * ctx->bin_blocks);
+  if (s == CS_OK) s = dalloc(ctx, &ctx->bk_sums, (size_t)kBucketMaxTiles * ctx->bin_blocks / scan_tile() + 2);
   if (s == CS_OK) s = dalloc(ctx, &ctx->n_dev, 1);
   if (s == CS_OK) s = dalloc(ctx, &ctx->rts_counts, (size_t)kRtsBlocks * kSortBins);
   if (s == CS_OK) s = dalloc(ctx, &ctx->rts_sums, (size_t)kRtsBlocks * kSortBins / 4096 + 2);
@@ -837,7 +843,6 @@ cs_status cs_skin_instances(cs_ctx* ctx, int32_t n_inst, const cs_instance* inst
   return CS_OK;
 }
 
-constexpr int kSegGrid = 512;     // workgroups of the split and LDS sort kernels
 
 static cs_status lsd_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles, const ViewDev* vp);
 
@@ -848,10 +853,10 @@ static cs_status bucket_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles) {
   uint32_t cap_p = (uint32_t)std::min<int64_t>(ctx->cap_pairs, kMaxPairsLimit);
   const uint32_t max_p = ctx->capturing ? cap_p : kMaxPairsLimit;
   ctx->mark(CS_STAGE_EMIT, 0);
-  HIP_TRY(launch_bucket_count(ctx->rd, cd, ctx->hdr, region, ctx->bk_counts, ctx->stream));
-  HIP_TRY(launch_scan_total(ctx->bk_counts, (uint32_t)n_tiles * kBucketBlocks, ctx->bk_sums, &ctx->hdr->n_pairs,
-                            ctx->hdr, max_p, ctx->stream));
-  HIP_TRY(launch_bucket_ranges(ctx->bk_counts, n_tiles, ctx->hdr, max_p, ctx->ranges, ctx->stream));
+  HIP_TRY(launch_bucket_count(ctx->rd, cd, ctx->hdr, region, ctx->bk_counts, ctx->bin_blocks, ctx->stream));
+  HIP_TRY(launch_scan_total(ctx->bk_counts, (uint32_t)n_tiles * (uint32_t)ctx->bin_blocks, ctx->bk_sums,
+                            &ctx->hdr->n_pairs, ctx->hdr, max_p, ctx->stream));
+  HIP_TRY(launch_bucket_ranges(ctx->bk_counts, n_tiles, ctx->hdr, max_p, ctx->ranges, ctx->bin_blocks, ctx->stream));
   if (!ctx->capturing) {
     CS_TRY(read_header(ctx));
     const int64_t n_pairs = ctx->hdr_host->n_pairs;
@@ -861,7 +866,8 @@ static cs_status bucket_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles) {
     }
     cap_p = (uint32_t)std::min<int64_t>(ctx->cap_pairs, kMaxPairsLimit);
   }
-  HIP_TRY(launch_bucket_scatter(ctx->rd, cd, ctx->hdr, cap_p, ctx->bk_counts, ctx->keys[0], ctx->stream));
+  HIP_TRY(launch_bucket_scatter(ctx->rd, cd, ctx->hdr, cap_p, ctx->bk_counts, ctx->keys[0], ctx->bin_blocks,
+                                ctx->stream));
   ctx->mark(CS_STAGE_EMIT, 1);
   ctx->mark(CS_STAGE_SORT, 0);
   SegLists lists{};
@@ -875,10 +881,11 @@ static cs_status bucket_bin_sort(cs_ctx* ctx, const CamDev& cd, int n_tiles) {
                (uint32_t)std::min<int64_t>(ctx->cap_split_segs, 0xffffffffll),
                (uint32_t)std::min<int64_t>(ctx->cap_split_items, 0xffffffffll)};
   HIP_TRY(launch_seg_split(ctx->ranges, region, n_tiles, ctx->hdr, cap_p, ctx->keys[0], ctx->keys[1], lists, wk,
-                           kSegGrid, ctx->stream));
+                           ctx->opt.sort_blocks, ctx->stream));
   ctx->mark(CS_STAGE_SEGSORT, 0);
   HIP_TRY(launch_seg_sort(ctx->ranges, region, n_tiles, ctx->hdr, cap_p, ctx->keys[0], ctx->keys[1], lists,
-                          ctx->vals[0], kSegGrid, ctx->opt.sort_ranks == CS_SORT_RANKS_BALLOT, ctx->stream));
+                          ctx->vals[0], ctx->opt.sort_blocks, ctx->opt.sort_ranks == CS_SORT_RANKS_BALLOT,
+                          ctx->stream));
   ctx->mark(CS_STAGE_SEGSORT, 1);
   ctx->mark(CS_STAGE_SORT, 1);
   ctx->sorted = 0;

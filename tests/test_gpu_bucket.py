@@ -19,13 +19,13 @@ from .gpu_common import check_sorted_pairs, gpu_frame_buffers
 pytestmark = pytest.mark.gpu
 
 
-def _render(scene, algo, tile=(16, 16), mode=None, thresholds=(), ranks=0):
+def _render(scene, algo, tile=(16, 16), mode=None, thresholds=(), ranks=0, blocks=(0, 0)):
     import torch
 
     from paper_2501_17792_amd import crowdsplat as cs
 
     mode = cs.CS_LOD_FULL if mode is None else mode
-    r = cs.Renderer(0, tile=tile, sort_algo=algo, sort_ranks=ranks)
+    r = cs.Renderer(0, tile=tile, sort_algo=algo, sort_ranks=ranks, blocks=blocks)
     r.upload_templates(scene.templates)
     r.set_crowd(scene.crowd)
     img = r.frame(scene.camera, mode, thresholds, stats=True)
@@ -89,6 +89,15 @@ def test_long_segments_multi_level_split():
     seg = (rg[:, 1] - rg[:, 0]).astype(np.int64)
     assert seg.max() > 4 * 16384  # far beyond one workgroup's LDS capacity: the split path ran
     print("max tile segment", seg.max(), "pairs", seg.sum())
+    # the workgroup counts the autotuner may pick leave every list and pixel unchanged
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    _, img0, rg0, sv0 = _render(sc, cs.CS_SORT_TILE_BUCKET)
+    for blocks in [(64, 64), (256, 1024), (1024, 4096), (777, 333)]:
+        _, img1, rg1, sv1 = _render(sc, cs.CS_SORT_TILE_BUCKET, blocks=blocks)
+        assert np.array_equal(rg1, rg0) and np.array_equal(sv1, sv0) and np.array_equal(img1, img0), blocks
+    with pytest.raises(cs.CrowdSplatError):
+        cs.Renderer(0, blocks=(2048, 0))
 
 
 def test_equal_depth_runs():
