@@ -186,10 +186,11 @@ typedef struct cs_lod_params {
  * clears the counts. The counts describe a frame already drawn, so the rule
  * assumes frames that change little from one to the next (an animation seen
  * from a steady camera) and that instance i stays the same avatar. Counts
- * serve the one selection that follows them; share 1 (plain BUDGET) applies
+ * serve the next selection on this context; share 1 (plain BUDGET) applies
  * while there are none: on the first frame, when the counted frame drew
- * another number of instances, and when another selection or a render that
- * did not count (a view render, an instrumented blend) came in between.
+ * another number of instances, when a selection of another mode came in
+ * between, and when the first render after the last BUDGET_VISIBLE selection
+ * did not count (a view render, an instrumented blend).
  * A captured frame carries this across its replays (the tag lives on the
  * device), so each replay reads the counts of the one before it. */
 
