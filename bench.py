@@ -61,7 +61,7 @@ BLEND_FLOPS_PER_EVAL = 24
 # lane-instructions per item (SQ_INSTS_VALU x 64 / items: splats for the projection, pairs for the sort and
 # the blend), summarised under profiles/crowd3500_1080p_budget_<tile>_kernels.md. Other sources, tiles or
 # workloads report null.
-MEASURED = {"digest": "6abbdb4434f5cd89", "lod": "learned_budget",
+MEASURED = {"digest": "062f9cd5a7f1e696", "lod": "learned_budget",
             "tiles": {(16, 32): {"traffic": {"blend": 1_768_265_772, "project_fused": 3_172_704_326,
                                              "segsort": 1_103_544_994},
                                  "valu_per_item": {"blend": 378.8, "project_fused": 423.3, "segsort": 120.2}},

@@ -131,48 +131,48 @@ __global__ __launch_bounds__(TW* TH) void blend_backward_kernel(
     const int cnt = (int)min((uint32_t)N, end - b);
     // process in groups of 64 pairs so the per-wave partials fit in LDS
     for (int g0 = ((cnt + 63) / 64 - 1) * 64; g0 >= 0; g0 -= 64) {
-      for (int jj = min(63, cnt - 1 - g0); jj >= 0; --jj) {
-        const int j = g0 + jj;
-        const int k = (int)(b - start) + j;
-        float gv[kGP];
+      // One pair: its terms for this lane's pixel, walking T and S back over
+      // it (returns whether the pixel took it).
+      auto pair_terms = [&](int j, float gv[kGP]) -> bool {
 #pragma unroll
         for (int e = 0; e < kGP; ++e) gv[e] = 0.f;
-        bool contrib = false;
+        const int k = (int)(b - start) + j;
         const float4 r0 = s_r0[j];
         const bool near = !(r0.x + r0.z < wx0 || r0.x - r0.z > wx1 || r0.y + r0.w < wy0 || r0.y - r0.w > wy1);
-        if (near && k <= last) {
-          const float4 r1 = s_r1[j], r2 = s_r2[j];
-          const float dx = pcx - r0.x, dy = pcy - r0.y;
-          const float praw = -0.5f * fmaf(r1.x * dx, dx, r1.z * dy * dy) - r1.y * dx * dy;
-          const float power = fminf(praw, 0.f);
-          const float e = __expf(power);
-          const float raw = r1.w * e;
-          const float alpha = fminf(0.99f, raw);
-          if (alpha >= (1.f / 255.f)) {
-            contrib = true;
-            T = T / (1.f - alpha);  // transmittance in front of this pair
-            const float w = alpha * T;
-            gv[6] = dpr * w;
-            gv[7] = dpg * w;
-            gv[8] = dpb * w;
-            const float ia = 1.f / (1.f - alpha);
-            const float dLda = dpr * (r2.x * T - Sr * ia) + dpg * (r2.y * T - Sg * ia) + dpb * (r2.z * T - Sb * ia);
-            Sr = fmaf(r2.x, w, Sr);
-            Sg = fmaf(r2.y, w, Sg);
-            Sb = fmaf(r2.z, w, Sb);
-            if (raw <= 0.99f) {
-              gv[5] = dLda * e;
-              if (praw <= 0.f) {
-                const float dLdp = dLda * alpha;
-                gv[0] = dLdp * fmaf(r1.x, dx, r1.y * dy);
-                gv[1] = dLdp * fmaf(r1.y, dx, r1.z * dy);
-                gv[2] = -0.5f * dLdp * dx * dx;
-                gv[3] = -dLdp * dx * dy;
-                gv[4] = -0.5f * dLdp * dy * dy;
-              }
-            }
+        if (!(near && k <= last)) return false;
+        const float4 r1 = s_r1[j], r2 = s_r2[j];
+        const float dx = pcx - r0.x, dy = pcy - r0.y;
+        const float praw = -0.5f * fmaf(r1.x * dx, dx, r1.z * dy * dy) - r1.y * dx * dy;
+        const float power = fminf(praw, 0.f);
+        const float e = __expf(power);
+        const float raw = r1.w * e;
+        const float alpha = fminf(0.99f, raw);
+        if (!(alpha >= (1.f / 255.f))) return false;
+        T = T / (1.f - alpha);  // transmittance in front of this pair
+        const float w = alpha * T;
+        gv[6] = dpr * w;
+        gv[7] = dpg * w;
+        gv[8] = dpb * w;
+        const float ia = 1.f / (1.f - alpha);
+        const float dLda = dpr * (r2.x * T - Sr * ia) + dpg * (r2.y * T - Sg * ia) + dpb * (r2.z * T - Sb * ia);
+        Sr = fmaf(r2.x, w, Sr);
+        Sg = fmaf(r2.y, w, Sg);
+        Sb = fmaf(r2.z, w, Sb);
+        if (raw <= 0.99f) {
+          gv[5] = dLda * e;
+          if (praw <= 0.f) {
+            const float dLdp = dLda * alpha;
+            gv[0] = dLdp * fmaf(r1.x, dx, r1.y * dy);
+            gv[1] = dLdp * fmaf(r1.y, dx, r1.z * dy);
+            gv[2] = -0.5f * dLdp * dx * dx;
+            gv[3] = -dLdp * dx * dy;
+            gv[4] = -0.5f * dLdp * dy * dy;
           }
         }
+        return true;
+      };
+      // The pair's nine sums over the wave, written to this wave's partials.
+      auto reduce_store = [&](int jj, bool contrib, float gv[kGP]) {
         const uint64_t cm = __ballot(contrib);
         if (cm != 0ull) {
           if (__popcll(cm) <= 6) {
@@ -197,6 +197,21 @@ __global__ __launch_bounds__(TW* TH) void blend_backward_kernel(
 #pragma unroll
           for (int e = 0; e < kGP; ++e) s_part[wave][e][jj] = gv[e];
         }
+      };
+      // two pairs per step: both walked back (in order), then both reduced,
+      // so the second pair's evaluation overlaps the first one's reduction
+      int jj = min(63, cnt - 1 - g0);
+      for (; jj >= 1; jj -= 2) {
+        float ga[kGP], gb[kGP];
+        const bool ca = pair_terms(g0 + jj, ga);
+        const bool cb = pair_terms(g0 + jj - 1, gb);
+        reduce_store(jj, ca, ga);
+        reduce_store(jj - 1, cb, gb);
+      }
+      if (jj == 0) {
+        float ga[kGP];
+        const bool ca = pair_terms(g0, ga);
+        reduce_store(0, ca, ga);
       }
       __syncthreads();
       // combine the waves in order and store at the pairs' emission slots
