@@ -56,18 +56,15 @@ FP32_PEAK_TFLOPS = 2 * ISSUE_PEAK / 1e12
 BLEND_FLOPS_PER_EVAL = 24
 
 # Counter measurements of the headline frame (learned LoD, frame budget) for the kernel sources they were
-# taken on (digest), per tile shape the autotuner may pick: HBM bytes per launch from two rocprofv3 --pmc
+# taken on (digest), per tile shape and blend split the autotuner may pick: HBM bytes per launch from two rocprofv3 --pmc
 # runs (FETCH_SIZE scaled by 2.000 and WRITE_SIZE by 1.000, the factors a plain 1 GiB copy gives) and VALU
 # lane-instructions per item (SQ_INSTS_VALU x 64 / items: splats for the projection, pairs for the sort and
-# the blend), summarised under profiles/crowd3500_1080p_budget_<tile>_kernels.md. Other sources, tiles or
+# the blend), summarised under profiles/crowd3500_1080p_budget_<shape>_kernels.md. Other sources, shapes or
 # workloads report null.
-MEASURED = {"digest": "062f9cd5a7f1e696", "lod": "learned_budget",
-            "tiles": {(16, 32): {"traffic": {"blend": 1_768_265_772, "project_fused": 3_172_704_326,
-                                             "segsort": 1_103_544_994},
-                                 "valu_per_item": {"blend": 378.8, "project_fused": 423.3, "segsort": 120.2}},
-                      (32, 16): {"traffic": {"blend": 1_769_286_428, "project_fused": 3_174_393_390,
-                                             "segsort": 1_071_544_782},
-                                 "valu_per_item": {"blend": 533.0, "project_fused": 423.3, "segsort": 120.1}}}}
+MEASURED = {"digest": "2b7e087ca81ec9e6", "lod": "learned_budget",
+            "tiles": {(32, 32, 4): {"traffic": {"blend": 3_305_432_157, "project_fused": 3_167_578_724,
+                                                "segsort": 917_472_016},
+                                    "valu_per_item": {"blend": 599.5, "project_fused": 422.7, "segsort": 119.9}}}}
 
 
 def kernel_digest():
@@ -382,7 +379,7 @@ def dominant_roofline(stage_ms, st, scene, uniq):
             "frac": round(a / HBM_PEAK_GBS, 4), "launch_ms": round(stage_ms[dom], 4), "bytes_per_launch": int(b)}
 
 
-def frame_roofline(stage_ms, stats, scene, uniq, tile, blend):
+def frame_roofline(stage_ms, stats, scene, uniq, tile, split, blend):
     """Roofline object of the dominant single-launch kernel of the timed
     frame (fused projection, LDS segment sort or compositing), timed with HIP
     events on its launch stream in the instrumented frames. Projection and
@@ -395,7 +392,7 @@ def frame_roofline(stage_ms, stats, scene, uniq, tile, blend):
     cand = {k: stage_ms[k] for k in kernels if stage_ms.get(k, 0.0) > 0}
     dom = max(cand, key=cand.get)
     t = stage_ms[dom] * 1e-3
-    meas = MEASURED["tiles"].get(tuple(tile)) if kernel_digest() == MEASURED["digest"] else None
+    meas = MEASURED["tiles"].get((*tile, split)) if kernel_digest() == MEASURED["digest"] else None
     out = {"kernel": kernels[dom], "launch_ms": round(stage_ms[dom], 4),
            "traffic": meas["traffic"].get(dom) if meas else None}
     if dom == "blend":
@@ -603,7 +600,7 @@ OFFSET_FLOPS_PER_INSTANCE = 2 * 80 * 64
 BF16_PEAK_TFLOPS = 2500.0  # dense bf16 matrix-core peak of one MI355X
 
 
-def offsets_leg(torch, scene, poses_all, lod, tile, pose_net, timed, frames=3, blocks=(0, 0)):
+def offsets_leg(torch, scene, poses_all, lod, tile, pose_net, timed, frames=3, blocks=(0, 0), split=1):
     """The headline frame with pose-dependent offsets: frame rate as timed
     (``timed``: captured frames in flight), then the offsets stage of eager
     instrumented frames (HIP events) against the matrix cores' bf16 peak on
@@ -615,7 +612,7 @@ def offsets_leg(torch, scene, poses_all, lod, tile, pose_net, timed, frames=3, b
     mode, thr, mlp_ptr, margin = lod
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        r = cs.Renderer(0, stream=stream, fuse=True, profile=True, tile=tile, blocks=blocks)
+        r = cs.Renderer(0, stream=stream, fuse=True, profile=True, tile=tile, blocks=blocks, blend_split=split)
         r.upload_templates(scene.templates)
         r.set_crowd(scene.crowd)
         r.upload_pose_net(*pose_net)
@@ -687,7 +684,8 @@ def main():
     ap.add_argument("--instances", type=int, default=3500)
     ap.add_argument("--net", default=os.path.join(ROOT, "paper_2501_17792_amd", "lod_net.npz"))
     ap.add_argument("--rules", default=os.path.join(ROOT, "paper_2501_17792_amd", "lod_frame_rules.json"))
-    ap.add_argument("--tile", default="auto", help="WxH or 'auto' (autotuned per run)")
+    ap.add_argument("--tile", default="auto",
+                    help="WxH, WxHsK (K workgroups composite each tile's rows) or 'auto' (autotuned per run)")
     ap.add_argument("--modes", default="", help="comma list of LoD modes to time (default: all)")
     ap.add_argument("--sweep", default="", choices=["", "tab2", "tab1", "paper_lod", "fit"],
                     help="instead of the headline: the Tab. 2 FPS sweep, the Tab. 1 memory sweep, the "
@@ -773,10 +771,11 @@ def main():
         modes = {k: v for k, v in modes.items() if k in keep}
     tile_timing = None
     blocks = (0, 0)  # (bin_blocks, sort_blocks): library defaults unless the autotuner picked others
+    split = 1  # workgroups compositing one binning tile's rows (blend_split)
     inflight = args.inflight
-    if args.tile == "auto":
-        from paper_2501_17792_amd import autotune
+    from paper_2501_17792_amd import autotune
 
+    if args.tile == "auto":
         cache = os.path.join(ROOT, "paper_2501_17792_amd", "autotune_cache.json")
         if args.retune and os.path.exists(cache):
             os.remove(cache)
@@ -784,15 +783,14 @@ def main():
                                                                 rule=head, cache_path=cache, log=log)
         inflight = inflight or tuned_inflight
         blocks = tuple(int(b) for b in tile_timing.get("blocks", (0, 0)))
+        split = int(tile_timing.get("split", 1))
     else:
-        tile = tuple(int(x) for x in args.tile.split("x"))
+        tile, split = autotune.parse_shape(args.tile)
     inflight = inflight or 3
-    log(f"tile {tile}, {inflight} frames in flight")
+    log(f"tile {tile}, blend split {split}, {inflight} frames in flight")
     # frame streams: a set on which the frames in flight advance evenly (short runs of the headline frame)
-    from paper_2501_17792_amd import autotune
-
     def trial(sts):
-        return autotune.frames_on(torch, scene, poses_all, modes[head], tile, sts, 80, 10, blocks)
+        return autotune.frames_on(torch, scene, poses_all, modes[head], tile, sts, 80, 10, blocks, split)
 
     streams, stream_sets = autotune.pick_streams(torch, dev, inflight, trial, log=log)
 
@@ -801,7 +799,7 @@ def main():
             imgs = [torch.zeros((3, sc.camera.height, sc.camera.width), device=dev) for _ in range(n)]
             rs = []
             for st in streams[:n]:
-                r = cs.Renderer(0, stream=st, fuse=True, tile=tile, blocks=blocks)
+                r = cs.Renderer(0, stream=st, fuse=True, tile=tile, blocks=blocks, blend_split=split)
                 r.upload_templates(sc.templates)
                 r.set_crowd(sc.crowd)
                 if pose_net is not None:
@@ -837,7 +835,7 @@ def main():
     if not args.no_offsets:
         pn = (synth.pose_net_weights(), [synth.pose_embeddings(1200 + t, tpl.n) for t, tpl in enumerate(scene.templates)])
         ro = run(modes[head], len(streams), pose_net=pn)
-        offsets = offsets_leg(torch, scene, poses_all, modes[head], tile, pn, ro, blocks=blocks)
+        offsets = offsets_leg(torch, scene, poses_all, modes[head], tile, pn, ro, blocks=blocks, split=split)
         log(f"{head} with pose-dependent offsets: {offsets['fps']:.1f} FPS, offsets stage {offsets['offsets_ms']:.3f} ms")
 
     res = results[head]
@@ -853,7 +851,8 @@ def main():
     def stage_profile(fuse, count=False):
         with torch.cuda.stream(stream):
             img = torch.zeros((3, scene.camera.height, scene.camera.width), device=dev)
-            rp = cs.Renderer(0, stream=stream, fuse=fuse, profile=True, tile=tile, count_blend=count, blocks=blocks)
+            rp = cs.Renderer(0, stream=stream, fuse=fuse, profile=True, tile=tile, count_blend=count, blocks=blocks,
+                             blend_split=split)
             rp.upload_templates(scene.templates)
             rp.set_crowd(scene.crowd)
             lvl_out = torch.zeros(scene.crowd.n, dtype=torch.int32, device=dev)
@@ -895,7 +894,7 @@ def main():
              "eval_slots_per_s_per_cu": round(float(ev[:, 1].mean() / (blend_ms * 1e-3)) / N_CU, 1),
              "live_fraction_of_slots": round(float(ev[:, 0].sum() / max(ev[:, 1].sum(), 1.0)), 4),
              "evals_per_pair": round(float(ev[:, 0].sum() / max(ev[:, 2].sum(), 1.0)), 3)}
-    roofline = frame_roofline(stage_ms, stats, scene, uniq, tile, blend)
+    roofline = frame_roofline(stage_ms, stats, scene, uniq, tile, split, blend)
     copy_gbs, copy_ok = copy_bandwidth(torch, stream)
     fit_res = None
     if args.fit_steps > 0:
@@ -935,7 +934,8 @@ def main():
                                "with a frame budget of 40 dB PSNR against full detail, hipGraph-captured frame "
                                "(pose upload inside), frames in flight on separate contexts",
                    "lod": head, "instances": scene.crowd.n, "width": scene.camera.width,
-                   "height": scene.camera.height, "tile": list(tile), "blocks": list(blocks)},
+                   "height": scene.camera.height, "tile": list(tile), "blend_split": split,
+                   "blocks": list(blocks)},
         "autotune": tile_timing,
         "frames_in_flight": len(streams), "frame_stream_sets_tried": stream_sets,
         "frame_ms_median": round(float(np.median(res["per"])), 4),

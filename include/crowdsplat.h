@@ -89,7 +89,11 @@ typedef struct cs_options {
                                 result does not depend on it                    */
   int32_t sort_blocks;       /* workgroups of the key splits and the LDS segment
                                 sort: 0 = 512, else 64..4096 (same result)      */
-  int32_t reserved[3];
+  int32_t blend_split;       /* workgroups compositing one binning tile, each
+                                over tile_h / blend_split rows (at least 8) and
+                                the whole tile's list: 0 or 1, 2, 4 (same
+                                pixels)                                         */
+  int32_t reserved[2];
 } cs_options;
 
 /* How the tile-bucket form's LDS segment sort ranks radix digits inside a

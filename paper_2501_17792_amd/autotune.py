@@ -23,7 +23,21 @@ import numpy as np
 
 from . import crowdsplat as cs
 
-CANDIDATES = [(16, 16), (8, 8), (16, 8), (8, 16), (32, 8), (32, 16), (16, 32)]
+# (tile width, tile height, workgroups compositing one tile): the binning
+# tile and how many workgroups split its rows in the blend
+CANDIDATES = [(16, 16, 1), (16, 16, 2), (8, 8, 1), (16, 8, 1), (8, 16, 1), (32, 8, 1), (32, 16, 1), (32, 16, 2),
+              (16, 32, 1), (16, 32, 2), (16, 32, 4), (32, 32, 1), (32, 32, 2), (32, 32, 4)]
+
+
+def shape_name(tw, th, split=1):
+    return f"{tw}x{th}" + (f"s{split}" if split > 1 else "")
+
+
+def parse_shape(name):
+    """((tw, th), split) of a ``shape_name``."""
+    base, _, sp = name.partition("s")
+    tw, th = (int(x) for x in base.split("x"))
+    return (tw, th), int(sp) if sp else 1
 # (bin_blocks, sort_blocks) tried at the chosen tile shape and frames in flight
 BLOCK_CANDIDATES = [(256, 512), (1024, 512), (512, 256), (512, 1024)]
 
@@ -49,18 +63,21 @@ def cache_key(torch, width, height, n_inst, rule=""):
 
 def tune(torch, scene, poses_all, stream, lod, frames: int = 20, candidates=CANDIDATES,
          cache_path: str | None = None, log=None):
-    """Returns (best tile, {tile: ms per frame})."""
+    """Returns (best shape name, {shape name: ms per frame}), one frame in
+    flight."""
     key = cache_key(torch, scene.camera.width, scene.camera.height, scene.crowd.n)
     if cache_path and os.path.exists(cache_path):
         with open(cache_path) as f:
             cache = json.load(f)
         if key in cache:
-            return tuple(cache[key]["tile"]), cache[key]["ms"]
+            return shape_name(*cache[key]["tile"], cache[key].get("split", 1)), cache[key]["ms"]
     mode, thr, mlp_ptr, margin = lod
     timing = {}
-    for tile in candidates:
+    for tw, th, split in candidates:
+        tile = (tw, th)
+        name = shape_name(tw, th, split)
         with torch.cuda.stream(stream):
-            r = cs.Renderer(0, stream=stream, tile=tile, fuse=True)
+            r = cs.Renderer(0, stream=stream, tile=tile, fuse=True, blend_split=split)
             r.upload_templates(scene.templates)
             r.set_crowd(scene.crowd)
             img = torch.zeros((3, scene.camera.height, scene.camera.width), device=poses_all.device)
@@ -74,9 +91,9 @@ def tune(torch, scene, poses_all, stream, lod, frames: int = 20, candidates=CAND
                 r.capture(scene.camera, img, mode, thr, mlp_ptr=mlp_ptr, margin=margin)
             except cs.CrowdSplatError as e:  # the shape does not fit (e.g. too many tile pairs)
                 r.close()
-                timing[f"{tile[0]}x{tile[1]}"] = None
+                timing[name] = None
                 if log:
-                    log(f"tile {tile}: skipped ({e})")
+                    log(f"shape {name}: skipped ({e})")
                 continue
             for k in range(3):
                 r.launch()
@@ -90,21 +107,21 @@ def tune(torch, scene, poses_all, stream, lod, frames: int = 20, candidates=CAND
             ok = r.poll().overflow == 0
             r.close()
         ms = e0.elapsed_time(e1) / frames
-        timing[f"{tile[0]}x{tile[1]}"] = round(ms, 4) if ok else None
+        timing[name] = round(ms, 4) if ok else None
         if log:
-            log(f"tile {tile}: {ms:.3f} ms/frame{'' if ok else ' (overflow, discarded)'}")
+            log(f"shape {name}: {ms:.3f} ms/frame{'' if ok else ' (overflow, discarded)'}")
     valid = {k: v for k, v in timing.items() if v is not None}
     best = min(valid, key=valid.get)
-    tile = tuple(int(x) for x in best.split("x"))
     if cache_path:
         cache = {}
         if os.path.exists(cache_path):
             with open(cache_path) as f:
                 cache = json.load(f)
-        cache[key] = {"tile": list(tile), "ms": timing}
+        tile, split = parse_shape(best)
+        cache[key] = {"tile": list(tile), "split": split, "ms": timing}
         with open(cache_path, "w") as f:
             json.dump(cache, f, indent=1)
-    return tile, timing
+    return best, timing
 
 
 def _overlap_span(torch, dev, streams, cycles):
@@ -263,10 +280,10 @@ def time_frames(torch, rs, scene, poses_all, imgs, streams, lod, steps, warmup, 
     return dict(ms=total / steps, per=per, stats=st0, frame0=frame0, overflow=overflow)
 
 
-def frames_on(torch, scene, poses_all, lod, tile, streams, frames, warmup=30, blocks=(0, 0)):
+def frames_on(torch, scene, poses_all, lod, tile, streams, frames, warmup=30, blocks=(0, 0), split=0):
     """``time_frames`` of captured frames alternating over fresh contexts on
     ``streams`` (one each); ``blocks``: the contexts' (bin_blocks,
-    sort_blocks)."""
+    sort_blocks); ``split``: their blend_split."""
     dev = poses_all.device
     n = len(streams)
     rs = []
@@ -274,7 +291,7 @@ def frames_on(torch, scene, poses_all, lod, tile, streams, frames, warmup=30, bl
         with torch.cuda.stream(streams[0]):
             imgs = [torch.zeros((3, scene.camera.height, scene.camera.width), device=dev) for _ in range(n)]
             for st in streams:
-                r = cs.Renderer(0, stream=st, fuse=True, tile=tile, blocks=blocks)
+                r = cs.Renderer(0, stream=st, fuse=True, tile=tile, blocks=blocks, blend_split=split)
                 rs.append(r)
                 r.upload_templates(scene.templates)
                 r.set_crowd(scene.crowd)
@@ -287,14 +304,15 @@ def frames_on(torch, scene, poses_all, lod, tile, streams, frames, warmup=30, bl
         torch.cuda.empty_cache()
 
 
-def _frame_rate(torch, scene, poses_all, lod, tile, n, frames, warmup=30, blocks=(0, 0)):
+def _frame_rate(torch, scene, poses_all, lod, tile, n, frames, warmup=30, blocks=(0, 0), split=0):
     """Frames per second of captured frames alternating over ``n`` fresh
     contexts (one stream each, a set whose frames advance evenly), timed by
     ``time_frames``; None on overflow."""
     dev = poses_all.device
     out = None
     for _ in range(4):
-        out = frames_on(torch, scene, poses_all, lod, tile, distinct_streams(torch, dev, n), frames, warmup, blocks)
+        out = frames_on(torch, scene, poses_all, lod, tile, distinct_streams(torch, dev, n), frames, warmup, blocks,
+                        split)
         if out["overflow"] or balanced(out, n):
             break
     return None if out["overflow"] else 1000.0 / out["ms"]
@@ -302,9 +320,11 @@ def _frame_rate(torch, scene, poses_all, lod, tile, n, frames, warmup=30, blocks
 
 def tune_frame(torch, scene, poses_all, stream, lod, rule="", inflights=(1, 2, 3, 4), top=3, frames=300,
                cache_path=None, log=None):
-    """(tile, frames in flight, record): the tile shapes ranked by ``tune``
-    (one frame in flight), then the best ``top`` shapes timed with each
-    count of frames in flight; the highest frame rate wins."""
+    """(tile, frames in flight, record): the shapes (tile and blend split)
+    ranked by ``tune`` (one frame in flight), then the best ``top`` shapes
+    timed with each count of frames in flight; the highest frame rate wins.
+    The record holds the blend split ("split") and the binning / sorting
+    workgroup counts ("blocks")."""
     key = cache_key(torch, scene.camera.width, scene.camera.height, scene.crowd.n, rule)
     cache = {}
     if cache_path and os.path.exists(cache_path):
@@ -313,18 +333,19 @@ def tune_frame(torch, scene, poses_all, stream, lod, rule="", inflights=(1, 2, 3
         if key in cache:
             c = cache[key]
             if log:
-                log(f"autotune cache hit {key}: tile {c['tile']}, {c['inflight']} in flight")
+                log(f"autotune cache hit {key}: tile {c['tile']}, split {c.get('split', 1)}, "
+                    f"{c['inflight']} in flight")
             return tuple(c["tile"]), int(c["inflight"]), dict(c, cached=True)
     _, single = tune(torch, scene, poses_all, stream, lod, frames=20, log=log)
     ranked = sorted((v, k) for k, v in single.items() if v is not None)[:top]
     fps = {}
     for _, name in ranked:
-        tile = tuple(int(x) for x in name.split("x"))
+        tile, split = parse_shape(name)
         for n in inflights:
-            v = _frame_rate(torch, scene, poses_all, lod, tile, n, frames)
+            v = _frame_rate(torch, scene, poses_all, lod, tile, n, frames, split=split)
             fps[f"{name}/{n}"] = round(v, 2) if v is not None else None
             if log:
-                log(f"tile {name}, {n} in flight: {v} FPS")
+                log(f"shape {name}, {n} in flight: {v} FPS")
     # the leaders once more, in reverse order, each judged by the lower of its
     # two rates (a configuration can read high once: four frames in flight
     # read 244 FPS in one measurement and 221 in the next and in the bench)
@@ -332,14 +353,15 @@ def tune_frame(torch, scene, poses_all, stream, lod, rule="", inflights=(1, 2, 3
     again = {}
     for k in reversed(leaders):
         name, n = k.split("/")
-        v = _frame_rate(torch, scene, poses_all, lod, tuple(int(x) for x in name.split("x")), int(n), frames)
+        t, sp = parse_shape(name)
+        v = _frame_rate(torch, scene, poses_all, lod, t, int(n), frames, split=sp)
         again[k] = round(v, 2) if v is not None else None
         if log:
-            log(f"tile {name}, {n} in flight, again: {v} FPS")
+            log(f"shape {name}, {n} in flight, again: {v} FPS")
     judged = {k: min(fps[k], again[k]) for k in leaders if again[k] is not None}
     best = max((v, k) for k, v in judged.items())[1]
     name, n = best.split("/")
-    tile = tuple(int(x) for x in name.split("x"))
+    tile, split = parse_shape(name)
     # then the workgroup counts of the binning kernels and of the key splits /
     # LDS segment sort at that shape; another count than the default (512,
     # 512) is kept only if it is faster in two measurements by more than 1%
@@ -347,16 +369,16 @@ def tune_frame(torch, scene, poses_all, stream, lod, rule="", inflights=(1, 2, 3
     blocks_fps = {}
     chosen, chosen_v = (0, 0), base
     for b in BLOCK_CANDIDATES:
-        v = _frame_rate(torch, scene, poses_all, lod, tile, int(n), frames, blocks=b)
+        v = _frame_rate(torch, scene, poses_all, lod, tile, int(n), frames, blocks=b, split=split)
         if v is not None and v > 1.01 * base:
-            v = min(v, _frame_rate(torch, scene, poses_all, lod, tile, int(n), frames, blocks=b) or 0.0)
+            v = min(v, _frame_rate(torch, scene, poses_all, lod, tile, int(n), frames, blocks=b, split=split) or 0.0)
         blocks_fps[f"{b[0]}/{b[1]}"] = round(v, 2) if v is not None else None
         if log:
-            log(f"tile {name}, {n} in flight, blocks {b}: {v} FPS")
+            log(f"shape {name}, {n} in flight, blocks {b}: {v} FPS")
         if v is not None and v > 1.01 * base and v > chosen_v:
             chosen, chosen_v = b, v
-    rec = {"tile": list(tile), "inflight": int(n), "blocks": list(chosen), "single_frame_ms": single, "fps": fps,
-           "fps_again": again, "blocks_fps": blocks_fps}
+    rec = {"tile": list(tile), "split": split, "inflight": int(n), "blocks": list(chosen), "single_frame_ms": single,
+           "fps": fps, "fps_again": again, "blocks_fps": blocks_fps}
     if cache_path:
         cache[key] = rec
         with open(cache_path, "w") as f:

@@ -54,7 +54,7 @@ class CsOptions(ctypes.Structure):
                 ("max_splats", ctypes.c_int64), ("max_pairs", ctypes.c_int64),
                 ("sort_algo", ctypes.c_int32), ("sort_ranks", ctypes.c_int32),
                 ("count_blend", ctypes.c_int32), ("bin_blocks", ctypes.c_int32), ("sort_blocks", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("blend_split", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class CsTemplateDesc(ctypes.Structure):
@@ -228,8 +228,9 @@ class Renderer:
     def __init__(self, device: int = 0, stream=None, tile=(16, 16), skin_mode=CS_SKIN_FULL,
                  launch_mode=CS_LAUNCH_BATCHED, fuse=False, max_splats=0, max_pairs=0,
                  profile=False, sort_algo=CS_SORT_TILE_BUCKET, sort_ranks=CS_SORT_RANKS_CHECKED,
-                 count_blend=False, blocks=(0, 0)):
-        """``blocks``: (bin_blocks, sort_blocks) of cs_options (0: defaults)."""
+                 count_blend=False, blocks=(0, 0), blend_split=0):
+        """``blocks``: (bin_blocks, sort_blocks) of cs_options (0: defaults);
+        ``blend_split``: workgroups compositing one binning tile (0: one)."""
         import torch
         self.torch = torch
         self.lib = load_library()
@@ -243,6 +244,7 @@ class Renderer:
         opt.sort_ranks = sort_ranks
         opt.count_blend = int(count_blend)
         opt.bin_blocks, opt.sort_blocks = (int(b) for b in blocks)
+        opt.blend_split = int(blend_split)
         opt.max_splats, opt.max_pairs = max_splats, max_pairs
         self.tile = tuple(tile)
         ctx = ctypes.c_void_p()

@@ -58,7 +58,8 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
                                                        float* __restrict__ image,
                                                        const FrameHdr* __restrict__ hdr, ViewDev view,
                                                        const uint32_t* __restrict__ order,
-                                                       unsigned long long* __restrict__ counters, VisDev vis) {
+                                                       unsigned long long* __restrict__ counters, VisDev vis,
+                                                       int split) {
   constexpr bool COUNT = MODE == kCount, VISIBLE = MODE == kVisible;
   constexpr int N = TW * TH;
   constexpr int ROWS = 64 / TW;  // pixel rows per wave
@@ -80,7 +81,22 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
   __shared__ uint32_t s_live[2][WAVES];
   __shared__ uint32_t s_mask[2][N];             // bit r: the splat's box reaches pixel row r of the tile
   __shared__ uint8_t s_list[WAVES][G][SUB];     // per group: offsets of the splats it must evaluate, in order
-  const int tile = order ? (int)order[blockIdx.x] : (int)blockIdx.x;
+  // A binning tile of TH * split rows may be composited by `split`
+  // workgroups of TH rows each, every one walking the whole tile's list:
+  // each pixel sees the same splats in the same order. The parts of one
+  // tile go to one XCD (workgroups are dealt to the XCDs round-robin by
+  // index), one after another, so that they share its L2 copy of the list:
+  // block b serves XCD b % 8 and, of that XCD's blocks, the (b / 8)-th, which
+  // is part (b / 8) % split of item 8 (b / 8 / split) + b % 8. The grid is
+  // rounded up to whole groups of 8 split blocks; the extra ones return.
+  int part = 0, item = (int)blockIdx.x;
+  if (split > 1) {
+    const int s = (int)blockIdx.x / kXcds;
+    part = s % split;
+    item = (s / split) * kXcds + (int)blockIdx.x % kXcds;
+    if (item >= cam.tiles_x * cam.tiles_y) return;
+  }
+  const int tile = order ? (int)order[item] : item;
   int tx, ty;
   float* out = image;
   int out_x0 = 0, out_y0 = 0, out_w = cam.W, out_h = cam.H;
@@ -108,12 +124,13 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
     ty = tile / cam.tiles_x;
   }
   const int lx = threadIdx.x % TW, ly = threadIdx.x / TW;
-  const int px = tx * TW + lx, py = ty * TH + ly;
+  const int row0 = ty * TH * split + part * TH;  // the block's first pixel row
+  const int px = tx * TW + lx, py = row0 + ly;
   const bool inside = px < cam.W && py < cam.H;
   const float pcx = (float)px + 0.5f, pcy = (float)py + 0.5f;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const float wx0 = (float)(tx * TW) + 0.5f, wx1 = (float)(tx * TW + TW - 1) + 0.5f;
-  const float ty0 = (float)(ty * TH) + 0.5f;
+  const float ty0 = (float)row0 + 0.5f;
   const uint32_t start = ranges[2 * tile], end = ranges[2 * tile + 1];
   const uint32_t n_splats = hdr->n_splats;
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
@@ -360,23 +377,24 @@ template <int TW, int TH>
 static hipError_t launch_blend_t(const uint32_t* ranges, const uint32_t* svals, const float4* rec,
                                  CamDev cam, float* image, const FrameHdr* hdr, const ViewDev* view,
                                  uint32_t* order, hipStream_t st, unsigned long long* counters,
-                                 const VisDev* vis) {
+                                 const VisDev* vis, int split) {
   if (view) {
     if (view->n_tiles > 0)
       blend_kernel<TW, TH, true><<<view->n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr, *view,
-                                                                      nullptr, nullptr, VisDev{});
+                                                                      nullptr, nullptr, VisDev{}, 1);
   } else {
     const int n_tiles = cam.tiles_x * cam.tiles_y;
+    const int grid = split > 1 ? (n_tiles + kXcds - 1) / kXcds * kXcds * split : n_tiles;
     if (order) tile_order_kernel<<<1, 1024, 0, st>>>(ranges, n_tiles, order);
     if (counters)
-      blend_kernel<TW, TH, false, kCount><<<n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr,
-                                                                        ViewDev{}, order, counters, VisDev{});
+      blend_kernel<TW, TH, false, kCount><<<grid, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr,
+                                                                     ViewDev{}, order, counters, VisDev{}, split);
     else if (vis)
-      blend_kernel<TW, TH, false, kVisible><<<n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr,
-                                                                          ViewDev{}, order, nullptr, *vis);
+      blend_kernel<TW, TH, false, kVisible><<<grid, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr,
+                                                                       ViewDev{}, order, nullptr, *vis, split);
     else
-      blend_kernel<TW, TH, false><<<n_tiles, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr, ViewDev{},
-                                                                order, nullptr, VisDev{});
+      blend_kernel<TW, TH, false><<<grid, TW * TH, 0, st>>>(ranges, svals, rec, cam, image, hdr, ViewDev{},
+                                                             order, nullptr, VisDev{}, split);
   }
   return hipGetLastError();
 }
@@ -387,12 +405,17 @@ static hipError_t launch_blend_t(const uint32_t* ranges, const uint32_t* svals, 
 // slots) for an instrumented frame.
 // vis: null, or the visible-pixel counts (zeroed) to accumulate the frame's
 // into (not with counters, nor for view tiles).
+// split: workgroups per binning tile (rows cut into equal parts of 8, 16 or
+// 32; 1 for view tiles).
 hipError_t launch_blend(const uint32_t* ranges, const uint32_t* svals, const float4* rec, CamDev cam,
                         float* image, const FrameHdr* hdr, const ViewDev* view, uint32_t* order,
-                        hipStream_t st, unsigned long long* counters, const VisDev* vis) {
+                        hipStream_t st, unsigned long long* counters, const VisDev* vis, int split) {
+  if (view) split = 1;
+  if (split < 1 || cam.th % split != 0) return hipErrorInvalidValue;
+  const int th = cam.th / split;
 #define CS_BLEND_CASE(W_, H_) \
-  if (cam.tw == W_ && cam.th == H_)      \
-    return launch_blend_t<W_, H_>(ranges, svals, rec, cam, image, hdr, view, order, st, counters, vis);
+  if (cam.tw == W_ && th == H_)          \
+    return launch_blend_t<W_, H_>(ranges, svals, rec, cam, image, hdr, view, order, st, counters, vis, split);
   CS_BLEND_CASE(8, 8)
   CS_BLEND_CASE(8, 16)
   CS_BLEND_CASE(8, 32)

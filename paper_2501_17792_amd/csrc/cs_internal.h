@@ -270,7 +270,8 @@ hipError_t launch_ranges(const uint64_t* skeys, FrameHdr* hdr, uint32_t max_pair
                          uint32_t* ranges, hipStream_t st);
 hipError_t launch_blend(const uint32_t* ranges, const uint32_t* svals, const float4* rec, CamDev cam,
                         float* image, const FrameHdr* hdr, const ViewDev* view, uint32_t* order,
-                        hipStream_t st, unsigned long long* counters = nullptr, const VisDev* vis = nullptr);
+                        hipStream_t st, unsigned long long* counters = nullptr, const VisDev* vis = nullptr,
+                        int split = 1);
 hipError_t launch_features(const cs_instance* inst, const float* pose, const float* joints,
                            const TemplateDev* tpl, int n_inst, int n_tpl, CamDev cam, const cs_mlp* net,
                            float* feat, hipStream_t st);

@@ -462,6 +462,10 @@ cs_status cs_create(int32_t device, void* stream, const cs_options* opt, cs_ctx*
   if (o.sort_algo != CS_SORT_TILE_BUCKET && o.sort_algo != CS_SORT_REDUCE_SCAN && o.sort_algo != CS_SORT_ONESWEEP)
     return CS_ERR_INVALID;
   if (o.sort_ranks != CS_SORT_RANKS_CHECKED && o.sort_ranks != CS_SORT_RANKS_BALLOT) return CS_ERR_INVALID;
+  if (o.blend_split == 0) o.blend_split = 1;
+  if ((o.blend_split != 1 && o.blend_split != 2 && o.blend_split != 4) || o.tile_h % o.blend_split != 0 ||
+      o.tile_h / o.blend_split < 8)
+    return CS_ERR_INVALID;
   if (o.bin_blocks == 0) o.bin_blocks = kBucketBlocks;
   if (o.sort_blocks == 0) o.sort_blocks = kSegGrid;
   if (o.bin_blocks < 64 || o.bin_blocks > kBucketMaxBlocks || o.sort_blocks < 64 || o.sort_blocks > 4096)
@@ -953,7 +957,8 @@ static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs
   if (n_tiles > 0)
     HIP_TRY(launch_blend(ctx->ranges, ctx->vals[ctx->sorted], ctx->rec, cd, image, ctx->hdr, vp,
                          view_mode ? nullptr : ctx->tile_order, ctx->stream,
-                         count ? &ctx->hdr->blend_evals : nullptr, count_vis ? &visd : nullptr));
+                         count ? &ctx->hdr->blend_evals : nullptr, count_vis ? &visd : nullptr,
+                         view_mode ? 1 : ctx->opt.blend_split));
   ctx->vis_frame = false;
   ctx->vis_maybe = ctx->vis_maybe || count_vis;
   ctx->mark(CS_STAGE_BLEND, 1);

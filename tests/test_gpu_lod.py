@@ -303,6 +303,40 @@ def test_frame_budget_selection_matches_oracle():
 
 
 @pytest.mark.timeout(400)
+def test_visible_counts_do_not_depend_on_blend_split():
+    """The per-instance visible-pixel counts of a counting render, and the
+    selection they feed, are the same whether a tile's rows are composited by
+    one workgroup or by two or four."""
+    import torch
+
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    templates, crowd, cam = _scene(n_inst=200)
+    n = crowd.n
+    out = []
+    for tile, split in [((16, 32), 1), ((16, 32), 2), ((16, 32), 4)]:
+        r = _renderer(templates, crowd, tile=tile, blend_split=split)
+        dev, _ = _net(r)
+        img = torch.zeros((3, cam.height, cam.width), device="cuda")
+        lv = []
+        for _ in range(2):
+            lvl = torch.zeros(n, dtype=torch.int32, device="cuda")
+            r.select_lod(cam, cs.CS_LOD_BUDGET_VISIBLE, (), level_out=lvl, psnr_min=40.0, margin=0.0,
+                         mlp_ptr=dev.data_ptr())
+            r.skin()
+            r.render(cam, img, stats=True)
+            torch.cuda.synchronize()
+            lv.append(lvl.cpu().numpy())
+        vis = r.debug("VISIBLE", np.uint32, n).astype(np.int64)
+        out.append((vis, lv, img.cpu().numpy()))
+        r.close()
+    assert out[0][0].sum() > 0
+    for vis, lv, im in out[1:]:
+        assert np.array_equal(vis, out[0][0])
+        assert all(np.array_equal(a, b) for a, b in zip(lv, out[0][1]))
+        assert np.array_equal(im, out[0][2])
+
+
 def test_visible_share_budget_matches_oracle():
     """CS_LOD_BUDGET_VISIBLE. The render after the selection counts, per
     instance, the pixels whose largest-weight splat (alpha T, the first of

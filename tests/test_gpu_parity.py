@@ -260,6 +260,29 @@ def test_tile_shape_launch_and_fusion_invariance():
             assert np.array_equal(img, ref), (fuse, kw)
 
 
+def test_blend_split_compositing_invariance():
+    """A binning tile's rows composited by 2 or 4 workgroups (blend_split)
+    give the bit-identical image, plain and with the compositing counters on;
+    splits that leave fewer than 8 rows per workgroup, or other counts, are
+    refused at creation."""
+    from paper_2501_17792_amd import crowdsplat as cs
+
+    sc = _small_c2_scene(n_inst=8)
+    _, ref = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, fuse=True)
+    for tile, split in [((16, 16), 2), ((16, 32), 2), ((16, 32), 4), ((32, 32), 2), ((32, 32), 4), ((8, 32), 4),
+                        ((32, 16), 2)]:
+        r, img = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, fuse=True, tile=tile, blend_split=split)
+        assert np.array_equal(img, ref), (tile, split)
+        assert r.last_stats.overflow == 0
+        rc, img_c = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, fuse=True, tile=tile, blend_split=split,
+                            profile=True, count_blend=True)
+        assert np.array_equal(img_c, ref), (tile, split, "counting")
+        assert rc.last_stats.blend_evals > 0
+    for tile, split in [((16, 16), 4), ((8, 8), 2), ((16, 32), 3), ((32, 32), 8), ((16, 16), -1)]:
+        with pytest.raises(cs.CrowdSplatError):
+            cs.Renderer(0, tile=tile, blend_split=split)
+
+
 def test_c2_slice_fused_matches_oracle():
     """Skinning fused into projection (camera-frame algebra) against the FP64
     oracle, records to pixels."""
