@@ -149,11 +149,17 @@ def test_views_equal_full_frames_of_one_instance():
 
     templates, crowd, cam = _scene(n_inst=12)
     r = _renderer(templates, crowd)
+    rs = _renderer(templates, crowd, blend_split=2)  # view tiles are composited whole whatever the split
     for lvl in (0, 3):
         r.select_lod(cam, cs.CS_LOD_CONSTANT, (), level=lvl)
         r.skin()
         atlas, views = r.render_views(cam)
         at = atlas.cpu().numpy()
+        rs.select_lod(cam, cs.CS_LOD_CONSTANT, (), level=lvl)
+        rs.skin()
+        atlas_s, views_s = rs.render_views(cam)
+        assert np.array_equal(np.asarray(views_s), np.asarray(views))
+        assert np.array_equal(atlas_s.cpu().numpy(), at)
         for i in range(crowd.n):
             x0, y0, w, h, _, off = views[i]
             if w == 0:
