@@ -61,7 +61,7 @@ BLEND_FLOPS_PER_EVAL = 24
 # lane-instructions per item (SQ_INSTS_VALU x 64 / items: splats for the projection, pairs for the sort and
 # the blend), summarised under profiles/crowd3500_1080p_budget_<shape>_kernels.md. Other sources, shapes or
 # workloads report null.
-MEASURED = {"digest": "2b7e087ca81ec9e6", "lod": "learned_budget",
+MEASURED = {"digest": "ebf93a646727c02b", "lod": "learned_budget",
             "tiles": {(32, 32, 4): {"traffic": {"blend": 3_305_432_157, "project_fused": 3_167_578_724,
                                                 "segsort": 917_472_016},
                                     "valu_per_item": {"blend": 599.5, "project_fused": 422.7, "segsort": 119.9}}}}
@@ -868,7 +868,8 @@ def main():
                     for name, v in t.items():
                         acc.setdefault(name, []).append(v)
                     evals.append((int(rp.last_stats.blend_evals), int(rp.last_stats.blend_eval_slots),
-                                  int(rp.last_stats.n_pairs), t.get("blend", 0.0)))
+                                  int(rp.last_stats.n_pairs), t.get("blend", 0.0),
+                                  int(rp.last_stats.blend_done_slots), int(rp.last_stats.blend_adds)))
             stream.synchronize()
             stp = rp.last_stats
             rp.close()
@@ -893,7 +894,13 @@ def main():
              "evals_per_s_per_cu": round(float(ev[:, 0].mean() / (blend_ms * 1e-3)) / N_CU, 1),
              "eval_slots_per_s_per_cu": round(float(ev[:, 1].mean() / (blend_ms * 1e-3)) / N_CU, 1),
              "live_fraction_of_slots": round(float(ev[:, 0].sum() / max(ev[:, 1].sum(), 1.0)), 4),
-             "evals_per_pair": round(float(ev[:, 0].sum() / max(ev[:, 2].sum(), 1.0)), 3)}
+             "evals_per_pair": round(float(ev[:, 0].sum() / max(ev[:, 2].sum(), 1.0)), 3),
+             # idle slots: lanes of finished pixels, and lanes past their group's list while another
+             # group of the wave still walks its own
+             "finished_fraction_of_slots": round(float(ev[:, 4].sum() / max(ev[:, 1].sum(), 1.0)), 4),
+             "past_list_fraction_of_slots": round(float((ev[:, 1] - ev[:, 0] - ev[:, 4]).sum()
+                                                        / max(ev[:, 1].sum(), 1.0)), 4),
+             "adds_per_frame": int(ev[:, 5].mean())}
     roofline = frame_roofline(stage_ms, stats, scene, uniq, tile, split, blend)
     copy_gbs, copy_ok = copy_bandwidth(torch, stream)
     fit_res = None

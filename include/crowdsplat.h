@@ -237,7 +237,14 @@ typedef struct cs_frame_stats {
                                 blend issued (the live ones plus lanes idle
                                 in a wave's step: finished pixels, shorter
                                 group lists); else 0                          */
-  int64_t reserved[3];
+  int64_t blend_done_slots;  /* count_blend only: of blend_eval_slots, those of
+                                lanes whose pixel had finished (or lies outside
+                                the image); the rest of the idle ones fall past
+                                the lane's group list; else 0                  */
+  int64_t blend_adds;        /* count_blend only: evaluations that added the
+                                splat to the pixel (alpha >= 1/255, not the
+                                stopping one); else 0                          */
+  int64_t reserved[1];
 } cs_frame_stats;
 
 /* Context lifetime. stream: a hipStream_t (NULL = the null stream). */

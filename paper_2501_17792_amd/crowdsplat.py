@@ -92,7 +92,8 @@ class CsFrameStats(ctypes.Structure):
                 ("n_instances", ctypes.c_int32), ("level_hist", ctypes.c_int32 * CS_MAX_LEVELS),
                 ("sort_fallbacks", ctypes.c_int32), ("reserved0", ctypes.c_int32),
                 ("blend_evals", ctypes.c_int64), ("blend_eval_slots", ctypes.c_int64),
-                ("reserved", ctypes.c_int64 * 3)]
+                ("blend_done_slots", ctypes.c_int64), ("blend_adds", ctypes.c_int64),
+                ("reserved", ctypes.c_int64 * 1)]
 
 
 CS_PNET_EMBED, CS_PNET_POSE, CS_PNET_HIDDEN = 32, 80, 64

@@ -135,7 +135,8 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
   const uint32_t n_splats = hdr->n_splats;
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f;
   bool done = !inside;
-  uint32_t n_live = 0, n_slots = 0;  // COUNT: live evaluations and lane slots of this lane
+  // COUNT: live evaluations, lane slots, slots with the pixel finished, adds
+  uint32_t n_live = 0, n_slots = 0, n_done = 0, n_add = 0;
   float best_w = -1.f;                // VISIBLE: largest weight added so far and its list position
   uint32_t best_pos = 0xffffffffu;
   // Software pipeline over batches: the tile's list entries are read 4
@@ -278,6 +279,7 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
             if constexpr (COUNT) {
               n_live += live ? 1u : 0u;
               n_slots += 1u;
+              n_done += done ? 1u : 0u;
             }
             const float dx = pcx - uv.x, dy = pcy - uv.y;
             float power = -0.5f * fmaf(r1.x * dx, dx, r1.z * dy * dy) - r1.y * dx * dy;
@@ -287,6 +289,7 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
             const bool hit = live && alpha >= (1.f / 255.f);
             const bool stop = hit && Tn < 1e-4f;  // stops without adding this splat
             const bool add = hit && !stop;
+            if constexpr (COUNT) n_add += add ? 1u : 0u;
             const float wgt = alpha * T;
             cr = add ? fmaf(r2.x, wgt, cr) : cr;
             cg = add ? fmaf(r2.y, wgt, cg) : cg;
@@ -328,15 +331,19 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
     }
   }
   if constexpr (COUNT) {
-    unsigned long long a = n_live, b = n_slots;
+    unsigned long long a = n_live, b = n_slots, c = n_done, d = n_add;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
       a += __shfl_xor(a, off);
       b += __shfl_xor(b, off);
+      c += __shfl_xor(c, off);
+      d += __shfl_xor(d, off);
     }
     if (lane == 0) {
       atomicAdd(&counters[0], a);
       atomicAdd(&counters[1], b);
+      atomicAdd(&counters[2], c);
+      atomicAdd(&counters[3], d);
     }
   }
   if constexpr (VISIBLE) {
@@ -401,8 +408,9 @@ static hipError_t launch_blend_t(const uint32_t* ranges, const uint32_t* svals, 
 
 // order: scratch of cam.tiles_x * cam.tiles_y entries for the longest-first
 // launch order, or null for tile-index order.
-// counters: null, or two zeroed 64-bit counters (live evaluations, lane
-// slots) for an instrumented frame.
+// counters: null, or four zeroed 64-bit counters (live evaluations, lane
+// slots, slots of finished pixels, evaluations that added) for an
+// instrumented frame.
 // vis: null, or the visible-pixel counts (zeroed) to accumulate the frame's
 // into (not with counters, nor for view tiles).
 // split: workgroups per binning tile (rows cut into equal parts of 8, 16 or

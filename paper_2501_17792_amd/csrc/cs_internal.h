@@ -129,6 +129,8 @@ struct FrameHdr {
   uint32_t sort_fallbacks; // LDS-sorted segments re-sorted with ballot ranks this frame
   unsigned long long blend_evals;  // instrumented frames: live (pixel, splat) evaluations of the blend
   unsigned long long blend_slots;  // instrumented frames: lane evaluation slots the blend issued
+  unsigned long long blend_done_slots;  // instrumented frames: of those, slots of finished / outside pixels
+  unsigned long long blend_adds;   // instrumented frames: evaluations that added a splat to a pixel
   uint32_t vis_ready;      // instance count of the frame the visible-pixel counts hold (0: none)
   uint32_t vis_pad;
 };

@@ -976,6 +976,8 @@ static cs_status render_impl(cs_ctx* ctx, const cs_camera* cam, float* image, cs
     stats->sort_fallbacks = (int32_t)h.sort_fallbacks;
     stats->blend_evals = (int64_t)h.blend_evals;
     stats->blend_eval_slots = (int64_t)h.blend_slots;
+    stats->blend_done_slots = (int64_t)h.blend_done_slots;
+    stats->blend_adds = (int64_t)h.blend_adds;
     if (h.overflow) return ctx->fail(CS_ERR_CAPACITY, "frame exceeded a capacity (see stats)");
   }
   return CS_OK;

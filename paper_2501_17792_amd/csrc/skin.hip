@@ -98,6 +98,8 @@ __global__ void frame_reset_kernel(FrameHdr* hdr, uint32_t* hist, int hist_len, 
     hdr->sort_fallbacks = 0;
     hdr->blend_evals = 0ull;
     hdr->blend_slots = 0ull;
+    hdr->blend_done_slots = 0ull;
+    hdr->blend_adds = 0ull;
     for (int p = 0; p < 8; ++p) hdr->ticket[p] = 0;
   }
   for (int i = t; i < hist_len; i += gridDim.x * blockDim.x) hist[i] = 0;

@@ -326,11 +326,19 @@ def test_blend_evaluation_counters():
         _, _, _, n_added = osplat._blend_list_chunked(gx.ravel() * 1.0, gy.ravel() * 1.0,
                                                        g["svals"][s0:s1].astype(np.int64), drec, cam.bg, 0, 0)
         added += int(n_added.sum())
-    print(f"evals {st.blend_evals}, slots {st.blend_eval_slots}, added {added}, list bound {upper}")
+    print(f"evals {st.blend_evals}, slots {st.blend_eval_slots} ({st.blend_done_slots} of finished pixels), "
+          f"adds {st.blend_adds}, oracle adds {added}, list bound {upper}")
     assert 0 < added <= st.blend_evals <= min(upper, st.blend_eval_slots)
+    assert st.blend_evals + st.blend_done_slots <= st.blend_eval_slots
+    # the device's adds against the FP64 oracle's over the same lists: equal
+    # but for pixels whose alpha or stopping test sits within rounding of its
+    # threshold (each moves a pixel's count by about one)
+    assert 0 < st.blend_adds <= st.blend_evals
+    assert abs(st.blend_adds - added) <= 1e-3 * added + 16
     for kw in ({}, dict(profile=True)):
         r = run_gpu(sc, cs.CS_LOD_FIXED, sc.lod_thresholds, **kw)[0]
         assert r.last_stats.blend_evals == 0 and r.last_stats.blend_eval_slots == 0
+        assert r.last_stats.blend_done_slots == 0 and r.last_stats.blend_adds == 0
 
 
 def test_determinism_and_graph_replay():
