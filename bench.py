@@ -61,10 +61,10 @@ BLEND_FLOPS_PER_EVAL = 24
 # lane-instructions per item (SQ_INSTS_VALU x 64 / items: splats for the projection, pairs for the sort and
 # the blend), summarised under profiles/crowd3500_1080p_budget_<shape>_kernels.md. Other sources, shapes or
 # workloads report null.
-MEASURED = {"digest": "ebf93a646727c02b", "lod": "learned_budget",
-            "tiles": {(32, 32, 4): {"traffic": {"blend": 3_305_432_157, "project_fused": 3_167_578_724,
-                                                "segsort": 917_472_016},
-                                    "valu_per_item": {"blend": 599.5, "project_fused": 422.7, "segsort": 119.9}}}}
+MEASURED = {"digest": "a3bad74c8ace29b0", "lod": "learned_budget",
+            "tiles": {(32, 32, 4): {"traffic": {"blend": 3_308_388_057, "project_fused": 3_167_018_319,
+                                                "segsort": 917_354_530},
+                                    "valu_per_item": {"blend": 587.9, "project_fused": 422.7, "segsort": 119.9}}}}
 
 
 def kernel_digest():

@@ -302,9 +302,9 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
               best_pos = better ? b + (uint32_t)j : best_pos;
             }
           };
-          // (k + 1 = n_max in the last pass: its lanes are all past their
-          // lists, so that half changes nothing)
-          for (int k = 0; k < n_max; k += 2) {
+          // pairs of entries while two are left; set A holds entry k + 2
+          // after the pass for entry k, so an odd last entry is A's
+          for (int k = 0; k + 1 < n_max; k += 2) {
             eval(k, a1, au, a2, jA);
             a1 = s_r1b[oA];
             a2 = s_r2b[oA];
@@ -320,6 +320,7 @@ __global__ __launch_bounds__(TW* TH) void blend_kernel(const uint32_t* __restric
             oB = off(k + 5);
             __builtin_amdgcn_sched_barrier(0);
           }
+          if (n_max & 1) eval(n_max - 1, a1, au, a2, jA);
         }
       }
       E = load_entry(b + 4 * N + tid);  // issued last: E's old value is dead by now
