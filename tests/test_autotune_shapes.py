@@ -30,3 +30,26 @@ def test_counter_measurements_name_candidate_shapes():
 
     for key in bench.MEASURED["tiles"]:
         assert key in autotune.CANDIDATES
+
+
+def test_frame_roofline_uses_counters_of_the_timed_shape_only():
+    """The bench's roofline object takes counter traffic and VALU issue only
+    for the tile shape and split they were measured at (and these sources):
+    compositing dominant here, its FP32 work against 78.6 TFLOP/s."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2501_17792_amd import synth
+
+    scene = synth.scene_c1()
+    stats = dict(n_splats=1_000_000, n_pairs=2_000_000)
+    stage = {"project_fused": 0.5, "segsort": 0.4, "blend": 1.0}
+    blend = {"evals_per_frame": 10_000_000}
+    measured = next(iter(bench.MEASURED["tiles"]))
+    ok = bench.kernel_digest() == bench.MEASURED["digest"]
+    r = bench.frame_roofline(stage, stats, scene, 0, measured[:2], measured[2], blend)
+    assert r["bound"] == "alu" and r["kernel"] == "blend_kernel"
+    assert abs(r["achieved"] - 10_000_000 * bench.BLEND_FLOPS_PER_EVAL / 1e-3 / 1e12) < 1e-3
+    assert (r["traffic"] is not None) == ok and ("issue" in r) == ok
+    other = (16, 16, 1) if measured != (16, 16, 1) else (32, 16, 1)
+    r2 = bench.frame_roofline(stage, stats, scene, 0, other[:2], other[2], blend)
+    assert r2["traffic"] is None and "issue" not in r2
