@@ -38,6 +38,8 @@ def parse_shape(name):
     base, _, sp = name.partition("s")
     tw, th = (int(x) for x in base.split("x"))
     return (tw, th), int(sp) if sp else 1
+
+
 # (bin_blocks, sort_blocks) tried at the chosen tile shape and frames in flight
 BLOCK_CANDIDATES = [(256, 512), (1024, 512), (512, 256), (512, 1024)]
 
